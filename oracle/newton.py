@@ -1,0 +1,113 @@
+"""Newton-Raphson with a backtracking line search (Sec. III.A, eq. linearized).
+
+The nonlinear DG residual is F(u) = A u + M S(u) - b, with the linear flux
+part A of Sec. II and a pointwise source S.  Each step solves the linearised
+problem (dA/du)(u) du = b - A(u) with preconditioned flexible GMRES to a
+relative tolerance, then backtracks the step length lambda until the
+sufficient-decrease condition holds, and updates u <- u + lambda du.
+
+Puncture source (the nonlinear workload): the equation
+Laplace(u) + beta (alpha (1+u) + 1)^-7 = 0 in flux form -Laplace(u) + S_u = 0
+has S_u(u) = -beta (alpha (1+u) + 1)^-7 and dS_u/du = 7 alpha beta
+(alpha (1+u) + 1)^-8.
+
+Readings:
+* f(u) = 1/2 ||F(u)||^2; the predicted decrease is that of the linear model,
+  so the initial slope is -||F(u)||^2; sufficient decrease
+  f(u + lambda du) <= f(u) + a lambda slope with a = 1e-4.
+* backtracking as in Dennis & Schnabel (the algorithm the paper names):
+  quadratic interpolation on the first backtrack, cubic afterwards, the new
+  lambda clamped to [0.1, 0.5] times the previous one, lambda = 1 first, at
+  most ``max_backtracks`` backtracks per step.
+* convergence when ||F(u)|| <= newton_rtol ||F(u_0)||.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .mesh import BoxMesh
+from .operator import apply_operator, mass_diagonal
+from .krylov import fgmres
+from .multigrid import VCycle
+
+
+def puncture_source(alpha, beta, u):
+    return -beta * (alpha * (1.0 + u) + 1.0) ** -7
+
+
+def puncture_source_derivative(alpha, beta, u):
+    return 7.0 * alpha * beta * (alpha * (1.0 + u) + 1.0) ** -8
+
+
+def backtrack(f0, slope, lam, f_lam, lam_prev, f_prev, first):
+    """Next trial step length (quadratic first, cubic afterwards)."""
+    if first:
+        t = -slope * lam ** 2 / (2.0 * (f_lam - f0 - slope * lam))
+    else:
+        r1 = f_lam - f0 - lam * slope
+        r2 = f_prev - f0 - lam_prev * slope
+        a = (r1 / lam ** 2 - r2 / lam_prev ** 2) / (lam - lam_prev)
+        b = (-lam_prev * r1 / lam ** 2 + lam * r2 / lam_prev ** 2) / (lam - lam_prev)
+        if a == 0.0:
+            t = -slope / (2.0 * b)
+        else:
+            disc = max(b * b - 3.0 * a * slope, 0.0)
+            t = (-b + np.sqrt(disc)) / (3.0 * a)
+    t = min(t, 0.5 * lam)
+    return max(t, 0.1 * lam)
+
+
+def newton_solve(mesh: BoxMesh, C, alpha, beta, b=None, u0=None, newton_rtol=1e-10,
+                 linear_rtol=1e-4, max_newton=20, levels=2, overlap=2, pre=3, post=3,
+                 subdomain_iters=3, sufficient_decrease=1e-4, max_backtracks=10,
+                 max_linear_iter=200):
+    """Returns (u, info) with the residual history and iteration counts."""
+    N = mesh.N
+    shape = (mesh.E, N, N, N)
+    alpha = np.asarray(alpha, float).reshape(shape)
+    beta = np.asarray(beta, float).reshape(shape)
+    b = np.zeros(shape) if b is None else np.asarray(b, float).reshape(shape)
+    u = np.zeros(shape) if u0 is None else np.asarray(u0, float).reshape(shape).copy()
+    M = mass_diagonal(mesh)
+
+    def F(v):
+        return apply_operator(mesh, v, C, source=puncture_source(alpha, beta, v)) - b
+
+    Fu = F(u)
+    norm0 = np.linalg.norm(Fu)
+    hist = [1.0]
+    linear_its = []
+    steps = 0
+    backtracks = 0
+    for _ in range(max_newton):
+        nrm = np.linalg.norm(Fu)
+        if nrm <= newton_rtol * norm0 or nrm == 0.0:
+            break
+        d = (M * puncture_source_derivative(alpha, beta, u)).reshape(-1)
+
+        def J(x):
+            return apply_operator(mesh, x.reshape(shape), C).reshape(-1) + d * x
+
+        V = VCycle(mesh, C, levels=levels, overlap=overlap, pre=pre, post=post,
+                   diag=d, subdomain_iters=subdomain_iters)
+        du, its, _ = fgmres(J, -Fu.reshape(-1), precondition=V, rtol=linear_rtol,
+                            max_iter=max_linear_iter)
+        linear_its.append(its)
+        du = du.reshape(shape)
+        f0 = 0.5 * nrm ** 2
+        slope = -nrm ** 2
+        lam, lam_prev, f_prev = 1.0, None, None
+        for bt in range(max_backtracks + 1):
+            Ft = F(u + lam * du)
+            ft = 0.5 * np.linalg.norm(Ft) ** 2
+            if ft <= f0 + sufficient_decrease * lam * slope or bt == max_backtracks:
+                break
+            new = backtrack(f0, slope, lam, ft, lam_prev, f_prev, first=(bt == 0))
+            lam_prev, f_prev, lam = lam, ft, new
+            backtracks += 1
+        u = u + lam * du
+        Fu = Ft
+        steps += 1
+        hist.append(np.linalg.norm(Fu) / norm0)
+    return u.reshape(-1), dict(steps=steps, history=hist, linear_iterations=linear_its,
+                               backtracks=backtracks)

@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module draws random numbers and evaluates the analytic problem data
+(sources, exact solutions, puncture background fields) at caller-supplied
+coordinates.  It holds none of the discretisation's or the solver's
+arithmetic: node positions come from whichever side (oracle or HIP library)
+asks for the data, and everything returned here is plain problem input.
+
+All random draws use ``numpy.random.default_rng(seed)`` (PCG64).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+# Seeds of the standard workloads.
+SEED_C2 = 2
+SEED_C3 = 3
+SEED_C5 = 5
+SEED_RANDOM_X0 = 7
+SEED_APPLY = 11
+SEED_ARRIVALS = 999
+SEED_REQUEST_BASE = 1000
+
+
+# ---------------------------------------------------------------------------
+# Manufactured solution of the Poisson test (Sec. IV.A, eq. prodofsin, in 3D)
+# ---------------------------------------------------------------------------
+def sin_product_solution(x, y, z):
+    """u = sin(pi x) sin(pi y) sin(pi z) on [0,1]^3."""
+    return np.sin(np.pi * x) * np.sin(np.pi * y) * np.sin(np.pi * z)
+
+
+def sin_product_source(x, y, z):
+    """f = -Laplace(u) = 3 pi^2 sin(pi x) sin(pi y) sin(pi z)."""
+    return 3.0 * np.pi ** 2 * sin_product_solution(x, y, z)
+
+
+# ---------------------------------------------------------------------------
+# Random-Fourier source with homogeneous Dirichlet data on a box
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass(frozen=True)
+class FourierModes:
+    amplitudes: np.ndarray  # [M]
+    wavenumbers: np.ndarray  # [M, 3], integers in 1..kmax
+    lower: tuple
+    upper: tuple
+
+
+def fourier_modes(seed: int, lower=(0.0, 0.0, 0.0), upper=(1.0, 1.0, 1.0),
+                  n_modes: int = 16, kmax: int = 4) -> FourierModes:
+    """Draw ``n_modes`` modes: integer wavenumbers uniform in 1..kmax per axis
+    and amplitudes from N(0,1)."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(1, kmax + 1, size=(n_modes, 3))
+    a = rng.standard_normal(n_modes)
+    return FourierModes(a, k, tuple(float(v) for v in lower),
+                        tuple(float(v) for v in upper))
+
+
+def _mode_products(m: FourierModes, x, y, z):
+    lo, hi = m.lower, m.upper
+    L = [hi[d] - lo[d] for d in range(3)]
+    out = []
+    for a, k in zip(m.amplitudes, m.wavenumbers):
+        s = (np.sin(np.pi * k[0] * (x - lo[0]) / L[0])
+             * np.sin(np.pi * k[1] * (y - lo[1]) / L[1])
+             * np.sin(np.pi * k[2] * (z - lo[2]) / L[2]))
+        lam = np.pi ** 2 * sum((k[d] / L[d]) ** 2 for d in range(3))
+        out.append((a, s, lam))
+    return out
+
+
+def fourier_source(m: FourierModes, x, y, z):
+    """f(x) = sum_m a_m prod_d sin(pi k_md (x_d - lo_d) / L_d)."""
+    return sum(a * s for a, s, _ in _mode_products(m, x, y, z))
+
+
+def fourier_solution(m: FourierModes, x, y, z):
+    """Exact solution of -Laplace(u) = f with u = 0 on the box boundary."""
+    return sum(a * s / lam for a, s, lam in _mode_products(m, x, y, z))
+
+
+# ---------------------------------------------------------------------------
+# Puncture-type nonlinear problem: Laplace(u) + beta (alpha (1+u) + 1)^-7 = 0
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass(frozen=True)
+class Punctures:
+    centers: np.ndarray  # [n, 3]
+    masses: np.ndarray  # [n]
+    momenta: np.ndarray  # [n, 3]
+
+
+def puncture_params(seed: int = SEED_C3, separation: float = 3.0,
+                    mass: float = 0.5, max_momentum: float = 0.2) -> Punctures:
+    """Two punctures at x = +-separation with seeded momenta |P| <= max_momentum
+    (direction = normalised N(0, I3), magnitude uniform on [0, max_momentum])."""
+    rng = np.random.default_rng(seed)
+    centers = np.array([[separation, 0.0, 0.0], [-separation, 0.0, 0.0]])
+    masses = np.array([mass, mass])
+    mom = []
+    for _ in range(2):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        mom.append(d * rng.uniform(0.0, max_momentum))
+    return Punctures(centers, masses, np.array(mom))
+
+
+def puncture_background(pp: Punctures, x, y, z, r_min: float = 1e-14):
+    """Brandt-Bruegmann background with Bowen-York extrinsic curvature.
+
+    1/alpha = sum_n M_n / (2 r_n);  beta = (1/8) alpha^7 Abar_ij Abar^ij with
+    Abar^ij = sum_n 3/(2 r_n^2) [P^i l^j + P^j l^i - (delta^ij - l^i l^j) P.l],
+    l = (x - C_n)/r_n.  Returns (alpha, beta) at the given points.
+    """
+    X = np.stack([np.asarray(x, float), np.asarray(y, float), np.asarray(z, float)])
+    inv_alpha = np.zeros(X.shape[1:])
+    A = np.zeros((3, 3) + X.shape[1:])
+    for c, M, P in zip(pp.centers, pp.masses, pp.momenta):
+        dx = X - c.reshape((3,) + (1,) * (X.ndim - 1))
+        r = np.maximum(np.sqrt((dx ** 2).sum(axis=0)), r_min)
+        l = dx / r
+        inv_alpha += M / (2.0 * r)
+        Pl = sum(P[i] * l[i] for i in range(3))
+        pref = 3.0 / (2.0 * r ** 2)
+        for i in range(3):
+            for j in range(3):
+                A[i, j] += pref * (P[i] * l[j] + P[j] * l[i]
+                                   - ((1.0 if i == j else 0.0) - l[i] * l[j]) * Pl)
+    alpha = 1.0 / inv_alpha
+    AA = (A ** 2).sum(axis=(0, 1))
+    beta = 0.125 * alpha ** 7 * AA
+    return alpha, beta
+
+
+# ---------------------------------------------------------------------------
+# Generic seeded fields and the request stream of the serving workload
+# ---------------------------------------------------------------------------
+def random_normal(seed: int, n: int) -> np.ndarray:
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+def random_uniform(seed: int, n: int, lo=-0.5, hi=0.5) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(lo, hi, n)
+
+
+@dataclasses.dataclass(frozen=True)
+class Request:
+    index: int
+    seed: int
+    arrival: float  # seconds after the stream starts
+    elements: tuple  # (nx, ny, nz)
+    p: int
+    side: float  # domain [0, side]^3
+
+
+def request_stream(n: int = 256, rate: float = 1.0, seed: int = SEED_ARRIVALS,
+                   cube_elements: bool = False, p_range=(3, 8), n_range=(2, 6),
+                   sides=(1, 2, 3, 4)) -> list:
+    """Poisson-process arrivals (exponential gaps of mean 1/rate).  Request i
+    draws its grid, degree and side from seed 1000+i."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=n)
+    t = np.cumsum(gaps) - gaps[0]
+    out = []
+    for i in range(n):
+        r = np.random.default_rng(SEED_REQUEST_BASE + i)
+        if cube_elements:
+            m = int(r.integers(n_range[0], n_range[1] + 1))
+            el = (m, m, m)
+        else:
+            el = tuple(int(v) for v in r.integers(n_range[0], n_range[1] + 1, size=3))
+        p = int(r.integers(p_range[0], p_range[1] + 1))
+        side = float(sides[int(r.integers(0, len(sides)))])
+        out.append(Request(i, SEED_REQUEST_BASE + i, float(t[i]), el, p, side))
+    return out
