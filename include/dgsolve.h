@@ -1,0 +1,152 @@
+/*
+ * dgsolve.h -- C ABI of the MI355X (gfx950) DG multigrid-Schwarz elliptic solver.
+ *
+ * Problem (arXiv:2111.06767, Sec. II, eq. matrix_eq): the discontinuous
+ * Galerkin discretisation of the Poisson equation -Laplace(u) = f on an
+ * axis-aligned box split into n_x * n_y * n_z equal elements, each with
+ * N = p+1 Legendre-Gauss-Lobatto points per dimension, homogeneous Dirichlet
+ * boundaries, and the internal-penalty numerical flux with penalty parameter C
+ * (eqs. dg_op_auxvars, dg_op_primal, numflux, penalty, bc).  The linear
+ * system A u = b is never assembled: only A u is defined.  Nonlinear problems
+ * A(u) = b are solved by repeated linearisation (Sec. III.A).
+ *
+ * Data layout.  Every field pointer is a DEVICE pointer to a contiguous FP64
+ * array owned by the caller, in the canonical nodal layout
+ *     idx = ((e * N + k) * N + j) * N + i,   e = (e_z * n_y + e_y) * n_x + e_x,
+ * i.e. the x point index i fastest, then y, then z, then the element.  The
+ * library owns its internal workspaces (device memory it allocates itself).
+ *
+ * Streams.  All device work is enqueued on the hipStream_t passed as
+ * `stream` (NULL = the null stream).  dgs_apply_operator, dgs_apply_mass,
+ * dgs_node_coordinates and dgs_precondition never synchronise the host.
+ * dgs_solve and dgs_newton_solve synchronise once per iteration to read the
+ * convergence scalars.
+ *
+ * Return codes.  DGS_OK (0) on success; DGS_NOT_CONVERGED (1) when an
+ * iteration limit was hit (outputs and stats are still valid); negative
+ * values are errors, described by dgs_last_error().  No C++ exception
+ * crosses this interface.  A problem handle is used by one thread at a time.
+ */
+#ifndef DGSOLVE_H
+#define DGSOLVE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DGS_OK 0
+#define DGS_NOT_CONVERGED 1
+#define DGS_ERR_INVALID (-1)   /* bad argument: p outside [1,8], element count < 1,
+                                  penalty <= 0, empty box, NULL pointer ...      */
+#define DGS_ERR_OOM (-2)       /* device allocation failed                       */
+#define DGS_ERR_HIP (-3)       /* a HIP runtime call or kernel launch failed     */
+#define DGS_ERR_NONFINITE (-4) /* NaN or Inf met in a reduction                  */
+
+#define DGS_FP64 0  /* every step in FP64                                         */
+#define DGS_MIXED 1 /* Schwarz subdomain solves in FP32 on MFMA with FP32
+                       accumulation; residuals, Gram-Schmidt, updates and the
+                       coarsest-level smoothing stay FP64                       */
+
+typedef struct dgs_problem dgs_problem; /* opaque, owned by the library */
+
+/* Axis-aligned box [lower, upper] (Sec. II: a single block). */
+typedef struct {
+  double lower[3];
+  double upper[3];
+} dgs_domain;
+
+/* Solver options; dgs_default_options() fills the defaults in brackets. */
+typedef struct {
+  int overlap;         /* N_overlap points into each face neighbour (Sec. III.D.1) [2] */
+  int mg_levels;       /* multigrid levels incl. the finest; 0 = until no
+                          dimension can be halved (Sec. III.C.1)                  [0] */
+  int pre_smooth;      /* Schwarz presmoothing steps per level (Sec. III.C.3)    [3] */
+  int post_smooth;     /* Schwarz postsmoothing steps per level                  [3] */
+  int precision;       /* DGS_FP64 or DGS_MIXED                            [DGS_FP64] */
+  int subdomain_iters; /* linearised problems only: 0 = apply the Poisson
+                          subdomain inverse once; k > 0 = k iterations of GMRES
+                          preconditioned by it (Sec. III.E.1)                    [3] */
+  int max_iter;        /* FGMRES iteration limit (no restart)                   [200] */
+  double rtol;         /* FGMRES relative residual tolerance                   [1e-10] */
+} dgs_options;
+
+/* Statistics of a solve.  `history` may be NULL; otherwise it receives up to
+   `history_capacity` relative residual estimates (entry 0 is 1.0). */
+typedef struct {
+  int iterations;       /* FGMRES iterations (summed over Newton steps)          */
+  int newton_steps;     /* Newton steps taken (dgs_newton_solve only)            */
+  int backtracks;       /* line-search backtracks (dgs_newton_solve only)        */
+  double rel_residual;  /* final true relative residual ||b-Au|| / ||b-Au0||     */
+  double* history;
+  int history_capacity;
+  int history_len;
+  double t_setup_s;     /* wall time of dgs_create_problem                        */
+  double t_solve_s;     /* wall time of the last solve call                       */
+} dgs_stats;
+
+void dgs_default_options(dgs_options* opt);
+
+/* Create a problem: mesh, LGL tables, multigrid hierarchy, and the explicit
+ * inverses of the Schwarz subdomain operators A_S = R_S A R_S^T
+ * (Sec. III.D.2, III.E.2), built on the device.
+ *   domain    box; upper > lower in every dimension
+ *   elements  n_x, n_y, n_z >= 1
+ *   p         polynomial degree, 1..8 (N = p+1 points per dimension)
+ *   penalty   C > 0 in sigma = C (p+1)^2 / h (eq. penalty)
+ *   opt       NULL = defaults
+ *   stream    hipStream_t for the set-up work
+ *   out       receives the handle; free it with dgs_destroy_problem.          */
+int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
+                       const dgs_options* opt, void* stream, dgs_problem** out);
+int dgs_destroy_problem(dgs_problem* prob);
+
+/* Number of degrees of freedom E * N^3. */
+int dgs_num_dofs(const dgs_problem* prob, long long* n);
+
+/* Physical coordinates of every point: xyz[d * ndof + idx], d = x, y, z. */
+int dgs_node_coordinates(const dgs_problem* prob, double* xyz, void* stream);
+
+/* b = M f with the LGL-quadrature mass matrix M = J w_i w_j w_k (eq. massmat). */
+int dgs_apply_mass(const dgs_problem* prob, const double* f, double* b, void* stream);
+
+/* Au = A u: the left-hand side of eq. dg_op_primal for the Poisson fluxes
+ * (eq. poisson_fluxform) with homogeneous Dirichlet boundaries.  u and Au must
+ * not overlap. */
+int dgs_apply_operator(dgs_problem* prob, const double* u, double* Au, void* stream);
+
+/* u <- u + sum of `steps` additive Schwarz iterations on A u = b on the
+ * finest grid (Sec. III.D.5, eq. schwarz_weighting); b and u must not overlap. */
+int dgs_schwarz_smooth(dgs_problem* prob, const double* b, double* u, int steps, void* stream);
+
+/* z = one multigrid V-cycle applied to r with zero initial guess
+ * (Sec. III.C.3); r and z must not overlap. */
+int dgs_precondition(dgs_problem* prob, const double* r, double* z, void* stream);
+
+/* Solve A u = b by flexible GMRES (Sec. III.B) preconditioned with one
+ * V-cycle per iteration.  u holds the initial guess on entry and the solution
+ * on exit.  Stops when the residual estimate drops below rtol ||b - A u0||;
+ * stats->rel_residual is the true relative residual of the result. */
+int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream);
+
+/* Solve the puncture-type equation Laplace(u) + beta (alpha (1+u) + 1)^-7 = f
+ * in DG form A u + M S(u) = b with S(u) = -beta (alpha (1+u) + 1)^-7, by
+ * Newton-Raphson with a backtracking line search (Sec. III.A).  alpha, beta
+ * are nodal fields; b = M f (all zero for the vacuum puncture problem).
+ * Each Newton step solves the linearisation to linear_rtol with FGMRES and a
+ * multigrid-Schwarz preconditioner on the linearised operator.  u holds the
+ * initial guess on entry and the solution on exit.  Converged when
+ * ||F(u)|| <= newton_rtol ||F(u0)||. */
+int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta, const double* b,
+                     double* u, double newton_rtol, double linear_rtol, int max_newton,
+                     dgs_stats* stats, void* stream);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* dgs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGSOLVE_H */

@@ -1,0 +1,236 @@
+"""Python binding of the C ABI in include/dgsolve.h (argument marshalling only).
+
+Fields are torch tensors on the GPU (float64, contiguous, canonical nodal
+layout); their device pointers and torch's current HIP stream are handed to
+the library.  Every computation runs in the library's HIP kernels.  The
+library must be built (``__graft_entry__.build()``); loading fails loudly
+otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgsolve.so")
+
+DGS_OK = 0
+DGS_NOT_CONVERGED = 1
+DGS_ERR_INVALID = -1
+DGS_ERR_OOM = -2
+DGS_ERR_HIP = -3
+DGS_ERR_NONFINITE = -4
+DGS_FP64 = 0
+DGS_MIXED = 1
+
+# Entry points declared in include/dgsolve.h.
+EXPORTED = (
+    "dgs_default_options", "dgs_create_problem", "dgs_destroy_problem", "dgs_num_dofs",
+    "dgs_node_coordinates", "dgs_apply_mass", "dgs_apply_operator", "dgs_schwarz_smooth",
+    "dgs_precondition", "dgs_solve", "dgs_newton_solve", "dgs_last_error",
+)
+
+
+class Domain(ctypes.Structure):
+    _fields_ = [("lower", ctypes.c_double * 3), ("upper", ctypes.c_double * 3)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("overlap", ctypes.c_int), ("mg_levels", ctypes.c_int),
+                ("pre_smooth", ctypes.c_int), ("post_smooth", ctypes.c_int),
+                ("precision", ctypes.c_int), ("subdomain_iters", ctypes.c_int),
+                ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("newton_steps", ctypes.c_int),
+                ("backtracks", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_capacity", ctypes.c_int),
+                ("history_len", ctypes.c_int), ("t_setup_s", ctypes.c_double),
+                ("t_solve_s", ctypes.c_double)]
+
+
+class DgsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dgsolve error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdgsolve.so and declare the argument types of every entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch ships its own HIP runtime with the same soname; loading torch first
+    # makes the library bind to that one runtime instead of a second copy
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    dp = ctypes.c_void_p  # device pointers
+    lib.dgs_default_options.argtypes = [ctypes.POINTER(Options)]
+    lib.dgs_default_options.restype = None
+    lib.dgs_create_problem.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.c_int, ctypes.c_double, ctypes.POINTER(Options), P,
+                                       ctypes.POINTER(P)]
+    lib.dgs_destroy_problem.argtypes = [P]
+    lib.dgs_num_dofs.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
+    lib.dgs_node_coordinates.argtypes = [P, dp, P]
+    lib.dgs_apply_mass.argtypes = [P, dp, dp, P]
+    lib.dgs_apply_operator.argtypes = [P, dp, dp, P]
+    lib.dgs_schwarz_smooth.argtypes = [P, dp, dp, ctypes.c_int, P]
+    lib.dgs_precondition.argtypes = [P, dp, dp, P]
+    lib.dgs_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
+    lib.dgs_newton_solve.argtypes = [P, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.POINTER(Stats), P]
+    lib.dgs_last_error.argtypes = []
+    lib.dgs_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("dgs_default_options", "dgs_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def default_options(**kw) -> Options:
+    lib = load_library()
+    o = Options()
+    lib.dgs_default_options(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": DGS_FP64, "mixed": DGS_MIXED}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _check(code, allow_not_converged=False):
+    if code == DGS_OK or (allow_not_converged and code == DGS_NOT_CONVERGED):
+        return code
+    msg = load_library().dgs_last_error().decode()
+    raise DgsError(code, msg)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, n=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """A DG Poisson problem on a box (see dgs_create_problem)."""
+
+    def __init__(self, lower, upper, elements, p, penalty=1.5, options: Options | None = None,
+                 stream=None, **opts):
+        lib = load_library()
+        self._lib = lib
+        self.options = options if options is not None else default_options(**opts)
+        dom = Domain((ctypes.c_double * 3)(*lower), (ctypes.c_double * 3)(*upper))
+        el = (ctypes.c_int * 3)(*elements)
+        h = ctypes.c_void_p()
+        _check(lib.dgs_create_problem(ctypes.byref(dom), el, int(p), float(penalty),
+                                      ctypes.byref(self.options), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.elements = tuple(int(v) for v in elements)
+        self.p, self.N = int(p), int(p) + 1
+        self.lower, self.upper = tuple(lower), tuple(upper)
+        n = ctypes.c_longlong()
+        _check(lib.dgs_num_dofs(h, ctypes.byref(n)))
+        self.ndof = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dgs_destroy_problem(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, n=None):
+        import torch
+        return torch.empty(self.ndof if n is None else n, dtype=torch.float64, device="cuda")
+
+    def node_coordinates(self, stream=None):
+        xyz = self._new(3 * self.ndof)
+        _check(self._lib.dgs_node_coordinates(self._h, _ptr(xyz, 3 * self.ndof), _stream(stream)))
+        return xyz.view(3, self.ndof)
+
+    def apply_mass(self, f, out=None, stream=None):
+        out = self._new() if out is None else out
+        _check(self._lib.dgs_apply_mass(self._h, _ptr(f, self.ndof, "f"), _ptr(out, self.ndof, "out"),
+                                        _stream(stream)))
+        return out
+
+    def apply(self, u, out=None, stream=None):
+        out = self._new() if out is None else out
+        _check(self._lib.dgs_apply_operator(self._h, _ptr(u, self.ndof, "u"),
+                                            _ptr(out, self.ndof, "out"), _stream(stream)))
+        return out
+
+    def smooth(self, b, u, steps, stream=None):
+        _check(self._lib.dgs_schwarz_smooth(self._h, _ptr(b, self.ndof, "b"), _ptr(u, self.ndof, "u"),
+                                            int(steps), _stream(stream)))
+        return u
+
+    def precondition(self, r, out=None, stream=None):
+        out = self._new() if out is None else out
+        _check(self._lib.dgs_precondition(self._h, _ptr(r, self.ndof, "r"), _ptr(out, self.ndof, "z"),
+                                          _stream(stream)))
+        return out
+
+    def solve(self, b, u=None, history=256, stream=None):
+        """Solve A u = b (u = initial guess, zero if None).  Returns (u, stats dict)."""
+        import torch
+        if u is None:
+            u = torch.zeros(self.ndof, dtype=torch.float64, device="cuda")
+        st, hist = _make_stats(history)
+        code = _check(self._lib.dgs_solve(self._h, _ptr(b, self.ndof, "b"), _ptr(u, self.ndof, "u"),
+                                          ctypes.byref(st), _stream(stream)), allow_not_converged=True)
+        return u, _stats_dict(st, hist, code)
+
+    def newton_solve(self, alpha, beta, b=None, u=None, newton_rtol=1e-10, linear_rtol=1e-4,
+                     max_newton=20, history=256, stream=None):
+        import torch
+        if u is None:
+            u = torch.zeros(self.ndof, dtype=torch.float64, device="cuda")
+        if b is None:
+            b = torch.zeros(self.ndof, dtype=torch.float64, device="cuda")
+        st, hist = _make_stats(history)
+        code = _check(self._lib.dgs_newton_solve(
+            self._h, _ptr(alpha, self.ndof, "alpha"), _ptr(beta, self.ndof, "beta"),
+            _ptr(b, self.ndof, "b"), _ptr(u, self.ndof, "u"), float(newton_rtol), float(linear_rtol),
+            int(max_newton), ctypes.byref(st), _stream(stream)), allow_not_converged=True)
+        return u, _stats_dict(st, hist, code)
+
+
+def _make_stats(history):
+    hist = (ctypes.c_double * max(1, history))()
+    st = Stats()
+    st.history = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+    st.history_capacity = history
+    return st, hist
+
+
+def _stats_dict(st, hist, code):
+    return dict(iterations=st.iterations, newton_steps=st.newton_steps, backtracks=st.backtracks,
+                rel_residual=st.rel_residual, history=[hist[i] for i in range(st.history_len)],
+                t_setup_s=st.t_setup_s, t_solve_s=st.t_solve_s, converged=(code == DGS_OK))

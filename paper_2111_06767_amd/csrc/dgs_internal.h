@@ -1,0 +1,135 @@
+// Internal declarations of the gfx950 DG multigrid-Schwarz solver library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dgs {
+
+constexpr int kMaxN = 9;  // p <= 8
+
+// ---------------------------------------------------------------------------
+// Host tables (LGL nodes/weights, derivative and child interpolation)
+// ---------------------------------------------------------------------------
+struct HostTables {
+  int N = 0;
+  std::vector<double> xi, w, D, Plo, Phi;  // D, Plo, Phi row-major N x N
+};
+HostTables make_tables(int N);
+
+// Kernel-argument copy of the tables (fixed size so one struct serves every N).
+struct DevTables {
+  double xi[kMaxN];
+  double w[kMaxN];
+  double D[kMaxN * kMaxN];
+  double Plo[kMaxN * kMaxN];
+  double Phi[kMaxN * kMaxN];
+};
+DevTables to_dev(const HostTables& t);
+
+// Geometry of one uniform box level.
+struct OpParams {
+  double h[3];
+  double penalty;
+  int E;
+};
+
+// Operator modes of the fused apply kernel.
+enum ApplyMode : int {
+  kApply = 0,         // out = A u
+  kResidual = 1,      // out = b - A u
+  kApplyDiag = 2,     // out = A u + d .* u
+  kResidualDiag = 3,  // out = b - (A u + d .* u)
+  kPuncture = 4,      // out = A u + M S(u) - b,  S = -beta (alpha (1+u) + 1)^-7
+};
+
+// Launch configuration of the operator kernel: elements per workgroup.
+struct ApplyConfig {
+  int epb = 0;  // 0 = default for N
+};
+
+hipError_t launch_apply(int N, int mode, const double* u, double* out, const double* b,
+                        const double* aux0, const double* aux1, const int* nbr, const OpParams& P,
+                        const DevTables& T, const ApplyConfig& cfg, hipStream_t s);
+hipError_t launch_mass(int N, const double* f, double* out, long long E, const double h[3],
+                       const DevTables& T, hipStream_t s);
+hipError_t launch_coords(int N, double* xyz, const int n[3], const double lower[3],
+                         const double h[3], const DevTables& T, hipStream_t s);
+
+// Schwarz subdomain data of one level.
+struct ClassInfo {
+  int n;            // subdomain size n_S
+  int count;        // number of subdomains (elements) in the class
+  long long inv_off;  // offset of this class's n x n matrix
+  long long rs_off;   // offset of this class's [count][n] block in RS / DU
+  int layout_off;     // offset into seg_loc / weights
+  int strip_off[6];   // offset of each face strip in the layout, -1 if absent
+};
+
+struct GemmTile {
+  int cls, m0, n0, pad;
+};
+
+// r_S = R_S r for every subdomain (one per element) into row elem_row[e].
+hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* elem_class,
+                         const long long* elem_row, const int* nbr, const ClassInfo* cls,
+                         const int* seg_loc, int E, hipStream_t s);
+hipError_t launch_subdomain_gemm(bool f32, const void* rs, const void* inv, void* du,
+                                 const ClassInfo* cls, const GemmTile* tiles, int ntiles,
+                                 double scale, hipStream_t s);
+// u += sum_S R_S^T (w_S du_S), pulled per point.
+hipError_t launch_scatter(int N, bool f32, double* u, const void* du, const double* weights,
+                          const int* elem_class, const long long* elem_row, const int* nbr,
+                          const ClassInfo* cls, int nov, long long E, hipStream_t s);
+
+// Multigrid transfer (per-dimension split flags).
+hipError_t launch_restrict(int N, const double* fine, double* coarse, const int nf[3],
+                           const int nc[3], const int split[3], const DevTables& T, hipStream_t s);
+hipError_t launch_prolongate_add(int N, const double* coarse, double* fine, const int nf[3],
+                                 const int nc[3], const int split[3], const DevTables& T,
+                                 hipStream_t s);
+
+// Vector kernels.
+hipError_t launch_fill(double* x, double v, long long n, hipStream_t s);
+hipError_t launch_copy(double* y, const double* x, long long n, hipStream_t s);
+hipError_t launch_axpy(double* y, double a, const double* x, long long n, hipStream_t s);
+// Multi-dot: h[i] = <V_i, w> for i < m (V_i = V + i * ldv); partial sums in
+// `partial` (blocks x m), final reduction into h (device).  Deterministic.
+int multidot_blocks(long long n);
+hipError_t launch_multidot(const double* V, long long ldv, int m, const double* w, long long n,
+                           double* partial, double* h, hipStream_t s);
+// w -= sum_i coef[i] * V_i  (coef on the device, scaled by `sign`)
+hipError_t launch_multi_axpy(double* w, const double* V, long long ldv, int m, const double* coef,
+                             long long n, hipStream_t s);
+// y = x / *nrm  (nrm on the device, the Euclidean norm squared's square root taken here)
+hipError_t launch_scale_by_inv_norm(double* y, const double* x, const double* nrm2, long long n,
+                                    hipStream_t s);
+// x += sum_i y[i] Z_i (y on the device)
+hipError_t launch_combine(double* x, const double* Z, long long ldz, int m, const double* y,
+                          long long n, hipStream_t s);
+// d = M * 7 alpha beta (alpha (1+u) + 1)^-8 (puncture linearisation diagonal)
+hipError_t launch_puncture_diag(int N, const double* alpha, const double* beta, const double* u,
+                                double* d, long long E, const double h[3], const DevTables& T,
+                                hipStream_t s);
+// y = x + lam * dx
+hipError_t launch_waxpy(double* y, const double* x, double lam, const double* dx, long long n,
+                        hipStream_t s);
+
+// Set-up kernels: batched Gauss-Jordan inversion of SPD matrices (padded to
+// n_pad with identity), unit-vector fill and column gather for the patch apply.
+hipError_t launch_gj_step(double* A, int n_pad, int batch, int k, double* colbuf, double* rowbuf,
+                          hipStream_t s);
+hipError_t launch_unit_columns(double* X, long long copy_stride, const int* idx, int ncols,
+                               hipStream_t s);
+hipError_t launch_gather_columns(const double* AX, long long copy_stride, const int* idx, int n,
+                                 double* A, int n_pad, hipStream_t s);
+hipError_t launch_finish_inverse(const double* Ainv, int n_pad, int n, double scale, double* out64,
+                                 float* out32, hipStream_t s);
+hipError_t launch_scale_copy(const double* A, int n_pad, int n, double scale, double* out64,
+                             float* out32, hipStream_t s);
+
+}  // namespace dgs

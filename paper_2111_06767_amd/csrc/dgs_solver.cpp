@@ -1,0 +1,852 @@
+// Host orchestration and C ABI of the gfx950 DG multigrid-Schwarz solver.
+//
+//   set-up       mesh levels (Sec. III.C.1), Schwarz subdomain classes and
+//                layouts (Sec. III.D.1-4), explicit subdomain inverses built on
+//                the device column by column (Sec. III.E.2)
+//   apply        A u (Sec. II)
+//   smooth       additive Schwarz steps (Sec. III.D.5)
+//   precondition one multigrid V-cycle (Sec. III.C.3)
+//   solve        flexible GMRES (Sec. III.B; Saad Alg. 9.6) with classical
+//                Gram-Schmidt applied twice, one host synchronisation per
+//                iteration for the Hessenberg column
+//   newton_solve Newton-Raphson with backtracking line search (Sec. III.A)
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dgsolve.h"
+#include "dgs_internal.h"
+
+using namespace dgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Status {
+  int code = DGS_OK;
+  std::string msg;
+};
+
+class DgsError {
+ public:
+  DgsError(int c, std::string m) : code(c), msg(std::move(m)) {}
+  int code;
+  std::string msg;
+};
+
+#define HIP_OK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      throw DgsError(e_ == hipErrorOutOfMemory ? DGS_ERR_OOM : DGS_ERR_HIP,                \
+                     std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <typename T>
+T* dalloc(size_t count) {
+  if (count == 0) count = 1;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, count * sizeof(T));
+  if (e != hipSuccess)
+    throw DgsError(e == hipErrorOutOfMemory ? DGS_ERR_OOM : DGS_ERR_HIP,
+                   std::string("hipMalloc: ") + hipGetErrorString(e));
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return;
+  HIP_OK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+const int kFace[6][2] = {{0, -1}, {0, 1}, {1, -1}, {1, 1}, {2, -1}, {2, 1}};
+
+// Boundary class: bit 2f set when face f of the element is external.
+int class_flags(const int c[3], const int n[3]) {
+  int fl = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (c[d] == 0) fl |= 1 << (2 * d);
+    if (c[d] == n[d] - 1) fl |= 1 << (2 * d + 1);
+  }
+  return fl;
+}
+
+struct ClassLayout {
+  int flags = 0;
+  int n = 0;
+  std::vector<int> seg_loc;     // seg * N^3 + local point
+  std::vector<double> weights;  // w_S at every subdomain point
+  int strip_off[6];
+};
+
+// 1D Schwarz weight (eq. schwarz_weight_function) extended to 1 toward
+// external faces.
+double smoothstep(double x) {
+  if (x > 1.0) return 1.0;
+  if (x < -1.0) return -1.0;
+  const double x2 = x * x;
+  return x * (15.0 - 10.0 * x2 + 3.0 * x2 * x2) / 8.0;
+}
+double weight1d(double xi, double delta, bool lo_ext, bool hi_ext) {
+  const double a = lo_ext ? 1.0 : smoothstep((xi + 1.0) / delta);
+  const double b = hi_ext ? -1.0 : smoothstep((xi - 1.0) / delta);
+  return 0.5 * (a - b);
+}
+
+ClassLayout make_layout(int flags, int N, int nov, const std::vector<double>& xi) {
+  ClassLayout L;
+  L.flags = flags;
+  const int N2 = N * N, N3 = N2 * N;
+  const double delta = 1.0 + xi[nov];
+  bool ext[3][2];
+  for (int d = 0; d < 3; ++d) {
+    ext[d][0] = (flags >> (2 * d)) & 1;
+    ext[d][1] = (flags >> (2 * d + 1)) & 1;
+  }
+  auto w1 = [&](int d, double x) { return weight1d(x, delta, ext[d][0], ext[d][1]); };
+  // central element
+  for (int k = 0; k < N; ++k)
+    for (int j = 0; j < N; ++j)
+      for (int i = 0; i < N; ++i) {
+        L.seg_loc.push_back((k * N + j) * N + i);
+        L.weights.push_back(w1(0, xi[i]) * w1(1, xi[j]) * w1(2, xi[k]));
+      }
+  for (int f = 0; f < 6; ++f) {
+    const int d = kFace[f][0], s = kFace[f][1];
+    if (ext[d][s > 0 ? 1 : 0]) {
+      L.strip_off[f] = -1;
+      continue;
+    }
+    L.strip_off[f] = (int)L.seg_loc.size();
+    const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+    for (int layer = 0; layer < nov; ++layer) {
+      const int m = s > 0 ? layer : N - 1 - layer;
+      const double xs = 2.0 * s + xi[m];
+      for (int b1 = 0; b1 < N; ++b1)
+        for (int b0 = 0; b0 < N; ++b0) {
+          int node[3];
+          node[d] = m;
+          node[t0] = b0;
+          node[t1] = b1;
+          L.seg_loc.push_back((f + 1) * N3 + (node[2] * N + node[1]) * N + node[0]);
+          const double aj = w1(t0, xi[b0]), ak = w1(t1, xi[b1]);
+          const double T = aj * ak + 0.5 * (1 - aj) * ak + 0.5 * aj * (1 - ak) +
+                           (1 - aj) * (1 - ak) / 3.0;
+          L.weights.push_back(w1(d, xs) * T);
+        }
+    }
+  }
+  L.n = (int)L.seg_loc.size();
+  return L;
+}
+
+struct Level {
+  int n[3] = {0, 0, 0};
+  long long E = 0;
+  double h[3] = {0, 0, 0};
+  int split[3] = {0, 0, 0};
+  bool has_coarser = false;
+  bool f32 = false;
+  OpParams op{};
+  int* d_nbr = nullptr;
+  // Schwarz
+  std::vector<ClassLayout> layouts;
+  std::vector<ClassInfo> cls;
+  ClassInfo* d_cls = nullptr;
+  int* d_seg_loc = nullptr;
+  double* d_weights = nullptr;
+  int* d_elem_class = nullptr;
+  long long* d_elem_row = nullptr;
+  GemmTile* d_tiles = nullptr;
+  int ntiles = 0;
+  long long inv_total = 0, rs_total = 0;
+  double* d_inv64 = nullptr;
+  float* d_inv32 = nullptr;
+  void* d_rs = nullptr;
+  void* d_du = nullptr;
+  // level vectors
+  double *d_u = nullptr, *d_b = nullptr, *d_r = nullptr, *d_diag = nullptr;
+};
+
+}  // namespace
+
+struct dgs_problem {
+  dgs_options opt{};
+  int p = 0, N = 0;
+  double penalty = 0;
+  dgs_domain dom{};
+  HostTables ht;
+  DevTables dt{};
+  ApplyConfig acfg;
+  std::vector<Level> levels;
+  std::vector<void*> allocations;
+  // Krylov workspace
+  int kry_m = 0;
+  double *d_V = nullptr, *d_Z = nullptr, *d_partial = nullptr, *d_h = nullptr, *d_y = nullptr;
+  double* d_tmp = nullptr;  // one full vector
+  double* d_tmp2 = nullptr;
+  bool diag_active = false;
+  double t_setup = 0;
+
+  long long nd(int l) const { return levels[l].E * (long long)N * N * N; }
+
+  template <typename T>
+  T* alloc(size_t count) {
+    T* p = dalloc<T>(count);
+    allocations.push_back(p);
+    return p;
+  }
+  ~dgs_problem() {
+    for (void* p : allocations) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+int nov_of(const dgs_problem* P) { return std::max(1, std::min(P->opt.overlap, P->N - 1)); }
+
+void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
+  L.E = (long long)L.n[0] * L.n[1] * L.n[2];
+  for (int d = 0; d < 3; ++d) L.h[d] = (P->dom.upper[d] - P->dom.lower[d]) / L.n[d];
+  L.op.h[0] = L.h[0];
+  L.op.h[1] = L.h[1];
+  L.op.h[2] = L.h[2];
+  L.op.penalty = P->penalty;
+  L.op.E = (int)L.E;
+  std::vector<int> nbr(L.E * 6);
+  for (long long e = 0; e < L.E; ++e) {
+    const int c[3] = {(int)(e % L.n[0]), (int)((e / L.n[0]) % L.n[1]),
+                      (int)(e / ((long long)L.n[0] * L.n[1]))};
+    for (int f = 0; f < 6; ++f) {
+      int cc[3] = {c[0], c[1], c[2]};
+      cc[kFace[f][0]] += kFace[f][1];
+      const int d = kFace[f][0];
+      nbr[e * 6 + f] = (cc[d] < 0 || cc[d] >= L.n[d])
+                           ? -1
+                           : (int)(((long long)cc[2] * L.n[1] + cc[1]) * L.n[0] + cc[0]);
+    }
+  }
+  L.d_nbr = P->alloc<int>(nbr.size());
+  upload(L.d_nbr, nbr, s);
+  HIP_OK(hipStreamSynchronize(s));  // nbr goes out of scope
+  const long long nd = L.E * (long long)P->N * P->N * P->N;
+  L.d_u = P->alloc<double>(nd);
+  L.d_b = P->alloc<double>(nd);
+  L.d_r = P->alloc<double>(nd);
+}
+
+// Schwarz classes, layouts, tiles and work buffers of a level.
+void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
+  const int N = P->N, nov = nov_of(P);
+  std::map<int, int> cls_of_flags;
+  std::vector<int> elem_flags(L.E);
+  for (long long e = 0; e < L.E; ++e) {
+    const int c[3] = {(int)(e % L.n[0]), (int)((e / L.n[0]) % L.n[1]),
+                      (int)(e / ((long long)L.n[0] * L.n[1]))};
+    elem_flags[e] = class_flags(c, L.n);
+    cls_of_flags.emplace(elem_flags[e], 0);
+  }
+  int ci = 0;
+  for (auto& kv : cls_of_flags) kv.second = ci++;
+  L.layouts.clear();
+  L.cls.assign(ci, ClassInfo{});
+  for (auto& kv : cls_of_flags) L.layouts.push_back(make_layout(kv.first, N, nov, P->ht.xi));
+  std::vector<int> elem_class(L.E), count(ci, 0), pos(L.E);
+  for (long long e = 0; e < L.E; ++e) {
+    elem_class[e] = cls_of_flags[elem_flags[e]];
+    pos[e] = count[elem_class[e]]++;
+  }
+  std::vector<int> seg_loc;
+  std::vector<double> weights;
+  long long inv_off = 0, rs_off = 0;
+  std::vector<GemmTile> tiles;
+  for (int c = 0; c < ci; ++c) {
+    ClassInfo& I = L.cls[c];
+    const ClassLayout& lay = L.layouts[c];
+    I.n = lay.n;
+    I.count = count[c];
+    I.inv_off = inv_off;
+    I.rs_off = rs_off;
+    I.layout_off = (int)seg_loc.size();
+    for (int f = 0; f < 6; ++f) I.strip_off[f] = lay.strip_off[f];
+    seg_loc.insert(seg_loc.end(), lay.seg_loc.begin(), lay.seg_loc.end());
+    weights.insert(weights.end(), lay.weights.begin(), lay.weights.end());
+    inv_off += (long long)lay.n * lay.n;
+    rs_off += (long long)lay.n * count[c];
+    for (int m0 = 0; m0 < I.count; m0 += 64)
+      for (int n0 = 0; n0 < I.n; n0 += 64) tiles.push_back(GemmTile{c, m0, n0, 0});
+  }
+  L.inv_total = inv_off;
+  L.rs_total = rs_off;
+  std::vector<long long> elem_row(L.E);
+  for (long long e = 0; e < L.E; ++e)
+    elem_row[e] = L.cls[elem_class[e]].rs_off + (long long)pos[e] * L.cls[elem_class[e]].n;
+  L.d_cls = P->alloc<ClassInfo>(ci);
+  upload(L.d_cls, L.cls, s);
+  L.d_seg_loc = P->alloc<int>(seg_loc.size());
+  upload(L.d_seg_loc, seg_loc, s);
+  L.d_weights = P->alloc<double>(weights.size());
+  upload(L.d_weights, weights, s);
+  L.d_elem_class = P->alloc<int>(L.E);
+  upload(L.d_elem_class, elem_class, s);
+  L.d_elem_row = P->alloc<long long>(L.E);
+  upload(L.d_elem_row, elem_row, s);
+  L.ntiles = (int)tiles.size();
+  L.d_tiles = P->alloc<GemmTile>(tiles.size());
+  upload(L.d_tiles, tiles, s);
+  if (L.f32) {
+    L.d_inv32 = P->alloc<float>(L.inv_total);
+    L.d_rs = P->alloc<float>(L.rs_total);
+    L.d_du = P->alloc<float>(L.rs_total);
+  } else {
+    L.d_inv64 = P->alloc<double>(L.inv_total);
+    L.d_rs = P->alloc<double>(L.rs_total);
+    L.d_du = P->alloc<double>(L.rs_total);
+  }
+  // host copies of the elem tables are kept in the layouts only
+  HIP_OK(hipStreamSynchronize(s));  // host vectors above go out of scope
+}
+
+// Explicit inverses of A_S for every (class flags, element aspect) key, built
+// on the device: the subdomain operator is assembled column by column by
+// applying the DG operator to unit vectors on a small patch (the central
+// element, its face neighbours and one all-zero element standing for every
+// element outside the subdomain), then inverted by Gauss-Jordan elimination
+// (A_S is symmetric positive definite, so no pivoting is needed).  Uniform
+// scaling of all element widths by lambda scales A_S by lambda, so one inverse
+// per key serves every level with the same aspect ratio.
+void build_inverses(dgs_problem* P, hipStream_t s) {
+  const int N = P->N, N3 = N * N * N;
+  struct Key {
+    int flags;
+    double ry, rz;
+  };
+  struct Use {
+    int level, cls;
+    int key;
+  };
+  std::vector<Key> keys;
+  std::vector<double> key_hx;  // reference width along x
+  std::vector<int> key_level;  // reference level
+  std::vector<Use> uses;
+  for (int l = 0; l < (int)P->levels.size(); ++l) {
+    const Level& L = P->levels[l];
+    const double ry = L.h[1] / L.h[0], rz = L.h[2] / L.h[0];
+    for (int c = 0; c < (int)L.layouts.size(); ++c) {
+      int found = -1;
+      for (int k = 0; k < (int)keys.size(); ++k)
+        if (keys[k].flags == L.layouts[c].flags && std::fabs(keys[k].ry - ry) <= 1e-13 * ry &&
+            std::fabs(keys[k].rz - rz) <= 1e-13 * rz)
+          found = k;
+      if (found < 0) {
+        keys.push_back(Key{L.layouts[c].flags, ry, rz});
+        key_hx.push_back(L.h[0]);
+        key_level.push_back(l);
+        found = (int)keys.size() - 1;
+      }
+      uses.push_back(Use{l, c, found});
+    }
+  }
+  // layout of each key (identical to any level's layout with those flags)
+  const int nov = nov_of(P);
+  std::vector<ClassLayout> klay;
+  int n_pad = 0;
+  for (auto& k : keys) {
+    klay.push_back(make_layout(k.flags, N, nov, P->ht.xi));
+    n_pad = std::max(n_pad, klay.back().n);
+  }
+  const int nk = (int)keys.size();
+  double* d_batch = dalloc<double>((size_t)nk * n_pad * n_pad);
+  std::unique_ptr<void, void (*)(void*)> g1(d_batch, [](void* p) { (void)hipFree(p); });
+  // identity padding everywhere first
+  {
+    std::vector<double> eye((size_t)n_pad * n_pad, 0.0);
+    for (int i = 0; i < n_pad; ++i) eye[(size_t)i * n_pad + i] = 1.0;
+    for (int k = 0; k < nk; ++k)
+      HIP_OK(hipMemcpyAsync(d_batch + (size_t)k * n_pad * n_pad, eye.data(),
+                            eye.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  for (int k = 0; k < nk; ++k) {
+    const ClassLayout& lay = klay[k];
+    const Level& Lref = P->levels[key_level[k]];
+    // patch: 0 = central, 1.. = existing face neighbours, last = zero element
+    int face_elem[6];
+    int Ep = 1;
+    for (int f = 0; f < 6; ++f) face_elem[f] = lay.strip_off[f] >= 0 ? Ep++ : -1;
+    const int zero = Ep++;
+    std::vector<int> pn(Ep * 6, -1);
+    for (int f = 0; f < 6; ++f) pn[0 * 6 + f] = face_elem[f];  // -1 = Dirichlet
+    for (int f = 0; f < 6; ++f) {
+      if (face_elem[f] < 0) continue;
+      const int b = face_elem[f];
+      for (int g = 0; g < 6; ++g) {
+        if (g == (f ^ 1)) {
+          pn[b * 6 + g] = 0;  // back to the central element
+        } else if (g == f) {
+          pn[b * 6 + g] = zero;  // far face: never reaches a subdomain row
+        } else {
+          const bool ext = (lay.flags >> g) & 1;  // same row of elements as the centre
+          pn[b * 6 + g] = ext ? -1 : zero;
+        }
+      }
+    }
+    const int n = lay.n;
+    std::vector<int> nb((size_t)n * Ep * 6);
+    for (int c = 0; c < n; ++c)
+      for (int q = 0; q < Ep * 6; ++q) nb[(size_t)c * Ep * 6 + q] = pn[q] < 0 ? -1 : pn[q] + c * Ep;
+    std::vector<int> idx(n);
+    for (int r = 0; r < n; ++r) {
+      const int seg = lay.seg_loc[r] / N3, loc = lay.seg_loc[r] % N3;
+      const int el = seg == 0 ? 0 : face_elem[seg - 1];
+      idx[r] = el * N3 + loc;
+    }
+    const long long stride = (long long)Ep * N3;
+    const long long tot = stride * n;
+    int* d_nb = dalloc<int>(nb.size());
+    std::unique_ptr<void, void (*)(void*)> g2(d_nb, [](void* p) { (void)hipFree(p); });
+    int* d_idx = dalloc<int>(n);
+    std::unique_ptr<void, void (*)(void*)> g3(d_idx, [](void* p) { (void)hipFree(p); });
+    double* d_X = dalloc<double>(tot);
+    std::unique_ptr<void, void (*)(void*)> g4(d_X, [](void* p) { (void)hipFree(p); });
+    double* d_AX = dalloc<double>(tot);
+    std::unique_ptr<void, void (*)(void*)> g5(d_AX, [](void* p) { (void)hipFree(p); });
+    upload(d_nb, nb, s);
+    upload(d_idx, idx, s);
+    HIP_OK(launch_fill(d_X, 0.0, tot, s));
+    HIP_OK(launch_unit_columns(d_X, stride, d_idx, n, s));
+    OpParams op = Lref.op;
+    op.E = (int)(Ep * (long long)n);
+    HIP_OK(launch_apply(N, kApply, d_X, d_AX, nullptr, nullptr, nullptr, d_nb, op, P->dt, P->acfg, s));
+    HIP_OK(launch_gather_columns(d_AX, stride, d_idx, n, d_batch + (size_t)k * n_pad * n_pad, n_pad, s));
+    HIP_OK(hipStreamSynchronize(s));
+  }
+  // batched Gauss-Jordan
+  double* d_col = dalloc<double>((size_t)nk * n_pad);
+  std::unique_ptr<void, void (*)(void*)> g6(d_col, [](void* p) { (void)hipFree(p); });
+  double* d_row = dalloc<double>((size_t)nk * n_pad);
+  std::unique_ptr<void, void (*)(void*)> g7(d_row, [](void* p) { (void)hipFree(p); });
+  for (int k = 0; k < n_pad; ++k) HIP_OK(launch_gj_step(d_batch, n_pad, nk, k, d_col, d_row, s));
+  // distribute the scaled, transposed inverses to every level and class
+  for (const Use& u : uses) {
+    Level& L = P->levels[u.level];
+    const ClassInfo& I = L.cls[u.cls];
+    const double scale = key_hx[u.key] / L.h[0];  // A_S(lambda h) = lambda A_S(h)
+    HIP_OK(launch_finish_inverse(d_batch + (size_t)u.key * n_pad * n_pad, n_pad, I.n, scale,
+                                 L.f32 ? nullptr : L.d_inv64 + I.inv_off,
+                                 L.f32 ? L.d_inv32 + I.inv_off : nullptr, s));
+  }
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------------------
+// Schwarz smoothing and the V-cycle
+// ---------------------------------------------------------------------------
+void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps, bool u_zero,
+                   hipStream_t s) {
+  Level& L = P->levels[l];
+  const int N = P->N;
+  const bool diag = P->diag_active && L.d_diag != nullptr;
+  for (int it = 0; it < steps; ++it) {
+    const double* r = b;
+    if (!(it == 0 && u_zero)) {
+      HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u, L.d_r, b, L.d_diag, nullptr,
+                          L.d_nbr, L.op, P->dt, P->acfg, s));
+      r = L.d_r;
+    }
+    HIP_OK(launch_gather(N, L.f32, r, L.d_rs, L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls,
+                         L.d_seg_loc, (int)L.E, s));
+    HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.f32 ? (const void*)L.d_inv32 : (const void*)L.d_inv64,
+                                 L.d_du, L.d_cls, L.d_tiles, L.ntiles, 1.0, s));
+    HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.d_weights, L.d_elem_class, L.d_elem_row, L.d_nbr,
+                          L.d_cls, nov_of(P), L.E, s));
+  }
+}
+
+void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
+  const int nl = (int)P->levels.size();
+  const int N = P->N;
+  std::vector<const double*> b(nl);
+  std::vector<double*> u(nl);
+  b[0] = r;
+  u[0] = z;
+  for (int l = 1; l < nl; ++l) {
+    b[l] = P->levels[l].d_b;
+    u[l] = P->levels[l].d_u;
+  }
+  for (int l = 0; l < nl; ++l) HIP_OK(launch_fill(u[l], 0.0, P->nd(l), s));
+  for (int l = 0; l < nl - 1; ++l) {
+    Level& L = P->levels[l];
+    schwarz_steps(P, l, b[l], u[l], P->opt.pre_smooth, true, s);
+    const bool diag = P->diag_active && L.d_diag != nullptr;
+    HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u[l], L.d_r, b[l], L.d_diag, nullptr,
+                        L.d_nbr, L.op, P->dt, P->acfg, s));
+    Level& C = P->levels[l + 1];
+    HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s));
+  }
+  schwarz_steps(P, nl - 1, b[nl - 1], u[nl - 1], P->opt.pre_smooth + P->opt.post_smooth, true, s);
+  for (int l = nl - 2; l >= 0; --l) {
+    Level& L = P->levels[l];
+    Level& C = P->levels[l + 1];
+    HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->dt, s));
+    schwarz_steps(P, l, b[l], u[l], P->opt.post_smooth, false, s);
+  }
+}
+
+void ensure_krylov(dgs_problem* P, int m) {
+  if (P->kry_m >= m) return;
+  for (double* p : {P->d_V, P->d_Z, P->d_partial, P->d_h, P->d_y, P->d_tmp, P->d_tmp2}) {
+    if (!p) continue;
+    auto it = std::find(P->allocations.begin(), P->allocations.end(), (void*)p);
+    if (it != P->allocations.end()) P->allocations.erase(it);
+    (void)hipFree(p);
+  }
+  const long long n = P->nd(0);
+  P->d_V = P->alloc<double>((size_t)(m + 1) * n);
+  P->d_Z = P->alloc<double>((size_t)m * n);
+  P->d_partial = P->alloc<double>((size_t)multidot_blocks(n) * (m + 2));
+  P->d_h = P->alloc<double>(3 * (m + 2));
+  P->d_y = P->alloc<double>(m + 1);
+  P->d_tmp = P->alloc<double>(n);
+  P->d_tmp2 = P->alloc<double>(n);
+  P->kry_m = m;
+}
+
+double device_norm2(dgs_problem* P, const double* x, long long n, hipStream_t s) {
+  HIP_OK(launch_multidot(x, n, 1, x, n, P->d_partial, P->d_h, s));
+  double v = 0;
+  HIP_OK(hipMemcpyAsync(&v, P->d_h, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return v;
+}
+
+// Apply either A or the linearised operator A + diag(d) on the finest level.
+void apply_fine(dgs_problem* P, const double* x, double* y, hipStream_t s) {
+  Level& L = P->levels[0];
+  const bool diag = P->diag_active && L.d_diag != nullptr;
+  HIP_OK(launch_apply(P->N, diag ? kApplyDiag : kApply, x, y, nullptr, L.d_diag, nullptr, L.d_nbr,
+                      L.op, P->dt, P->acfg, s));
+}
+
+void residual_fine(dgs_problem* P, const double* x, const double* b, double* r, hipStream_t s) {
+  Level& L = P->levels[0];
+  const bool diag = P->diag_active && L.d_diag != nullptr;
+  HIP_OK(launch_apply(P->N, diag ? kResidualDiag : kResidual, x, r, b, L.d_diag, nullptr, L.d_nbr,
+                      L.op, P->dt, P->acfg, s));
+}
+
+struct FgmresResult {
+  int iterations = 0;
+  double rel_residual = 0;
+  bool converged = false;
+  std::vector<double> history;
+};
+
+// Flexible GMRES (Saad Alg. 9.6) on the fine level, x holds x0 on entry.
+FgmresResult fgmres(dgs_problem* P, const double* b, double* x, double rtol, int max_iter,
+                    hipStream_t s) {
+  FgmresResult R;
+  const long long n = P->nd(0);
+  ensure_krylov(P, max_iter);
+  double* V = P->d_V;
+  double* Z = P->d_Z;
+  residual_fine(P, x, b, V, s);
+  const double beta2 = device_norm2(P, V, n, s);
+  if (!std::isfinite(beta2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite initial residual");
+  const double beta = std::sqrt(beta2);
+  R.history.push_back(1.0);
+  if (beta == 0.0) {
+    R.converged = true;
+    return R;
+  }
+  HIP_OK(launch_scale_by_inv_norm(V, V, P->d_h, n, s));
+  const int m = max_iter;
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
+  g[0] = beta;
+  std::vector<double> hh(2 * (m + 2));
+  int j = 0;
+  for (j = 0; j < m; ++j) {
+    double* vj = V + (size_t)j * n;
+    double* zj = Z + (size_t)j * n;
+    double* w = V + (size_t)(j + 1) * n;
+    vcycle(P, vj, zj, s);
+    apply_fine(P, zj, w, s);
+    // classical Gram-Schmidt, twice
+    double* h1 = P->d_h;
+    double* h2 = P->d_h + (m + 2);
+    double* hn = P->d_h + 2 * (m + 2);
+    HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h1, s));
+    HIP_OK(launch_multi_axpy(w, V, n, j + 1, h1, n, s));
+    HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h2, s));
+    HIP_OK(launch_multi_axpy(w, V, n, j + 1, h2, n, s));
+    HIP_OK(launch_multidot(w, n, 1, w, n, P->d_partial, hn, s));
+    HIP_OK(hipMemcpyAsync(hh.data(), P->d_h, sizeof(double) * 2 * (m + 2), hipMemcpyDeviceToHost, s));
+    double hn2 = 0;
+    HIP_OK(hipMemcpyAsync(&hn2, hn, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    double* col = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
+    for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(m + 2) + i];
+    col[j + 1] = std::sqrt(hn2);
+    for (int i = 0; i <= j + 1; ++i)
+      if (!std::isfinite(col[i])) throw DgsError(DGS_ERR_NONFINITE, "non-finite Hessenberg entry");
+    if (hn2 > 0.0) HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));
+    for (int i = 0; i < j; ++i) {
+      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double den = std::hypot(col[j], col[j + 1]);
+    cs[j] = col[j] / den;
+    sn[j] = col[j + 1] / den;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    R.history.push_back(std::fabs(g[j + 1]) / beta);
+    if (std::fabs(g[j + 1]) <= rtol * beta || hn2 == 0.0) {
+      R.converged = true;
+      ++j;
+      break;
+    }
+  }
+  const int k = std::min(j, m);
+  // back substitution for y
+  std::vector<double> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double t = g[i];
+    for (int q = i + 1; q < k; ++q) t -= H[(size_t)q * (m + 1) + i] * y[q];
+    y[i] = t / H[(size_t)i * (m + 1) + i];
+  }
+  if (k > 0) {
+    HIP_OK(hipMemcpyAsync(P->d_y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    HIP_OK(launch_combine(x, Z, n, k, P->d_y, n, s));
+  }
+  R.iterations = k;
+  residual_fine(P, x, b, P->d_tmp, s);
+  R.rel_residual = std::sqrt(device_norm2(P, P->d_tmp, n, s)) / beta;
+  return R;
+}
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const DgsError& e) {
+    return fail(e.code, e.msg);
+  } catch (const std::bad_alloc&) {
+    return fail(DGS_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(DGS_ERR_HIP, e.what());
+  }
+}
+
+void fill_stats(dgs_stats* st, const FgmresResult& R, double t0, double t_setup) {
+  if (!st) return;
+  st->iterations = R.iterations;
+  st->rel_residual = R.rel_residual;
+  st->t_solve_s = now_s() - t0;
+  st->t_setup_s = t_setup;
+  st->history_len = 0;
+  if (st->history && st->history_capacity > 0) {
+    const int n = std::min<int>(st->history_capacity, (int)R.history.size());
+    for (int i = 0; i < n; ++i) st->history[i] = R.history[i];
+    st->history_len = n;
+  }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+void dgs_default_options(dgs_options* o) {
+  if (!o) return;
+  o->overlap = 2;
+  o->mg_levels = 0;
+  o->pre_smooth = 3;
+  o->post_smooth = 3;
+  o->precision = DGS_FP64;
+  o->subdomain_iters = 3;
+  o->max_iter = 200;
+  o->rtol = 1e-10;
+}
+
+const char* dgs_last_error(void) { return g_last_error.c_str(); }
+
+int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
+                       const dgs_options* opt, void* stream, dgs_problem** out) {
+  return guarded([&]() -> int {
+    if (!domain || !elements || !out) return fail(DGS_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 8]");
+    if (!(penalty > 0.0) || !std::isfinite(penalty)) return fail(DGS_ERR_INVALID, "penalty must be > 0");
+    for (int d = 0; d < 3; ++d) {
+      if (elements[d] < 1) return fail(DGS_ERR_INVALID, "element counts must be >= 1");
+      if (!(domain->upper[d] > domain->lower[d]) || !std::isfinite(domain->upper[d] - domain->lower[d]))
+        return fail(DGS_ERR_INVALID, "domain upper must exceed lower");
+    }
+    dgs_options o;
+    dgs_default_options(&o);
+    if (opt) o = *opt;
+    if (o.overlap < 1 || o.pre_smooth < 0 || o.post_smooth < 0 || o.mg_levels < 0 ||
+        o.max_iter < 1 || !(o.rtol > 0.0) || o.subdomain_iters < 0 ||
+        (o.precision != DGS_FP64 && o.precision != DGS_MIXED))
+      return fail(DGS_ERR_INVALID, "invalid options");
+    const long long E0 = (long long)elements[0] * elements[1] * elements[2];
+    const long long N3 = (long long)(p + 1) * (p + 1) * (p + 1);
+    if (E0 > (1LL << 30) / 8 || E0 * N3 > (1LL << 31) - 1)
+      return fail(DGS_ERR_INVALID, "mesh too large for 32-bit element indexing");
+    const double t0 = now_s();
+    hipStream_t s = as_stream(stream);
+    std::unique_ptr<dgs_problem> P(new dgs_problem());
+    P->opt = o;
+    P->p = p;
+    P->N = p + 1;
+    P->penalty = penalty;
+    P->dom = *domain;
+    P->ht = make_tables(P->N);
+    P->dt = to_dev(P->ht);
+    // hierarchy (Sec. III.C.1): halve every even element count > 1
+    int n[3] = {elements[0], elements[1], elements[2]};
+    const int max_levels = o.mg_levels > 0 ? o.mg_levels : 64;
+    for (int l = 0; l < max_levels; ++l) {
+      Level L;
+      L.n[0] = n[0];
+      L.n[1] = n[1];
+      L.n[2] = n[2];
+      bool any = false;
+      for (int d = 0; d < 3; ++d) {
+        L.split[d] = (n[d] > 1 && n[d] % 2 == 0) ? 1 : 0;
+        any = any || L.split[d];
+      }
+      P->levels.push_back(L);
+      if (!any || l == max_levels - 1) break;
+      for (int d = 0; d < 3; ++d)
+        if (L.split[d]) n[d] /= 2;
+    }
+    const int nl = (int)P->levels.size();
+    for (int l = 0; l < nl; ++l) {
+      Level& L = P->levels[l];
+      L.has_coarser = l < nl - 1;
+      if (!L.has_coarser) L.split[0] = L.split[1] = L.split[2] = 0;
+      // mixed precision: FP32 subdomain solves everywhere except the coarsest grid
+      L.f32 = (o.precision == DGS_MIXED) && L.has_coarser;
+      build_level_mesh(P.get(), L, s);
+      build_level_schwarz(P.get(), L, s);
+    }
+    build_inverses(P.get(), s);
+    HIP_OK(hipStreamSynchronize(s));
+    P->t_setup = now_s() - t0;
+    *out = P.release();
+    return DGS_OK;
+  });
+}
+
+int dgs_destroy_problem(dgs_problem* prob) {
+  return guarded([&]() -> int {
+    if (!prob) return DGS_OK;
+    (void)hipDeviceSynchronize();
+    delete prob;
+    return DGS_OK;
+  });
+}
+
+int dgs_num_dofs(const dgs_problem* prob, long long* n) {
+  if (!prob || !n) return fail(DGS_ERR_INVALID, "NULL argument");
+  *n = prob->nd(0);
+  return DGS_OK;
+}
+
+int dgs_node_coordinates(const dgs_problem* prob, double* xyz, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !xyz) return fail(DGS_ERR_INVALID, "NULL argument");
+    const Level& L = prob->levels[0];
+    HIP_OK(launch_coords(prob->N, xyz, L.n, prob->dom.lower, L.h, prob->dt, as_stream(stream)));
+    return DGS_OK;
+  });
+}
+
+int dgs_apply_mass(const dgs_problem* prob, const double* f, double* b, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !f || !b) return fail(DGS_ERR_INVALID, "NULL argument");
+    const Level& L = prob->levels[0];
+    HIP_OK(launch_mass(prob->N, f, b, L.E, L.h, prob->dt, as_stream(stream)));
+    return DGS_OK;
+  });
+}
+
+int dgs_apply_operator(dgs_problem* prob, const double* u, double* Au, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !u || !Au) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (u == Au) return fail(DGS_ERR_INVALID, "u and Au must not overlap");
+    Level& L = prob->levels[0];
+    HIP_OK(launch_apply(prob->N, kApply, u, Au, nullptr, nullptr, nullptr, L.d_nbr, L.op, prob->dt,
+                        prob->acfg, as_stream(stream)));
+    return DGS_OK;
+  });
+}
+
+int dgs_schwarz_smooth(dgs_problem* prob, const double* b, double* u, int steps, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (steps < 0) return fail(DGS_ERR_INVALID, "steps must be >= 0");
+    schwarz_steps(prob, 0, b, u, steps, false, as_stream(stream));
+    return DGS_OK;
+  });
+}
+
+int dgs_precondition(dgs_problem* prob, const double* r, double* z, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !r || !z) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (r == z) return fail(DGS_ERR_INVALID, "r and z must not overlap");
+    vcycle(prob, r, z, as_stream(stream));
+    return DGS_OK;
+  });
+}
+
+int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    const double t0 = now_s();
+    prob->diag_active = false;
+    FgmresResult R = fgmres(prob, b, u, prob->opt.rtol, prob->opt.max_iter, as_stream(stream));
+    fill_stats(stats, R, t0, prob->t_setup);
+    if (stats) {
+      stats->newton_steps = 0;
+      stats->backtracks = 0;
+    }
+    if (!std::isfinite(R.rel_residual)) return fail(DGS_ERR_NONFINITE, "non-finite residual");
+    return R.converged ? DGS_OK : DGS_NOT_CONVERGED;
+  });
+}
+
+int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta, const double* b,
+                     double* u, double newton_rtol, double linear_rtol, int max_newton,
+                     dgs_stats* stats, void* stream) {
+  return fail(DGS_ERR_INVALID, "newton_solve not available yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+"""GPU parity of the Schwarz smoother, the V-cycle and the FGMRES solve
+against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import krylov, mesh as omesh, multigrid, operator as oop, schwarz
+from tests.gpu_util import announce, rel_max, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+SMOOTH_CASES = [((1, 1, 1), 3, 2), ((2, 2, 2), 3, 2), ((3, 2, 4), 2, 2), ((3, 3, 3), 4, 1),
+                ((2, 3, 2), 5, 3), ((4, 2, 2), 6, 2), ((2, 2, 1), 1, 2)]
+
+
+@pytest.mark.parametrize("elements,p,overlap", SMOOTH_CASES)
+def test_schwarz_steps_match_oracle(elements, p, overlap):
+    import paper_2111_06767_amd as dg
+    announce(f"schwarz parity elements={elements} p={p} overlap={overlap}")
+    upper = (1.0, 1.3, 0.7)
+    prob = dg.Problem((0, 0, 0), upper, elements, p, penalty=1.5, overlap=overlap)
+    m = omesh.BoxMesh((0, 0, 0), upper, elements, p)
+    b = W.random_normal(21, m.ndof)
+    u0 = W.random_uniform(22, m.ndof)
+    S = schwarz.SchwarzSmoother(m, 1.5, overlap)
+    for steps in (1, 2):
+        ref = S.smooth(u0, b, steps)
+        u = to_gpu(u0)
+        prob.smooth(to_gpu(b), u, steps)
+        assert rel_max(to_np(u), ref) < 1e-11, (steps, rel_max(to_np(u), ref))
+
+
+@pytest.mark.parametrize("elements,p,levels", [((2, 2, 2), 3, 2), ((4, 2, 2), 2, 3), ((4, 4, 3), 3, 0),
+                                               ((4, 4, 4), 4, 3), ((2, 2, 2), 6, 2)])
+def test_vcycle_matches_oracle(elements, p, levels):
+    import paper_2111_06767_amd as dg
+    announce(f"vcycle parity elements={elements} p={p} levels={levels}")
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels)
+    m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), elements, p)
+    V = multigrid.VCycle(m, 1.5, levels=levels if levels else 64)
+    r = W.random_normal(31, m.ndof)
+    got = to_np(prob.precondition(to_gpu(r)))
+    assert rel_max(got, V(r)) < 1e-10, rel_max(got, V(r))
+
+
+def _c1_problem():
+    m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 2, 2), 3)
+    x, y, z = m.node_coordinates()
+    b = oop.apply_mass(m, W.sin_product_source(x, y, z)).reshape(-1)
+    return m, b, W.sin_product_solution(x, y, z).reshape(-1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c1_solve_matches_oracle(precision):
+    import paper_2111_06767_amd as dg
+    announce(f"c1 solve {precision}")
+    m, b, uex = _c1_problem()
+    A = lambda v: oop.apply_operator(m, v.reshape(m.E, 4, 4, 4), 1.5).reshape(-1)
+    u_ref, its_ref, _ = krylov.fgmres(A, b, precondition=multigrid.VCycle(m, 1.5, levels=2),
+                                      rtol=1e-10)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), (2, 2, 2), 3, mg_levels=2, precision=precision)
+    u, st = prob.solve(to_gpu(b))
+    u = to_np(u)
+    assert st["converged"]
+    assert st["rel_residual"] <= 1e-10
+    # the oracle's own operator confirms the residual
+    assert np.linalg.norm(b - A(u)) / np.linalg.norm(b) <= 1e-10
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
+    if precision == "fp64":
+        assert abs(st["iterations"] - its_ref) <= 1
+    assert np.sqrt(np.mean((u - uex) ** 2)) < 1e-3  # discretisation error level
+
+
+def test_random_initial_guess_and_fgmres_history():
+    import paper_2111_06767_amd as dg
+    announce("solve random x0 3x3x3 p=4")
+    m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (4, 4, 4), 3)
+    x, y, z = m.node_coordinates()
+    b = oop.apply_mass(m, W.sin_product_source(x, y, z)).reshape(-1)
+    x0 = W.random_uniform(W.SEED_RANDOM_X0, m.ndof)
+    A = lambda v: oop.apply_operator(m, v.reshape(m.E, 4, 4, 4), 1.5).reshape(-1)
+    u_ref, its_ref, hist_ref = krylov.fgmres(A, b, x0=x0, precondition=multigrid.VCycle(m, 1.5, levels=3),
+                                             rtol=1e-10)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), (4, 4, 4), 3, mg_levels=3)
+    u, st = prob.solve(to_gpu(b), to_gpu(x0))
+    assert st["converged"] and st["rel_residual"] <= 1e-10
+    assert abs(st["iterations"] - its_ref) <= 1
+    k = min(len(hist_ref), len(st["history"]))
+    np.testing.assert_allclose(st["history"][:k], hist_ref[:k], rtol=1e-6, atol=1e-13)
+    assert np.linalg.norm(to_np(u) - u_ref) / np.linalg.norm(u_ref) <= 1e-9
+
+
+def test_not_converged_and_nonfinite():
+    import torch
+    import paper_2111_06767_amd as dg
+    announce("error paths")
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), (2, 2, 2), 3, max_iter=1, rtol=1e-14)
+    b = to_gpu(W.random_normal(3, prob.ndof))
+    u, st = prob.solve(b)
+    assert not st["converged"] and st["iterations"] == 1
+    bad = b.clone()
+    bad[5] = float("nan")
+    with pytest.raises(dg.DgsError) as ei:
+        prob.solve(bad)
+    assert ei.value.code == dg.DGS_ERR_NONFINITE
+    del torch
