@@ -70,6 +70,7 @@ typedef struct {
                           preconditioned by it (Sec. III.E.1)                    [3] */
   int max_iter;        /* FGMRES iteration limit (no restart)                   [200] */
   double rtol;         /* FGMRES relative residual tolerance                   [1e-10] */
+  int use_graphs;      /* 1 = replay each V-cycle from a captured hipGraph        [1] */
 } dgs_options;
 
 /* Statistics of a solve.  `history` may be NULL; otherwise it receives up to

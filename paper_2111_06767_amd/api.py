@@ -39,7 +39,8 @@ class Options(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int), ("mg_levels", ctypes.c_int),
                 ("pre_smooth", ctypes.c_int), ("post_smooth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("subdomain_iters", ctypes.c_int),
-                ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double)]
+                ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("use_graphs", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

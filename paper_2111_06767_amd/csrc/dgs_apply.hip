@@ -1,13 +1,19 @@
 // DG operator apply on gfx950 (Sec. II, eqs. dg_op_auxvars, dg_op_primal,
 // massmat, stiffmat, liftop, numflux, penalty, bc).
 //
-// One kernel computes A u for a batch of elements.  Each element is handled by
-// N^2 lanes; lane (i, j) owns the z-line of points (i, j, 0..N-1) in
-// registers.  Derivatives along z stay in registers, derivatives along x and
-// y go through LDS (sum factorisation).  The neighbour data the numerical flux
-// needs (the neighbour's trace and its own normal derivative on the shared
-// face) is computed from the neighbour's points read straight from global
-// memory, so the whole apply is one pass: read u, write A u.
+// One kernel computes A u for a batch of elements with line-based sum
+// factorisation.  Each element is handled by N^2 lanes; lane t = a + N b
+// plays three roles: it owns the x-line (j, k) = (a, b), the y-line
+// (i, k) = (a, b) and the z-line (i, j) = (a, b).  The z-line lives in
+// registers; x- and y-lines are read from one LDS copy of the element.  Each
+// role applies the 1D derivative to its whole line, adds the lift and the
+// numerical flux at the line's two face points (the neighbour's trace and its
+// own normal derivative come from the neighbour's line, read straight from
+// global memory), and applies the transposed derivative.  The three partial
+// results meet in LDS.  The derivative matrix entries are compile-time
+// indexed, so they are uniform across the wave (scalar loads), and every LDS
+// access is one read or write per point.  The whole apply is one pass: read u,
+// write A u.
 //
 // With LGL quadrature the strong form is evaluated through summation by parts,
 //   -M D_d v_d + ML_d n_d v_d = D_d^T M v_d      (exact for LGL points),
@@ -21,214 +27,244 @@
 namespace dgs {
 namespace {
 
-// Point with index m along dimension d and transverse indices (a, b) (lower
-// transverse dimension first), as an offset inside one element.
-template <int N>
-__device__ __forceinline__ int face_line_point(int d, int m, int a, int b) {
-  if (d == 0) return (b * N + a) * N + m;
-  if (d == 1) return (b * N + m) * N + a;
-  return (m * N + b) * N + a;
-}
-
 template <int N, int EPB>
 __global__ void __launch_bounds__(256)
 k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ bvec,
         const double* __restrict__ aux0, const double* __restrict__ aux1,
         const int* __restrict__ nbr, OpParams P, DevTables T, int mode) {
   constexpr int N2 = N * N, N3 = N2 * N;
-  __shared__ double sD[N * N];
+  constexpr int PIT = N + 1;          // padded row pitch (bank spread for line reads)
+  constexpr int S3 = N * N * PIT;
+  __shared__ double sU[EPB][S3], sX[EPB][S3];
   __shared__ double sw[N];
-  __shared__ double su[EPB][N3];
-  __shared__ double sq[EPB][N3];
-  __shared__ double sf[EPB][6][2][N2];
 
   const int tid = threadIdx.x;
-  for (int t = tid; t < N * N; t += blockDim.x) sD[t] = T.D[t];
   if (tid < N) sw[tid] = T.w[tid];
   const int slot = tid / N2;
-  const int ij = tid - slot * N2;
-  const int i = ij % N, j = ij / N;
-  const long long e = (long long)blockIdx.x * EPB + slot;
+  const int t = tid - slot * N2;
+  const int a = t % N, b = t / N;
+  // XCD-aware block order: the hardware deals workgroups round-robin to the
+  // 8 XCDs, so hand each XCD a contiguous run of elements (neighbours then
+  // share that XCD's L2).
+  const unsigned G = gridDim.x, per = G / 8u;
+  const unsigned blk = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
+  const long long e = (long long)blk * EPB + slot;
   const bool active = (slot < EPB) && (e < P.E);
-  const double rh0 = 2.0 / P.h[0], rh1 = 2.0 / P.h[1], rh2 = 2.0 / P.h[2];
+  const double rh0 = P.rh[0], rh1 = P.rh[1], rh2 = P.rh[2];
+  const double J = P.J;
+  auto L = [](int k, int j, int i) { return (k * N + j) * PIT + i; };
 
-  double uk[N];
+  double uz[N], zlo[N], zhi[N];
   int nb[6];
   if (active) {
     const double* ue = u + e * N3;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      uk[k] = ue[k * N2 + ij];
-      su[slot][k * N2 + ij] = uk[k];
+      uz[k] = ue[k * N2 + t];
+      sU[slot][L(k, b, a)] = uz[k];
     }
 #pragma unroll
     for (int f = 0; f < 6; ++f) nb[f] = nbr[e * 6 + f];
+    // neighbour z-lines, issued early
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      zlo[m] = nb[4] >= 0 ? u[(long long)nb[4] * N3 + m * N2 + t] : 0.0;
+      zhi[m] = nb[5] >= 0 ? u[(long long)nb[5] * N3 + m * N2 + t] : 0.0;
+    }
   }
   __syncthreads();
 
-  // Neighbour trace and neighbour normal derivative on each shared face.
   if (active) {
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      if (nb[f] < 0) continue;
-      const int d = f >> 1;
-      const int fi = (f & 1) ? 0 : N - 1;  // neighbour's layer on the shared face
-      const double* ub = u + (long long)nb[f] * N3;
-      double dn = 0.0, ue = 0.0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        const double v = ub[face_line_point<N>(d, m, i, j)];
-        dn += sD[fi * N + m] * v;
-        if (m == fi) ue = v;
-      }
-      const double rh = d == 0 ? rh0 : (d == 1 ? rh1 : rh2);
-      sf[slot][f][0][ij] = ue;
-      sf[slot][f][1][ij] = dn * rh;
-    }
-  }
-
-  double gx[N], gy[N], gz[N], au[N];
-  const double J = P.h[0] * P.h[1] * P.h[2] * 0.125;
-  if (active) {
-    const double* s = su[slot];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      double ax = 0.0, ay = 0.0, az = 0.0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) {
-        ax += sD[i * N + m] * s[k * N2 + j * N + m];
-        ay += sD[j * N + m] * s[k * N2 + m * N + i];
-        az += sD[k * N + m] * uk[m];
-      }
-      gx[k] = ax * rh0;
-      gy[k] = ay * rh1;
-      gz[k] = az * rh2;
-      au[k] = 0.0;
-    }
-  }
-  __syncthreads();  // neighbour face data visible
-
-  if (active) {
-    const double wend = sw[0];
-    // faces normal to x: lanes with i = 0 (f = 0) or i = N-1 (f = 1)
-    if (i == 0 || i == N - 1) {
-      const int f = (i == 0) ? 0 : 1;
-      const double sgn = (i == 0) ? -1.0 : 1.0;
-      const double sig = P.penalty * (double)(N * N) / P.h[0];
-      const double JF = J * rh0;
-      const double lf = 1.0 / (P.h[0] * wend);
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const int fn = j + N * k;
-        const double ui = uk[k], gi = gx[k];
-        double ue, ge;
-        if (nb[f] >= 0) {
-          ue = sf[slot][f][0][fn];
-          ge = sf[slot][f][1][fn];
-        } else {
-          ue = -ui;
-          ge = gi;
-        }
-        au[k] -= JF * sw[j] * sw[k] * (0.5 * sgn * (gi + ge) - sig * (ui - ue));
-        gx[k] += lf * sgn * (ue - ui);
-      }
-    }
-    // faces normal to y: lanes with j = 0 (f = 2) or j = N-1 (f = 3)
-    if (j == 0 || j == N - 1) {
-      const int f = (j == 0) ? 2 : 3;
-      const double sgn = (j == 0) ? -1.0 : 1.0;
-      const double sig = P.penalty * (double)(N * N) / P.h[1];
-      const double JF = J * rh1;
-      const double lf = 1.0 / (P.h[1] * wend);
-#pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const int fn = i + N * k;
-        const double ui = uk[k], gi = gy[k];
-        double ue, ge;
-        if (nb[f] >= 0) {
-          ue = sf[slot][f][0][fn];
-          ge = sf[slot][f][1][fn];
-        } else {
-          ue = -ui;
-          ge = gi;
-        }
-        au[k] -= JF * sw[i] * sw[k] * (0.5 * sgn * (gi + ge) - sig * (ui - ue));
-        gy[k] += lf * sgn * (ue - ui);
-      }
-    }
-    // faces normal to z: every lane, points k = 0 (f = 4) and k = N-1 (f = 5)
+    const double wa = sw[a], wb = sw[b];
+    // ---------------- x role: line (j, k) = (a, b) ----------------
     {
-      const double sig = P.penalty * (double)(N * N) / P.h[2];
-      const double JF = J * rh2;
-      const double lf = 1.0 / (P.h[2] * wend);
-      const double wf = JF * sw[i] * sw[j];
+      double line[N], g[N];
+#pragma unroll
+      for (int m = 0; m < N; ++m) line[m] = sU[slot][L(b, a, m)];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) acc += T.D[i * N + m] * line[m];
+        g[i] = acc * rh0;
+      }
+      const double sig = P.sig[0];
+      const double wf = J * rh0 * wa * wb;
+      const double lf = P.lf[0];
+      double flux[2];
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
-        const int f = 4 + side;
-        const int k = side ? N - 1 : 0;
-        const double sgn = side ? 1.0 : -1.0;
-        const double ui = uk[k], gi = gz[k];
+        const int ie = side ? N - 1 : 0;
+        const int fi = side ? 0 : N - 1;
+        const double sg = side ? 1.0 : -1.0;
+        const int nbr_e = nb[side];
+        const double ui = line[ie], gi = g[ie];
         double ue, ge;
-        if (nb[f] >= 0) {
-          ue = sf[slot][f][0][ij];
-          ge = sf[slot][f][1][ij];
+        if (nbr_e >= 0) {
+          const double* ub = u + (long long)nbr_e * N3 + b * N2 + a * N;
+          double acc = 0.0, v = 0.0;
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const double x = ub[m];
+            acc += T.D[fi * N + m] * x;
+            if (m == fi) v = x;
+          }
+          ue = v;
+          ge = acc * rh0;
         } else {
           ue = -ui;
           ge = gi;
         }
-        au[k] -= wf * (0.5 * sgn * (gi + ge) - sig * (ui - ue));
-        gz[k] += lf * sgn * (ue - ui);
+        flux[side] = wf * (0.5 * sg * (gi + ge) - sig * (ui - ue));
+        g[ie] += lf * sg * (ue - ui);
+      }
+      const double jw = J * wa * wb;
+#pragma unroll
+      for (int m = 0; m < N; ++m) g[m] *= jw * sw[m];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) acc += T.D[m * N + i] * g[m];
+        double c = acc * rh0;
+        if (i == 0) c -= flux[0];
+        if (i == N - 1) c -= flux[1];
+        sX[slot][L(b, a, i)] = c;
       }
     }
   }
-  __syncthreads();  // every lane has finished reading su
+  __syncthreads();  // x-role partial sums complete before the y role adds to them
   if (active) {
+    const double wa = sw[a], wb = sw[b];
+    // ---------------- y role: line (i, k) = (a, b) ----------------
+    {
+      double line[N], g[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-      const double jw = J * sw[i] * sw[j] * sw[k];
-      su[slot][k * N2 + ij] = jw * gx[k];
-      sq[slot][k * N2 + ij] = jw * gy[k];
-      gz[k] *= jw;
+      for (int m = 0; m < N; ++m) line[m] = sU[slot][L(b, m, a)];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) acc += T.D[j * N + m] * line[m];
+        g[j] = acc * rh1;
+      }
+      const double sig = P.sig[1];
+      const double wf = J * rh1 * wa * wb;
+      const double lf = P.lf[1];
+      double flux[2];
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int je = side ? N - 1 : 0;
+        const int fi = side ? 0 : N - 1;
+        const double sg = side ? 1.0 : -1.0;
+        const int nbr_e = nb[2 + side];
+        const double ui = line[je], gi = g[je];
+        double ue, ge;
+        if (nbr_e >= 0) {
+          const double* ub = u + (long long)nbr_e * N3 + b * N2 + a;
+          double acc = 0.0, v = 0.0;
+#pragma unroll
+          for (int m = 0; m < N; ++m) {
+            const double x = ub[m * N];
+            acc += T.D[fi * N + m] * x;
+            if (m == fi) v = x;
+          }
+          ue = v;
+          ge = acc * rh1;
+        } else {
+          ue = -ui;
+          ge = gi;
+        }
+        flux[side] = wf * (0.5 * sg * (gi + ge) - sig * (ui - ue));
+        g[je] += lf * sg * (ue - ui);
+      }
+      const double jw = J * wa * wb;
+#pragma unroll
+      for (int m = 0; m < N; ++m) g[m] *= jw * sw[m];
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) acc += T.D[m * N + j] * g[m];
+        double c = acc * rh1;
+        if (j == 0) c -= flux[0];
+        if (j == N - 1) c -= flux[1];
+        sX[slot][L(b, j, a)] += c;
+      }
     }
   }
   __syncthreads();
+
   if (active) {
-    const double* qx = su[slot];
-    const double* qy = sq[slot];
+    const double wa = sw[a], wb = sw[b];
+    // ---------------- z role: line (i, j) = (a, b), in registers ----------------
+    double g[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      double ax = 0.0, ay = 0.0, az = 0.0;
+      double acc = 0.0;
 #pragma unroll
-      for (int m = 0; m < N; ++m) {
-        ax += sD[m * N + i] * qx[k * N2 + j * N + m];
-        ay += sD[m * N + j] * qy[k * N2 + m * N + i];
-        az += sD[m * N + k] * gz[m];
+      for (int m = 0; m < N; ++m) acc += T.D[k * N + m] * uz[m];
+      g[k] = acc * rh2;
+    }
+    const double sig = P.sig[2];
+    const double wf = J * rh2 * wa * wb;
+    const double lf = P.lf[2];
+    double flux[2];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int ke = side ? N - 1 : 0;
+      const int fi = side ? 0 : N - 1;
+      const double sg = side ? 1.0 : -1.0;
+      const double ui = uz[ke], gi = g[ke];
+      double ue, ge;
+      if (nb[4 + side] >= 0) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) acc += T.D[fi * N + m] * (side ? zhi[m] : zlo[m]);
+        ue = side ? zhi[fi] : zlo[fi];
+        ge = acc * rh2;
+      } else {
+        ue = -ui;
+        ge = gi;
       }
-      double r = au[k] + rh0 * ax + rh1 * ay + rh2 * az;
-      const long long g = e * N3 + k * N2 + ij;
+      flux[side] = wf * (0.5 * sg * (gi + ge) - sig * (ui - ue));
+      g[ke] += lf * sg * (ue - ui);
+    }
+    const double jw = J * wa * wb;
+#pragma unroll
+    for (int m = 0; m < N; ++m) g[m] *= jw * sw[m];
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) acc += T.D[m * N + k] * g[m];
+      double r = acc * rh2 + sX[slot][L(k, b, a)];
+      if (k == 0) r -= flux[0];
+      if (k == N - 1) r -= flux[1];
+      const long long gi = e * N3 + k * N2 + t;
       switch (mode) {
         case kApply:
           break;
         case kResidual:
-          r = bvec[g] - r;
+          r = bvec[gi] - r;
           break;
         case kApplyDiag:
-          r += aux0[g] * uk[k];
+          r += aux0[gi] * uz[k];
           break;
         case kResidualDiag:
-          r = bvec[g] - (r + aux0[g] * uk[k]);
+          r = bvec[gi] - (r + aux0[gi] * uz[k]);
           break;
         case kPuncture: {
-          const double t = aux0[g] * (1.0 + uk[k]) + 1.0;
-          const double t2 = t * t, t4 = t2 * t2;
-          const double S = -aux1[g] / (t4 * t2 * t);
-          r += J * sw[i] * sw[j] * sw[k] * S - bvec[g];
+          const double tt = aux0[gi] * (1.0 + uz[k]) + 1.0;
+          const double t2 = tt * tt, t4 = t2 * t2;
+          const double S = -aux1[gi] / (t4 * t2 * tt);
+          r += jw * sw[k] * S - bvec[gi];
           break;
         }
         default:
           break;
       }
-      out[g] = r;
+      out[gi] = r;
     }
   }
 }
@@ -239,7 +275,8 @@ hipError_t launch_apply_t(int mode, const double* u, double* out, const double* 
                           const OpParams& P, const DevTables& T, hipStream_t s) {
   if (P.E <= 0) return hipSuccess;
   const int threads = ((EPB * N * N + 63) / 64) * 64;
-  const long long blocks = ((long long)P.E + EPB - 1) / EPB;
+  const long long need = ((long long)P.E + EPB - 1) / EPB;
+  const long long blocks = ((need + 7) / 8) * 8;  // whole rounds over the 8 XCDs
   hipLaunchKernelGGL((k_apply<N, EPB>), dim3((unsigned)blocks), dim3(threads), 0, s, u, out, b,
                      aux0, aux1, nbr, P, T, mode);
   return hipGetLastError();

@@ -36,7 +36,11 @@ struct OpParams {
   double h[3];
   double penalty;
   int E;
+  // derived on the host (set_derived): 2/h_d, sigma_d, lift factor 1/(h_d w_end),
+  // J = h_x h_y h_z / 8
+  double rh[3], sig[3], lf[3], J;
 };
+void set_derived(OpParams& P, int N, double w_end);
 
 // Operator modes of the fused apply kernel.
 enum ApplyMode : int {
@@ -64,27 +68,36 @@ hipError_t launch_coords(int N, double* xyz, const int n[3], const double lower[
 struct ClassInfo {
   int n;            // subdomain size n_S
   int count;        // number of subdomains (elements) in the class
-  long long inv_off;  // offset of this class's n x n matrix
+  long long inv_off;  // offset of this class's n x n matrix (transposed inverse)
+  double scale;       // factor applied to the stored inverse for this level
   long long rs_off;   // offset of this class's [count][n] block in RS / DU
   int layout_off;     // offset into seg_loc / weights
   int strip_off[6];   // offset of each face strip in the layout, -1 if absent
 };
 
+// One output tile of a class GEMM over the K range [k0, k1); split-K part
+// `part` writes its partial product to part * part_stride + rs_off.
 struct GemmTile {
-  int cls, m0, n0, pad;
+  int cls, m0, n0, part, k0, k1;
 };
 
 // r_S = R_S r for every subdomain (one per element) into row elem_row[e].
 hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* elem_class,
                          const long long* elem_row, const int* nbr, const ClassInfo* cls,
                          const int* seg_loc, int E, hipStream_t s);
+// Grouped subdomain GEMM: tiles_big use 64 x 128 block tiles (classes with
+// many subdomains), tiles_small 16 x 128 (classes with few).
+constexpr int kGemmBigM = 64, kGemmSmallM = 16, kGemmN = 128, kGemmSmallCount = 32;
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, const void* inv, void* du,
-                                 const ClassInfo* cls, const GemmTile* tiles, int ntiles,
-                                 double scale, hipStream_t s);
-// u += sum_S R_S^T (w_S du_S), pulled per point.
-hipError_t launch_scatter(int N, bool f32, double* u, const void* du, const double* weights,
-                          const int* elem_class, const long long* elem_row, const int* nbr,
-                          const ClassInfo* cls, int nov, long long E, hipStream_t s);
+                                 long long part_stride, const ClassInfo* cls,
+                                 const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
+                                 int nsmall, hipStream_t s);
+// u += sum_S R_S^T (w_S du_S), pulled per point; du is the sum of `parts`
+// split-K partial products spaced part_stride apart.
+hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
+                          long long part_stride, const double* weights, const int* elem_class,
+                          const long long* elem_row, const int* nbr, const ClassInfo* cls, int nov,
+                          long long E, hipStream_t s);
 
 // Multigrid transfer (per-dimension split flags).
 hipError_t launch_restrict(int N, const double* fine, double* coarse, const int nf[3],

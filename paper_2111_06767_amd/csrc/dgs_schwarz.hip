@@ -43,11 +43,19 @@ k_gather_rows(const double* __restrict__ r, T* __restrict__ rs, const int* __res
 // Pull-based weighted scatter: every point adds its own subdomain's
 // correction and the overlap corrections of the face neighbours' subdomains.
 template <typename T>
+__device__ __forceinline__ double sum_parts(const T* __restrict__ du, long long idx, int parts,
+                                            long long stride) {
+  double v = 0.0;
+  for (int q = 0; q < parts; ++q) v += (double)du[q * stride + idx];
+  return v;
+}
+
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_scatter(double* __restrict__ u, const T* __restrict__ du, const double* __restrict__ weights,
-          const int* __restrict__ elem_class, const long long* __restrict__ elem_row,
-          const int* __restrict__ nbr, const ClassInfo* __restrict__ cls, int N, int nov,
-          long long total) {
+k_scatter(double* __restrict__ u, const T* __restrict__ du, int parts, long long pstride,
+          const double* __restrict__ weights, const int* __restrict__ elem_class,
+          const long long* __restrict__ elem_row, const int* __restrict__ nbr,
+          const ClassInfo* __restrict__ cls, int N, int nov, long long total) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int N2 = N * N, N3 = N2 * N;
@@ -55,7 +63,7 @@ k_scatter(double* __restrict__ u, const T* __restrict__ du, const double* __rest
   const int loc = (int)(g - e * N3);
   const int idx[3] = {loc % N, (loc / N) % N, loc / N2};
   const ClassInfo ce = cls[elem_class[e]];
-  double acc = weights[ce.layout_off + loc] * (double)du[elem_row[e] + loc];
+  double acc = weights[ce.layout_off + loc] * sum_parts(du, elem_row[e] + loc, parts, pstride);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int b = nbr[e * 6 + f];
@@ -69,7 +77,7 @@ k_scatter(double* __restrict__ u, const T* __restrict__ du, const double* __rest
     const ClassInfo cb = cls[elem_class[b]];
     const int so = cb.strip_off[f ^ 1];
     const int k = so + layer * N2 + t1 * N + t0;
-    acc += weights[cb.layout_off + k] * (double)du[elem_row[b] + k];
+    acc += weights[cb.layout_off + k] * sum_parts(du, elem_row[b] + k, parts, pstride);
   }
   u[g] += acc;
 }
@@ -103,70 +111,90 @@ struct Mfma<float> {
   static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T>
+// Tiled grouped GEMM.  Four waves arranged WM x WN, each computing TM x TN
+// MFMA tiles of 16 x 16; the block tile is BM = 16 WM TM rows by BN = 16 WN TN
+// columns, the K loop steps by BK with the next tile prefetched into registers
+// while the current one is multiplied out of LDS.
+template <typename T, int WM, int WN, int TM, int TN, int BK>
 __global__ void __launch_bounds__(256)
 k_sub_gemm(const T* __restrict__ rs, const T* __restrict__ inv, T* __restrict__ du,
-           const ClassInfo* __restrict__ cls, const GemmTile* __restrict__ tiles, double scale) {
-  constexpr int BM = 64, BN = 64, BK = 16;
+           long long pstride, const ClassInfo* __restrict__ cls,
+           const GemmTile* __restrict__ tiles) {
+  constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
+  constexpr int PA = 1, PB = 4;
+  constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+  static_assert(NA >= 1 && NB >= 1 && (BM * BK) % 256 == 0 && (BK * BN) % 256 == 0, "tile");
   typedef typename Mfma<T>::v4 v4;
-  __shared__ T As[BK][BM + 4];
-  __shared__ T Bs[BK][BN + 4];
+  __shared__ T As[BK][BM + PA];
+  __shared__ T Bs[BK][BN + PB];
   const GemmTile tl = tiles[blockIdx.x];
   const ClassInfo ci = cls[tl.cls];
   const int n = ci.n, M = ci.count;
   const T* A = rs + ci.rs_off;
   const T* B = inv + ci.inv_off;
-  T* C = du + ci.rs_off;
-  const int m0 = tl.m0, n0 = tl.n0;
+  T* C = du + tl.part * pstride + ci.rs_off;
+  const int m0 = tl.m0, n0 = tl.n0, kbeg = tl.k0, kend = tl.k1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
-  v4 acc[2][2];
+  const int wm = wave / WN, wn = wave % WN;
+  v4 acc[TM][TN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+    for (int b = 0; b < TN; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
-  const int ar = tid >> 2, ac = (tid & 3) * 4;    // A tile loader: row, k
-  const int bk = tid >> 4, bc = (tid & 15) * 4;   // B tile loader: k, col
-  for (int k0 = 0; k0 < n; k0 += BK) {
-    {
-      const int row = m0 + ar;
+  T ra[NA], rb[NB];
+  auto load = [&](int k0) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int col = k0 + ac + q;
-        As[ac + q][ar] = (row < M && col < n) ? A[(long long)row * n + col] : (T)0;
-      }
-      const int krow = k0 + bk;
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      const int row = m0 + e / BK, col = k0 + e % BK;
+      ra[q] = (row < M && col < kend) ? A[(long long)row * n + col] : (T)0;
+    }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int col = n0 + bc + q;
-        Bs[bk][bc + q] = (krow < n && col < n) ? B[(long long)krow * n + col] : (T)0;
-      }
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      const int kr = k0 + e / BN, col = n0 + e % BN;
+      rb[q] = (kr < kend && col < n) ? B[(long long)kr * n + col] : (T)0;
+    }
+  };
+  load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      As[e % BK][e / BK] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      Bs[e / BN][e % BN] = rb[q];
     }
     __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + (lane >> 4);
-      T a0 = As[kr][wm * 32 + (lane & 15)];
-      T a1 = As[kr][wm * 32 + 16 + (lane & 15)];
-      T b0 = Bs[kr][wn * 32 + (lane & 15)];
-      T b1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
-      acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
-      acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
-      acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
-      acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
+      T av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[kr][(wm * TM + a) * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[kr][(wn * TN + b) * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
     }
     __syncthreads();
   }
-  const T sc = (T)scale;
+  const T sc = (T)ci.scale;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < TM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < TN; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm * 32 + a * 16 + Mfma<T>::row(lane, r);
-        const int col = n0 + wn * 32 + b * 16 + (lane & 15);
+        const int row = m0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
+        const int col = n0 + (wn * TN + b) * 16 + (lane & 15);
         if (row < M && col < n) C[(long long)row * n + col] = sc * acc[a][b][r];
       }
 }
@@ -188,30 +216,40 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 }
 
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, const void* inv, void* du,
-                                 const ClassInfo* cls, const GemmTile* tiles, int ntiles,
-                                 double scale, hipStream_t s) {
-  if (ntiles <= 0) return hipSuccess;
-  if (f32)
-    hipLaunchKernelGGL(k_sub_gemm<float>, dim3(ntiles), dim3(256), 0, s, (const float*)rs,
-                       (const float*)inv, (float*)du, cls, tiles, scale);
-  else
-    hipLaunchKernelGGL(k_sub_gemm<double>, dim3(ntiles), dim3(256), 0, s, (const double*)rs,
-                       (const double*)inv, (double*)du, cls, tiles, scale);
+                                 long long ps, const ClassInfo* cls,
+                                 const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
+                                 int nsmall, hipStream_t s) {
+  if (f32) {
+    if (nbig > 0)
+      hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 32>), dim3(nbig), dim3(256), 0, s,
+                         (const float*)rs, (const float*)inv, (float*)du, ps, cls, tiles_big);
+    if (nsmall > 0)
+      hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), dim3(nsmall), dim3(256), 0, s,
+                         (const float*)rs, (const float*)inv, (float*)du, ps, cls, tiles_small);
+  } else {
+    if (nbig > 0)
+      hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), dim3(nbig), dim3(256), 0, s,
+                         (const double*)rs, (const double*)inv, (double*)du, ps, cls, tiles_big);
+    if (nsmall > 0)
+      hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 2, 16>), dim3(nsmall), dim3(256), 0, s,
+                         (const double*)rs, (const double*)inv, (double*)du, ps, cls, tiles_small);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_scatter(int N, bool f32, double* u, const void* du, const double* weights,
-                               const int* elem_class, const long long* elem_row, const int* nbr,
-                               const ClassInfo* cls, int nov, long long E, hipStream_t s) {
+hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
+                          long long pstride, const double* weights, const int* elem_class,
+                          const long long* elem_row, const int* nbr, const ClassInfo* cls, int nov,
+                          long long E, hipStream_t s) {
   const long long total = E * N * N * N;
   if (total <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((total + 255) / 256);
   if (f32)
-    hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(256), 0, s, u, (const float*)du,
-                       weights, elem_class, elem_row, nbr, cls, N, nov, total);
+    hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(256), 0, s, u, (const float*)du, parts,
+                       pstride, weights, elem_class, elem_row, nbr, cls, N, nov, total);
   else
     hipLaunchKernelGGL(k_scatter<double>, dim3(blocks), dim3(256), 0, s, u, (const double*)du,
-                       weights, elem_class, elem_row, nbr, cls, N, nov, total);
+                       parts, pstride, weights, elem_class, elem_row, nbr, cls, N, nov, total);
   return hipGetLastError();
 }
 

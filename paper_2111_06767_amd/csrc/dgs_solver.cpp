@@ -170,11 +170,11 @@ struct Level {
   double* d_weights = nullptr;
   int* d_elem_class = nullptr;
   long long* d_elem_row = nullptr;
-  GemmTile* d_tiles = nullptr;
-  int ntiles = 0;
-  long long inv_total = 0, rs_total = 0;
-  double* d_inv64 = nullptr;
-  float* d_inv32 = nullptr;
+  GemmTile* d_tiles_big = nullptr;
+  GemmTile* d_tiles_small = nullptr;
+  int nbig = 0, nsmall = 0;
+  int kparts = 1;  // split-K factor of the class GEMMs
+  long long rs_total = 0;
   void* d_rs = nullptr;
   void* d_du = nullptr;
   // level vectors
@@ -198,8 +198,16 @@ struct dgs_problem {
   double *d_V = nullptr, *d_Z = nullptr, *d_partial = nullptr, *d_h = nullptr, *d_y = nullptr;
   double* d_tmp = nullptr;  // one full vector
   double* d_tmp2 = nullptr;
+  double* h_pinned = nullptr;  // pinned host staging for reduction results
+  int h_pinned_len = 0;
   bool diag_active = false;
   double t_setup = 0;
+  // stored subdomain inverses, one per (class flags, aspect) key
+  double* d_inv64 = nullptr;
+  float* d_inv32 = nullptr;
+  // captured V-cycles (index: linearised operator or not) and the capture stream
+  hipGraphExec_t vgraph[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;
 
   long long nd(int l) const { return levels[l].E * (long long)N * N * N; }
 
@@ -211,6 +219,10 @@ struct dgs_problem {
   }
   ~dgs_problem() {
     for (void* p : allocations) (void)hipFree(p);
+    if (h_pinned) (void)hipHostFree(h_pinned);
+    for (auto& g : vgraph)
+      if (g) (void)hipGraphExecDestroy(g);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
   }
 };
 
@@ -226,6 +238,7 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
   L.op.h[2] = L.h[2];
   L.op.penalty = P->penalty;
   L.op.E = (int)L.E;
+  set_derived(L.op, P->N, P->ht.w[0]);
   std::vector<int> nbr(L.E * 6);
   for (long long e = 0; e < L.E; ++e) {
     const int c[3] = {(int)(e % L.n[0]), (int)((e / L.n[0]) % L.n[1]),
@@ -271,26 +284,46 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   }
   std::vector<int> seg_loc;
   std::vector<double> weights;
-  long long inv_off = 0, rs_off = 0;
-  std::vector<GemmTile> tiles;
+  long long rs_off = 0;
+  std::vector<GemmTile> big, small;
   for (int c = 0; c < ci; ++c) {
     ClassInfo& I = L.cls[c];
     const ClassLayout& lay = L.layouts[c];
     I.n = lay.n;
     I.count = count[c];
-    I.inv_off = inv_off;
+    I.inv_off = 0;  // set once the inverses exist
+    I.scale = 1.0;
     I.rs_off = rs_off;
     I.layout_off = (int)seg_loc.size();
     for (int f = 0; f < 6; ++f) I.strip_off[f] = lay.strip_off[f];
     seg_loc.insert(seg_loc.end(), lay.seg_loc.begin(), lay.seg_loc.end());
     weights.insert(weights.end(), lay.weights.begin(), lay.weights.end());
-    inv_off += (long long)lay.n * lay.n;
     rs_off += (long long)lay.n * count[c];
-    for (int m0 = 0; m0 < I.count; m0 += 64)
-      for (int n0 = 0; n0 < I.n; n0 += 64) tiles.push_back(GemmTile{c, m0, n0, 0});
   }
-  L.inv_total = inv_off;
   L.rs_total = rs_off;
+  // split K until there are enough tiles to fill the 256 compute units
+  int base = 0;
+  for (int c = 0; c < ci; ++c) {
+    const int bm = L.cls[c].count <= kGemmSmallCount ? kGemmSmallM : kGemmBigM;
+    base += ((L.cls[c].count + bm - 1) / bm) * ((L.cls[c].n + kGemmN - 1) / kGemmN);
+  }
+  L.kparts = 1;
+  while (L.kparts < 4 && base * L.kparts < 512) L.kparts *= 2;
+  for (int c = 0; c < ci; ++c) {
+    const ClassInfo& I = L.cls[c];
+    const bool is_small = I.count <= kGemmSmallCount;
+    const int bm = is_small ? kGemmSmallM : kGemmBigM;
+    // K chunks in multiples of 32 so FP32 and FP64 tiles both stay aligned
+    const int chunk = ((I.n + L.kparts - 1) / L.kparts + 31) / 32 * 32;
+    for (int part = 0; part < L.kparts; ++part) {
+      const int k0 = part * chunk, k1 = std::min(I.n, (part + 1) * chunk);
+      for (int m0 = 0; m0 < I.count; m0 += bm)
+        for (int n0 = 0; n0 < I.n; n0 += kGemmN) {
+          // an empty K range still writes zeros so every part is defined
+          (is_small ? small : big).push_back(GemmTile{c, m0, n0, part, k0, std::max(k0, k1)});
+        }
+    }
+  }
   std::vector<long long> elem_row(L.E);
   for (long long e = 0; e < L.E; ++e)
     elem_row[e] = L.cls[elem_class[e]].rs_off + (long long)pos[e] * L.cls[elem_class[e]].n;
@@ -304,17 +337,18 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   upload(L.d_elem_class, elem_class, s);
   L.d_elem_row = P->alloc<long long>(L.E);
   upload(L.d_elem_row, elem_row, s);
-  L.ntiles = (int)tiles.size();
-  L.d_tiles = P->alloc<GemmTile>(tiles.size());
-  upload(L.d_tiles, tiles, s);
+  L.nbig = (int)big.size();
+  L.nsmall = (int)small.size();
+  L.d_tiles_big = P->alloc<GemmTile>(big.size());
+  upload(L.d_tiles_big, big, s);
+  L.d_tiles_small = P->alloc<GemmTile>(small.size());
+  upload(L.d_tiles_small, small, s);
   if (L.f32) {
-    L.d_inv32 = P->alloc<float>(L.inv_total);
     L.d_rs = P->alloc<float>(L.rs_total);
-    L.d_du = P->alloc<float>(L.rs_total);
+    L.d_du = P->alloc<float>(L.rs_total * L.kparts);
   } else {
-    L.d_inv64 = P->alloc<double>(L.inv_total);
     L.d_rs = P->alloc<double>(L.rs_total);
-    L.d_du = P->alloc<double>(L.rs_total);
+    L.d_du = P->alloc<double>(L.rs_total * L.kparts);
   }
   // host copies of the elem tables are kept in the layouts only
   HIP_OK(hipStreamSynchronize(s));  // host vectors above go out of scope
@@ -440,19 +474,89 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
   double* d_row = dalloc<double>((size_t)nk * n_pad);
   std::unique_ptr<void, void (*)(void*)> g7(d_row, [](void* p) { (void)hipFree(p); });
   for (int k = 0; k < n_pad; ++k) HIP_OK(launch_gj_step(d_batch, n_pad, nk, k, d_col, d_row, s));
-  // distribute the scaled, transposed inverses to every level and class
+  // one stored (transposed) inverse per key, in the precisions its levels use;
+  // each level's classes point at it with the scale h_ref / h
+  std::vector<long long> koff(nk);
+  std::vector<char> need64(nk, 0), need32(nk, 0);
+  long long total = 0;
+  for (int k = 0; k < nk; ++k) {
+    koff[k] = total;
+    total += (long long)klay[k].n * klay[k].n;
+  }
+  for (const Use& u : uses) (P->levels[u.level].f32 ? need32 : need64)[u.key] = 1;
+  bool any64 = false, any32 = false;
+  for (int k = 0; k < nk; ++k) {
+    any64 = any64 || need64[k];
+    any32 = any32 || need32[k];
+  }
+  if (any64) P->d_inv64 = P->alloc<double>(total);
+  if (any32) P->d_inv32 = P->alloc<float>(total);
+  for (int k = 0; k < nk; ++k)
+    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, klay[k].n, 1.0,
+                                 need64[k] ? P->d_inv64 + koff[k] : nullptr,
+                                 need32[k] ? P->d_inv32 + koff[k] : nullptr, s));
   for (const Use& u : uses) {
     Level& L = P->levels[u.level];
-    const ClassInfo& I = L.cls[u.cls];
-    const double scale = key_hx[u.key] / L.h[0];  // A_S(lambda h) = lambda A_S(h)
-    HIP_OK(launch_finish_inverse(d_batch + (size_t)u.key * n_pad * n_pad, n_pad, I.n, scale,
-                                 L.f32 ? nullptr : L.d_inv64 + I.inv_off,
-                                 L.f32 ? L.d_inv32 + I.inv_off : nullptr, s));
+    ClassInfo& I = L.cls[u.cls];
+    I.inv_off = koff[u.key];
+    I.scale = key_hx[u.key] / L.h[0];  // A_S(lambda h) = lambda A_S(h)
   }
+  for (Level& L : P->levels) upload(L.d_cls, L.cls, s);
   HIP_OK(hipStreamSynchronize(s));
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Per-degree launch-shape autotuner of the operator kernel: time every
+// candidate elements-per-workgroup value on the finest mesh and keep the
+// fastest.  Results are cached per (N, element count) for the process.
+std::mutex g_tune_mutex;
+std::map<std::pair<int, long long>, int> g_tuned_epb;
+
+void autotune_apply(dgs_problem* P, hipStream_t s) {
+  Level& L = P->levels[0];
+  const auto key = std::make_pair(P->N, L.E);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    auto it = g_tuned_epb.find(key);
+    if (it != g_tuned_epb.end()) {
+      P->acfg.epb = it->second;
+      return;
+    }
+  }
+  const long long n = P->nd(0);
+  HIP_OK(launch_fill(L.d_u, 1.0, n, s));
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  const int cands[3] = {1, 2, 0};
+  int best = 0;
+  float best_ms = 1e30f;
+  const int reps = L.E >= 4096 ? 5 : 20;
+  for (int c : cands) {
+    ApplyConfig cfg;
+    cfg.epb = c;
+    HIP_OK(launch_apply(P->N, kApply, L.d_u, L.d_r, nullptr, nullptr, nullptr, L.d_nbr, L.op, P->dt,
+                        cfg, s));  // warm-up
+    HIP_OK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r)
+      HIP_OK(launch_apply(P->N, kApply, L.d_u, L.d_r, nullptr, nullptr, nullptr, L.d_nbr, L.op,
+                          P->dt, cfg, s));
+    HIP_OK(hipEventRecord(e1, s));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->acfg.epb = best;
+  std::lock_guard<std::mutex> lk(g_tune_mutex);
+  g_tuned_epb[key] = best;
+}
 
 // ---------------------------------------------------------------------------
 // Schwarz smoothing and the V-cycle
@@ -471,14 +575,15 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
     }
     HIP_OK(launch_gather(N, L.f32, r, L.d_rs, L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls,
                          L.d_seg_loc, (int)L.E, s));
-    HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.f32 ? (const void*)L.d_inv32 : (const void*)L.d_inv64,
-                                 L.d_du, L.d_cls, L.d_tiles, L.ntiles, 1.0, s));
-    HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.d_weights, L.d_elem_class, L.d_elem_row, L.d_nbr,
-                          L.d_cls, nov_of(P), L.E, s));
+    HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.f32 ? (const void*)P->d_inv32 : (const void*)P->d_inv64,
+                                 L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
+                                 L.d_tiles_small, L.nsmall, s));
+    HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.kparts, L.rs_total, L.d_weights, L.d_elem_class,
+                          L.d_elem_row, L.d_nbr, L.d_cls, nov_of(P), L.E, s));
   }
 }
 
-void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
+void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s) {
   const int nl = (int)P->levels.size();
   const int N = P->N;
   std::vector<const double*> b(nl);
@@ -508,6 +613,40 @@ void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
   }
 }
 
+// One V-cycle.  With graphs enabled the cycle is captured once (per operator
+// kind) on an internal stream, reading level 0's right-hand-side buffer and
+// writing level 0's solution buffer, and replayed on the caller's stream with
+// one copy in and one copy out.
+void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
+  if (!P->opt.use_graphs) {
+    vcycle_eager(P, r, z, s);
+    return;
+  }
+  Level& L0 = P->levels[0];
+  const long long n = P->nd(0);
+  const int gi = (P->diag_active && L0.d_diag) ? 1 : 0;
+  if (!P->vgraph[gi]) {
+    if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    HIP_OK(hipStreamSynchronize(s));
+    HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t graph = nullptr;
+    try {
+      vcycle_eager(P, L0.d_b, L0.d_u, P->cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(P->cap_stream, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    HIP_OK(hipStreamEndCapture(P->cap_stream, &graph));
+    hipError_t e = hipGraphInstantiate(&P->vgraph[gi], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIP_OK(e);
+  }
+  HIP_OK(launch_copy(L0.d_b, r, n, s));
+  HIP_OK(hipGraphLaunch(P->vgraph[gi], s));
+  HIP_OK(launch_copy(z, L0.d_u, n, s));
+}
+
 void ensure_krylov(dgs_problem* P, int m) {
   if (P->kry_m >= m) return;
   for (double* p : {P->d_V, P->d_Z, P->d_partial, P->d_h, P->d_y, P->d_tmp, P->d_tmp2}) {
@@ -524,15 +663,18 @@ void ensure_krylov(dgs_problem* P, int m) {
   P->d_y = P->alloc<double>(m + 1);
   P->d_tmp = P->alloc<double>(n);
   P->d_tmp2 = P->alloc<double>(n);
+  if (P->h_pinned) (void)hipHostFree(P->h_pinned);
+  P->h_pinned = nullptr;
+  HIP_OK(hipHostMalloc((void**)&P->h_pinned, sizeof(double) * 3 * (m + 2), hipHostMallocDefault));
+  P->h_pinned_len = 3 * (m + 2);
   P->kry_m = m;
 }
 
 double device_norm2(dgs_problem* P, const double* x, long long n, hipStream_t s) {
   HIP_OK(launch_multidot(x, n, 1, x, n, P->d_partial, P->d_h, s));
-  double v = 0;
-  HIP_OK(hipMemcpyAsync(&v, P->d_h, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipMemcpyAsync(P->h_pinned, P->d_h, sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  return v;
+  return P->h_pinned[0];
 }
 
 // Apply either A or the linearised operator A + diag(d) on the finest level.
@@ -595,10 +737,12 @@ FgmresResult fgmres(dgs_problem* P, const double* b, double* x, double rtol, int
     HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h2, s));
     HIP_OK(launch_multi_axpy(w, V, n, j + 1, h2, n, s));
     HIP_OK(launch_multidot(w, n, 1, w, n, P->d_partial, hn, s));
-    HIP_OK(hipMemcpyAsync(hh.data(), P->d_h, sizeof(double) * 2 * (m + 2), hipMemcpyDeviceToHost, s));
-    double hn2 = 0;
-    HIP_OK(hipMemcpyAsync(&hn2, hn, sizeof(double), hipMemcpyDeviceToHost, s));
+    // one copy of h1, h2 and |w|^2 (contiguous on the device) per iteration
+    HIP_OK(hipMemcpyAsync(P->h_pinned, P->d_h, sizeof(double) * (2 * (m + 2) + 1),
+                          hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
+    for (int i = 0; i < 2 * (m + 2); ++i) hh[i] = P->h_pinned[i];
+    const double hn2 = P->h_pinned[2 * (m + 2)];
     double* col = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
     for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(m + 2) + i];
     col[j + 1] = std::sqrt(hn2);
@@ -692,6 +836,7 @@ void dgs_default_options(dgs_options* o) {
   o->subdomain_iters = 3;
   o->max_iter = 200;
   o->rtol = 1e-10;
+  o->use_graphs = 1;
 }
 
 const char* dgs_last_error(void) { return g_last_error.c_str(); }
@@ -758,6 +903,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
       build_level_schwarz(P.get(), L, s);
     }
     build_inverses(P.get(), s);
+    autotune_apply(P.get(), s);
     HIP_OK(hipStreamSynchronize(s));
     P->t_setup = now_s() - t0;
     *out = P.release();

@@ -99,6 +99,15 @@ HostTables make_tables(int N) {
   return t;
 }
 
+void set_derived(OpParams& P, int N, double w_end) {
+  for (int d = 0; d < 3; ++d) {
+    P.rh[d] = 2.0 / P.h[d];
+    P.sig[d] = P.penalty * (double)(N * N) / P.h[d];  // eq. penalty, p_int = p_ext
+    P.lf[d] = 1.0 / (P.h[d] * w_end);
+  }
+  P.J = P.h[0] * P.h[1] * P.h[2] * 0.125;
+}
+
 DevTables to_dev(const HostTables& t) {
   DevTables d;
   std::memset(&d, 0, sizeof(d));

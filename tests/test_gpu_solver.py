@@ -104,3 +104,29 @@ def test_not_converged_and_nonfinite():
         prob.solve(bad)
     assert ei.value.code == dg.DGS_ERR_NONFINITE
     del torch
+
+
+def test_graph_replays_match_eager():
+    # the captured V-cycle, replayed several times with eager work and
+    # synchronisations in between, equals the eager V-cycle bit for bit
+    import torch
+    import paper_2111_06767_amd as dg
+    announce("graph replay vs eager 4x4x4 p=3")
+    pg = dg.Problem((0, 0, 0), (1, 1, 1), (4, 4, 4), 3, mg_levels=3, use_graphs=1)
+    pe = dg.Problem((0, 0, 0), (1, 1, 1), (4, 4, 4), 3, mg_levels=3, use_graphs=0)
+    for seed in (41, 42, 43, 44):
+        r = to_gpu(W.random_normal(seed, pg.ndof))
+        zg = pg.precondition(r)
+        torch.cuda.synchronize()
+        junk = pe.apply(r)  # unrelated eager work between replays
+        ze = pe.precondition(r)
+        assert torch.equal(zg, ze), seed
+        del junk
+    for prec in ("fp64", "mixed"):
+        pg = dg.Problem((0, 0, 0), (1, 1, 1), (4, 4, 2), 4, mg_levels=2, precision=prec, use_graphs=1)
+        pe = dg.Problem((0, 0, 0), (1, 1, 1), (4, 4, 2), 4, mg_levels=2, precision=prec, use_graphs=0)
+        b = to_gpu(W.random_normal(45, pg.ndof))
+        ug, sg = pg.solve(b)
+        ue, se = pe.solve(b)
+        assert sg["iterations"] == se["iterations"]
+        assert torch.equal(ug, ue)
