@@ -67,7 +67,7 @@ typedef struct {
   int precision;       /* DGS_FP64 or DGS_MIXED                            [DGS_FP64] */
   int subdomain_iters; /* linearised problems only: 0 = apply the Poisson
                           subdomain inverse once; k > 0 = k iterations of GMRES
-                          preconditioned by it (Sec. III.E.1)                    [3] */
+                          preconditioned by it (Sec. III.E.1), k <= 8            [3] */
   int max_iter;        /* FGMRES iteration limit (no restart)                   [200] */
   double rtol;         /* FGMRES relative residual tolerance                   [1e-10] */
   int use_graphs;      /* 1 = replay each V-cycle from a captured hipGraph        [1] */
@@ -130,6 +130,17 @@ int dgs_precondition(dgs_problem* prob, const double* r, double* z, void* stream
  * on exit.  Stops when the residual estimate drops below rtol ||b - A u0||;
  * stats->rel_residual is the true relative residual of the result. */
 int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream);
+
+/* Add a pointwise term: subsequent dgs_schwarz_smooth, dgs_precondition and
+ * dgs_solve act on A + diag(d) (d a device field in the nodal layout, e.g. the
+ * mass-weighted derivative M S'(u) of a nonlinear source, eq. linearized);
+ * d = NULL removes it.  dgs_apply_operator always applies A alone.  The field
+ * is copied (and restricted to the coarse grids, d_{l+1} = R d_l); the caller
+ * may free d afterwards.  With subdomain_iters = k > 0 each subdomain problem
+ * (A_S + diag(R_S d)) du_S = r_S is solved by k iterations of GMRES
+ * preconditioned by the explicit Poisson inverse (Laplacian approximation,
+ * Sec. III.E.1); with k = 0 the Poisson inverse is applied alone. */
+int dgs_set_diagonal(dgs_problem* prob, const double* d, void* stream);
 
 /* Solve the puncture-type equation Laplace(u) + beta (alpha (1+u) + 1)^-7 = f
  * in DG form A u + M S(u) = b with S(u) = -beta (alpha (1+u) + 1)^-7, by

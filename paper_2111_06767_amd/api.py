@@ -27,7 +27,7 @@ DGS_MIXED = 1
 EXPORTED = (
     "dgs_default_options", "dgs_create_problem", "dgs_destroy_problem", "dgs_num_dofs",
     "dgs_node_coordinates", "dgs_apply_mass", "dgs_apply_operator", "dgs_schwarz_smooth",
-    "dgs_precondition", "dgs_solve", "dgs_newton_solve", "dgs_last_error",
+    "dgs_precondition", "dgs_solve", "dgs_newton_solve", "dgs_last_error", "dgs_set_diagonal",
 )
 
 
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_apply_operator.argtypes = [P, dp, dp, P]
     lib.dgs_schwarz_smooth.argtypes = [P, dp, dp, ctypes.c_int, P]
     lib.dgs_precondition.argtypes = [P, dp, dp, P]
+    lib.dgs_set_diagonal.argtypes = [P, dp, P]
     lib.dgs_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
     lib.dgs_newton_solve.argtypes = [P, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.POINTER(Stats), P]
@@ -197,6 +198,11 @@ class Problem:
         _check(self._lib.dgs_precondition(self._h, _ptr(r, self.ndof, "r"), _ptr(out, self.ndof, "z"),
                                           _stream(stream)))
         return out
+
+    def set_diagonal(self, d=None, stream=None):
+        """Operator A + diag(d) for smoothing, preconditioning and solves (None: A)."""
+        ptr = ctypes.c_void_p(None) if d is None else _ptr(d, self.ndof, "d")
+        _check(self._lib.dgs_set_diagonal(self._h, ptr, _stream(stream)))
 
     def solve(self, b, u=None, history=256, stream=None):
         """Solve A u = b (u = initial guess, zero if None).  Returns (u, stats dict)."""

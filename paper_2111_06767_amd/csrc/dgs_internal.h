@@ -70,6 +70,8 @@ struct ClassInfo {
   int count;        // number of subdomains (elements) in the class
   long long inv_off;  // offset of this class's n x n matrix (transposed inverse)
   double scale;       // factor applied to the stored inverse for this level
+  long long op_off;   // offset of the class's subdomain operator A_S (transposed)
+  double scale_op;    // factor applied to the stored A_S for this level
   long long rs_off;   // offset of this class's [count][n] block in RS / DU
   int layout_off;     // offset into seg_loc / weights
   int strip_off[6];   // offset of each face strip in the layout, -1 if absent
@@ -88,10 +90,30 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 // Grouped subdomain GEMM: tiles_big use 64 x 128 block tiles (classes with
 // many subdomains), tiles_small 16 x 128 (classes with few).
 constexpr int kGemmBigM = 64, kGemmSmallM = 16, kGemmN = 128, kGemmSmallCount = 32;
+// use_op = 0: multiply by the stored inverse (offset inv_off, factor scale);
+// use_op = 1: by the stored subdomain operator (op_off, scale_op).
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, const void* inv, void* du,
                                  long long part_stride, const ClassInfo* cls,
                                  const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
-                                 int nsmall, hipStream_t s);
+                                 int nsmall, int use_op, hipStream_t s);
+// out[i] = sum over parts of part_base[p * stride + i]
+hipError_t launch_reduce_parts(bool f32, void* out, const void* parts_base, int parts,
+                               long long stride, long long total, hipStream_t s);
+// Batched subdomain GMRES(k) pieces (one workgroup per subdomain):
+//   start:   beta = |r_S|, V_0 = r_S / beta
+//   arnoldi: w = W + d_S .* Z_j, modified Gram-Schmidt against V_0..V_j,
+//            H[:, j], V_{j+1} = w / |w|
+//   finish:  least-squares solve of the Hessenberg system, du_S = sum y_j Z_j
+hipError_t launch_sub_start(bool f32, const void* rs, void* V0, double* beta,
+                            const int* elem_class, const long long* elem_row, const ClassInfo* cls,
+                            int E, hipStream_t s);
+hipError_t launch_sub_arnoldi(int N, bool f32, int j, int kmax, const void* W, void* V, const void* Zj,
+                              long long stride, const double* diag, double* H,
+                              const int* elem_class, const long long* elem_row, const int* nbr,
+                              const ClassInfo* cls, const int* seg_loc, int E, hipStream_t s);
+hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride, const double* H,
+                             const double* beta, void* du, const int* elem_class,
+                             const long long* elem_row, const ClassInfo* cls, int E, hipStream_t s);
 // u += sum_S R_S^T (w_S du_S), pulled per point; du is the sum of `parts`
 // split-K partial products spaced part_stride apart.
 hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,

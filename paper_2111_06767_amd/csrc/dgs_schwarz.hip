@@ -119,7 +119,7 @@ template <typename T, int WM, int WN, int TM, int TN, int BK>
 __global__ void __launch_bounds__(256)
 k_sub_gemm(const T* __restrict__ rs, const T* __restrict__ inv, T* __restrict__ du,
            long long pstride, const ClassInfo* __restrict__ cls,
-           const GemmTile* __restrict__ tiles) {
+           const GemmTile* __restrict__ tiles, int use_op) {
   constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
   constexpr int PA = 1, PB = 4;
   constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
@@ -131,7 +131,7 @@ k_sub_gemm(const T* __restrict__ rs, const T* __restrict__ inv, T* __restrict__ 
   const ClassInfo ci = cls[tl.cls];
   const int n = ci.n, M = ci.count;
   const T* A = rs + ci.rs_off;
-  const T* B = inv + ci.inv_off;
+  const T* B = inv + (use_op ? ci.op_off : ci.inv_off);
   T* C = du + tl.part * pstride + ci.rs_off;
   const int m0 = tl.m0, n0 = tl.n0, kbeg = tl.k0, kend = tl.k1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -186,7 +186,7 @@ k_sub_gemm(const T* __restrict__ rs, const T* __restrict__ inv, T* __restrict__ 
     }
     __syncthreads();
   }
-  const T sc = (T)ci.scale;
+  const T sc = (T)(use_op ? ci.scale_op : ci.scale);
 #pragma unroll
   for (int a = 0; a < TM; ++a)
 #pragma unroll
@@ -199,7 +199,232 @@ k_sub_gemm(const T* __restrict__ rs, const T* __restrict__ inv, T* __restrict__ 
       }
 }
 
+template <typename T>
+__global__ void k_reduce_parts(T* __restrict__ out, const T* __restrict__ parts, int np,
+                               long long stride, long long total) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  double v = 0.0;
+  for (int p = 0; p < np; ++p) v += (double)parts[p * stride + g];
+  out[g] = (T)v;
+}
+
+__device__ __forceinline__ double block_reduce_sum(double v, double* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();  // red may still be read from a previous reduction
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+  return t;  // every thread gets the same sum, in the same order
+}
+
+constexpr int kSubThreads = 256;
+constexpr int kSubPer = 8;  // points per thread: n_S <= 2048
+
+template <typename T>
+__global__ void __launch_bounds__(kSubThreads)
+k_sub_start(const T* __restrict__ rs, T* __restrict__ V0, double* __restrict__ beta,
+            const int* __restrict__ elem_class, const long long* __restrict__ elem_row,
+            const ClassInfo* __restrict__ cls, int E) {
+  __shared__ double red[kSubThreads / 64];
+  const int e = blockIdx.x;
+  if (e >= E) return;
+  const int n = cls[elem_class[e]].n;
+  const long long row = elem_row[e];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += kSubThreads) {
+    const double x = (double)rs[row + i];
+    s += x * x;
+  }
+  const double b = sqrt(block_reduce_sum(s, red));
+  if (threadIdx.x == 0) beta[e] = b;
+  for (int i = threadIdx.x; i < n; i += kSubThreads)
+    V0[row + i] = b > 0.0 ? (T)((double)rs[row + i] / b) : (T)0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSubThreads)
+k_sub_arnoldi(int j, int kmax, const T* __restrict__ W, T* __restrict__ V, const T* __restrict__ Zj,
+              long long stride, const double* __restrict__ diag, double* __restrict__ H,
+              const int* __restrict__ elem_class, const long long* __restrict__ elem_row,
+              const int* __restrict__ nbr, const ClassInfo* __restrict__ cls,
+              const int* __restrict__ seg_loc, int E, int N3) {
+  __shared__ double red[kSubThreads / 64];
+  __shared__ long long src[7];
+  const int e = blockIdx.x;
+  if (e >= E) return;
+  const ClassInfo ci = cls[elem_class[e]];
+  const int n = ci.n;
+  const long long row = elem_row[e];
+  if (threadIdx.x < 7) {
+    const int el = threadIdx.x == 0 ? e : nbr[(long long)e * 6 + threadIdx.x - 1];
+    src[threadIdx.x] = (long long)el * N3;
+  }
+  __syncthreads();
+  const int* lay = seg_loc + ci.layout_off;
+  double w[kSubPer];
+#pragma unroll
+  for (int q = 0; q < kSubPer; ++q) {
+    const int i = threadIdx.x + q * kSubThreads;
+    w[q] = 0.0;
+    if (i < n) {
+      const int sl = lay[i];
+      const int seg = sl / N3;
+      const double d = diag[src[seg] + (sl - seg * N3)];
+      w[q] = (double)W[row + i] + d * (double)Zj[row + i];
+    }
+  }
+  double* Hs = H + (long long)e * (kmax + 1) * kmax;  // column-major (kmax+1) x kmax
+  for (int i = 0; i <= j; ++i) {
+    const T* vi = V + i * stride + row;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSubPer; ++q) {
+      const int p = threadIdx.x + q * kSubThreads;
+      if (p < n) s += w[q] * (double)vi[p];
+    }
+    const double h = block_reduce_sum(s, red);
+#pragma unroll
+    for (int q = 0; q < kSubPer; ++q) {
+      const int p = threadIdx.x + q * kSubThreads;
+      if (p < n) w[q] -= h * (double)vi[p];
+    }
+    if (threadIdx.x == 0) Hs[j * (kmax + 1) + i] = h;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kSubPer; ++q) s += w[q] * w[q];
+  const double hn = sqrt(block_reduce_sum(s, red));
+  if (threadIdx.x == 0) Hs[j * (kmax + 1) + j + 1] = hn;
+  if (j + 1 <= kmax) {
+    T* vn = V + (j + 1) * stride + row;
+#pragma unroll
+    for (int q = 0; q < kSubPer; ++q) {
+      const int p = threadIdx.x + q * kSubThreads;
+      if (p < n) vn[p] = hn > 0.0 ? (T)(w[q] / hn) : (T)0;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSubThreads)
+k_sub_finish(int kmax, const T* __restrict__ Z, long long stride, const double* __restrict__ H,
+             const double* __restrict__ beta, T* __restrict__ du,
+             const int* __restrict__ elem_class, const long long* __restrict__ elem_row,
+             const ClassInfo* __restrict__ cls, int E) {
+  __shared__ double y[16];
+  __shared__ int mm;
+  const int e = blockIdx.x;
+  if (e >= E) return;
+  const int n = cls[elem_class[e]].n;
+  const long long row = elem_row[e];
+  if (threadIdx.x == 0) {
+    // least squares min |beta e1 - H y| by Givens rotations, stopping at a
+    // breakdown column (zero subdiagonal)
+    double h[9][8], g[9];
+    const double* Hs = H + (long long)e * (kmax + 1) * kmax;
+    int m = kmax;
+    for (int jj = 0; jj < kmax; ++jj)
+      if (Hs[jj * (kmax + 1) + jj + 1] == 0.0) {
+        m = jj + 1;
+        break;
+      }
+    for (int jj = 0; jj < m; ++jj)
+      for (int ii = 0; ii <= m; ++ii) h[ii][jj] = (ii <= jj + 1) ? Hs[jj * (kmax + 1) + ii] : 0.0;
+    for (int ii = 0; ii <= m; ++ii) g[ii] = 0.0;
+    g[0] = beta[e];
+    if (g[0] == 0.0) {
+      m = 0;
+    } else {
+      for (int jj = 0; jj < m; ++jj) {
+        const double a = h[jj][jj], b = h[jj + 1][jj];
+        const double r = sqrt(a * a + b * b);
+        const double c = a / r, sn = b / r;
+        for (int q = jj; q < m; ++q) {
+          const double t0 = h[jj][q], t1 = h[jj + 1][q];
+          h[jj][q] = c * t0 + sn * t1;
+          h[jj + 1][q] = -sn * t0 + c * t1;
+        }
+        const double g0 = g[jj], g1 = g[jj + 1];
+        g[jj] = c * g0 + sn * g1;
+        g[jj + 1] = -sn * g0 + c * g1;
+      }
+      for (int ii = m - 1; ii >= 0; --ii) {
+        double t = g[ii];
+        for (int q = ii + 1; q < m; ++q) t -= h[ii][q] * y[q];
+        y[ii] = t / h[ii][ii];
+      }
+    }
+    mm = m;
+  }
+  __syncthreads();
+  const int m = mm;
+  for (int i = threadIdx.x; i < n; i += kSubThreads) {
+    double v = 0.0;
+    for (int jj = 0; jj < m; ++jj) v += y[jj] * (double)Z[jj * stride + row + i];
+    du[row + i] = (T)v;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_reduce_parts(bool f32, void* out, const void* parts_base, int parts,
+                               long long stride, long long total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (f32)
+    hipLaunchKernelGGL(k_reduce_parts<float>, dim3(blocks), dim3(256), 0, s, (float*)out,
+                       (const float*)parts_base, parts, stride, total);
+  else
+    hipLaunchKernelGGL(k_reduce_parts<double>, dim3(blocks), dim3(256), 0, s, (double*)out,
+                       (const double*)parts_base, parts, stride, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_start(bool f32, const void* rs, void* V0, double* beta,
+                            const int* elem_class, const long long* elem_row, const ClassInfo* cls,
+                            int E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_sub_start<float>, dim3(E), dim3(kSubThreads), 0, s, (const float*)rs,
+                       (float*)V0, beta, elem_class, elem_row, cls, E);
+  else
+    hipLaunchKernelGGL(k_sub_start<double>, dim3(E), dim3(kSubThreads), 0, s, (const double*)rs,
+                       (double*)V0, beta, elem_class, elem_row, cls, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_arnoldi(int N, bool f32, int j, int kmax, const void* W, void* V, const void* Zj,
+                              long long stride, const double* diag, double* H,
+                              const int* elem_class, const long long* elem_row, const int* nbr,
+                              const ClassInfo* cls, const int* seg_loc, int E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  const int N3 = N * N * N;
+  if (f32)
+    hipLaunchKernelGGL(k_sub_arnoldi<float>, dim3(E), dim3(kSubThreads), 0, s, j, kmax,
+                       (const float*)W, (float*)V, (const float*)Zj, stride, diag, H, elem_class,
+                       elem_row, nbr, cls, seg_loc, E, N3);
+  else
+    hipLaunchKernelGGL(k_sub_arnoldi<double>, dim3(E), dim3(kSubThreads), 0, s, j, kmax,
+                       (const double*)W, (double*)V, (const double*)Zj, stride, diag, H, elem_class,
+                       elem_row, nbr, cls, seg_loc, E, N3);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride, const double* H,
+                             const double* beta, void* du, const int* elem_class,
+                             const long long* elem_row, const ClassInfo* cls, int E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_sub_finish<float>, dim3(E), dim3(kSubThreads), 0, s, kmax, (const float*)Z,
+                       stride, H, beta, (float*)du, elem_class, elem_row, cls, E);
+  else
+    hipLaunchKernelGGL(k_sub_finish<double>, dim3(E), dim3(kSubThreads), 0, s, kmax,
+                       (const double*)Z, stride, H, beta, (double*)du, elem_class, elem_row, cls, E);
+  return hipGetLastError();
+}
 
 hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* elem_class,
                          const long long* elem_row, const int* nbr, const ClassInfo* cls,
@@ -218,21 +443,21 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, const void* inv, void* du,
                                  long long ps, const ClassInfo* cls,
                                  const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
-                                 int nsmall, hipStream_t s) {
+                                 int nsmall, int use_op, hipStream_t s) {
   if (f32) {
     if (nbig > 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 32>), dim3(nbig), dim3(256), 0, s,
-                         (const float*)rs, (const float*)inv, (float*)du, ps, cls, tiles_big);
+                         (const float*)rs, (const float*)inv, (float*)du, ps, cls, tiles_big, use_op);
     if (nsmall > 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), dim3(nsmall), dim3(256), 0, s,
-                         (const float*)rs, (const float*)inv, (float*)du, ps, cls, tiles_small);
+                         (const float*)rs, (const float*)inv, (float*)du, ps, cls, tiles_small, use_op);
   } else {
     if (nbig > 0)
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), dim3(nbig), dim3(256), 0, s,
-                         (const double*)rs, (const double*)inv, (double*)du, ps, cls, tiles_big);
+                         (const double*)rs, (const double*)inv, (double*)du, ps, cls, tiles_big, use_op);
     if (nsmall > 0)
       hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 2, 16>), dim3(nsmall), dim3(256), 0, s,
-                         (const double*)rs, (const double*)inv, (double*)du, ps, cls, tiles_small);
+                         (const double*)rs, (const double*)inv, (double*)du, ps, cls, tiles_small, use_op);
   }
   return hipGetLastError();
 }

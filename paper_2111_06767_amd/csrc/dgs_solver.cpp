@@ -179,6 +179,11 @@ struct Level {
   void* d_du = nullptr;
   // level vectors
   double *d_u = nullptr, *d_b = nullptr, *d_r = nullptr, *d_diag = nullptr;
+  // batched subdomain GMRES(k) work space (level precision)
+  void *d_gV = nullptr, *d_gZ = nullptr, *d_gW = nullptr;
+  double *d_gH = nullptr, *d_gbeta = nullptr;
+  int gk = 0;
+  int max_n = 0;
 };
 
 }  // namespace
@@ -205,6 +210,9 @@ struct dgs_problem {
   // stored subdomain inverses, one per (class flags, aspect) key
   double* d_inv64 = nullptr;
   float* d_inv32 = nullptr;
+  double* d_op64 = nullptr;  // stored subdomain operators, same keys and offsets
+  float* d_op32 = nullptr;
+  double* d_newton = nullptr;  // Newton work vectors
   // captured V-cycles (index: linearised operator or not) and the capture stream
   hipGraphExec_t vgraph[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
@@ -301,6 +309,8 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
     rs_off += (long long)lay.n * count[c];
   }
   L.rs_total = rs_off;
+  L.max_n = 0;
+  for (int c = 0; c < ci; ++c) L.max_n = std::max(L.max_n, L.cls[c].n);
   // split K until there are enough tiles to fill the 256 compute units
   int base = 0;
   for (int c = 0; c < ci; ++c) {
@@ -468,6 +478,26 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
     HIP_OK(launch_gather_columns(d_AX, stride, d_idx, n, d_batch + (size_t)k * n_pad * n_pad, n_pad, s));
     HIP_OK(hipStreamSynchronize(s));
   }
+  // keep A_S itself (transposed, unscaled) for the linearised subdomain solver
+  std::vector<long long> koff(nk);
+  long long total = 0;
+  for (int k = 0; k < nk; ++k) {
+    koff[k] = total;
+    total += (long long)klay[k].n * klay[k].n;
+  }
+  std::vector<char> need64(nk, 0), need32(nk, 0);
+  for (const Use& u : uses) (P->levels[u.level].f32 ? need32 : need64)[u.key] = 1;
+  bool any64 = false, any32 = false;
+  for (int k = 0; k < nk; ++k) {
+    any64 = any64 || need64[k];
+    any32 = any32 || need32[k];
+  }
+  if (any64) P->d_op64 = P->alloc<double>(total);
+  if (any32) P->d_op32 = P->alloc<float>(total);
+  for (int k = 0; k < nk; ++k)
+    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, klay[k].n, 1.0,
+                                 need64[k] ? P->d_op64 + koff[k] : nullptr,
+                                 need32[k] ? P->d_op32 + koff[k] : nullptr, s));
   // batched Gauss-Jordan
   double* d_col = dalloc<double>((size_t)nk * n_pad);
   std::unique_ptr<void, void (*)(void*)> g6(d_col, [](void* p) { (void)hipFree(p); });
@@ -476,19 +506,6 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
   for (int k = 0; k < n_pad; ++k) HIP_OK(launch_gj_step(d_batch, n_pad, nk, k, d_col, d_row, s));
   // one stored (transposed) inverse per key, in the precisions its levels use;
   // each level's classes point at it with the scale h_ref / h
-  std::vector<long long> koff(nk);
-  std::vector<char> need64(nk, 0), need32(nk, 0);
-  long long total = 0;
-  for (int k = 0; k < nk; ++k) {
-    koff[k] = total;
-    total += (long long)klay[k].n * klay[k].n;
-  }
-  for (const Use& u : uses) (P->levels[u.level].f32 ? need32 : need64)[u.key] = 1;
-  bool any64 = false, any32 = false;
-  for (int k = 0; k < nk; ++k) {
-    any64 = any64 || need64[k];
-    any32 = any32 || need32[k];
-  }
   if (any64) P->d_inv64 = P->alloc<double>(total);
   if (any32) P->d_inv32 = P->alloc<float>(total);
   for (int k = 0; k < nk; ++k)
@@ -500,6 +517,8 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
     ClassInfo& I = L.cls[u.cls];
     I.inv_off = koff[u.key];
     I.scale = key_hx[u.key] / L.h[0];  // A_S(lambda h) = lambda A_S(h)
+    I.op_off = koff[u.key];
+    I.scale_op = L.h[0] / key_hx[u.key];
   }
   for (Level& L : P->levels) upload(L.d_cls, L.cls, s);
   HIP_OK(hipStreamSynchronize(s));
@@ -561,6 +580,38 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Schwarz smoothing and the V-cycle
 // ---------------------------------------------------------------------------
+
+// Subdomain problems of the linearised operator, (A_S + diag(R_S d)) du_S = r_S,
+// solved for every subdomain at once by k iterations of right-preconditioned
+// GMRES with the Poisson inverse as preconditioner (Laplacian approximation,
+// Sec. III.E.1).  Input: the gathered residuals in L.d_rs; output: du_S in
+// part 0 of L.d_du.
+void subdomain_gmres(dgs_problem* P, Level& L, hipStream_t s) {
+  const int k = P->opt.subdomain_iters;
+  const int N = P->N;
+  const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+  const long long st = L.rs_total;
+  auto slot = [&](void* base, int i) { return (void*)((char*)base + es * (size_t)st * i); };
+  const void* inv = L.f32 ? (const void*)P->d_inv32 : (const void*)P->d_inv64;
+  const void* op = L.f32 ? (const void*)P->d_op32 : (const void*)P->d_op64;
+  HIP_OK(launch_sub_start(L.f32, L.d_rs, L.d_gV, L.d_gbeta, L.d_elem_class, L.d_elem_row, L.d_cls,
+                          (int)L.E, s));
+  for (int j = 0; j < k; ++j) {
+    void* Vj = slot(L.d_gV, j);
+    void* Zj = slot(L.d_gZ, j);
+    HIP_OK(launch_subdomain_gemm(L.f32, Vj, inv, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
+                                 L.d_tiles_small, L.nsmall, 0, s));
+    HIP_OK(launch_reduce_parts(L.f32, Zj, L.d_du, L.kparts, st, st, s));
+    HIP_OK(launch_subdomain_gemm(L.f32, Zj, op, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
+                                 L.d_tiles_small, L.nsmall, 1, s));
+    HIP_OK(launch_reduce_parts(L.f32, L.d_gW, L.d_du, L.kparts, st, st, s));
+    HIP_OK(launch_sub_arnoldi(N, L.f32, j, k, L.d_gW, L.d_gV, Zj, st, L.d_diag, L.d_gH,
+                              L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls, L.d_seg_loc, (int)L.E,
+                              s));
+  }
+  HIP_OK(launch_sub_finish(L.f32, k, L.d_gZ, st, L.d_gH, L.d_gbeta, L.d_du, L.d_elem_class,
+                           L.d_elem_row, L.d_cls, (int)L.E, s));
+}
 void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps, bool u_zero,
                    hipStream_t s) {
   Level& L = P->levels[l];
@@ -575,9 +626,15 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
     }
     HIP_OK(launch_gather(N, L.f32, r, L.d_rs, L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls,
                          L.d_seg_loc, (int)L.E, s));
+    if (diag && P->opt.subdomain_iters > 0) {
+      subdomain_gmres(P, L, s);
+      HIP_OK(launch_scatter(N, L.f32, u, L.d_du, 1, L.rs_total, L.d_weights, L.d_elem_class,
+                            L.d_elem_row, L.d_nbr, L.d_cls, nov_of(P), L.E, s));
+      continue;
+    }
     HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.f32 ? (const void*)P->d_inv32 : (const void*)P->d_inv64,
                                  L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
-                                 L.d_tiles_small, L.nsmall, s));
+                                 L.d_tiles_small, L.nsmall, 0, s));
     HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.kparts, L.rs_total, L.d_weights, L.d_elem_class,
                           L.d_elem_row, L.d_nbr, L.d_cls, nov_of(P), L.E, s));
   }
@@ -690,6 +747,37 @@ void residual_fine(dgs_problem* P, const double* x, const double* b, double* r, 
   const bool diag = P->diag_active && L.d_diag != nullptr;
   HIP_OK(launch_apply(P->N, diag ? kResidualDiag : kResidual, x, r, b, L.d_diag, nullptr, L.d_nbr,
                       L.op, P->dt, P->acfg, s));
+}
+
+// Make subsequent smoothing, V-cycles and solves act on A + diag(d): copy d
+// to the finest level and restrict it down the hierarchy (d_{l+1} = R d_l).
+void set_diagonal(dgs_problem* P, const double* d, hipStream_t s) {
+  if (!d) {
+    P->diag_active = false;
+    return;
+  }
+  const int k = P->opt.subdomain_iters;
+  for (Level& L : P->levels) {
+    if (!L.d_diag) L.d_diag = P->alloc<double>(L.E * (long long)P->N * P->N * P->N);
+    if (k > 0 && L.gk < k) {
+      if (L.max_n > 2048)
+        throw DgsError(DGS_ERR_INVALID, "subdomain GMRES supports subdomains of at most 2048 points");
+      const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+      L.d_gV = P->alloc<char>(es * (size_t)L.rs_total * (k + 1));
+      L.d_gZ = P->alloc<char>(es * (size_t)L.rs_total * k);
+      L.d_gW = P->alloc<char>(es * (size_t)L.rs_total);
+      L.d_gH = P->alloc<double>((size_t)L.E * (k + 1) * k);
+      L.d_gbeta = P->alloc<double>(L.E);
+      L.gk = k;
+    }
+  }
+  HIP_OK(launch_copy(P->levels[0].d_diag, d, P->nd(0), s));
+  for (size_t l = 0; l + 1 < P->levels.size(); ++l) {
+    Level& L = P->levels[l];
+    Level& C = P->levels[l + 1];
+    HIP_OK(launch_restrict(P->N, L.d_diag, C.d_diag, L.n, C.n, L.split, P->dt, s));
+  }
+  P->diag_active = true;
 }
 
 struct FgmresResult {
@@ -857,7 +945,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     dgs_default_options(&o);
     if (opt) o = *opt;
     if (o.overlap < 1 || o.pre_smooth < 0 || o.post_smooth < 0 || o.mg_levels < 0 ||
-        o.max_iter < 1 || !(o.rtol > 0.0) || o.subdomain_iters < 0 ||
+        o.max_iter < 1 || !(o.rtol > 0.0) || o.subdomain_iters < 0 || o.subdomain_iters > 8 ||
         (o.precision != DGS_FP64 && o.precision != DGS_MIXED))
       return fail(DGS_ERR_INVALID, "invalid options");
     const long long E0 = (long long)elements[0] * elements[1] * elements[2];
@@ -977,7 +1065,6 @@ int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, v
   return guarded([&]() -> int {
     if (!prob || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
     const double t0 = now_s();
-    prob->diag_active = false;
     FgmresResult R = fgmres(prob, b, u, prob->opt.rtol, prob->opt.max_iter, as_stream(stream));
     fill_stats(stats, R, t0, prob->t_setup);
     if (stats) {
@@ -989,10 +1076,114 @@ int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, v
   });
 }
 
+int dgs_set_diagonal(dgs_problem* prob, const double* d, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob) return fail(DGS_ERR_INVALID, "NULL argument");
+    set_diagonal(prob, d, as_stream(stream));
+    return DGS_OK;
+  });
+}
+
 int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta, const double* b,
                      double* u, double newton_rtol, double linear_rtol, int max_newton,
                      dgs_stats* stats, void* stream) {
-  return fail(DGS_ERR_INVALID, "newton_solve not available yet");
+  return guarded([&]() -> int {
+    if (!prob || !alpha || !beta || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (!(newton_rtol > 0.0) || !(linear_rtol > 0.0) || max_newton < 1)
+      return fail(DGS_ERR_INVALID, "invalid Newton tolerances");
+    dgs_problem* P = prob;
+    hipStream_t s = as_stream(stream);
+    const double t0 = now_s();
+    const long long n = P->nd(0);
+    ensure_krylov(P, P->opt.max_iter);
+    if (!P->d_newton) P->d_newton = P->alloc<double>((size_t)5 * n);
+    double* F = P->d_newton;
+    double* Ft = F + n;
+    double* du = F + 2 * n;
+    double* ut = F + 3 * n;
+    double* work = F + 4 * n;
+    Level& L0 = P->levels[0];
+    auto residual = [&](const double* x, double* out) {  // A x + M S(x) - b
+      HIP_OK(launch_apply(P->N, kPuncture, x, out, b, alpha, beta, L0.d_nbr, L0.op, P->dt, P->acfg,
+                          s));
+    };
+    auto norm2 = [&](const double* x) { return device_norm2(P, x, n, s); };
+    P->diag_active = false;
+    residual(u, F);
+    double nrm2 = norm2(F);
+    if (!std::isfinite(nrm2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite nonlinear residual");
+    const double norm0 = std::sqrt(nrm2);
+    std::vector<double> hist{1.0};
+    int its = 0, steps = 0, backtracks = 0;
+    bool converged = norm0 == 0.0;
+    const double alpha_sd = 1e-4;  // sufficient-decrease parameter
+    const int max_bt = 10;
+    for (int step = 0; step < max_newton && !converged; ++step) {
+      // linearisation A + diag(M dS/du(u)) and the linear solve for du
+      HIP_OK(launch_puncture_diag(P->N, alpha, beta, u, work, L0.E, L0.h, P->dt, s));
+      set_diagonal(P, work, s);
+      HIP_OK(launch_fill(work, 0.0, n, s));
+      HIP_OK(launch_axpy(work, -1.0, F, n, s));  // right-hand side -F
+      HIP_OK(launch_fill(du, 0.0, n, s));
+      FgmresResult R = fgmres(P, work, du, linear_rtol, P->opt.max_iter, s);
+      its += R.iterations;
+      P->diag_active = false;
+      // backtracking line search on f = |F|^2 / 2 with the linear model's slope
+      const double f0 = 0.5 * nrm2, slope = -nrm2;
+      double lam = 1.0, lam_prev = 0.0, f_prev = 0.0, ft = 0.0;
+      for (int bt = 0; bt <= max_bt; ++bt) {
+        HIP_OK(launch_waxpy(ut, u, lam, du, n, s));
+        residual(ut, Ft);
+        ft = 0.5 * norm2(Ft);
+        if (!std::isfinite(ft)) throw DgsError(DGS_ERR_NONFINITE, "non-finite trial residual");
+        if (ft <= f0 + alpha_sd * lam * slope || bt == max_bt) break;
+        double next;
+        if (bt == 0) {
+          next = -slope * lam * lam / (2.0 * (ft - f0 - slope * lam));
+        } else {
+          const double r1 = ft - f0 - lam * slope, r2 = f_prev - f0 - lam_prev * slope;
+          const double ca = (r1 / (lam * lam) - r2 / (lam_prev * lam_prev)) / (lam - lam_prev);
+          const double cb = (-lam_prev * r1 / (lam * lam) + lam * r2 / (lam_prev * lam_prev)) /
+                            (lam - lam_prev);
+          if (ca == 0.0) {
+            next = -slope / (2.0 * cb);
+          } else {
+            const double disc = std::max(cb * cb - 3.0 * ca * slope, 0.0);
+            next = (-cb + std::sqrt(disc)) / (3.0 * ca);
+          }
+        }
+        next = std::min(next, 0.5 * lam);
+        next = std::max(next, 0.1 * lam);
+        lam_prev = lam;
+        f_prev = ft;
+        lam = next;
+        ++backtracks;
+      }
+      HIP_OK(launch_copy(u, ut, n, s));
+      std::swap(F, Ft);
+      nrm2 = 2.0 * ft;
+      ++steps;
+      hist.push_back(std::sqrt(nrm2) / norm0);
+      converged = std::sqrt(nrm2) <= newton_rtol * norm0;
+    }
+    P->diag_active = false;
+    HIP_OK(hipStreamSynchronize(s));
+    if (stats) {
+      stats->iterations = its;
+      stats->newton_steps = steps;
+      stats->backtracks = backtracks;
+      stats->rel_residual = std::sqrt(nrm2) / (norm0 > 0 ? norm0 : 1.0);
+      stats->t_solve_s = now_s() - t0;
+      stats->t_setup_s = P->t_setup;
+      stats->history_len = 0;
+      if (stats->history && stats->history_capacity > 0) {
+        const int m = std::min<int>(stats->history_capacity, (int)hist.size());
+        for (int i = 0; i < m; ++i) stats->history[i] = hist[i];
+        stats->history_len = m;
+      }
+    }
+    return converged ? DGS_OK : DGS_NOT_CONVERGED;
+  });
 }
 
 }  // extern "C"
