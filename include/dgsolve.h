@@ -154,6 +154,45 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
                      double* u, double newton_rtol, double linear_rtol, int max_newton,
                      dgs_stats* stats, void* stream);
 
+/* The p+1 Legendre-Gauss-Lobatto points on [-1, 1] (ascending), so that a
+ * caller can place its data: point (i, j, k) of element (e_x, e_y, e_z) sits at
+ * x = lower_x + h_x (e_x + (xi_i + 1) / 2), and likewise in y and z. */
+int dgs_lgl_nodes(int p, double* xi);
+
+/* ---- Serving: continuous batching of many Poisson solves on one device ----
+ * Requests queue until their estimated device footprint fits in
+ * hbm_budget_bytes and one of max_active slots is free; every admitted request
+ * keeps its mesh, multigrid hierarchy and Krylov basis resident until it
+ * finishes, and shares the subdomain inverses of a process-wide cache.  Each
+ * dgs_server_step admits what fits and advances every active request by one
+ * FGMRES stage, each on its own stream, so requests overlap on the device;
+ * a request's arithmetic is the same alone or in a mix (dgs_solve on the same
+ * inputs gives the same bits).  Single-threaded use. */
+typedef struct dgs_server dgs_server;
+typedef struct {
+  double hbm_budget_bytes; /* admission limit on the summed request footprints      */
+  int max_active;          /* at most this many requests on the device at once      */
+  double penalty;          /* C of every request                                    */
+  dgs_options solver;      /* options of every request                              */
+} dgs_server_options;
+
+int dgs_server_create(const dgs_server_options* opt, dgs_server** out);
+int dgs_server_destroy(dgs_server* server);
+/* Queue -Laplace(u) = f with u = 0 on the box: f (host, n = E N^3 values in
+ * the canonical layout) is copied.  *id receives the request id. */
+int dgs_server_submit(dgs_server* server, const dgs_domain* domain, const int elements[3], int p,
+                      const double* f, long long n, long long* id);
+/* Admit, then advance every active request by one stage; reports the counts. */
+int dgs_server_step(dgs_server* server, int* n_active, int* n_queued);
+/* Ids of finished requests (up to capacity) and their number. */
+int dgs_server_finished(dgs_server* server, long long* ids, int capacity, int* count);
+/* Copy a finished request's solution (host, n values) and stats, and release
+ * it.  times[0..3] = submit, admit and completion time in seconds since the
+ * server was created, and the footprint in bytes.  Returns DGS_OK,
+ * DGS_NOT_CONVERGED, or DGS_ERR_OOM for a request larger than the budget. */
+int dgs_server_fetch(dgs_server* server, long long id, double* u, long long n, dgs_stats* stats,
+                     double times[4]);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* dgs_last_error(void);
 

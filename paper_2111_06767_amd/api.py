@@ -28,6 +28,8 @@ EXPORTED = (
     "dgs_default_options", "dgs_create_problem", "dgs_destroy_problem", "dgs_num_dofs",
     "dgs_node_coordinates", "dgs_apply_mass", "dgs_apply_operator", "dgs_schwarz_smooth",
     "dgs_precondition", "dgs_solve", "dgs_newton_solve", "dgs_last_error", "dgs_set_diagonal",
+    "dgs_lgl_nodes", "dgs_server_create", "dgs_server_destroy", "dgs_server_submit",
+    "dgs_server_step", "dgs_server_finished", "dgs_server_fetch",
 )
 
 
@@ -49,6 +51,11 @@ class Stats(ctypes.Structure):
                 ("history", ctypes.POINTER(ctypes.c_double)), ("history_capacity", ctypes.c_int),
                 ("history_len", ctypes.c_int), ("t_setup_s", ctypes.c_double),
                 ("t_solve_s", ctypes.c_double)]
+
+
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_double), ("max_active", ctypes.c_int),
+                ("penalty", ctypes.c_double), ("solver", Options)]
 
 
 class DgsError(RuntimeError):
@@ -90,6 +97,18 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
     lib.dgs_newton_solve.argtypes = [P, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.POINTER(Stats), P]
+    lib.dgs_lgl_nodes.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.dgs_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
+    lib.dgs_server_destroy.argtypes = [P]
+    lib.dgs_server_submit.argtypes = [P, ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]
+    lib.dgs_server_step.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.dgs_server_finished.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]
+    lib.dgs_server_fetch.argtypes = [P, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.c_longlong, ctypes.POINTER(Stats),
+                                     ctypes.POINTER(ctypes.c_double)]
     lib.dgs_last_error.argtypes = []
     lib.dgs_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -241,3 +260,92 @@ def _stats_dict(st, hist, code):
     return dict(iterations=st.iterations, newton_steps=st.newton_steps, backtracks=st.backtracks,
                 rel_residual=st.rel_residual, history=[hist[i] for i in range(st.history_len)],
                 t_setup_s=st.t_setup_s, t_solve_s=st.t_solve_s, converged=(code == DGS_OK))
+
+
+def lgl_nodes(p):
+    """The p+1 LGL points on [-1, 1] (from the library)."""
+    import numpy as np
+    out = (ctypes.c_double * (p + 1))()
+    _check(load_library().dgs_lgl_nodes(int(p), out))
+    return np.array(out[:])
+
+
+def points(lower, upper, elements, p):
+    """Host coordinates (3, E*N^3) of every point in the canonical layout:
+    x = lower + h (e + (xi + 1) / 2) per dimension (see dgs_lgl_nodes)."""
+    import numpy as np
+    xi = lgl_nodes(p)
+    N = p + 1
+    nx, ny, nz = elements
+    out = []
+    for d, (n_d, lo, hi) in enumerate(zip(elements, lower, upper)):
+        h = (hi - lo) / n_d
+        c = lo + h * (np.arange(n_d)[:, None] + (xi[None, :] + 1.0) / 2.0)  # [e_d, node]
+        shape = [1] * 6
+        shape[2 - d] = n_d      # grid axes (e_z, e_y, e_x)
+        shape[5 - d] = N        # node axes (k, j, i)
+        full = np.broadcast_to(c.reshape(shape), (nz, ny, nx, N, N, N))
+        out.append(np.ascontiguousarray(full).reshape(-1))
+    return np.stack(out)
+
+
+class Server:
+    """Continuous-batching solve server (see dgs_server_* in include/dgsolve.h)."""
+
+    def __init__(self, hbm_budget_bytes=64e9, max_active=16, penalty=1.5, **solver_opts):
+        lib = load_library()
+        self._lib = lib
+        o = ServerOptions()
+        o.hbm_budget_bytes = float(hbm_budget_bytes)
+        o.max_active = int(max_active)
+        o.penalty = float(penalty)
+        o.solver = default_options(**solver_opts)
+        h = ctypes.c_void_p()
+        _check(lib.dgs_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._sizes = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dgs_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, lower, upper, elements, p, f):
+        import numpy as np
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        dom = Domain((ctypes.c_double * 3)(*lower), (ctypes.c_double * 3)(*upper))
+        rid = ctypes.c_longlong()
+        _check(self._lib.dgs_server_submit(self._h, ctypes.byref(dom), (ctypes.c_int * 3)(*elements),
+                                           int(p), f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           f.size, ctypes.byref(rid)))
+        self._sizes[rid.value] = f.size
+        return rid.value
+
+    def step(self):
+        a, q = ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.dgs_server_step(self._h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def finished(self):
+        c = ctypes.c_int()
+        _check(self._lib.dgs_server_finished(self._h, None, 0, ctypes.byref(c)))
+        ids = (ctypes.c_longlong * max(1, c.value))()
+        _check(self._lib.dgs_server_finished(self._h, ids, c.value, ctypes.byref(c)))
+        return [ids[i] for i in range(c.value)]
+
+    def fetch(self, rid, history=64):
+        """(u, stats, times) of a finished request; times = submit, admit, done, footprint."""
+        import numpy as np
+        n = self._sizes.pop(rid)
+        u = np.empty(n)
+        st, hist = _make_stats(history)
+        times = (ctypes.c_double * 4)()
+        code = _check(self._lib.dgs_server_fetch(self._h, rid, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 n, ctypes.byref(st), times), allow_not_converged=True)
+        return u, _stats_dict(st, hist, code), list(times)

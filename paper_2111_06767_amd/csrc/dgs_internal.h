@@ -68,9 +68,9 @@ hipError_t launch_coords(int N, double* xyz, const int n[3], const double lower[
 struct ClassInfo {
   int n;            // subdomain size n_S
   int count;        // number of subdomains (elements) in the class
-  long long inv_off;  // offset of this class's n x n matrix (transposed inverse)
+  const void* inv;    // stored transposed inverse (n x n, level precision)
+  const void* op;     // stored transposed subdomain operator A_S (level precision)
   double scale;       // factor applied to the stored inverse for this level
-  long long op_off;   // offset of the class's subdomain operator A_S (transposed)
   double scale_op;    // factor applied to the stored A_S for this level
   long long rs_off;   // offset of this class's [count][n] block in RS / DU
   int layout_off;     // offset into seg_loc / weights
@@ -90,9 +90,9 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 // Grouped subdomain GEMM: tiles_big use 64 x 128 block tiles (classes with
 // many subdomains), tiles_small 16 x 128 (classes with few).
 constexpr int kGemmBigM = 64, kGemmSmallM = 16, kGemmN = 128, kGemmSmallCount = 32;
-// use_op = 0: multiply by the stored inverse (offset inv_off, factor scale);
-// use_op = 1: by the stored subdomain operator (op_off, scale_op).
-hipError_t launch_subdomain_gemm(bool f32, const void* rs, const void* inv, void* du,
+// use_op = 0: multiply by the stored inverse (factor scale);
+// use_op = 1: by the stored subdomain operator (factor scale_op).
+hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,
                                  long long part_stride, const ClassInfo* cls,
                                  const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
                                  int nsmall, int use_op, hipStream_t s);

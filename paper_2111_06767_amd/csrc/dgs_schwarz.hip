@@ -14,16 +14,45 @@
 namespace dgs {
 namespace {
 
+// Subdomains are grouped by canonical boundary class: an element whose class
+// is the mirror image of a canonical class (a high external face where the
+// canonical class has the low one) uses the canonical class's inverse with its
+// points mirrored.  elem_class[e] = group | (mirror mask << 24), mask bit d set
+// when dimension d is mirrored.
+constexpr int kGroupMask = 0xFFFFFF;
+
+__device__ __forceinline__ int mirror_loc(int loc, int mask, int N) {
+  if (!mask) return loc;
+  int i = loc % N, j = (loc / N) % N, k = loc / (N * N);
+  if (mask & 1) i = N - 1 - i;
+  if (mask & 2) j = N - 1 - j;
+  if (mask & 4) k = N - 1 - k;
+  return (k * N + j) * N + i;
+}
+
+// canonical (segment, point) -> the element's own frame
+__device__ __forceinline__ void mirror_point(int& seg, int& loc, int mask, int N) {
+  if (!mask) return;
+  loc = mirror_loc(loc, mask, N);
+  if (seg > 0) {
+    const int f = seg - 1;
+    seg = (((mask >> (f >> 1)) & 1) ? (f ^ 1) : f) + 1;
+  }
+}
+
 // r_S = R_S r for the subdomain of element e (one workgroup per subdomain);
 // row elem_row[e] of the class block receives the n_S gathered values.
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_gather_rows(const double* __restrict__ r, T* __restrict__ rs, const int* __restrict__ elem_class,
               const long long* __restrict__ elem_row, const int* __restrict__ nbr,
-              const ClassInfo* __restrict__ cls, const int* __restrict__ seg_loc, int E, int N3) {
+              const ClassInfo* __restrict__ cls, const int* __restrict__ seg_loc, int E, int N) {
   const int e = blockIdx.x;
   if (e >= E) return;
-  const ClassInfo ci = cls[elem_class[e]];
+  const int N3 = N * N * N;
+  const int cv = elem_class[e];
+  const int mask = cv >> 24;
+  const ClassInfo ci = cls[cv & kGroupMask];
   __shared__ long long src[7];
   if (threadIdx.x < 7) {
     const int el = threadIdx.x == 0 ? e : nbr[(long long)e * 6 + threadIdx.x - 1];
@@ -34,8 +63,9 @@ k_gather_rows(const double* __restrict__ r, T* __restrict__ rs, const int* __res
   const int* lay = seg_loc + ci.layout_off;
   for (int k = threadIdx.x; k < ci.n; k += blockDim.x) {
     const int sl = lay[k];
-    const int seg = sl / N3;
-    const int loc = sl - seg * N3;
+    int seg = sl / N3;
+    int loc = sl - seg * N3;
+    mirror_point(seg, loc, mask, N);
     out[k] = (T)r[src[seg] + loc];
   }
 }
@@ -62,8 +92,10 @@ k_scatter(double* __restrict__ u, const T* __restrict__ du, int parts, long long
   const long long e = g / N3;
   const int loc = (int)(g - e * N3);
   const int idx[3] = {loc % N, (loc / N) % N, loc / N2};
-  const ClassInfo ce = cls[elem_class[e]];
-  double acc = weights[ce.layout_off + loc] * sum_parts(du, elem_row[e] + loc, parts, pstride);
+  const int cve = elem_class[e];
+  const ClassInfo ce = cls[cve & kGroupMask];
+  const int lc = mirror_loc(loc, cve >> 24, N);
+  double acc = weights[ce.layout_off + lc] * sum_parts(du, elem_row[e] + lc, parts, pstride);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const int b = nbr[e * 6 + f];
@@ -72,10 +104,14 @@ k_scatter(double* __restrict__ u, const T* __restrict__ du, int parts, long long
     const int m = idx[d];
     const int layer = (f & 1) ? (N - 1 - m) : m;
     if (layer >= nov) continue;
-    const int t0 = d == 0 ? idx[1] : idx[0];
-    const int t1 = d == 2 ? idx[1] : idx[2];
-    const ClassInfo cb = cls[elem_class[b]];
-    const int so = cb.strip_off[f ^ 1];
+    const int d0 = d == 0 ? 1 : 0, d1 = d == 2 ? 1 : 2;  // transverse dimensions
+    const int cvb = elem_class[b];
+    const int mb = cvb >> 24;
+    const ClassInfo cb = cls[cvb & kGroupMask];
+    const int g = ((mb >> d) & 1) ? f : (f ^ 1);  // b's face toward e, canonical frame
+    const int t0 = ((mb >> d0) & 1) ? N - 1 - idx[d0] : idx[d0];
+    const int t1 = ((mb >> d1) & 1) ? N - 1 - idx[d1] : idx[d1];
+    const int so = cb.strip_off[g];
     const int k = so + layer * N2 + t1 * N + t0;
     acc += weights[cb.layout_off + k] * sum_parts(du, elem_row[b] + k, parts, pstride);
   }
@@ -117,7 +153,7 @@ struct Mfma<float> {
 // while the current one is multiplied out of LDS.
 template <typename T, int WM, int WN, int TM, int TN, int BK>
 __global__ void __launch_bounds__(256)
-k_sub_gemm(const T* __restrict__ rs, const T* __restrict__ inv, T* __restrict__ du,
+k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
            long long pstride, const ClassInfo* __restrict__ cls,
            const GemmTile* __restrict__ tiles, int use_op) {
   constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
@@ -131,7 +167,7 @@ k_sub_gemm(const T* __restrict__ rs, const T* __restrict__ inv, T* __restrict__ 
   const ClassInfo ci = cls[tl.cls];
   const int n = ci.n, M = ci.count;
   const T* A = rs + ci.rs_off;
-  const T* B = inv + (use_op ? ci.op_off : ci.inv_off);
+  const T* B = (const T*)(use_op ? ci.op : ci.inv);
   T* C = du + tl.part * pstride + ci.rs_off;
   const int m0 = tl.m0, n0 = tl.n0, kbeg = tl.k0, kend = tl.k1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -231,7 +267,7 @@ k_sub_start(const T* __restrict__ rs, T* __restrict__ V0, double* __restrict__ b
   __shared__ double red[kSubThreads / 64];
   const int e = blockIdx.x;
   if (e >= E) return;
-  const int n = cls[elem_class[e]].n;
+  const int n = cls[elem_class[e] & kGroupMask].n;
   const long long row = elem_row[e];
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += kSubThreads) {
@@ -250,12 +286,15 @@ k_sub_arnoldi(int j, int kmax, const T* __restrict__ W, T* __restrict__ V, const
               long long stride, const double* __restrict__ diag, double* __restrict__ H,
               const int* __restrict__ elem_class, const long long* __restrict__ elem_row,
               const int* __restrict__ nbr, const ClassInfo* __restrict__ cls,
-              const int* __restrict__ seg_loc, int E, int N3) {
+              const int* __restrict__ seg_loc, int E, int N) {
   __shared__ double red[kSubThreads / 64];
   __shared__ long long src[7];
+  const int N3 = N * N * N;
   const int e = blockIdx.x;
   if (e >= E) return;
-  const ClassInfo ci = cls[elem_class[e]];
+  const int cv = elem_class[e];
+  const int mask = cv >> 24;
+  const ClassInfo ci = cls[cv & kGroupMask];
   const int n = ci.n;
   const long long row = elem_row[e];
   if (threadIdx.x < 7) {
@@ -271,8 +310,10 @@ k_sub_arnoldi(int j, int kmax, const T* __restrict__ W, T* __restrict__ V, const
     w[q] = 0.0;
     if (i < n) {
       const int sl = lay[i];
-      const int seg = sl / N3;
-      const double d = diag[src[seg] + (sl - seg * N3)];
+      int seg = sl / N3;
+      int loc = sl - seg * N3;
+      mirror_point(seg, loc, mask, N);
+      const double d = diag[src[seg] + loc];
       w[q] = (double)W[row + i] + d * (double)Zj[row + i];
     }
   }
@@ -318,7 +359,7 @@ k_sub_finish(int kmax, const T* __restrict__ Z, long long stride, const double* 
   __shared__ int mm;
   const int e = blockIdx.x;
   if (e >= E) return;
-  const int n = cls[elem_class[e]].n;
+  const int n = cls[elem_class[e] & kGroupMask].n;
   const long long row = elem_row[e];
   if (threadIdx.x == 0) {
     // least squares min |beta e1 - H y| by Givens rotations, stopping at a
@@ -401,15 +442,14 @@ hipError_t launch_sub_arnoldi(int N, bool f32, int j, int kmax, const void* W, v
                               const int* elem_class, const long long* elem_row, const int* nbr,
                               const ClassInfo* cls, const int* seg_loc, int E, hipStream_t s) {
   if (E <= 0) return hipSuccess;
-  const int N3 = N * N * N;
   if (f32)
     hipLaunchKernelGGL(k_sub_arnoldi<float>, dim3(E), dim3(kSubThreads), 0, s, j, kmax,
                        (const float*)W, (float*)V, (const float*)Zj, stride, diag, H, elem_class,
-                       elem_row, nbr, cls, seg_loc, E, N3);
+                       elem_row, nbr, cls, seg_loc, E, N);
   else
     hipLaunchKernelGGL(k_sub_arnoldi<double>, dim3(E), dim3(kSubThreads), 0, s, j, kmax,
                        (const double*)W, (double*)V, (const double*)Zj, stride, diag, H, elem_class,
-                       elem_row, nbr, cls, seg_loc, E, N3);
+                       elem_row, nbr, cls, seg_loc, E, N);
   return hipGetLastError();
 }
 
@@ -430,34 +470,33 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
                          const long long* elem_row, const int* nbr, const ClassInfo* cls,
                          const int* seg_loc, int E, hipStream_t s) {
   if (E <= 0) return hipSuccess;
-  const int N3 = N * N * N;
   if (f32)
     hipLaunchKernelGGL(k_gather_rows<float>, dim3(E), dim3(256), 0, s, r, (float*)rs, elem_class,
-                       elem_row, nbr, cls, seg_loc, E, N3);
+                       elem_row, nbr, cls, seg_loc, E, N);
   else
     hipLaunchKernelGGL(k_gather_rows<double>, dim3(E), dim3(256), 0, s, r, (double*)rs, elem_class,
-                       elem_row, nbr, cls, seg_loc, E, N3);
+                       elem_row, nbr, cls, seg_loc, E, N);
   return hipGetLastError();
 }
 
-hipError_t launch_subdomain_gemm(bool f32, const void* rs, const void* inv, void* du,
+hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,
                                  long long ps, const ClassInfo* cls,
                                  const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
                                  int nsmall, int use_op, hipStream_t s) {
   if (f32) {
     if (nbig > 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 32>), dim3(nbig), dim3(256), 0, s,
-                         (const float*)rs, (const float*)inv, (float*)du, ps, cls, tiles_big, use_op);
+                         (const float*)rs, (float*)du, ps, cls, tiles_big, use_op);
     if (nsmall > 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), dim3(nsmall), dim3(256), 0, s,
-                         (const float*)rs, (const float*)inv, (float*)du, ps, cls, tiles_small, use_op);
+                         (const float*)rs, (float*)du, ps, cls, tiles_small, use_op);
   } else {
     if (nbig > 0)
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), dim3(nbig), dim3(256), 0, s,
-                         (const double*)rs, (const double*)inv, (double*)du, ps, cls, tiles_big, use_op);
+                         (const double*)rs, (double*)du, ps, cls, tiles_big, use_op);
     if (nsmall > 0)
       hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 2, 16>), dim3(nsmall), dim3(256), 0, s,
-                         (const double*)rs, (const double*)inv, (double*)du, ps, cls, tiles_small, use_op);
+                         (const double*)rs, (double*)du, ps, cls, tiles_small, use_op);
   }
   return hipGetLastError();
 }

@@ -207,11 +207,6 @@ struct dgs_problem {
   int h_pinned_len = 0;
   bool diag_active = false;
   double t_setup = 0;
-  // stored subdomain inverses, one per (class flags, aspect) key
-  double* d_inv64 = nullptr;
-  float* d_inv32 = nullptr;
-  double* d_op64 = nullptr;  // stored subdomain operators, same keys and offsets
-  float* d_op32 = nullptr;
   double* d_newton = nullptr;  // Newton work vectors
   // captured V-cycles (index: linearised operator or not) and the capture stream
   hipGraphExec_t vgraph[2] = {nullptr, nullptr};
@@ -272,13 +267,25 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
 // Schwarz classes, layouts, tiles and work buffers of a level.
 void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   const int N = P->N, nov = nov_of(P);
+  // canonical class: a dimension with only its high face external is mirrored
+  // so that the low face is the external one (the DG operator, the subdomain
+  // geometry and the weights are all symmetric under the mirror)
   std::map<int, int> cls_of_flags;
-  std::vector<int> elem_flags(L.E);
+  std::vector<int> elem_flags(L.E), elem_mask(L.E);
   for (long long e = 0; e < L.E; ++e) {
     const int c[3] = {(int)(e % L.n[0]), (int)((e / L.n[0]) % L.n[1]),
                       (int)(e / ((long long)L.n[0] * L.n[1]))};
-    elem_flags[e] = class_flags(c, L.n);
-    cls_of_flags.emplace(elem_flags[e], 0);
+    int fl = class_flags(c, L.n), mask = 0;
+    for (int d = 0; d < 3; ++d) {
+      const int lo = (fl >> (2 * d)) & 1, hi = (fl >> (2 * d + 1)) & 1;
+      if (!lo && hi) {
+        mask |= 1 << d;
+        fl = (fl & ~(3 << (2 * d))) | (1 << (2 * d));
+      }
+    }
+    elem_flags[e] = fl;
+    elem_mask[e] = mask;
+    cls_of_flags.emplace(fl, 0);
   }
   int ci = 0;
   for (auto& kv : cls_of_flags) kv.second = ci++;
@@ -299,8 +306,10 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
     const ClassLayout& lay = L.layouts[c];
     I.n = lay.n;
     I.count = count[c];
-    I.inv_off = 0;  // set once the inverses exist
+    I.inv = nullptr;  // set once the inverses exist
+    I.op = nullptr;
     I.scale = 1.0;
+    I.scale_op = 1.0;
     I.rs_off = rs_off;
     I.layout_off = (int)seg_loc.size();
     for (int f = 0; f < 6; ++f) I.strip_off[f] = lay.strip_off[f];
@@ -343,8 +352,10 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   upload(L.d_seg_loc, seg_loc, s);
   L.d_weights = P->alloc<double>(weights.size());
   upload(L.d_weights, weights, s);
+  std::vector<int> elem_code(L.E);
+  for (long long e = 0; e < L.E; ++e) elem_code[e] = elem_class[e] | (elem_mask[e] << 24);
   L.d_elem_class = P->alloc<int>(L.E);
-  upload(L.d_elem_class, elem_class, s);
+  upload(L.d_elem_class, elem_code, s);
   L.d_elem_row = P->alloc<long long>(L.E);
   upload(L.d_elem_row, elem_row, s);
   L.nbig = (int)big.size();
@@ -371,51 +382,44 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
 // element outside the subdomain), then inverted by Gauss-Jordan elimination
 // (A_S is symmetric positive definite, so no pivoting is needed).  Uniform
 // scaling of all element widths by lambda scales A_S by lambda, so one inverse
-// per key serves every level with the same aspect ratio.
-void build_inverses(dgs_problem* P, hipStream_t s) {
+// per key serves every level and every problem with the same aspect ratio.
+// Keys live in a process-wide cache shared by all problems on a device (a
+// serving process reuses them across requests); cache memory is held until
+// the process ends.
+struct CacheEntry {
+  int device, N, nov, flags;
+  double ry, rz, penalty, hx;  // key and the reference width along x
+  int n;
+  double* inv64 = nullptr;
+  float* inv32 = nullptr;
+  double* op64 = nullptr;
+  float* op32 = nullptr;
+};
+std::mutex g_cache_mutex;
+std::vector<std::unique_ptr<CacheEntry>> g_cache;
+
+CacheEntry* cache_find(int device, int N, int nov, int flags, double ry, double rz, double penalty) {
+  for (auto& c : g_cache)
+    if (c->device == device && c->N == N && c->nov == nov && c->flags == flags &&
+        c->penalty == penalty && std::fabs(c->ry - ry) <= 1e-12 * ry &&
+        std::fabs(c->rz - rz) <= 1e-12 * rz)
+      return c.get();
+  return nullptr;
+}
+
+void build_keys(dgs_problem* P, const std::vector<std::unique_ptr<CacheEntry>>& todo,
+                const std::vector<const Level*>& ref, hipStream_t s) {
   const int N = P->N, N3 = N * N * N;
-  struct Key {
-    int flags;
-    double ry, rz;
-  };
-  struct Use {
-    int level, cls;
-    int key;
-  };
-  std::vector<Key> keys;
-  std::vector<double> key_hx;  // reference width along x
-  std::vector<int> key_level;  // reference level
-  std::vector<Use> uses;
-  for (int l = 0; l < (int)P->levels.size(); ++l) {
-    const Level& L = P->levels[l];
-    const double ry = L.h[1] / L.h[0], rz = L.h[2] / L.h[0];
-    for (int c = 0; c < (int)L.layouts.size(); ++c) {
-      int found = -1;
-      for (int k = 0; k < (int)keys.size(); ++k)
-        if (keys[k].flags == L.layouts[c].flags && std::fabs(keys[k].ry - ry) <= 1e-13 * ry &&
-            std::fabs(keys[k].rz - rz) <= 1e-13 * rz)
-          found = k;
-      if (found < 0) {
-        keys.push_back(Key{L.layouts[c].flags, ry, rz});
-        key_hx.push_back(L.h[0]);
-        key_level.push_back(l);
-        found = (int)keys.size() - 1;
-      }
-      uses.push_back(Use{l, c, found});
-    }
-  }
-  // layout of each key (identical to any level's layout with those flags)
-  const int nov = nov_of(P);
+  const int nk = (int)todo.size();
+  if (nk == 0) return;
   std::vector<ClassLayout> klay;
   int n_pad = 0;
-  for (auto& k : keys) {
-    klay.push_back(make_layout(k.flags, N, nov, P->ht.xi));
+  for (auto& k : todo) {
+    klay.push_back(make_layout(k->flags, N, k->nov, P->ht.xi));
     n_pad = std::max(n_pad, klay.back().n);
   }
-  const int nk = (int)keys.size();
   double* d_batch = dalloc<double>((size_t)nk * n_pad * n_pad);
   std::unique_ptr<void, void (*)(void*)> g1(d_batch, [](void* p) { (void)hipFree(p); });
-  // identity padding everywhere first
   {
     std::vector<double> eye((size_t)n_pad * n_pad, 0.0);
     for (int i = 0; i < n_pad; ++i) eye[(size_t)i * n_pad + i] = 1.0;
@@ -426,7 +430,6 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
   }
   for (int k = 0; k < nk; ++k) {
     const ClassLayout& lay = klay[k];
-    const Level& Lref = P->levels[key_level[k]];
     // patch: 0 = central, 1.. = existing face neighbours, last = zero element
     int face_elem[6];
     int Ep = 1;
@@ -472,53 +475,88 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
     upload(d_idx, idx, s);
     HIP_OK(launch_fill(d_X, 0.0, tot, s));
     HIP_OK(launch_unit_columns(d_X, stride, d_idx, n, s));
-    OpParams op = Lref.op;
+    OpParams op = ref[k]->op;
     op.E = (int)(Ep * (long long)n);
     HIP_OK(launch_apply(N, kApply, d_X, d_AX, nullptr, nullptr, nullptr, d_nb, op, P->dt, P->acfg, s));
     HIP_OK(launch_gather_columns(d_AX, stride, d_idx, n, d_batch + (size_t)k * n_pad * n_pad, n_pad, s));
     HIP_OK(hipStreamSynchronize(s));
   }
-  // keep A_S itself (transposed, unscaled) for the linearised subdomain solver
-  std::vector<long long> koff(nk);
-  long long total = 0;
+  // keep A_S itself (transposed) for the linearised subdomain solver
   for (int k = 0; k < nk; ++k) {
-    koff[k] = total;
-    total += (long long)klay[k].n * klay[k].n;
+    CacheEntry& c = *todo[k];
+    c.n = klay[k].n;
+    const size_t nn = (size_t)c.n * c.n;
+    c.op64 = dalloc<double>(nn);
+    c.op32 = dalloc<float>(nn);
+    c.inv64 = dalloc<double>(nn);
+    c.inv32 = dalloc<float>(nn);
+    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, c.n, 1.0, c.op64,
+                                 c.op32, s));
   }
-  std::vector<char> need64(nk, 0), need32(nk, 0);
-  for (const Use& u : uses) (P->levels[u.level].f32 ? need32 : need64)[u.key] = 1;
-  bool any64 = false, any32 = false;
-  for (int k = 0; k < nk; ++k) {
-    any64 = any64 || need64[k];
-    any32 = any32 || need32[k];
-  }
-  if (any64) P->d_op64 = P->alloc<double>(total);
-  if (any32) P->d_op32 = P->alloc<float>(total);
-  for (int k = 0; k < nk; ++k)
-    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, klay[k].n, 1.0,
-                                 need64[k] ? P->d_op64 + koff[k] : nullptr,
-                                 need32[k] ? P->d_op32 + koff[k] : nullptr, s));
-  // batched Gauss-Jordan
   double* d_col = dalloc<double>((size_t)nk * n_pad);
   std::unique_ptr<void, void (*)(void*)> g6(d_col, [](void* p) { (void)hipFree(p); });
   double* d_row = dalloc<double>((size_t)nk * n_pad);
   std::unique_ptr<void, void (*)(void*)> g7(d_row, [](void* p) { (void)hipFree(p); });
   for (int k = 0; k < n_pad; ++k) HIP_OK(launch_gj_step(d_batch, n_pad, nk, k, d_col, d_row, s));
-  // one stored (transposed) inverse per key, in the precisions its levels use;
-  // each level's classes point at it with the scale h_ref / h
-  if (any64) P->d_inv64 = P->alloc<double>(total);
-  if (any32) P->d_inv32 = P->alloc<float>(total);
-  for (int k = 0; k < nk; ++k)
-    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, klay[k].n, 1.0,
-                                 need64[k] ? P->d_inv64 + koff[k] : nullptr,
-                                 need32[k] ? P->d_inv32 + koff[k] : nullptr, s));
+  for (int k = 0; k < nk; ++k) {
+    CacheEntry& c = *todo[k];
+    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, c.n, 1.0, c.inv64,
+                                 c.inv32, s));
+  }
+  HIP_OK(hipStreamSynchronize(s));
+}
+
+void build_inverses(dgs_problem* P, hipStream_t s) {
+  int device = 0;
+  HIP_OK(hipGetDevice(&device));
+  const int nov = nov_of(P);
+  std::lock_guard<std::mutex> lk(g_cache_mutex);
+  std::vector<std::unique_ptr<CacheEntry>> todo;
+  std::vector<const Level*> ref;
+  struct Use {
+    int level, cls;
+    CacheEntry* entry;
+  };
+  std::vector<Use> uses;
+  std::vector<std::pair<int, int>> pending;  // (level, class) waiting for a new key
+  for (int l = 0; l < (int)P->levels.size(); ++l) {
+    const Level& L = P->levels[l];
+    const double ry = L.h[1] / L.h[0], rz = L.h[2] / L.h[0];
+    for (int c = 0; c < (int)L.layouts.size(); ++c) {
+      const int flags = L.layouts[c].flags;
+      CacheEntry* e = cache_find(device, P->N, nov, flags, ry, rz, P->penalty);
+      if (!e) {
+        for (auto& t : todo)
+          if (t->flags == flags && std::fabs(t->ry - ry) <= 1e-12 * ry &&
+              std::fabs(t->rz - rz) <= 1e-12 * rz)
+            e = t.get();
+      }
+      if (!e) {
+        std::unique_ptr<CacheEntry> ne(new CacheEntry());
+        ne->device = device;
+        ne->N = P->N;
+        ne->nov = nov;
+        ne->flags = flags;
+        ne->ry = ry;
+        ne->rz = rz;
+        ne->penalty = P->penalty;
+        ne->hx = L.h[0];
+        e = ne.get();
+        todo.push_back(std::move(ne));
+        ref.push_back(&L);
+      }
+      uses.push_back(Use{l, c, e});
+    }
+  }
+  build_keys(P, todo, ref, s);
+  for (auto& t : todo) g_cache.push_back(std::move(t));
   for (const Use& u : uses) {
     Level& L = P->levels[u.level];
     ClassInfo& I = L.cls[u.cls];
-    I.inv_off = koff[u.key];
-    I.scale = key_hx[u.key] / L.h[0];  // A_S(lambda h) = lambda A_S(h)
-    I.op_off = koff[u.key];
-    I.scale_op = L.h[0] / key_hx[u.key];
+    I.inv = L.f32 ? (const void*)u.entry->inv32 : (const void*)u.entry->inv64;
+    I.op = L.f32 ? (const void*)u.entry->op32 : (const void*)u.entry->op64;
+    I.scale = u.entry->hx / L.h[0];  // A_S(lambda h) = lambda A_S(h)
+    I.scale_op = L.h[0] / u.entry->hx;
   }
   for (Level& L : P->levels) upload(L.d_cls, L.cls, s);
   HIP_OK(hipStreamSynchronize(s));
@@ -592,17 +630,15 @@ void subdomain_gmres(dgs_problem* P, Level& L, hipStream_t s) {
   const size_t es = L.f32 ? sizeof(float) : sizeof(double);
   const long long st = L.rs_total;
   auto slot = [&](void* base, int i) { return (void*)((char*)base + es * (size_t)st * i); };
-  const void* inv = L.f32 ? (const void*)P->d_inv32 : (const void*)P->d_inv64;
-  const void* op = L.f32 ? (const void*)P->d_op32 : (const void*)P->d_op64;
   HIP_OK(launch_sub_start(L.f32, L.d_rs, L.d_gV, L.d_gbeta, L.d_elem_class, L.d_elem_row, L.d_cls,
                           (int)L.E, s));
   for (int j = 0; j < k; ++j) {
     void* Vj = slot(L.d_gV, j);
     void* Zj = slot(L.d_gZ, j);
-    HIP_OK(launch_subdomain_gemm(L.f32, Vj, inv, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
+    HIP_OK(launch_subdomain_gemm(L.f32, Vj, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
                                  L.d_tiles_small, L.nsmall, 0, s));
     HIP_OK(launch_reduce_parts(L.f32, Zj, L.d_du, L.kparts, st, st, s));
-    HIP_OK(launch_subdomain_gemm(L.f32, Zj, op, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
+    HIP_OK(launch_subdomain_gemm(L.f32, Zj, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
                                  L.d_tiles_small, L.nsmall, 1, s));
     HIP_OK(launch_reduce_parts(L.f32, L.d_gW, L.d_du, L.kparts, st, st, s));
     HIP_OK(launch_sub_arnoldi(N, L.f32, j, k, L.d_gW, L.d_gV, Zj, st, L.d_diag, L.d_gH,
@@ -632,8 +668,7 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
                             L.d_elem_row, L.d_nbr, L.d_cls, nov_of(P), L.E, s));
       continue;
     }
-    HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.f32 ? (const void*)P->d_inv32 : (const void*)P->d_inv64,
-                                 L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
+    HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
                                  L.d_tiles_small, L.nsmall, 0, s));
     HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.kparts, L.rs_total, L.d_weights, L.d_elem_class,
                           L.d_elem_row, L.d_nbr, L.d_cls, nov_of(P), L.E, s));
@@ -722,8 +757,8 @@ void ensure_krylov(dgs_problem* P, int m) {
   P->d_tmp2 = P->alloc<double>(n);
   if (P->h_pinned) (void)hipHostFree(P->h_pinned);
   P->h_pinned = nullptr;
-  HIP_OK(hipHostMalloc((void**)&P->h_pinned, sizeof(double) * 3 * (m + 2), hipHostMallocDefault));
-  P->h_pinned_len = 3 * (m + 2);
+  HIP_OK(hipHostMalloc((void**)&P->h_pinned, sizeof(double) * 4 * (m + 2), hipHostMallocDefault));
+  P->h_pinned_len = 4 * (m + 2);
   P->kry_m = m;
 }
 
@@ -787,91 +822,151 @@ struct FgmresResult {
   std::vector<double> history;
 };
 
-// Flexible GMRES (Saad Alg. 9.6) on the fine level, x holds x0 on entry.
+// Flexible GMRES (Saad Alg. 9.6) on the fine level as a resumable state
+// machine: issue() enqueues the device work of the current stage on the
+// stream without waiting, complete() runs the host part once the stream has
+// been synchronised.  Stages: start (r0 = b - A x0 and its norm), one stage
+// per iteration (V-cycle, operator, classical Gram-Schmidt twice, norm, the
+// Hessenberg column to pinned memory), finish (x = x0 + Z y, true residual).
+// dgs_solve runs the stages back to back; the server interleaves the stages
+// of many requests, so a request computes the same numbers alone or in a mix.
+struct FgmresRun {
+  dgs_problem* P = nullptr;
+  const double* b = nullptr;
+  double* x = nullptr;
+  double rtol = 0;
+  int m = 0;
+  hipStream_t s = nullptr;
+  enum Stage { kStart, kIter, kFinish, kDone } stage = kStart;
+  int j = 0;
+  double beta = 0;
+  std::vector<double> H, cs, sn, g;
+  FgmresResult R;
+
+  void init(dgs_problem* p, const double* bb, double* xx, double rt, int mi, hipStream_t st) {
+    P = p;
+    b = bb;
+    x = xx;
+    rtol = rt;
+    m = mi;
+    s = st;
+    ensure_krylov(P, m);
+    stage = kStart;
+    j = 0;
+    H.assign((size_t)(m + 1) * m, 0.0);
+    cs.assign(m, 0.0);
+    sn.assign(m, 0.0);
+    g.assign(m + 1, 0.0);
+    R = FgmresResult();
+  }
+  bool done() const { return stage == kDone; }
+
+  void issue() {
+    const long long n = P->nd(0);
+    double* V = P->d_V;
+    double* Z = P->d_Z;
+    double* hp = P->h_pinned;
+    if (stage == kStart) {
+      residual_fine(P, x, b, V, s);
+      HIP_OK(launch_multidot(V, n, 1, V, n, P->d_partial, P->d_h, s));
+      HIP_OK(hipMemcpyAsync(hp, P->d_h, sizeof(double), hipMemcpyDeviceToHost, s));
+    } else if (stage == kIter) {
+      double* vj = V + (size_t)j * n;
+      double* zj = Z + (size_t)j * n;
+      double* w = V + (size_t)(j + 1) * n;
+      vcycle(P, vj, zj, s);
+      apply_fine(P, zj, w, s);
+      double* h1 = P->d_h;
+      double* h2 = P->d_h + (m + 2);
+      double* hn = P->d_h + 2 * (m + 2);
+      HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h1, s));
+      HIP_OK(launch_multi_axpy(w, V, n, j + 1, h1, n, s));
+      HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h2, s));
+      HIP_OK(launch_multi_axpy(w, V, n, j + 1, h2, n, s));
+      HIP_OK(launch_multidot(w, n, 1, w, n, P->d_partial, hn, s));
+      // h1, h2 and |w|^2 are contiguous on the device: one copy
+      HIP_OK(hipMemcpyAsync(hp, P->d_h, sizeof(double) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, s));
+      HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));  // unused if |w| = 0 (the run stops)
+    } else if (stage == kFinish) {
+      const int k = R.iterations;
+      std::vector<double> y(k, 0.0);
+      for (int i = k - 1; i >= 0; --i) {
+        double t = g[i];
+        for (int q = i + 1; q < k; ++q) t -= H[(size_t)q * (m + 1) + i] * y[q];
+        y[i] = t / H[(size_t)i * (m + 1) + i];
+      }
+      double* ypin = hp + 3 * (m + 2);
+      for (int i = 0; i < k; ++i) ypin[i] = y[i];
+      if (k > 0) {
+        HIP_OK(hipMemcpyAsync(P->d_y, ypin, sizeof(double) * k, hipMemcpyHostToDevice, s));
+        HIP_OK(launch_combine(x, Z, n, k, P->d_y, n, s));
+      }
+      residual_fine(P, x, b, P->d_tmp, s);
+      HIP_OK(launch_multidot(P->d_tmp, n, 1, P->d_tmp, n, P->d_partial, P->d_h, s));
+      HIP_OK(hipMemcpyAsync(hp, P->d_h, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+  }
+
+  void complete() {
+    const double* hp = P->h_pinned;
+    if (stage == kStart) {
+      const double beta2 = hp[0];
+      if (!std::isfinite(beta2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite initial residual");
+      beta = std::sqrt(beta2);
+      R.history.push_back(1.0);
+      if (beta == 0.0) {
+        R.converged = true;
+        stage = kDone;
+        return;
+      }
+      g[0] = beta;
+      HIP_OK(launch_scale_by_inv_norm(P->d_V, P->d_V, P->d_h, P->nd(0), s));
+      stage = kIter;
+    } else if (stage == kIter) {
+      double* col = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
+      for (int i = 0; i <= j; ++i) col[i] = hp[i] + hp[(m + 2) + i];
+      const double hn2 = hp[2 * (m + 2)];
+      col[j + 1] = std::sqrt(hn2);
+      for (int i = 0; i <= j + 1; ++i)
+        if (!std::isfinite(col[i])) throw DgsError(DGS_ERR_NONFINITE, "non-finite Hessenberg entry");
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = std::hypot(col[j], col[j + 1]);
+      cs[j] = col[j] / den;
+      sn[j] = col[j + 1] / den;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      R.history.push_back(std::fabs(g[j + 1]) / beta);
+      ++j;
+      R.iterations = j;
+      if (std::fabs(g[j]) <= rtol * beta || hn2 == 0.0) {
+        R.converged = true;
+        stage = kFinish;
+      } else if (j >= m) {
+        stage = kFinish;
+      }
+    } else if (stage == kFinish) {
+      R.rel_residual = std::sqrt(hp[0]) / beta;
+      stage = kDone;
+    }
+  }
+};
+
 FgmresResult fgmres(dgs_problem* P, const double* b, double* x, double rtol, int max_iter,
                     hipStream_t s) {
-  FgmresResult R;
-  const long long n = P->nd(0);
-  ensure_krylov(P, max_iter);
-  double* V = P->d_V;
-  double* Z = P->d_Z;
-  residual_fine(P, x, b, V, s);
-  const double beta2 = device_norm2(P, V, n, s);
-  if (!std::isfinite(beta2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite initial residual");
-  const double beta = std::sqrt(beta2);
-  R.history.push_back(1.0);
-  if (beta == 0.0) {
-    R.converged = true;
-    return R;
-  }
-  HIP_OK(launch_scale_by_inv_norm(V, V, P->d_h, n, s));
-  const int m = max_iter;
-  std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1, 0.0);
-  g[0] = beta;
-  std::vector<double> hh(2 * (m + 2));
-  int j = 0;
-  for (j = 0; j < m; ++j) {
-    double* vj = V + (size_t)j * n;
-    double* zj = Z + (size_t)j * n;
-    double* w = V + (size_t)(j + 1) * n;
-    vcycle(P, vj, zj, s);
-    apply_fine(P, zj, w, s);
-    // classical Gram-Schmidt, twice
-    double* h1 = P->d_h;
-    double* h2 = P->d_h + (m + 2);
-    double* hn = P->d_h + 2 * (m + 2);
-    HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h1, s));
-    HIP_OK(launch_multi_axpy(w, V, n, j + 1, h1, n, s));
-    HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h2, s));
-    HIP_OK(launch_multi_axpy(w, V, n, j + 1, h2, n, s));
-    HIP_OK(launch_multidot(w, n, 1, w, n, P->d_partial, hn, s));
-    // one copy of h1, h2 and |w|^2 (contiguous on the device) per iteration
-    HIP_OK(hipMemcpyAsync(P->h_pinned, P->d_h, sizeof(double) * (2 * (m + 2) + 1),
-                          hipMemcpyDeviceToHost, s));
+  FgmresRun run;
+  run.init(P, b, x, rtol, max_iter, s);
+  while (!run.done()) {
+    run.issue();
     HIP_OK(hipStreamSynchronize(s));
-    for (int i = 0; i < 2 * (m + 2); ++i) hh[i] = P->h_pinned[i];
-    const double hn2 = P->h_pinned[2 * (m + 2)];
-    double* col = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
-    for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[(m + 2) + i];
-    col[j + 1] = std::sqrt(hn2);
-    for (int i = 0; i <= j + 1; ++i)
-      if (!std::isfinite(col[i])) throw DgsError(DGS_ERR_NONFINITE, "non-finite Hessenberg entry");
-    if (hn2 > 0.0) HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));
-    for (int i = 0; i < j; ++i) {
-      const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-      col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-      col[i] = t;
-    }
-    const double den = std::hypot(col[j], col[j + 1]);
-    cs[j] = col[j] / den;
-    sn[j] = col[j + 1] / den;
-    col[j] = den;
-    col[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    R.history.push_back(std::fabs(g[j + 1]) / beta);
-    if (std::fabs(g[j + 1]) <= rtol * beta || hn2 == 0.0) {
-      R.converged = true;
-      ++j;
-      break;
-    }
+    run.complete();
   }
-  const int k = std::min(j, m);
-  // back substitution for y
-  std::vector<double> y(k, 0.0);
-  for (int i = k - 1; i >= 0; --i) {
-    double t = g[i];
-    for (int q = i + 1; q < k; ++q) t -= H[(size_t)q * (m + 1) + i] * y[q];
-    y[i] = t / H[(size_t)i * (m + 1) + i];
-  }
-  if (k > 0) {
-    HIP_OK(hipMemcpyAsync(P->d_y, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
-    HIP_OK(launch_combine(x, Z, n, k, P->d_y, n, s));
-  }
-  R.iterations = k;
-  residual_fine(P, x, b, P->d_tmp, s);
-  R.rel_residual = std::sqrt(device_norm2(P, P->d_tmp, n, s)) / beta;
-  return R;
+  return run.R;
 }
 
 int fail(int code, const std::string& msg) {
@@ -905,6 +1000,135 @@ void fill_stats(dgs_stats* st, const FgmresResult& R, double t0, double t_setup)
     for (int i = 0; i < n; ++i) st->history[i] = R.history[i];
     st->history_len = n;
   }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Serving: continuous batching of many solves on one device
+// ===========================================================================
+// Requests wait in a FIFO queue until their estimated device footprint fits in
+// the budget and a slot is free.  Every active request owns a problem (mesh,
+// hierarchy, Krylov basis, all resident until it finishes) and a stream; the
+// subdomain inverses come from the shared process-wide cache.  Each step
+// enqueues the next FGMRES stage of every active request on its stream, so the
+// requests' kernels overlap on the device, then completes all of them on the
+// host; finished requests free their memory and queued ones are admitted.
+namespace {
+
+struct ServerRequest {
+  long long id = 0;
+  dgs_domain dom{};
+  int elements[3] = {0, 0, 0};
+  int p = 0;
+  std::vector<double> f;  // host copy of f at the points
+  size_t footprint = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  dgs_problem* prob = nullptr;
+  hipStream_t stream = nullptr;
+  double *d_b = nullptr, *d_u = nullptr;
+  FgmresRun run;
+  std::vector<double> u;  // result
+  FgmresResult result;
+  double t_setup = 0;
+  int status = 0;
+};
+
+}  // namespace
+
+struct dgs_server {
+  dgs_server_options opt{};
+  long long next_id = 1;
+  size_t used = 0;
+  std::vector<std::unique_ptr<ServerRequest>> queue, active;
+  std::map<long long, std::unique_ptr<ServerRequest>> finished;
+  std::vector<hipStream_t> free_streams;
+  double t0 = 0;
+  ~dgs_server() {
+    for (auto& r : active) {
+      if (r->prob) delete r->prob;
+      if (r->d_b) (void)hipFree(r->d_b);
+      if (r->d_u) (void)hipFree(r->d_u);
+      if (r->stream) (void)hipStreamDestroy(r->stream);
+    }
+    for (hipStream_t st : free_streams) (void)hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+size_t request_footprint(const dgs_server* S, const int el[3], int p) {
+  const double ndof = (double)el[0] * el[1] * el[2] * (p + 1.0) * (p + 1.0) * (p + 1.0);
+  // Krylov basis (2m+1 vectors), b and u, Newton-free work vectors, level
+  // vectors and Schwarz buffers (about 16 vectors' worth, all levels together)
+  const double vecs = 2.0 * S->opt.solver.max_iter + 1 + 2 + 4 + 16;
+  return (size_t)(ndof * 8.0 * vecs);
+}
+
+void server_admit(dgs_server* S) {
+  while (!S->queue.empty() && (int)S->active.size() < S->opt.max_active) {
+    ServerRequest& r = *S->queue.front();
+    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && !S->active.empty()) break;
+    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && S->active.empty() &&
+        r.footprint > (size_t)S->opt.hbm_budget_bytes) {
+      // can never fit: reject
+      std::unique_ptr<ServerRequest> rq = std::move(S->queue.front());
+      S->queue.erase(S->queue.begin());
+      rq->status = DGS_ERR_OOM;
+      rq->t_done = now_s() - S->t0;
+      S->finished[rq->id] = std::move(rq);
+      continue;
+    }
+    std::unique_ptr<ServerRequest> rq = std::move(S->queue.front());
+    S->queue.erase(S->queue.begin());
+    if (!S->free_streams.empty()) {
+      rq->stream = S->free_streams.back();
+      S->free_streams.pop_back();
+    } else {
+      HIP_OK(hipStreamCreateWithFlags(&rq->stream, hipStreamNonBlocking));
+    }
+    const double ta = now_s();
+    dgs_problem* prob = nullptr;
+    const int code = dgs_create_problem(&rq->dom, rq->elements, rq->p, S->opt.penalty,
+                                        &S->opt.solver, rq->stream, &prob);
+    if (code != DGS_OK) throw DgsError(code, g_last_error);
+    rq->prob = prob;
+    const long long n = prob->nd(0);
+    rq->d_b = dalloc<double>(n);
+    rq->d_u = dalloc<double>(n);
+    // f to the device (pinned staging is not needed: a one-off copy), b = M f
+    HIP_OK(hipMemcpyAsync(rq->d_u, rq->f.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                          rq->stream));
+    const Level& L0 = prob->levels[0];
+    HIP_OK(launch_mass(prob->N, rq->d_u, rq->d_b, L0.E, L0.h, prob->dt, rq->stream));
+    HIP_OK(launch_fill(rq->d_u, 0.0, n, rq->stream));
+    rq->run.init(prob, rq->d_b, rq->d_u, S->opt.solver.rtol, S->opt.solver.max_iter, rq->stream);
+    rq->t_setup = now_s() - ta;
+    rq->t_admit = ta - S->t0;
+    S->used += rq->footprint;
+    S->active.push_back(std::move(rq));
+  }
+}
+
+void server_retire(dgs_server* S, std::unique_ptr<ServerRequest> rq) {
+  const long long n = rq->prob->nd(0);
+  rq->u.resize(n);
+  HIP_OK(hipMemcpyAsync(rq->u.data(), rq->d_u, sizeof(double) * n, hipMemcpyDeviceToHost, rq->stream));
+  HIP_OK(hipStreamSynchronize(rq->stream));
+  rq->result = rq->run.R;
+  rq->status = rq->result.converged ? DGS_OK : DGS_NOT_CONVERGED;
+  rq->t_done = now_s() - S->t0;
+  delete rq->prob;
+  rq->prob = nullptr;
+  (void)hipFree(rq->d_b);
+  (void)hipFree(rq->d_u);
+  rq->d_b = rq->d_u = nullptr;
+  S->free_streams.push_back(rq->stream);
+  rq->stream = nullptr;
+  S->used -= rq->footprint;
+  rq->f.clear();
+  rq->f.shrink_to_fit();
+  S->finished[rq->id] = std::move(rq);
 }
 
 }  // namespace
@@ -1183,6 +1407,140 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
       }
     }
     return converged ? DGS_OK : DGS_NOT_CONVERGED;
+  });
+}
+
+int dgs_lgl_nodes(int p, double* xi) {
+  return guarded([&]() -> int {
+    if (!xi || p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "need p in [1, 8] and xi");
+    HostTables t = make_tables(p + 1);
+    for (int i = 0; i <= p; ++i) xi[i] = t.xi[i];
+    return DGS_OK;
+  });
+}
+
+int dgs_server_create(const dgs_server_options* opt, dgs_server** out) {
+  return guarded([&]() -> int {
+    if (!opt || !out) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (opt->max_active < 1 || !(opt->hbm_budget_bytes > 0) || !(opt->penalty > 0))
+      return fail(DGS_ERR_INVALID, "invalid server options");
+    dgs_server* S = new dgs_server();
+    S->opt = *opt;
+    S->t0 = now_s();
+    *out = S;
+    return DGS_OK;
+  });
+}
+
+int dgs_server_destroy(dgs_server* S) {
+  return guarded([&]() -> int {
+    if (S) {
+      (void)hipDeviceSynchronize();
+      delete S;
+    }
+    return DGS_OK;
+  });
+}
+
+int dgs_server_submit(dgs_server* S, const dgs_domain* domain, const int elements[3], int p,
+                      const double* f, long long n, long long* id) {
+  return guarded([&]() -> int {
+    if (!S || !domain || !elements || !f || !id) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 8]");
+    for (int d = 0; d < 3; ++d)
+      if (elements[d] < 1 || !(domain->upper[d] > domain->lower[d]))
+        return fail(DGS_ERR_INVALID, "bad mesh");
+    const long long nd = (long long)elements[0] * elements[1] * elements[2] * (p + 1) * (p + 1) * (p + 1);
+    if (n != nd) return fail(DGS_ERR_INVALID, "f has the wrong length");
+    std::unique_ptr<ServerRequest> r(new ServerRequest());
+    r->id = S->next_id++;
+    r->dom = *domain;
+    for (int d = 0; d < 3; ++d) r->elements[d] = elements[d];
+    r->p = p;
+    r->f.assign(f, f + n);
+    r->footprint = request_footprint(S, elements, p);
+    r->t_submit = now_s() - S->t0;
+    *id = r->id;
+    S->queue.push_back(std::move(r));
+    return DGS_OK;
+  });
+}
+
+int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
+  return guarded([&]() -> int {
+    if (!S) return fail(DGS_ERR_INVALID, "NULL argument");
+    server_admit(S);
+    for (auto& r : S->active) r->run.issue();
+    std::vector<std::unique_ptr<ServerRequest>> still;
+    for (auto& r : S->active) {
+      HIP_OK(hipStreamSynchronize(r->stream));
+      r->run.complete();
+    }
+    for (auto& r : S->active) {
+      if (r->run.done())
+        server_retire(S, std::move(r));
+      else
+        still.push_back(std::move(r));
+    }
+    S->active = std::move(still);
+    if (n_active) *n_active = (int)S->active.size();
+    if (n_queued) *n_queued = (int)S->queue.size();
+    return DGS_OK;
+  });
+}
+
+int dgs_server_finished(dgs_server* S, long long* ids, int capacity, int* count) {
+  return guarded([&]() -> int {
+    if (!S || !count) return fail(DGS_ERR_INVALID, "NULL argument");
+    int c = 0;
+    for (auto& kv : S->finished) {
+      if (ids && c < capacity) ids[c] = kv.first;
+      ++c;
+    }
+    *count = c;
+    return DGS_OK;
+  });
+}
+
+int dgs_server_fetch(dgs_server* S, long long id, double* u, long long n, dgs_stats* stats,
+                     double times[4]) {
+  return guarded([&]() -> int {
+    if (!S) return fail(DGS_ERR_INVALID, "NULL argument");
+    auto it = S->finished.find(id);
+    if (it == S->finished.end()) return fail(DGS_ERR_INVALID, "request not finished or unknown");
+    ServerRequest& r = *it->second;
+    if (r.status < 0) {
+      const int st = r.status;
+      S->finished.erase(it);
+      return fail(st, "request rejected: its footprint exceeds the device budget");
+    }
+    if (u) {
+      if (n != (long long)r.u.size()) return fail(DGS_ERR_INVALID, "u has the wrong length");
+      std::copy(r.u.begin(), r.u.end(), u);
+    }
+    if (stats) {
+      stats->iterations = r.result.iterations;
+      stats->newton_steps = 0;
+      stats->backtracks = 0;
+      stats->rel_residual = r.result.rel_residual;
+      stats->t_setup_s = r.t_setup;
+      stats->t_solve_s = r.t_done - r.t_admit;
+      stats->history_len = 0;
+      if (stats->history && stats->history_capacity > 0) {
+        const int m = std::min<int>(stats->history_capacity, (int)r.result.history.size());
+        for (int i = 0; i < m; ++i) stats->history[i] = r.result.history[i];
+        stats->history_len = m;
+      }
+    }
+    if (times) {
+      times[0] = r.t_submit;
+      times[1] = r.t_admit;
+      times[2] = r.t_done;
+      times[3] = (double)r.footprint;
+    }
+    const int status = r.status;
+    S->finished.erase(it);
+    return status;
   });
 }
 

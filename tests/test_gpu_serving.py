@@ -1,0 +1,98 @@
+"""GPU tests of the continuous-batching server: every request's result is
+bit-identical alone and in a mix, admission respects the device budget, and
+results satisfy the oracle's DG equations."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mesh as omesh, operator as oop
+from tests.gpu_util import announce, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+REQS = [((2, 3, 2), 3, 1.0), ((3, 2, 2), 4, 2.0), ((2, 2, 2), 5, 1.0), ((4, 2, 3), 3, 3.0),
+        ((2, 2, 3), 6, 4.0), ((3, 3, 3), 4, 2.0)]
+
+
+def _f(elements, p, side, seed):
+    import paper_2111_06767_amd as dg
+    modes = W.fourier_modes(seed, (0, 0, 0), (side, side, side))
+    xyz = dg.points((0, 0, 0), (side,) * 3, elements, p)
+    return W.fourier_source(modes, *xyz)
+
+
+def _alone(elements, p, side, f, **opts):
+    import torch
+    import paper_2111_06767_amd as dg
+    prob = dg.Problem((0, 0, 0), (side,) * 3, elements, p, **opts)
+    b = prob.apply_mass(to_gpu(f))
+    u, st = prob.solve(b, torch.zeros_like(b))
+    return to_np(u), st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mix_equals_alone(precision):
+    import paper_2111_06767_amd as dg
+    announce(f"serving mix vs alone {precision}")
+    srv = dg.Server(hbm_budget_bytes=32e9, max_active=4, precision=precision, max_iter=60)
+    ids = {}
+    for i, (el, p, side) in enumerate(REQS):
+        f = _f(el, p, side, 1000 + i)
+        ids[srv.submit((0, 0, 0), (side,) * 3, el, p, f)] = (el, p, side, f)
+    active_seen = 0
+    while True:
+        a, q = srv.step()
+        active_seen = max(active_seen, a)
+        if a == 0 and q == 0:
+            break
+    assert active_seen > 1  # requests really overlapped
+    for rid in srv.finished():
+        u, st, times = srv.fetch(rid)
+        el, p, side, f = ids[rid]
+        ua, sta = _alone(el, p, side, f, precision=precision, max_iter=60)
+        assert st["converged"] and st["rel_residual"] <= 1e-10
+        assert st["iterations"] == sta["iterations"]
+        assert np.array_equal(u, ua), (rid, np.abs(u - ua).max())
+        assert times[0] <= times[1] <= times[2]
+
+
+def test_admission_by_budget_and_rejection():
+    import paper_2111_06767_amd as dg
+    announce("serving admission")
+    # budget for about one 2x2x2 p=4 request at a time
+    one = 2 * 2 * 2 * 125 * 8 * (2 * 40 + 1 + 2 + 4 + 16)
+    srv = dg.Server(hbm_budget_bytes=1.5 * one, max_active=8, max_iter=40)
+    for i in range(3):
+        srv.submit((0, 0, 0), (1, 1, 1), (2, 2, 2), 4, _f((2, 2, 2), 4, 1.0, 2000 + i))
+    big = srv.submit((0, 0, 0), (1, 1, 1), (4, 4, 4), 4, _f((4, 4, 4), 4, 1.0, 2100))
+    while True:
+        a, q = srv.step()
+        assert a <= 1
+        if a == 0 and q == 0:
+            break
+    done = srv.finished()
+    assert len(done) == 4
+    for rid in done:
+        if rid == big:
+            with pytest.raises(dg.DgsError) as ei:
+                srv.fetch(rid)
+            assert ei.value.code == dg.DGS_ERR_OOM
+        else:
+            u, st, _ = srv.fetch(rid)
+            assert st["converged"]
+
+
+def test_served_result_solves_oracle_equations():
+    import paper_2111_06767_amd as dg
+    announce("serving vs oracle residual")
+    el, p, side = (3, 2, 2), 4, 2.0
+    f = _f(el, p, side, 3000)
+    srv = dg.Server(max_active=2)
+    rid = srv.submit((0, 0, 0), (side,) * 3, el, p, f)
+    while srv.step() != (0, 0):
+        pass
+    u, st, _ = srv.fetch(rid)
+    m = omesh.BoxMesh((0, 0, 0), (side,) * 3, el, p)
+    b = oop.apply_mass(m, f.reshape(m.E, m.N, m.N, m.N)).reshape(-1)
+    r = b - oop.apply_operator(m, u.reshape(m.E, m.N, m.N, m.N), 1.5).reshape(-1)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
