@@ -95,6 +95,97 @@ def time_apply(dg, elements, p, reps=100, warm=10):
                 algorithmic_bytes=16 * n, achieved_gbs=16 * n / (ms * 1e-3) / 1e9)
 
 
+def time_c5(dg, steps=3):
+    """The 16^3, p = 7 share (2.1 M DOFs, 4 levels): FP64 and mixed solves."""
+    import torch
+    import workloads as W
+    out = {}
+    for prec in ("mixed", "fp64"):
+        prob = dg.Problem((0, 0, 0), (1, 1, 1), (16, 16, 16), 7, penalty=1.5, mg_levels=4,
+                          precision=prec)
+        xyz = prob.node_coordinates()
+        modes = W.fourier_modes(W.SEED_C5)
+        f = torch.as_tensor(W.fourier_source(modes, *(xyz[d].cpu().numpy() for d in range(3)))).cuda()
+        b = prob.apply_mass(f)
+        u, st, times, _ = time_solves(prob, b, steps, 1)
+        out[prec] = dict(ms_p50=round(1e3 * _pct(times, 50), 3), iterations=st["iterations"],
+                         rel_residual=st["rel_residual"], setup_s=round(st["t_setup_s"], 3),
+                         u=u.cpu().numpy())
+        prob.close()
+    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["ms_p50"] / out["mixed"]["ms_p50"], 3)
+    out["mixed_vs_fp64_solution_rel_diff"] = float(
+        np.linalg.norm(out["mixed"]["u"] - out["fp64"]["u"]) / np.linalg.norm(out["fp64"]["u"]))
+    for prec in ("mixed", "fp64"):
+        del out[prec]["u"]
+    return out
+
+
+def run_serving(dg, n_requests=256, max_active=16, precision="mixed"):
+    """Poisson-process stream of solves (grids {2..6}^3, p in 3..8, cube sides
+    1..4, random-Fourier sources): a closed-loop pass measures the saturation
+    throughput, then requests arrive at 0.8 of it and p50/p99 latency and
+    throughput are recorded."""
+    import workloads as W
+    reqs = W.request_stream(n_requests, rate=1.0)
+    data = []
+    for r in reqs:
+        side = r.side
+        xyz = dg.points((0, 0, 0), (side,) * 3, r.elements, r.p)
+        f = W.fourier_source(W.fourier_modes(r.seed, (0, 0, 0), (side,) * 3), *xyz)
+        data.append((r, f))
+
+    def closed_loop():
+        srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60)
+        t0 = time.perf_counter()
+        for r, f in data:
+            srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)
+        while srv.step() != (0, 0):
+            pass
+        dt = time.perf_counter() - t0
+        its = []
+        for rid in srv.finished():
+            _, st, _ = srv.fetch(rid)
+            its.append(st["iterations"])
+        srv.close()
+        return n_requests / dt, its
+
+    cold_tput, _ = closed_loop()  # fills the inverse cache
+    warm_tput, its = closed_loop()
+    rate = 0.8 * warm_tput
+    gaps = np.array([r.arrival for r, _ in data]) / rate  # unit-rate arrivals rescaled
+    srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60)
+    t0 = time.perf_counter()
+    nxt = 0
+    ids = {}
+    peak_active = 0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < n_requests and gaps[nxt] <= now:
+            r, f = data[nxt]
+            ids[srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)] = nxt
+            nxt += 1
+        a, q = srv.step()
+        peak_active = max(peak_active, a)
+        if nxt == n_requests and a == 0 and q == 0:
+            break
+        if a == 0 and q == 0 and nxt < n_requests:
+            time.sleep(max(0.0, min(0.001, gaps[nxt] - (time.perf_counter() - t0))))
+    makespan = time.perf_counter() - t0
+    lat, conv = [], 0
+    for rid in srv.finished():
+        _, st, times = srv.fetch(rid)
+        lat.append(times[2] - times[0])
+        conv += int(st["converged"] and st["rel_residual"] <= 1e-10)
+    srv.close()
+    return dict(requests=n_requests, precision=precision, max_active=max_active,
+                saturation_solves_per_s_cold_cache=round(cold_tput, 2),
+                saturation_solves_per_s=round(warm_tput, 2), arrival_rate_per_s=round(rate, 2),
+                solves_per_s=round(n_requests / makespan, 2),
+                latency_ms_p50=round(1e3 * _pct(lat, 50), 2), latency_ms_p99=round(1e3 * _pct(lat, 99), 2),
+                converged_to_1e10=conv, peak_active=peak_active,
+                iterations_p50=float(np.median(its)), iterations_max=int(max(its)))
+
+
 def cpu_baseline():
     """The oracle solving the same workload once (setup not counted)."""
     import workloads as W
@@ -123,6 +214,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large-apply", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -152,6 +246,9 @@ def main():
                 "frac": round(roof_src["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": f"DG operator apply, {roof_src['elements']} elements p={roof_src['p']}, "
                           f"16 B/DOF algorithmic (read u, write Au)"}
+
+    c5 = None if args.no_c5 else time_c5(dg)
+    serving = None if args.no_serving else run_serving(dg, args.serve_requests)
 
     cpu = None
     u_oracle = None
@@ -186,6 +283,8 @@ def main():
         "rms_error_vs_exact": {"mixed": mixed["err_exact"], "fp64": fp64["err_exact"]},
         "setup_s": {"mixed": round(mixed["setup_s"], 3), "fp64": round(fp64["setup_s"], 3)},
         "apply": {"c2_shape": apply_c2, "16^3_p7": apply_c5, "40^3_p7": apply_big},
+        "c5_16x16x16_p7": c5,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
