@@ -27,15 +27,68 @@
 namespace dgs {
 namespace {
 
+// y = M x for a centro-antisymmetric M through its even-odd split (half the
+// multiply-adds of the plain product; the constants are wave-uniform).
+template <int N>
+__device__ __forceinline__ void eo_apply(const double (&x)[N], double (&y)[N], const EvenOdd& E) {
+  constexpr int H = N / 2;
+  double ev[H], od[H];
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    ev[m] = x[m] + x[N - 1 - m];
+    od[m] = x[m] - x[N - 1 - m];
+  }
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    double a = 0.0, c = 0.0;
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      a += E.P[i * H + m] * ev[m];
+      c += E.Q[i * H + m] * od[m];
+    }
+    if constexpr (N % 2 == 1) a += E.cf[i] * x[H];
+    y[i] = a + c;
+    y[N - 1 - i] = c - a;
+  }
+  if constexpr (N % 2 == 1) {
+    double c = 0.0;
+#pragma unroll
+    for (int m = 0; m < H; ++m) c += E.rc[m] * od[m];
+    y[H] = c;
+  }
+}
+
+// Neighbour's trace (ue) and normal derivative (ge, along +d) on the shared
+// face from its line x[0..N-1] along d; fi is the neighbour's layer on the face.
+template <int N>
+__device__ __forceinline__ void face_from_line(const double (&x)[N], int side, double rh,
+                                               const DevTables& T, double& ue, double& ge) {
+  double acc = 0.0;
+  if (side) {  // neighbour on the high side: its low face (layer 0)
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc += T.D[m] * x[m];
+    ue = x[0];
+  } else {  // neighbour on the low side: its high face (layer N-1)
+#pragma unroll
+    for (int m = 0; m < N; ++m) acc += T.D[(N - 1) * N + m] * x[m];
+    ue = x[N - 1];
+  }
+  ge = acc * rh;
+}
+
 template <int N, int EPB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(((EPB * N * N + 63) / 64) * 64)
 k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ bvec,
         const double* __restrict__ aux0, const double* __restrict__ aux1,
         const int* __restrict__ nbr, OpParams P, DevTables T, int mode) {
   constexpr int N2 = N * N, N3 = N2 * N;
-  constexpr int PIT = N + 1;          // padded row pitch (bank spread for line reads)
+  constexpr int PIT = N + 1;  // padded row pitch (bank spread for line reads)
   constexpr int S3 = N * N * PIT;
-  __shared__ double sU[EPB][S3], sX[EPB][S3];
+  // sU: the element; sA / sB: its -x / +x neighbours (loaded coalesced, so
+  // the x-lines the flux needs are read from LDS rather than as 64-byte
+  // strided rows from memory); sA / sB are reused for the transposed x and y
+  // contributions in the second phase
+  __shared__ double sU[EPB][S3], sA[EPB][S3], sB[EPB][S3];
   __shared__ double sw[N];
 
   const int tid = threadIdx.x;
@@ -50,197 +103,161 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   const unsigned blk = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
   const long long e = (long long)blk * EPB + slot;
   const bool active = (slot < EPB) && (e < P.E);
-  const double rh0 = P.rh[0], rh1 = P.rh[1], rh2 = P.rh[2];
   const double J = P.J;
   auto L = [](int k, int j, int i) { return (k * N + j) * PIT + i; };
 
-  double uz[N], zlo[N], zhi[N];
+  double uz[N], zlo[N], zhi[N], ylo[N], yhi[N];
   int nb[6];
   if (active) {
     const double* ue = u + e * N3;
 #pragma unroll
+    for (int f = 0; f < 6; ++f) nb[f] = nbr[e * 6 + f];
+    const long long xl0 = nb[0] >= 0 ? (long long)nb[0] : e;
+    const long long xh0 = nb[1] >= 0 ? (long long)nb[1] : e;
+#pragma unroll
     for (int k = 0; k < N; ++k) {
       uz[k] = ue[k * N2 + t];
       sU[slot][L(k, b, a)] = uz[k];
+      sA[slot][L(k, b, a)] = u[xl0 * N3 + k * N2 + t];
+      sB[slot][L(k, b, a)] = u[xh0 * N3 + k * N2 + t];
     }
-#pragma unroll
-    for (int f = 0; f < 6; ++f) nb[f] = nbr[e * 6 + f];
-    // neighbour z-lines, issued early
+    // every neighbour line this lane needs, issued before the first barrier
+    // (a missing neighbour reads the element itself; its result is replaced by
+    // the Dirichlet ghost state)
+    const long long yl = nb[2] >= 0 ? (long long)nb[2] : e;
+    const long long yh = nb[3] >= 0 ? (long long)nb[3] : e;
+    const long long zl = nb[4] >= 0 ? (long long)nb[4] : e;
+    const long long zh = nb[5] >= 0 ? (long long)nb[5] : e;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      zlo[m] = nb[4] >= 0 ? u[(long long)nb[4] * N3 + m * N2 + t] : 0.0;
-      zhi[m] = nb[5] >= 0 ? u[(long long)nb[5] * N3 + m * N2 + t] : 0.0;
+      ylo[m] = u[yl * N3 + b * N2 + m * N + a];
+      yhi[m] = u[yh * N3 + b * N2 + m * N + a];
+      zlo[m] = u[zl * N3 + m * N2 + t];
+      zhi[m] = u[zh * N3 + m * N2 + t];
     }
   }
   __syncthreads();
 
+  // forward phase: q_d = M (grad_d u + lift) on every line, flux at line ends
+  double qx[N], qy[N], qz[N];
+  double fx[2], fy[2], fz[2];
   if (active) {
     const double wa = sw[a], wb = sw[b];
-    // ---------------- x role: line (j, k) = (a, b) ----------------
+    const double jwab = J * wa * wb;
+    // ---- x role: line (j, k) = (a, b) ----
     {
       double line[N], g[N];
 #pragma unroll
       for (int m = 0; m < N; ++m) line[m] = sU[slot][L(b, a, m)];
+      eo_apply<N>(line, g, T.fwd);
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) acc += T.D[i * N + m] * line[m];
-        g[i] = acc * rh0;
-      }
-      const double sig = P.sig[0];
-      const double wf = J * rh0 * wa * wb;
-      const double lf = P.lf[0];
-      double flux[2];
+      for (int m = 0; m < N; ++m) g[m] *= P.rh[0];
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const int ie = side ? N - 1 : 0;
-        const int fi = side ? 0 : N - 1;
         const double sg = side ? 1.0 : -1.0;
-        const int nbr_e = nb[side];
+        // branch-free: a missing neighbour reads the element itself and the
+        // result is replaced by the Dirichlet ghost state
+        const bool has = nb[side] >= 0;
         const double ui = line[ie], gi = g[ie];
         double ue, ge;
-        if (nbr_e >= 0) {
-          const double* ub = u + (long long)nbr_e * N3 + b * N2 + a * N;
-          double acc = 0.0, v = 0.0;
+        double xn[N];
 #pragma unroll
-          for (int m = 0; m < N; ++m) {
-            const double x = ub[m];
-            acc += T.D[fi * N + m] * x;
-            if (m == fi) v = x;
-          }
-          ue = v;
-          ge = acc * rh0;
-        } else {
-          ue = -ui;
-          ge = gi;
-        }
-        flux[side] = wf * (0.5 * sg * (gi + ge) - sig * (ui - ue));
-        g[ie] += lf * sg * (ue - ui);
+        for (int m = 0; m < N; ++m) xn[m] = side ? sB[slot][L(b, a, m)] : sA[slot][L(b, a, m)];
+        face_from_line<N>(xn, side, P.rh[0], T, ue, ge);
+        ue = has ? ue : -ui;
+        ge = has ? ge : gi;
+        fx[side] = jwab * P.rh[0] * (0.5 * sg * (gi + ge) - P.sig[0] * (ui - ue));
+        g[ie] += P.lf[0] * sg * (ue - ui);
       }
-      const double jw = J * wa * wb;
 #pragma unroll
-      for (int m = 0; m < N; ++m) g[m] *= jw * sw[m];
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) acc += T.D[m * N + i] * g[m];
-        double c = acc * rh0;
-        if (i == 0) c -= flux[0];
-        if (i == N - 1) c -= flux[1];
-        sX[slot][L(b, a, i)] = c;
-      }
+      for (int m = 0; m < N; ++m) qx[m] = jwab * T.w[m] * g[m];
     }
-  }
-  __syncthreads();  // x-role partial sums complete before the y role adds to them
-  if (active) {
-    const double wa = sw[a], wb = sw[b];
-    // ---------------- y role: line (i, k) = (a, b) ----------------
+    // ---- y role: line (i, k) = (a, b) ----
     {
       double line[N], g[N];
 #pragma unroll
       for (int m = 0; m < N; ++m) line[m] = sU[slot][L(b, m, a)];
+      eo_apply<N>(line, g, T.fwd);
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) acc += T.D[j * N + m] * line[m];
-        g[j] = acc * rh1;
-      }
-      const double sig = P.sig[1];
-      const double wf = J * rh1 * wa * wb;
-      const double lf = P.lf[1];
-      double flux[2];
+      for (int m = 0; m < N; ++m) g[m] *= P.rh[1];
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const int je = side ? N - 1 : 0;
-        const int fi = side ? 0 : N - 1;
         const double sg = side ? 1.0 : -1.0;
-        const int nbr_e = nb[2 + side];
+        const bool has = nb[2 + side] >= 0;
         const double ui = line[je], gi = g[je];
         double ue, ge;
-        if (nbr_e >= 0) {
-          const double* ub = u + (long long)nbr_e * N3 + b * N2 + a;
-          double acc = 0.0, v = 0.0;
-#pragma unroll
-          for (int m = 0; m < N; ++m) {
-            const double x = ub[m * N];
-            acc += T.D[fi * N + m] * x;
-            if (m == fi) v = x;
-          }
-          ue = v;
-          ge = acc * rh1;
-        } else {
-          ue = -ui;
-          ge = gi;
-        }
-        flux[side] = wf * (0.5 * sg * (gi + ge) - sig * (ui - ue));
-        g[je] += lf * sg * (ue - ui);
+        if (side)
+          face_from_line<N>(yhi, 1, P.rh[1], T, ue, ge);
+        else
+          face_from_line<N>(ylo, 0, P.rh[1], T, ue, ge);
+        ue = has ? ue : -ui;
+        ge = has ? ge : gi;
+        fy[side] = jwab * P.rh[1] * (0.5 * sg * (gi + ge) - P.sig[1] * (ui - ue));
+        g[je] += P.lf[1] * sg * (ue - ui);
       }
-      const double jw = J * wa * wb;
 #pragma unroll
-      for (int m = 0; m < N; ++m) g[m] *= jw * sw[m];
+      for (int m = 0; m < N; ++m) qy[m] = jwab * T.w[m] * g[m];
+    }
+    // ---- z role: line (i, j) = (a, b), in registers ----
+    {
+      double g[N];
+      eo_apply<N>(uz, g, T.fwd);
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        double acc = 0.0;
+      for (int m = 0; m < N; ++m) g[m] *= P.rh[2];
 #pragma unroll
-        for (int m = 0; m < N; ++m) acc += T.D[m * N + j] * g[m];
-        double c = acc * rh1;
-        if (j == 0) c -= flux[0];
-        if (j == N - 1) c -= flux[1];
-        sX[slot][L(b, j, a)] += c;
+      for (int side = 0; side < 2; ++side) {
+        const int ke = side ? N - 1 : 0;
+        const double sg = side ? 1.0 : -1.0;
+        const double ui = uz[ke], gi = g[ke];
+        const bool has = nb[4 + side] >= 0;
+        double ue, ge;
+        if (side)
+          face_from_line<N>(zhi, 1, P.rh[2], T, ue, ge);
+        else
+          face_from_line<N>(zlo, 0, P.rh[2], T, ue, ge);
+        ue = has ? ue : -ui;
+        ge = has ? ge : gi;
+        fz[side] = jwab * P.rh[2] * (0.5 * sg * (gi + ge) - P.sig[2] * (ui - ue));
+        g[ke] += P.lf[2] * sg * (ue - ui);
       }
+#pragma unroll
+      for (int m = 0; m < N; ++m) qz[m] = jwab * T.w[m] * g[m];
+    }
+  }
+  __syncthreads();  // every forward read of sA / sB is done: they are reused below
+
+  // transpose phase: sum_d D_d^T q_d - flux terms, x and y parts through LDS
+  if (active) {
+    double c[N];
+    eo_apply<N>(qx, c, T.bwd);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double v = c[i] * P.rh[0];
+      if (i == 0) v -= fx[0];
+      if (i == N - 1) v -= fx[1];
+      sA[slot][L(b, a, i)] = v;
+    }
+    eo_apply<N>(qy, c, T.bwd);
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double v = c[j] * P.rh[1];
+      if (j == 0) v -= fy[0];
+      if (j == N - 1) v -= fy[1];
+      sB[slot][L(b, j, a)] = v;
     }
   }
   __syncthreads();
-
   if (active) {
-    const double wa = sw[a], wb = sw[b];
-    // ---------------- z role: line (i, j) = (a, b), in registers ----------------
-    double g[N];
+    double c[N];
+    eo_apply<N>(qz, c, T.bwd);
+    const double jwab = J * sw[a] * sw[b];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) acc += T.D[k * N + m] * uz[m];
-      g[k] = acc * rh2;
-    }
-    const double sig = P.sig[2];
-    const double wf = J * rh2 * wa * wb;
-    const double lf = P.lf[2];
-    double flux[2];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int ke = side ? N - 1 : 0;
-      const int fi = side ? 0 : N - 1;
-      const double sg = side ? 1.0 : -1.0;
-      const double ui = uz[ke], gi = g[ke];
-      double ue, ge;
-      if (nb[4 + side] >= 0) {
-        double acc = 0.0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) acc += T.D[fi * N + m] * (side ? zhi[m] : zlo[m]);
-        ue = side ? zhi[fi] : zlo[fi];
-        ge = acc * rh2;
-      } else {
-        ue = -ui;
-        ge = gi;
-      }
-      flux[side] = wf * (0.5 * sg * (gi + ge) - sig * (ui - ue));
-      g[ke] += lf * sg * (ue - ui);
-    }
-    const double jw = J * wa * wb;
-#pragma unroll
-    for (int m = 0; m < N; ++m) g[m] *= jw * sw[m];
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m < N; ++m) acc += T.D[m * N + k] * g[m];
-      double r = acc * rh2 + sX[slot][L(k, b, a)];
-      if (k == 0) r -= flux[0];
-      if (k == N - 1) r -= flux[1];
+      double r = c[k] * P.rh[2] + sA[slot][L(k, b, a)] + sB[slot][L(k, b, a)];
+      if (k == 0) r -= fz[0];
+      if (k == N - 1) r -= fz[1];
       const long long gi = e * N3 + k * N2 + t;
       switch (mode) {
         case kApply:
@@ -258,7 +275,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
           const double tt = aux0[gi] * (1.0 + uz[k]) + 1.0;
           const double t2 = tt * tt, t4 = t2 * t2;
           const double S = -aux1[gi] / (t4 * t2 * tt);
-          r += jw * sw[k] * S - bvec[gi];
+          r += jwab * T.w[k] * S - bvec[gi];
           break;
         }
         default:

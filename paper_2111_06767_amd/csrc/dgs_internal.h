@@ -21,6 +21,20 @@ struct HostTables {
 };
 HostTables make_tables(int N);
 
+// Even-odd split of a centro-antisymmetric N x N matrix M (M[N-1-i][N-1-j] =
+// -M[i][j], true of the LGL derivative and its transpose): with H = N/2,
+// e_m = x_m + x_{N-1-m}, o_m = x_m - x_{N-1-m},
+//   a_i = sum_m P[i][m] e_m (+ cf[i] x_c for odd N), c_i = sum_m Q[i][m] o_m,
+//   (M x)_i = a_i + c_i, (M x)_{N-1-i} = c_i - a_i, (M x)_c = sum_m rc[m] o_m,
+// where P = (M[i][m] + M[i][N-1-m]) / 2, Q = (M[i][m] - M[i][N-1-m]) / 2,
+// cf[i] = M[i][c], rc[m] = M[c][m] and c = H is the middle index of odd N.
+struct EvenOdd {
+  double P[(kMaxN / 2) * (kMaxN / 2)];
+  double Q[(kMaxN / 2) * (kMaxN / 2)];
+  double cf[kMaxN / 2];
+  double rc[kMaxN / 2];
+};
+
 // Kernel-argument copy of the tables (fixed size so one struct serves every N).
 struct DevTables {
   double xi[kMaxN];
@@ -28,6 +42,8 @@ struct DevTables {
   double D[kMaxN * kMaxN];
   double Plo[kMaxN * kMaxN];
   double Phi[kMaxN * kMaxN];
+  EvenOdd fwd;  // D
+  EvenOdd bwd;  // D^T
 };
 DevTables to_dev(const HostTables& t);
 

@@ -73,6 +73,15 @@ HostTables make_tables(int N) {
       if (i != j) t.D[i * N + j] = Pn[i] / (Pn[j] * (t.xi[i] - t.xi[j]));
   t.D[0] = -N * (N - 1.0) / 4.0;
   t.D[(N - 1) * N + N - 1] = N * (N - 1.0) / 4.0;
+  // the LGL points are symmetric, so D[N-1-i][N-1-j] = -D[i][j]; impose it on
+  // the rounded values so the even-odd evaluation is exact to rounding
+  {
+    std::vector<double> Ds(N * N);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j)
+        Ds[i * N + j] = 0.5 * (t.D[i * N + j] - t.D[(N - 1 - i) * N + (N - 1 - j)]);
+    t.D = Ds;
+  }
 
   // barycentric weights
   std::vector<double> lam(N, 1.0);
@@ -108,10 +117,28 @@ void set_derived(OpParams& P, int N, double w_end) {
   P.J = P.h[0] * P.h[1] * P.h[2] * 0.125;
 }
 
+namespace {
+void even_odd(const std::vector<double>& M, int N, bool transpose, EvenOdd& eo) {
+  auto at = [&](int i, int j) { return transpose ? M[j * N + i] : M[i * N + j]; };
+  const int H = N / 2;
+  for (int i = 0; i < H; ++i)
+    for (int m = 0; m < H; ++m) {
+      eo.P[i * H + m] = 0.5 * (at(i, m) + at(i, N - 1 - m));
+      eo.Q[i * H + m] = 0.5 * (at(i, m) - at(i, N - 1 - m));
+    }
+  if (N % 2 == 1) {
+    for (int i = 0; i < H; ++i) eo.cf[i] = at(i, H);
+    for (int m = 0; m < H; ++m) eo.rc[m] = at(H, m);
+  }
+}
+}  // namespace
+
 DevTables to_dev(const HostTables& t) {
   DevTables d;
   std::memset(&d, 0, sizeof(d));
   const int N = t.N;
+  even_odd(t.D, N, false, d.fwd);
+  even_odd(t.D, N, true, d.bwd);
   for (int i = 0; i < N; ++i) {
     d.xi[i] = t.xi[i];
     d.w[i] = t.w[i];
