@@ -80,7 +80,8 @@ template <int N, int EPB>
 __global__ void __launch_bounds__(((EPB * N * N + 63) / 64) * 64)
 k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ bvec,
         const double* __restrict__ aux0, const double* __restrict__ aux1,
-        const int* __restrict__ nbr, OpParams P, DevTables T, int mode) {
+        const int* __restrict__ nbr, OpParams P, DevTables T, int mode,
+        const int* __restrict__ order) {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int PIT = N + 1;  // padded row pitch (bank spread for line reads)
   constexpr int S3 = N * N * PIT;
@@ -101,8 +102,9 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   // share that XCD's L2).
   const unsigned G = gridDim.x, per = G / 8u;
   const unsigned blk = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
-  const long long e = (long long)blk * EPB + slot;
-  const bool active = (slot < EPB) && (e < P.E);
+  const long long pos = (long long)blk * EPB + slot;
+  const bool active = (slot < EPB) && (pos < P.E);
+  const long long e = (active && order) ? (long long)order[pos] : pos;
   const double J = P.J;
   auto L = [](int k, int j, int i) { return (k * N + j) * PIT + i; };
 
@@ -289,24 +291,24 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
 template <int N, int EPB>
 hipError_t launch_apply_t(int mode, const double* u, double* out, const double* b,
                           const double* aux0, const double* aux1, const int* nbr,
-                          const OpParams& P, const DevTables& T, hipStream_t s) {
+                          const OpParams& P, const DevTables& T, hipStream_t s, const int* order) {
   if (P.E <= 0) return hipSuccess;
   const int threads = ((EPB * N * N + 63) / 64) * 64;
   const long long need = ((long long)P.E + EPB - 1) / EPB;
   const long long blocks = ((need + 7) / 8) * 8;  // whole rounds over the 8 XCDs
   hipLaunchKernelGGL((k_apply<N, EPB>), dim3((unsigned)blocks), dim3(threads), 0, s, u, out, b,
-                     aux0, aux1, nbr, P, T, mode);
+                     aux0, aux1, nbr, P, T, mode, order);
   return hipGetLastError();
 }
 
 template <int N>
 hipError_t launch_apply_n(int epb, int mode, const double* u, double* out, const double* b,
                           const double* aux0, const double* aux1, const int* nbr,
-                          const OpParams& P, const DevTables& T, hipStream_t s) {
+                          const OpParams& P, const DevTables& T, hipStream_t s, const int* order) {
   constexpr int def = (N == 2) ? 64 : (256 / (N * N));  // >= 3 for every N <= 9
-  if (epb == 1) return launch_apply_t<N, 1>(mode, u, out, b, aux0, aux1, nbr, P, T, s);
-  if (epb == 2) return launch_apply_t<N, 2>(mode, u, out, b, aux0, aux1, nbr, P, T, s);
-  return launch_apply_t<N, def>(mode, u, out, b, aux0, aux1, nbr, P, T, s);
+  if (epb == 1) return launch_apply_t<N, 1>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+  if (epb == 2) return launch_apply_t<N, 2>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+  return launch_apply_t<N, def>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
 }
 
 // b = M f, M = J w_i w_j w_k
@@ -340,16 +342,17 @@ __global__ void k_coords(double* __restrict__ xyz, long long total, int N, int n
 
 hipError_t launch_apply(int N, int mode, const double* u, double* out, const double* b,
                         const double* aux0, const double* aux1, const int* nbr, const OpParams& P,
-                        const DevTables& T, const ApplyConfig& cfg, hipStream_t s) {
+                        const DevTables& T, const ApplyConfig& cfg, hipStream_t s,
+                        const int* order) {
   switch (N) {
-    case 2: return launch_apply_n<2>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s);
-    case 3: return launch_apply_n<3>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s);
-    case 4: return launch_apply_n<4>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s);
-    case 5: return launch_apply_n<5>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s);
-    case 6: return launch_apply_n<6>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s);
-    case 7: return launch_apply_n<7>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s);
-    case 8: return launch_apply_n<8>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s);
-    case 9: return launch_apply_n<9>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s);
+    case 2: return launch_apply_n<2>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+    case 3: return launch_apply_n<3>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+    case 4: return launch_apply_n<4>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+    case 5: return launch_apply_n<5>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+    case 6: return launch_apply_n<6>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+    case 7: return launch_apply_n<7>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+    case 8: return launch_apply_n<8>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+    case 9: return launch_apply_n<9>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
     default: return hipErrorInvalidValue;
   }
 }

@@ -107,40 +107,7 @@ __global__ void k_puncture_diag(const double* __restrict__ alpha, const double* 
   d[g] = J * T.w[i] * T.w[j] * T.w[k] * 7.0 * alpha[g] * beta[g] / (t4 * t4);
 }
 
-// ---- set-up: batched Gauss-Jordan inversion (SPD, no pivoting) -------------
-__global__ void k_gj_save(const double* __restrict__ A, int n_pad, int batch, int k,
-                          double* __restrict__ colbuf, double* __restrict__ rowbuf) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long tot = (long long)batch * n_pad;
-  if (g >= tot) return;
-  const long long b = g / n_pad;
-  const int t = (int)(g - b * n_pad);
-  const double* M = A + b * (long long)n_pad * n_pad;
-  colbuf[g] = M[(long long)t * n_pad + k];
-  rowbuf[g] = M[(long long)k * n_pad + t];
-}
-
-__global__ void k_gj_update(double* __restrict__ A, int n_pad, int batch, int k,
-                            const double* __restrict__ colbuf, const double* __restrict__ rowbuf) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long nn = (long long)n_pad * n_pad;
-  if (g >= nn * batch) return;
-  const long long b = g / nn;
-  const long long rem = g - b * nn;
-  const int i = (int)(rem / n_pad), j = (int)(rem - (long long)i * n_pad);
-  const double* col = colbuf + b * n_pad;
-  const double* row = rowbuf + b * n_pad;
-  const double p = 1.0 / row[k];
-  double v;
-  if (i == k) {
-    v = (j == k) ? p : row[j] * p;
-  } else {
-    const double f = col[i];
-    v = (j == k) ? -f * p : A[g] - f * row[j] * p;
-  }
-  A[g] = v;
-}
-
+// ---- set-up: unit columns and column gather for the patch assembly ----------
 __global__ void k_unit_columns(double* __restrict__ X, long long stride, const int* __restrict__ idx,
                                int ncols) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -251,16 +218,6 @@ hipError_t launch_puncture_diag(int N, const double* alpha, const double* beta, 
   const double J = h[0] * h[1] * h[2] * 0.125;
   hipLaunchKernelGGL(k_puncture_diag, dim3(nblk(total)), dim3(256), 0, s, alpha, beta, u, d, total,
                      N, J, T);
-  return hipGetLastError();
-}
-
-hipError_t launch_gj_step(double* A, int n_pad, int batch, int k, double* colbuf, double* rowbuf,
-                          hipStream_t s) {
-  const long long tot = (long long)batch * n_pad;
-  hipLaunchKernelGGL(k_gj_save, dim3(nblk(tot)), dim3(256), 0, s, A, n_pad, batch, k, colbuf, rowbuf);
-  const long long all = (long long)batch * n_pad * n_pad;
-  hipLaunchKernelGGL(k_gj_update, dim3(nblk(all)), dim3(256), 0, s, A, n_pad, batch, k, colbuf,
-                     rowbuf);
   return hipGetLastError();
 }
 

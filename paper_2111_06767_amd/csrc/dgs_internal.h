@@ -72,9 +72,12 @@ struct ApplyConfig {
   int epb = 0;  // 0 = default for N
 };
 
+// order (optional, may be NULL): processing order of the elements, a
+// permutation of 0..E-1 that keeps face neighbours close in time.
 hipError_t launch_apply(int N, int mode, const double* u, double* out, const double* b,
                         const double* aux0, const double* aux1, const int* nbr, const OpParams& P,
-                        const DevTables& T, const ApplyConfig& cfg, hipStream_t s);
+                        const DevTables& T, const ApplyConfig& cfg, hipStream_t s,
+                        const int* order = nullptr);
 hipError_t launch_mass(int N, const double* f, double* out, long long E, const double h[3],
                        const DevTables& T, hipStream_t s);
 hipError_t launch_coords(int N, double* xyz, const int n[3], const double lower[3],
@@ -170,10 +173,12 @@ hipError_t launch_puncture_diag(int N, const double* alpha, const double* beta, 
 hipError_t launch_waxpy(double* y, const double* x, double lam, const double* dx, long long n,
                         hipStream_t s);
 
-// Set-up kernels: batched Gauss-Jordan inversion of SPD matrices (padded to
-// n_pad with identity), unit-vector fill and column gather for the patch apply.
-hipError_t launch_gj_step(double* A, int n_pad, int batch, int k, double* colbuf, double* rowbuf,
-                          hipStream_t s);
+// Set-up kernels: unit-vector fill and column gather for the patch apply, the
+// blocked inversion, and the transposed copies of the results.
+// Blocked Gauss-Jordan inversion in place of a batch of n x n SPD matrices,
+// n a multiple of 64; work buffers P (batch*64*64), R and C (batch*64*n each).
+hipError_t launch_block_inverse(double* A, int n, int batch, double* Pbuf, double* Rbuf,
+                                double* Cbuf, hipStream_t s);
 hipError_t launch_unit_columns(double* X, long long copy_stride, const int* idx, int ncols,
                                hipStream_t s);
 hipError_t launch_gather_columns(const double* AX, long long copy_stride, const int* idx, int n,

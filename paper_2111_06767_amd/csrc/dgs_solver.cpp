@@ -162,6 +162,7 @@ struct Level {
   bool f32 = false;
   OpParams op{};
   int* d_nbr = nullptr;
+  int* d_order = nullptr;  // element processing order of the operator kernel
   // Schwarz
   std::vector<ClassLayout> layouts;
   std::vector<ClassInfo> cls;
@@ -257,7 +258,21 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
   }
   L.d_nbr = P->alloc<int>(nbr.size());
   upload(L.d_nbr, nbr, s);
-  HIP_OK(hipStreamSynchronize(s));  // nbr goes out of scope
+  // processing order: columns of 8 x 8 elements in x-y, each swept through z
+  // (x fastest inside a layer), so that every face neighbour of an element is
+  // processed within about one column layer of it and is still in L2
+  std::vector<int> order;
+  order.reserve(L.E);
+  const int T = 8;
+  for (int ty = 0; ty < L.n[1]; ty += T)
+    for (int tx = 0; tx < L.n[0]; tx += T)
+      for (int z = 0; z < L.n[2]; ++z)
+        for (int y = ty; y < std::min(ty + T, L.n[1]); ++y)
+          for (int x = tx; x < std::min(tx + T, L.n[0]); ++x)
+            order.push_back((int)(((long long)z * L.n[1] + y) * L.n[0] + x));
+  L.d_order = P->alloc<int>(order.size());
+  upload(L.d_order, order, s);
+  HIP_OK(hipStreamSynchronize(s));  // nbr and order go out of scope
   const long long nd = L.E * (long long)P->N * P->N * P->N;
   L.d_u = P->alloc<double>(nd);
   L.d_b = P->alloc<double>(nd);
@@ -418,6 +433,7 @@ void build_keys(dgs_problem* P, const std::vector<std::unique_ptr<CacheEntry>>& 
     klay.push_back(make_layout(k->flags, N, k->nov, P->ht.xi));
     n_pad = std::max(n_pad, klay.back().n);
   }
+  n_pad = (n_pad + 63) / 64 * 64;  // the blocked inversion works on 64-wide blocks
   double* d_batch = dalloc<double>((size_t)nk * n_pad * n_pad);
   std::unique_ptr<void, void (*)(void*)> g1(d_batch, [](void* p) { (void)hipFree(p); });
   {
@@ -493,11 +509,13 @@ void build_keys(dgs_problem* P, const std::vector<std::unique_ptr<CacheEntry>>& 
     HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, c.n, 1.0, c.op64,
                                  c.op32, s));
   }
-  double* d_col = dalloc<double>((size_t)nk * n_pad);
-  std::unique_ptr<void, void (*)(void*)> g6(d_col, [](void* p) { (void)hipFree(p); });
-  double* d_row = dalloc<double>((size_t)nk * n_pad);
-  std::unique_ptr<void, void (*)(void*)> g7(d_row, [](void* p) { (void)hipFree(p); });
-  for (int k = 0; k < n_pad; ++k) HIP_OK(launch_gj_step(d_batch, n_pad, nk, k, d_col, d_row, s));
+  double* d_P = dalloc<double>((size_t)nk * 64 * 64);
+  std::unique_ptr<void, void (*)(void*)> g6(d_P, [](void* p) { (void)hipFree(p); });
+  double* d_R = dalloc<double>((size_t)nk * 64 * n_pad);
+  std::unique_ptr<void, void (*)(void*)> g7(d_R, [](void* p) { (void)hipFree(p); });
+  double* d_C = dalloc<double>((size_t)nk * 64 * n_pad);
+  std::unique_ptr<void, void (*)(void*)> g8(d_C, [](void* p) { (void)hipFree(p); });
+  HIP_OK(launch_block_inverse(d_batch, n_pad, nk, d_P, d_R, d_C, s));
   for (int k = 0; k < nk; ++k) {
     CacheEntry& c = *todo[k];
     HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, c.n, 1.0, c.inv64,
@@ -594,11 +612,11 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
     ApplyConfig cfg;
     cfg.epb = c;
     HIP_OK(launch_apply(P->N, kApply, L.d_u, L.d_r, nullptr, nullptr, nullptr, L.d_nbr, L.op, P->dt,
-                        cfg, s));  // warm-up
+                        cfg, s, L.d_order));  // warm-up
     HIP_OK(hipEventRecord(e0, s));
     for (int r = 0; r < reps; ++r)
       HIP_OK(launch_apply(P->N, kApply, L.d_u, L.d_r, nullptr, nullptr, nullptr, L.d_nbr, L.op,
-                          P->dt, cfg, s));
+                          P->dt, cfg, s, L.d_order));
     HIP_OK(hipEventRecord(e1, s));
     HIP_OK(hipEventSynchronize(e1));
     float ms = 0;
@@ -657,7 +675,7 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
     const double* r = b;
     if (!(it == 0 && u_zero)) {
       HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u, L.d_r, b, L.d_diag, nullptr,
-                          L.d_nbr, L.op, P->dt, P->acfg, s));
+                          L.d_nbr, L.op, P->dt, P->acfg, s, L.d_order));
       r = L.d_r;
     }
     HIP_OK(launch_gather(N, L.f32, r, L.d_rs, L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls,
@@ -692,7 +710,7 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s) {
     schwarz_steps(P, l, b[l], u[l], P->opt.pre_smooth, true, s);
     const bool diag = P->diag_active && L.d_diag != nullptr;
     HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u[l], L.d_r, b[l], L.d_diag, nullptr,
-                        L.d_nbr, L.op, P->dt, P->acfg, s));
+                        L.d_nbr, L.op, P->dt, P->acfg, s, L.d_order));
     Level& C = P->levels[l + 1];
     HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s));
   }
@@ -774,14 +792,14 @@ void apply_fine(dgs_problem* P, const double* x, double* y, hipStream_t s) {
   Level& L = P->levels[0];
   const bool diag = P->diag_active && L.d_diag != nullptr;
   HIP_OK(launch_apply(P->N, diag ? kApplyDiag : kApply, x, y, nullptr, L.d_diag, nullptr, L.d_nbr,
-                      L.op, P->dt, P->acfg, s));
+                      L.op, P->dt, P->acfg, s, L.d_order));
 }
 
 void residual_fine(dgs_problem* P, const double* x, const double* b, double* r, hipStream_t s) {
   Level& L = P->levels[0];
   const bool diag = P->diag_active && L.d_diag != nullptr;
   HIP_OK(launch_apply(P->N, diag ? kResidualDiag : kResidual, x, r, b, L.d_diag, nullptr, L.d_nbr,
-                      L.op, P->dt, P->acfg, s));
+                      L.op, P->dt, P->acfg, s, L.d_order));
 }
 
 // Make subsequent smoothing, V-cycles and solves act on A + diag(d): copy d
@@ -1262,7 +1280,7 @@ int dgs_apply_operator(dgs_problem* prob, const double* u, double* Au, void* str
     if (u == Au) return fail(DGS_ERR_INVALID, "u and Au must not overlap");
     Level& L = prob->levels[0];
     HIP_OK(launch_apply(prob->N, kApply, u, Au, nullptr, nullptr, nullptr, L.d_nbr, L.op, prob->dt,
-                        prob->acfg, as_stream(stream)));
+                        prob->acfg, as_stream(stream), L.d_order));
     return DGS_OK;
   });
 }
@@ -1329,7 +1347,7 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
     Level& L0 = P->levels[0];
     auto residual = [&](const double* x, double* out) {  // A x + M S(x) - b
       HIP_OK(launch_apply(P->N, kPuncture, x, out, b, alpha, beta, L0.d_nbr, L0.op, P->dt, P->acfg,
-                          s));
+                          s, L0.d_order));
     };
     auto norm2 = [&](const double* x) { return device_norm2(P, x, n, s); };
     P->diag_active = false;
