@@ -114,7 +114,10 @@ constexpr int kGemmBigM = 64, kGemmSmallM = 16, kGemmN = 128, kGemmSmallCount = 
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,
                                  long long part_stride, const ClassInfo* cls,
                                  const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
-                                 int nsmall, int use_op, hipStream_t s);
+                                 int nsmall, int use_op, hipStream_t s, int variant = 0);
+// Number of K-depth variants of the large-tile GEMM (0: 16 FP64 / 32 FP32,
+// 1: 32 FP64 / 64 FP32); the set-up autotuner picks one per level.
+constexpr int kGemmVariants = 2;
 // out[i] = sum over parts of part_base[p * stride + i]
 hipError_t launch_reduce_parts(bool f32, void* out, const void* parts_base, int parts,
                                long long stride, long long total, hipStream_t s);

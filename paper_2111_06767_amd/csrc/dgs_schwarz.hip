@@ -482,16 +482,22 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,
                                  long long ps, const ClassInfo* cls,
                                  const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
-                                 int nsmall, int use_op, hipStream_t s) {
+                                 int nsmall, int use_op, hipStream_t s, int variant) {
   if (f32) {
-    if (nbig > 0)
+    if (nbig > 0 && variant == 1)
+      hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 64>), dim3(nbig), dim3(256), 0, s,
+                         (const float*)rs, (float*)du, ps, cls, tiles_big, use_op);
+    else if (nbig > 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 32>), dim3(nbig), dim3(256), 0, s,
                          (const float*)rs, (float*)du, ps, cls, tiles_big, use_op);
     if (nsmall > 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), dim3(nsmall), dim3(256), 0, s,
                          (const float*)rs, (float*)du, ps, cls, tiles_small, use_op);
   } else {
-    if (nbig > 0)
+    if (nbig > 0 && variant == 1)
+      hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 32>), dim3(nbig), dim3(256), 0, s,
+                         (const double*)rs, (double*)du, ps, cls, tiles_big, use_op);
+    else if (nbig > 0)
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), dim3(nbig), dim3(256), 0, s,
                          (const double*)rs, (double*)du, ps, cls, tiles_big, use_op);
     if (nsmall > 0)

@@ -175,6 +175,7 @@ struct Level {
   GemmTile* d_tiles_small = nullptr;
   int nbig = 0, nsmall = 0;
   int kparts = 1;  // split-K factor of the class GEMMs
+  int gemm_variant = 0;  // large-tile GEMM variant chosen by the autotuner
   long long rs_total = 0;
   void* d_rs = nullptr;
   void* d_du = nullptr;
@@ -633,6 +634,51 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
   g_tuned_epb[key] = best;
 }
 
+// K-depth of the large-tile class GEMM, timed on every level that has large
+// tiles (with that level's own tiles and buffers); cached per level shape.
+std::map<std::tuple<int, long long, int, int, int>, int> g_tuned_gemm;
+
+void autotune_gemm(dgs_problem* P, hipStream_t s) {
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  for (Level& L : P->levels) {
+    if (L.nbig == 0) continue;
+    const auto key = std::make_tuple(P->N, L.E, (int)L.f32, P->opt.overlap, L.nbig);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mutex);
+      auto it = g_tuned_gemm.find(key);
+      if (it != g_tuned_gemm.end()) {
+        L.gemm_variant = it->second;
+        continue;
+      }
+    }
+    const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+    HIP_OK(hipMemsetAsync(L.d_rs, 0, es * (size_t)L.rs_total, s));
+    float best_ms = 1e30f;
+    for (int v = 0; v < kGemmVariants; ++v) {
+      HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
+                                   nullptr, 0, 0, s, v));  // warm-up
+      HIP_OK(hipEventRecord(e0, s));
+      for (int r = 0; r < 5; ++r)
+        HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big,
+                                     L.nbig, nullptr, 0, 0, s, v));
+      HIP_OK(hipEventRecord(e1, s));
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best_ms) {
+        best_ms = ms;
+        L.gemm_variant = v;
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mutex);
+    g_tuned_gemm[key] = L.gemm_variant;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 // ---------------------------------------------------------------------------
 // Schwarz smoothing and the V-cycle
 // ---------------------------------------------------------------------------
@@ -654,10 +700,10 @@ void subdomain_gmres(dgs_problem* P, Level& L, hipStream_t s) {
     void* Vj = slot(L.d_gV, j);
     void* Zj = slot(L.d_gZ, j);
     HIP_OK(launch_subdomain_gemm(L.f32, Vj, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
-                                 L.d_tiles_small, L.nsmall, 0, s));
+                                 L.d_tiles_small, L.nsmall, 0, s, L.gemm_variant));
     HIP_OK(launch_reduce_parts(L.f32, Zj, L.d_du, L.kparts, st, st, s));
     HIP_OK(launch_subdomain_gemm(L.f32, Zj, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
-                                 L.d_tiles_small, L.nsmall, 1, s));
+                                 L.d_tiles_small, L.nsmall, 1, s, L.gemm_variant));
     HIP_OK(launch_reduce_parts(L.f32, L.d_gW, L.d_du, L.kparts, st, st, s));
     HIP_OK(launch_sub_arnoldi(N, L.f32, j, k, L.d_gW, L.d_gV, Zj, st, L.d_diag, L.d_gH,
                               L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls, L.d_seg_loc, (int)L.E,
@@ -687,8 +733,12 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
       continue;
     }
     HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
-                                 L.d_tiles_small, L.nsmall, 0, s));
-    HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.kparts, L.rs_total, L.d_weights, L.d_elem_class,
+                                 L.d_tiles_small, L.nsmall, 0, s, L.gemm_variant));
+    // sum the split-K partials with one coalesced pass (in place into part 0)
+    // so the scatter's scattered reads touch a single copy
+    if (L.kparts > 1)
+      HIP_OK(launch_reduce_parts(L.f32, L.d_du, L.d_du, L.kparts, L.rs_total, L.rs_total, s));
+    HIP_OK(launch_scatter(N, L.f32, u, L.d_du, 1, L.rs_total, L.d_weights, L.d_elem_class,
                           L.d_elem_row, L.d_nbr, L.d_cls, nov_of(P), L.E, s));
   }
 }
@@ -1234,6 +1284,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     }
     build_inverses(P.get(), s);
     autotune_apply(P.get(), s);
+    autotune_gemm(P.get(), s);
     HIP_OK(hipStreamSynchronize(s));
     P->t_setup = now_s() - t0;
     *out = P.release();
