@@ -138,10 +138,20 @@ hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride
                              const long long* elem_row, const ClassInfo* cls, int E, hipStream_t s);
 // u += sum_S R_S^T (w_S du_S), pulled per point; du is the sum of `parts`
 // split-K partial products spaced part_stride apart.
+// Pull table of the weighted scatter, 7 entries per element: entry 0 is the
+// element's own subdomain, entry 1 + f the subdomain of its face-f neighbour.
+struct PullEntry {
+  long long du;  // entry 0: the element's row in the correction block;
+                 // faces: start of the neighbour's strip toward the element (-1: none)
+  int w;         // matching offset in the weight table
+  int flip;      // entry 0: mirror mask of the element; faces: bits 0 / 1 reverse the
+                 // first / second transverse index (the neighbour is mirrored there)
+};
+
+// u += sum_S R_S^T (w_S du_S), summing `parts` split-K partials (1..4) of du.
 hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
-                          long long part_stride, const double* weights, const int* elem_class,
-                          const long long* elem_row, const int* nbr, const ClassInfo* cls, int nov,
-                          long long E, hipStream_t s);
+                          long long part_stride, const double* weights, const PullEntry* pull,
+                          int nov, long long E, hipStream_t s);
 
 // Multigrid transfer (per-dimension split flags).
 hipError_t launch_restrict(int N, const double* fine, double* coarse, const int nf[3],

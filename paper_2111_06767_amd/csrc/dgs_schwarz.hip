@@ -72,48 +72,47 @@ k_gather_rows(const double* __restrict__ r, T* __restrict__ rs, const int* __res
 
 // Pull-based weighted scatter: every point adds its own subdomain's
 // correction and the overlap corrections of the face neighbours' subdomains.
-template <typename T>
-__device__ __forceinline__ double sum_parts(const T* __restrict__ du, long long idx, int parts,
+// The per-element pull table holds every offset, so each point issues its
+// (at most 7 x PARTS) loads at once: absent or out-of-overlap terms read a
+// valid address and are discarded by a select, not skipped by a branch.
+template <typename T, int PARTS>
+__device__ __forceinline__ double sum_parts(const T* __restrict__ du, long long idx,
                                             long long stride) {
   double v = 0.0;
-  for (int q = 0; q < parts; ++q) v += (double)du[q * stride + idx];
+#pragma unroll
+  for (int q = 0; q < PARTS; ++q) v += (double)du[q * stride + idx];
   return v;
 }
 
-template <typename T>
+template <typename T, int PARTS>
 __global__ void __launch_bounds__(256)
-k_scatter(double* __restrict__ u, const T* __restrict__ du, int parts, long long pstride,
-          const double* __restrict__ weights, const int* __restrict__ elem_class,
-          const long long* __restrict__ elem_row, const int* __restrict__ nbr,
-          const ClassInfo* __restrict__ cls, int N, int nov, long long total) {
+k_scatter(double* __restrict__ u, const T* __restrict__ du, long long pstride,
+          const double* __restrict__ weights, const PullEntry* __restrict__ pull, int N, int nov,
+          long long total) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int N2 = N * N, N3 = N2 * N;
   const long long e = g / N3;
   const int loc = (int)(g - e * N3);
   const int idx[3] = {loc % N, (loc / N) % N, loc / N2};
-  const int cve = elem_class[e];
-  const ClassInfo ce = cls[cve & kGroupMask];
-  const int lc = mirror_loc(loc, cve >> 24, N);
-  double acc = weights[ce.layout_off + lc] * sum_parts(du, elem_row[e] + lc, parts, pstride);
+  const PullEntry* pe = pull + e * 7;
+  const PullEntry own = pe[0];
+  const int lc = mirror_loc(loc, own.flip, N);
+  double acc = weights[own.w + lc] * sum_parts<T, PARTS>(du, own.du + lc, pstride);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
-    const int b = nbr[e * 6 + f];
-    if (b < 0) continue;
+    const PullEntry q = pe[1 + f];
     const int d = f >> 1;
-    const int m = idx[d];
-    const int layer = (f & 1) ? (N - 1 - m) : m;
-    if (layer >= nov) continue;
+    const int layer = (f & 1) ? (N - 1 - idx[d]) : idx[d];
     const int d0 = d == 0 ? 1 : 0, d1 = d == 2 ? 1 : 2;  // transverse dimensions
-    const int cvb = elem_class[b];
-    const int mb = cvb >> 24;
-    const ClassInfo cb = cls[cvb & kGroupMask];
-    const int g = ((mb >> d) & 1) ? f : (f ^ 1);  // b's face toward e, canonical frame
-    const int t0 = ((mb >> d0) & 1) ? N - 1 - idx[d0] : idx[d0];
-    const int t1 = ((mb >> d1) & 1) ? N - 1 - idx[d1] : idx[d1];
-    const int so = cb.strip_off[g];
-    const int k = so + layer * N2 + t1 * N + t0;
-    acc += weights[cb.layout_off + k] * sum_parts(du, elem_row[b] + k, parts, pstride);
+    const int t0 = (q.flip & 1) ? N - 1 - idx[d0] : idx[d0];
+    const int t1 = (q.flip & 2) ? N - 1 - idx[d1] : idx[d1];
+    const bool ok = q.du >= 0 && layer < nov;
+    const int k = ok ? layer * N2 + t1 * N + t0 : lc;
+    const long long bd = ok ? q.du : own.du;
+    const int bw = ok ? q.w : own.w;
+    const double v = weights[bw + k] * sum_parts<T, PARTS>(du, bd + k, pstride);
+    acc += ok ? v : 0.0;
   }
   u[g] += acc;
 }
@@ -507,20 +506,35 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,
   return hipGetLastError();
 }
 
+template <typename T, int PARTS>
+void scatter_launch(unsigned blocks, hipStream_t s, double* u, const void* du, long long pstride,
+                    const double* weights, const PullEntry* pull, int N, int nov, long long total) {
+  hipLaunchKernelGGL((k_scatter<T, PARTS>), dim3(blocks), dim3(256), 0, s, u, (const T*)du, pstride,
+                     weights, pull, N, nov, total);
+}
+
+template <typename T>
+hipError_t scatter_parts(int parts, unsigned blocks, hipStream_t s, double* u, const void* du,
+                         long long pstride, const double* weights, const PullEntry* pull, int N,
+                         int nov, long long total) {
+  switch (parts) {
+    case 1: scatter_launch<T, 1>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
+    case 2: scatter_launch<T, 2>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
+    case 3: scatter_launch<T, 3>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
+    case 4: scatter_launch<T, 4>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
-                          long long pstride, const double* weights, const int* elem_class,
-                          const long long* elem_row, const int* nbr, const ClassInfo* cls, int nov,
+                          long long pstride, const double* weights, const PullEntry* pull, int nov,
                           long long E, hipStream_t s) {
   const long long total = E * N * N * N;
   if (total <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((total + 255) / 256);
-  if (f32)
-    hipLaunchKernelGGL(k_scatter<float>, dim3(blocks), dim3(256), 0, s, u, (const float*)du, parts,
-                       pstride, weights, elem_class, elem_row, nbr, cls, N, nov, total);
-  else
-    hipLaunchKernelGGL(k_scatter<double>, dim3(blocks), dim3(256), 0, s, u, (const double*)du,
-                       parts, pstride, weights, elem_class, elem_row, nbr, cls, N, nov, total);
-  return hipGetLastError();
+  return f32 ? scatter_parts<float>(parts, blocks, s, u, du, pstride, weights, pull, N, nov, total)
+             : scatter_parts<double>(parts, blocks, s, u, du, pstride, weights, pull, N, nov, total);
 }
 
 }  // namespace dgs

@@ -171,6 +171,7 @@ struct Level {
   double* d_weights = nullptr;
   int* d_elem_class = nullptr;
   long long* d_elem_row = nullptr;
+  PullEntry* d_pull = nullptr;  // scatter pull table, 7 entries per element
   GemmTile* d_tiles_big = nullptr;
   GemmTile* d_tiles_small = nullptr;
   int nbig = 0, nsmall = 0;
@@ -235,15 +236,9 @@ namespace {
 
 int nov_of(const dgs_problem* P) { return std::max(1, std::min(P->opt.overlap, P->N - 1)); }
 
-void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
-  L.E = (long long)L.n[0] * L.n[1] * L.n[2];
-  for (int d = 0; d < 3; ++d) L.h[d] = (P->dom.upper[d] - P->dom.lower[d]) / L.n[d];
-  L.op.h[0] = L.h[0];
-  L.op.h[1] = L.h[1];
-  L.op.h[2] = L.h[2];
-  L.op.penalty = P->penalty;
-  L.op.E = (int)L.E;
-  set_derived(L.op, P->N, P->ht.w[0]);
+// Face neighbours of every element (-1 at the boundary), faces ordered
+// -x, +x, -y, +y, -z, +z.
+std::vector<int> host_neighbors(const Level& L) {
   std::vector<int> nbr(L.E * 6);
   for (long long e = 0; e < L.E; ++e) {
     const int c[3] = {(int)(e % L.n[0]), (int)((e / L.n[0]) % L.n[1]),
@@ -257,6 +252,19 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
                            : (int)(((long long)cc[2] * L.n[1] + cc[1]) * L.n[0] + cc[0]);
     }
   }
+  return nbr;
+}
+
+void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
+  L.E = (long long)L.n[0] * L.n[1] * L.n[2];
+  for (int d = 0; d < 3; ++d) L.h[d] = (P->dom.upper[d] - P->dom.lower[d]) / L.n[d];
+  L.op.h[0] = L.h[0];
+  L.op.h[1] = L.h[1];
+  L.op.h[2] = L.h[2];
+  L.op.penalty = P->penalty;
+  L.op.E = (int)L.E;
+  set_derived(L.op, P->N, P->ht.w[0]);
+  const std::vector<int> nbr = host_neighbors(L);
   L.d_nbr = P->alloc<int>(nbr.size());
   upload(L.d_nbr, nbr, s);
   // processing order: columns of 8 x 8 elements in x-y, each swept through z
@@ -374,6 +382,30 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   upload(L.d_elem_class, elem_code, s);
   L.d_elem_row = P->alloc<long long>(L.E);
   upload(L.d_elem_row, elem_row, s);
+  // scatter pull table: the element's own row, and for every face neighbour b
+  // the start of b's strip toward the element (in b's canonical frame)
+  const std::vector<int> nbr = host_neighbors(L);
+  std::vector<PullEntry> pull(L.E * 7);
+  for (long long e = 0; e < L.E; ++e) {
+    const ClassInfo& ce = L.cls[elem_class[e]];
+    pull[e * 7] = PullEntry{elem_row[e], ce.layout_off, elem_mask[e]};
+    for (int f = 0; f < 6; ++f) {
+      const int b = nbr[e * 6 + f];
+      if (b < 0) {
+        pull[e * 7 + 1 + f] = PullEntry{-1, 0, 0};
+        continue;
+      }
+      const int d = f >> 1, d0 = d == 0 ? 1 : 0, d1 = d == 2 ? 1 : 2;
+      const int mb = elem_mask[b];
+      const int g = ((mb >> d) & 1) ? f : (f ^ 1);  // b's face toward e, canonical frame
+      const ClassInfo& cb = L.cls[elem_class[b]];
+      if (cb.strip_off[g] < 0) throw DgsError(DGS_ERR_HIP, "subdomain strip missing");
+      pull[e * 7 + 1 + f] = PullEntry{elem_row[b] + cb.strip_off[g], cb.layout_off + cb.strip_off[g],
+                                      ((mb >> d0) & 1) | (((mb >> d1) & 1) << 1)};
+    }
+  }
+  L.d_pull = P->alloc<PullEntry>(pull.size());
+  upload(L.d_pull, pull, s);
   L.nbig = (int)big.size();
   L.nsmall = (int)small.size();
   L.d_tiles_big = P->alloc<GemmTile>(big.size());
@@ -728,18 +760,15 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
                          L.d_seg_loc, (int)L.E, s));
     if (diag && P->opt.subdomain_iters > 0) {
       subdomain_gmres(P, L, s);
-      HIP_OK(launch_scatter(N, L.f32, u, L.d_du, 1, L.rs_total, L.d_weights, L.d_elem_class,
-                            L.d_elem_row, L.d_nbr, L.d_cls, nov_of(P), L.E, s));
+      HIP_OK(launch_scatter(N, L.f32, u, L.d_du, 1, L.rs_total, L.d_weights, L.d_pull, nov_of(P),
+                            L.E, s));
       continue;
     }
     HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
                                  L.d_tiles_small, L.nsmall, 0, s, L.gemm_variant));
-    // sum the split-K partials with one coalesced pass (in place into part 0)
-    // so the scatter's scattered reads touch a single copy
-    if (L.kparts > 1)
-      HIP_OK(launch_reduce_parts(L.f32, L.d_du, L.d_du, L.kparts, L.rs_total, L.rs_total, s));
-    HIP_OK(launch_scatter(N, L.f32, u, L.d_du, 1, L.rs_total, L.d_weights, L.d_elem_class,
-                          L.d_elem_row, L.d_nbr, L.d_cls, nov_of(P), L.E, s));
+    // the scatter sums the split-K partials itself
+    HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.kparts, L.rs_total, L.d_weights, L.d_pull,
+                          nov_of(P), L.E, s));
   }
 }
 
