@@ -30,6 +30,43 @@ sys.path.insert(0, ROOT)
 
 METRIC = "solve time to 1e-10 rel residual & DG apply GDOF/s; mixed vs FP64; p50/p99"
 HBM_PEAK_GBS = 8000.0
+MFMA_FP32_PEAK_TFLOPS = 157.3
+MFMA_FP64_PEAK_TFLOPS = 78.6
+
+# HBM traffic per launch of the two roofline kernels, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs of this script, each scaled by what the same
+# counter reads for the plain copy of COPY_BYTES made below.  A figure is
+# reported only while the sources it was measured on are unchanged.
+MEASURED_TRAFFIC = {
+    "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
+                                   "paper_2111_06767_amd/csrc/dgs_internal.h"],
+                       "sha256": "bfd9dda9e9f60d6c9c680e09915dd34869e963589c47c9af42e5bc5635a88690",
+                       "bytes": 55610341},
+    "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
+                          "paper_2111_06767_amd/csrc/dgs_internal.h"],
+              "sha256": "b9039f01922400995d344d45092b02708edaf5dd16920e447748c608e85ef1cb",
+              "bytes": 635274918},
+}
+
+
+def _sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for rel in paths:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    t = MEASURED_TRAFFIC[kernel]
+    if t["bytes"] is None or _sources_sha256(t["sources"]) != t["sha256"]:
+        return None
+    return t["bytes"]
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _pct(a, q):
@@ -70,8 +107,11 @@ def time_solves(prob, b, steps, warmup):
     return u, stats, times, total
 
 
-def time_apply(dg, elements, p, reps=100, warm=10):
-    """Average apply duration with HIP events on torch's current stream."""
+def time_apply(dg, elements, p, reps=100, warm=10, calibration_copy=False):
+    """Average apply duration with HIP events on torch's current stream (the
+    stream the library launches on).  With calibration_copy, one plain
+    device-to-device copy of the input vector follows the timed applies: the
+    known-size transfer the HBM counters are scaled by."""
     import torch
     import workloads as W
     prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=1)
@@ -87,12 +127,30 @@ def time_apply(dg, elements, p, reps=100, warm=10):
     e1.record(s)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
+    if calibration_copy:
+        out.copy_(u)
+        torch.cuda.synchronize()
     n = prob.ndof
     prob.close()
     del u, out
     torch.cuda.empty_cache()
     return dict(elements=list(elements), p=p, ndof=n, ms_per_apply=ms, gdofs=n / (ms * 1e-3) / 1e9,
                 algorithmic_bytes=16 * n, achieved_gbs=16 * n / (ms * 1e-3) / 1e9)
+
+
+def time_subdomain_gemm(prob, reps=50, warm=5):
+    """Average duration of the fine-level grouped subdomain-solve GEMM (one
+    Schwarz sweep's du_S = s A_S^-1 r_S), HIP events on torch's current stream."""
+    import torch
+    s = torch.cuda.current_stream()
+    prob.subdomain_solves(0, warm)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    flops = prob.subdomain_solves(0, reps)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return dict(flops_per_launch=flops, ms_per_launch=ms, achieved_tflops=flops / (ms * 1e-3) / 1e12)
 
 
 def time_c5(dg, steps=3):
@@ -228,6 +286,7 @@ def main():
 
     res = {}
     for prec in ("mixed", "fp64"):
+        _log(f"8^3 p=6 {prec}: set-up and {args.warmup}+{args.steps} solves")
         prob, b, uex = build_c2(dg, prec)
         u, st, times, total = time_solves(prob, b, args.steps, args.warmup)
         un = u.cpu().numpy()
@@ -237,22 +296,42 @@ def main():
 
     mixed, fp64 = res["mixed"], res["fp64"]
     sol_diff = float(np.linalg.norm(mixed["u"] - fp64["u"]) / np.linalg.norm(fp64["u"]))
+    _log("subdomain GEMM and apply timings")
+    gemm = time_subdomain_gemm(mixed["prob"])
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
     apply_c5 = time_apply(dg, (16, 16, 16), 7)
-    apply_big = None if args.no_large_apply else time_apply(dg, (40, 40, 40), 7, reps=50)
+    apply_big = None if args.no_large_apply else time_apply(dg, (40, 40, 40), 7, reps=50,
+                                                             calibration_copy=True)
+    roofline = {"bound": "mfma", "achieved": round(gemm["achieved_tflops"], 2),
+                "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(gemm["achieved_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic("subdomain_gemm"),
+                "kernel": "grouped subdomain-solve GEMM (FP32 MFMA) of one Schwarz sweep on the "
+                          "8^3 p=6 fine level, 2 sum_S n_S^2 = "
+                          f"{gemm['flops_per_launch']:.4g} flop per launch",
+                "ms_per_launch": round(gemm["ms_per_launch"], 5)}
     roof_src = apply_big or apply_c5
-    roofline = {"bound": "hbm", "achieved": round(roof_src["achieved_gbs"], 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(roof_src["achieved_gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"DG operator apply, {roof_src['elements']} elements p={roof_src['p']}, "
-                          f"16 B/DOF algorithmic (read u, write Au)"}
+    roofline_apply = {"bound": "hbm", "achieved": round(roof_src["achieved_gbs"], 1),
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": round(roof_src["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                      "traffic": measured_traffic("apply") if apply_big else None,
+                      "kernel": f"DG operator apply, {roof_src['elements']} elements "
+                                f"p={roof_src['p']}, 16 B/DOF algorithmic (read u, write Au)",
+                      "ms_per_launch": round(roof_src["ms_per_apply"], 5)}
+    if apply_big:
+        roofline_apply["calibration_copy_bytes"] = 8 * apply_big["ndof"]
 
+    if not args.no_c5:
+        _log("16^3 p=7 solves")
     c5 = None if args.no_c5 else time_c5(dg)
+    if not args.no_serving:
+        _log(f"serving stream of {args.serve_requests} requests")
     serving = None if args.no_serving else run_serving(dg, args.serve_requests)
 
     cpu = None
     u_oracle = None
     if not args.no_cpu_baseline:
+        _log("oracle on the host CPU")
         cpu, u_oracle = cpu_baseline()
 
     out = {
@@ -286,6 +365,7 @@ def main():
         "c5_16x16x16_p7": c5,
         "serving": serving,
         "roofline": roofline,
+        "roofline_apply": roofline_apply,
         "cpu_baseline": cpu,
     }
     if u_oracle is not None:

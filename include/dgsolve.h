@@ -154,6 +154,18 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
                      double* u, double newton_rtol, double linear_rtol, int max_newton,
                      dgs_stats* stats, void* stream);
 
+/* The subdomain solves of one Schwarz sweep alone (Sec. III.D.2, III.E.2):
+ * du_S = s A_S^-1 r_S for every subdomain of multigrid level `level`
+ * (0 = finest), one grouped GEMM launch on the matrix cores, repeated `reps`
+ * (>= 0) times on `stream`.  It reads the level's gathered residuals r_S as
+ * the last smoothing step left them (values do not change the work done) and
+ * writes only library workspace, so no caller-visible state changes.  Meant
+ * for timing this dominant kernel of a Schwarz step with events recorded on
+ * the same stream.  *flops (may be NULL) receives the algorithmic flop count
+ * of one sweep, 2 * sum over subdomains S of n_S^2.  DGS_ERR_INVALID for a
+ * level outside [0, levels). */
+int dgs_subdomain_solves(dgs_problem* prob, int level, int reps, double* flops, void* stream);
+
 /* The p+1 Legendre-Gauss-Lobatto points on [-1, 1] (ascending), so that a
  * caller can place its data: point (i, j, k) of element (e_x, e_y, e_z) sits at
  * x = lower_x + h_x (e_x + (xi_i + 1) / 2), and likewise in y and z. */

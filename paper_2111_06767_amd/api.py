@@ -29,7 +29,7 @@ EXPORTED = (
     "dgs_node_coordinates", "dgs_apply_mass", "dgs_apply_operator", "dgs_schwarz_smooth",
     "dgs_precondition", "dgs_solve", "dgs_newton_solve", "dgs_last_error", "dgs_set_diagonal",
     "dgs_lgl_nodes", "dgs_server_create", "dgs_server_destroy", "dgs_server_submit",
-    "dgs_server_step", "dgs_server_finished", "dgs_server_fetch",
+    "dgs_server_step", "dgs_server_finished", "dgs_server_fetch", "dgs_subdomain_solves",
 )
 
 
@@ -217,6 +217,14 @@ class Problem:
         _check(self._lib.dgs_precondition(self._h, _ptr(r, self.ndof, "r"), _ptr(out, self.ndof, "z"),
                                           _stream(stream)))
         return out
+
+    def subdomain_solves(self, level=0, reps=1, stream=None):
+        """Launch the grouped subdomain-solve GEMM of one Schwarz sweep on
+        `level` `reps` times (timing aid); returns its flops per sweep."""
+        flops = ctypes.c_double()
+        _check(self._lib.dgs_subdomain_solves(self._h, int(level), int(reps), ctypes.byref(flops),
+                                              _stream(stream)))
+        return flops.value
 
     def set_diagonal(self, d=None, stream=None):
         """Operator A + diag(d) for smoothing, preconditioning and solves (None: A)."""

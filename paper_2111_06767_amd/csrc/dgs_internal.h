@@ -109,6 +109,15 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 // Grouped subdomain GEMM: tiles_big use 64 x 128 block tiles (classes with
 // many subdomains), tiles_small 16 x 128 (classes with few).
 constexpr int kGemmBigM = 64, kGemmSmallM = 16, kGemmN = 128, kGemmSmallCount = 32;
+
+// Work list of one level's grouped GEMM (one launch): every class in 64-row
+// tiles when any class has more than kGemmSmallCount subdomains, else every
+// class in 16-row tiles; the K range split into kparts partial products.
+struct GemmPlan {
+  std::vector<GemmTile> big, small;
+  int kparts = 1;
+};
+GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls);
 // use_op = 0: multiply by the stored inverse (factor scale);
 // use_op = 1: by the stored subdomain operator (factor scale_op).
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,

@@ -478,6 +478,33 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
   return hipGetLastError();
 }
 
+GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls) {
+  GemmPlan plan;
+  bool any_big = false;
+  for (const ClassInfo& c : cls) any_big = any_big || c.count > kGemmSmallCount;
+  // the few partly filled tiles of small classes run beside the large ones
+  const bool is_small = !any_big;
+  const int bm = is_small ? kGemmSmallM : kGemmBigM;
+  // split K until there are enough tiles to fill the 256 compute units
+  int base = 0;
+  for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + kGemmN - 1) / kGemmN);
+  plan.kparts = 1;
+  while (plan.kparts < 4 && base * plan.kparts < 512) plan.kparts *= 2;
+  for (int c = 0; c < (int)cls.size(); ++c) {
+    const ClassInfo& I = cls[c];
+    // K chunks in multiples of 32 so FP32 and FP64 tiles both stay aligned
+    const int chunk = ((I.n + plan.kparts - 1) / plan.kparts + 31) / 32 * 32;
+    for (int part = 0; part < plan.kparts; ++part) {
+      const int k0 = part * chunk, k1 = std::min(I.n, (part + 1) * chunk);
+      for (int m0 = 0; m0 < I.count; m0 += bm)
+        for (int n0 = 0; n0 < I.n; n0 += kGemmN)
+          // an empty K range still writes zeros so every part is defined
+          (is_small ? plan.small : plan.big).push_back(GemmTile{c, m0, n0, part, k0, std::max(k0, k1)});
+    }
+  }
+  return plan;
+}
+
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,
                                  long long ps, const ClassInfo* cls,
                                  const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,

@@ -324,7 +324,6 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   std::vector<int> seg_loc;
   std::vector<double> weights;
   long long rs_off = 0;
-  std::vector<GemmTile> big, small;
   for (int c = 0; c < ci; ++c) {
     ClassInfo& I = L.cls[c];
     const ClassLayout& lay = L.layouts[c];
@@ -344,29 +343,10 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   L.rs_total = rs_off;
   L.max_n = 0;
   for (int c = 0; c < ci; ++c) L.max_n = std::max(L.max_n, L.cls[c].n);
-  // split K until there are enough tiles to fill the 256 compute units
-  int base = 0;
-  for (int c = 0; c < ci; ++c) {
-    const int bm = L.cls[c].count <= kGemmSmallCount ? kGemmSmallM : kGemmBigM;
-    base += ((L.cls[c].count + bm - 1) / bm) * ((L.cls[c].n + kGemmN - 1) / kGemmN);
-  }
-  L.kparts = 1;
-  while (L.kparts < 4 && base * L.kparts < 512) L.kparts *= 2;
-  for (int c = 0; c < ci; ++c) {
-    const ClassInfo& I = L.cls[c];
-    const bool is_small = I.count <= kGemmSmallCount;
-    const int bm = is_small ? kGemmSmallM : kGemmBigM;
-    // K chunks in multiples of 32 so FP32 and FP64 tiles both stay aligned
-    const int chunk = ((I.n + L.kparts - 1) / L.kparts + 31) / 32 * 32;
-    for (int part = 0; part < L.kparts; ++part) {
-      const int k0 = part * chunk, k1 = std::min(I.n, (part + 1) * chunk);
-      for (int m0 = 0; m0 < I.count; m0 += bm)
-        for (int n0 = 0; n0 < I.n; n0 += kGemmN) {
-          // an empty K range still writes zeros so every part is defined
-          (is_small ? small : big).push_back(GemmTile{c, m0, n0, part, k0, std::max(k0, k1)});
-        }
-    }
-  }
+  const GemmPlan plan = plan_subdomain_gemm(L.cls);
+  L.kparts = plan.kparts;
+  const std::vector<GemmTile>& big = plan.big;
+  const std::vector<GemmTile>& small = plan.small;
   std::vector<long long> elem_row(L.E);
   for (long long e = 0; e < L.E; ++e)
     elem_row[e] = L.cls[elem_class[e]].rs_off + (long long)pos[e] * L.cls[elem_class[e]].n;
@@ -699,7 +679,8 @@ void autotune_gemm(dgs_problem* P, hipStream_t s) {
       HIP_OK(hipEventSynchronize(e1));
       float ms = 0;
       HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best_ms) {
+      // a later variant must win by 3 % so near ties resolve the same way
+      if (ms < 0.97f * best_ms) {
         best_ms = ms;
         L.gemm_variant = v;
       }
@@ -1370,6 +1351,26 @@ int dgs_schwarz_smooth(dgs_problem* prob, const double* b, double* u, int steps,
     if (!prob || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
     if (steps < 0) return fail(DGS_ERR_INVALID, "steps must be >= 0");
     schwarz_steps(prob, 0, b, u, steps, false, as_stream(stream));
+    return DGS_OK;
+  });
+}
+
+int dgs_subdomain_solves(dgs_problem* prob, int level, int reps, double* flops, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (level < 0 || level >= (int)prob->levels.size())
+      return fail(DGS_ERR_INVALID, "level out of range");
+    if (reps < 0) return fail(DGS_ERR_INVALID, "reps must be >= 0");
+    Level& L = prob->levels[level];
+    if (flops) {
+      double f = 0.0;
+      for (const ClassInfo& c : L.cls) f += 2.0 * (double)c.n * (double)c.n * (double)c.count;
+      *flops = f;
+    }
+    const hipStream_t s = as_stream(stream);
+    for (int r = 0; r < reps; ++r)
+      HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big,
+                                   L.nbig, L.d_tiles_small, L.nsmall, 0, s, L.gemm_variant));
     return DGS_OK;
   });
 }

@@ -48,3 +48,11 @@ def test_default_options_and_invalid_arguments_without_gpu():
     bad = m.api.Domain((ctypes.c_double * 3)(0, 0, 0), (ctypes.c_double * 3)(1, 0, 1))
     assert lib.dgs_create_problem(ctypes.byref(bad), (ctypes.c_int * 3)(1, 1, 1), 3, 1.5,
                                   ctypes.byref(o), None, ctypes.byref(h)) == m.DGS_ERR_INVALID
+
+
+def test_subdomain_solves_rejects_null_problem_without_gpu():
+    import paper_2111_06767_amd as m
+    if not os.path.exists(m.api.LIB_PATH):
+        pytest.skip("library not built")
+    lib = m.load_library()
+    assert lib.dgs_subdomain_solves(None, 0, 1, None, None) == m.DGS_ERR_INVALID

@@ -130,3 +130,20 @@ def test_graph_replays_match_eager():
         ue, se = pe.solve(b)
         assert sg["iterations"] == se["iterations"]
         assert torch.equal(ug, ue)
+
+
+@pytest.mark.parametrize("elements,p,levels", [((8, 8, 8), 6, 3), ((3, 2, 4), 3, 2)])
+def test_subdomain_solves_flop_count(elements, p, levels):
+    """The timing entry point reports 2 sum_S n_S^2 per sweep on every level,
+    n_S taken from the oracle's subdomain layouts; it rejects a bad level."""
+    import paper_2111_06767_amd as dg
+    announce(f"subdomain_solves flops elements={elements} p={p}")
+    for prec in ("fp64", "mixed"):
+        prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, precision=prec)
+        meshes = multigrid.hierarchy(omesh.BoxMesh((0, 0, 0), (1, 1, 1), elements, p), levels)
+        for lv, (m, _) in enumerate(meshes):
+            want = sum(2.0 * len(schwarz.subdomain_layout(m, e, 2)[0]) ** 2 for e in range(m.E))
+            assert prob.subdomain_solves(lv, reps=2) == want
+        with pytest.raises(dg.api.DgsError):
+            prob.subdomain_solves(len(meshes))
+        prob.close()
