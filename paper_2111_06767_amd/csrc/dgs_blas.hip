@@ -44,29 +44,94 @@ __global__ void k_waxpy(double* __restrict__ y, const double* __restrict__ x, do
   if (g < n) y[g] = x[g] + lam * dx[g];
 }
 
-// partial[b * m + i] = sum over block b's chunk of V_i . w
-__global__ void __launch_bounds__(kDotThreads)
-k_multidot_partial(const double* __restrict__ V, long long ldv, int m, const double* __restrict__ w,
-                   long long n, long long chunk, double* __restrict__ partial) {
-  __shared__ double red[kDotThreads / 64];
-  const long long start = (long long)blockIdx.x * chunk;
-  const long long end = start + chunk < n ? start + chunk : n;
-  for (int i = 0; i < m; ++i) {
-    const double* v = V + (long long)i * ldv;
-    double s = 0.0;
-    for (long long g = start + threadIdx.x; g < end; g += kDotThreads) s += v[g] * w[g];
-    const double t = block_sum(s, red);
-    if (threadIdx.x == 0) partial[(long long)blockIdx.x * m + i] = t;
+// Two-stage dot products: the vector is cut into multidot_blocks(n) fixed
+// chunks; block b writes partial[b * m + i] = (its chunk of V_i) . w, eight
+// vectors per pass, and one block per i then sums the partials in a fixed
+// order.  The fused variants first apply w -= sum_i coef_i V_i on the same
+// chunk (each thread updates the points it later reads back itself, so no
+// barrier is needed between the two phases).
+constexpr int kDotGroup = 8;
+
+template <int G>
+__device__ __forceinline__ void group_store(double (&v)[G], double* red, double* out, int count) {
+  constexpr int W = kDotThreads / 64;
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+    for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_down(v[q], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < G; ++q) red[q * W + wave] = v[q];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < count) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) t += red[threadIdx.x * W + w];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void chunk_dots(const double* __restrict__ V, long long ldv, int m,
+                                           const double* w, long long start, long long end,
+                                           double* red, double* __restrict__ partial) {
+  for (int i0 = 0; i0 < m; i0 += kDotGroup) {
+    double acc[kDotGroup];
+#pragma unroll
+    for (int q = 0; q < kDotGroup; ++q) acc[q] = 0.0;
+    for (long long g = start + threadIdx.x; g < end; g += kDotThreads) {
+      const double wg = w[g];
+#pragma unroll
+      for (int q = 0; q < kDotGroup; ++q)
+        if (i0 + q < m) acc[q] += V[(long long)(i0 + q) * ldv + g] * wg;
+    }
+    group_store<kDotGroup>(acc, red, partial + (long long)blockIdx.x * m + i0,
+                           m - i0 < kDotGroup ? m - i0 : kDotGroup);
   }
 }
 
-__global__ void k_multidot_final(const double* __restrict__ partial, int nblocks, int m,
-                                 double* __restrict__ h) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
+__global__ void __launch_bounds__(kDotThreads)
+k_multidot_partial(const double* __restrict__ V, long long ldv, int m, const double* __restrict__ w,
+                   long long n, long long chunk, double* __restrict__ partial) {
+  __shared__ double red[kDotGroup * (kDotThreads / 64)];
+  const long long start = (long long)blockIdx.x * chunk;
+  const long long end = start + chunk < n ? start + chunk : n;
+  chunk_dots(V, ldv, m, w, start, end, red, partial);
+}
+
+// w -= sum_{i < m} coef_i V_i, then partial dots of V_0..V_{m-1} with the new
+// w (norm_only = 0), or of w with itself (norm_only = 1, one value per block).
+__global__ void __launch_bounds__(kDotThreads)
+k_axpy_multidot_partial(const double* __restrict__ V, long long ldv, int m,
+                        const double* __restrict__ coef, double* w, long long n, long long chunk,
+                        int norm_only, double* __restrict__ partial) {
+  __shared__ double red[kDotGroup * (kDotThreads / 64)];
+  const long long start = (long long)blockIdx.x * chunk;
+  const long long end = start + chunk < n ? start + chunk : n;
+  for (long long g = start + threadIdx.x; g < end; g += kDotThreads) {
+    double acc = w[g];
+    for (int i = 0; i < m; ++i) acc -= coef[i] * V[(long long)i * ldv + g];
+    w[g] = acc;
+  }
+  if (norm_only) {
+    double acc[1] = {0.0};
+    for (long long g = start + threadIdx.x; g < end; g += kDotThreads) acc[0] += w[g] * w[g];
+    group_store<1>(acc, red, partial + blockIdx.x, 1);
+  } else {
+    chunk_dots(V, ldv, m, w, start, end, red, partial);
+  }
+}
+
+// h[i] = sum_b partial[b * m + i], one block per i, fixed order
+__global__ void __launch_bounds__(kDotThreads)
+k_multidot_final(const double* __restrict__ partial, int nblocks, int m, double* __restrict__ h) {
+  __shared__ double red[kDotThreads / 64];
+  const int i = blockIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * m + i];
-  h[i] = s;
+  for (int b = threadIdx.x; b < nblocks; b += kDotThreads) s += partial[(long long)b * m + i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) h[i] = s;
 }
 
 __global__ void k_multi_axpy(double* __restrict__ w, const double* __restrict__ V, long long ldv,
@@ -172,7 +237,7 @@ hipError_t launch_waxpy(double* y, const double* x, double lam, const double* dx
 }
 
 int multidot_blocks(long long n) {
-  long long b = (n + 4095) / 4096;  // ~4096 elements per block
+  long long b = (n + 511) / 512;  // ~512 points per block: enough blocks for 256 CUs
   if (b < 1) b = 1;
   if (b > 1024) b = 1024;
   return (int)b;
@@ -185,7 +250,20 @@ hipError_t launch_multidot(const double* V, long long ldv, int m, const double* 
   const long long chunk = (n + nb - 1) / nb;
   hipLaunchKernelGGL(k_multidot_partial, dim3(nb), dim3(kDotThreads), 0, s, V, ldv, m, w, n, chunk,
                      partial);
-  hipLaunchKernelGGL(k_multidot_final, dim3(nblk(m, 64)), dim3(64), 0, s, partial, nb, m, h);
+  hipLaunchKernelGGL(k_multidot_final, dim3(m), dim3(kDotThreads), 0, s, partial, nb, m, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_multidot(const double* V, long long ldv, int m, const double* coef, double* w,
+                                long long n, bool norm_only, double* partial, double* h,
+                                hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int nb = multidot_blocks(n);
+  const long long chunk = (n + nb - 1) / nb;
+  hipLaunchKernelGGL(k_axpy_multidot_partial, dim3(nb), dim3(kDotThreads), 0, s, V, ldv, m, coef, w,
+                     n, chunk, norm_only ? 1 : 0, partial);
+  const int mh = norm_only ? 1 : m;
+  hipLaunchKernelGGL(k_multidot_final, dim3(mh), dim3(kDotThreads), 0, s, partial, nb, mh, h);
   return hipGetLastError();
 }
 

@@ -178,6 +178,11 @@ hipError_t launch_axpy(double* y, double a, const double* x, long long n, hipStr
 int multidot_blocks(long long n);
 hipError_t launch_multidot(const double* V, long long ldv, int m, const double* w, long long n,
                            double* partial, double* h, hipStream_t s);
+// w -= sum_{i < m} coef_i V_i (coef on the device), then h_i = V_i . w for
+// i < m, or h_0 = w . w when norm_only; the same fixed-order reductions.
+hipError_t launch_axpy_multidot(const double* V, long long ldv, int m, const double* coef, double* w,
+                                long long n, bool norm_only, double* partial, double* h,
+                                hipStream_t s);
 // w -= sum_i coef[i] * V_i  (coef on the device, scaled by `sign`)
 hipError_t launch_multi_axpy(double* w, const double* V, long long ldv, int m, const double* coef,
                              long long n, hipStream_t s);

@@ -31,12 +31,25 @@ __device__ __forceinline__ void line_apply(const double* __restrict__ in, double
   }
 }
 
+// Restriction of one coarse element, sum-factorised across its children: the
+// x pass combines each pair of children that differ in x, the y pass each
+// pair of those results that differ in y, the z pass the last pair:
+//   T1[oy][oz](a, j, k) = sum_ox sum_m Px_ox(m, a) child[ox][oy][oz](m, j, k)
+//   T2[oz](a, b, k)     = sum_oy sum_n Py_oy(n, b) T1[oy][oz](a, n, k)
+//   coarse(a, b, c)     = sum_oz sum_o Pz_oz(o, c) T2[oz](a, b, o)
+// with P = identity and a single child in a dimension that is not split.
+template <int N>
+__device__ __forceinline__ double pcoef(const double* sPlo, const double* sPhi, int split, int half,
+                                        int m, int a) {
+  return split ? (half ? sPhi[m * N + a] : sPlo[m * N + a]) : (m == a ? 1.0 : 0.0);
+}
+
 template <int N>
 __global__ void __launch_bounds__(256)
 k_restrict(const double* __restrict__ fine, double* __restrict__ coarse, int nfx, int nfy,
            int ncx, int ncy, int ncz, int sx, int sy, int sz, DevTables T) {
-  constexpr int N3 = N * N * N;
-  __shared__ double buf0[N3], buf1[N3];
+  constexpr int N2 = N * N, N3 = N2 * N;
+  __shared__ double T1[4][N3], T2[2][N3];
   __shared__ double sPlo[N * N], sPhi[N * N];
   const int tid = threadIdx.x;
   for (int t = tid; t < N * N; t += blockDim.x) {
@@ -45,39 +58,46 @@ k_restrict(const double* __restrict__ fine, double* __restrict__ coarse, int nfx
   }
   const long long ec = blockIdx.x;
   const int cx = (int)(ec % ncx), cy = (int)((ec / ncx) % ncy), cz = (int)(ec / ((long long)ncx * ncy));
-  double acc[(N3 + 255) / 256];
+  __syncthreads();
+  // x pass, straight from the fine field
+  for (int t = tid; t < (sy + 1) * (sz + 1) * N3; t += blockDim.x) {
+    const int slot = t / N3, p = t - slot * N3;
+    const int oy = slot % (sy + 1), oz = slot / (sy + 1);
+    const int a = p % N, jk = p / N;
+    const int fy = sy ? 2 * cy + oy : cy, fz = sz ? 2 * cz + oz : cz;
+    double acc = 0.0;
+    for (int ox = 0; ox <= sx; ++ox) {
+      const int fx = sx ? 2 * cx + ox : cx;
+      const double* src = fine + (((long long)fz * nfy + fy) * nfx + fx) * N3 + jk * N;
 #pragma unroll
-  for (int q = 0; q < (N3 + 255) / 256; ++q) acc[q] = 0.0;
-  const int split[3] = {sx, sy, sz};
-  for (int oz = 0; oz <= sz; ++oz)
-    for (int oy = 0; oy <= sy; ++oy)
-      for (int ox = 0; ox <= sx; ++ox) {
-        const int fx = sx ? 2 * cx + ox : cx, fy = sy ? 2 * cy + oy : cy, fz = sz ? 2 * cz + oz : cz;
-        const long long ef = ((long long)fz * nfy + fy) * nfx + fx;
-        __syncthreads();
-        for (int p = tid; p < N3; p += blockDim.x) buf0[p] = fine[ef * N3 + p];
-        __syncthreads();
-        double* cur = buf0;
-        double* nxt = buf1;
-        const int half[3] = {ox, oy, oz};
-        for (int d = 0; d < 3; ++d) {
-          if (!split[d]) continue;
-          line_apply<N>(cur, nxt, half[d] ? sPhi : sPlo, true, d, tid, blockDim.x);
-          __syncthreads();
-          double* t = cur;
-          cur = nxt;
-          nxt = t;
-        }
+      for (int m = 0; m < N; ++m) acc += pcoef<N>(sPlo, sPhi, sx, ox, m, a) * src[m];
+    }
+    T1[slot][p] = acc;
+  }
+  __syncthreads();
+  // y pass
+  for (int t = tid; t < (sz + 1) * N3; t += blockDim.x) {
+    const int oz = t / N3, p = t - oz * N3;
+    const int a = p % N, b = (p / N) % N, k = p / N2;
+    double acc = 0.0;
+    for (int oy = 0; oy <= sy; ++oy) {
+      const double* src = T1[oz * (sy + 1) + oy] + k * N2 + a;
 #pragma unroll
-        for (int q = 0; q < (N3 + 255) / 256; ++q) {
-          const int p = tid + 256 * q;
-          if (p < N3) acc[q] += cur[p];
-        }
-      }
+      for (int n = 0; n < N; ++n) acc += pcoef<N>(sPlo, sPhi, sy, oy, n, b) * src[n * N];
+    }
+    T2[oz][p] = acc;
+  }
+  __syncthreads();
+  // z pass
+  for (int p = tid; p < N3; p += blockDim.x) {
+    const int ab = p % N2, c = p / N2;
+    double acc = 0.0;
+    for (int oz = 0; oz <= sz; ++oz) {
+      const double* src = T2[oz] + ab;
 #pragma unroll
-  for (int q = 0; q < (N3 + 255) / 256; ++q) {
-    const int p = tid + 256 * q;
-    if (p < N3) coarse[ec * N3 + p] = acc[q];
+      for (int o = 0; o < N; ++o) acc += pcoef<N>(sPlo, sPhi, sz, oz, o, c) * src[o * N2];
+    }
+    coarse[ec * N3 + p] = acc;
   }
 }
 

@@ -957,11 +957,11 @@ struct FgmresRun {
       double* h1 = P->d_h;
       double* h2 = P->d_h + (m + 2);
       double* hn = P->d_h + 2 * (m + 2);
+      // classical Gram-Schmidt twice; each correction is fused with the
+      // reduction that follows it
       HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h1, s));
-      HIP_OK(launch_multi_axpy(w, V, n, j + 1, h1, n, s));
-      HIP_OK(launch_multidot(V, n, j + 1, w, n, P->d_partial, h2, s));
-      HIP_OK(launch_multi_axpy(w, V, n, j + 1, h2, n, s));
-      HIP_OK(launch_multidot(w, n, 1, w, n, P->d_partial, hn, s));
+      HIP_OK(launch_axpy_multidot(V, n, j + 1, h1, w, n, false, P->d_partial, h2, s));
+      HIP_OK(launch_axpy_multidot(V, n, j + 1, h2, w, n, true, P->d_partial, hn, s));
       // h1, h2 and |w|^2 are contiguous on the device: one copy
       HIP_OK(hipMemcpyAsync(hp, P->d_h, sizeof(double) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, s));
       HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));  // unused if |w| = 0 (the run stops)
