@@ -76,12 +76,62 @@ __device__ __forceinline__ void face_from_line(const double (&x)[N], int side, d
   ge = acc * rh;
 }
 
+// Gather-out of one z-line of the residual (lane (a, b), points k = 0..N-1)
+// into the subdomain rows: the element's own row (mirrored into its class
+// frame) and the overlap strips of its face neighbours' subdomains, at the
+// offsets of the scatter's pull table.  A strip entry is layer * N^2 + t1 * N
+// + t0 (layer counted from the shared face into this element, t0 / t1 the
+// transverse indices in the neighbour's frame).
+template <typename TS, int N>
+__device__ __forceinline__ void store_subdomain_rows(const double (&rz)[N], TS* __restrict__ rs,
+                                                     const PullEntry* pe, int a, int b, int nov) {
+  constexpr int N2 = N * N;
+  const PullEntry own = pe[0];
+  {
+    const int mi = (own.flip & 1) ? N - 1 - a : a;
+    const int mj = (own.flip & 2) ? N - 1 - b : b;
+    const bool fk = own.flip & 4;
+    TS* p = rs + own.du + mj * N + mi;
+#pragma unroll
+    for (int k = 0; k < N; ++k) p[(fk ? N - 1 - k : k) * N2] = (TS)rz[k];
+  }
+  // x and y faces: the lane's layer is fixed and t1 = k
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const PullEntry q = pe[1 + f];
+    const int id = f < 2 ? a : b;
+    const int layer = (f & 1) ? N - 1 - id : id;
+    if (q.du >= 0 && layer < nov) {
+      int t0 = f < 2 ? b : a;
+      if (q.flip & 1) t0 = N - 1 - t0;
+      const bool f1 = q.flip & 2;
+      TS* p = rs + q.du + layer * N2 + t0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) p[(f1 ? N - 1 - k : k) * N] = (TS)rz[k];
+    }
+  }
+  // z faces: the layer is the point's own k (uniform across the element)
+#pragma unroll
+  for (int f = 4; f < 6; ++f) {
+    const PullEntry q = pe[1 + f];
+    if (q.du < 0) continue;
+    const int t0 = (q.flip & 1) ? N - 1 - a : a;
+    const int t1 = (q.flip & 2) ? N - 1 - b : b;
+    TS* p = rs + q.du + t1 * N + t0;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int layer = f == 4 ? k : N - 1 - k;
+      if (layer < nov) p[layer * N2] = (TS)rz[k];
+    }
+  }
+}
+
 template <int N, int EPB>
 __global__ void __launch_bounds__(((EPB * N * N + 63) / 64) * 64)
 k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ bvec,
         const double* __restrict__ aux0, const double* __restrict__ aux1,
         const int* __restrict__ nbr, OpParams P, DevTables T, int mode,
-        const int* __restrict__ order) {
+        const int* __restrict__ order, GatherOut go) {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int PIT = N + 1;  // padded row pitch (bank spread for line reads)
   constexpr int S3 = N * N * PIT;
@@ -91,6 +141,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   // contributions in the second phase
   __shared__ double sU[EPB][S3], sA[EPB][S3], sB[EPB][S3];
   __shared__ double sw[N];
+  __shared__ PullEntry sPull[EPB][7];  // gather-out mode only
 
   const int tid = threadIdx.x;
   if (tid < N) sw[tid] = T.w[tid];
@@ -107,6 +158,13 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   const long long e = (active && order) ? (long long)order[pos] : pos;
   const double J = P.J;
   auto L = [](int k, int j, int i) { return (k * N + j) * PIT + i; };
+  if (go.rs) {
+    for (int q = tid; q < EPB * 7; q += blockDim.x) {
+      const int s7 = q / 7, j7 = q - s7 * 7;
+      const long long ps = (long long)blk * EPB + s7;
+      if (ps < P.E) sPull[s7][j7] = go.pull[(order ? (long long)order[ps] : ps) * 7 + j7];
+    }
+  }
 
   double uz[N], zlo[N], zhi[N], ylo[N], yhi[N];
   int nb[6];
@@ -250,11 +308,26 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       sB[slot][L(b, j, a)] = v;
     }
   }
+  // the right-hand side and diagonal of this lane's z-line, loaded before the
+  // barrier and before any store (the gather-out stores may not be reordered
+  // ahead of later loads, so loads inside the store loop would serialise)
+  double bz[N], dz[N];
+  if (active) {
+    const bool need_b = mode == kResidual || mode == kResidualDiag || mode == kPuncture;
+    const bool need_d = mode == kApplyDiag || mode == kResidualDiag || mode == kPuncture;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const long long gi = e * N3 + k * N2 + t;
+      bz[k] = need_b ? bvec[gi] : 0.0;
+      dz[k] = need_d ? aux0[gi] : 0.0;
+    }
+  }
   __syncthreads();
   if (active) {
     double c[N];
     eo_apply<N>(qz, c, T.bwd);
     const double jwab = J * sw[a] * sw[b];
+    double rz[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       double r = c[k] * P.rh[2] + sA[slot][L(k, b, a)] + sB[slot][L(k, b, a)];
@@ -265,25 +338,33 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         case kApply:
           break;
         case kResidual:
-          r = bvec[gi] - r;
+          r = bz[k] - r;
           break;
         case kApplyDiag:
-          r += aux0[gi] * uz[k];
+          r += dz[k] * uz[k];
           break;
         case kResidualDiag:
-          r = bvec[gi] - (r + aux0[gi] * uz[k]);
+          r = bz[k] - (r + dz[k] * uz[k]);
           break;
         case kPuncture: {
-          const double tt = aux0[gi] * (1.0 + uz[k]) + 1.0;
+          const double tt = dz[k] * (1.0 + uz[k]) + 1.0;
           const double t2 = tt * tt, t4 = t2 * t2;
           const double S = -aux1[gi] / (t4 * t2 * tt);
-          r += jwab * T.w[k] * S - bvec[gi];
+          r += jwab * T.w[k] * S - bz[k];
           break;
         }
         default:
           break;
       }
-      out[gi] = r;
+      rz[k] = r;
+    }
+    if (!go.rs) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) out[e * N3 + k * N2 + t] = rz[k];
+    } else if (go.f32) {
+      store_subdomain_rows<float, N>(rz, (float*)go.rs, sPull[slot], a, b, go.nov);
+    } else {
+      store_subdomain_rows<double, N>(rz, (double*)go.rs, sPull[slot], a, b, go.nov);
     }
   }
 }
@@ -291,24 +372,26 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
 template <int N, int EPB>
 hipError_t launch_apply_t(int mode, const double* u, double* out, const double* b,
                           const double* aux0, const double* aux1, const int* nbr,
-                          const OpParams& P, const DevTables& T, hipStream_t s, const int* order) {
+                          const OpParams& P, const DevTables& T, hipStream_t s, const int* order,
+                          const GatherOut& go) {
   if (P.E <= 0) return hipSuccess;
   const int threads = ((EPB * N * N + 63) / 64) * 64;
   const long long need = ((long long)P.E + EPB - 1) / EPB;
   const long long blocks = ((need + 7) / 8) * 8;  // whole rounds over the 8 XCDs
   hipLaunchKernelGGL((k_apply<N, EPB>), dim3((unsigned)blocks), dim3(threads), 0, s, u, out, b,
-                     aux0, aux1, nbr, P, T, mode, order);
+                     aux0, aux1, nbr, P, T, mode, order, go);
   return hipGetLastError();
 }
 
 template <int N>
 hipError_t launch_apply_n(int epb, int mode, const double* u, double* out, const double* b,
                           const double* aux0, const double* aux1, const int* nbr,
-                          const OpParams& P, const DevTables& T, hipStream_t s, const int* order) {
+                          const OpParams& P, const DevTables& T, hipStream_t s, const int* order,
+                          const GatherOut& go) {
   constexpr int def = (N == 2) ? 64 : (256 / (N * N));  // >= 3 for every N <= 9
-  if (epb == 1) return launch_apply_t<N, 1>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-  if (epb == 2) return launch_apply_t<N, 2>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-  return launch_apply_t<N, def>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+  if (epb == 1) return launch_apply_t<N, 1>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+  if (epb == 2) return launch_apply_t<N, 2>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+  return launch_apply_t<N, def>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
 }
 
 // b = M f, M = J w_i w_j w_k
@@ -343,16 +426,17 @@ __global__ void k_coords(double* __restrict__ xyz, long long total, int N, int n
 hipError_t launch_apply(int N, int mode, const double* u, double* out, const double* b,
                         const double* aux0, const double* aux1, const int* nbr, const OpParams& P,
                         const DevTables& T, const ApplyConfig& cfg, hipStream_t s,
-                        const int* order) {
+                        const int* order, const GatherOut& go) {
+  if (go.rs && (mode != kResidual && mode != kResidualDiag)) return hipErrorInvalidValue;
   switch (N) {
-    case 2: return launch_apply_n<2>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-    case 3: return launch_apply_n<3>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-    case 4: return launch_apply_n<4>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-    case 5: return launch_apply_n<5>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-    case 6: return launch_apply_n<6>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-    case 7: return launch_apply_n<7>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-    case 8: return launch_apply_n<8>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
-    case 9: return launch_apply_n<9>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order);
+    case 2: return launch_apply_n<2>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+    case 3: return launch_apply_n<3>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+    case 4: return launch_apply_n<4>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+    case 5: return launch_apply_n<5>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+    case 6: return launch_apply_n<6>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+    case 7: return launch_apply_n<7>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+    case 8: return launch_apply_n<8>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+    case 9: return launch_apply_n<9>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
     default: return hipErrorInvalidValue;
   }
 }

@@ -72,12 +72,32 @@ struct ApplyConfig {
   int epb = 0;  // 0 = default for N
 };
 
+// Pull table of the weighted scatter, 7 entries per element: entry 0 is the
+// element's own subdomain, entry 1 + f the subdomain of its face-f neighbour.
+struct PullEntry {
+  long long du;  // entry 0: the element's row in the correction block;
+                 // faces: start of the neighbour's strip toward the element (-1: none)
+  int w;         // matching offset in the weight table
+  int flip;      // entry 0: mirror mask of the element; faces: bits 0 / 1 reverse the
+                 // first / second transverse index (the neighbour is mirrored there)
+};
+
+// Residual modes only: instead of r, write r_S = R_S r for every subdomain
+// (the element's own row and its points in the face neighbours' overlap
+// strips, located through the scatter's pull table) into the gather block rs.
+struct GatherOut {
+  void* rs = nullptr;  // nullptr: write r to `out` as usual
+  bool f32 = false;    // rs holds FP32 (mixed-precision level) or FP64 values
+  const PullEntry* pull = nullptr;
+  int nov = 0;         // overlap layers
+};
+
 // order (optional, may be NULL): processing order of the elements, a
 // permutation of 0..E-1 that keeps face neighbours close in time.
 hipError_t launch_apply(int N, int mode, const double* u, double* out, const double* b,
                         const double* aux0, const double* aux1, const int* nbr, const OpParams& P,
                         const DevTables& T, const ApplyConfig& cfg, hipStream_t s,
-                        const int* order = nullptr);
+                        const int* order = nullptr, const GatherOut& go = GatherOut{});
 hipError_t launch_mass(int N, const double* f, double* out, long long E, const double h[3],
                        const DevTables& T, hipStream_t s);
 hipError_t launch_coords(int N, double* xyz, const int n[3], const double lower[3],
@@ -147,15 +167,6 @@ hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride
                              const long long* elem_row, const ClassInfo* cls, int E, hipStream_t s);
 // u += sum_S R_S^T (w_S du_S), pulled per point; du is the sum of `parts`
 // split-K partial products spaced part_stride apart.
-// Pull table of the weighted scatter, 7 entries per element: entry 0 is the
-// element's own subdomain, entry 1 + f the subdomain of its face-f neighbour.
-struct PullEntry {
-  long long du;  // entry 0: the element's row in the correction block;
-                 // faces: start of the neighbour's strip toward the element (-1: none)
-  int w;         // matching offset in the weight table
-  int flip;      // entry 0: mirror mask of the element; faces: bits 0 / 1 reverse the
-                 // first / second transverse index (the neighbour is mirrored there)
-};
 
 // u += sum_S R_S^T (w_S du_S), summing `parts` split-K partials (1..4) of du.
 hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
