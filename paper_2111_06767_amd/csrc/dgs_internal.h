@@ -129,6 +129,7 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 // Grouped subdomain GEMM: tiles_big use 64 x 128 block tiles (classes with
 // many subdomains), tiles_small 16 x 128 (classes with few).
 constexpr int kGemmBigM = 64, kGemmSmallM = 16, kGemmN = 128, kGemmSmallCount = 32;
+constexpr int kMaxParts = 16;  // split-K partial products (1, 2, 4, 8 or 16)
 
 // Work list of one level's grouped GEMM (one launch): every class in 64-row
 // tiles when any class has more than kGemmSmallCount subdomains, else every
@@ -168,7 +169,7 @@ hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride
 // u += sum_S R_S^T (w_S du_S), pulled per point; du is the sum of `parts`
 // split-K partial products spaced part_stride apart.
 
-// u += sum_S R_S^T (w_S du_S), summing `parts` split-K partials (1..4) of du.
+// u += sum_S R_S^T (w_S du_S), summing `parts` split-K partials (1, 2, 4, 8, 16) of du.
 hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
                           long long part_stride, const double* weights, const PullEntry* pull,
                           int nov, long long E, hipStream_t s);

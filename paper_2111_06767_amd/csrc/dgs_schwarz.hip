@@ -485,11 +485,14 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls) {
   // the few partly filled tiles of small classes run beside the large ones
   const bool is_small = !any_big;
   const int bm = is_small ? kGemmSmallM : kGemmBigM;
-  // split K until there are enough tiles to fill the 256 compute units
+  // split K until there are enough tiles to fill the 256 compute units; the
+  // short K loops of few-subdomain levels are latency-bound, so they split
+  // further (the scatter sums the parts)
   int base = 0;
   for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + kGemmN - 1) / kGemmN);
+  const int max_parts = is_small ? kMaxParts : 4;
   plan.kparts = 1;
-  while (plan.kparts < 4 && base * plan.kparts < 512) plan.kparts *= 2;
+  while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
   for (int c = 0; c < (int)cls.size(); ++c) {
     const ClassInfo& I = cls[c];
     // K chunks in multiples of 32 so FP32 and FP64 tiles both stay aligned
@@ -549,6 +552,8 @@ hipError_t scatter_parts(int parts, unsigned blocks, hipStream_t s, double* u, c
     case 2: scatter_launch<T, 2>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
     case 3: scatter_launch<T, 3>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
     case 4: scatter_launch<T, 4>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
+    case 8: scatter_launch<T, 8>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
+    case 16: scatter_launch<T, 16>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
