@@ -126,28 +126,24 @@ struct GemmTile {
 hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* elem_class,
                          const long long* elem_row, const int* nbr, const ClassInfo* cls,
                          const int* seg_loc, int E, hipStream_t s);
-// Grouped subdomain GEMM: tiles_big use 64 x 128 block tiles (classes with
-// many subdomains), tiles_small 16 x 128 (classes with few).
-constexpr int kGemmBigM = 64, kGemmSmallM = 16, kGemmN = 128, kGemmSmallCount = 32;
+// Grouped subdomain GEMM of one level, one launch: DU_c = scale * RS_c * B_c
+// for every class c (B_c the stored transposed inverse, or with use_op the
+// stored A_S and factor scale_op).  Output tiles of BM rows (subdomains) by
+// kGemmN columns: BM = 16 when no class has more than kGemmSmallCount
+// subdomains, else 32 (variant 0) or 64 (variant 1), picked per level by the
+// set-up autotuner.  The K range is split into kparts partial products.
+constexpr int kGemmN = 128, kGemmSmallCount = 32;
 constexpr int kMaxParts = 16;  // split-K partial products (1, 2, 4, 8 or 16)
-
-// Work list of one level's grouped GEMM (one launch): every class in 64-row
-// tiles when any class has more than kGemmSmallCount subdomains, else every
-// class in 16-row tiles; the K range split into kparts partial products.
+constexpr int kGemmVariants = 2;
 struct GemmPlan {
-  std::vector<GemmTile> big, small;
+  std::vector<GemmTile> tiles;
+  bool small = false;
   int kparts = 1;
 };
-GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls);
-// use_op = 0: multiply by the stored inverse (factor scale);
-// use_op = 1: by the stored subdomain operator (factor scale_op).
-hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,
-                                 long long part_stride, const ClassInfo* cls,
-                                 const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
-                                 int nsmall, int use_op, hipStream_t s, int variant = 0);
-// Number of K-depth variants of the large-tile GEMM (0: 16 FP64 / 32 FP32,
-// 1: 32 FP64 / 64 FP32); the set-up autotuner picks one per level.
-constexpr int kGemmVariants = 2;
+GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant);
+hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long part_stride,
+                                 const ClassInfo* cls, const GemmTile* tiles, int ntiles,
+                                 bool small, int use_op, hipStream_t s, int variant);
 // out[i] = sum over parts of part_base[p * stride + i]
 hipError_t launch_reduce_parts(bool f32, void* out, const void* parts_base, int parts,
                                long long stride, long long total, hipStream_t s);

@@ -156,11 +156,14 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
            long long pstride, const ClassInfo* __restrict__ cls,
            const GemmTile* __restrict__ tiles, int use_op) {
   constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
-  constexpr int PA = 1, PB = 4;
+  // LDS row paddings: the MFMA operand reads touch 16 lanes per row and 2 (FP32)
+  // or 1 (FP64) rows per LDS cycle; row strides of 36 / 144 words (FP32) put
+  // those row groups on disjoint banks, an odd stride does it for FP64 A rows
+  constexpr int PA = sizeof(T) == 4 ? 4 : 1, PB = sizeof(T) == 4 ? 16 : 8;
   constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
   static_assert(NA >= 1 && NB >= 1 && (BM * BK) % 256 == 0 && (BK * BN) % 256 == 0, "tile");
   typedef typename Mfma<T>::v4 v4;
-  __shared__ T As[BK][BM + PA];
+  __shared__ T As[BM][BK + PA];  // row-major like RS: coalesced, conflict-free stores
   __shared__ T Bs[BK][BN + PB];
   const GemmTile tl = tiles[blockIdx.x];
   const ClassInfo ci = cls[tl.cls];
@@ -197,7 +200,7 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int e = tid + 256 * q;
-      As[e % BK][e / BK] = ra[q];
+      As[e / BK][e % BK] = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -211,7 +214,7 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
       const int kr = kk + (lane >> 4);
       T av[TM], bv[TN];
 #pragma unroll
-      for (int a = 0; a < TM; ++a) av[a] = As[kr][(wm * TM + a) * 16 + (lane & 15)];
+      for (int a = 0; a < TM; ++a) av[a] = As[(wm * TM + a) * 16 + (lane & 15)][kr];
 #pragma unroll
       for (int b = 0; b < TN; ++b) bv[b] = Bs[kr][(wn * TN + b) * 16 + (lane & 15)];
 #pragma unroll
@@ -478,19 +481,19 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
   return hipGetLastError();
 }
 
-GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls) {
+GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
   GemmPlan plan;
   bool any_big = false;
   for (const ClassInfo& c : cls) any_big = any_big || c.count > kGemmSmallCount;
   // the few partly filled tiles of small classes run beside the large ones
-  const bool is_small = !any_big;
-  const int bm = is_small ? kGemmSmallM : kGemmBigM;
+  plan.small = !any_big;
+  const int bm = plan.small ? 16 : (variant == 0 ? 32 : 64);
   // split K until there are enough tiles to fill the 256 compute units; the
   // short K loops of few-subdomain levels are latency-bound, so they split
   // further (the scatter sums the parts)
   int base = 0;
   for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + kGemmN - 1) / kGemmN);
-  const int max_parts = is_small ? kMaxParts : 4;
+  const int max_parts = plan.small ? kMaxParts : 4;
   plan.kparts = 1;
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
   for (int c = 0; c < (int)cls.size(); ++c) {
@@ -502,36 +505,41 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls) {
       for (int m0 = 0; m0 < I.count; m0 += bm)
         for (int n0 = 0; n0 < I.n; n0 += kGemmN)
           // an empty K range still writes zeros so every part is defined
-          (is_small ? plan.small : plan.big).push_back(GemmTile{c, m0, n0, part, k0, std::max(k0, k1)});
+          plan.tiles.push_back(GemmTile{c, m0, n0, part, k0, std::max(k0, k1)});
     }
   }
   return plan;
 }
 
-hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du,
-                                 long long ps, const ClassInfo* cls,
-                                 const GemmTile* tiles_big, int nbig, const GemmTile* tiles_small,
-                                 int nsmall, int use_op, hipStream_t s, int variant) {
+hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long ps,
+                                 const ClassInfo* cls, const GemmTile* tiles, int ntiles,
+                                 bool small, int use_op, hipStream_t s, int variant) {
+  if (ntiles <= 0) return hipSuccess;
+  const dim3 grid((unsigned)ntiles), block(256);
   if (f32) {
-    if (nbig > 0 && variant == 1)
-      hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 64>), dim3(nbig), dim3(256), 0, s,
-                         (const float*)rs, (float*)du, ps, cls, tiles_big, use_op);
-    else if (nbig > 0)
-      hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 32>), dim3(nbig), dim3(256), 0, s,
-                         (const float*)rs, (float*)du, ps, cls, tiles_big, use_op);
-    if (nsmall > 0)
-      hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), dim3(nsmall), dim3(256), 0, s,
-                         (const float*)rs, (float*)du, ps, cls, tiles_small, use_op);
+    const float* a = (const float*)rs;
+    float* c = (float*)du;
+    if (small)
+      hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
+    else if (variant == 0)
+      hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 1, 4, 32>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
+    else
+      hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 32>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
   } else {
-    if (nbig > 0 && variant == 1)
-      hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 32>), dim3(nbig), dim3(256), 0, s,
-                         (const double*)rs, (double*)du, ps, cls, tiles_big, use_op);
-    else if (nbig > 0)
-      hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), dim3(nbig), dim3(256), 0, s,
-                         (const double*)rs, (double*)du, ps, cls, tiles_big, use_op);
-    if (nsmall > 0)
-      hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 2, 16>), dim3(nsmall), dim3(256), 0, s,
-                         (const double*)rs, (double*)du, ps, cls, tiles_small, use_op);
+    const double* a = (const double*)rs;
+    double* c = (double*)du;
+    if (small)
+      hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 2, 16>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
+    else if (variant == 0)
+      hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 1, 4, 16>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
+    else
+      hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
   }
   return hipGetLastError();
 }

@@ -172,9 +172,11 @@ struct Level {
   int* d_elem_class = nullptr;
   long long* d_elem_row = nullptr;
   PullEntry* d_pull = nullptr;  // scatter pull table, 7 entries per element
-  GemmTile* d_tiles_big = nullptr;
-  GemmTile* d_tiles_small = nullptr;
-  int nbig = 0, nsmall = 0;
+  // grouped subdomain GEMM: one work list per tile variant
+  GemmTile* d_tiles[kGemmVariants] = {};
+  int ntiles[kGemmVariants] = {};
+  int kparts_of[kGemmVariants] = {};
+  bool gemm_small = false;
   int kparts = 1;  // split-K factor of the class GEMMs
   int gemm_variant = 0;  // large-tile GEMM variant chosen by the autotuner
   ApplyConfig acfg;      // operator-kernel launch shape chosen by the autotuner
@@ -343,10 +345,19 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   L.rs_total = rs_off;
   L.max_n = 0;
   for (int c = 0; c < ci; ++c) L.max_n = std::max(L.max_n, L.cls[c].n);
-  const GemmPlan plan = plan_subdomain_gemm(L.cls);
-  L.kparts = plan.kparts;
-  const std::vector<GemmTile>& big = plan.big;
-  const std::vector<GemmTile>& small = plan.small;
+  int max_parts = 1;
+  for (int v = 0; v < kGemmVariants; ++v) {
+    const GemmPlan plan = plan_subdomain_gemm(L.cls, v);
+    L.gemm_small = plan.small;
+    L.kparts_of[v] = plan.kparts;
+    L.ntiles[v] = (int)plan.tiles.size();
+    L.d_tiles[v] = P->alloc<GemmTile>(plan.tiles.size());
+    upload(L.d_tiles[v], plan.tiles, s);
+    HIP_OK(hipStreamSynchronize(s));  // plan.tiles goes out of scope
+    max_parts = std::max(max_parts, plan.kparts);
+  }
+  L.gemm_variant = 0;
+  L.kparts = L.kparts_of[0];
   std::vector<long long> elem_row(L.E);
   for (long long e = 0; e < L.E; ++e)
     elem_row[e] = L.cls[elem_class[e]].rs_off + (long long)pos[e] * L.cls[elem_class[e]].n;
@@ -386,18 +397,12 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   }
   L.d_pull = P->alloc<PullEntry>(pull.size());
   upload(L.d_pull, pull, s);
-  L.nbig = (int)big.size();
-  L.nsmall = (int)small.size();
-  L.d_tiles_big = P->alloc<GemmTile>(big.size());
-  upload(L.d_tiles_big, big, s);
-  L.d_tiles_small = P->alloc<GemmTile>(small.size());
-  upload(L.d_tiles_small, small, s);
   if (L.f32) {
     L.d_rs = P->alloc<float>(L.rs_total);
-    L.d_du = P->alloc<float>(L.rs_total * L.kparts);
+    L.d_du = P->alloc<float>(L.rs_total * max_parts);
   } else {
     L.d_rs = P->alloc<double>(L.rs_total);
-    L.d_du = P->alloc<double>(L.rs_total * L.kparts);
+    L.d_du = P->alloc<double>(L.rs_total * max_parts);
   }
   // host copies of the elem tables are kept in the layouts only
   HIP_OK(hipStreamSynchronize(s));  // host vectors above go out of scope
@@ -599,6 +604,14 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 // Per-degree launch-shape autotuner of the operator kernel: time every
 // candidate elements-per-workgroup value on the finest mesh and keep the
 // fastest.  Results are cached per (N, element count) for the process.
+// The level's grouped subdomain GEMM in its tuned variant; part_stride is the
+// distance between the split-K partial products in DU.
+hipError_t gemm_level(Level& L, const void* rs, long long part_stride, int use_op, hipStream_t s) {
+  const int v = L.gemm_variant;
+  return launch_subdomain_gemm(L.f32, rs, L.d_du, part_stride, L.d_cls, L.d_tiles[v], L.ntiles[v],
+                               L.gemm_small, use_op, s, v);
+}
+
 std::mutex g_tune_mutex;
 // Elements per workgroup of the operator kernel, timed per level in the mode
 // the Schwarz steps launch most (residual with the gather written out) and
@@ -663,47 +676,64 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
   (void)hipEventDestroy(e1);
 }
 
-// K-depth of the large-tile class GEMM, timed on every level that has large
-// tiles (with that level's own tiles and buffers); cached per level shape.
-std::map<std::tuple<int, long long, int, int, int>, int> g_tuned_gemm;
+// Row-tile height of the grouped subdomain GEMM (32 or 64 subdomains, each
+// with its own split of K), timed together with the scatter that sums its
+// partial products, on every level with large tiles; cached per level shape.
+std::map<std::tuple<int, int, int, int, int, int>, int> g_tuned_gemm;
 
 void autotune_gemm(dgs_problem* P, hipStream_t s) {
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
+  const int N = P->N;
   for (Level& L : P->levels) {
-    if (L.nbig == 0) continue;
-    const auto key = std::make_tuple(P->N, L.E, (int)L.f32, P->opt.overlap, L.nbig);
+    if (L.gemm_small || L.ntiles[0] == 0) continue;  // a single variant
+    const auto key = std::make_tuple(N, L.n[0], L.n[1], L.n[2], (int)L.f32, nov_of(P));
+    int best = 0;
+    bool cached = false;
     {
       std::lock_guard<std::mutex> lk(g_tune_mutex);
       auto it = g_tuned_gemm.find(key);
       if (it != g_tuned_gemm.end()) {
-        L.gemm_variant = it->second;
-        continue;
+        best = it->second;
+        cached = true;
       }
     }
-    const size_t es = L.f32 ? sizeof(float) : sizeof(double);
-    HIP_OK(hipMemsetAsync(L.d_rs, 0, es * (size_t)L.rs_total, s));
-    float best_ms = 1e30f;
-    for (int v = 0; v < kGemmVariants; ++v) {
-      HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
-                                   nullptr, 0, 0, s, v));  // warm-up
-      HIP_OK(hipEventRecord(e0, s));
-      for (int r = 0; r < 5; ++r)
-        HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big,
-                                     L.nbig, nullptr, 0, 0, s, v));
-      HIP_OK(hipEventRecord(e1, s));
-      HIP_OK(hipEventSynchronize(e1));
-      float ms = 0;
-      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-      // a later variant must win by 3 % so near ties resolve the same way
-      if (ms < 0.97f * best_ms) {
-        best_ms = ms;
+    if (!cached) {
+      const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+      HIP_OK(hipMemsetAsync(L.d_rs, 0, es * (size_t)L.rs_total, s));
+      HIP_OK(launch_fill(L.d_u, 0.0, L.E * (long long)N * N * N, s));
+      float best_ms = 1e30f;
+      for (int v = 0; v < kGemmVariants; ++v) {
         L.gemm_variant = v;
+        L.kparts = L.kparts_of[v];
+        auto sweep = [&]() {
+          HIP_OK(gemm_level(L, L.d_rs, L.rs_total, 0, s));
+          HIP_OK(launch_scatter(N, L.f32, L.d_u, L.d_du, L.kparts, L.rs_total, L.d_weights,
+                                L.d_pull, nov_of(P), L.E, s));
+        };
+        sweep();  // warm-up
+        float tmin = 1e30f;
+        for (int trial = 0; trial < 3; ++trial) {
+          HIP_OK(hipEventRecord(e0, s));
+          for (int r = 0; r < 3; ++r) sweep();
+          HIP_OK(hipEventRecord(e1, s));
+          HIP_OK(hipEventSynchronize(e1));
+          float ms = 0;
+          HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+          tmin = std::min(tmin, ms);
+        }
+        // a later variant must win by 3 % so near ties resolve the same way
+        if (tmin < 0.97f * best_ms) {
+          best_ms = tmin;
+          best = v;
+        }
       }
+      std::lock_guard<std::mutex> lk(g_tune_mutex);
+      g_tuned_gemm[key] = best;
     }
-    std::lock_guard<std::mutex> lk(g_tune_mutex);
-    g_tuned_gemm[key] = L.gemm_variant;
+    L.gemm_variant = best;
+    L.kparts = L.kparts_of[best];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -729,11 +759,9 @@ void subdomain_gmres(dgs_problem* P, Level& L, hipStream_t s) {
   for (int j = 0; j < k; ++j) {
     void* Vj = slot(L.d_gV, j);
     void* Zj = slot(L.d_gZ, j);
-    HIP_OK(launch_subdomain_gemm(L.f32, Vj, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
-                                 L.d_tiles_small, L.nsmall, 0, s, L.gemm_variant));
+    HIP_OK(gemm_level(L, Vj, st, 0, s));
     HIP_OK(launch_reduce_parts(L.f32, Zj, L.d_du, L.kparts, st, st, s));
-    HIP_OK(launch_subdomain_gemm(L.f32, Zj, L.d_du, st, L.d_cls, L.d_tiles_big, L.nbig,
-                                 L.d_tiles_small, L.nsmall, 1, s, L.gemm_variant));
+    HIP_OK(gemm_level(L, Zj, st, 1, s));
     HIP_OK(launch_reduce_parts(L.f32, L.d_gW, L.d_du, L.kparts, st, st, s));
     HIP_OK(launch_sub_arnoldi(N, L.f32, j, k, L.d_gW, L.d_gV, Zj, st, L.d_diag, L.d_gH,
                               L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls, L.d_seg_loc, (int)L.E,
@@ -768,8 +796,7 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
                             L.E, s));
       continue;
     }
-    HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big, L.nbig,
-                                 L.d_tiles_small, L.nsmall, 0, s, L.gemm_variant));
+    HIP_OK(gemm_level(L, L.d_rs, L.rs_total, 0, s));
     // the scatter sums the split-K partials itself
     HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.kparts, L.rs_total, L.d_weights, L.d_pull,
                           nov_of(P), L.E, s));
@@ -1392,8 +1419,7 @@ int dgs_subdomain_solves(dgs_problem* prob, int level, int reps, double* flops, 
     }
     const hipStream_t s = as_stream(stream);
     for (int r = 0; r < reps; ++r)
-      HIP_OK(launch_subdomain_gemm(L.f32, L.d_rs, L.d_du, L.rs_total, L.d_cls, L.d_tiles_big,
-                                   L.nbig, L.d_tiles_small, L.nsmall, 0, s, L.gemm_variant));
+      HIP_OK(gemm_level(L, L.d_rs, L.rs_total, 0, s));
     return DGS_OK;
   });
 }
