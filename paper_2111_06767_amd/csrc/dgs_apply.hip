@@ -170,8 +170,19 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   int nb[6];
   if (active) {
     const double* ue = u + e * N3;
+    if (P.n[0] > 0) {  // box grid: no table lookup on the critical path
+      const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+      const int ie = (int)e, ex = ie % nx, ey = (ie / nx) % ny, ez = ie / (nx * ny);
+      nb[0] = ex > 0 ? ie - 1 : -1;
+      nb[1] = ex < nx - 1 ? ie + 1 : -1;
+      nb[2] = ey > 0 ? ie - nx : -1;
+      nb[3] = ey < ny - 1 ? ie + nx : -1;
+      nb[4] = ez > 0 ? ie - nx * ny : -1;
+      nb[5] = ez < nz - 1 ? ie + nx * ny : -1;
+    } else {
 #pragma unroll
-    for (int f = 0; f < 6; ++f) nb[f] = nbr[e * 6 + f];
+      for (int f = 0; f < 6; ++f) nb[f] = nbr[e * 6 + f];
+    }
     const long long xl0 = nb[0] >= 0 ? (long long)nb[0] : e;
     const long long xh0 = nb[1] >= 0 ? (long long)nb[1] : e;
 #pragma unroll

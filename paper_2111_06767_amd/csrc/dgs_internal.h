@@ -52,6 +52,9 @@ struct OpParams {
   double h[3];
   double penalty;
   int E;
+  // element grid n_x, n_y, n_z of a box (face neighbours follow from an
+  // element's position); n[0] = 0: take them from the neighbour table instead
+  int n[3];
   // derived on the host (set_derived): 2/h_d, sigma_d, lift factor 1/(h_d w_end),
   // J = h_x h_y h_z / 8
   double rh[3], sig[3], lf[3], J;
@@ -130,11 +133,13 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 // for every class c (B_c the stored transposed inverse, or with use_op the
 // stored A_S and factor scale_op).  Output tiles of BM rows (subdomains) by
 // kGemmN columns: BM = 16 when no class has more than kGemmSmallCount
-// subdomains, else 32 (variant 0) or 64 (variant 1), picked per level by the
-// set-up autotuner.  The K range is split into kparts partial products.
+// subdomains; else variant 0: BM = 32, K split in up to 4; variant 1: BM = 64,
+// up to 4; variant 2: BM = 32, up to 8 partial products (more workgroups in
+// flight, more for the scatter to sum).  The set-up autotuner picks one per
+// level.
 constexpr int kGemmN = 128, kGemmSmallCount = 32;
 constexpr int kMaxParts = 16;  // split-K partial products (1, 2, 4, 8 or 16)
-constexpr int kGemmVariants = 2;
+constexpr int kGemmVariants = 3;
 struct GemmPlan {
   std::vector<GemmTile> tiles;
   bool small = false;

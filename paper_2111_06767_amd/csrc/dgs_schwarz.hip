@@ -487,13 +487,13 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
   for (const ClassInfo& c : cls) any_big = any_big || c.count > kGemmSmallCount;
   // the few partly filled tiles of small classes run beside the large ones
   plan.small = !any_big;
-  const int bm = plan.small ? 16 : (variant == 0 ? 32 : 64);
+  const int bm = plan.small ? 16 : (variant == 1 ? 64 : 32);
   // split K until there are enough tiles to fill the 256 compute units; the
   // short K loops of few-subdomain levels are latency-bound, so they split
   // further (the scatter sums the parts)
   int base = 0;
   for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + kGemmN - 1) / kGemmN);
-  const int max_parts = plan.small ? kMaxParts : 4;
+  const int max_parts = plan.small ? kMaxParts : (variant == 2 ? 8 : 4);
   plan.kparts = 1;
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
   for (int c = 0; c < (int)cls.size(); ++c) {
@@ -522,7 +522,7 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     if (small)
       hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
-    else if (variant == 0)
+    else if (variant != 1)
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 1, 4, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
     else
@@ -534,7 +534,7 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     if (small)
       hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 2, 16>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
-    else if (variant == 0)
+    else if (variant != 1)
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 1, 4, 16>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
     else

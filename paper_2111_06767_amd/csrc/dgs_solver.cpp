@@ -265,6 +265,9 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
   L.op.h[2] = L.h[2];
   L.op.penalty = P->penalty;
   L.op.E = (int)L.E;
+  L.op.n[0] = L.n[0];
+  L.op.n[1] = L.n[1];
+  L.op.n[2] = L.n[2];
   set_derived(L.op, P->N, P->ht.w[0]);
   const std::vector<int> nbr = host_neighbors(L);
   L.d_nbr = P->alloc<int>(nbr.size());
@@ -281,8 +284,12 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
         for (int y = ty; y < std::min(ty + T, L.n[1]); ++y)
           for (int x = tx; x < std::min(tx + T, L.n[0]); ++x)
             order.push_back((int)(((long long)z * L.n[1] + y) * L.n[0] + x));
-  L.d_order = P->alloc<int>(order.size());
-  upload(L.d_order, order, s);
+  bool identity = true;
+  for (size_t i = 0; i < order.size() && identity; ++i) identity = order[i] == (int)i;
+  if (!identity) {  // the identity order needs no table (and no load)
+    L.d_order = P->alloc<int>(order.size());
+    upload(L.d_order, order, s);
+  }
   HIP_OK(hipStreamSynchronize(s));  // nbr and order go out of scope
   const long long nd = L.E * (long long)P->N * P->N * P->N;
   L.d_u = P->alloc<double>(nd);
@@ -511,6 +518,7 @@ void build_keys(dgs_problem* P, const std::vector<std::unique_ptr<CacheEntry>>& 
     HIP_OK(launch_unit_columns(d_X, stride, d_idx, n, s));
     OpParams op = ref[k]->op;
     op.E = (int)(Ep * (long long)n);
+    op.n[0] = op.n[1] = op.n[2] = 0;  // patch elements: neighbours from the table
     HIP_OK(launch_apply(N, kApply, d_X, d_AX, nullptr, nullptr, nullptr, d_nb, op, P->dt,
                         ApplyConfig{}, s));
     HIP_OK(launch_gather_columns(d_AX, stride, d_idx, n, d_batch + (size_t)k * n_pad * n_pad, n_pad, s));
@@ -676,9 +684,9 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
   (void)hipEventDestroy(e1);
 }
 
-// Row-tile height of the grouped subdomain GEMM (32 or 64 subdomains, each
-// with its own split of K), timed together with the scatter that sums its
-// partial products, on every level with large tiles; cached per level shape.
+// Tile variant of the grouped subdomain GEMM (row-tile height and K split),
+// timed together with the scatter that sums its partial products, on every
+// level with large tiles; cached per level shape.
 std::map<std::tuple<int, int, int, int, int, int>, int> g_tuned_gemm;
 
 void autotune_gemm(dgs_problem* P, hipStream_t s) {
