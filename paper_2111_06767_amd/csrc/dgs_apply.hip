@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(((EPB * N * N + 63) / 64) * 64)
 k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ bvec,
         const double* __restrict__ aux0, const double* __restrict__ aux1,
         const int* __restrict__ nbr, OpParams P, DevTables T, int mode,
-        const int* __restrict__ order, GatherOut go) {
+        const int* __restrict__ order, GatherOut go, double* __restrict__ ucopy) {
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int PIT = N + 1;  // padded row pitch (bank spread for line reads)
   constexpr int S3 = N * N * PIT;
@@ -369,6 +369,10 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       }
       rz[k] = r;
     }
+    if (ucopy) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) ucopy[e * N3 + k * N2 + t] = uz[k];
+    }
     if (!go.rs) {
 #pragma unroll
       for (int k = 0; k < N; ++k) out[e * N3 + k * N2 + t] = rz[k];
@@ -384,13 +388,13 @@ template <int N, int EPB>
 hipError_t launch_apply_t(int mode, const double* u, double* out, const double* b,
                           const double* aux0, const double* aux1, const int* nbr,
                           const OpParams& P, const DevTables& T, hipStream_t s, const int* order,
-                          const GatherOut& go) {
+                          const GatherOut& go, double* ucopy) {
   if (P.E <= 0) return hipSuccess;
   const int threads = ((EPB * N * N + 63) / 64) * 64;
   const long long need = ((long long)P.E + EPB - 1) / EPB;
   const long long blocks = ((need + 7) / 8) * 8;  // whole rounds over the 8 XCDs
   hipLaunchKernelGGL((k_apply<N, EPB>), dim3((unsigned)blocks), dim3(threads), 0, s, u, out, b,
-                     aux0, aux1, nbr, P, T, mode, order, go);
+                     aux0, aux1, nbr, P, T, mode, order, go, ucopy);
   return hipGetLastError();
 }
 
@@ -398,11 +402,11 @@ template <int N>
 hipError_t launch_apply_n(int epb, int mode, const double* u, double* out, const double* b,
                           const double* aux0, const double* aux1, const int* nbr,
                           const OpParams& P, const DevTables& T, hipStream_t s, const int* order,
-                          const GatherOut& go) {
+                          const GatherOut& go, double* ucopy) {
   constexpr int def = (N == 2) ? 64 : (256 / (N * N));  // >= 3 for every N <= 9
-  if (epb == 1) return launch_apply_t<N, 1>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-  if (epb == 2) return launch_apply_t<N, 2>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-  return launch_apply_t<N, def>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+  if (epb == 1) return launch_apply_t<N, 1>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+  if (epb == 2) return launch_apply_t<N, 2>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+  return launch_apply_t<N, def>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
 }
 
 // b = M f, M = J w_i w_j w_k
@@ -437,17 +441,17 @@ __global__ void k_coords(double* __restrict__ xyz, long long total, int N, int n
 hipError_t launch_apply(int N, int mode, const double* u, double* out, const double* b,
                         const double* aux0, const double* aux1, const int* nbr, const OpParams& P,
                         const DevTables& T, const ApplyConfig& cfg, hipStream_t s,
-                        const int* order, const GatherOut& go) {
+                        const int* order, const GatherOut& go, double* ucopy) {
   if (go.rs && (mode != kResidual && mode != kResidualDiag)) return hipErrorInvalidValue;
   switch (N) {
-    case 2: return launch_apply_n<2>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-    case 3: return launch_apply_n<3>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-    case 4: return launch_apply_n<4>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-    case 5: return launch_apply_n<5>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-    case 6: return launch_apply_n<6>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-    case 7: return launch_apply_n<7>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-    case 8: return launch_apply_n<8>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
-    case 9: return launch_apply_n<9>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go);
+    case 2: return launch_apply_n<2>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 3: return launch_apply_n<3>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 4: return launch_apply_n<4>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 5: return launch_apply_n<5>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 6: return launch_apply_n<6>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 7: return launch_apply_n<7>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 8: return launch_apply_n<8>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 9: return launch_apply_n<9>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
     default: return hipErrorInvalidValue;
   }
 }

@@ -152,11 +152,13 @@ __global__ void k_combine(double* __restrict__ x, const double* __restrict__ Z, 
   x[g] = acc;
 }
 
-__global__ void k_scale_inv_norm(double* __restrict__ y, const double* __restrict__ x,
-                                 const double* __restrict__ nrm2, long long n) {
+__global__ void k_scale_inv_norm(double* y, const double* x, const double* __restrict__ nrm2,
+                                 long long n, double* __restrict__ y2) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
-  y[g] = x[g] / sqrt(nrm2[0]);
+  const double v = x[g] / sqrt(nrm2[0]);
+  y[g] = v;
+  if (y2) y2[g] = v;
 }
 
 __global__ void k_puncture_diag(const double* __restrict__ alpha, const double* __restrict__ beta,
@@ -275,9 +277,9 @@ hipError_t launch_multi_axpy(double* w, const double* V, long long ldv, int m, c
 }
 
 hipError_t launch_scale_by_inv_norm(double* y, const double* x, const double* nrm2, long long n,
-                                    hipStream_t s) {
+                                    hipStream_t s, double* y2) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_inv_norm, dim3(nblk(n)), dim3(256), 0, s, y, x, nrm2, n);
+  hipLaunchKernelGGL(k_scale_inv_norm, dim3(nblk(n)), dim3(256), 0, s, y, x, nrm2, n, y2);
   return hipGetLastError();
 }
 

@@ -100,7 +100,8 @@ struct GatherOut {
 hipError_t launch_apply(int N, int mode, const double* u, double* out, const double* b,
                         const double* aux0, const double* aux1, const int* nbr, const OpParams& P,
                         const DevTables& T, const ApplyConfig& cfg, hipStream_t s,
-                        const int* order = nullptr, const GatherOut& go = GatherOut{});
+                        const int* order = nullptr, const GatherOut& go = GatherOut{},
+                        double* ucopy = nullptr);  // ucopy: optional copy of u
 hipError_t launch_mass(int N, const double* f, double* out, long long E, const double h[3],
                        const DevTables& T, hipStream_t s);
 hipError_t launch_coords(int N, double* xyz, const int n[3], const double lower[3],
@@ -171,9 +172,10 @@ hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride
 // split-K partial products spaced part_stride apart.
 
 // u += sum_S R_S^T (w_S du_S), summing `parts` split-K partials (1, 2, 4, 8, 16) of du.
+// assign: u = (the sum) instead of u += (the sum), for a u that starts at zero.
 hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
                           long long part_stride, const double* weights, const PullEntry* pull,
-                          int nov, long long E, hipStream_t s);
+                          int nov, long long E, hipStream_t s, bool assign = false);
 
 // Multigrid transfer (per-dimension split flags).
 hipError_t launch_restrict(int N, const double* fine, double* coarse, const int nf[3],
@@ -201,7 +203,7 @@ hipError_t launch_multi_axpy(double* w, const double* V, long long ldv, int m, c
                              long long n, hipStream_t s);
 // y = x / *nrm  (nrm on the device, the Euclidean norm squared's square root taken here)
 hipError_t launch_scale_by_inv_norm(double* y, const double* x, const double* nrm2, long long n,
-                                    hipStream_t s);
+                                    hipStream_t s, double* y2 = nullptr);  // y2: optional copy
 // x += sum_i y[i] Z_i (y on the device)
 hipError_t launch_combine(double* x, const double* Z, long long ldz, int m, const double* y,
                           long long n, hipStream_t s);

@@ -88,7 +88,7 @@ template <typename T, int PARTS>
 __global__ void __launch_bounds__(256)
 k_scatter(double* __restrict__ u, const T* __restrict__ du, long long pstride,
           const double* __restrict__ weights, const PullEntry* __restrict__ pull, int N, int nov,
-          long long total) {
+          long long total, int assign) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= total) return;
   const int N2 = N * N, N3 = N2 * N;
@@ -114,7 +114,10 @@ k_scatter(double* __restrict__ u, const T* __restrict__ du, long long pstride,
     const double v = weights[bw + k] * sum_parts<T, PARTS>(du, bd + k, pstride);
     acc += ok ? v : 0.0;
   }
-  u[g] += acc;
+  if (assign)  // u starts from zero: write instead of add (no clearing pass)
+    u[g] = acc;
+  else
+    u[g] += acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -546,22 +549,23 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
 
 template <typename T, int PARTS>
 void scatter_launch(unsigned blocks, hipStream_t s, double* u, const void* du, long long pstride,
-                    const double* weights, const PullEntry* pull, int N, int nov, long long total) {
+                    const double* weights, const PullEntry* pull, int N, int nov, long long total,
+                    int assign) {
   hipLaunchKernelGGL((k_scatter<T, PARTS>), dim3(blocks), dim3(256), 0, s, u, (const T*)du, pstride,
-                     weights, pull, N, nov, total);
+                     weights, pull, N, nov, total, assign);
 }
 
 template <typename T>
 hipError_t scatter_parts(int parts, unsigned blocks, hipStream_t s, double* u, const void* du,
                          long long pstride, const double* weights, const PullEntry* pull, int N,
-                         int nov, long long total) {
+                         int nov, long long total, int assign) {
   switch (parts) {
-    case 1: scatter_launch<T, 1>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
-    case 2: scatter_launch<T, 2>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
-    case 3: scatter_launch<T, 3>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
-    case 4: scatter_launch<T, 4>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
-    case 8: scatter_launch<T, 8>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
-    case 16: scatter_launch<T, 16>(blocks, s, u, du, pstride, weights, pull, N, nov, total); break;
+    case 1: scatter_launch<T, 1>(blocks, s, u, du, pstride, weights, pull, N, nov, total, assign); break;
+    case 2: scatter_launch<T, 2>(blocks, s, u, du, pstride, weights, pull, N, nov, total, assign); break;
+    case 3: scatter_launch<T, 3>(blocks, s, u, du, pstride, weights, pull, N, nov, total, assign); break;
+    case 4: scatter_launch<T, 4>(blocks, s, u, du, pstride, weights, pull, N, nov, total, assign); break;
+    case 8: scatter_launch<T, 8>(blocks, s, u, du, pstride, weights, pull, N, nov, total, assign); break;
+    case 16: scatter_launch<T, 16>(blocks, s, u, du, pstride, weights, pull, N, nov, total, assign); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -569,12 +573,14 @@ hipError_t scatter_parts(int parts, unsigned blocks, hipStream_t s, double* u, c
 
 hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
                           long long pstride, const double* weights, const PullEntry* pull, int nov,
-                          long long E, hipStream_t s) {
+                          long long E, hipStream_t s, bool assign) {
   const long long total = E * N * N * N;
   if (total <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)((total + 255) / 256);
-  return f32 ? scatter_parts<float>(parts, blocks, s, u, du, pstride, weights, pull, N, nov, total)
-             : scatter_parts<double>(parts, blocks, s, u, du, pstride, weights, pull, N, nov, total);
+  const int as = assign ? 1 : 0;
+  return f32 ? scatter_parts<float>(parts, blocks, s, u, du, pstride, weights, pull, N, nov, total, as)
+             : scatter_parts<double>(parts, blocks, s, u, du, pstride, weights, pull, N, nov, total,
+                                     as);
 }
 
 }  // namespace dgs

@@ -801,13 +801,13 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
     if (diag && P->opt.subdomain_iters > 0) {
       subdomain_gmres(P, L, s);
       HIP_OK(launch_scatter(N, L.f32, u, L.d_du, 1, L.rs_total, L.d_weights, L.d_pull, nov_of(P),
-                            L.E, s));
+                            L.E, s, it == 0 && u_zero));
       continue;
     }
     HIP_OK(gemm_level(L, L.d_rs, L.rs_total, 0, s));
     // the scatter sums the split-K partials itself
     HIP_OK(launch_scatter(N, L.f32, u, L.d_du, L.kparts, L.rs_total, L.d_weights, L.d_pull,
-                          nov_of(P), L.E, s));
+                          nov_of(P), L.E, s, it == 0 && u_zero));
   }
 }
 
@@ -822,7 +822,12 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s) {
     b[l] = P->levels[l].d_b;
     u[l] = P->levels[l].d_u;
   }
-  for (int l = 0; l < nl; ++l) HIP_OK(launch_fill(u[l], 0.0, P->nd(l), s));
+  // every level starts from zero: the first smoothing step writes u, so only
+  // a level without smoothing steps needs clearing
+  for (int l = 0; l < nl; ++l) {
+    const int steps = l < nl - 1 ? P->opt.pre_smooth : P->opt.pre_smooth + P->opt.post_smooth;
+    if (steps == 0) HIP_OK(launch_fill(u[l], 0.0, P->nd(l), s));
+  }
   for (int l = 0; l < nl - 1; ++l) {
     Level& L = P->levels[l];
     schwarz_steps(P, l, b[l], u[l], P->opt.pre_smooth, true, s);
@@ -845,13 +850,10 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s) {
 // kind) on an internal stream, reading level 0's right-hand-side buffer and
 // writing level 0's solution buffer, and replayed on the caller's stream with
 // one copy in and one copy out.
-void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
-  if (!P->opt.use_graphs) {
-    vcycle_eager(P, r, z, s);
-    return;
-  }
+// One captured V-cycle from the finest level's d_b into its d_u (the graph
+// for the current operator kind is captured on first use).
+void vcycle_graph(dgs_problem* P, hipStream_t s) {
   Level& L0 = P->levels[0];
-  const long long n = P->nd(0);
   const int gi = (P->diag_active && L0.d_diag) ? 1 : 0;
   if (!P->vgraph[gi]) {
     if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
@@ -870,8 +872,18 @@ void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
     (void)hipGraphDestroy(graph);
     HIP_OK(e);
   }
-  HIP_OK(launch_copy(L0.d_b, r, n, s));
   HIP_OK(hipGraphLaunch(P->vgraph[gi], s));
+}
+
+void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
+  if (!P->opt.use_graphs) {
+    vcycle_eager(P, r, z, s);
+    return;
+  }
+  Level& L0 = P->levels[0];
+  const long long n = P->nd(0);
+  HIP_OK(launch_copy(L0.d_b, r, n, s));
+  vcycle_graph(P, s);
   HIP_OK(launch_copy(z, L0.d_u, n, s));
 }
 
@@ -906,11 +918,13 @@ double device_norm2(dgs_problem* P, const double* x, long long n, hipStream_t s)
 }
 
 // Apply either A or the linearised operator A + diag(d) on the finest level.
-void apply_fine(dgs_problem* P, const double* x, double* y, hipStream_t s) {
+// xcopy (optional) receives a copy of x.
+void apply_fine(dgs_problem* P, const double* x, double* y, hipStream_t s,
+                double* xcopy = nullptr) {
   Level& L = P->levels[0];
   const bool diag = P->diag_active && L.d_diag != nullptr;
   HIP_OK(launch_apply(P->N, diag ? kApplyDiag : kApply, x, y, nullptr, L.d_diag, nullptr, L.d_nbr,
-                      L.op, P->dt, L.acfg, s, L.d_order));
+                      L.op, P->dt, L.acfg, s, L.d_order, GatherOut{}, xcopy));
 }
 
 void residual_fine(dgs_problem* P, const double* x, const double* b, double* r, hipStream_t s) {
@@ -1010,8 +1024,15 @@ struct FgmresRun {
       double* vj = V + (size_t)j * n;
       double* zj = Z + (size_t)j * n;
       double* w = V + (size_t)(j + 1) * n;
-      vcycle(P, vj, zj, s);
-      apply_fine(P, zj, w, s);
+      if (P->opt.use_graphs) {
+        // v_j is already in the V-cycle's input (written when it was
+        // normalised); the operator kernel copies the output z_j out
+        vcycle_graph(P, s);
+        apply_fine(P, P->levels[0].d_u, w, s, zj);
+      } else {
+        vcycle(P, vj, zj, s);
+        apply_fine(P, zj, w, s);
+      }
       double* h1 = P->d_h;
       double* h2 = P->d_h + (m + 2);
       double* hn = P->d_h + 2 * (m + 2);
@@ -1022,7 +1043,10 @@ struct FgmresRun {
       HIP_OK(launch_axpy_multidot(V, n, j + 1, h2, w, n, true, P->d_partial, hn, s));
       // h1, h2 and |w|^2 are contiguous on the device: one copy
       HIP_OK(hipMemcpyAsync(hp, P->d_h, sizeof(double) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, s));
-      HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));  // unused if |w| = 0 (the run stops)
+      // v_{j+1} = w / |w| (unused if |w| = 0: the run stops), also into the
+      // V-cycle's input for the next iteration
+      HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s,
+                                      P->opt.use_graphs ? P->levels[0].d_b : nullptr));
     } else if (stage == kFinish) {
       const int k = R.iterations;
       std::vector<double> y(k, 0.0);
@@ -1056,7 +1080,8 @@ struct FgmresRun {
         return;
       }
       g[0] = beta;
-      HIP_OK(launch_scale_by_inv_norm(P->d_V, P->d_V, P->d_h, P->nd(0), s));
+      HIP_OK(launch_scale_by_inv_norm(P->d_V, P->d_V, P->d_h, P->nd(0), s,
+                                      P->opt.use_graphs ? P->levels[0].d_b : nullptr));
       stage = kIter;
     } else if (stage == kIter) {
       double* col = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
