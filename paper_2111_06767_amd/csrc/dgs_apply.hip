@@ -126,12 +126,16 @@ __device__ __forceinline__ void store_subdomain_rows(const double (&rz)[N], TS* 
   }
 }
 
-template <int N, int EPB>
+// MODE is an ApplyMode; GO = 0 writes out, GO = 1 / 2 writes r_S into FP32 /
+// FP64 subdomain rows (residual modes only).  Each combination is compiled
+// separately so that it carries only its own loads, stores and registers.
+template <int N, int EPB, int MODE, int GO>
 __global__ void __launch_bounds__(((EPB * N * N + 63) / 64) * 64)
 k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ bvec,
         const double* __restrict__ aux0, const double* __restrict__ aux1,
-        const int* __restrict__ nbr, OpParams P, DevTables T, int mode,
+        const int* __restrict__ nbr, OpParams P, DevTables T,
         const int* __restrict__ order, GatherOut go, double* __restrict__ ucopy) {
+  static_assert(GO == 0 || MODE == kResidual || MODE == kResidualDiag, "gather-out mode");
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int PIT = N + 1;  // padded row pitch (bank spread for line reads)
   constexpr int S3 = N * N * PIT;
@@ -141,7 +145,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   // contributions in the second phase
   __shared__ double sU[EPB][S3], sA[EPB][S3], sB[EPB][S3];
   __shared__ double sw[N];
-  __shared__ PullEntry sPull[EPB][7];  // gather-out mode only
+  __shared__ PullEntry sPull[GO ? EPB : 1][7];  // gather-out only
 
   const int tid = threadIdx.x;
   if (tid < N) sw[tid] = T.w[tid];
@@ -158,7 +162,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   const long long e = (active && order) ? (long long)order[pos] : pos;
   const double J = P.J;
   auto L = [](int k, int j, int i) { return (k * N + j) * PIT + i; };
-  if (go.rs) {
+  if constexpr (GO != 0) {
     for (int q = tid; q < EPB * 7; q += blockDim.x) {
       const int s7 = q / 7, j7 = q - s7 * 7;
       const long long ps = (long long)blk * EPB + s7;
@@ -322,15 +326,15 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   // the right-hand side and diagonal of this lane's z-line, loaded before the
   // barrier and before any store (the gather-out stores may not be reordered
   // ahead of later loads, so loads inside the store loop would serialise)
-  double bz[N], dz[N];
+  constexpr bool need_b = MODE == kResidual || MODE == kResidualDiag || MODE == kPuncture;
+  constexpr bool need_d = MODE == kApplyDiag || MODE == kResidualDiag || MODE == kPuncture;
+  double bz[need_b ? N : 1], dz[need_d ? N : 1];
   if (active) {
-    const bool need_b = mode == kResidual || mode == kResidualDiag || mode == kPuncture;
-    const bool need_d = mode == kApplyDiag || mode == kResidualDiag || mode == kPuncture;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const long long gi = e * N3 + k * N2 + t;
-      bz[k] = need_b ? bvec[gi] : 0.0;
-      dz[k] = need_d ? aux0[gi] : 0.0;
+      if constexpr (need_b) bz[k] = bvec[gi];
+      if constexpr (need_d) dz[k] = aux0[gi];
     }
   }
   __syncthreads();
@@ -345,27 +349,17 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       if (k == 0) r -= fz[0];
       if (k == N - 1) r -= fz[1];
       const long long gi = e * N3 + k * N2 + t;
-      switch (mode) {
-        case kApply:
-          break;
-        case kResidual:
-          r = bz[k] - r;
-          break;
-        case kApplyDiag:
-          r += dz[k] * uz[k];
-          break;
-        case kResidualDiag:
-          r = bz[k] - (r + dz[k] * uz[k]);
-          break;
-        case kPuncture: {
-          const double tt = dz[k] * (1.0 + uz[k]) + 1.0;
-          const double t2 = tt * tt, t4 = t2 * t2;
-          const double S = -aux1[gi] / (t4 * t2 * tt);
-          r += jwab * T.w[k] * S - bz[k];
-          break;
-        }
-        default:
-          break;
+      if constexpr (MODE == kResidual) {
+        r = bz[k] - r;
+      } else if constexpr (MODE == kApplyDiag) {
+        r += dz[k] * uz[k];
+      } else if constexpr (MODE == kResidualDiag) {
+        r = bz[k] - (r + dz[k] * uz[k]);
+      } else if constexpr (MODE == kPuncture) {
+        const double tt = dz[k] * (1.0 + uz[k]) + 1.0;
+        const double t2 = tt * tt, t4 = t2 * t2;
+        const double S = -aux1[gi] / (t4 * t2 * tt);
+        r += jwab * T.w[k] * S - bz[k];
       }
       rz[k] = r;
     }
@@ -373,15 +367,27 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
 #pragma unroll
       for (int k = 0; k < N; ++k) ucopy[e * N3 + k * N2 + t] = uz[k];
     }
-    if (!go.rs) {
+    if constexpr (GO == 0) {
 #pragma unroll
       for (int k = 0; k < N; ++k) out[e * N3 + k * N2 + t] = rz[k];
-    } else if (go.f32) {
+    } else if constexpr (GO == 1) {
       store_subdomain_rows<float, N>(rz, (float*)go.rs, sPull[slot], a, b, go.nov);
     } else {
       store_subdomain_rows<double, N>(rz, (double*)go.rs, sPull[slot], a, b, go.nov);
     }
   }
+}
+
+template <int N, int EPB, int MODE, int GO>
+hipError_t launch_apply_k(const double* u, double* out, const double* b, const double* aux0,
+                          const double* aux1, const int* nbr, const OpParams& P, const DevTables& T,
+                          hipStream_t s, const int* order, const GatherOut& go, double* ucopy) {
+  const int threads = ((EPB * N * N + 63) / 64) * 64;
+  const long long need = ((long long)P.E + EPB - 1) / EPB;
+  const long long blocks = ((need + 7) / 8) * 8;  // whole rounds over the 8 XCDs
+  hipLaunchKernelGGL((k_apply<N, EPB, MODE, GO>), dim3((unsigned)blocks), dim3(threads), 0, s, u,
+                     out, b, aux0, aux1, nbr, P, T, order, go, ucopy);
+  return hipGetLastError();
 }
 
 template <int N, int EPB>
@@ -390,12 +396,22 @@ hipError_t launch_apply_t(int mode, const double* u, double* out, const double* 
                           const OpParams& P, const DevTables& T, hipStream_t s, const int* order,
                           const GatherOut& go, double* ucopy) {
   if (P.E <= 0) return hipSuccess;
-  const int threads = ((EPB * N * N + 63) / 64) * 64;
-  const long long need = ((long long)P.E + EPB - 1) / EPB;
-  const long long blocks = ((need + 7) / 8) * 8;  // whole rounds over the 8 XCDs
-  hipLaunchKernelGGL((k_apply<N, EPB>), dim3((unsigned)blocks), dim3(threads), 0, s, u, out, b,
-                     aux0, aux1, nbr, P, T, mode, order, go, ucopy);
-  return hipGetLastError();
+  const int gox = go.rs ? (go.f32 ? 1 : 2) : 0;
+#define DGS_APPLY(M, G) \
+  launch_apply_k<N, EPB, M, G>(u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy)
+  switch (mode) {
+    case kApply: return DGS_APPLY(kApply, 0);
+    case kApplyDiag: return DGS_APPLY(kApplyDiag, 0);
+    case kPuncture: return DGS_APPLY(kPuncture, 0);
+    case kResidual:
+      return gox == 0 ? DGS_APPLY(kResidual, 0)
+                      : (gox == 1 ? DGS_APPLY(kResidual, 1) : DGS_APPLY(kResidual, 2));
+    case kResidualDiag:
+      return gox == 0 ? DGS_APPLY(kResidualDiag, 0)
+                      : (gox == 1 ? DGS_APPLY(kResidualDiag, 1) : DGS_APPLY(kResidualDiag, 2));
+    default: return hipErrorInvalidValue;
+  }
+#undef DGS_APPLY
 }
 
 template <int N>
