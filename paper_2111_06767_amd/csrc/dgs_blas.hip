@@ -192,14 +192,16 @@ __global__ void k_gather_columns(const double* __restrict__ AX, long long stride
 }
 
 // out[k * n + row] = scale * Ainv[row * n_pad + k]  (transpose, FP64 and FP32)
-__global__ void k_finish_inverse(const double* __restrict__ Ainv, int n_pad, int n, double scale,
-                                 double* __restrict__ out64, float* __restrict__ out32) {
+__global__ void k_finish_inverse(const double* __restrict__ Ainv, int n_pad, int n, int ld,
+                                 double scale, double* __restrict__ out64,
+                                 float* __restrict__ out32) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= (long long)n * n) return;
   const int k = (int)(g / n), row = (int)(g - (long long)k * n);
   const double v = scale * Ainv[(long long)row * n_pad + k];
-  if (out64) out64[g] = v;
-  if (out32) out32[g] = (float)v;
+  const long long o = (long long)k * ld + row;
+  if (out64) out64[o] = v;
+  if (out32) out32[o] = (float)v;
 }
 
 __global__ void k_scale_copy(const double* __restrict__ A, int n_pad, int n, double scale,
@@ -317,11 +319,11 @@ hipError_t launch_gather_columns(const double* AX, long long copy_stride, const 
   return hipGetLastError();
 }
 
-hipError_t launch_finish_inverse(const double* Ainv, int n_pad, int n, double scale, double* out64,
-                                 float* out32, hipStream_t s) {
+hipError_t launch_finish_inverse(const double* Ainv, int n_pad, int n, int ld, double scale,
+                                 double* out64, float* out32, hipStream_t s) {
   const long long tot = (long long)n * n;
   if (tot <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finish_inverse, dim3(nblk(tot)), dim3(256), 0, s, Ainv, n_pad, n, scale,
+  hipLaunchKernelGGL(k_finish_inverse, dim3(nblk(tot)), dim3(256), 0, s, Ainv, n_pad, n, ld, scale,
                      out64, out32);
   return hipGetLastError();
 }

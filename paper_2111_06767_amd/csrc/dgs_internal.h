@@ -75,6 +75,8 @@ struct ApplyConfig {
   int epb = 0;  // 0 = default for N
 };
 
+constexpr int kGemmLd = 128, kGemmRows = 64;
+
 // Pull table of the weighted scatter, 7 entries per element: entry 0 is the
 // element's own subdomain, entry 1 + f the subdomain of its face-f neighbour.
 struct PullEntry {
@@ -111,11 +113,17 @@ hipError_t launch_coords(int N, double* xyz, const int n[3], const double lower[
 struct ClassInfo {
   int n;            // subdomain size n_S
   int count;        // number of subdomains (elements) in the class
+  // Padded storage, zero outside the n x n / count x n values, so that the
+  // class GEMM reads whole 16-byte vectors without bounds checks:
+  int ld;           // row stride of the class's RS / DU rows and of its stored
+                    // matrices: n rounded up to a multiple of kGemmLd
+  int rows;         // RS / DU rows reserved: count rounded up to kGemmRows
+  int kext;         // K extent of the products: n rounded up to 32
   const void* inv;    // stored transposed inverse (n x n, level precision)
   const void* op;     // stored transposed subdomain operator A_S (level precision)
   double scale;       // factor applied to the stored inverse for this level
   double scale_op;    // factor applied to the stored A_S for this level
-  long long rs_off;   // offset of this class's [count][n] block in RS / DU
+  long long rs_off;   // offset of this class's [rows][ld] block in RS / DU
   int layout_off;     // offset into seg_loc / weights
   int strip_off[6];   // offset of each face strip in the layout, -1 if absent
 };
@@ -225,8 +233,10 @@ hipError_t launch_unit_columns(double* X, long long copy_stride, const int* idx,
                                hipStream_t s);
 hipError_t launch_gather_columns(const double* AX, long long copy_stride, const int* idx, int n,
                                  double* A, int n_pad, hipStream_t s);
-hipError_t launch_finish_inverse(const double* Ainv, int n_pad, int n, double scale, double* out64,
-                                 float* out32, hipStream_t s);
+// out[k * ld + row] = scale * Ainv[row * n_pad + k] for row, k < n (the
+// transposed matrix, in a caller-zeroed ld x ld array)
+hipError_t launch_finish_inverse(const double* Ainv, int n_pad, int n, int ld, double scale,
+                                 double* out64, float* out32, hipStream_t s);
 hipError_t launch_scale_copy(const double* A, int n_pad, int n, double scale, double* out64,
                              float* out32, hipStream_t s);
 

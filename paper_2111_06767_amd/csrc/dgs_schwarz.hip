@@ -160,17 +160,23 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
            const GemmTile* __restrict__ tiles, int use_op) {
   constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
   // LDS row paddings: the MFMA operand reads touch 16 lanes per row and 2 (FP32)
-  // or 1 (FP64) rows per LDS cycle; row strides of 36 / 144 words (FP32) put
-  // those row groups on disjoint banks, an odd stride does it for FP64 A rows
-  constexpr int PA = sizeof(T) == 4 ? 4 : 1, PB = sizeof(T) == 4 ? 16 : 8;
-  constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
-  static_assert(NA >= 1 && NB >= 1 && (BM * BK) % 256 == 0 && (BK * BN) % 256 == 0, "tile");
+  // or 1 (FP64) rows per LDS cycle; row strides of 36 / 144 floats (FP32) and
+  // 18 / 136 doubles (FP64) put those row groups on disjoint banks and keep
+  // every row 16-byte aligned for vector stores
+  constexpr int PA = sizeof(T) == 4 ? 4 : 2, PB = sizeof(T) == 4 ? 16 : 8;
+  // tiles move as 16-byte vectors: the class blocks are padded (zero outside
+  // the values) so that no load needs a bounds check
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(VW)));
+  constexpr int AV = BM * BK / VW, BV = BK * BN / VW;
+  constexpr int NAV = (AV + 255) / 256, NBV = BV / 256;
+  static_assert(BV % 256 == 0 && BK % VW == 0, "tile");
   typedef typename Mfma<T>::v4 v4;
-  __shared__ T As[BM][BK + PA];  // row-major like RS: coalesced, conflict-free stores
-  __shared__ T Bs[BK][BN + PB];
+  __shared__ __attribute__((aligned(16))) T As[BM][BK + PA];  // row-major like RS
+  __shared__ __attribute__((aligned(16))) T Bs[BK][BN + PB];
   const GemmTile tl = tiles[blockIdx.x];
   const ClassInfo ci = cls[tl.cls];
-  const int n = ci.n, M = ci.count;
+  const int ld = ci.ld;
   const T* A = rs + ci.rs_off;
   const T* B = (const T*)(use_op ? ci.op : ci.inv);
   T* C = du + tl.part * pstride + ci.rs_off;
@@ -183,32 +189,38 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
 #pragma unroll
     for (int b = 0; b < TN; ++b) acc[a][b] = v4{0, 0, 0, 0};
 
-  T ra[NA], rb[NB];
+  vec ra[NAV], rb[NBV];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + 256 * q;
-      const int row = m0 + e / BK, col = k0 + e % BK;
-      ra[q] = (row < M && col < kend) ? A[(long long)row * n + col] : (T)0;
+    for (int q = 0; q < NAV; ++q) {
+      const int idx = tid + 256 * q;
+      if (AV % 256 == 0 || idx < AV) {
+        const int r = idx / (BK / VW), c = idx % (BK / VW);
+        ra[q] = *(const vec*)(A + (long long)(m0 + r) * ld + k0 + c * VW);
+      }
     }
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = tid + 256 * q;
-      const int kr = k0 + e / BN, col = n0 + e % BN;
-      rb[q] = (kr < kend && col < n) ? B[(long long)kr * n + col] : (T)0;
+    for (int q = 0; q < NBV; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / (BN / VW), c = idx % (BN / VW);
+      rb[q] = *(const vec*)(B + (long long)(k0 + r) * ld + n0 + c * VW);
     }
   };
-  load(kbeg);
+  if (kbeg < kend) load(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int e = tid + 256 * q;
-      As[e / BK][e % BK] = ra[q];
+    for (int q = 0; q < NAV; ++q) {
+      const int idx = tid + 256 * q;
+      if (AV % 256 == 0 || idx < AV) {
+        const int r = idx / (BK / VW), c = idx % (BK / VW);
+        *(vec*)&As[r][c * VW] = ra[q];
+      }
     }
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = tid + 256 * q;
-      Bs[e / BN][e % BN] = rb[q];
+    for (int q = 0; q < NBV; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / (BN / VW), c = idx % (BN / VW);
+      *(vec*)&Bs[r][c * VW] = rb[q];
     }
     __syncthreads();
     if (k0 + BK < kend) load(k0 + BK);
@@ -227,6 +239,8 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
     }
     __syncthreads();
   }
+  // the tile lies inside the padded class block: padding rows and columns
+  // receive zeros (their operands are zero)
   const T sc = (T)(use_op ? ci.scale_op : ci.scale);
 #pragma unroll
   for (int a = 0; a < TM; ++a)
@@ -236,7 +250,7 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
         const int col = n0 + (wn * TN + b) * 16 + (lane & 15);
-        if (row < M && col < n) C[(long long)row * n + col] = sc * acc[a][b][r];
+        C[(long long)row * ld + col] = sc * acc[a][b][r];
       }
 }
 
@@ -501,10 +515,11 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
   for (int c = 0; c < (int)cls.size(); ++c) {
     const ClassInfo& I = cls[c];
-    // K chunks in multiples of 32 so FP32 and FP64 tiles both stay aligned
-    const int chunk = ((I.n + plan.kparts - 1) / plan.kparts + 31) / 32 * 32;
+    // K runs over the padded extent in chunks of whole 32-wide steps (FP32 and
+    // FP64 tiles both stay aligned)
+    const int chunk = ((I.kext + plan.kparts - 1) / plan.kparts + 31) / 32 * 32;
     for (int part = 0; part < plan.kparts; ++part) {
-      const int k0 = part * chunk, k1 = std::min(I.n, (part + 1) * chunk);
+      const int k0 = part * chunk, k1 = std::min(I.kext, (part + 1) * chunk);
       for (int m0 = 0; m0 < I.count; m0 += bm)
         for (int n0 = 0; n0 < I.n; n0 += kGemmN)
           // an empty K range still writes zeros so every part is defined

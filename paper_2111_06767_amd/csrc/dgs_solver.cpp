@@ -338,6 +338,9 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
     const ClassLayout& lay = L.layouts[c];
     I.n = lay.n;
     I.count = count[c];
+    I.ld = (lay.n + kGemmLd - 1) / kGemmLd * kGemmLd;
+    I.rows = (count[c] + kGemmRows - 1) / kGemmRows * kGemmRows;
+    I.kext = (lay.n + 31) / 32 * 32;
     I.inv = nullptr;  // set once the inverses exist
     I.op = nullptr;
     I.scale = 1.0;
@@ -347,7 +350,7 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
     for (int f = 0; f < 6; ++f) I.strip_off[f] = lay.strip_off[f];
     seg_loc.insert(seg_loc.end(), lay.seg_loc.begin(), lay.seg_loc.end());
     weights.insert(weights.end(), lay.weights.begin(), lay.weights.end());
-    rs_off += (long long)lay.n * count[c];
+    rs_off += (long long)I.ld * I.rows;
   }
   L.rs_total = rs_off;
   L.max_n = 0;
@@ -367,7 +370,7 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   L.kparts = L.kparts_of[0];
   std::vector<long long> elem_row(L.E);
   for (long long e = 0; e < L.E; ++e)
-    elem_row[e] = L.cls[elem_class[e]].rs_off + (long long)pos[e] * L.cls[elem_class[e]].n;
+    elem_row[e] = L.cls[elem_class[e]].rs_off + (long long)pos[e] * L.cls[elem_class[e]].ld;
   L.d_cls = P->alloc<ClassInfo>(ci);
   upload(L.d_cls, L.cls, s);
   L.d_seg_loc = P->alloc<int>(seg_loc.size());
@@ -404,13 +407,12 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   }
   L.d_pull = P->alloc<PullEntry>(pull.size());
   upload(L.d_pull, pull, s);
-  if (L.f32) {
-    L.d_rs = P->alloc<float>(L.rs_total);
-    L.d_du = P->alloc<float>(L.rs_total * max_parts);
-  } else {
-    L.d_rs = P->alloc<double>(L.rs_total);
-    L.d_du = P->alloc<double>(L.rs_total * max_parts);
-  }
+  // the padding of the subdomain rows is never written and must read as zero
+  const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+  L.d_rs = P->alloc<char>(es * (size_t)L.rs_total);
+  L.d_du = P->alloc<char>(es * (size_t)L.rs_total * max_parts);
+  HIP_OK(hipMemsetAsync(L.d_rs, 0, es * (size_t)L.rs_total, s));
+  HIP_OK(hipMemsetAsync(L.d_du, 0, es * (size_t)L.rs_total * max_parts, s));
   // host copies of the elem tables are kept in the layouts only
   HIP_OK(hipStreamSynchronize(s));  // host vectors above go out of scope
 }
@@ -429,7 +431,7 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
 struct CacheEntry {
   int device, N, nov, flags;
   double ry, rz, penalty, hx;  // key and the reference width along x
-  int n;
+  int n, ld;
   double* inv64 = nullptr;
   float* inv32 = nullptr;
   double* op64 = nullptr;
@@ -528,13 +530,18 @@ void build_keys(dgs_problem* P, const std::vector<std::unique_ptr<CacheEntry>>& 
   for (int k = 0; k < nk; ++k) {
     CacheEntry& c = *todo[k];
     c.n = klay[k].n;
-    const size_t nn = (size_t)c.n * c.n;
+    c.ld = (c.n + kGemmLd - 1) / kGemmLd * kGemmLd;
+    const size_t nn = (size_t)c.ld * c.ld;  // zero-padded to ld x ld
     c.op64 = dalloc<double>(nn);
     c.op32 = dalloc<float>(nn);
     c.inv64 = dalloc<double>(nn);
     c.inv32 = dalloc<float>(nn);
-    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, c.n, 1.0, c.op64,
-                                 c.op32, s));
+    HIP_OK(hipMemsetAsync(c.op64, 0, nn * sizeof(double), s));
+    HIP_OK(hipMemsetAsync(c.op32, 0, nn * sizeof(float), s));
+    HIP_OK(hipMemsetAsync(c.inv64, 0, nn * sizeof(double), s));
+    HIP_OK(hipMemsetAsync(c.inv32, 0, nn * sizeof(float), s));
+    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, c.n, c.ld, 1.0,
+                                 c.op64, c.op32, s));
   }
   double* d_P = dalloc<double>((size_t)nk * 64 * 64);
   std::unique_ptr<void, void (*)(void*)> g6(d_P, [](void* p) { (void)hipFree(p); });
@@ -545,8 +552,8 @@ void build_keys(dgs_problem* P, const std::vector<std::unique_ptr<CacheEntry>>& 
   HIP_OK(launch_block_inverse(d_batch, n_pad, nk, d_P, d_R, d_C, s));
   for (int k = 0; k < nk; ++k) {
     CacheEntry& c = *todo[k];
-    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, c.n, 1.0, c.inv64,
-                                 c.inv32, s));
+    HIP_OK(launch_finish_inverse(d_batch + (size_t)k * n_pad * n_pad, n_pad, c.n, c.ld, 1.0,
+                                 c.inv64, c.inv32, s));
   }
   HIP_OK(hipStreamSynchronize(s));
 }
@@ -951,6 +958,9 @@ void set_diagonal(dgs_problem* P, const double* d, hipStream_t s) {
       L.d_gV = P->alloc<char>(es * (size_t)L.rs_total * (k + 1));
       L.d_gZ = P->alloc<char>(es * (size_t)L.rs_total * k);
       L.d_gW = P->alloc<char>(es * (size_t)L.rs_total);
+      // the GEMMs read the row padding of the bases: it must be zero
+      HIP_OK(hipMemsetAsync(L.d_gV, 0, es * (size_t)L.rs_total * (k + 1), s));
+      HIP_OK(hipMemsetAsync(L.d_gZ, 0, es * (size_t)L.rs_total * k, s));
       L.d_gH = P->alloc<double>((size_t)L.E * (k + 1) * k);
       L.d_gbeta = P->alloc<double>(L.E);
       L.gk = k;
