@@ -40,12 +40,12 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 MEASURED_TRAFFIC = {
     "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
-                       "sha256": "bfd9dda9e9f60d6c9c680e09915dd34869e963589c47c9af42e5bc5635a88690",
-                       "bytes": 55610341},
+                       "sha256": "acbb470d24b5256f845ad4920d91d6039e1029da1d9c9be4f909b11c280fd046",
+                       "bytes": 65640243},
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
-              "sha256": "b9039f01922400995d344d45092b02708edaf5dd16920e447748c608e85ef1cb",
-              "bytes": 635274918},
+              "sha256": "6b6347979dcc519e55bbca6d7433e9455ee9c164a42d82a826956a3d61748b8d",
+              "bytes": 633190960},
 }
 
 

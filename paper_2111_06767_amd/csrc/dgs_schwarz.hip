@@ -510,7 +510,7 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
   // further (the scatter sums the parts)
   int base = 0;
   for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + kGemmN - 1) / kGemmN);
-  const int max_parts = plan.small ? kMaxParts : (variant == 2 ? 8 : 4);
+  const int max_parts = plan.small ? kMaxParts : 4;
   plan.kparts = 1;
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
   for (int c = 0; c < (int)cls.size(); ++c) {
@@ -540,7 +540,7 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     if (small)
       hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
-    else if (variant != 1)
+    else if (variant == 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 1, 4, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
     else
@@ -552,7 +552,7 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     if (small)
       hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 2, 16>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
-    else if (variant != 1)
+    else if (variant == 0)
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 1, 4, 16>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
     else
