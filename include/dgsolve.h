@@ -179,13 +179,17 @@ int dgs_lgl_nodes(int p, double* xi);
  * dgs_server_step admits what fits and advances every active request by one
  * FGMRES stage, each on its own stream, so requests overlap on the device;
  * a request's arithmetic is the same alone or in a mix (dgs_solve on the same
- * inputs gives the same bits).  Single-threaded use. */
+ * inputs gives the same bits).  The server_* calls come from one caller thread
+ * at a time; the server's own worker threads share the stage work. */
 typedef struct dgs_server dgs_server;
 typedef struct {
   double hbm_budget_bytes; /* admission limit on the summed request footprints      */
   int max_active;          /* at most this many requests on the device at once      */
   double penalty;          /* C of every request                                    */
   dgs_options solver;      /* options of every request                              */
+  int host_threads;        /* worker threads that issue and complete the active
+                              requests' stages in parallel (launching is
+                              host-bound for small requests); 0 = 4              */
 } dgs_server_options;
 
 int dgs_server_create(const dgs_server_options* opt, dgs_server** out);

@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_double), ("max_active", ctypes.c_int),
-                ("penalty", ctypes.c_double), ("solver", Options)]
+                ("penalty", ctypes.c_double), ("solver", Options), ("host_threads", ctypes.c_int)]
 
 
 class DgsError(RuntimeError):
@@ -300,13 +300,15 @@ def points(lower, upper, elements, p):
 class Server:
     """Continuous-batching solve server (see dgs_server_* in include/dgsolve.h)."""
 
-    def __init__(self, hbm_budget_bytes=64e9, max_active=16, penalty=1.5, **solver_opts):
+    def __init__(self, hbm_budget_bytes=64e9, max_active=16, penalty=1.5, host_threads=0,
+                 **solver_opts):
         lib = load_library()
         self._lib = lib
         o = ServerOptions()
         o.hbm_budget_bytes = float(hbm_budget_bytes)
         o.max_active = int(max_active)
         o.penalty = float(penalty)
+        o.host_threads = int(host_threads)
         o.solver = default_options(**solver_opts)
         h = ctypes.c_void_p()
         _check(lib.dgs_server_create(ctypes.byref(o), ctypes.byref(h)))

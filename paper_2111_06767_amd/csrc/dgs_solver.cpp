@@ -14,11 +14,15 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <condition_variable>
 #include <cstring>
+#include <exception>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -1207,8 +1211,81 @@ struct ServerRequest {
 
 }  // namespace
 
+namespace {
+
+// Persistent worker threads bound to one device: run(f) calls f(w) on every
+// worker w = 0..n-1 in parallel and returns when all are done, rethrowing the
+// first exception a worker raised.
+class WorkerPool {
+ public:
+  WorkerPool(int n, int device) : errors_(n) {
+    for (int w = 0; w < n; ++w) threads_.emplace_back([this, w, device] { loop(w, device); });
+  }
+  ~WorkerPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      quit_ = true;
+    }
+    cv_start_.notify_all();
+    for (auto& t : threads_) t.join();
+  }
+  int size() const { return (int)threads_.size(); }
+  void run(const std::function<void(int)>& f) {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      task_ = f;
+      pending_ = (int)threads_.size();
+      ++generation_;
+    }
+    cv_start_.notify_all();
+    std::unique_lock<std::mutex> lk(m_);
+    cv_done_.wait(lk, [this] { return pending_ == 0; });
+    for (auto& e : errors_)
+      if (e) {
+        std::exception_ptr first = e;
+        for (auto& x : errors_) x = nullptr;
+        std::rethrow_exception(first);
+      }
+  }
+
+ private:
+  void loop(int w, int device) {
+    (void)hipSetDevice(device);
+    long long seen = 0;
+    for (;;) {
+      std::function<void(int)> f;
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_start_.wait(lk, [&] { return quit_ || generation_ != seen; });
+        if (quit_) return;
+        seen = generation_;
+        f = task_;
+      }
+      try {
+        f(w);
+      } catch (...) {
+        errors_[w] = std::current_exception();
+      }
+      std::lock_guard<std::mutex> lk(m_);
+      if (--pending_ == 0) cv_done_.notify_one();
+    }
+  }
+  std::vector<std::thread> threads_;
+  std::vector<std::exception_ptr> errors_;
+  std::mutex m_;
+  std::condition_variable cv_start_, cv_done_;
+  std::function<void(int)> task_;
+  long long generation_ = 0;
+  int pending_ = 0;
+  bool quit_ = false;
+};
+
+}  // namespace
+
 struct dgs_server {
   dgs_server_options opt{};
+  int device = 0;
+  std::unique_ptr<WorkerPool> pool;  // launching is host-bound: stages run in parallel
   long long next_id = 1;
   size_t used = 0;
   std::vector<std::unique_ptr<ServerRequest>> queue, active;
@@ -1216,6 +1293,7 @@ struct dgs_server {
   std::vector<hipStream_t> free_streams;
   double t0 = 0;
   ~dgs_server() {
+    pool.reset();
     for (auto& r : active) {
       if (r->prob) delete r->prob;
       if (r->d_b) (void)hipFree(r->d_b);
@@ -1615,10 +1693,14 @@ int dgs_server_create(const dgs_server_options* opt, dgs_server** out) {
     if (!opt || !out) return fail(DGS_ERR_INVALID, "NULL argument");
     if (opt->max_active < 1 || !(opt->hbm_budget_bytes > 0) || !(opt->penalty > 0))
       return fail(DGS_ERR_INVALID, "invalid server options");
-    dgs_server* S = new dgs_server();
+    if (opt->host_threads < 0) return fail(DGS_ERR_INVALID, "host_threads must be >= 0");
+    std::unique_ptr<dgs_server> S(new dgs_server());
     S->opt = *opt;
     S->t0 = now_s();
-    *out = S;
+    HIP_OK(hipGetDevice(&S->device));
+    const int threads = std::min(opt->host_threads > 0 ? opt->host_threads : 4, opt->max_active);
+    if (threads > 1) S->pool.reset(new WorkerPool(threads, S->device));
+    *out = S.release();
     return DGS_OK;
   });
 }
@@ -1661,12 +1743,22 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
   return guarded([&]() -> int {
     if (!S) return fail(DGS_ERR_INVALID, "NULL argument");
     server_admit(S);
-    for (auto& r : S->active) r->run.issue();
-    std::vector<std::unique_ptr<ServerRequest>> still;
-    for (auto& r : S->active) {
-      HIP_OK(hipStreamSynchronize(r->stream));
-      r->run.complete();
+    // each worker issues the next stage of every W-th request, then waits for
+    // those and completes them on the host (requests never share state)
+    auto work = [S](size_t first, size_t stride) {
+      for (size_t i = first; i < S->active.size(); i += stride) S->active[i]->run.issue();
+      for (size_t i = first; i < S->active.size(); i += stride) {
+        HIP_OK(hipStreamSynchronize(S->active[i]->stream));
+        S->active[i]->run.complete();
+      }
+    };
+    if (S->pool && S->active.size() > 1) {
+      const size_t W = (size_t)S->pool->size();
+      S->pool->run([&work, W](int w) { work((size_t)w, W); });
+    } else {
+      work(0, 1);
     }
+    std::vector<std::unique_ptr<ServerRequest>> still;
     for (auto& r : S->active) {
       if (r->run.done())
         server_retire(S, std::move(r));

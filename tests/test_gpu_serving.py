@@ -30,11 +30,15 @@ def _alone(elements, p, side, f, **opts):
     return to_np(u), st
 
 
+@pytest.mark.parametrize("host_threads", [1, 3])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_mix_equals_alone(precision):
+def test_mix_equals_alone(precision, host_threads):
+    """Requests advanced by one host thread, or by three worker threads
+    sharing the stages, give the bits of a solo solve."""
     import paper_2111_06767_amd as dg
-    announce(f"serving mix vs alone {precision}")
-    srv = dg.Server(hbm_budget_bytes=32e9, max_active=4, precision=precision, max_iter=60)
+    announce(f"serving mix vs alone {precision} host_threads={host_threads}")
+    srv = dg.Server(hbm_budget_bytes=32e9, max_active=4, precision=precision, max_iter=60,
+                    host_threads=host_threads)
     ids = {}
     for i, (el, p, side) in enumerate(REQS):
         f = _f(el, p, side, 1000 + i)
