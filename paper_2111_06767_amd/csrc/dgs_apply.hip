@@ -170,7 +170,11 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
     }
   }
 
-  double uz[N], zlo[N], zhi[N], ylo[N], yhi[N];
+  // uz: the lane's z-line; yf / zf: trace and normal derivative of the y / z
+  // neighbours on the shared faces (index side * 2 + {trace, derivative}),
+  // reduced from their lines as soon as they arrive so the lines do not stay
+  // in registers through the forward phase
+  double uz[N], yf[4], zf[4];
   int nb[6];
   if (active) {
     const double* ue = u + e * N3;
@@ -203,6 +207,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
     const long long yh = nb[3] >= 0 ? (long long)nb[3] : e;
     const long long zl = nb[4] >= 0 ? (long long)nb[4] : e;
     const long long zh = nb[5] >= 0 ? (long long)nb[5] : e;
+    double ylo[N], yhi[N], zlo[N], zhi[N];
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       ylo[m] = u[yl * N3 + b * N2 + m * N + a];
@@ -210,6 +215,10 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       zlo[m] = u[zl * N3 + m * N2 + t];
       zhi[m] = u[zh * N3 + m * N2 + t];
     }
+    face_from_line<N>(ylo, 0, P.rh[1], T, yf[0], yf[1]);
+    face_from_line<N>(yhi, 1, P.rh[1], T, yf[2], yf[3]);
+    face_from_line<N>(zlo, 0, P.rh[2], T, zf[0], zf[1]);
+    face_from_line<N>(zhi, 1, P.rh[2], T, zf[2], zf[3]);
   }
   __syncthreads();
 
@@ -262,13 +271,8 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         const double sg = side ? 1.0 : -1.0;
         const bool has = nb[2 + side] >= 0;
         const double ui = line[je], gi = g[je];
-        double ue, ge;
-        if (side)
-          face_from_line<N>(yhi, 1, P.rh[1], T, ue, ge);
-        else
-          face_from_line<N>(ylo, 0, P.rh[1], T, ue, ge);
-        ue = has ? ue : -ui;
-        ge = has ? ge : gi;
+        const double ue = has ? yf[2 * side] : -ui;
+        const double ge = has ? yf[2 * side + 1] : gi;
         fy[side] = jwab * P.rh[1] * (0.5 * sg * (gi + ge) - P.sig[1] * (ui - ue));
         g[je] += P.lf[1] * sg * (ue - ui);
       }
@@ -287,13 +291,8 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         const double sg = side ? 1.0 : -1.0;
         const double ui = uz[ke], gi = g[ke];
         const bool has = nb[4 + side] >= 0;
-        double ue, ge;
-        if (side)
-          face_from_line<N>(zhi, 1, P.rh[2], T, ue, ge);
-        else
-          face_from_line<N>(zlo, 0, P.rh[2], T, ue, ge);
-        ue = has ? ue : -ui;
-        ge = has ? ge : gi;
+        const double ue = has ? zf[2 * side] : -ui;
+        const double ge = has ? zf[2 * side + 1] : gi;
         fz[side] = jwab * P.rh[2] * (0.5 * sg * (gi + ge) - P.sig[2] * (ui - ue));
         g[ke] += P.lf[2] * sg * (ue - ui);
       }

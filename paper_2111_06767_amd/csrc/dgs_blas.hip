@@ -153,12 +153,22 @@ __global__ void k_combine(double* __restrict__ x, const double* __restrict__ Z, 
 }
 
 __global__ void k_scale_inv_norm(double* y, const double* x, const double* __restrict__ nrm2,
-                                 long long n, double* __restrict__ y2) {
+                                 long long n, double* __restrict__ y2, int N, GatherOut go) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const double v = x[g] / sqrt(nrm2[0]);
   y[g] = v;
   if (y2) y2[g] = v;
+  if (go.rs) {  // the finest level's r_S rows for the first smoothing step
+    const int N3 = N * N * N;
+    const long long e = g / N3;
+    const int loc = (int)(g - e * N3);
+    const int i = loc % N, j = (loc / N) % N, k = loc / (N * N);
+    if (go.f32)
+      gather_out_point<float>((float*)go.rs, go.pull + e * 7, N, go.nov, i, j, k, v);
+    else
+      gather_out_point<double>((double*)go.rs, go.pull + e * 7, N, go.nov, i, j, k, v);
+  }
 }
 
 __global__ void k_puncture_diag(const double* __restrict__ alpha, const double* __restrict__ beta,
@@ -279,9 +289,10 @@ hipError_t launch_multi_axpy(double* w, const double* V, long long ldv, int m, c
 }
 
 hipError_t launch_scale_by_inv_norm(double* y, const double* x, const double* nrm2, long long n,
-                                    hipStream_t s, double* y2) {
+                                    hipStream_t s, double* y2, int N, const GatherOut& go) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scale_inv_norm, dim3(nblk(n)), dim3(256), 0, s, y, x, nrm2, n, y2);
+  if (go.rs && N < 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scale_inv_norm, dim3(nblk(n)), dim3(256), 0, s, y, x, nrm2, n, y2, N, go);
   return hipGetLastError();
 }
 

@@ -87,6 +87,33 @@ struct PullEntry {
                  // first / second transverse index (the neighbour is mirrored there)
 };
 
+// Write the value v of point (i, j, k) of an element into the subdomain rows
+// that hold it: the element's own row (pe[0], mirrored into its class frame)
+// and the overlap strips of its face neighbours' subdomains (pe[1 + f]), at
+// the offsets of the scatter's pull table (the transpose of its reads).
+template <typename TS>
+__device__ __forceinline__ void gather_out_point(TS* rs, const PullEntry* pe, int N, int nov,
+                                                 int i, int j, int k, double v) {
+  const int N2 = N * N;
+  const PullEntry own = pe[0];
+  const int mi = (own.flip & 1) ? N - 1 - i : i;
+  const int mj = (own.flip & 2) ? N - 1 - j : j;
+  const int mk = (own.flip & 4) ? N - 1 - k : k;
+  rs[own.du + (mk * N + mj) * N + mi] = (TS)v;
+  const int idx[3] = {i, j, k};
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const PullEntry q = pe[1 + f];
+    const int d = f >> 1;
+    const int layer = (f & 1) ? N - 1 - idx[d] : idx[d];
+    if (q.du < 0 || layer >= nov) continue;
+    int t0 = d == 0 ? j : i, t1 = d == 2 ? j : k;
+    if (q.flip & 1) t0 = N - 1 - t0;
+    if (q.flip & 2) t1 = N - 1 - t1;
+    rs[q.du + layer * N2 + t1 * N + t0] = (TS)v;
+  }
+}
+
 // Residual modes only: instead of r, write r_S = R_S r for every subdomain
 // (the element's own row and its points in the face neighbours' overlap
 // strips, located through the scatter's pull table) into the gather block rs.
@@ -185,7 +212,8 @@ hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
 
 // Multigrid transfer (per-dimension split flags).
 hipError_t launch_restrict(int N, const double* fine, double* coarse, const int nf[3],
-                           const int nc[3], const int split[3], const DevTables& T, hipStream_t s);
+                           const int nc[3], const int split[3], const DevTables& T, hipStream_t s,
+                           const GatherOut& go = GatherOut{});  // go: also the coarse r_S rows
 hipError_t launch_prolongate_add(int N, const double* coarse, double* fine, const int nf[3],
                                  const int nc[3], const int split[3], const DevTables& T,
                                  hipStream_t s);
@@ -207,9 +235,12 @@ hipError_t launch_axpy_multidot(const double* V, long long ldv, int m, const dou
 // w -= sum_i coef[i] * V_i  (coef on the device, scaled by `sign`)
 hipError_t launch_multi_axpy(double* w, const double* V, long long ldv, int m, const double* coef,
                              long long n, hipStream_t s);
-// y = x / *nrm  (nrm on the device, the Euclidean norm squared's square root taken here)
+// y = x / sqrt(*nrm2); y2 (optional) receives a copy; with go.rs the values
+// are also written into the finest level's subdomain rows (N points per
+// dimension, go.pull of that level).
 hipError_t launch_scale_by_inv_norm(double* y, const double* x, const double* nrm2, long long n,
-                                    hipStream_t s, double* y2 = nullptr);  // y2: optional copy
+                                    hipStream_t s, double* y2 = nullptr, int N = 0,
+                                    const GatherOut& go = GatherOut{});  // y2: optional copy
 // x += sum_i y[i] Z_i (y on the device)
 hipError_t launch_combine(double* x, const double* Z, long long ldz, int m, const double* y,
                           long long n, hipStream_t s);

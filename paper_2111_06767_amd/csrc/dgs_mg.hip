@@ -47,16 +47,18 @@ __device__ __forceinline__ double pcoef(const double* sPlo, const double* sPhi, 
 template <int N>
 __global__ void __launch_bounds__(256)
 k_restrict(const double* __restrict__ fine, double* __restrict__ coarse, int nfx, int nfy,
-           int ncx, int ncy, int ncz, int sx, int sy, int sz, DevTables T) {
+           int ncx, int ncy, int ncz, int sx, int sy, int sz, DevTables T, GatherOut go) {
   constexpr int N2 = N * N, N3 = N2 * N;
   __shared__ double T1[4][N3], T2[2][N3];
   __shared__ double sPlo[N * N], sPhi[N * N];
+  __shared__ PullEntry sPull[7];
   const int tid = threadIdx.x;
   for (int t = tid; t < N * N; t += blockDim.x) {
     sPlo[t] = T.Plo[t];
     sPhi[t] = T.Phi[t];
   }
   const long long ec = blockIdx.x;
+  if (go.rs && tid < 7) sPull[tid] = go.pull[ec * 7 + tid];
   const int cx = (int)(ec % ncx), cy = (int)((ec / ncx) % ncy), cz = (int)(ec / ((long long)ncx * ncy));
   __syncthreads();
   // x pass, straight from the fine field
@@ -98,6 +100,13 @@ k_restrict(const double* __restrict__ fine, double* __restrict__ coarse, int nfx
       for (int o = 0; o < N; ++o) acc += pcoef<N>(sPlo, sPhi, sz, oz, o, c) * src[o * N2];
     }
     coarse[ec * N3 + p] = acc;
+    if (go.rs) {  // the coarse level's r_S rows for its first smoothing step
+      const int i = p % N, j = (p / N) % N;
+      if (go.f32)
+        gather_out_point<float>((float*)go.rs, sPull, N, go.nov, i, j, c, acc);
+      else
+        gather_out_point<double>((double*)go.rs, sPull, N, go.nov, i, j, c, acc);
+    }
   }
 }
 
@@ -136,10 +145,10 @@ k_prolongate_add(const double* __restrict__ coarse, double* __restrict__ fine, i
 
 template <int N>
 hipError_t restrict_n(const double* fine, double* coarse, const int nf[3], const int nc[3],
-                      const int split[3], const DevTables& T, hipStream_t s) {
+                      const int split[3], const DevTables& T, hipStream_t s, const GatherOut& go) {
   const long long Ec = (long long)nc[0] * nc[1] * nc[2];
   hipLaunchKernelGGL(k_restrict<N>, dim3((unsigned)Ec), dim3(256), 0, s, fine, coarse, nf[0], nf[1],
-                     nc[0], nc[1], nc[2], split[0], split[1], split[2], T);
+                     nc[0], nc[1], nc[2], split[0], split[1], split[2], T, go);
   return hipGetLastError();
 }
 
@@ -155,16 +164,17 @@ hipError_t prolong_n(const double* coarse, double* fine, const int nf[3], const 
 }  // namespace
 
 hipError_t launch_restrict(int N, const double* fine, double* coarse, const int nf[3],
-                           const int nc[3], const int split[3], const DevTables& T, hipStream_t s) {
+                           const int nc[3], const int split[3], const DevTables& T, hipStream_t s,
+                           const GatherOut& go) {
   switch (N) {
-    case 2: return restrict_n<2>(fine, coarse, nf, nc, split, T, s);
-    case 3: return restrict_n<3>(fine, coarse, nf, nc, split, T, s);
-    case 4: return restrict_n<4>(fine, coarse, nf, nc, split, T, s);
-    case 5: return restrict_n<5>(fine, coarse, nf, nc, split, T, s);
-    case 6: return restrict_n<6>(fine, coarse, nf, nc, split, T, s);
-    case 7: return restrict_n<7>(fine, coarse, nf, nc, split, T, s);
-    case 8: return restrict_n<8>(fine, coarse, nf, nc, split, T, s);
-    case 9: return restrict_n<9>(fine, coarse, nf, nc, split, T, s);
+    case 2: return restrict_n<2>(fine, coarse, nf, nc, split, T, s, go);
+    case 3: return restrict_n<3>(fine, coarse, nf, nc, split, T, s, go);
+    case 4: return restrict_n<4>(fine, coarse, nf, nc, split, T, s, go);
+    case 5: return restrict_n<5>(fine, coarse, nf, nc, split, T, s, go);
+    case 6: return restrict_n<6>(fine, coarse, nf, nc, split, T, s, go);
+    case 7: return restrict_n<7>(fine, coarse, nf, nc, split, T, s, go);
+    case 8: return restrict_n<8>(fine, coarse, nf, nc, split, T, s, go);
+    case 9: return restrict_n<9>(fine, coarse, nf, nc, split, T, s, go);
     default: return hipErrorInvalidValue;
   }
 }

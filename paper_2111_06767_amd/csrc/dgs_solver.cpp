@@ -789,21 +789,30 @@ void subdomain_gmres(dgs_problem* P, Level& L, hipStream_t s) {
   HIP_OK(launch_sub_finish(L.f32, k, L.d_gZ, st, L.d_gH, L.d_gbeta, L.d_du, L.d_elem_class,
                            L.d_elem_row, L.d_cls, (int)L.E, s));
 }
-void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps, bool u_zero,
-                   hipStream_t s) {
-  Level& L = P->levels[l];
-  const int N = P->N;
-  const bool diag = P->diag_active && L.d_diag != nullptr;
+// The level's gather-out target: its subdomain rows and pull table.
+GatherOut level_gather(const dgs_problem* P, const Level& L) {
   GatherOut go;
   go.rs = L.d_rs;
   go.f32 = L.f32;
   go.pull = L.d_pull;
   go.nov = nov_of(P);
+  return go;
+}
+
+// rs_ready: the first step's r_S = R_S b is already in the level's rows
+// (written by the kernel that produced b).
+void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps, bool u_zero,
+                   hipStream_t s, bool rs_ready = false) {
+  Level& L = P->levels[l];
+  const int N = P->N;
+  const bool diag = P->diag_active && L.d_diag != nullptr;
+  const GatherOut go = level_gather(P, L);
   for (int it = 0; it < steps; ++it) {
     if (it == 0 && u_zero) {
-      // r = b: gather it
-      HIP_OK(launch_gather(N, L.f32, b, L.d_rs, L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls,
-                           L.d_seg_loc, (int)L.E, s));
+      // r = b: gather it (unless its producer already did)
+      if (!rs_ready)
+        HIP_OK(launch_gather(N, L.f32, b, L.d_rs, L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls,
+                             L.d_seg_loc, (int)L.E, s));
     } else {
       // the residual kernel writes r_S = R_S (b - A u) straight into the rows
       HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u, nullptr, b, L.d_diag, nullptr,
@@ -822,7 +831,9 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
   }
 }
 
-void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s) {
+// rs0_ready: the finest level's rows already hold R_S r.
+void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
+                  bool rs0_ready = false) {
   const int nl = (int)P->levels.size();
   const int N = P->N;
   std::vector<const double*> b(nl);
@@ -841,14 +852,16 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s) {
   }
   for (int l = 0; l < nl - 1; ++l) {
     Level& L = P->levels[l];
-    schwarz_steps(P, l, b[l], u[l], P->opt.pre_smooth, true, s);
+    schwarz_steps(P, l, b[l], u[l], P->opt.pre_smooth, true, s, l == 0 ? rs0_ready : true);
     const bool diag = P->diag_active && L.d_diag != nullptr;
     HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u[l], L.d_r, b[l], L.d_diag, nullptr,
                         L.d_nbr, L.op, P->dt, L.acfg, s, L.d_order));
     Level& C = P->levels[l + 1];
-    HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s));
+    // the restriction also writes the coarse level's first r_S rows
+    HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
   }
-  schwarz_steps(P, nl - 1, b[nl - 1], u[nl - 1], P->opt.pre_smooth + P->opt.post_smooth, true, s);
+  schwarz_steps(P, nl - 1, b[nl - 1], u[nl - 1], P->opt.pre_smooth + P->opt.post_smooth, true, s,
+                nl > 1 ? true : rs0_ready);
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = P->levels[l];
     Level& C = P->levels[l + 1];
@@ -872,7 +885,7 @@ void vcycle_graph(dgs_problem* P, hipStream_t s) {
     HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
     hipGraph_t graph = nullptr;
     try {
-      vcycle_eager(P, L0.d_b, L0.d_u, P->cap_stream);
+      vcycle_eager(P, L0.d_b, L0.d_u, P->cap_stream, /*rs0_ready=*/true);
     } catch (...) {
       (void)hipStreamEndCapture(P->cap_stream, &graph);
       if (graph) (void)hipGraphDestroy(graph);
@@ -894,6 +907,8 @@ void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
   Level& L0 = P->levels[0];
   const long long n = P->nd(0);
   HIP_OK(launch_copy(L0.d_b, r, n, s));
+  HIP_OK(launch_gather(P->N, L0.f32, L0.d_b, L0.d_rs, L0.d_elem_class, L0.d_elem_row, L0.d_nbr,
+                       L0.d_cls, L0.d_seg_loc, (int)L0.E, s));
   vcycle_graph(P, s);
   HIP_OK(launch_copy(z, L0.d_u, n, s));
 }
@@ -1059,8 +1074,11 @@ struct FgmresRun {
       HIP_OK(hipMemcpyAsync(hp, P->d_h, sizeof(double) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, s));
       // v_{j+1} = w / |w| (unused if |w| = 0: the run stops), also into the
       // V-cycle's input for the next iteration
-      HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s,
-                                      P->opt.use_graphs ? P->levels[0].d_b : nullptr));
+      if (P->opt.use_graphs)
+        HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s, P->levels[0].d_b, P->N,
+                                        level_gather(P, P->levels[0])));
+      else
+        HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));
     } else if (stage == kFinish) {
       const int k = R.iterations;
       std::vector<double> y(k, 0.0);
@@ -1094,8 +1112,11 @@ struct FgmresRun {
         return;
       }
       g[0] = beta;
-      HIP_OK(launch_scale_by_inv_norm(P->d_V, P->d_V, P->d_h, P->nd(0), s,
-                                      P->opt.use_graphs ? P->levels[0].d_b : nullptr));
+      if (P->opt.use_graphs)
+        HIP_OK(launch_scale_by_inv_norm(P->d_V, P->d_V, P->d_h, P->nd(0), s, P->levels[0].d_b, P->N,
+                                        level_gather(P, P->levels[0])));
+      else
+        HIP_OK(launch_scale_by_inv_norm(P->d_V, P->d_V, P->d_h, P->nd(0), s));
       stage = kIter;
     } else if (stage == kIter) {
       double* col = &H[(size_t)j * (m + 1)];  // column j, rows 0..j+1
