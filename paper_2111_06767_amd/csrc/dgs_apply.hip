@@ -139,11 +139,9 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int PIT = N + 1;  // padded row pitch (bank spread for line reads)
   constexpr int S3 = N * N * PIT;
-  // sU: the element; sA / sB: its -x / +x neighbours (loaded coalesced, so
-  // the x-lines the flux needs are read from LDS rather than as 64-byte
-  // strided rows from memory); sA / sB are reused for the transposed x and y
-  // contributions in the second phase
-  __shared__ double sU[EPB][S3], sA[EPB][S3], sB[EPB][S3];
+  // sU: the element (its x- and y-lines for the forward phase); after the
+  // forward phase sA and sU take the transposed x and y contributions
+  __shared__ double sU[EPB][S3], sA[EPB][S3];
   __shared__ double sw[N];
   __shared__ PullEntry sPull[GO ? EPB : 1][7];  // gather-out only
 
@@ -174,7 +172,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   // neighbours on the shared faces (index side * 2 + {trace, derivative}),
   // reduced from their lines as soon as they arrive so the lines do not stay
   // in registers through the forward phase
-  double uz[N], yf[4], zf[4];
+  double uz[N], xf[4], yf[4], zf[4];
   int nb[6];
   if (active) {
     const double* ue = u + e * N3;
@@ -197,8 +195,6 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
     for (int k = 0; k < N; ++k) {
       uz[k] = ue[k * N2 + t];
       sU[slot][L(k, b, a)] = uz[k];
-      sA[slot][L(k, b, a)] = u[xl0 * N3 + k * N2 + t];
-      sB[slot][L(k, b, a)] = u[xh0 * N3 + k * N2 + t];
     }
     // every neighbour line this lane needs, issued before the first barrier
     // (a missing neighbour reads the element itself; its result is replaced by
@@ -207,7 +203,12 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
     const long long yh = nb[3] >= 0 ? (long long)nb[3] : e;
     const long long zl = nb[4] >= 0 ? (long long)nb[4] : e;
     const long long zh = nb[5] >= 0 ? (long long)nb[5] : e;
-    double ylo[N], yhi[N], zlo[N], zhi[N];
+    double xlo[N], xhi[N], ylo[N], yhi[N], zlo[N], zhi[N];
+#pragma unroll
+    for (int m = 0; m < N; ++m) {  // x-lines: N contiguous values per lane
+      xlo[m] = u[xl0 * N3 + b * N2 + a * N + m];
+      xhi[m] = u[xh0 * N3 + b * N2 + a * N + m];
+    }
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       ylo[m] = u[yl * N3 + b * N2 + m * N + a];
@@ -215,6 +216,8 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       zlo[m] = u[zl * N3 + m * N2 + t];
       zhi[m] = u[zh * N3 + m * N2 + t];
     }
+    face_from_line<N>(xlo, 0, P.rh[0], T, xf[0], xf[1]);
+    face_from_line<N>(xhi, 1, P.rh[0], T, xf[2], xf[3]);
     face_from_line<N>(ylo, 0, P.rh[1], T, yf[0], yf[1]);
     face_from_line<N>(yhi, 1, P.rh[1], T, yf[2], yf[3]);
     face_from_line<N>(zlo, 0, P.rh[2], T, zf[0], zf[1]);
@@ -244,13 +247,8 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         // result is replaced by the Dirichlet ghost state
         const bool has = nb[side] >= 0;
         const double ui = line[ie], gi = g[ie];
-        double ue, ge;
-        double xn[N];
-#pragma unroll
-        for (int m = 0; m < N; ++m) xn[m] = side ? sB[slot][L(b, a, m)] : sA[slot][L(b, a, m)];
-        face_from_line<N>(xn, side, P.rh[0], T, ue, ge);
-        ue = has ? ue : -ui;
-        ge = has ? ge : gi;
+        const double ue = has ? xf[2 * side] : -ui;
+        const double ge = has ? xf[2 * side + 1] : gi;
         fx[side] = jwab * P.rh[0] * (0.5 * sg * (gi + ge) - P.sig[0] * (ui - ue));
         g[ie] += P.lf[0] * sg * (ue - ui);
       }
@@ -300,7 +298,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       for (int m = 0; m < N; ++m) qz[m] = jwab * T.w[m] * g[m];
     }
   }
-  __syncthreads();  // every forward read of sA / sB is done: they are reused below
+  __syncthreads();  // every forward read of sU is done: sA and sU are written below
 
   // transpose phase: sum_d D_d^T q_d - flux terms, x and y parts through LDS
   if (active) {
@@ -319,7 +317,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       double v = c[j] * P.rh[1];
       if (j == 0) v -= fy[0];
       if (j == N - 1) v -= fy[1];
-      sB[slot][L(b, j, a)] = v;
+      sU[slot][L(b, j, a)] = v;
     }
   }
   // the right-hand side and diagonal of this lane's z-line, loaded before the
@@ -344,7 +342,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
     double rz[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      double r = c[k] * P.rh[2] + sA[slot][L(k, b, a)] + sB[slot][L(k, b, a)];
+      double r = c[k] * P.rh[2] + sA[slot][L(k, b, a)] + sU[slot][L(k, b, a)];
       if (k == 0) r -= fz[0];
       if (k == N - 1) r -= fz[1];
       const long long gi = e * N3 + k * N2 + t;
