@@ -166,6 +166,20 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
  * level outside [0, levels). */
 int dgs_subdomain_solves(dgs_problem* prob, int level, int reps, double* flops, void* stream);
 
+/* Launch shape of the operator kernel on multigrid level `level` (Sec. II
+ * operator; the shape changes only how elements are grouped into workgroups,
+ * never the arithmetic, so every shape gives bit-identical results):
+ *   1, 2  elements per workgroup;
+ *   0     the default group for p (256 / (p+1)^2 elements);
+ *  -1     2 x 2 x 2 bricks of elements, whose in-brick face neighbours are
+ *         read from on-chip memory (p = 7 only).
+ * The autotuner sets one per level when the problem is created;
+ * dgs_set_apply_shape overrides it (DGS_ERR_INVALID for a level outside
+ * [0, levels) or a shape not listed / not available for p), and
+ * dgs_get_apply_shape reads it into *shape. */
+int dgs_set_apply_shape(dgs_problem* prob, int level, int shape);
+int dgs_get_apply_shape(const dgs_problem* prob, int level, int* shape);
+
 /* The p+1 Legendre-Gauss-Lobatto points on [-1, 1] (ascending), so that a
  * caller can place its data: point (i, j, k) of element (e_x, e_y, e_z) sits at
  * x = lower_x + h_x (e_x + (xi_i + 1) / 2), and likewise in y and z. */

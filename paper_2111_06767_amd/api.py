@@ -30,6 +30,7 @@ EXPORTED = (
     "dgs_precondition", "dgs_solve", "dgs_newton_solve", "dgs_last_error", "dgs_set_diagonal",
     "dgs_lgl_nodes", "dgs_server_create", "dgs_server_destroy", "dgs_server_submit",
     "dgs_server_step", "dgs_server_finished", "dgs_server_fetch", "dgs_subdomain_solves",
+    "dgs_set_apply_shape", "dgs_get_apply_shape",
 )
 
 
@@ -109,6 +110,10 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_server_fetch.argtypes = [P, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double),
                                      ctypes.c_longlong, ctypes.POINTER(Stats),
                                      ctypes.POINTER(ctypes.c_double)]
+    lib.dgs_subdomain_solves.argtypes = [P, ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double), P]
+    lib.dgs_set_apply_shape.argtypes = [P, ctypes.c_int, ctypes.c_int]
+    lib.dgs_get_apply_shape.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.dgs_last_error.argtypes = []
     lib.dgs_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -225,6 +230,17 @@ class Problem:
         _check(self._lib.dgs_subdomain_solves(self._h, int(level), int(reps), ctypes.byref(flops),
                                               _stream(stream)))
         return flops.value
+
+    def apply_shape(self, level=0):
+        """Operator-kernel launch shape of `level`: elements per workgroup
+        (1, 2; 0 = default for p) or -1 for 2 x 2 x 2 element bricks (p = 7)."""
+        v = ctypes.c_int()
+        _check(self._lib.dgs_get_apply_shape(self._h, int(level), ctypes.byref(v)))
+        return v.value
+
+    def set_apply_shape(self, shape, level=0):
+        """Override the autotuned operator-kernel launch shape of `level`."""
+        _check(self._lib.dgs_set_apply_shape(self._h, int(level), int(shape)))
 
     def set_diagonal(self, d=None, stream=None):
         """Operator A + diag(d) for smoothing, preconditioning and solves (None: A)."""

@@ -129,13 +129,21 @@ __device__ __forceinline__ void store_subdomain_rows(const double (&rz)[N], TS* 
 // MODE is an ApplyMode; GO = 0 writes out, GO = 1 / 2 writes r_S into FP32 /
 // FP64 subdomain rows (residual modes only).  Each combination is compiled
 // separately so that it carries only its own loads, stores and registers.
-template <int N, int EPB, int MODE, int GO>
+//
+// BR = true (N = 8): a workgroup takes a 2 x 2 x 2 brick of elements of a box grid
+// (EPB = 8, slot s at offset (s & 1, (s >> 1) & 1, s >> 2) in the brick;
+// order[] lists the bricks).  Each element then has one face neighbour per
+// direction inside the brick, whose lines are read from that element's LDS
+// copy, and only the three outside neighbours come from global memory: four
+// element reads per element instead of seven.
+template <int N, int EPB, int MODE, int GO, bool BR>
 __global__ void __launch_bounds__(((EPB * N * N + 63) / 64) * 64)
 k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ bvec,
         const double* __restrict__ aux0, const double* __restrict__ aux1,
         const int* __restrict__ nbr, OpParams P, DevTables T,
         const int* __restrict__ order, GatherOut go, double* __restrict__ ucopy) {
   static_assert(GO == 0 || MODE == kResidual || MODE == kResidualDiag, "gather-out mode");
+  static_assert(!BR || EPB == 8, "a brick holds 8 elements");
   constexpr int N2 = N * N, N3 = N2 * N;
   constexpr int PIT = N + 1;  // padded row pitch (bank spread for line reads)
   constexpr int S3 = N * N * PIT;
@@ -147,7 +155,9 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
 
   const int tid = threadIdx.x;
   if (tid < N) sw[tid] = T.w[tid];
-  const int slot = tid / N2;
+  // with N^2 = 64 a slot is one wavefront: say so, so that everything derived
+  // from the element index stays in scalar registers
+  const int slot = (N2 % 64 == 0) ? __builtin_amdgcn_readfirstlane(tid / N2) : tid / N2;
   const int t = tid - slot * N2;
   const int a = t % N, b = t / N;
   // XCD-aware block order: the hardware deals workgroups round-robin to the
@@ -155,21 +165,39 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   // share that XCD's L2).
   const unsigned G = gridDim.x, per = G / 8u;
   const unsigned blk = (blockIdx.x % 8u) * per + blockIdx.x / 8u;
-  const long long pos = (long long)blk * EPB + slot;
-  const bool active = (slot < EPB) && (pos < P.E);
-  const long long e = (active && order) ? (long long)order[pos] : pos;
+  // element of slot s of this block, -1 for none; with one element per
+  // block it is derived from blockIdx alone (uniform across the wave)
+  auto element_of = [&](int s) -> long long {
+    if constexpr (BR) {
+      const int nx = P.n[0], ny = P.n[1], nz = P.n[2];
+      const int nbx = (nx + 1) >> 1, nby = (ny + 1) >> 1, nbz = (nz + 1) >> 1;
+      if (blk >= (unsigned)(nbx * nby * nbz)) return -1;
+      const int bl = order[blk];
+      const int bx = bl % nbx, by = (bl / nbx) % nby, bz = bl / (nbx * nby);
+      const int ex = 2 * bx + (s & 1), ey = 2 * by + ((s >> 1) & 1), ez = 2 * bz + (s >> 2);
+      if (ex >= nx || ey >= ny || ez >= nz) return -1;
+      return ((long long)ez * ny + ey) * nx + ex;
+    } else {
+      const long long ps = EPB == 1 ? (long long)blk : (long long)blk * EPB + s;
+      if (ps >= P.E) return -1;
+      return order ? (long long)order[ps] : ps;
+    }
+  };
+  const long long e0 = slot < EPB ? element_of(EPB == 1 ? 0 : slot) : -1;
+  const bool active = e0 >= 0;
+  const long long e = active ? e0 : 0;
   const double J = P.J;
   auto L = [](int k, int j, int i) { return (k * N + j) * PIT + i; };
   if constexpr (GO != 0) {
     for (int q = tid; q < EPB * 7; q += blockDim.x) {
       const int s7 = q / 7, j7 = q - s7 * 7;
-      const long long ps = (long long)blk * EPB + s7;
-      if (ps < P.E) sPull[s7][j7] = go.pull[(order ? (long long)order[ps] : ps) * 7 + j7];
+      const long long es = element_of(s7);
+      if (es >= 0) sPull[s7][j7] = go.pull[es * 7 + j7];
     }
   }
 
-  // uz: the lane's z-line; yf / zf: trace and normal derivative of the y / z
-  // neighbours on the shared faces (index side * 2 + {trace, derivative}),
+  // uz: the lane's z-line; xf / yf / zf: trace and normal derivative of the
+  // x / y / z neighbours on the shared faces (index side * 2 + {trace, derivative}),
   // reduced from their lines as soon as they arrive so the lines do not stay
   // in registers through the forward phase
   double uz[N], xf[4], yf[4], zf[4];
@@ -189,45 +217,98 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
 #pragma unroll
       for (int f = 0; f < 6; ++f) nb[f] = nbr[e * 6 + f];
     }
-    const long long xl0 = nb[0] >= 0 ? (long long)nb[0] : e;
-    const long long xh0 = nb[1] >= 0 ? (long long)nb[1] : e;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       uz[k] = ue[k * N2 + t];
       sU[slot][L(k, b, a)] = uz[k];
     }
-    // every neighbour line this lane needs, issued before the first barrier
-    // (a missing neighbour reads the element itself; its result is replaced by
-    // the Dirichlet ghost state)
-    const long long yl = nb[2] >= 0 ? (long long)nb[2] : e;
-    const long long yh = nb[3] >= 0 ? (long long)nb[3] : e;
-    const long long zl = nb[4] >= 0 ? (long long)nb[4] : e;
-    const long long zh = nb[5] >= 0 ? (long long)nb[5] : e;
-    double xlo[N], xhi[N], ylo[N], yhi[N], zlo[N], zhi[N];
+    // every neighbour line this lane reads from global memory, issued before
+    // the first barrier (a missing neighbour reads the element itself; its
+    // result is replaced by the Dirichlet ghost state)
+    auto nbi = [&](int f) -> long long { return nb[f] >= 0 ? (long long)nb[f] : e; };
+    if constexpr (BR) {
+      // the neighbour on side o_d of direction d is outside the brick
+      const int ox = slot & 1, oy = (slot >> 1) & 1, oz = slot >> 2;
+      const long long xo = nbi(ox), yo = nbi(2 + oy), zo = nbi(4 + oz);
+      double xl[N], yl[N], zl[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) {  // x-lines: N contiguous values per lane
-      xlo[m] = u[xl0 * N3 + b * N2 + a * N + m];
-      xhi[m] = u[xh0 * N3 + b * N2 + a * N + m];
-    }
+      for (int m = 0; m < N; ++m) {
+        xl[m] = u[xo * N3 + b * N2 + a * N + m];
+        yl[m] = u[yo * N3 + b * N2 + m * N + a];
+        zl[m] = u[zo * N3 + m * N2 + t];
+      }
+      // parked in the high / low pair of the outside side; the inside side
+      // is filled after the barrier
+      face_from_line<N>(xl, ox, P.rh[0], T, xf[0], xf[1]);
+      face_from_line<N>(yl, oy, P.rh[1], T, yf[0], yf[1]);
+      face_from_line<N>(zl, oz, P.rh[2], T, zf[0], zf[1]);
+    } else {
+      const long long xl0 = nbi(0), xh0 = nbi(1), yl = nbi(2), yh = nbi(3), zl = nbi(4),
+                      zh = nbi(5);
+      double xlo[N], xhi[N], ylo[N], yhi[N], zlo[N], zhi[N];
 #pragma unroll
-    for (int m = 0; m < N; ++m) {
-      ylo[m] = u[yl * N3 + b * N2 + m * N + a];
-      yhi[m] = u[yh * N3 + b * N2 + m * N + a];
-      zlo[m] = u[zl * N3 + m * N2 + t];
-      zhi[m] = u[zh * N3 + m * N2 + t];
+      for (int m = 0; m < N; ++m) {  // x-lines: N contiguous values per lane
+        xlo[m] = u[xl0 * N3 + b * N2 + a * N + m];
+        xhi[m] = u[xh0 * N3 + b * N2 + a * N + m];
+      }
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        ylo[m] = u[yl * N3 + b * N2 + m * N + a];
+        yhi[m] = u[yh * N3 + b * N2 + m * N + a];
+        zlo[m] = u[zl * N3 + m * N2 + t];
+        zhi[m] = u[zh * N3 + m * N2 + t];
+      }
+      face_from_line<N>(xlo, 0, P.rh[0], T, xf[0], xf[1]);
+      face_from_line<N>(xhi, 1, P.rh[0], T, xf[2], xf[3]);
+      face_from_line<N>(ylo, 0, P.rh[1], T, yf[0], yf[1]);
+      face_from_line<N>(yhi, 1, P.rh[1], T, yf[2], yf[3]);
+      face_from_line<N>(zlo, 0, P.rh[2], T, zf[0], zf[1]);
+      face_from_line<N>(zhi, 1, P.rh[2], T, zf[2], zf[3]);
     }
-    face_from_line<N>(xlo, 0, P.rh[0], T, xf[0], xf[1]);
-    face_from_line<N>(xhi, 1, P.rh[0], T, xf[2], xf[3]);
-    face_from_line<N>(ylo, 0, P.rh[1], T, yf[0], yf[1]);
-    face_from_line<N>(yhi, 1, P.rh[1], T, yf[2], yf[3]);
-    face_from_line<N>(zlo, 0, P.rh[2], T, zf[0], zf[1]);
-    face_from_line<N>(zhi, 1, P.rh[2], T, zf[2], zf[3]);
+  } else if (BR && slot < EPB) {
+    // an empty brick slot: defined values for its neighbours' reads (they
+    // are discarded, the face is a domain boundary)
+#pragma unroll
+    for (int k = 0; k < N; ++k) sU[slot][L(k, b, a)] = 0.0;
   }
   __syncthreads();
+  if constexpr (BR) {
+    if (active) {  // the inside neighbours' lines, from their LDS copies
+      const int ox = slot & 1, oy = (slot >> 1) & 1, oz = slot >> 2;
+      double xl[N], yl[N], zl[N];
+#pragma unroll
+      for (int m = 0; m < N; ++m) {
+        xl[m] = sU[slot ^ 1][L(b, a, m)];
+        yl[m] = sU[slot ^ 2][L(b, m, a)];
+        zl[m] = sU[slot ^ 4][L(m, b, a)];
+      }
+      double xu, xg, yu, yg, zu, zg;
+      face_from_line<N>(xl, 1 - ox, P.rh[0], T, xu, xg);
+      face_from_line<N>(yl, 1 - oy, P.rh[1], T, yu, yg);
+      face_from_line<N>(zl, 1 - oz, P.rh[2], T, zu, zg);
+      // low side outside (o_d = 0): outside pair low, inside pair high
+      xf[2] = ox ? xf[0] : xu;
+      xf[3] = ox ? xf[1] : xg;
+      xf[0] = ox ? xu : xf[0];
+      xf[1] = ox ? xg : xf[1];
+      yf[2] = oy ? yf[0] : yu;
+      yf[3] = oy ? yf[1] : yg;
+      yf[0] = oy ? yu : yf[0];
+      yf[1] = oy ? yg : yf[1];
+      zf[2] = oz ? zf[0] : zu;
+      zf[3] = oz ? zf[1] : zg;
+      zf[0] = oz ? zu : zf[0];
+      zf[1] = oz ? zg : zf[1];
+    }
+  }
 
-  // forward phase: q_d = M (grad_d u + lift) on every line, flux at line ends
-  double qx[N], qy[N], qz[N];
-  double fx[2], fy[2], fz[2];
+  // forward phase: q_d = M (grad_d u + lift) on every line, flux at line
+  // ends, each role followed as early as possible by its transposed product
+  // D_d^T q_d: the x role's goes straight to sA (which the forward phase does
+  // not read), the z role's stays in registers, and only the y role's q waits
+  // for the barrier (its result overwrites sU, which other lanes still read)
+  double qy[N], cz[N];
+  double fy[2], fz[2];
   if (active) {
     const double wa = sw[a], wb = sw[b];
     const double jwab = J * wa * wb;
@@ -239,6 +320,7 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       eo_apply<N>(line, g, T.fwd);
 #pragma unroll
       for (int m = 0; m < N; ++m) g[m] *= P.rh[0];
+      double fx[2];
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const int ie = side ? N - 1 : 0;
@@ -253,7 +335,15 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         g[ie] += P.lf[0] * sg * (ue - ui);
       }
 #pragma unroll
-      for (int m = 0; m < N; ++m) qx[m] = jwab * T.w[m] * g[m];
+      for (int m = 0; m < N; ++m) line[m] = jwab * T.w[m] * g[m];
+      eo_apply<N>(line, g, T.bwd);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double v = g[i] * P.rh[0];
+        if (i == 0) v -= fx[0];
+        if (i == N - 1) v -= fx[1];
+        sA[slot][L(b, a, i)] = v;
+      }
     }
     // ---- y role: line (i, k) = (a, b) ----
     {
@@ -295,22 +385,14 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         g[ke] += P.lf[2] * sg * (ue - ui);
       }
 #pragma unroll
-      for (int m = 0; m < N; ++m) qz[m] = jwab * T.w[m] * g[m];
+      for (int m = 0; m < N; ++m) g[m] = jwab * T.w[m] * g[m];
+      eo_apply<N>(g, cz, T.bwd);
     }
   }
-  __syncthreads();  // every forward read of sU is done: sA and sU are written below
+  __syncthreads();  // every forward read of sU is done: the y part is written below
 
-  // transpose phase: sum_d D_d^T q_d - flux terms, x and y parts through LDS
   if (active) {
     double c[N];
-    eo_apply<N>(qx, c, T.bwd);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double v = c[i] * P.rh[0];
-      if (i == 0) v -= fx[0];
-      if (i == N - 1) v -= fx[1];
-      sA[slot][L(b, a, i)] = v;
-    }
     eo_apply<N>(qy, c, T.bwd);
 #pragma unroll
     for (int j = 0; j < N; ++j) {
@@ -336,13 +418,11 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   }
   __syncthreads();
   if (active) {
-    double c[N];
-    eo_apply<N>(qz, c, T.bwd);
     const double jwab = J * sw[a] * sw[b];
     double rz[N];
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      double r = c[k] * P.rh[2] + sA[slot][L(k, b, a)] + sU[slot][L(k, b, a)];
+      double r = cz[k] * P.rh[2] + sA[slot][L(k, b, a)] + sU[slot][L(k, b, a)];
       if (k == 0) r -= fz[0];
       if (k == N - 1) r -= fz[1];
       const long long gi = e * N3 + k * N2 + t;
@@ -375,19 +455,21 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
   }
 }
 
-template <int N, int EPB, int MODE, int GO>
+template <int N, int EPB, int MODE, int GO, bool BR>
 hipError_t launch_apply_k(const double* u, double* out, const double* b, const double* aux0,
                           const double* aux1, const int* nbr, const OpParams& P, const DevTables& T,
                           hipStream_t s, const int* order, const GatherOut& go, double* ucopy) {
   const int threads = ((EPB * N * N + 63) / 64) * 64;
-  const long long need = ((long long)P.E + EPB - 1) / EPB;
+  long long need = ((long long)P.E + EPB - 1) / EPB;
+  if (BR)
+    need = (long long)((P.n[0] + 1) / 2) * ((P.n[1] + 1) / 2) * ((P.n[2] + 1) / 2);
   const long long blocks = ((need + 7) / 8) * 8;  // whole rounds over the 8 XCDs
-  hipLaunchKernelGGL((k_apply<N, EPB, MODE, GO>), dim3((unsigned)blocks), dim3(threads), 0, s, u,
-                     out, b, aux0, aux1, nbr, P, T, order, go, ucopy);
+  hipLaunchKernelGGL((k_apply<N, EPB, MODE, GO, BR>), dim3((unsigned)blocks), dim3(threads), 0, s,
+                     u, out, b, aux0, aux1, nbr, P, T, order, go, ucopy);
   return hipGetLastError();
 }
 
-template <int N, int EPB>
+template <int N, int EPB, bool BR>
 hipError_t launch_apply_t(int mode, const double* u, double* out, const double* b,
                           const double* aux0, const double* aux1, const int* nbr,
                           const OpParams& P, const DevTables& T, hipStream_t s, const int* order,
@@ -395,7 +477,7 @@ hipError_t launch_apply_t(int mode, const double* u, double* out, const double* 
   if (P.E <= 0) return hipSuccess;
   const int gox = go.rs ? (go.f32 ? 1 : 2) : 0;
 #define DGS_APPLY(M, G) \
-  launch_apply_k<N, EPB, M, G>(u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy)
+  launch_apply_k<N, EPB, M, G, BR>(u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy)
   switch (mode) {
     case kApply: return DGS_APPLY(kApply, 0);
     case kApplyDiag: return DGS_APPLY(kApplyDiag, 0);
@@ -412,14 +494,27 @@ hipError_t launch_apply_t(int mode, const double* u, double* out, const double* 
 }
 
 template <int N>
-hipError_t launch_apply_n(int epb, int mode, const double* u, double* out, const double* b,
-                          const double* aux0, const double* aux1, const int* nbr,
+hipError_t launch_apply_n(const ApplyConfig& cfg, int mode, const double* u, double* out,
+                          const double* b, const double* aux0, const double* aux1, const int* nbr,
                           const OpParams& P, const DevTables& T, hipStream_t s, const int* order,
                           const GatherOut& go, double* ucopy) {
   constexpr int def = (N == 2) ? 64 : (256 / (N * N));  // >= 3 for every N <= 9
-  if (epb == 1) return launch_apply_t<N, 1>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-  if (epb == 2) return launch_apply_t<N, 2>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-  return launch_apply_t<N, def>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+  if (cfg.bricks) {
+    // bricks pay off only where one element fills a wavefront (N^2 = 64):
+    // then every brick decision is wave-uniform
+    if constexpr (N == 8) {
+      if (P.n[0] <= 0) return hipErrorInvalidValue;  // bricks need the box grid
+      return launch_apply_t<N, 8, true>(mode, u, out, b, aux0, aux1, nbr, P, T, s, cfg.bricks, go,
+                                        ucopy);
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  if (cfg.epb == 1)
+    return launch_apply_t<N, 1, false>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+  if (cfg.epb == 2)
+    return launch_apply_t<N, 2, false>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+  return launch_apply_t<N, def, false>(mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
 }
 
 // b = M f, M = J w_i w_j w_k
@@ -457,14 +552,14 @@ hipError_t launch_apply(int N, int mode, const double* u, double* out, const dou
                         const int* order, const GatherOut& go, double* ucopy) {
   if (go.rs && (mode != kResidual && mode != kResidualDiag)) return hipErrorInvalidValue;
   switch (N) {
-    case 2: return launch_apply_n<2>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-    case 3: return launch_apply_n<3>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-    case 4: return launch_apply_n<4>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-    case 5: return launch_apply_n<5>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-    case 6: return launch_apply_n<6>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-    case 7: return launch_apply_n<7>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-    case 8: return launch_apply_n<8>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
-    case 9: return launch_apply_n<9>(cfg.epb, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 2: return launch_apply_n<2>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 3: return launch_apply_n<3>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 4: return launch_apply_n<4>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 5: return launch_apply_n<5>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 6: return launch_apply_n<6>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 7: return launch_apply_n<7>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 8: return launch_apply_n<8>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 9: return launch_apply_n<9>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
     default: return hipErrorInvalidValue;
   }
 }

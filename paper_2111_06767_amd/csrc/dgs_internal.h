@@ -70,9 +70,11 @@ enum ApplyMode : int {
   kPuncture = 4,      // out = A u + M S(u) - b,  S = -beta (alpha (1+u) + 1)^-7
 };
 
-// Launch configuration of the operator kernel: elements per workgroup.
+// Launch configuration of the operator kernel: elements per workgroup, or
+// 2 x 2 x 2 bricks of a box grid taken in the order of the brick table.
 struct ApplyConfig {
-  int epb = 0;  // 0 = default for N
+  int epb = 0;                   // 0 = default for N
+  const int* bricks = nullptr;   // device table of brick indices (N = 8)
 };
 
 constexpr int kGemmLd = 128, kGemmRows = 64;

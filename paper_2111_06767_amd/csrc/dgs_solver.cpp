@@ -167,6 +167,7 @@ struct Level {
   OpParams op{};
   int* d_nbr = nullptr;
   int* d_order = nullptr;  // element processing order of the operator kernel
+  int* d_bricks = nullptr;  // the same order over 2 x 2 x 2 bricks (N = 8)
   // Schwarz
   std::vector<ClassLayout> layouts;
   std::vector<ClassInfo> cls;
@@ -293,6 +294,21 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
   if (!identity) {  // the identity order needs no table (and no load)
     L.d_order = P->alloc<int>(order.size());
     upload(L.d_order, order, s);
+  }
+  if (P->N == 8) {  // bricks (p = 7): the same column order at brick granularity
+    const int bn[3] = {(L.n[0] + 1) / 2, (L.n[1] + 1) / 2, (L.n[2] + 1) / 2};
+    const int TB = T / 2;
+    std::vector<int> border;
+    border.reserve((size_t)bn[0] * bn[1] * bn[2]);
+    for (int ty = 0; ty < bn[1]; ty += TB)
+      for (int tx = 0; tx < bn[0]; tx += TB)
+        for (int z = 0; z < bn[2]; ++z)
+          for (int y = ty; y < std::min(ty + TB, bn[1]); ++y)
+            for (int x = tx; x < std::min(tx + TB, bn[0]); ++x)
+              border.push_back((z * bn[1] + y) * bn[0] + x);
+    L.d_bricks = P->alloc<int>(border.size());
+    upload(L.d_bricks, border, s);
+    HIP_OK(hipStreamSynchronize(s));
   }
   HIP_OK(hipStreamSynchronize(s));  // nbr and order go out of scope
   const long long nd = L.E * (long long)P->N * P->N * P->N;
@@ -650,6 +666,7 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
       auto it = g_tuned_epb.find(key);
       if (it != g_tuned_epb.end()) {
         L.acfg.epb = it->second;
+        L.acfg.bricks = it->second < 0 ? L.d_bricks : nullptr;
         continue;
       }
     }
@@ -661,13 +678,17 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
     go.f32 = L.f32;
     go.pull = L.d_pull;
     go.nov = nov_of(P);
-    const int cands[3] = {1, 2, 0};
+    // elements per workgroup; -1: 2 x 2 x 2 bricks
+    const int cands[4] = {1, 2, 0, -1};
+    const int ncand = L.d_bricks ? 4 : 3;
     const int reps = L.E >= 4096 ? 3 : 8;
     int best = cands[0];
     float best_ms = 1e30f;
-    for (int c : cands) {
+    for (int ci = 0; ci < ncand; ++ci) {
+      const int c = cands[ci];
       ApplyConfig cfg;
       cfg.epb = c;
+      cfg.bricks = c < 0 ? L.d_bricks : nullptr;
       HIP_OK(launch_apply(N, kResidual, L.d_u, nullptr, L.d_b, nullptr, nullptr, L.d_nbr, L.op,
                           P->dt, cfg, s, L.d_order, go));  // warm-up
       float tmin = 1e30f;
@@ -688,6 +709,7 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
       }
     }
     L.acfg.epb = best;
+    L.acfg.bricks = best < 0 ? L.d_bricks : nullptr;
     std::lock_guard<std::mutex> lk(g_tune_mutex);
     g_tuned_epb[key] = best;
   }
@@ -1564,6 +1586,28 @@ int dgs_subdomain_solves(dgs_problem* prob, int level, int reps, double* flops, 
       HIP_OK(gemm_level(L, L.d_rs, L.rs_total, 0, s));
     return DGS_OK;
   });
+}
+
+int dgs_set_apply_shape(dgs_problem* prob, int level, int shape) {
+  return guarded([&]() -> int {
+    if (!prob) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (level < 0 || level >= (int)prob->levels.size())
+      return fail(DGS_ERR_INVALID, "level out of range");
+    Level& L = prob->levels[level];
+    if (shape < -1 || shape > 2) return fail(DGS_ERR_INVALID, "unknown apply shape");
+    if (shape == -1 && !L.d_bricks) return fail(DGS_ERR_INVALID, "bricks need p = 7");
+    L.acfg.epb = shape;
+    L.acfg.bricks = shape < 0 ? L.d_bricks : nullptr;
+    return DGS_OK;
+  });
+}
+
+int dgs_get_apply_shape(const dgs_problem* prob, int level, int* shape) {
+  if (!prob || !shape) return fail(DGS_ERR_INVALID, "NULL argument");
+  if (level < 0 || level >= (int)prob->levels.size())
+    return fail(DGS_ERR_INVALID, "level out of range");
+  *shape = prob->levels[level].acfg.bricks ? -1 : prob->levels[level].acfg.epb;
+  return DGS_OK;
 }
 
 int dgs_precondition(dgs_problem* prob, const double* r, double* z, void* stream) {

@@ -79,3 +79,53 @@ def test_apply_is_linear_and_symmetric_on_gpu():
     a, b = torch.dot(y, Ax).item(), torch.dot(x, Ay).item()
     assert abs(a - b) < 1e-12 * abs(a)
     assert torch.dot(x, Ax).item() > 0
+
+
+SHAPE_CASES = [((3, 2, 5), 2), ((5, 3, 2), 5), ((4, 4, 4), 6), ((7, 3, 2), 7), ((1, 1, 1), 7),
+               ((2, 3, 4), 8), ((9, 8, 7), 7), ((2, 2, 2), 7)]
+
+
+@pytest.mark.parametrize("elements,p", SHAPE_CASES)
+def test_every_launch_shape_gives_the_same_apply(elements, p):
+    """Elements per workgroup and 2x2x2 bricks (odd grids leave ragged bricks)
+    only regroup the elements: every shape returns the same bits, and they
+    match the oracle."""
+    import paper_2111_06767_amd as dg
+    announce(f"apply launch shapes elements={elements} p={p}")
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, penalty=1.5, mg_levels=1)
+    m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), elements, p)
+    u = to_gpu(W.random_normal(W.SEED_APPLY + 17 * p, m.ndof))
+    shapes = [1, 2, 0] + ([-1] if p == 7 else [])
+    outs = {}
+    for sh in shapes:
+        prob.set_apply_shape(sh)
+        assert prob.apply_shape() == sh
+        outs[sh] = to_np(prob.apply(u))
+    if p != 7:
+        with pytest.raises(dg.DgsError):
+            prob.set_apply_shape(-1)
+    prob.close()
+    for sh in shapes[1:]:
+        assert np.array_equal(outs[sh], outs[1]), sh
+    ref = oop.apply_operator(m, to_np(u).reshape(m.E, m.N, m.N, m.N), 1.5).reshape(-1)
+    assert rel_max(outs[1], ref) < 1e-13
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_brick_shape_solve_is_bit_identical(precision):
+    """The whole preconditioned solve (residuals with the fused subdomain-row
+    gather on every level) with bricks on every level equals the one with one
+    element per workgroup, bit for bit."""
+    import paper_2111_06767_amd as dg
+    announce(f"brick-shape solve 5x4x6 p=7 {precision}")
+    b = to_gpu(W.random_normal(3, 5 * 4 * 6 * 512))
+    sols = []
+    for sh in (1, -1):
+        prob = dg.Problem((0, 0, 0), (1, 1, 1), (5, 4, 6), 7, mg_levels=3, precision=precision)
+        for lev in range(3):
+            prob.set_apply_shape(sh, level=lev)
+        u, st = prob.solve(b)
+        sols.append((to_np(u), st["iterations"]))
+        prob.close()
+    assert sols[0][1] == sols[1][1]
+    assert np.array_equal(sols[0][0], sols[1][0])
