@@ -40,12 +40,12 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 MEASURED_TRAFFIC = {
     "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
-                       "sha256": "acbb470d24b5256f845ad4920d91d6039e1029da1d9c9be4f909b11c280fd046",
-                       "bytes": 65640243},
+                       "sha256": "208ecbb942fb030c242a5be8817da6d01c4abd800c51e701b7f8b85b1d6a7113",
+                       "bytes": 65640287},
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
-              "sha256": "6b6347979dcc519e55bbca6d7433e9455ee9c164a42d82a826956a3d61748b8d",
-              "bytes": 633190960},
+              "sha256": "ad72540737b17cda60f634aa8916a55faeedbd64a88271cf7eaafc6c4f36786a",
+              "bytes": 633420809},
 }
 
 
@@ -131,10 +131,12 @@ def time_apply(dg, elements, p, reps=100, warm=10, calibration_copy=False):
         out.copy_(u)
         torch.cuda.synchronize()
     n = prob.ndof
+    shape = prob.apply_shape()
     prob.close()
     del u, out
     torch.cuda.empty_cache()
-    return dict(elements=list(elements), p=p, ndof=n, ms_per_apply=ms, gdofs=n / (ms * 1e-3) / 1e9,
+    return dict(elements=list(elements), p=p, ndof=n, launch_shape=shape,
+                ms_per_apply=ms, gdofs=n / (ms * 1e-3) / 1e9,
                 algorithmic_bytes=16 * n, achieved_gbs=16 * n / (ms * 1e-3) / 1e9)
 
 
@@ -178,7 +180,7 @@ def time_c5(dg, steps=3):
     return out
 
 
-def run_serving(dg, n_requests=256, max_active=16, precision="mixed"):
+def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threads=0):
     """Poisson-process stream of solves (grids {2..6}^3, p in 3..8, cube sides
     1..4, random-Fourier sources): a closed-loop pass measures the saturation
     throughput, then requests arrive at 0.8 of it and p50/p99 latency and
@@ -193,7 +195,8 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed"):
         data.append((r, f))
 
     def closed_loop():
-        srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60)
+        srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60,
+                    host_threads=host_threads)
         t0 = time.perf_counter()
         for r, f in data:
             srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)
@@ -211,7 +214,8 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed"):
     warm_tput, its = closed_loop()
     rate = 0.8 * warm_tput
     gaps = np.array([r.arrival for r, _ in data]) / rate  # unit-rate arrivals rescaled
-    srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60)
+    srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60,
+                    host_threads=host_threads)
     t0 = time.perf_counter()
     nxt = 0
     ids = {}
@@ -275,6 +279,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
+    # host threads that issue the active requests' stages (0: the library default)
+    ap.add_argument("--serve-threads", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -316,7 +322,10 @@ def main():
                       "frac": round(roof_src["achieved_gbs"] / HBM_PEAK_GBS, 4),
                       "traffic": measured_traffic("apply") if apply_big else None,
                       "kernel": f"DG operator apply, {roof_src['elements']} elements "
-                                f"p={roof_src['p']}, 16 B/DOF algorithmic (read u, write Au)",
+                                f"p={roof_src['p']}, 16 B/DOF algorithmic (read u, write Au), "
+                                "launch shape " + ("2x2x2 element bricks" if roof_src["launch_shape"] < 0
+                                                   else f"{roof_src['launch_shape']} elements/workgroup"
+                                                   " (0: default)"),
                       "ms_per_launch": round(roof_src["ms_per_apply"], 5)}
     if apply_big:
         roofline_apply["calibration_copy_bytes"] = 8 * apply_big["ndof"]
@@ -326,7 +335,8 @@ def main():
     c5 = None if args.no_c5 else time_c5(dg)
     if not args.no_serving:
         _log(f"serving stream of {args.serve_requests} requests")
-    serving = None if args.no_serving else run_serving(dg, args.serve_requests)
+    serving = None if args.no_serving else run_serving(dg, args.serve_requests,
+                                                          host_threads=args.serve_threads)
 
     cpu = None
     u_oracle = None
