@@ -506,11 +506,12 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
   plan.small = !any_big;
   const int bm = plan.small ? 16 : (variant == 1 ? 64 : 32);
   // split K until there are enough tiles to fill the 256 compute units; the
-  // short K loops of few-subdomain levels are latency-bound, so they split
-  // further (the scatter sums the parts)
+  // short K loops of few-subdomain levels are latency-bound, so they may
+  // split further (up to 16 parts in variant 0, 4 in variant 1: more parts
+  // shorten the GEMM and lengthen the scatter that sums them)
   int base = 0;
   for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + kGemmN - 1) / kGemmN);
-  const int max_parts = plan.small ? kMaxParts : 4;
+  const int max_parts = plan.small ? (variant == 1 ? 4 : kMaxParts) : 4;
   plan.kparts = 1;
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
   for (int c = 0; c < (int)cls.size(); ++c) {

@@ -728,7 +728,7 @@ void autotune_gemm(dgs_problem* P, hipStream_t s) {
   HIP_OK(hipEventCreate(&e1));
   const int N = P->N;
   for (Level& L : P->levels) {
-    if (L.gemm_small || L.ntiles[0] == 0) continue;  // a single variant
+    if (L.ntiles[0] == 0) continue;
     const auto key = std::make_tuple(N, L.n[0], L.n[1], L.n[2], (int)L.f32, nov_of(P));
     int best = 0;
     bool cached = false;
