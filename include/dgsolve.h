@@ -191,7 +191,10 @@ int dgs_lgl_nodes(int p, double* xi);
  * keeps its mesh, multigrid hierarchy and Krylov basis resident until it
  * finishes, and shares the subdomain inverses of a process-wide cache.  Each
  * dgs_server_step admits what fits and advances every active request by one
- * FGMRES stage, each on its own stream, so requests overlap on the device;
+ * FGMRES stage, each on its own stream, so requests overlap on the device: it
+ * completes the stage a request has in flight and at once issues the next,
+ * so the device keeps working between calls.  Retired requests' memory is
+ * released in batches (freeing waits for the whole device);
  * a request's arithmetic is the same alone or in a mix (dgs_solve on the same
  * inputs gives the same bits).  The server_* calls come from one caller thread
  * at a time; the server's own worker threads share the stage work. */

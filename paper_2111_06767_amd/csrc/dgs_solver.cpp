@@ -1246,6 +1246,7 @@ struct ServerRequest {
   hipStream_t stream = nullptr;
   double *d_b = nullptr, *d_u = nullptr;
   FgmresRun run;
+  bool in_flight = false;  // a stage is issued on the stream and not yet completed
   std::vector<double> u;  // result
   FgmresResult result;
   double t_setup = 0;
@@ -1325,24 +1326,44 @@ class WorkerPool {
 
 }  // namespace
 
+// Device memory of a retired request, freed later in a batch: freeing waits
+// for the whole device, which would drain the other requests' stages.
+struct RetiredMemory {
+  dgs_problem* prob;
+  double *d_b, *d_u;
+  size_t footprint;
+};
+
 struct dgs_server {
   dgs_server_options opt{};
   int device = 0;
   std::unique_ptr<WorkerPool> pool;  // launching is host-bound: stages run in parallel
   long long next_id = 1;
-  size_t used = 0;
+  size_t used = 0;  // footprints of the active requests and of the unfreed retired ones
   std::vector<std::unique_ptr<ServerRequest>> queue, active;
   std::map<long long, std::unique_ptr<ServerRequest>> finished;
   std::vector<hipStream_t> free_streams;
+  std::vector<RetiredMemory> retired;
   double t0 = 0;
+  void free_retired() {
+    for (RetiredMemory& m : retired) {
+      delete m.prob;
+      (void)hipFree(m.d_b);
+      (void)hipFree(m.d_u);
+      used -= m.footprint;
+    }
+    retired.clear();
+  }
   ~dgs_server() {
     pool.reset();
     for (auto& r : active) {
+      if (r->stream) (void)hipStreamSynchronize(r->stream);  // a stage may be in flight
       if (r->prob) delete r->prob;
       if (r->d_b) (void)hipFree(r->d_b);
       if (r->d_u) (void)hipFree(r->d_u);
       if (r->stream) (void)hipStreamDestroy(r->stream);
     }
+    free_retired();
     for (hipStream_t st : free_streams) (void)hipStreamDestroy(st);
   }
 };
@@ -1357,9 +1378,16 @@ size_t request_footprint(const dgs_server* S, const int el[3], int p) {
   return (size_t)(ndof * 8.0 * vecs);
 }
 
+// Retired requests' memory is released in batches of this many, or sooner
+// when a queued request would otherwise not fit the budget.
+constexpr size_t kRetiredBatch = 16;
+
 void server_admit(dgs_server* S) {
+  if (S->retired.size() >= kRetiredBatch) S->free_retired();
   while (!S->queue.empty() && (int)S->active.size() < S->opt.max_active) {
     ServerRequest& r = *S->queue.front();
+    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && !S->retired.empty())
+      S->free_retired();
     if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && !S->active.empty()) break;
     if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && S->active.empty() &&
         r.footprint > (size_t)S->opt.hbm_budget_bytes) {
@@ -1410,14 +1438,11 @@ void server_retire(dgs_server* S, std::unique_ptr<ServerRequest> rq) {
   rq->result = rq->run.R;
   rq->status = rq->result.converged ? DGS_OK : DGS_NOT_CONVERGED;
   rq->t_done = now_s() - S->t0;
-  delete rq->prob;
+  S->retired.push_back(RetiredMemory{rq->prob, rq->d_b, rq->d_u, rq->footprint});
   rq->prob = nullptr;
-  (void)hipFree(rq->d_b);
-  (void)hipFree(rq->d_u);
   rq->d_b = rq->d_u = nullptr;
   S->free_streams.push_back(rq->stream);
   rq->stream = nullptr;
-  S->used -= rq->footprint;
   rq->f.clear();
   rq->f.shrink_to_fit();
   S->finished[rq->id] = std::move(rq);
@@ -1808,13 +1833,23 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
   return guarded([&]() -> int {
     if (!S) return fail(DGS_ERR_INVALID, "NULL argument");
     server_admit(S);
-    // each worker issues the next stage of every W-th request, then waits for
-    // those and completes them on the host (requests never share state)
+    // each worker takes every W-th request: it waits for the stage the
+    // request has in flight, completes it on the host and at once issues the
+    // next one, so every unfinished request leaves this call with a stage on
+    // the device and the device keeps working between calls (requests never
+    // share state)
     auto work = [S](size_t first, size_t stride) {
-      for (size_t i = first; i < S->active.size(); i += stride) S->active[i]->run.issue();
       for (size_t i = first; i < S->active.size(); i += stride) {
-        HIP_OK(hipStreamSynchronize(S->active[i]->stream));
-        S->active[i]->run.complete();
+        ServerRequest& r = *S->active[i];
+        if (r.in_flight) {
+          HIP_OK(hipStreamSynchronize(r.stream));
+          r.in_flight = false;
+          r.run.complete();
+        }
+        if (!r.run.done()) {
+          r.run.issue();
+          r.in_flight = true;
+        }
       }
     };
     if (S->pool && S->active.size() > 1) {
@@ -1831,6 +1866,7 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
         still.push_back(std::move(r));
     }
     S->active = std::move(still);
+    if (S->active.empty() && S->queue.empty()) S->free_retired();  // idle: return the memory
     if (n_active) *n_active = (int)S->active.size();
     if (n_queued) *n_queued = (int)S->queue.size();
     return DGS_OK;
