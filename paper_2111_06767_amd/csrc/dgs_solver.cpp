@@ -1382,14 +1382,40 @@ size_t request_footprint(const dgs_server* S, const int el[3], int p) {
 // when a queued request would otherwise not fit the budget.
 constexpr size_t kRetiredBatch = 16;
 
+// Set-up of one admitted request on its stream: problem (hierarchy, classes,
+// inverses from the cache), b = M f, u = 0, and the FGMRES state.
+void server_setup(dgs_server* S, ServerRequest& r) {
+  const double ta = now_s();
+  dgs_problem* prob = nullptr;
+  const int code = dgs_create_problem(&r.dom, r.elements, r.p, S->opt.penalty, &S->opt.solver,
+                                      r.stream, &prob);
+  if (code != DGS_OK) throw DgsError(code, g_last_error);
+  r.prob = prob;
+  const long long n = prob->nd(0);
+  r.d_b = dalloc<double>(n);
+  r.d_u = dalloc<double>(n);
+  // f to the device (pinned staging is not needed: a one-off copy), b = M f
+  HIP_OK(hipMemcpyAsync(r.d_u, r.f.data(), sizeof(double) * n, hipMemcpyHostToDevice, r.stream));
+  const Level& L0 = prob->levels[0];
+  HIP_OK(launch_mass(prob->N, r.d_u, r.d_b, L0.E, L0.h, prob->dt, r.stream));
+  HIP_OK(launch_fill(r.d_u, 0.0, n, r.stream));
+  r.run.init(prob, r.d_b, r.d_u, S->opt.solver.rtol, S->opt.solver.max_iter, r.stream);
+  r.t_setup = now_s() - ta;
+  r.t_admit = ta - S->t0;
+}
+
 void server_admit(dgs_server* S) {
   if (S->retired.size() >= kRetiredBatch) S->free_retired();
-  while (!S->queue.empty() && (int)S->active.size() < S->opt.max_active) {
+  // choose what fits, then set the chosen requests up in parallel (the
+  // set-up is host-bound; the requests already running keep the device busy)
+  std::vector<std::unique_ptr<ServerRequest>> admitted;
+  while (!S->queue.empty() && (int)(S->active.size() + admitted.size()) < S->opt.max_active) {
     ServerRequest& r = *S->queue.front();
     if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && !S->retired.empty())
       S->free_retired();
-    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && !S->active.empty()) break;
-    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && S->active.empty() &&
+    const bool none_running = S->active.empty() && admitted.empty();
+    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && !none_running) break;
+    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && none_running &&
         r.footprint > (size_t)S->opt.hbm_budget_bytes) {
       // can never fit: reject
       std::unique_ptr<ServerRequest> rq = std::move(S->queue.front());
@@ -1407,27 +1433,19 @@ void server_admit(dgs_server* S) {
     } else {
       HIP_OK(hipStreamCreateWithFlags(&rq->stream, hipStreamNonBlocking));
     }
-    const double ta = now_s();
-    dgs_problem* prob = nullptr;
-    const int code = dgs_create_problem(&rq->dom, rq->elements, rq->p, S->opt.penalty,
-                                        &S->opt.solver, rq->stream, &prob);
-    if (code != DGS_OK) throw DgsError(code, g_last_error);
-    rq->prob = prob;
-    const long long n = prob->nd(0);
-    rq->d_b = dalloc<double>(n);
-    rq->d_u = dalloc<double>(n);
-    // f to the device (pinned staging is not needed: a one-off copy), b = M f
-    HIP_OK(hipMemcpyAsync(rq->d_u, rq->f.data(), sizeof(double) * n, hipMemcpyHostToDevice,
-                          rq->stream));
-    const Level& L0 = prob->levels[0];
-    HIP_OK(launch_mass(prob->N, rq->d_u, rq->d_b, L0.E, L0.h, prob->dt, rq->stream));
-    HIP_OK(launch_fill(rq->d_u, 0.0, n, rq->stream));
-    rq->run.init(prob, rq->d_b, rq->d_u, S->opt.solver.rtol, S->opt.solver.max_iter, rq->stream);
-    rq->t_setup = now_s() - ta;
-    rq->t_admit = ta - S->t0;
     S->used += rq->footprint;
-    S->active.push_back(std::move(rq));
+    admitted.push_back(std::move(rq));
   }
+  if (admitted.empty()) return;
+  if (S->pool && admitted.size() > 1) {
+    const size_t W = (size_t)S->pool->size();
+    S->pool->run([&](int w) {
+      for (size_t i = (size_t)w; i < admitted.size(); i += W) server_setup(S, *admitted[i]);
+    });
+  } else {
+    for (auto& rq : admitted) server_setup(S, *rq);
+  }
+  for (auto& rq : admitted) S->active.push_back(std::move(rq));
 }
 
 void server_retire(dgs_server* S, std::unique_ptr<ServerRequest> rq) {
