@@ -866,10 +866,18 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
     b[l] = P->levels[l].d_b;
     u[l] = P->levels[l].d_u;
   }
+  // the coarsest level takes pre- and postsmoothing (Sec. III.C.3); when it
+  // is a single element with the plain operator, its one subdomain is the
+  // whole level and the subdomain solve is exact, so the first step already
+  // gives the solution and further steps would change it only by rounding
+  const Level& Lc = P->levels[nl - 1];
+  int coarse_steps = P->opt.pre_smooth + P->opt.post_smooth;
+  if (Lc.E == 1 && !(P->diag_active && Lc.d_diag != nullptr))
+    coarse_steps = std::min(coarse_steps, 1);
   // every level starts from zero: the first smoothing step writes u, so only
   // a level without smoothing steps needs clearing
   for (int l = 0; l < nl; ++l) {
-    const int steps = l < nl - 1 ? P->opt.pre_smooth : P->opt.pre_smooth + P->opt.post_smooth;
+    const int steps = l < nl - 1 ? P->opt.pre_smooth : coarse_steps;
     if (steps == 0) HIP_OK(launch_fill(u[l], 0.0, P->nd(l), s));
   }
   for (int l = 0; l < nl - 1; ++l) {
@@ -882,7 +890,7 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
     // the restriction also writes the coarse level's first r_S rows
     HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
   }
-  schwarz_steps(P, nl - 1, b[nl - 1], u[nl - 1], P->opt.pre_smooth + P->opt.post_smooth, true, s,
+  schwarz_steps(P, nl - 1, b[nl - 1], u[nl - 1], coarse_steps, true, s,
                 nl > 1 ? true : rs0_ready);
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = P->levels[l];
