@@ -170,10 +170,10 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 // Grouped subdomain GEMM of one level, one launch: DU_c = scale * RS_c * B_c
 // for every class c (B_c the stored transposed inverse, or with use_op the
 // stored A_S and factor scale_op).  Output tiles of BM rows (subdomains) by
-// kGemmN columns: BM = 16 when no class has more than kGemmSmallCount
+// BN columns: BM = 16, BN = 64 when no class has more than kGemmSmallCount
 // subdomains, with the K range split into up to 16 (variant 0) or 4
-// (variant 1) partial products; else BM = 32 (variant 0) or 64 (variant 1)
-// and up to 4 parts.  The set-up autotuner picks one per level.
+// (variant 1) partial products; else BM = 32 (variant 0) or 64 (variant 1),
+// BN = kGemmN and up to 4 parts.  The set-up autotuner picks one per level.
 constexpr int kGemmN = 128, kGemmSmallCount = 32;
 constexpr int kMaxParts = 16;  // split-K partial products (1, 2, 4, 8 or 16)
 constexpr int kGemmVariants = 2;

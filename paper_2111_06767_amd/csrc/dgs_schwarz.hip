@@ -510,7 +510,10 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
   // split further (up to 16 parts in variant 0, 4 in variant 1: more parts
   // shorten the GEMM and lengthen the scatter that sums them)
   int base = 0;
-  for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + kGemmN - 1) / kGemmN);
+  // few-subdomain levels: 16 x 64 tiles, twice as many and half as long as
+  // 16 x 128 ones (these launches are latency-bound)
+  const int bn = plan.small ? 64 : kGemmN;
+  for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + bn - 1) / bn);
   const int max_parts = plan.small ? (variant == 1 ? 4 : kMaxParts) : 4;
   plan.kparts = 1;
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
@@ -522,7 +525,7 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
     for (int part = 0; part < plan.kparts; ++part) {
       const int k0 = part * chunk, k1 = std::min(I.kext, (part + 1) * chunk);
       for (int m0 = 0; m0 < I.count; m0 += bm)
-        for (int n0 = 0; n0 < I.n; n0 += kGemmN)
+        for (int n0 = 0; n0 < I.n; n0 += bn)
           // an empty K range still writes zeros so every part is defined
           plan.tiles.push_back(GemmTile{c, m0, n0, part, k0, std::max(k0, k1)});
     }
@@ -539,7 +542,7 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     const float* a = (const float*)rs;
     float* c = (float*)du;
     if (small)
-      hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 2, 32>), grid, block, 0, s, a, c, ps, cls,
+      hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 1, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
     else if (variant == 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 1, 4, 32>), grid, block, 0, s, a, c, ps, cls,
@@ -551,7 +554,7 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     const double* a = (const double*)rs;
     double* c = (double*)du;
     if (small)
-      hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 2, 16>), grid, block, 0, s, a, c, ps, cls,
+      hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 1, 16>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
     else if (variant == 0)
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 1, 4, 16>), grid, block, 0, s, a, c, ps, cls,
