@@ -171,12 +171,13 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 // for every class c (B_c the stored transposed inverse, or with use_op the
 // stored A_S and factor scale_op).  Output tiles of BM rows (subdomains) by
 // BN columns: BM = 16, BN = 64 when no class has more than kGemmSmallCount
-// subdomains, with the K range split into up to 16 (variant 0) or 4
-// (variant 1) partial products; else BM = 32 (variant 0) or 64 (variant 1),
-// BN = kGemmN and up to 4 parts.  The set-up autotuner picks one per level.
+// subdomains, with the K range split into up to 16 (variant 0), 4 (variant 1)
+// or 8 (variant 2) partial products; else BM x BN = 32 x kGemmN (variant 0),
+// 64 x kGemmN (variant 1) or 32 x 64 (variant 2) and up to 4 parts.  The
+// set-up autotuner picks one per level.
 constexpr int kGemmN = 128, kGemmSmallCount = 32;
 constexpr int kMaxParts = 16;  // split-K partial products (1, 2, 4, 8 or 16)
-constexpr int kGemmVariants = 2;
+constexpr int kGemmVariants = 3;
 struct GemmPlan {
   std::vector<GemmTile> tiles;
   bool small = false;

@@ -505,16 +505,18 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
   // the few partly filled tiles of small classes run beside the large ones
   plan.small = !any_big;
   const int bm = plan.small ? 16 : (variant == 1 ? 64 : 32);
+  // few-subdomain levels: 16 x 64 tiles, twice as many and half as long as
+  // 16 x 128 ones (these launches are latency-bound); variant 2 of the large
+  // levels: 32 x 64 tiles, for levels whose 32 x 128 tiles leave the compute
+  // units short of work
+  const int bn = (plan.small || variant == 2) ? 64 : kGemmN;
   // split K until there are enough tiles to fill the 256 compute units; the
   // short K loops of few-subdomain levels are latency-bound, so they may
   // split further (up to 16 parts in variant 0, 4 in variant 1: more parts
   // shorten the GEMM and lengthen the scatter that sums them)
   int base = 0;
-  // few-subdomain levels: 16 x 64 tiles, twice as many and half as long as
-  // 16 x 128 ones (these launches are latency-bound)
-  const int bn = plan.small ? 64 : kGemmN;
   for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + bn - 1) / bn);
-  const int max_parts = plan.small ? (variant == 1 ? 4 : kMaxParts) : 4;
+  const int max_parts = plan.small ? (variant == 1 ? 4 : (variant == 2 ? 8 : kMaxParts)) : 4;
   plan.kparts = 1;
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
   for (int c = 0; c < (int)cls.size(); ++c) {
@@ -547,6 +549,9 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     else if (variant == 0)
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 1, 4, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
+    else if (variant == 2)
+      hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 1, 2, 32>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
     else
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
@@ -558,6 +563,9 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
                          tiles, use_op);
     else if (variant == 0)
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 1, 4, 16>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
+    else if (variant == 2)
+      hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 1, 2, 16>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
     else
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), grid, block, 0, s, a, c, ps, cls,
