@@ -184,7 +184,10 @@ struct Level {
   bool gemm_small = false;
   int kparts = 1;  // split-K factor of the class GEMMs
   int gemm_variant = 0;  // large-tile GEMM variant chosen by the autotuner
-  ApplyConfig acfg;      // operator-kernel launch shape chosen by the autotuner
+  // operator-kernel launch shapes chosen by the autotuner: acfg for the
+  // Schwarz residuals that write subdomain rows, acfg_out for the launches
+  // that write a vector (A u, residuals, the puncture residual)
+  ApplyConfig acfg, acfg_out;
   long long rs_total = 0;
   void* d_rs = nullptr;
   void* d_du = nullptr;
@@ -652,66 +655,105 @@ std::mutex g_tune_mutex;
 // the Schwarz steps launch most (residual with the gather written out) and
 // cached per level shape.  Each candidate's time is the best of 3 trials; a
 // later candidate must win by 3 % so near ties resolve the same way.
-std::map<std::tuple<int, long long, int, int, int>, int> g_tuned_epb;
+std::map<std::tuple<int, long long, int, int, int, int>, int> g_tuned_epb;
 
+ApplyConfig shape_config(const Level& L, int shape) {
+  ApplyConfig c;
+  c.epb = shape;
+  c.bricks = shape < 0 ? L.d_bricks : nullptr;
+  return c;
+}
+
+// Time `launch` (kernel launches on s): the minimum over `trials` trials of
+// a repetition count sized so that a trial lasts about `trial_ms`.
+template <typename F>
+float time_launches(F&& launch, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float trial_ms,
+                    int trials) {
+  launch();  // warm-up
+  HIP_OK(hipEventRecord(e0, s));
+  launch();
+  HIP_OK(hipEventRecord(e1, s));
+  HIP_OK(hipEventSynchronize(e1));
+  float one = 0;
+  HIP_OK(hipEventElapsedTime(&one, e0, e1));
+  const int reps = std::max(3, std::min(200, (int)(trial_ms / std::max(one, 1e-4f))));
+  float tmin = 1e30f;
+  for (int trial = 0; trial < trials; ++trial) {
+    HIP_OK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) launch();
+    HIP_OK(hipEventRecord(e1, s));
+    HIP_OK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    tmin = std::min(tmin, ms / reps);
+  }
+  return tmin;
+}
+
+// Per-level launch-shape autotuner of the operator kernel, once for each use:
+// the Schwarz residual with its subdomain-row stores (acfg) and the plain
+// apply that writes a vector (acfg_out).  Candidates are timed in order and
+// a later one must win by 3 %, so near ties resolve the same way every time.
 void autotune_apply(dgs_problem* P, hipStream_t s) {
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   const int N = P->N;
   for (Level& L : P->levels) {
-    const auto key = std::make_tuple(N, L.E, L.n[0], L.n[1], (int)L.f32);
-    {
-      std::lock_guard<std::mutex> lk(g_tune_mutex);
-      auto it = g_tuned_epb.find(key);
-      if (it != g_tuned_epb.end()) {
-        L.acfg.epb = it->second;
-        L.acfg.bricks = it->second < 0 ? L.d_bricks : nullptr;
-        continue;
-      }
-    }
     const long long n = L.E * (long long)N * N * N;
-    HIP_OK(launch_fill(L.d_u, 1.0, n, s));
-    HIP_OK(launch_fill(L.d_b, 0.0, n, s));
-    GatherOut go;
-    go.rs = L.d_rs;
-    go.f32 = L.f32;
-    go.pull = L.d_pull;
-    go.nov = nov_of(P);
-    // elements per workgroup; -1: 2 x 2 x 2 bricks
-    const int cands[4] = {1, 2, 0, -1};
-    const int ncand = L.d_bricks ? 4 : 3;
-    const int reps = L.E >= 4096 ? 3 : 8;
-    int best = cands[0];
-    float best_ms = 1e30f;
-    for (int ci = 0; ci < ncand; ++ci) {
-      const int c = cands[ci];
-      ApplyConfig cfg;
-      cfg.epb = c;
-      cfg.bricks = c < 0 ? L.d_bricks : nullptr;
-      HIP_OK(launch_apply(N, kResidual, L.d_u, nullptr, L.d_b, nullptr, nullptr, L.d_nbr, L.op,
-                          P->dt, cfg, s, L.d_order, go));  // warm-up
-      float tmin = 1e30f;
-      for (int trial = 0; trial < 3; ++trial) {
-        HIP_OK(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r)
-          HIP_OK(launch_apply(N, kResidual, L.d_u, nullptr, L.d_b, nullptr, nullptr, L.d_nbr, L.op,
-                              P->dt, cfg, s, L.d_order, go));
-        HIP_OK(hipEventRecord(e1, s));
-        HIP_OK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-        tmin = std::min(tmin, ms);
+    bool filled = false;
+    for (int use = 0; use < 2; ++use) {
+      ApplyConfig& target = use == 0 ? L.acfg : L.acfg_out;
+      const auto key = std::make_tuple(N, L.E, L.n[0], L.n[1], (int)L.f32, use);
+      {
+        std::lock_guard<std::mutex> lk(g_tune_mutex);
+        auto it = g_tuned_epb.find(key);
+        if (it != g_tuned_epb.end()) {
+          target = shape_config(L, it->second);
+          continue;
+        }
       }
-      if (tmin < 0.97f * best_ms) {
-        best_ms = tmin;
-        best = c;
+      if (!filled) {
+        HIP_OK(launch_fill(L.d_u, 1.0, n, s));
+        HIP_OK(launch_fill(L.d_b, 0.0, n, s));
+        filled = true;
       }
+      GatherOut go;
+      go.rs = L.d_rs;
+      go.f32 = L.f32;
+      go.pull = L.d_pull;
+      go.nov = nov_of(P);
+      // large levels are timed for longer: their choice matters and is
+      // made once per shape, while the small shapes of a serving stream are
+      // many and latency-bound
+      const float tune_ms = L.E >= 512 ? 0.5f : 0.1f;
+      const int tune_trials = L.E >= 512 ? 5 : 3;
+      // elements per workgroup; -1: 2 x 2 x 2 bricks
+      const int cands[4] = {1, 2, 0, -1};
+      const int ncand = L.d_bricks ? 4 : 3;
+      int best = cands[0];
+      float best_ms = 1e30f;
+      for (int ci = 0; ci < ncand; ++ci) {
+        const ApplyConfig cfg = shape_config(L, cands[ci]);
+        const float t = time_launches(
+            [&]() {
+              if (use == 0)
+                HIP_OK(launch_apply(N, kResidual, L.d_u, nullptr, L.d_b, nullptr, nullptr,
+                                    L.d_nbr, L.op, P->dt, cfg, s, L.d_order, go));
+              else
+                HIP_OK(launch_apply(N, kApply, L.d_u, L.d_r, nullptr, nullptr, nullptr, L.d_nbr,
+                                    L.op, P->dt, cfg, s, L.d_order));
+            },
+            s, e0, e1, tune_ms, tune_trials);
+        if (t < 0.97f * best_ms) {
+          best_ms = t;
+          best = cands[ci];
+        }
+      }
+      target = shape_config(L, best);
+      std::lock_guard<std::mutex> lk(g_tune_mutex);
+      g_tuned_epb[key] = best;
     }
-    L.acfg.epb = best;
-    L.acfg.bricks = best < 0 ? L.d_bricks : nullptr;
-    std::lock_guard<std::mutex> lk(g_tune_mutex);
-    g_tuned_epb[key] = best;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -748,25 +790,16 @@ void autotune_gemm(dgs_problem* P, hipStream_t s) {
       for (int v = 0; v < kGemmVariants; ++v) {
         L.gemm_variant = v;
         L.kparts = L.kparts_of[v];
-        auto sweep = [&]() {
-          HIP_OK(gemm_level(L, L.d_rs, L.rs_total, 0, s));
-          HIP_OK(launch_scatter(N, L.f32, L.d_u, L.d_du, L.kparts, L.rs_total, L.d_weights,
-                                L.d_pull, nov_of(P), L.E, s));
-        };
-        sweep();  // warm-up
-        float tmin = 1e30f;
-        for (int trial = 0; trial < 3; ++trial) {
-          HIP_OK(hipEventRecord(e0, s));
-          for (int r = 0; r < 3; ++r) sweep();
-          HIP_OK(hipEventRecord(e1, s));
-          HIP_OK(hipEventSynchronize(e1));
-          float ms = 0;
-          HIP_OK(hipEventElapsedTime(&ms, e0, e1));
-          tmin = std::min(tmin, ms);
-        }
+        const float t = time_launches(
+            [&]() {
+              HIP_OK(gemm_level(L, L.d_rs, L.rs_total, 0, s));
+              HIP_OK(launch_scatter(N, L.f32, L.d_u, L.d_du, L.kparts, L.rs_total, L.d_weights,
+                                    L.d_pull, nov_of(P), L.E, s));
+            },
+            s, e0, e1, L.E >= 512 ? 0.5f : 0.1f, L.E >= 512 ? 5 : 3);
         // a later variant must win by 3 % so near ties resolve the same way
-        if (tmin < 0.97f * best_ms) {
-          best_ms = tmin;
+        if (t < 0.97f * best_ms) {
+          best_ms = t;
           best = v;
         }
       }
@@ -885,7 +918,7 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
     schwarz_steps(P, l, b[l], u[l], P->opt.pre_smooth, true, s, l == 0 ? rs0_ready : true);
     const bool diag = P->diag_active && L.d_diag != nullptr;
     HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u[l], L.d_r, b[l], L.d_diag, nullptr,
-                        L.d_nbr, L.op, P->dt, L.acfg, s, L.d_order));
+                        L.d_nbr, L.op, P->dt, L.acfg_out, s, L.d_order));
     Level& C = P->levels[l + 1];
     // the restriction also writes the coarse level's first r_S rows
     HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
@@ -980,14 +1013,14 @@ void apply_fine(dgs_problem* P, const double* x, double* y, hipStream_t s,
   Level& L = P->levels[0];
   const bool diag = P->diag_active && L.d_diag != nullptr;
   HIP_OK(launch_apply(P->N, diag ? kApplyDiag : kApply, x, y, nullptr, L.d_diag, nullptr, L.d_nbr,
-                      L.op, P->dt, L.acfg, s, L.d_order, GatherOut{}, xcopy));
+                      L.op, P->dt, L.acfg_out, s, L.d_order, GatherOut{}, xcopy));
 }
 
 void residual_fine(dgs_problem* P, const double* x, const double* b, double* r, hipStream_t s) {
   Level& L = P->levels[0];
   const bool diag = P->diag_active && L.d_diag != nullptr;
   HIP_OK(launch_apply(P->N, diag ? kResidualDiag : kResidual, x, r, b, L.d_diag, nullptr, L.d_nbr,
-                      L.op, P->dt, L.acfg, s, L.d_order));
+                      L.op, P->dt, L.acfg_out, s, L.d_order));
 }
 
 // Make subsequent smoothing, V-cycles and solves act on A + diag(d): copy d
@@ -1606,7 +1639,7 @@ int dgs_apply_operator(dgs_problem* prob, const double* u, double* Au, void* str
     if (u == Au) return fail(DGS_ERR_INVALID, "u and Au must not overlap");
     Level& L = prob->levels[0];
     HIP_OK(launch_apply(prob->N, kApply, u, Au, nullptr, nullptr, nullptr, L.d_nbr, L.op, prob->dt,
-                        L.acfg, as_stream(stream), L.d_order));
+                        L.acfg_out, as_stream(stream), L.d_order));
     return DGS_OK;
   });
 }
@@ -1647,8 +1680,7 @@ int dgs_set_apply_shape(dgs_problem* prob, int level, int shape) {
     Level& L = prob->levels[level];
     if (shape < -1 || shape > 2) return fail(DGS_ERR_INVALID, "unknown apply shape");
     if (shape == -1 && !L.d_bricks) return fail(DGS_ERR_INVALID, "bricks need p = 7");
-    L.acfg.epb = shape;
-    L.acfg.bricks = shape < 0 ? L.d_bricks : nullptr;
+    L.acfg = L.acfg_out = shape_config(L, shape);
     return DGS_OK;
   });
 }
@@ -1657,7 +1689,7 @@ int dgs_get_apply_shape(const dgs_problem* prob, int level, int* shape) {
   if (!prob || !shape) return fail(DGS_ERR_INVALID, "NULL argument");
   if (level < 0 || level >= (int)prob->levels.size())
     return fail(DGS_ERR_INVALID, "level out of range");
-  *shape = prob->levels[level].acfg.bricks ? -1 : prob->levels[level].acfg.epb;
+  *shape = prob->levels[level].acfg_out.epb;
   return DGS_OK;
 }
 
@@ -1713,7 +1745,7 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
     double* work = F + 4 * n;
     Level& L0 = P->levels[0];
     auto residual = [&](const double* x, double* out) {  // A x + M S(x) - b
-      HIP_OK(launch_apply(P->N, kPuncture, x, out, b, alpha, beta, L0.d_nbr, L0.op, P->dt, L0.acfg,
+      HIP_OK(launch_apply(P->N, kPuncture, x, out, b, alpha, beta, L0.d_nbr, L0.op, P->dt, L0.acfg_out,
                           s, L0.d_order));
     };
     auto norm2 = [&](const double* x) { return device_norm2(P, x, n, s); };
