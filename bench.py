@@ -107,7 +107,7 @@ def time_solves(prob, b, steps, warmup):
     return u, stats, times, total
 
 
-def time_apply(dg, elements, p, reps=100, warm=10, calibration_copy=False):
+def time_apply(dg, elements, p, reps=100, warm=10, calibration_copy=False, shape=None):
     """Average apply duration with HIP events on torch's current stream (the
     stream the library launches on).  With calibration_copy, one plain
     device-to-device copy of the input vector follows the timed applies: the
@@ -115,6 +115,8 @@ def time_apply(dg, elements, p, reps=100, warm=10, calibration_copy=False):
     import torch
     import workloads as W
     prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=1)
+    if shape is not None:
+        prob.set_apply_shape(shape)
     u = torch.as_tensor(W.random_normal(W.SEED_APPLY, prob.ndof)).cuda()
     out = torch.empty_like(u)
     for _ in range(warm):
@@ -281,6 +283,11 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=256)
     # host threads that issue the active requests' stages (0: the library default)
     ap.add_argument("--serve-threads", type=int, default=0)
+    # pin the autotuned choices of the two roofline kernels (the 8^3 p=6 mixed
+    # problem's fine-level GEMM variant, the 40^3 p=7 apply's launch shape), so
+    # that a profiled run launches the kernels an unprofiled run chose
+    ap.add_argument("--gemm-variant", type=int, default=None)
+    ap.add_argument("--apply-shape", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -294,6 +301,8 @@ def main():
     for prec in ("mixed", "fp64"):
         _log(f"8^3 p=6 {prec}: set-up and {args.warmup}+{args.steps} solves")
         prob, b, uex = build_c2(dg, prec)
+        if prec == "mixed" and args.gemm_variant is not None:
+            prob.set_gemm_variant(args.gemm_variant, level=0)
         u, st, times, total = time_solves(prob, b, args.steps, args.warmup)
         un = u.cpu().numpy()
         res[prec] = dict(prob=prob, u=un, stats=st, times=times, total=total,
@@ -307,14 +316,17 @@ def main():
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
     apply_c5 = time_apply(dg, (16, 16, 16), 7)
     apply_big = None if args.no_large_apply else time_apply(dg, (40, 40, 40), 7, reps=50,
-                                                             calibration_copy=True)
+                                                             calibration_copy=True,
+                                                             shape=args.apply_shape)
     roofline = {"bound": "mfma", "achieved": round(gemm["achieved_tflops"], 2),
                 "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(gemm["achieved_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic("subdomain_gemm"),
                 "kernel": "grouped subdomain-solve GEMM (FP32 MFMA) of one Schwarz sweep on the "
                           "8^3 p=6 fine level, 2 sum_S n_S^2 = "
-                          f"{gemm['flops_per_launch']:.4g} flop per launch",
+                          f"{gemm['flops_per_launch']:.4g} flop per launch, tile variant "
+                          f"{mixed['prob'].gemm_variant(0)}",
+                "gemm_variant": mixed["prob"].gemm_variant(0),
                 "ms_per_launch": round(gemm["ms_per_launch"], 5)}
     roof_src = apply_big or apply_c5
     roofline_apply = {"bound": "hbm", "achieved": round(roof_src["achieved_gbs"], 1),
@@ -327,6 +339,7 @@ def main():
                                                    else f"{roof_src['launch_shape']} elements/workgroup"
                                                    " (0: default)"),
                       "ms_per_launch": round(roof_src["ms_per_apply"], 5)}
+    roofline_apply["launch_shape"] = roof_src["launch_shape"]
     if apply_big:
         roofline_apply["calibration_copy_bytes"] = 8 * apply_big["ndof"]
 

@@ -173,12 +173,26 @@ int dgs_subdomain_solves(dgs_problem* prob, int level, int reps, double* flops, 
  *   0     the default group for p (256 / (p+1)^2 elements);
  *  -1     2 x 2 x 2 bricks of elements, whose in-brick face neighbours are
  *         read from on-chip memory (p = 7 only).
- * The autotuner sets one per level when the problem is created;
- * dgs_set_apply_shape overrides it (DGS_ERR_INVALID for a level outside
+ * The autotuner sets them per level when the problem is created, one for the
+ * Schwarz residual launches that store subdomain rows and one for the
+ * launches that write a vector (this entry's A u among them);
+ * dgs_set_apply_shape sets both (DGS_ERR_INVALID for a level outside
  * [0, levels) or a shape not listed / not available for p), and
- * dgs_get_apply_shape reads it into *shape. */
+ * dgs_get_apply_shape reads the vector-writing one into *shape. */
 int dgs_set_apply_shape(dgs_problem* prob, int level, int shape);
 int dgs_get_apply_shape(const dgs_problem* prob, int level, int* shape);
+
+/* Tile variant of the grouped subdomain-solve GEMM on multigrid level
+ * `level` (Sec. III.D.2 subdomain solves; the variant changes the tiling and
+ * the split of the K range, so results agree to rounding):
+ *   levels whose classes all have at most 32 subdomains: 16 x 64 tiles with
+ *   up to 16 (0), 4 (1) or 8 (2) K parts; other levels: 32 x 128 (0),
+ *   64 x 128 (1) or 32 x 64 (2) tiles with up to 4 K parts.
+ * The autotuner sets one per level when the problem is created;
+ * dgs_set_gemm_variant overrides it (DGS_ERR_INVALID for a level outside
+ * [0, levels) or a variant outside [0, 2]), dgs_get_gemm_variant reads it. */
+int dgs_set_gemm_variant(dgs_problem* prob, int level, int variant);
+int dgs_get_gemm_variant(const dgs_problem* prob, int level, int* variant);
 
 /* The p+1 Legendre-Gauss-Lobatto points on [-1, 1] (ascending), so that a
  * caller can place its data: point (i, j, k) of element (e_x, e_y, e_z) sits at

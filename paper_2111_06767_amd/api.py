@@ -30,7 +30,7 @@ EXPORTED = (
     "dgs_precondition", "dgs_solve", "dgs_newton_solve", "dgs_last_error", "dgs_set_diagonal",
     "dgs_lgl_nodes", "dgs_server_create", "dgs_server_destroy", "dgs_server_submit",
     "dgs_server_step", "dgs_server_finished", "dgs_server_fetch", "dgs_subdomain_solves",
-    "dgs_set_apply_shape", "dgs_get_apply_shape",
+    "dgs_set_apply_shape", "dgs_get_apply_shape", "dgs_set_gemm_variant", "dgs_get_gemm_variant",
 )
 
 
@@ -114,6 +114,8 @@ def load_library(path: str = LIB_PATH):
                                          ctypes.POINTER(ctypes.c_double), P]
     lib.dgs_set_apply_shape.argtypes = [P, ctypes.c_int, ctypes.c_int]
     lib.dgs_get_apply_shape.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.dgs_set_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.c_int]
+    lib.dgs_get_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.dgs_last_error.argtypes = []
     lib.dgs_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -241,6 +243,16 @@ class Problem:
     def set_apply_shape(self, shape, level=0):
         """Override the autotuned operator-kernel launch shape of `level`."""
         _check(self._lib.dgs_set_apply_shape(self._h, int(level), int(shape)))
+
+    def gemm_variant(self, level=0):
+        """Tile variant (0, 1, 2) of the subdomain-solve GEMM on `level`."""
+        v = ctypes.c_int()
+        _check(self._lib.dgs_get_gemm_variant(self._h, int(level), ctypes.byref(v)))
+        return v.value
+
+    def set_gemm_variant(self, variant, level=0):
+        """Override the autotuned GEMM tile variant of `level`."""
+        _check(self._lib.dgs_set_gemm_variant(self._h, int(level), int(variant)))
 
     def set_diagonal(self, d=None, stream=None):
         """Operator A + diag(d) for smoothing, preconditioning and solves (None: A)."""

@@ -1685,6 +1685,27 @@ int dgs_set_apply_shape(dgs_problem* prob, int level, int shape) {
   });
 }
 
+int dgs_set_gemm_variant(dgs_problem* prob, int level, int variant) {
+  return guarded([&]() -> int {
+    if (!prob) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (level < 0 || level >= (int)prob->levels.size())
+      return fail(DGS_ERR_INVALID, "level out of range");
+    if (variant < 0 || variant >= kGemmVariants) return fail(DGS_ERR_INVALID, "unknown variant");
+    Level& L = prob->levels[level];
+    L.gemm_variant = variant;
+    L.kparts = L.kparts_of[variant];
+    return DGS_OK;
+  });
+}
+
+int dgs_get_gemm_variant(const dgs_problem* prob, int level, int* variant) {
+  if (!prob || !variant) return fail(DGS_ERR_INVALID, "NULL argument");
+  if (level < 0 || level >= (int)prob->levels.size())
+    return fail(DGS_ERR_INVALID, "level out of range");
+  *variant = prob->levels[level].gemm_variant;
+  return DGS_OK;
+}
+
 int dgs_get_apply_shape(const dgs_problem* prob, int level, int* shape) {
   if (!prob || !shape) return fail(DGS_ERR_INVALID, "NULL argument");
   if (level < 0 || level >= (int)prob->levels.size())
