@@ -40,12 +40,12 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 MEASURED_TRAFFIC = {
     "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
-                       "sha256": "208ecbb942fb030c242a5be8817da6d01c4abd800c51e701b7f8b85b1d6a7113",
-                       "bytes": 65640287},
+                       "sha256": "564137d29ffe0c22f5e1f7f5105854cd31b591581ad649b63c46f89e2af09412",
+                       "bytes": 89161633},
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
-              "sha256": "ad72540737b17cda60f634aa8916a55faeedbd64a88271cf7eaafc6c4f36786a",
-              "bytes": 633420809},
+              "sha256": "a735d1960f4035b420a06bdfde5a1a3da83b6d10989757cd9a753531e0c6727f",
+              "bytes": 633577790},
 }
 
 
