@@ -199,7 +199,7 @@ int dgs_get_gemm_variant(const dgs_problem* prob, int level, int* variant);
  * x = lower_x + h_x (e_x + (xi_i + 1) / 2), and likewise in y and z. */
 int dgs_lgl_nodes(int p, double* xi);
 
-/* ---- Serving: continuous batching of many Poisson solves on one device ----
+/* ---- Serving: continuous batching of many Poisson and puncture solves on one device ----
  * Requests queue until their estimated device footprint fits in
  * hbm_budget_bytes and one of max_active slots is free; every admitted request
  * keeps its mesh, multigrid hierarchy and Krylov basis resident until it
@@ -229,6 +229,19 @@ int dgs_server_destroy(dgs_server* server);
  * the canonical layout) is copied.  *id receives the request id. */
 int dgs_server_submit(dgs_server* server, const dgs_domain* domain, const int elements[3], int p,
                       const double* f, long long n, long long* id);
+/* Queue the puncture equation Laplace(u) + beta (alpha (1+u) + 1)^-7 = f in
+ * the DG form A u + M S(u) = b of dgs_newton_solve (Sec. III.A), with u = 0
+ * on the box and u0 = 0: alpha, beta and b (host, n values each in the
+ * canonical layout; b may be NULL for b = 0) are copied.  Its stages are
+ * Newton steps: each linearises, solves the linear system with FGMRES to
+ * linear_rtol and line-searches, on a server worker thread.  Converged when
+ * ||F(u)|| <= newton_rtol ||F(0)||, else it stops after max_newton steps.
+ * dgs_server_fetch fills newton_steps and backtracks.  *id receives the id. */
+int dgs_server_submit_puncture(dgs_server* server, const dgs_domain* domain,
+                               const int elements[3], int p, const double* alpha,
+                               const double* beta, const double* b, long long n,
+                               double newton_rtol, double linear_rtol, int max_newton,
+                               long long* id);
 /* Admit, then advance every active request by one stage; reports the counts. */
 int dgs_server_step(dgs_server* server, int* n_active, int* n_queued);
 /* Ids of finished requests (up to capacity) and their number. */

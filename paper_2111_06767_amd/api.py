@@ -31,6 +31,7 @@ EXPORTED = (
     "dgs_lgl_nodes", "dgs_server_create", "dgs_server_destroy", "dgs_server_submit",
     "dgs_server_step", "dgs_server_finished", "dgs_server_fetch", "dgs_subdomain_solves",
     "dgs_set_apply_shape", "dgs_get_apply_shape", "dgs_set_gemm_variant", "dgs_get_gemm_variant",
+    "dgs_server_submit_puncture",
 )
 
 
@@ -104,6 +105,11 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_server_submit.argtypes = [P, ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
                                       ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                       ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]
+    lib.dgs_server_submit_puncture.argtypes = [
+        P, ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+        ctypes.POINTER(ctypes.c_double), ctypes.c_longlong, ctypes.c_double, ctypes.c_double,
+        ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
     lib.dgs_server_step.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.dgs_server_finished.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]
@@ -363,6 +369,24 @@ class Server:
                                            int(p), f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                            f.size, ctypes.byref(rid)))
         self._sizes[rid.value] = f.size
+        return rid.value
+
+    def submit_puncture(self, lower, upper, elements, p, alpha, beta, b=None, newton_rtol=1e-10,
+                        linear_rtol=1e-4, max_newton=20):
+        """Queue the puncture equation A u + M S(u) = b (b = 0 when None), u = 0 on the
+        box, solved by Newton from u0 = 0; alpha, beta, b are host arrays at the points."""
+        import numpy as np
+        dp = ctypes.POINTER(ctypes.c_double)
+        a = np.ascontiguousarray(alpha, dtype=np.float64).reshape(-1)
+        be = np.ascontiguousarray(beta, dtype=np.float64).reshape(-1)
+        bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+        dom = Domain((ctypes.c_double * 3)(*lower), (ctypes.c_double * 3)(*upper))
+        rid = ctypes.c_longlong()
+        _check(self._lib.dgs_server_submit_puncture(
+            self._h, ctypes.byref(dom), (ctypes.c_int * 3)(*elements), int(p), a.ctypes.data_as(dp),
+            be.ctypes.data_as(dp), None if bb is None else bb.ctypes.data_as(dp), a.size,
+            float(newton_rtol), float(linear_rtol), int(max_newton), ctypes.byref(rid)))
+        self._sizes[rid.value] = a.size
         return rid.value
 
     def step(self):

@@ -1228,6 +1228,114 @@ FgmresResult fgmres(dgs_problem* P, const double* b, double* x, double rtol, int
   return run.R;
 }
 
+// Newton-Raphson with a backtracking line search (Sec. III.A) as a resumable
+// run: init() evaluates the first residual, each step() performs one Newton
+// step (linearise, solve the linear system with FGMRES to linear_rtol, line
+// search) and waits for it; done() once converged or after max_newton steps.
+struct NewtonRun {
+  dgs_problem* P = nullptr;
+  const double *alpha = nullptr, *beta = nullptr, *b = nullptr;
+  double* u = nullptr;
+  double newton_rtol = 0, linear_rtol = 0;
+  int max_newton = 0;
+  hipStream_t s = nullptr;
+  long long n = 0;
+  double *F = nullptr, *Ft = nullptr, *du = nullptr, *ut = nullptr, *work = nullptr;
+  double nrm2 = 0, norm0 = 0;
+  std::vector<double> hist;
+  int its = 0, steps = 0, backtracks = 0;
+  bool converged = false;
+
+  void residual(const double* x, double* out) {  // A x + M S(x) - b
+    const Level& L0 = P->levels[0];
+    HIP_OK(launch_apply(P->N, kPuncture, x, out, b, alpha, beta, L0.d_nbr, L0.op, P->dt,
+                        L0.acfg_out, s, L0.d_order));
+  }
+  void init(dgs_problem* p, const double* a, const double* be, const double* bb, double* uu,
+            double nrt, double lrt, int mn, hipStream_t st) {
+    P = p;
+    alpha = a;
+    beta = be;
+    b = bb;
+    u = uu;
+    newton_rtol = nrt;
+    linear_rtol = lrt;
+    max_newton = mn;
+    s = st;
+    n = P->nd(0);
+    ensure_krylov(P, P->opt.max_iter);
+    if (!P->d_newton) P->d_newton = P->alloc<double>((size_t)5 * n);
+    F = P->d_newton;
+    Ft = F + n;
+    du = F + 2 * n;
+    ut = F + 3 * n;
+    work = F + 4 * n;
+    P->diag_active = false;
+    residual(u, F);
+    nrm2 = device_norm2(P, F, n, s);
+    if (!std::isfinite(nrm2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite nonlinear residual");
+    norm0 = std::sqrt(nrm2);
+    hist.assign(1, 1.0);
+    its = steps = backtracks = 0;
+    converged = norm0 == 0.0;
+  }
+  bool done() const { return converged || steps >= max_newton; }
+  double rel_residual() const { return std::sqrt(nrm2) / (norm0 > 0 ? norm0 : 1.0); }
+
+  void step() {
+    // linearisation A + diag(M dS/du(u)) and the linear solve for du
+    const Level& L0 = P->levels[0];
+    HIP_OK(launch_puncture_diag(P->N, alpha, beta, u, work, L0.E, L0.h, P->dt, s));
+    set_diagonal(P, work, s);
+    HIP_OK(launch_fill(work, 0.0, n, s));
+    HIP_OK(launch_axpy(work, -1.0, F, n, s));  // right-hand side -F
+    HIP_OK(launch_fill(du, 0.0, n, s));
+    FgmresResult R = fgmres(P, work, du, linear_rtol, P->opt.max_iter, s);
+    its += R.iterations;
+    P->diag_active = false;
+    // backtracking line search on f = |F|^2 / 2 with the linear model's slope
+    const double alpha_sd = 1e-4;  // sufficient-decrease parameter
+    const int max_bt = 10;
+    const double f0 = 0.5 * nrm2, slope = -nrm2;
+    double lam = 1.0, lam_prev = 0.0, f_prev = 0.0, ft = 0.0;
+    for (int bt = 0; bt <= max_bt; ++bt) {
+      HIP_OK(launch_waxpy(ut, u, lam, du, n, s));
+      residual(ut, Ft);
+      ft = 0.5 * device_norm2(P, Ft, n, s);
+      if (!std::isfinite(ft)) throw DgsError(DGS_ERR_NONFINITE, "non-finite trial residual");
+      if (ft <= f0 + alpha_sd * lam * slope || bt == max_bt) break;
+      double next;
+      if (bt == 0) {
+        next = -slope * lam * lam / (2.0 * (ft - f0 - slope * lam));
+      } else {
+        const double r1 = ft - f0 - lam * slope, r2 = f_prev - f0 - lam_prev * slope;
+        const double ca = (r1 / (lam * lam) - r2 / (lam_prev * lam_prev)) / (lam - lam_prev);
+        const double cb = (-lam_prev * r1 / (lam * lam) + lam * r2 / (lam_prev * lam_prev)) /
+                          (lam - lam_prev);
+        if (ca == 0.0) {
+          next = -slope / (2.0 * cb);
+        } else {
+          const double disc = std::max(cb * cb - 3.0 * ca * slope, 0.0);
+          next = (-cb + std::sqrt(disc)) / (3.0 * ca);
+        }
+      }
+      next = std::min(next, 0.5 * lam);
+      next = std::max(next, 0.1 * lam);
+      lam_prev = lam;
+      f_prev = ft;
+      lam = next;
+      ++backtracks;
+    }
+    HIP_OK(launch_copy(u, ut, n, s));
+    std::swap(F, Ft);
+    nrm2 = 2.0 * ft;
+    ++steps;
+    hist.push_back(std::sqrt(nrm2) / norm0);
+    converged = std::sqrt(nrm2) <= newton_rtol * norm0;
+    HIP_OK(hipStreamSynchronize(s));
+  }
+};
+
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
@@ -1288,6 +1396,16 @@ struct ServerRequest {
   double *d_b = nullptr, *d_u = nullptr;
   FgmresRun run;
   bool in_flight = false;  // a stage is issued on the stream and not yet completed
+  // puncture requests (kind 1): Newton steps are the stages
+  int kind = 0;
+  std::vector<double> alpha, beta;  // host copies of the fields (b stays in f)
+  bool has_b = false;
+  double *d_alpha = nullptr, *d_beta = nullptr;
+  double newton_rtol = 0, linear_rtol = 0;
+  int max_newton = 0;
+  NewtonRun nrun;
+  int newton_steps = 0, backtracks = 0;
+  bool done() const { return kind == 0 ? run.done() : nrun.done(); }
   std::vector<double> u;  // result
   FgmresResult result;
   double t_setup = 0;
@@ -1371,7 +1489,7 @@ class WorkerPool {
 // for the whole device, which would drain the other requests' stages.
 struct RetiredMemory {
   dgs_problem* prob;
-  double *d_b, *d_u;
+  double *d_b, *d_u, *d_alpha, *d_beta;
   size_t footprint;
 };
 
@@ -1389,8 +1507,8 @@ struct dgs_server {
   void free_retired() {
     for (RetiredMemory& m : retired) {
       delete m.prob;
-      (void)hipFree(m.d_b);
-      (void)hipFree(m.d_u);
+      for (double* d : {m.d_b, m.d_u, m.d_alpha, m.d_beta})
+        if (d) (void)hipFree(d);
       used -= m.footprint;
     }
     retired.clear();
@@ -1400,8 +1518,8 @@ struct dgs_server {
     for (auto& r : active) {
       if (r->stream) (void)hipStreamSynchronize(r->stream);  // a stage may be in flight
       if (r->prob) delete r->prob;
-      if (r->d_b) (void)hipFree(r->d_b);
-      if (r->d_u) (void)hipFree(r->d_u);
+      for (double* d : {r->d_b, r->d_u, r->d_alpha, r->d_beta})
+        if (d) (void)hipFree(d);
       if (r->stream) (void)hipStreamDestroy(r->stream);
     }
     free_retired();
@@ -1435,12 +1553,31 @@ void server_setup(dgs_server* S, ServerRequest& r) {
   const long long n = prob->nd(0);
   r.d_b = dalloc<double>(n);
   r.d_u = dalloc<double>(n);
-  // f to the device (pinned staging is not needed: a one-off copy), b = M f
-  HIP_OK(hipMemcpyAsync(r.d_u, r.f.data(), sizeof(double) * n, hipMemcpyHostToDevice, r.stream));
-  const Level& L0 = prob->levels[0];
-  HIP_OK(launch_mass(prob->N, r.d_u, r.d_b, L0.E, L0.h, prob->dt, r.stream));
-  HIP_OK(launch_fill(r.d_u, 0.0, n, r.stream));
-  r.run.init(prob, r.d_b, r.d_u, S->opt.solver.rtol, S->opt.solver.max_iter, r.stream);
+  if (r.kind == 0) {
+    // f to the device (pinned staging is not needed: a one-off copy), b = M f
+    HIP_OK(hipMemcpyAsync(r.d_u, r.f.data(), sizeof(double) * n, hipMemcpyHostToDevice, r.stream));
+    const Level& L0 = prob->levels[0];
+    HIP_OK(launch_mass(prob->N, r.d_u, r.d_b, L0.E, L0.h, prob->dt, r.stream));
+    HIP_OK(launch_fill(r.d_u, 0.0, n, r.stream));
+    r.run.init(prob, r.d_b, r.d_u, S->opt.solver.rtol, S->opt.solver.max_iter, r.stream);
+  } else {
+    // the puncture equation: alpha, beta and b (zero when not given) to the
+    // device, u0 = 0, and the first nonlinear residual
+    r.d_alpha = dalloc<double>(n);
+    r.d_beta = dalloc<double>(n);
+    HIP_OK(hipMemcpyAsync(r.d_alpha, r.alpha.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                          r.stream));
+    HIP_OK(hipMemcpyAsync(r.d_beta, r.beta.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                          r.stream));
+    if (r.has_b)
+      HIP_OK(hipMemcpyAsync(r.d_b, r.f.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                            r.stream));
+    else
+      HIP_OK(launch_fill(r.d_b, 0.0, n, r.stream));
+    HIP_OK(launch_fill(r.d_u, 0.0, n, r.stream));
+    r.nrun.init(prob, r.d_alpha, r.d_beta, r.d_b, r.d_u, r.newton_rtol, r.linear_rtol,
+                r.max_newton, r.stream);
+  }
   r.t_setup = now_s() - ta;
   r.t_admit = ta - S->t0;
 }
@@ -1494,12 +1631,26 @@ void server_retire(dgs_server* S, std::unique_ptr<ServerRequest> rq) {
   rq->u.resize(n);
   HIP_OK(hipMemcpyAsync(rq->u.data(), rq->d_u, sizeof(double) * n, hipMemcpyDeviceToHost, rq->stream));
   HIP_OK(hipStreamSynchronize(rq->stream));
-  rq->result = rq->run.R;
+  if (rq->kind == 0) {
+    rq->result = rq->run.R;
+  } else {
+    rq->result.iterations = rq->nrun.its;
+    rq->result.rel_residual = rq->nrun.rel_residual();
+    rq->result.converged = rq->nrun.converged;
+    rq->result.history = rq->nrun.hist;
+    rq->newton_steps = rq->nrun.steps;
+    rq->backtracks = rq->nrun.backtracks;
+  }
   rq->status = rq->result.converged ? DGS_OK : DGS_NOT_CONVERGED;
   rq->t_done = now_s() - S->t0;
-  S->retired.push_back(RetiredMemory{rq->prob, rq->d_b, rq->d_u, rq->footprint});
+  S->retired.push_back(
+      RetiredMemory{rq->prob, rq->d_b, rq->d_u, rq->d_alpha, rq->d_beta, rq->footprint});
   rq->prob = nullptr;
-  rq->d_b = rq->d_u = nullptr;
+  rq->d_b = rq->d_u = rq->d_alpha = rq->d_beta = nullptr;
+  rq->alpha.clear();
+  rq->alpha.shrink_to_fit();
+  rq->beta.clear();
+  rq->beta.shrink_to_fit();
   S->free_streams.push_back(rq->stream);
   rq->stream = nullptr;
   rq->f.clear();
@@ -1753,94 +1904,25 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
     if (!prob || !alpha || !beta || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
     if (!(newton_rtol > 0.0) || !(linear_rtol > 0.0) || max_newton < 1)
       return fail(DGS_ERR_INVALID, "invalid Newton tolerances");
-    dgs_problem* P = prob;
     hipStream_t s = as_stream(stream);
     const double t0 = now_s();
-    const long long n = P->nd(0);
-    ensure_krylov(P, P->opt.max_iter);
-    if (!P->d_newton) P->d_newton = P->alloc<double>((size_t)5 * n);
-    double* F = P->d_newton;
-    double* Ft = F + n;
-    double* du = F + 2 * n;
-    double* ut = F + 3 * n;
-    double* work = F + 4 * n;
-    Level& L0 = P->levels[0];
-    auto residual = [&](const double* x, double* out) {  // A x + M S(x) - b
-      HIP_OK(launch_apply(P->N, kPuncture, x, out, b, alpha, beta, L0.d_nbr, L0.op, P->dt, L0.acfg_out,
-                          s, L0.d_order));
-    };
-    auto norm2 = [&](const double* x) { return device_norm2(P, x, n, s); };
-    P->diag_active = false;
-    residual(u, F);
-    double nrm2 = norm2(F);
-    if (!std::isfinite(nrm2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite nonlinear residual");
-    const double norm0 = std::sqrt(nrm2);
-    std::vector<double> hist{1.0};
-    int its = 0, steps = 0, backtracks = 0;
-    bool converged = norm0 == 0.0;
-    const double alpha_sd = 1e-4;  // sufficient-decrease parameter
-    const int max_bt = 10;
-    for (int step = 0; step < max_newton && !converged; ++step) {
-      // linearisation A + diag(M dS/du(u)) and the linear solve for du
-      HIP_OK(launch_puncture_diag(P->N, alpha, beta, u, work, L0.E, L0.h, P->dt, s));
-      set_diagonal(P, work, s);
-      HIP_OK(launch_fill(work, 0.0, n, s));
-      HIP_OK(launch_axpy(work, -1.0, F, n, s));  // right-hand side -F
-      HIP_OK(launch_fill(du, 0.0, n, s));
-      FgmresResult R = fgmres(P, work, du, linear_rtol, P->opt.max_iter, s);
-      its += R.iterations;
-      P->diag_active = false;
-      // backtracking line search on f = |F|^2 / 2 with the linear model's slope
-      const double f0 = 0.5 * nrm2, slope = -nrm2;
-      double lam = 1.0, lam_prev = 0.0, f_prev = 0.0, ft = 0.0;
-      for (int bt = 0; bt <= max_bt; ++bt) {
-        HIP_OK(launch_waxpy(ut, u, lam, du, n, s));
-        residual(ut, Ft);
-        ft = 0.5 * norm2(Ft);
-        if (!std::isfinite(ft)) throw DgsError(DGS_ERR_NONFINITE, "non-finite trial residual");
-        if (ft <= f0 + alpha_sd * lam * slope || bt == max_bt) break;
-        double next;
-        if (bt == 0) {
-          next = -slope * lam * lam / (2.0 * (ft - f0 - slope * lam));
-        } else {
-          const double r1 = ft - f0 - lam * slope, r2 = f_prev - f0 - lam_prev * slope;
-          const double ca = (r1 / (lam * lam) - r2 / (lam_prev * lam_prev)) / (lam - lam_prev);
-          const double cb = (-lam_prev * r1 / (lam * lam) + lam * r2 / (lam_prev * lam_prev)) /
-                            (lam - lam_prev);
-          if (ca == 0.0) {
-            next = -slope / (2.0 * cb);
-          } else {
-            const double disc = std::max(cb * cb - 3.0 * ca * slope, 0.0);
-            next = (-cb + std::sqrt(disc)) / (3.0 * ca);
-          }
-        }
-        next = std::min(next, 0.5 * lam);
-        next = std::max(next, 0.1 * lam);
-        lam_prev = lam;
-        f_prev = ft;
-        lam = next;
-        ++backtracks;
-      }
-      HIP_OK(launch_copy(u, ut, n, s));
-      std::swap(F, Ft);
-      nrm2 = 2.0 * ft;
-      ++steps;
-      hist.push_back(std::sqrt(nrm2) / norm0);
-      converged = std::sqrt(nrm2) <= newton_rtol * norm0;
-    }
-    P->diag_active = false;
+    NewtonRun nr;
+    nr.init(prob, alpha, beta, b, u, newton_rtol, linear_rtol, max_newton, s);
+    while (!nr.done()) nr.step();
+    prob->diag_active = false;
     HIP_OK(hipStreamSynchronize(s));
+    const bool converged = nr.converged;
     if (stats) {
-      stats->iterations = its;
-      stats->newton_steps = steps;
-      stats->backtracks = backtracks;
-      stats->rel_residual = std::sqrt(nrm2) / (norm0 > 0 ? norm0 : 1.0);
+      stats->iterations = nr.its;
+      stats->newton_steps = nr.steps;
+      stats->backtracks = nr.backtracks;
+      stats->rel_residual = nr.rel_residual();
       stats->t_solve_s = now_s() - t0;
-      stats->t_setup_s = P->t_setup;
+      stats->t_setup_s = prob->t_setup;
       stats->history_len = 0;
       if (stats->history && stats->history_capacity > 0) {
-        const int m = std::min<int>(stats->history_capacity, (int)hist.size());
-        for (int i = 0; i < m; ++i) stats->history[i] = hist[i];
+        const int m = std::min<int>(stats->history_capacity, (int)nr.hist.size());
+        for (int i = 0; i < m; ++i) stats->history[i] = nr.hist[i];
         stats->history_len = m;
       }
     }
@@ -1908,6 +1990,43 @@ int dgs_server_submit(dgs_server* S, const dgs_domain* domain, const int element
   });
 }
 
+int dgs_server_submit_puncture(dgs_server* S, const dgs_domain* domain, const int elements[3],
+                               int p, const double* alpha, const double* beta, const double* b,
+                               long long n, double newton_rtol, double linear_rtol,
+                               int max_newton, long long* id) {
+  return guarded([&]() -> int {
+    if (!S || !domain || !elements || !alpha || !beta || !id)
+      return fail(DGS_ERR_INVALID, "NULL argument");
+    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 8]");
+    for (int d = 0; d < 3; ++d)
+      if (elements[d] < 1 || !(domain->upper[d] > domain->lower[d]))
+        return fail(DGS_ERR_INVALID, "bad mesh");
+    if (!(newton_rtol > 0.0) || !(linear_rtol > 0.0) || max_newton < 1)
+      return fail(DGS_ERR_INVALID, "invalid Newton tolerances");
+    const long long nd = (long long)elements[0] * elements[1] * elements[2] * (p + 1) * (p + 1) * (p + 1);
+    if (n != nd) return fail(DGS_ERR_INVALID, "fields have the wrong length");
+    std::unique_ptr<ServerRequest> r(new ServerRequest());
+    r->id = S->next_id++;
+    r->kind = 1;
+    r->dom = *domain;
+    for (int d = 0; d < 3; ++d) r->elements[d] = elements[d];
+    r->p = p;
+    r->alpha.assign(alpha, alpha + n);
+    r->beta.assign(beta, beta + n);
+    r->has_b = b != nullptr;
+    if (b) r->f.assign(b, b + n);
+    r->newton_rtol = newton_rtol;
+    r->linear_rtol = linear_rtol;
+    r->max_newton = max_newton;
+    // the Poisson footprint plus alpha, beta and the Newton work vectors
+    r->footprint = request_footprint(S, elements, p) + (size_t)(7.0 * 8.0 * (double)n);
+    r->t_submit = now_s() - S->t0;
+    *id = r->id;
+    S->queue.push_back(std::move(r));
+    return DGS_OK;
+  });
+}
+
 int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
   return guarded([&]() -> int {
     if (!S) return fail(DGS_ERR_INVALID, "NULL argument");
@@ -1920,6 +2039,10 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
     auto work = [S](size_t first, size_t stride) {
       for (size_t i = first; i < S->active.size(); i += stride) {
         ServerRequest& r = *S->active[i];
+        if (r.kind == 1) {  // a Newton step runs to its end on the worker
+          if (!r.nrun.done()) r.nrun.step();
+          continue;
+        }
         if (r.in_flight) {
           HIP_OK(hipStreamSynchronize(r.stream));
           r.in_flight = false;
@@ -1939,7 +2062,7 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
     }
     std::vector<std::unique_ptr<ServerRequest>> still;
     for (auto& r : S->active) {
-      if (r->run.done())
+      if (r->done())
         server_retire(S, std::move(r));
       else
         still.push_back(std::move(r));
@@ -1983,8 +2106,8 @@ int dgs_server_fetch(dgs_server* S, long long id, double* u, long long n, dgs_st
     }
     if (stats) {
       stats->iterations = r.result.iterations;
-      stats->newton_steps = 0;
-      stats->backtracks = 0;
+      stats->newton_steps = r.newton_steps;
+      stats->backtracks = r.backtracks;
       stats->rel_residual = r.result.rel_residual;
       stats->t_setup_s = r.t_setup;
       stats->t_solve_s = r.t_done - r.t_admit;

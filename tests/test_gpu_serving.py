@@ -100,3 +100,46 @@ def test_served_result_solves_oracle_equations():
     b = oop.apply_mass(m, f.reshape(m.E, m.N, m.N, m.N)).reshape(-1)
     r = b - oop.apply_operator(m, u.reshape(m.E, m.N, m.N, m.N), 1.5).reshape(-1)
     assert np.linalg.norm(r) / np.linalg.norm(b) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_puncture_requests_in_a_mix_equal_newton_alone(precision):
+    """Nonlinear puncture requests (Newton steps as stages) served beside
+    Poisson requests give the bits of a solo dgs_newton_solve, and their
+    solutions satisfy the oracle's nonlinear DG equations."""
+    import paper_2111_06767_amd as dg
+    from oracle import newton as onewton
+    from tests.test_gpu_newton import _puncture
+    announce(f"serving puncture + Poisson mix {precision}")
+    opts = dict(precision=precision, max_iter=60, subdomain_iters=3)
+    punct = [((2, 2, 2), 4), ((3, 2, 2), 3)]
+    fields = [_puncture(el, p) for el, p in punct]
+    srv = dg.Server(hbm_budget_bytes=32e9, max_active=4, host_threads=2, **opts)
+    ids = []
+    for (el, p), (m, alpha, beta) in zip(punct, fields):
+        ids.append(("n", el, p, srv.submit_puncture((-20,) * 3, (20,) * 3, el, p, alpha, beta,
+                                                     newton_rtol=1e-10, linear_rtol=1e-4)))
+        el2, p2, side = REQS[len(ids)]
+        ids.append(("p", el2, p2, srv.submit((0, 0, 0), (side,) * 3, el2, p2,
+                                             _f(el2, p2, side, 70 + len(ids)))))
+    while srv.step() != (0, 0):
+        pass
+    for kind, el, p, rid in ids:
+        u, st, _ = srv.fetch(rid)
+        assert st["converged"], (kind, el, p, st)
+        if kind != "n":
+            continue
+        m, alpha, beta = fields[punct.index((el, p))]
+        prob = dg.Problem((-20,) * 3, (20,) * 3, el, p, **opts)
+        u1, st1 = prob.newton_solve(to_gpu(alpha), to_gpu(beta), newton_rtol=1e-10,
+                                    linear_rtol=1e-4)
+        prob.close()
+        assert st["newton_steps"] == st1["newton_steps"] and st["iterations"] == st1["iterations"]
+        assert np.array_equal(u, to_np(u1))
+        N = p + 1
+        F = lambda v: oop.apply_operator(m, v.reshape(m.E, N, N, N), 1.5,
+                                         source=onewton.puncture_source(alpha, beta, v)
+                                         .reshape(m.E, N, N, N))
+        r0 = np.linalg.norm(F(np.zeros(m.ndof)))
+        assert np.linalg.norm(F(u)) / r0 <= 1.5e-10
+    srv.close()
