@@ -315,6 +315,13 @@ def main():
     gemm = time_subdomain_gemm(mixed["prob"])
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
     apply_c5 = time_apply(dg, (16, 16, 16), 7)
+    # every degree at about 2 M DOFs (n^3 (p+1)^3)
+    sweep = {}
+    for p, n in ((3, 32), (4, 25), (5, 21), (6, 18), (7, 16), (8, 14)):
+        r = time_apply(dg, (n, n, n), p, reps=50, warm=5)
+        sweep[f"p{p}_{n}^3"] = dict(ndof=r["ndof"], gdofs=round(r["gdofs"], 1),
+                                    achieved_gbs=round(r["achieved_gbs"], 1),
+                                    launch_shape=r["launch_shape"])
     apply_big = None if args.no_large_apply else time_apply(dg, (40, 40, 40), 7, reps=50,
                                                              calibration_copy=True,
                                                              shape=args.apply_shape)
@@ -384,7 +391,8 @@ def main():
         "mixed_vs_fp64_solution_rel_diff": sol_diff,
         "rms_error_vs_exact": {"mixed": mixed["err_exact"], "fp64": fp64["err_exact"]},
         "setup_s": {"mixed": round(mixed["setup_s"], 3), "fp64": round(fp64["setup_s"], 3)},
-        "apply": {"c2_shape": apply_c2, "16^3_p7": apply_c5, "40^3_p7": apply_big},
+        "apply": {"c2_shape": apply_c2, "16^3_p7": apply_c5, "40^3_p7": apply_big,
+                  "sweep_2M_dofs": sweep},
         "c5_16x16x16_p7": c5,
         "serving": serving,
         "roofline": roofline,
