@@ -207,8 +207,11 @@ int dgs_lgl_nodes(int p, double* xi);
  * dgs_server_step admits what fits and advances every active request by one
  * FGMRES stage, each on its own stream, so requests overlap on the device: it
  * completes the stage a request has in flight and at once issues the next,
- * so the device keeps working between calls.  Retired requests' memory is
- * released in batches (freeing waits for the whole device);
+ * so the device keeps working between calls.  A finished request's problem
+ * (hierarchy, Krylov basis, captured V-cycle graphs) stays resident for the
+ * next request of the same box, grid and degree (up to 32 are kept, their
+ * footprints counted against the budget); other memory is released in
+ * batches (freeing waits for the whole device);
  * a request's arithmetic is the same alone or in a mix (dgs_solve on the same
  * inputs gives the same bits).  The server_* calls come from one caller thread
  * at a time; the server's own worker threads share the stage work. */

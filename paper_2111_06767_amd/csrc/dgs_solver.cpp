@@ -11,6 +11,7 @@
 //                iteration for the Hessenberg column
 //   newton_solve Newton-Raphson with backtracking line search (Sec. III.A)
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1405,6 +1406,7 @@ struct ServerRequest {
   int max_newton = 0;
   NewtonRun nrun;
   int newton_steps = 0, backtracks = 0;
+  bool reused = false;  // set up on a finished request's problem of the same shape
   bool done() const { return kind == 0 ? run.done() : nrun.done(); }
   std::vector<double> u;  // result
   FgmresResult result;
@@ -1503,10 +1505,29 @@ struct dgs_server {
   std::map<long long, std::unique_ptr<ServerRequest>> finished;
   std::vector<hipStream_t> free_streams;
   std::vector<RetiredMemory> retired;
+  // finished requests' problems (hierarchy, inverses' class tables, Krylov
+  // basis, captured V-cycle graphs) kept for the next request of the same
+  // box, grid and degree; most recently used last.  Their footprints stay in
+  // `used` until they are freed.
+  struct Idle {
+    std::array<double, 6> box;
+    std::array<int, 4> grid;  // elements, p
+    dgs_problem* prob;
+    double *d_b, *d_u;
+    size_t footprint;
+  };
+  std::vector<Idle> idle;
   double t0 = 0;
+  void evict_idle(size_t keep) {  // oldest first, into the batch of frees
+    while (idle.size() > keep) {
+      Idle& m = idle.front();
+      retired.push_back(RetiredMemory{m.prob, m.d_b, m.d_u, nullptr, nullptr, m.footprint});
+      idle.erase(idle.begin());
+    }
+  }
   void free_retired() {
     for (RetiredMemory& m : retired) {
-      delete m.prob;
+      if (m.prob) delete m.prob;
       for (double* d : {m.d_b, m.d_u, m.d_alpha, m.d_beta})
         if (d) (void)hipFree(d);
       used -= m.footprint;
@@ -1522,6 +1543,7 @@ struct dgs_server {
         if (d) (void)hipFree(d);
       if (r->stream) (void)hipStreamDestroy(r->stream);
     }
+    evict_idle(0);
     free_retired();
     for (hipStream_t st : free_streams) (void)hipStreamDestroy(st);
   }
@@ -1540,19 +1562,24 @@ size_t request_footprint(const dgs_server* S, const int el[3], int p) {
 // Retired requests' memory is released in batches of this many, or sooner
 // when a queued request would otherwise not fit the budget.
 constexpr size_t kRetiredBatch = 16;
+// finished requests' problems kept resident for reuse
+constexpr size_t kIdleMax = 32;
 
 // Set-up of one admitted request on its stream: problem (hierarchy, classes,
 // inverses from the cache), b = M f, u = 0, and the FGMRES state.
 void server_setup(dgs_server* S, ServerRequest& r) {
   const double ta = now_s();
-  dgs_problem* prob = nullptr;
-  const int code = dgs_create_problem(&r.dom, r.elements, r.p, S->opt.penalty, &S->opt.solver,
-                                      r.stream, &prob);
-  if (code != DGS_OK) throw DgsError(code, g_last_error);
-  r.prob = prob;
+  if (!r.reused) {
+    dgs_problem* created = nullptr;
+    const int code = dgs_create_problem(&r.dom, r.elements, r.p, S->opt.penalty, &S->opt.solver,
+                                        r.stream, &created);
+    if (code != DGS_OK) throw DgsError(code, g_last_error);
+    r.prob = created;
+    r.d_b = dalloc<double>(created->nd(0));
+    r.d_u = dalloc<double>(created->nd(0));
+  }
+  dgs_problem* prob = r.prob;
   const long long n = prob->nd(0);
-  r.d_b = dalloc<double>(n);
-  r.d_u = dalloc<double>(n);
   if (r.kind == 0) {
     // f to the device (pinned staging is not needed: a one-off copy), b = M f
     HIP_OK(hipMemcpyAsync(r.d_u, r.f.data(), sizeof(double) * n, hipMemcpyHostToDevice, r.stream));
@@ -1589,12 +1616,24 @@ void server_admit(dgs_server* S) {
   std::vector<std::unique_ptr<ServerRequest>> admitted;
   while (!S->queue.empty() && (int)(S->active.size() + admitted.size()) < S->opt.max_active) {
     ServerRequest& r = *S->queue.front();
-    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && !S->retired.empty())
+    const std::array<double, 6> box = {r.dom.lower[0], r.dom.lower[1], r.dom.lower[2],
+                                       r.dom.upper[0], r.dom.upper[1], r.dom.upper[2]};
+    const std::array<int, 4> grid = {r.elements[0], r.elements[1], r.elements[2], r.p};
+    int match = -1;  // most recently used idle problem of this shape
+    for (int i = (int)S->idle.size() - 1; i >= 0 && match < 0; --i)
+      if (S->idle[i].box == box && S->idle[i].grid == grid) match = i;
+    // a reused problem's footprint is already counted
+    const size_t need = match >= 0 ? 0 : r.footprint;
+    const size_t budget = (size_t)S->opt.hbm_budget_bytes;
+    if (S->used + need > budget) {
+      S->evict_idle(0);
+      match = -1;
       S->free_retired();
+    }
+    const size_t need2 = match >= 0 ? 0 : r.footprint;
     const bool none_running = S->active.empty() && admitted.empty();
-    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && !none_running) break;
-    if (S->used + r.footprint > (size_t)S->opt.hbm_budget_bytes && none_running &&
-        r.footprint > (size_t)S->opt.hbm_budget_bytes) {
+    if (S->used + need2 > budget && !none_running) break;
+    if (S->used + need2 > budget && none_running && r.footprint > budget) {
       // can never fit: reject
       std::unique_ptr<ServerRequest> rq = std::move(S->queue.front());
       S->queue.erase(S->queue.begin());
@@ -1611,7 +1650,17 @@ void server_admit(dgs_server* S) {
     } else {
       HIP_OK(hipStreamCreateWithFlags(&rq->stream, hipStreamNonBlocking));
     }
-    S->used += rq->footprint;
+    if (match >= 0) {
+      const dgs_server::Idle m = S->idle[match];
+      S->idle.erase(S->idle.begin() + match);
+      rq->prob = m.prob;
+      rq->d_b = m.d_b;
+      rq->d_u = m.d_u;
+      rq->footprint = m.footprint;
+      rq->reused = true;
+    } else {
+      S->used += rq->footprint;
+    }
     admitted.push_back(std::move(rq));
   }
   if (admitted.empty()) return;
@@ -1643,8 +1692,16 @@ void server_retire(dgs_server* S, std::unique_ptr<ServerRequest> rq) {
   }
   rq->status = rq->result.converged ? DGS_OK : DGS_NOT_CONVERGED;
   rq->t_done = now_s() - S->t0;
-  S->retired.push_back(
-      RetiredMemory{rq->prob, rq->d_b, rq->d_u, rq->d_alpha, rq->d_beta, rq->footprint});
+  // the problem stays resident for the next request of its shape; the
+  // puncture fields go with the next batch of frees
+  S->idle.push_back(dgs_server::Idle{
+      {rq->dom.lower[0], rq->dom.lower[1], rq->dom.lower[2], rq->dom.upper[0], rq->dom.upper[1],
+       rq->dom.upper[2]},
+      {rq->elements[0], rq->elements[1], rq->elements[2], rq->p},
+      rq->prob, rq->d_b, rq->d_u, rq->footprint});
+  if (rq->d_alpha || rq->d_beta)
+    S->retired.push_back(RetiredMemory{nullptr, nullptr, nullptr, rq->d_alpha, rq->d_beta, 0});
+  S->evict_idle(kIdleMax);
   rq->prob = nullptr;
   rq->d_b = rq->d_u = rq->d_alpha = rq->d_beta = nullptr;
   rq->alpha.clear();

@@ -143,3 +143,28 @@ def test_puncture_requests_in_a_mix_equal_newton_alone(precision):
         r0 = np.linalg.norm(F(np.zeros(m.ndof)))
         assert np.linalg.norm(F(u)) / r0 <= 1.5e-10
     srv.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_reused_problems_give_the_bits_of_fresh_ones(precision):
+    """Requests of a shape seen before run on the finished request's resident
+    problem (hierarchy, Krylov basis, captured V-cycle graphs); with two slots
+    and repeated shapes most requests do, and each still equals a solo solve."""
+    import paper_2111_06767_amd as dg
+    announce(f"serving problem reuse {precision}")
+    shapes = [((2, 3, 2), 3, 1.0), ((3, 2, 2), 4, 2.0), ((2, 2, 2), 5, 1.0)]
+    reqs = [shapes[i % 3] + (90 + i,) for i in range(9)]
+    srv = dg.Server(hbm_budget_bytes=32e9, max_active=2, precision=precision, max_iter=60,
+                    host_threads=2)
+    ids = []
+    for el, p, side, seed in reqs:
+        f = _f(el, p, side, seed)
+        ids.append((el, p, side, f, srv.submit((0, 0, 0), (side,) * 3, el, p, f)))
+    while srv.step() != (0, 0):
+        pass
+    for el, p, side, f, rid in ids:
+        u, st, _ = srv.fetch(rid)
+        u1, st1 = _alone(el, p, side, f, precision=precision, max_iter=60)
+        assert st["converged"] and st["iterations"] == st1["iterations"]
+        assert np.array_equal(u, u1), (el, p)
+    srv.close()
