@@ -1622,15 +1622,19 @@ void server_admit(dgs_server* S) {
     int match = -1;  // most recently used idle problem of this shape
     for (int i = (int)S->idle.size() - 1; i >= 0 && match < 0; --i)
       if (S->idle[i].box == box && S->idle[i].grid == grid) match = i;
-    // a reused problem's footprint is already counted
-    const size_t need = match >= 0 ? 0 : r.footprint;
+    // a reused problem's footprint is already counted; only what this request
+    // needs beyond it (a puncture request on a Poisson request's problem) is new
+    auto extra = [&](int i) -> size_t {
+      return r.footprint > S->idle[i].footprint ? r.footprint - S->idle[i].footprint : 0;
+    };
+    const size_t need = match >= 0 ? extra(match) : r.footprint;
     const size_t budget = (size_t)S->opt.hbm_budget_bytes;
     if (S->used + need > budget) {
       S->evict_idle(0);
       match = -1;
       S->free_retired();
     }
-    const size_t need2 = match >= 0 ? 0 : r.footprint;
+    const size_t need2 = match >= 0 ? extra(match) : r.footprint;
     const bool none_running = S->active.empty() && admitted.empty();
     if (S->used + need2 > budget && !none_running) break;
     if (S->used + need2 > budget && none_running && r.footprint > budget) {
@@ -1656,7 +1660,8 @@ void server_admit(dgs_server* S) {
       rq->prob = m.prob;
       rq->d_b = m.d_b;
       rq->d_u = m.d_u;
-      rq->footprint = m.footprint;
+      S->used += need2;
+      rq->footprint = m.footprint + need2;
       rq->reused = true;
     } else {
       S->used += rq->footprint;
