@@ -1609,10 +1609,11 @@ void server_setup(dgs_server* S, ServerRequest& r) {
   r.t_admit = ta - S->t0;
 }
 
-void server_admit(dgs_server* S) {
+// Admission: the queued requests that fit (slots, budget), in order, with a
+// stream and, where one of the same shape is idle, a resident problem; their
+// set-up is left to the workers.
+std::vector<std::unique_ptr<ServerRequest>> server_select(dgs_server* S) {
   if (S->retired.size() >= kRetiredBatch) S->free_retired();
-  // choose what fits, then set the chosen requests up in parallel (the
-  // set-up is host-bound; the requests already running keep the device busy)
   std::vector<std::unique_ptr<ServerRequest>> admitted;
   while (!S->queue.empty() && (int)(S->active.size() + admitted.size()) < S->opt.max_active) {
     ServerRequest& r = *S->queue.front();
@@ -1668,16 +1669,7 @@ void server_admit(dgs_server* S) {
     }
     admitted.push_back(std::move(rq));
   }
-  if (admitted.empty()) return;
-  if (S->pool && admitted.size() > 1) {
-    const size_t W = (size_t)S->pool->size();
-    S->pool->run([&](int w) {
-      for (size_t i = (size_t)w; i < admitted.size(); i += W) server_setup(S, *admitted[i]);
-    });
-  } else {
-    for (auto& rq : admitted) server_setup(S, *rq);
-  }
-  for (auto& rq : admitted) S->active.push_back(std::move(rq));
+  return admitted;
 }
 
 void server_retire(dgs_server* S, std::unique_ptr<ServerRequest> rq) {
@@ -2092,13 +2084,15 @@ int dgs_server_submit_puncture(dgs_server* S, const dgs_domain* domain, const in
 int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
   return guarded([&]() -> int {
     if (!S) return fail(DGS_ERR_INVALID, "NULL argument");
-    server_admit(S);
-    // each worker takes every W-th request: it waits for the stage the
-    // request has in flight, completes it on the host and at once issues the
-    // next one, so every unfinished request leaves this call with a stage on
-    // the device and the device keeps working between calls (requests never
-    // share state)
-    auto work = [S](size_t first, size_t stride) {
+    std::vector<std::unique_ptr<ServerRequest>> admitted = server_select(S);
+    // each worker first sets up every W-th newly admitted request (host work
+    // that overlaps the stages already on the device), then takes every W-th
+    // active request: it waits for the stage the request has in flight,
+    // completes it on the host and at once issues the next one, so every
+    // unfinished request leaves this call with a stage on the device and the
+    // device keeps working between calls (requests never share state)
+    auto work = [S, &admitted](size_t first, size_t stride) {
+      for (size_t i = first; i < admitted.size(); i += stride) server_setup(S, *admitted[i]);
       for (size_t i = first; i < S->active.size(); i += stride) {
         ServerRequest& r = *S->active[i];
         if (r.kind == 1) {  // a Newton step runs to its end on the worker
@@ -2115,13 +2109,21 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
           r.in_flight = true;
         }
       }
+      for (size_t i = first; i < admitted.size(); i += stride) {  // their first stages
+        ServerRequest& r = *admitted[i];
+        if (r.kind == 0 && !r.run.done()) {
+          r.run.issue();
+          r.in_flight = true;
+        }
+      }
     };
-    if (S->pool && S->active.size() > 1) {
+    if (S->pool && S->active.size() + admitted.size() > 1) {
       const size_t W = (size_t)S->pool->size();
       S->pool->run([&work, W](int w) { work((size_t)w, W); });
     } else {
       work(0, 1);
     }
+    for (auto& rq : admitted) S->active.push_back(std::move(rq));
     std::vector<std::unique_ptr<ServerRequest>> still;
     for (auto& r : S->active) {
       if (r->done())
