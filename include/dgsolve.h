@@ -204,10 +204,11 @@ int dgs_lgl_nodes(int p, double* xi);
  * hbm_budget_bytes and one of max_active slots is free; every admitted request
  * keeps its mesh, multigrid hierarchy and Krylov basis resident until it
  * finishes, and shares the subdomain inverses of a process-wide cache.  Each
- * dgs_server_step admits what fits and advances every active request by one
- * FGMRES stage, each on its own stream, so requests overlap on the device: it
- * completes the stage a request has in flight and at once issues the next,
- * so the device keeps working between calls.  A finished request's problem
+ * dgs_server_step admits what fits and advances the active requests by FGMRES
+ * stages (Newton steps for puncture requests), each on its own stream, so
+ * requests overlap on the device: a request whose stage has finished is
+ * completed and its next stage issued at once, so the device keeps working
+ * between calls and a small request does not wait for a large one.  A finished request's problem
  * (hierarchy, Krylov basis, captured V-cycle graphs) stays resident for the
  * next request of the same box, grid and degree (up to 32 are kept, their
  * footprints counted against the budget); other memory is released in
@@ -245,7 +246,10 @@ int dgs_server_submit_puncture(dgs_server* server, const dgs_domain* domain,
                                const double* beta, const double* b, long long n,
                                double newton_rtol, double linear_rtol, int max_newton,
                                long long* id);
-/* Admit, then advance every active request by one stage; reports the counts. */
+/* Admit what fits, then advance the active requests: each one whose stage
+ * has finished on the device is completed and its next stage issued (if none
+ * of a worker's requests has finished, the worker waits for one, so every
+ * call makes progress); reports the active and queued counts. */
 int dgs_server_step(dgs_server* server, int* n_active, int* n_queued);
 /* Ids of finished requests (up to capacity) and their number. */
 int dgs_server_finished(dgs_server* server, long long* ids, int capacity, int* count);

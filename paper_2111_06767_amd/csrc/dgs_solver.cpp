@@ -2087,27 +2087,52 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
     std::vector<std::unique_ptr<ServerRequest>> admitted = server_select(S);
     // each worker first sets up every W-th newly admitted request (host work
     // that overlaps the stages already on the device), then takes every W-th
-    // active request: it waits for the stage the request has in flight,
-    // completes it on the host and at once issues the next one, so every
-    // unfinished request leaves this call with a stage on the device and the
-    // device keeps working between calls (requests never share state)
+    // active request: a request whose stage has finished is completed on the
+    // host and its next stage issued at once; one whose stage is still on the
+    // device is left to run, so a small request does not wait for a large
+    // one.  If none of the worker's requests has finished, it waits for the
+    // first one that is in flight, so every call makes progress.  Every
+    // unfinished request leaves this call with a stage on the device
+    // (requests never share state).
     auto work = [S, &admitted](size_t first, size_t stride) {
       for (size_t i = first; i < admitted.size(); i += stride) server_setup(S, *admitted[i]);
-      for (size_t i = first; i < S->active.size(); i += stride) {
-        ServerRequest& r = *S->active[i];
-        if (r.kind == 1) {  // a Newton step runs to its end on the worker
-          if (!r.nrun.done()) r.nrun.step();
-          continue;
-        }
-        if (r.in_flight) {
-          HIP_OK(hipStreamSynchronize(r.stream));
-          r.in_flight = false;
-          r.run.complete();
-        }
+      auto advance = [](ServerRequest& r) {
+        r.in_flight = false;
+        r.run.complete();
         if (!r.run.done()) {
           r.run.issue();
           r.in_flight = true;
         }
+      };
+      bool progressed = false;
+      ServerRequest* waiting = nullptr;
+      for (size_t i = first; i < S->active.size(); i += stride) {
+        ServerRequest& r = *S->active[i];
+        if (r.kind == 1) {  // a Newton step runs to its end on the worker
+          if (!r.nrun.done()) r.nrun.step();
+          progressed = true;
+          continue;
+        }
+        if (!r.in_flight) {
+          if (!r.run.done()) {
+            r.run.issue();
+            r.in_flight = true;
+          }
+          progressed = true;
+          continue;
+        }
+        const hipError_t q = hipStreamQuery(r.stream);
+        if (q == hipErrorNotReady) {
+          if (!waiting) waiting = &r;
+          continue;
+        }
+        HIP_OK(q);
+        advance(r);
+        progressed = true;
+      }
+      if (!progressed && waiting) {
+        HIP_OK(hipStreamSynchronize(waiting->stream));
+        advance(*waiting);
       }
       for (size_t i = first; i < admitted.size(); i += stride) {  // their first stages
         ServerRequest& r = *admitted[i];
