@@ -460,20 +460,24 @@ struct CacheEntry {
   float* inv32 = nullptr;
   double* op64 = nullptr;
   float* op32 = nullptr;
+  // an entry is listed as soon as one problem starts building it; others
+  // that need it wait until it is ready (or drop it when its build failed)
+  bool ready = false, failed = false;
 };
 std::mutex g_cache_mutex;
+std::condition_variable g_cache_cv;
 std::vector<std::unique_ptr<CacheEntry>> g_cache;
 
 CacheEntry* cache_find(int device, int N, int nov, int flags, double ry, double rz, double penalty) {
   for (auto& c : g_cache)
-    if (c->device == device && c->N == N && c->nov == nov && c->flags == flags &&
+    if (!c->failed && c->device == device && c->N == N && c->nov == nov && c->flags == flags &&
         c->penalty == penalty && std::fabs(c->ry - ry) <= 1e-12 * ry &&
         std::fabs(c->rz - rz) <= 1e-12 * rz)
       return c.get();
   return nullptr;
 }
 
-void build_keys(dgs_problem* P, const std::vector<std::unique_ptr<CacheEntry>>& todo,
+void build_keys(dgs_problem* P, const std::vector<CacheEntry*>& todo,
                 const std::vector<const Level*>& ref, hipStream_t s) {
   const int N = P->N, N3 = N * N * N;
   const int nk = (int)todo.size();
@@ -586,27 +590,23 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
   int device = 0;
   HIP_OK(hipGetDevice(&device));
   const int nov = nov_of(P);
-  std::lock_guard<std::mutex> lk(g_cache_mutex);
-  std::vector<std::unique_ptr<CacheEntry>> todo;
+  // the keys this problem needs: found in the cache (ready or being built by
+  // another problem) or listed now and built here, outside the lock, so that
+  // problems of different shapes build their inverses concurrently
+  std::unique_lock<std::mutex> lk(g_cache_mutex);
+  std::vector<CacheEntry*> todo;
   std::vector<const Level*> ref;
   struct Use {
     int level, cls;
     CacheEntry* entry;
   };
   std::vector<Use> uses;
-  std::vector<std::pair<int, int>> pending;  // (level, class) waiting for a new key
   for (int l = 0; l < (int)P->levels.size(); ++l) {
     const Level& L = P->levels[l];
     const double ry = L.h[1] / L.h[0], rz = L.h[2] / L.h[0];
     for (int c = 0; c < (int)L.layouts.size(); ++c) {
       const int flags = L.layouts[c].flags;
       CacheEntry* e = cache_find(device, P->N, nov, flags, ry, rz, P->penalty);
-      if (!e) {
-        for (auto& t : todo)
-          if (t->flags == flags && std::fabs(t->ry - ry) <= 1e-12 * ry &&
-              std::fabs(t->rz - rz) <= 1e-12 * rz)
-            e = t.get();
-      }
       if (!e) {
         std::unique_ptr<CacheEntry> ne(new CacheEntry());
         ne->device = device;
@@ -618,14 +618,33 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
         ne->penalty = P->penalty;
         ne->hx = L.h[0];
         e = ne.get();
-        todo.push_back(std::move(ne));
+        g_cache.push_back(std::move(ne));
+        todo.push_back(e);
         ref.push_back(&L);
       }
       uses.push_back(Use{l, c, e});
     }
   }
-  build_keys(P, todo, ref, s);
-  for (auto& t : todo) g_cache.push_back(std::move(t));
+  lk.unlock();
+  try {
+    build_keys(P, todo, ref, s);
+  } catch (...) {
+    lk.lock();
+    for (CacheEntry* e : todo) e->failed = true;
+    g_cache_cv.notify_all();
+    throw;
+  }
+  lk.lock();
+  for (CacheEntry* e : todo) e->ready = true;
+  g_cache_cv.notify_all();
+  g_cache_cv.wait(lk, [&]() {
+    for (const Use& u : uses)
+      if (!u.entry->ready && !u.entry->failed) return false;
+    return true;
+  });
+  for (const Use& u : uses)
+    if (u.entry->failed) throw DgsError(DGS_ERR_HIP, "building a subdomain inverse failed");
+  lk.unlock();
   for (const Use& u : uses) {
     Level& L = P->levels[u.level];
     ClassInfo& I = L.cls[u.cls];
