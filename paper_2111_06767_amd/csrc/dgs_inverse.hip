@@ -18,15 +18,21 @@ constexpr int BS = 64;  // block size
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// P = A[K,K]^-1 for every matrix of the batch (one workgroup each).
-__global__ void __launch_bounds__(256) k_bgj_diag(const double* __restrict__ A, int n, int kb,
-                                                  double* __restrict__ Pbuf) {
+// P = A[K,K]^-1 for every matrix of the batch (one workgroup each).  The 64
+// elimination steps are sequential, so the block uses 1024 lanes (four
+// entries each) to keep every step short.
+constexpr int kDiagThreads = 1024;
+__global__ void __launch_bounds__(kDiagThreads) k_bgj_diag(const double* __restrict__ A, int n,
+                                                           int kb, double* __restrict__ Pbuf) {
+  constexpr int PER = BS * BS / kDiagThreads;
   __shared__ double M[BS][BS + 1];
   __shared__ double col[BS], row[BS];
   const int b = blockIdx.x;
   const double* Ab = A + (long long)b * n * n;
   const int k0 = kb * BS;
-  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = threadIdx.x + i * kDiagThreads;
     const int r = t / BS, c = t % BS;
     M[r][c] = Ab[(long long)(k0 + r) * n + k0 + c];
   }
@@ -38,7 +44,9 @@ __global__ void __launch_bounds__(256) k_bgj_diag(const double* __restrict__ A, 
     }
     __syncthreads();
     const double p = 1.0 / row[k];
-    for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int t = threadIdx.x + i * kDiagThreads;
       const int r = t / BS, c = t % BS;
       double v;
       if (r == k)
@@ -50,7 +58,11 @@ __global__ void __launch_bounds__(256) k_bgj_diag(const double* __restrict__ A, 
     __syncthreads();
   }
   double* Pb = Pbuf + (long long)b * BS * BS;
-  for (int t = threadIdx.x; t < BS * BS; t += blockDim.x) Pb[t] = M[t / BS][t % BS];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int t = threadIdx.x + i * kDiagThreads;
+    Pb[t] = M[t / BS][t % BS];
+  }
 }
 
 // 64x64x64 tile product on MFMA: acc += X(64x64, LDS) * Y(64x64, LDS).
@@ -170,7 +182,7 @@ hipError_t launch_block_inverse(double* A, int n, int batch, double* Pbuf, doubl
   if (n % BS != 0 || batch <= 0) return hipErrorInvalidValue;
   const int nt = n / BS;
   for (int kb = 0; kb < nt; ++kb) {
-    hipLaunchKernelGGL(k_bgj_diag, dim3(batch), dim3(256), 0, s, A, n, kb, Pbuf);
+    hipLaunchKernelGGL(k_bgj_diag, dim3(batch), dim3(kDiagThreads), 0, s, A, n, kb, Pbuf);
     hipLaunchKernelGGL(k_bgj_panels, dim3(batch * nt), dim3(256), 0, s, A, n, kb, Pbuf, Rbuf, Cbuf);
     hipLaunchKernelGGL(k_bgj_update, dim3(batch * nt * nt), dim3(256), 0, s, A, n, kb, Pbuf, Rbuf,
                        Cbuf);
