@@ -41,11 +41,11 @@ MEASURED_TRAFFIC = {
     "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
                        "sha256": "564137d29ffe0c22f5e1f7f5105854cd31b591581ad649b63c46f89e2af09412",
-                       "bytes": 89161246},
+                       "bytes": 89161326},
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
               "sha256": "a735d1960f4035b420a06bdfde5a1a3da83b6d10989757cd9a753531e0c6727f",
-              "bytes": 633669498},
+              "bytes": 633609941},
 }
 
 
