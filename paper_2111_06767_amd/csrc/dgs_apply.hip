@@ -77,37 +77,42 @@ __device__ __forceinline__ void face_from_line(const double (&x)[N], int side, d
 }
 
 // Gather-out of one z-line of the residual (lane (a, b), points k = 0..N-1)
-// into the subdomain rows: the element's own row (mirrored into its class
-// frame) and the overlap strips of its face neighbours' subdomains, at the
-// offsets of the scatter's pull table.  A strip entry is layer * N^2 + t1 * N
-// + t0 (layer counted from the shared face into this element, t0 / t1 the
-// transverse indices in the neighbour's frame).
+// into the subdomain rows: the element's own row (in its class frame) and the
+// overlap strips of its face neighbours' subdomains, at the offsets of the
+// scatter's pull table.  A strip entry is layer * N^2 + t1 * N + t0 (layer
+// counted from the shared face into this element, t0 / t1 the transverse
+// indices in the neighbour's class frame).
 template <typename TS, int N>
 __device__ __forceinline__ void store_subdomain_rows(const double (&rz)[N], TS* __restrict__ rs,
                                                      const PullEntry* pe, int a, int b, int nov) {
   constexpr int N2 = N * N;
   const PullEntry own = pe[0];
   {
+    int s0, s1, s2;
+    frame_strides(own.flip, N, s0, s1, s2);
     const int mi = (own.flip & 1) ? N - 1 - a : a;
     const int mj = (own.flip & 2) ? N - 1 - b : b;
     const bool fk = own.flip & 4;
-    TS* p = rs + own.du + mj * N + mi;
+    TS* p = rs + own.du + mi * s0 + mj * s1;
 #pragma unroll
-    for (int k = 0; k < N; ++k) p[(fk ? N - 1 - k : k) * N2] = (TS)rz[k];
+    for (int k = 0; k < N; ++k) p[(fk ? N - 1 - k : k) * s2] = (TS)rz[k];
   }
-  // x and y faces: the lane's layer is fixed and t1 = k
+  // x and y faces: the lane's layer is fixed; of the two transverse
+  // coordinates one is the lane's other index and one is k
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     const PullEntry q = pe[1 + f];
     const int id = f < 2 ? a : b;
     const int layer = (f & 1) ? N - 1 - id : id;
     if (q.du >= 0 && layer < nov) {
-      int t0 = f < 2 ? b : a;
-      if (q.flip & 1) t0 = N - 1 - t0;
-      const bool f1 = q.flip & 2;
-      TS* p = rs + q.du + layer * N2 + t0;
+      const bool sw = q.flip & 4;
+      int tf = f < 2 ? b : a;
+      if (sw ? (q.flip & 2) : (q.flip & 1)) tf = N - 1 - tf;
+      const bool fkk = sw ? (q.flip & 1) : (q.flip & 2);
+      const int sk = sw ? 1 : N;
+      TS* p = rs + q.du + layer * N2 + tf * (sw ? N : 1);
 #pragma unroll
-      for (int k = 0; k < N; ++k) p[(f1 ? N - 1 - k : k) * N] = (TS)rz[k];
+      for (int k = 0; k < N; ++k) p[(fkk ? N - 1 - k : k) * sk] = (TS)rz[k];
     }
   }
   // z faces: the layer is the point's own k (uniform across the element)
@@ -115,8 +120,8 @@ __device__ __forceinline__ void store_subdomain_rows(const double (&rz)[N], TS* 
   for (int f = 4; f < 6; ++f) {
     const PullEntry q = pe[1 + f];
     if (q.du < 0) continue;
-    const int t0 = (q.flip & 1) ? N - 1 - a : a;
-    const int t1 = (q.flip & 2) ? N - 1 - b : b;
+    int t0 = a, t1 = b;
+    strip_coords(t0, t1, q.flip, N);
     TS* p = rs + q.du + t1 * N + t0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {

@@ -79,29 +79,73 @@ struct ApplyConfig {
 
 constexpr int kGemmLd = 128, kGemmRows = 64;
 
+// Class frames.  A subdomain is stored in the frame of its canonical boundary
+// class: the element's own axes are first mirrored (bit d of a 3-bit mask
+// reverses axis d), then two axes of equal element width may be exchanged
+// (transposition t: 0 none, 1 axes 0 / 1, 2 axes 0 / 2, 3 axes 1 / 2), so that
+// the face, edge and corner subdomains of all orientations share one class.
+// A frame code is mask | t << 3.
+__host__ __device__ __forceinline__ int frame_axis(int d, int t) {
+  // the axis that holds axis d after transposition t (t is an involution)
+  if (t == 1) return d == 0 ? 1 : (d == 1 ? 0 : 2);
+  if (t == 2) return d == 0 ? 2 : (d == 2 ? 0 : 1);
+  if (t == 3) return d == 1 ? 2 : (d == 2 ? 1 : 0);
+  return d;
+}
+
+// Offsets of a point's three own-axis coordinates in its class frame: a point
+// (i, j, k) lies at mi * s0 + mj * s1 + mk * s2, m the mirrored coordinates.
+__device__ __forceinline__ void frame_strides(int code, int N, int& s0, int& s1, int& s2) {
+  const int t = code >> 3, N2 = N * N;
+  s0 = t == 1 ? N : (t == 2 ? N2 : 1);
+  s1 = t == 1 ? 1 : (t == 3 ? N2 : N);
+  s2 = t == 2 ? 1 : (t == 3 ? N : N2);
+}
+
+// own point (i, j, k) -> its offset in the class frame
+__device__ __forceinline__ int to_class_frame(int i, int j, int k, int code, int N) {
+  int s0, s1, s2;
+  frame_strides(code, N, s0, s1, s2);
+  const int mi = (code & 1) ? N - 1 - i : i;
+  const int mj = (code & 2) ? N - 1 - j : j;
+  const int mk = (code & 4) ? N - 1 - k : k;
+  return mi * s0 + mj * s1 + mk * s2;
+}
+
+// Overlap strips: (t0, t1) are the point's coordinates along the two own
+// axes transverse to the shared face, in ascending axis order; the flip bits
+// of the neighbour's pull entry map them into the neighbour's class frame.
+__device__ __forceinline__ void strip_coords(int& t0, int& t1, int flip, int N) {
+  if (flip & 4) {
+    const int t = t0;
+    t0 = t1;
+    t1 = t;
+  }
+  if (flip & 1) t0 = N - 1 - t0;
+  if (flip & 2) t1 = N - 1 - t1;
+}
+
 // Pull table of the weighted scatter, 7 entries per element: entry 0 is the
 // element's own subdomain, entry 1 + f the subdomain of its face-f neighbour.
 struct PullEntry {
   long long du;  // entry 0: the element's row in the correction block;
                  // faces: start of the neighbour's strip toward the element (-1: none)
   int w;         // matching offset in the weight table
-  int flip;      // entry 0: mirror mask of the element; faces: bits 0 / 1 reverse the
-                 // first / second transverse index (the neighbour is mirrored there)
+  int flip;      // entry 0: frame code of the element; faces: bit 2 exchanges the two
+                 // transverse coordinates, then bits 0 / 1 reverse the first / second
+                 // (the neighbour's class frame there)
 };
 
 // Write the value v of point (i, j, k) of an element into the subdomain rows
-// that hold it: the element's own row (pe[0], mirrored into its class frame)
-// and the overlap strips of its face neighbours' subdomains (pe[1 + f]), at
-// the offsets of the scatter's pull table (the transpose of its reads).
+// that hold it: the element's own row (pe[0], in its class frame) and the
+// overlap strips of its face neighbours' subdomains (pe[1 + f]), at the
+// offsets of the scatter's pull table (the transpose of its reads).
 template <typename TS>
 __device__ __forceinline__ void gather_out_point(TS* rs, const PullEntry* pe, int N, int nov,
                                                  int i, int j, int k, double v) {
   const int N2 = N * N;
   const PullEntry own = pe[0];
-  const int mi = (own.flip & 1) ? N - 1 - i : i;
-  const int mj = (own.flip & 2) ? N - 1 - j : j;
-  const int mk = (own.flip & 4) ? N - 1 - k : k;
-  rs[own.du + (mk * N + mj) * N + mi] = (TS)v;
+  rs[own.du + to_class_frame(i, j, k, own.flip, N)] = (TS)v;
   const int idx[3] = {i, j, k};
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -110,8 +154,7 @@ __device__ __forceinline__ void gather_out_point(TS* rs, const PullEntry* pe, in
     const int layer = (f & 1) ? N - 1 - idx[d] : idx[d];
     if (q.du < 0 || layer >= nov) continue;
     int t0 = d == 0 ? j : i, t1 = d == 2 ? j : k;
-    if (q.flip & 1) t0 = N - 1 - t0;
-    if (q.flip & 2) t1 = N - 1 - t1;
+    strip_coords(t0, t1, q.flip, N);
     rs[q.du + layer * N2 + t1 * N + t0] = (TS)v;
   }
 }

@@ -15,28 +15,29 @@ namespace dgs {
 namespace {
 
 // Subdomains are grouped by canonical boundary class: an element whose class
-// is the mirror image of a canonical class (a high external face where the
-// canonical class has the low one) uses the canonical class's inverse with its
-// points mirrored.  elem_class[e] = group | (mirror mask << 24), mask bit d set
-// when dimension d is mirrored.
+// is a mirror image and / or an exchange of equal-width axes of a canonical
+// class uses the canonical class's inverse with its points mapped into the
+// class frame.  elem_class[e] = group | (frame code << 24).
 constexpr int kGroupMask = 0xFFFFFF;
 
-__device__ __forceinline__ int mirror_loc(int loc, int mask, int N) {
-  if (!mask) return loc;
-  int i = loc % N, j = (loc / N) % N, k = loc / (N * N);
-  if (mask & 1) i = N - 1 - i;
-  if (mask & 2) j = N - 1 - j;
-  if (mask & 4) k = N - 1 - k;
-  return (k * N + j) * N + i;
-}
-
-// canonical (segment, point) -> the element's own frame
-__device__ __forceinline__ void mirror_point(int& seg, int& loc, int mask, int N) {
-  if (!mask) return;
-  loc = mirror_loc(loc, mask, N);
+// class-frame point (seg, loc) -> the element's own frame: seg 0 is the
+// element itself, seg 1 + f the face neighbour across class-frame face f
+__device__ __forceinline__ void frame_point(int& seg, int& loc, int code, int N) {
+  if (!code) return;
+  const int t = code >> 3;
+  const int c0 = loc % N, c1 = (loc / N) % N, c2 = loc / (N * N);
+  // the transposition is its own inverse
+  int m0 = t == 1 ? c1 : (t == 2 ? c2 : c0);
+  int m1 = t == 1 ? c0 : (t == 3 ? c2 : c1);
+  int m2 = t == 2 ? c0 : (t == 3 ? c1 : c2);
+  if (code & 1) m0 = N - 1 - m0;
+  if (code & 2) m1 = N - 1 - m1;
+  if (code & 4) m2 = N - 1 - m2;
+  loc = (m2 * N + m1) * N + m0;
   if (seg > 0) {
     const int f = seg - 1;
-    seg = (((mask >> (f >> 1)) & 1) ? (f ^ 1) : f) + 1;
+    const int d = frame_axis(f >> 1, t);
+    seg = 2 * d + ((f & 1) ^ ((code >> d) & 1)) + 1;
   }
 }
 
@@ -51,7 +52,7 @@ k_gather_rows(const double* __restrict__ r, T* __restrict__ rs, const int* __res
   if (e >= E) return;
   const int N3 = N * N * N;
   const int cv = elem_class[e];
-  const int mask = cv >> 24;
+  const int code = cv >> 24;
   const ClassInfo ci = cls[cv & kGroupMask];
   __shared__ long long src[7];
   if (threadIdx.x < 7) {
@@ -65,7 +66,7 @@ k_gather_rows(const double* __restrict__ r, T* __restrict__ rs, const int* __res
     const int sl = lay[k];
     int seg = sl / N3;
     int loc = sl - seg * N3;
-    mirror_point(seg, loc, mask, N);
+    frame_point(seg, loc, code, N);
     out[k] = (T)r[src[seg] + loc];
   }
 }
@@ -97,16 +98,15 @@ k_scatter(double* __restrict__ u, const T* __restrict__ du, long long pstride,
   const int idx[3] = {loc % N, (loc / N) % N, loc / N2};
   const PullEntry* pe = pull + e * 7;
   const PullEntry own = pe[0];
-  const int lc = mirror_loc(loc, own.flip, N);
+  const int lc = to_class_frame(idx[0], idx[1], idx[2], own.flip, N);
   double acc = weights[own.w + lc] * sum_parts<T, PARTS>(du, own.du + lc, pstride);
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
     const PullEntry q = pe[1 + f];
     const int d = f >> 1;
     const int layer = (f & 1) ? (N - 1 - idx[d]) : idx[d];
-    const int d0 = d == 0 ? 1 : 0, d1 = d == 2 ? 1 : 2;  // transverse dimensions
-    const int t0 = (q.flip & 1) ? N - 1 - idx[d0] : idx[d0];
-    const int t1 = (q.flip & 2) ? N - 1 - idx[d1] : idx[d1];
+    int t0 = idx[d == 0 ? 1 : 0], t1 = idx[d == 2 ? 1 : 2];  // transverse coordinates
+    strip_coords(t0, t1, q.flip, N);
     const bool ok = q.du >= 0 && layer < nov;
     const int k = ok ? layer * N2 + t1 * N + t0 : lc;
     const long long bd = ok ? q.du : own.du;
@@ -312,7 +312,7 @@ k_sub_arnoldi(int j, int kmax, const T* __restrict__ W, T* __restrict__ V, const
   const int e = blockIdx.x;
   if (e >= E) return;
   const int cv = elem_class[e];
-  const int mask = cv >> 24;
+  const int code = cv >> 24;
   const ClassInfo ci = cls[cv & kGroupMask];
   const int n = ci.n;
   const long long row = elem_row[e];
@@ -331,7 +331,7 @@ k_sub_arnoldi(int j, int kmax, const T* __restrict__ W, T* __restrict__ V, const
       const int sl = lay[i];
       int seg = sl / N3;
       int loc = sl - seg * N3;
-      mirror_point(seg, loc, mask, N);
+      frame_point(seg, loc, code, N);
       const double d = diag[src[seg] + loc];
       w[q] = (double)W[row + i] + d * (double)Zj[row + i];
     }

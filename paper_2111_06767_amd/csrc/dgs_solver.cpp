@@ -326,9 +326,12 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   const int N = P->N, nov = nov_of(P);
   // canonical class: a dimension with only its high face external is mirrored
   // so that the low face is the external one (the DG operator, the subdomain
-  // geometry and the weights are all symmetric under the mirror)
+  // geometry and the weights are all symmetric under the mirror); then, of the
+  // exchanges of two axes with equal element widths (under which they are
+  // symmetric too), the one that gives the largest flags is taken, so that
+  // faces, edges and corners of every orientation share a class
   std::map<int, int> cls_of_flags;
-  std::vector<int> elem_flags(L.E), elem_mask(L.E);
+  std::vector<int> elem_flags(L.E), elem_code(L.E);
   for (long long e = 0; e < L.E; ++e) {
     const int c[3] = {(int)(e % L.n[0]), (int)((e / L.n[0]) % L.n[1]),
                       (int)(e / ((long long)L.n[0] * L.n[1]))};
@@ -340,9 +343,20 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
         fl = (fl & ~(3 << (2 * d))) | (1 << (2 * d));
       }
     }
-    elem_flags[e] = fl;
-    elem_mask[e] = mask;
-    cls_of_flags.emplace(fl, 0);
+    int best = fl, best_t = 0;
+    for (int t = 1; t <= 3; ++t) {
+      const int a = t == 3 ? 1 : 0, b = t == 1 ? 1 : 2;
+      if (L.h[a] != L.h[b]) continue;
+      int ft = 0;
+      for (int d = 0; d < 3; ++d) ft |= ((fl >> (2 * frame_axis(d, t))) & 3) << (2 * d);
+      if (ft > best) {
+        best = ft;
+        best_t = t;
+      }
+    }
+    elem_flags[e] = best;
+    elem_code[e] = mask | best_t << 3;
+    cls_of_flags.emplace(best, 0);
   }
   int ci = 0;
   for (auto& kv : cls_of_flags) kv.second = ci++;
@@ -401,32 +415,37 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   upload(L.d_seg_loc, seg_loc, s);
   L.d_weights = P->alloc<double>(weights.size());
   upload(L.d_weights, weights, s);
-  std::vector<int> elem_code(L.E);
-  for (long long e = 0; e < L.E; ++e) elem_code[e] = elem_class[e] | (elem_mask[e] << 24);
+  std::vector<int> elem_cv(L.E);
+  for (long long e = 0; e < L.E; ++e) elem_cv[e] = elem_class[e] | (elem_code[e] << 24);
   L.d_elem_class = P->alloc<int>(L.E);
-  upload(L.d_elem_class, elem_code, s);
+  upload(L.d_elem_class, elem_cv, s);
   L.d_elem_row = P->alloc<long long>(L.E);
   upload(L.d_elem_row, elem_row, s);
   // scatter pull table: the element's own row, and for every face neighbour b
-  // the start of b's strip toward the element (in b's canonical frame)
+  // the start of b's strip toward the element (in b's class frame)
   const std::vector<int> nbr = host_neighbors(L);
   std::vector<PullEntry> pull(L.E * 7);
   for (long long e = 0; e < L.E; ++e) {
     const ClassInfo& ce = L.cls[elem_class[e]];
-    pull[e * 7] = PullEntry{elem_row[e], ce.layout_off, elem_mask[e]};
+    pull[e * 7] = PullEntry{elem_row[e], ce.layout_off, elem_code[e]};
     for (int f = 0; f < 6; ++f) {
       const int b = nbr[e * 6 + f];
       if (b < 0) {
         pull[e * 7 + 1 + f] = PullEntry{-1, 0, 0};
         continue;
       }
-      const int d = f >> 1, d0 = d == 0 ? 1 : 0, d1 = d == 2 ? 1 : 2;
-      const int mb = elem_mask[b];
-      const int g = ((mb >> d) & 1) ? f : (f ^ 1);  // b's face toward e, canonical frame
+      const int d = f >> 1, d0 = d == 0 ? 1 : 0;
+      const int mb = elem_code[b] & 7, tb = elem_code[b] >> 3;
+      // b's face toward e (own side (f ^ 1) & 1 along axis d) in b's class frame
+      const int dc = frame_axis(d, tb);
+      const int g = 2 * dc + (((f ^ 1) & 1) ^ ((mb >> d) & 1));
+      // the own axes that b's class-frame transverse axes (ascending) hold
+      const int x0 = frame_axis(dc == 0 ? 1 : 0, tb), x1 = frame_axis(dc == 2 ? 1 : 2, tb);
       const ClassInfo& cb = L.cls[elem_class[b]];
       if (cb.strip_off[g] < 0) throw DgsError(DGS_ERR_HIP, "subdomain strip missing");
       pull[e * 7 + 1 + f] = PullEntry{elem_row[b] + cb.strip_off[g], cb.layout_off + cb.strip_off[g],
-                                      ((mb >> d0) & 1) | (((mb >> d1) & 1) << 1)};
+                                      ((mb >> x0) & 1) | (((mb >> x1) & 1) << 1) |
+                                          ((x0 != d0 ? 1 : 0) << 2)};
     }
   }
   L.d_pull = P->alloc<PullEntry>(pull.size());

@@ -17,12 +17,18 @@ def _diag(m, seed):
     return (oop.mass_diagonal(m) * c).reshape(-1)
 
 
-@pytest.mark.parametrize("elements,p,k", [((2, 2, 2), 3, 3), ((3, 2, 2), 2, 3), ((2, 2, 2), 4, 0),
-                                          ((3, 3, 2), 3, 2)])
-def test_linearised_schwarz_matches_oracle(elements, p, k):
+BOX = (1.0, 1.2, 0.9)
+
+
+# the unit-cube cases give axes of equal element width: classes shared across
+# axes, the subdomain's diagonal read through exchanged-axis frames
+@pytest.mark.parametrize("elements,p,k,upper", [((2, 2, 2), 3, 3, BOX), ((3, 2, 2), 2, 3, BOX),
+                                                ((2, 2, 2), 4, 0, BOX), ((3, 3, 2), 3, 2, BOX),
+                                                ((3, 3, 3), 3, 3, (1, 1, 1)),
+                                                ((2, 3, 3), 2, 2, (1, 1.5, 1.5))])
+def test_linearised_schwarz_matches_oracle(elements, p, k, upper):
     import paper_2111_06767_amd as dg
-    announce(f"linearised schwarz elements={elements} p={p} k={k}")
-    upper = (1.0, 1.2, 0.9)
+    announce(f"linearised schwarz elements={elements} p={p} k={k} upper={upper}")
     prob = dg.Problem((0, 0, 0), upper, elements, p, subdomain_iters=k)
     m = omesh.BoxMesh((0, 0, 0), upper, elements, p)
     d = _diag(m, 5)

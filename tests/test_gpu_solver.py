@@ -9,15 +9,21 @@ from tests.gpu_util import announce, rel_max, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
 
-SMOOTH_CASES = [((1, 1, 1), 3, 2), ((2, 2, 2), 3, 2), ((3, 2, 4), 2, 2), ((3, 3, 3), 4, 1),
-                ((2, 3, 2), 5, 3), ((4, 2, 2), 6, 2), ((2, 2, 1), 1, 2)]
+BOX = (1.0, 1.3, 0.7)
+# on BOX every axis has its own element width; the other boxes give axes of
+# equal width, whose face, edge and corner subdomains share classes across
+# axes (stored in exchanged-axis frames)
+SMOOTH_CASES = [((1, 1, 1), 3, 2, BOX), ((2, 2, 2), 3, 2, BOX), ((3, 2, 4), 2, 2, BOX),
+                ((3, 3, 3), 4, 1, BOX), ((2, 3, 2), 5, 3, BOX), ((4, 2, 2), 6, 2, BOX),
+                ((2, 2, 1), 1, 2, BOX), ((3, 3, 3), 4, 1, (1, 1, 1)), ((4, 4, 4), 3, 2, (1, 1, 1)),
+                ((4, 4, 2), 2, 2, (1, 1, 0.5)), ((1, 3, 3), 3, 2, (1, 1, 1)),
+                ((2, 4, 4), 3, 2, (1, 1, 1)), ((3, 4, 3), 2, 2, (0.75, 1, 0.75))]
 
 
-@pytest.mark.parametrize("elements,p,overlap", SMOOTH_CASES)
-def test_schwarz_steps_match_oracle(elements, p, overlap):
+@pytest.mark.parametrize("elements,p,overlap,upper", SMOOTH_CASES)
+def test_schwarz_steps_match_oracle(elements, p, overlap, upper):
     import paper_2111_06767_amd as dg
-    announce(f"schwarz parity elements={elements} p={p} overlap={overlap}")
-    upper = (1.0, 1.3, 0.7)
+    announce(f"schwarz parity elements={elements} p={p} overlap={overlap} upper={upper}")
     prob = dg.Problem((0, 0, 0), upper, elements, p, penalty=1.5, overlap=overlap)
     m = omesh.BoxMesh((0, 0, 0), upper, elements, p)
     b = W.random_normal(21, m.ndof)
