@@ -40,12 +40,12 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 MEASURED_TRAFFIC = {
     "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
-                       "sha256": "564137d29ffe0c22f5e1f7f5105854cd31b591581ad649b63c46f89e2af09412",
-                       "bytes": 89161326},
+                       "sha256": "5dea343a6e1f780b881748020e2d0b1bfb1d163c87280b1d670af6f5fc76dc74",
+                       "bytes": 68707827},
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
-              "sha256": "a735d1960f4035b420a06bdfde5a1a3da83b6d10989757cd9a753531e0c6727f",
-              "bytes": 633609941},
+              "sha256": "4602b98bc01a188b2050dd5b483cb767663a83cee811d9418e9f1c68cf3e5d34",
+              "bytes": 633404853},
 }
 
 
