@@ -89,6 +89,17 @@ typedef struct {
 
 void dgs_default_options(dgs_options* opt);
 
+/* Device allocator for a problem's own workspace (multigrid fields, class
+ * tables, subdomain blocks, Krylov basis), e.g. a shim over PyTorch's caching
+ * allocator.  alloc returns `bytes` of device memory on the current device,
+ * aligned to 256 bytes, or NULL when it has none; free releases a pointer
+ * that alloc returned.  Both are called on the thread that calls the
+ * library, free only once the device has finished the problem's work.  The
+ * process-wide cache of subdomain inverses, which outlives any problem, is
+ * always allocated by the library itself. */
+typedef void* (*dgs_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*dgs_free_fn)(void* ptr, void* ctx);
+
 /* Create a problem: mesh, LGL tables, multigrid hierarchy, and the explicit
  * inverses of the Schwarz subdomain operators A_S = R_S A R_S^T
  * (Sec. III.D.2, III.E.2), built on the device.
@@ -97,10 +108,16 @@ void dgs_default_options(dgs_options* opt);
  *   p         polynomial degree, 1..8 (N = p+1 points per dimension)
  *   penalty   C > 0 in sigma = C (p+1)^2 / h (eq. penalty)
  *   opt       NULL = defaults
+ *   alloc_fn, free_fn, alloc_ctx
+ *             the problem's device allocator (both NULL = hipMalloc / hipFree;
+ *             one NULL without the other is DGS_ERR_INVALID).  A NULL from
+ *             alloc_fn fails the call with DGS_ERR_OOM, a pointer not aligned
+ *             to 256 bytes with DGS_ERR_INVALID; what was allocated is freed.
  *   stream    hipStream_t for the set-up work
  *   out       receives the handle; free it with dgs_destroy_problem.          */
 int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
-                       const dgs_options* opt, void* stream, dgs_problem** out);
+                       const dgs_options* opt, dgs_alloc_fn alloc_fn, dgs_free_fn free_fn,
+                       void* alloc_ctx, void* stream, dgs_problem** out);
 int dgs_destroy_problem(dgs_problem* prob);
 
 /* Number of degrees of freedom E * N^3. */

@@ -86,8 +86,8 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_default_options.argtypes = [ctypes.POINTER(Options)]
     lib.dgs_default_options.restype = None
     lib.dgs_create_problem.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
-                                       ctypes.c_int, ctypes.c_double, ctypes.POINTER(Options), P,
-                                       ctypes.POINTER(P)]
+                                       ctypes.c_int, ctypes.c_double, ctypes.POINTER(Options),
+                                       ALLOC_FN, FREE_FN, P, P, ctypes.POINTER(P)]
     lib.dgs_destroy_problem.argtypes = [P]
     lib.dgs_num_dofs.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
     lib.dgs_node_coordinates.argtypes = [P, dp, P]
@@ -167,19 +167,58 @@ def _ptr(t, n=None, name="tensor"):
     return ctypes.c_void_p(t.data_ptr())
 
 
+# dgs_alloc_fn / dgs_free_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchAllocator:
+    """A problem's device workspace from PyTorch's caching allocator (the
+    dgs_alloc_fn / dgs_free_fn pair of dgs_create_problem).  `live` holds the
+    blocks handed out and not yet returned."""
+
+    def __init__(self):
+        self.live = {}
+        self.allocated = 0
+
+    def alloc(self, nbytes):
+        import torch
+        ptr = torch.cuda.caching_allocator_alloc(int(nbytes))
+        self.live[ptr] = int(nbytes)
+        self.allocated += 1
+        return ptr
+
+    def free(self, ptr):
+        import torch
+        self.live.pop(ptr)
+        torch.cuda.caching_allocator_delete(ptr)
+
+
 class Problem:
-    """A DG Poisson problem on a box (see dgs_create_problem)."""
+    """A DG Poisson problem on a box (see dgs_create_problem).  `allocator`:
+    an object with alloc(nbytes) -> device address and free(address), such as
+    TorchAllocator, for the problem's own device memory (None: the library's
+    hipMalloc)."""
 
     def __init__(self, lower, upper, elements, p, penalty=1.5, options: Options | None = None,
-                 stream=None, **opts):
+                 stream=None, allocator=None, **opts):
         lib = load_library()
         self._lib = lib
         self.options = options if options is not None else default_options(**opts)
         dom = Domain((ctypes.c_double * 3)(*lower), (ctypes.c_double * 3)(*upper))
         el = (ctypes.c_int * 3)(*elements)
         h = ctypes.c_void_p()
+        self._h = None
+        self.allocator = allocator
+        if allocator is not None:
+            # kept on the problem: the library calls them until it is destroyed
+            self._alloc_cb = ALLOC_FN(lambda nbytes, ctx: allocator.alloc(nbytes))
+            self._free_cb = FREE_FN(lambda ptr, ctx: allocator.free(ptr))
+        else:
+            self._alloc_cb, self._free_cb = ALLOC_FN(), FREE_FN()
         _check(lib.dgs_create_problem(ctypes.byref(dom), el, int(p), float(penalty),
-                                      ctypes.byref(self.options), _stream(stream), ctypes.byref(h)))
+                                      ctypes.byref(self.options), self._alloc_cb, self._free_cb,
+                                      None, _stream(stream), ctypes.byref(h)))
         self._h = h
         self.elements = tuple(int(v) for v in elements)
         self.p, self.N = int(p), int(p) + 1

@@ -212,6 +212,10 @@ struct dgs_problem {
   DevTables dt{};
   std::vector<Level> levels;
   std::vector<void*> allocations;
+  // the caller's device allocator (null: hipMalloc / hipFree)
+  dgs_alloc_fn alloc_fn = nullptr;
+  dgs_free_fn free_fn = nullptr;
+  void* alloc_ctx = nullptr;
   // Krylov workspace
   int kry_m = 0;
   double *d_V = nullptr, *d_Z = nullptr, *d_partial = nullptr, *d_h = nullptr, *d_y = nullptr;
@@ -230,12 +234,40 @@ struct dgs_problem {
 
   template <typename T>
   T* alloc(size_t count) {
-    T* p = dalloc<T>(count);
+    T* p = nullptr;
+    if (alloc_fn) {
+      const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+      p = static_cast<T*>(alloc_fn(bytes, alloc_ctx));
+      if (!p) throw DgsError(DGS_ERR_OOM, "the caller's allocator returned NULL");
+      if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+        free_fn(p, alloc_ctx);
+        throw DgsError(DGS_ERR_INVALID, "the caller's allocator returned a pointer not 256-byte aligned");
+      }
+    } else {
+      p = dalloc<T>(count);
+    }
     allocations.push_back(p);
     return p;
   }
+  // p must be one of `allocations` and no longer in use on the device
+  void release(void* p) {
+    auto it = std::find(allocations.begin(), allocations.end(), p);
+    if (it != allocations.end()) allocations.erase(it);
+    if (free_fn)
+      free_fn(p, alloc_ctx);
+    else
+      (void)hipFree(p);
+  }
   ~dgs_problem() {
-    for (void* p : allocations) (void)hipFree(p);
+    // a caller's allocator may hand the memory out again at once: let the
+    // device finish with it first (also when set-up failed half-way)
+    if (free_fn && !allocations.empty()) (void)hipDeviceSynchronize();
+    for (void* p : allocations) {
+      if (free_fn)
+        free_fn(p, alloc_ctx);
+      else
+        (void)hipFree(p);
+    }
     if (h_pinned) (void)hipHostFree(h_pinned);
     for (auto& g : vgraph)
       if (g) (void)hipGraphExecDestroy(g);
@@ -1017,12 +1049,11 @@ void vcycle(dgs_problem* P, const double* r, double* z, hipStream_t s) {
 
 void ensure_krylov(dgs_problem* P, int m) {
   if (P->kry_m >= m) return;
-  for (double* p : {P->d_V, P->d_Z, P->d_partial, P->d_h, P->d_y, P->d_tmp, P->d_tmp2}) {
-    if (!p) continue;
-    auto it = std::find(P->allocations.begin(), P->allocations.end(), (void*)p);
-    if (it != P->allocations.end()) P->allocations.erase(it);
-    (void)hipFree(p);
-  }
+  // the old basis may still be read by work in flight (hipFree would wait
+  // for the device by itself; a caller's allocator may not)
+  if (P->kry_m > 0 && P->free_fn) HIP_OK(hipDeviceSynchronize());
+  for (double* p : {P->d_V, P->d_Z, P->d_partial, P->d_h, P->d_y, P->d_tmp, P->d_tmp2})
+    if (p) P->release(p);
   const long long n = P->nd(0);
   P->d_V = P->alloc<double>((size_t)(m + 1) * n);
   P->d_Z = P->alloc<double>((size_t)m * n);
@@ -1610,7 +1641,7 @@ void server_setup(dgs_server* S, ServerRequest& r) {
   if (!r.reused) {
     dgs_problem* created = nullptr;
     const int code = dgs_create_problem(&r.dom, r.elements, r.p, S->opt.penalty, &S->opt.solver,
-                                        r.stream, &created);
+                                        nullptr, nullptr, nullptr, r.stream, &created);
     if (code != DGS_OK) throw DgsError(code, g_last_error);
     r.prob = created;
     r.d_b = dalloc<double>(created->nd(0));
@@ -1773,10 +1804,12 @@ void dgs_default_options(dgs_options* o) {
 const char* dgs_last_error(void) { return g_last_error.c_str(); }
 
 int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
-                       const dgs_options* opt, void* stream, dgs_problem** out) {
+                       const dgs_options* opt, dgs_alloc_fn alloc_fn, dgs_free_fn free_fn,
+                       void* alloc_ctx, void* stream, dgs_problem** out) {
   return guarded([&]() -> int {
     if (!domain || !elements || !out) return fail(DGS_ERR_INVALID, "NULL argument");
     *out = nullptr;
+    if (!alloc_fn != !free_fn) return fail(DGS_ERR_INVALID, "alloc_fn and free_fn go together");
     if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 8]");
     if (!(penalty > 0.0) || !std::isfinite(penalty)) return fail(DGS_ERR_INVALID, "penalty must be > 0");
     for (int d = 0; d < 3; ++d) {
@@ -1798,6 +1831,9 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     const double t0 = now_s();
     hipStream_t s = as_stream(stream);
     std::unique_ptr<dgs_problem> P(new dgs_problem());
+    P->alloc_fn = alloc_fn;
+    P->free_fn = free_fn;
+    P->alloc_ctx = alloc_ctx;
     P->opt = o;
     P->p = p;
     P->N = p + 1;

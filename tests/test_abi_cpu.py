@@ -42,12 +42,20 @@ def test_default_options_and_invalid_arguments_without_gpu():
     h = ctypes.c_void_p()
     for el, p, C in [((0, 1, 1), 3, 1.5), ((1, 1, 1), 0, 1.5), ((1, 1, 1), 9, 1.5), ((1, 1, 1), 3, 0.0)]:
         code = lib.dgs_create_problem(ctypes.byref(dom), (ctypes.c_int * 3)(*el), p, C,
-                                      ctypes.byref(o), None, ctypes.byref(h))
+                                      ctypes.byref(o), m.api.ALLOC_FN(), m.api.FREE_FN(), None,
+                                      None, ctypes.byref(h))
         assert code == m.DGS_ERR_INVALID
         assert lib.dgs_last_error().decode() != ""
     bad = m.api.Domain((ctypes.c_double * 3)(0, 0, 0), (ctypes.c_double * 3)(1, 0, 1))
     assert lib.dgs_create_problem(ctypes.byref(bad), (ctypes.c_int * 3)(1, 1, 1), 3, 1.5,
-                                  ctypes.byref(o), None, ctypes.byref(h)) == m.DGS_ERR_INVALID
+                                  ctypes.byref(o), m.api.ALLOC_FN(), m.api.FREE_FN(), None, None,
+                                  ctypes.byref(h)) == m.DGS_ERR_INVALID
+    # an allocator needs both functions
+    alloc_only = m.api.ALLOC_FN(lambda nbytes, ctx: None)
+    assert lib.dgs_create_problem(ctypes.byref(dom), (ctypes.c_int * 3)(1, 1, 1), 3, 1.5,
+                                  ctypes.byref(o), alloc_only, m.api.FREE_FN(), None, None,
+                                  ctypes.byref(h)) == m.DGS_ERR_INVALID
+    assert "together" in lib.dgs_last_error().decode()
 
 
 def test_subdomain_solves_rejects_null_problem_without_gpu():

@@ -153,3 +153,37 @@ def test_subdomain_solves_flop_count(elements, p, levels):
         with pytest.raises(dg.api.DgsError):
             prob.subdomain_solves(len(meshes))
         prob.close()
+
+
+def test_caller_allocator_gives_the_same_bits():
+    """dgs_create_problem with the caller's device allocator (PyTorch's caching
+    allocator): the problem's memory comes from torch, every block returns on
+    destroy, and the solve gives the bits of a problem on the library's own
+    memory (torch's blocks are reused, not zeroed, so nothing may rely on
+    fresh memory reading zero)."""
+    import torch
+    import paper_2111_06767_amd as dg
+    announce("caller allocator 4x4x4 p=4 mixed")
+    # dirty the cache first: blocks handed out below then hold old values
+    junk = torch.full((1 << 22,), float("nan"), dtype=torch.float64, device="cuda")
+    del junk
+    b = to_gpu(W.random_normal(41, 4 * 4 * 4 * 125))
+    results = []
+    for alloc in (None, dg.TorchAllocator()):
+        m0 = torch.cuda.memory_allocated()
+        prob = dg.Problem((0, 0, 0), (1, 1, 1), (4, 4, 4), 4, mg_levels=3, precision="mixed",
+                          allocator=alloc)
+        u, st = prob.solve(b)
+        torch.cuda.synchronize()
+        results.append((to_np(u), st["iterations"], st["rel_residual"]))
+        if alloc is not None:
+            assert alloc.allocated > 0 and alloc.live
+            assert torch.cuda.memory_allocated() - m0 >= sum(alloc.live.values())
+        del u
+        prob.close()
+        if alloc is not None:
+            assert not alloc.live
+            assert torch.cuda.memory_allocated() == m0
+    assert results[0][1] == results[1][1] and results[0][2] == results[1][2]
+    assert np.array_equal(results[0][0], results[1][0])
+    assert results[1][2] <= 1e-10
