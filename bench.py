@@ -10,8 +10,10 @@ Workload (one step = one full solve to a 1e-10 relative residual):
 
 Also measured: operator-apply throughput (GDOF/s) with HIP events on the
 stream the kernel runs on, on the same shape and on a 40^3, p = 7 shape whose
-vectors (262 MB) exceed the 256 MB Infinity Cache, and the oracle on the host
-CPU on a bounded sample (one solve of the same workload).
+vectors (262 MB) exceed the 256 MB Infinity Cache; the ceilings the GPU
+reaches outside the library (a 512 MiB copy, an FP32 torch.matmul) beside the
+vendor peaks; and the oracle on the host CPU on a bounded sample (one solve of
+the same workload).
 
 Prints one JSON line.
 """
@@ -155,6 +157,40 @@ def time_subdomain_gemm(prob, reps=50, warm=5):
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
     return dict(flops_per_launch=flops, ms_per_launch=ms, achieved_tflops=flops / (ms * 1e-3) / 1e12)
+
+
+def measured_ceilings():
+    """What this GPU reaches outside the library, reported beside the vendor
+    peaks: a device-to-device copy of 512 MiB (read and write counted), and
+    an FP32 8192^3 product through torch.matmul (the vendor BLAS)."""
+    import torch
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n = 1 << 26
+    a = torch.empty(n, dtype=torch.float64, device="cuda").normal_()
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    e0.record(s)
+    for _ in range(20):
+        c.copy_(a)
+    e1.record(s)
+    e1.synchronize()
+    copy_gbs = 2 * 8 * n * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, c
+    m = 8192
+    x = torch.randn(m, m, device="cuda", dtype=torch.float32)
+    y = torch.randn(m, m, device="cuda", dtype=torch.float32)
+    for _ in range(3):
+        z = x @ y
+    e0.record(s)
+    for _ in range(10):
+        z = x @ y
+    e1.record(s)
+    e1.synchronize()
+    gemm_tflops = 2 * m ** 3 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    del x, y, z
+    return dict(copy_gbs=copy_gbs, fp32_gemm_tflops=gemm_tflops)
 
 
 def time_c5(dg, steps=3):
@@ -349,6 +385,15 @@ def main():
     roofline_apply["launch_shape"] = roof_src["launch_shape"]
     if apply_big:
         roofline_apply["calibration_copy_bytes"] = 8 * apply_big["ndof"]
+    ceil = measured_ceilings()
+    roofline["measured_ceiling"] = {
+        "what": "FP32 8192^3 torch.matmul (vendor BLAS) on this GPU", "unit": "TFLOP/s",
+        "value": round(ceil["fp32_gemm_tflops"], 1),
+        "frac": round(gemm["achieved_tflops"] / ceil["fp32_gemm_tflops"], 4)}
+    roofline_apply["measured_ceiling"] = {
+        "what": "device-to-device copy of 512 MiB on this GPU (read + write)", "unit": "GB/s",
+        "value": round(ceil["copy_gbs"], 1),
+        "frac": round(roof_src["achieved_gbs"] / ceil["copy_gbs"], 4)}
 
     if not args.no_c5:
         _log("16^3 p=7 solves")
