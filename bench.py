@@ -109,6 +109,24 @@ def time_solves(prob, b, steps, warmup):
     return u, stats, times, total
 
 
+def time_cg(prob, b, reps=10):
+    """The same solve by preconditioned conjugate gradients (dgs_cg_solve),
+    one V-cycle per iteration: p50 wall time and iterations."""
+    import torch
+    u = torch.zeros_like(b)
+    prob.solve_cg(b, u)
+    times, st = [], None
+    for _ in range(reps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = prob.solve_cg(b, u)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    return dict(ms_p50=round(1e3 * _pct(times, 50), 3), iterations=st["iterations"],
+                rel_residual=st["rel_residual"], converged=st["converged"])
+
+
 def time_apply(dg, elements, p, reps=100, warm=10, calibration_copy=False, shape=None):
     """Average apply duration with HIP events on torch's current stream (the
     stream the library launches on).  With calibration_copy, one plain
@@ -341,12 +359,14 @@ def main():
             prob.set_gemm_variant(args.gemm_variant, level=0)
         u, st, times, total = time_solves(prob, b, args.steps, args.warmup)
         un = u.cpu().numpy()
-        res[prec] = dict(prob=prob, u=un, stats=st, times=times, total=total,
+        res[prec] = dict(prob=prob, b=b, u=un, stats=st, times=times, total=total,
                          err_exact=float(np.sqrt(np.mean((un - uex) ** 2))),
                          setup_s=st["t_setup_s"])
 
     mixed, fp64 = res["mixed"], res["fp64"]
     sol_diff = float(np.linalg.norm(mixed["u"] - fp64["u"]) / np.linalg.norm(fp64["u"]))
+    _log("8^3 p=6 by preconditioned conjugate gradients")
+    cg = {prec: time_cg(res[prec]["prob"], res[prec]["b"]) for prec in ("mixed", "fp64")}
     _log("subdomain GEMM and apply timings")
     gemm = time_subdomain_gemm(mixed["prob"])
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
@@ -438,6 +458,7 @@ def main():
         "setup_s": {"mixed": round(mixed["setup_s"], 3), "fp64": round(fp64["setup_s"], 3)},
         "apply": {"c2_shape": apply_c2, "16^3_p7": apply_c5, "40^3_p7": apply_big,
                   "sweep_2M_dofs": sweep},
+        "c2_conjugate_gradients": cg,
         "c5_16x16x16_p7": c5,
         "serving": serving,
         "roofline": roofline,

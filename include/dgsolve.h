@@ -148,6 +148,18 @@ int dgs_precondition(dgs_problem* prob, const double* r, double* z, void* stream
  * stats->rel_residual is the true relative residual of the result. */
 int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream);
 
+/* Solve A u = b by preconditioned conjugate gradients (Sec. III.B, the
+ * algorithm for symmetric positive definite problems; Saad 2003, Alg. 9.1)
+ * with one V-cycle per iteration as the preconditioner.  The direction update
+ * uses beta = (z_{k+1}, r_{k+1} - r_k) / (z_k, r_k), which keeps the method
+ * usable with the V-cycle, a preconditioner that is not symmetric.  u holds
+ * the initial guess on entry and the solution on exit; rtol and max_iter of
+ * the options apply to the recursively updated residual, stats->rel_residual
+ * is the true relative residual of the result.  DGS_NOT_CONVERGED also when a
+ * direction p has p.Ap <= 0 (A not positive definite).  b and u must not
+ * overlap; the call synchronises the stream twice per iteration. */
+int dgs_cg_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream);
+
 /* Add a pointwise term: subsequent dgs_schwarz_smooth, dgs_precondition and
  * dgs_solve act on A + diag(d) (d a device field in the nodal layout, e.g. the
  * mass-weighted derivative M S'(u) of a nonlinear source, eq. linearized);

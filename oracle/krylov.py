@@ -1,4 +1,6 @@
-"""Flexible GMRES (Sec. III.B; Saad 2003, Alg. 9.6).
+"""Flexible GMRES (Sec. III.B; Saad 2003, Alg. 9.6) and preconditioned
+conjugate gradients for symmetric positive definite problems (Sec. III.B;
+Saad 2003, Alg. 9.1).
 
 One operator application and one preconditioner application per iteration;
 the new basis vector is orthogonalised against all previous ones (modified
@@ -67,3 +69,46 @@ def fgmres(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200):
 def H_next_zero(w):
     """Lucky breakdown: the new Krylov vector vanished."""
     return not np.any(w)
+
+
+def cg(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200):
+    """Preconditioned conjugate gradients (Sec. III.B; Saad 2003, Alg. 9.1)
+    for symmetric positive definite A.  Returns (x, iterations, history of
+    ||r_k|| / ||r_0||).
+
+    Reading: the direction update takes beta_k = (z_{k+1}, r_{k+1} - r_k) /
+    (z_k, r_k) (the Polak-Ribiere form).  For a fixed symmetric positive
+    definite preconditioner (z_{k+1}, r_k) vanishes and this is Saad's
+    (z_{k+1}, r_{k+1}) / (z_k, r_k); unlike that form it keeps working when
+    the preconditioner is not a fixed symmetric matrix, as the multigrid
+    V-cycle with weighted additive Schwarz smoothing is not.  The iteration
+    stops when the recursively updated residual satisfies ||r_k|| <= rtol
+    ||r_0||.  One operator application, one preconditioner application and
+    one round of dot products per iteration."""
+    b = np.asarray(b, float).reshape(-1)
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, float).reshape(-1).copy()
+    M = precondition if precondition is not None else (lambda v: v.copy())
+    r = b - apply_A(x)
+    nr0 = np.linalg.norm(r)
+    hist = [1.0]
+    if nr0 == 0.0:
+        return x, 0, hist
+    z = M(r)
+    p = z.copy()
+    rz = np.dot(r, z)
+    k = 0
+    for k in range(1, max_iter + 1):
+        q = apply_A(p)
+        alpha = rz / np.dot(p, q)
+        x = x + alpha * p
+        r_next = r - alpha * q
+        nr = np.linalg.norm(r_next)
+        hist.append(nr / nr0)
+        if nr <= rtol * nr0:
+            break
+        z = M(r_next)
+        rz_next = np.dot(r_next, z)
+        beta = (rz_next - np.dot(r, z)) / rz
+        p = z + beta * p
+        r, rz = r_next, rz_next
+    return x, k, hist

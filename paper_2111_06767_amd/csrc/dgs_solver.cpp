@@ -1298,6 +1298,84 @@ FgmresResult fgmres(dgs_problem* P, const double* b, double* x, double rtol, int
   return run.R;
 }
 
+// Preconditioned conjugate gradients for symmetric positive definite
+// problems (Sec. III.B; Saad Alg. 9.1) on the fine level, with the direction
+// update beta = (z_{k+1}, r_{k+1} - r_k) / (z_k, r_k), which equals the
+// textbook (z_{k+1}, r_{k+1}) / (z_k, r_k) for a fixed symmetric positive
+// definite preconditioner and stays usable with the V-cycle, which is not.
+// Per iteration: one operator application, one V-cycle, and two host round
+// trips (p.Ap, then the dot products of z_{k+1} with both residuals and
+// |r_{k+1}|^2 in one copy).  Stops when |r_k| <= rtol |r_0| (the recursive
+// residual); the returned residual is the true one.
+FgmresResult cg(dgs_problem* P, const double* b, double* x, double rtol, int max_iter,
+                hipStream_t s) {
+  const long long n = P->nd(0);
+  ensure_krylov(P, 4);
+  double* R = P->d_V;  // rows 0 and 1: r_k and r_{k+1}, alternating
+  double* z = P->d_Z;
+  double* pdir[2] = {P->d_Z + n, P->d_Z + 2 * n};  // p_k and p_{k+1}, alternating
+  double* q = P->d_tmp;
+  double* h = P->d_h;
+  double* hp = P->h_pinned;
+  FgmresResult res;
+  res.history.push_back(1.0);
+  auto fetch = [&](int count) {
+    HIP_OK(hipMemcpyAsync(hp, h, sizeof(double) * count, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i)
+      if (!std::isfinite(hp[i])) throw DgsError(DGS_ERR_NONFINITE, "non-finite value in CG");
+  };
+  int cur = 0, pc = 0;
+  residual_fine(P, x, b, R, s);
+  vcycle(P, R, z, s);
+  HIP_OK(launch_copy(pdir[0], z, n, s));
+  HIP_OK(launch_multidot(R, n, 1, R, n, P->d_partial, h, s));
+  HIP_OK(launch_multidot(R, n, 1, z, n, P->d_partial, h + 1, s));
+  fetch(2);
+  const double nr0 = std::sqrt(hp[0]);
+  double rz = hp[1];
+  if (nr0 == 0.0) {
+    res.converged = true;
+    return res;
+  }
+  for (int k = 1; k <= max_iter; ++k) {
+    double* p = pdir[pc];
+    double* r = R + (size_t)cur * n;
+    double* r_next = R + (size_t)(1 - cur) * n;
+    apply_fine(P, p, q, s);
+    HIP_OK(launch_multidot(p, n, 1, q, n, P->d_partial, h, s));
+    fetch(1);
+    if (!(hp[0] > 0.0)) break;  // A is not positive definite on p: stop, not converged
+    const double alpha = rz / hp[0];
+    HIP_OK(launch_axpy(x, alpha, p, n, s));
+    HIP_OK(launch_waxpy(r_next, r, -alpha, q, n, s));
+    res.iterations = k;
+    // z_{k+1} is computed before |r_{k+1}| is known: one V-cycle more than
+    // needed at the end, one host round trip less in every iteration
+    vcycle(P, r_next, z, s);
+    HIP_OK(launch_multidot(R, n, 2, z, n, P->d_partial, h, s));  // (r_0 row, z), (r_1 row, z)
+    HIP_OK(launch_multidot(r_next, n, 1, r_next, n, P->d_partial, h + 2, s));
+    fetch(3);
+    const double nr = std::sqrt(hp[2]);
+    res.history.push_back(nr / nr0);
+    if (nr <= rtol * nr0) {
+      res.converged = true;
+      break;
+    }
+    const double rz_next = hp[1 - cur], zr_old = hp[cur];
+    const double beta = (rz_next - zr_old) / rz;
+    HIP_OK(launch_waxpy(pdir[1 - pc], z, beta, p, n, s));
+    rz = rz_next;
+    cur = 1 - cur;
+    pc = 1 - pc;
+  }
+  residual_fine(P, x, b, P->d_tmp2, s);
+  HIP_OK(launch_multidot(P->d_tmp2, n, 1, P->d_tmp2, n, P->d_partial, h, s));
+  fetch(1);
+  res.rel_residual = std::sqrt(hp[0]) / nr0;
+  return res;
+}
+
 // Newton-Raphson with a backtracking line search (Sec. III.A) as a resumable
 // run: init() evaluates the first residual, each step() performs one Newton
 // step (linearise, solve the linear system with FGMRES to linear_rtol, line
@@ -2007,6 +2085,22 @@ int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, v
     if (!prob || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
     const double t0 = now_s();
     FgmresResult R = fgmres(prob, b, u, prob->opt.rtol, prob->opt.max_iter, as_stream(stream));
+    fill_stats(stats, R, t0, prob->t_setup);
+    if (stats) {
+      stats->newton_steps = 0;
+      stats->backtracks = 0;
+    }
+    if (!std::isfinite(R.rel_residual)) return fail(DGS_ERR_NONFINITE, "non-finite residual");
+    return R.converged ? DGS_OK : DGS_NOT_CONVERGED;
+  });
+}
+
+int dgs_cg_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (b == u) return fail(DGS_ERR_INVALID, "b and u must not overlap");
+    const double t0 = now_s();
+    FgmresResult R = cg(prob, b, u, prob->opt.rtol, prob->opt.max_iter, as_stream(stream));
     fill_stats(stats, R, t0, prob->t_setup);
     if (stats) {
       stats->newton_steps = 0;

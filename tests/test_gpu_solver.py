@@ -187,3 +187,37 @@ def test_caller_allocator_gives_the_same_bits():
     assert results[0][1] == results[1][1] and results[0][2] == results[1][2]
     assert np.array_equal(results[0][0], results[1][0])
     assert results[1][2] <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("elements,p,levels", [((2, 2, 2), 3, 2), ((4, 2, 2), 3, 2),
+                                               ((4, 4, 4), 4, 3), ((3, 2, 2), 2, 0)])
+def test_cg_solve_matches_oracle(elements, p, levels, precision):
+    """Preconditioned CG (Sec. III.B, Saad Alg. 9.1) on the GPU against the
+    oracle's CG with the oracle's V-cycle: iteration counts within one, the
+    same solution, and a true residual at the tolerance."""
+    import paper_2111_06767_amd as dg
+    announce(f"cg solve elements={elements} p={p} levels={levels} {precision}")
+    N = p + 1
+    m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), elements, p)
+    x, y, z = m.node_coordinates()
+    b = oop.apply_mass(m, W.sin_product_source(x, y, z)).reshape(-1)
+    b = b + 1e-2 * W.random_normal(61, m.ndof) * np.abs(b).max()
+    A = lambda v: oop.apply_operator(m, v.reshape(m.E, N, N, N), 1.5).reshape(-1)
+    V = multigrid.VCycle(m, 1.5, levels=levels if levels else 64)
+    u_ref, its_ref, _ = krylov.cg(A, b, precondition=V, rtol=1e-10)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, precision=precision)
+    u, st = prob.solve_cg(to_gpu(b))
+    u = to_np(u)
+    assert st["converged"], st
+    assert abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
+    assert st["rel_residual"] <= 2e-10
+    assert np.linalg.norm(b - A(u)) / np.linalg.norm(b) <= 2e-10
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
+    # history: 1, then the recursive residuals, the last one at the tolerance
+    h = st["history"]
+    assert h[0] == 1.0 and h[-1] <= 1e-10 and len(h) == st["iterations"] + 1
+    # a zero right-hand side with a zero guess needs no iteration
+    u0, st0 = prob.solve_cg(to_gpu(np.zeros(m.ndof)))
+    assert st0["converged"] and st0["iterations"] == 0 and not to_np(u0).any()
+    prob.close()

@@ -41,3 +41,58 @@ def test_nonzero_initial_guess_and_estimate_is_true_residual():
     true = np.linalg.norm(b - A(x)) / r0
     assert true <= 2e-10
     assert abs(true - hist[-1]) <= 1e-11
+
+
+def _spd(n, seed, cond=30.0):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    return Q @ np.diag(np.geomspace(1.0, cond, n)) @ Q.T
+
+
+def _galerkin_iterate(A, b, K):
+    """The point of the space spanned by the columns of K that minimises the
+    A-norm of the error: the k-th conjugate-gradient iterate when K spans the
+    k-th (preconditioned) Krylov space."""
+    Q, _ = np.linalg.qr(K)
+    return Q @ np.linalg.solve(Q.T @ A @ Q, Q.T @ b)
+
+
+def test_cg_iterates_minimise_the_energy_error_over_krylov_spaces():
+    # x_k = argmin over x in K_k(A, b) of ||x - x*||_A, built independently
+    # from an orthonormal basis of the Krylov space; with a fixed SPD
+    # preconditioner M the space is K_k(M A, M b)
+    n = 12
+    A = _spd(n, 3)
+    b = np.random.default_rng(4).standard_normal(n)
+    Mp = _spd(n, 5, cond=4.0)
+    for precond in (None, Mp):
+        M = (lambda v: v.copy()) if precond is None else (lambda v: precond @ v)
+        for k in range(1, 6):
+            x, its, _ = krylov.cg(lambda v: A @ v, b, precondition=M, rtol=1e-300, max_iter=k)
+            assert its == k
+            cols = [M(b)]
+            for _ in range(k - 1):
+                cols.append(M(A @ cols[-1]))
+            ref = _galerkin_iterate(A, b, np.stack(cols, axis=1))
+            np.testing.assert_allclose(x, ref, rtol=1e-9, atol=1e-12)
+
+
+def test_cg_solves_spd_dg_poisson_and_stops_at_rtol():
+    # the DG Poisson operator is symmetric positive definite; unpreconditioned
+    # CG reaches the dense solution, and with the (non-symmetric) V-cycle the
+    # flexible update still converges to the same solution
+    m = mesh.BoxMesh([0, 0, 0], [1, 1, 1], (2, 2, 1), 2)
+    A = operator.assemble(m, 1.5)
+    assert np.allclose(A, A.T) and np.linalg.eigvalsh(A).min() > 0
+    b = np.random.default_rng(6).standard_normal(m.ndof)
+    ref = np.linalg.solve(A, b)
+    x, k, hist = krylov.cg(lambda v: A @ v, b, rtol=1e-12, max_iter=10 * m.ndof)
+    np.testing.assert_allclose(x, ref, rtol=1e-8, atol=1e-10)
+    assert hist[-1] <= 1e-12 and all(h > 1e-12 for h in hist[:-1])
+    V = multigrid.VCycle(m, 1.5, levels=2)
+    x, k2, hist = krylov.cg(lambda v: A @ v, b, precondition=V, rtol=1e-10)
+    assert k2 < k and hist[-1] <= 1e-10
+    np.testing.assert_allclose(x, ref, rtol=1e-8, atol=1e-10)
+    # a zero right-hand side needs no iteration
+    x0, k0, h0 = krylov.cg(lambda v: A @ v, np.zeros(m.ndof))
+    assert k0 == 0 and h0 == [1.0] and not np.any(x0)
