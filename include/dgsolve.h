@@ -71,6 +71,9 @@ typedef struct {
   int max_iter;        /* FGMRES iteration limit (no restart)                   [200] */
   double rtol;         /* FGMRES relative residual tolerance                   [1e-10] */
   int use_graphs;      /* 1 = replay each V-cycle from a captured hipGraph        [1] */
+  int restart;         /* FGMRES: 0 = no restart; m > 0 = restarted FGMRES(m),
+                          cycles of at most m iterations from the true residual
+                          (max_iter bounds all cycles together)                 [0] */
 } dgs_options;
 
 /* Statistics of a solve.  `history` may be NULL; otherwise it receives up to

@@ -9,33 +9,57 @@ rotations, and the iteration stops when the residual estimate drops below
 rtol times the initial residual norm.  The solution is x0 + Z y with Z the
 preconditioned vectors.
 
-Readings: no restart; the residual is the Euclidean 2-norm of the massive DG
-residual b - A x over all points; the stopping test uses the Givens estimate.
+Readings: no restart unless asked for; the residual is the Euclidean 2-norm
+of the massive DG residual b - A x over all points; the stopping test uses
+the Givens estimate.
 """
 from __future__ import annotations
 
 import numpy as np
 
 
-def fgmres(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200):
-    """Returns (x, iterations, history of relative residual estimates)."""
+def fgmres(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200, restart=None):
+    """Returns (x, iterations, history of relative residual estimates).
+
+    restart=m: restarted FGMRES(m), cycles of at most m iterations, each
+    started from the true residual of the previous cycle's solution; the
+    tolerance and the history stay relative to the first cycle's ||r_0||
+    and max_iter bounds the iterations of all cycles together."""
     b = np.asarray(b, float).reshape(-1)
-    x0 = np.zeros_like(b) if x0 is None else np.asarray(x0, float).reshape(-1).copy()
+    x = np.zeros_like(b) if x0 is None else np.asarray(x0, float).reshape(-1).copy()
     M = precondition if precondition is not None else (lambda v: v.copy())
-    r0 = b - apply_A(x0)
-    beta = np.linalg.norm(r0)
+    m = max_iter if not restart else min(restart, max_iter)
     hist = [1.0]
-    if beta == 0.0:
-        return x0, 0, hist
+    beta0 = None
+    total = 0
+    while True:
+        r0 = b - apply_A(x)
+        beta = np.linalg.norm(r0)
+        if beta0 is None:
+            beta0 = beta
+        if beta == 0.0:
+            return x, total, hist
+        x, k, done = _fgmres_cycle(apply_A, M, x, r0, beta, beta0, rtol,
+                                   min(m, max_iter - total), hist)
+        total += k
+        if done or total >= max_iter:
+            return x, total, hist
+
+
+def _fgmres_cycle(apply_A, M, x0, r0, beta, beta0, rtol, m, hist):
+    """One cycle of at most m iterations from x0 with residual r0 = b - A x0
+    (beta = ||r0||); appends the estimates |g_{j+1}| / beta0 to hist and
+    returns (x, iterations, converged)."""
     V = [r0 / beta]
     Z = []
-    H = np.zeros((max_iter + 1, max_iter))
-    cs = np.zeros(max_iter)
-    sn = np.zeros(max_iter)
-    g = np.zeros(max_iter + 1)
+    H = np.zeros((m + 1, m))
+    cs = np.zeros(m)
+    sn = np.zeros(m)
+    g = np.zeros(m + 1)
     g[0] = beta
+    done = False
     j = 0
-    for j in range(max_iter):
+    for j in range(m):
         z = M(V[j])
         Z.append(z)
         w = apply_A(z)
@@ -53,8 +77,8 @@ def fgmres(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200):
         H[j + 1, j] = 0.0
         g[j + 1] = -sn[j] * g[j]
         g[j] = cs[j] * g[j]
-        hist.append(abs(g[j + 1]) / beta)
-        done = abs(g[j + 1]) <= rtol * beta
+        hist.append(abs(g[j + 1]) / beta0)
+        done = abs(g[j + 1]) <= rtol * beta0
         if not done and H_next_zero(w):
             done = True
         if done:
@@ -63,7 +87,7 @@ def fgmres(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200):
     k = j + 1
     y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
     x = x0 + sum(y[i] * Z[i] for i in range(k))
-    return x, k, hist
+    return x, k, done
 
 
 def H_next_zero(w):

@@ -1147,11 +1147,14 @@ struct FgmresRun {
   const double* b = nullptr;
   double* x = nullptr;
   double rtol = 0;
-  int m = 0;
+  int m = 0;          // iterations of one cycle (the Krylov basis size)
+  int max_total = 0;  // iterations of all cycles together
   hipStream_t s = nullptr;
   enum Stage { kStart, kIter, kFinish, kDone } stage = kStart;
-  int j = 0;
-  double beta = 0;
+  int j = 0;          // iteration within the cycle
+  int cycles = 0;
+  double beta = 0;    // |r_0| of the cycle
+  double beta0 = 0;   // |r_0| of the first cycle: the reference of rtol and the history
   std::vector<double> H, cs, sn, g;
   FgmresResult R;
 
@@ -1160,16 +1163,23 @@ struct FgmresRun {
     b = bb;
     x = xx;
     rtol = rt;
-    m = mi;
+    max_total = mi;
+    // restarted FGMRES(m): cycles of at most m iterations, each started from
+    // the true residual of the previous cycle's solution
+    m = P->opt.restart > 0 ? std::min(P->opt.restart, mi) : mi;
     s = st;
     ensure_krylov(P, m);
+    cycles = 0;
+    R = FgmresResult();
+    new_cycle();
+  }
+  void new_cycle() {
     stage = kStart;
     j = 0;
     H.assign((size_t)(m + 1) * m, 0.0);
     cs.assign(m, 0.0);
     sn.assign(m, 0.0);
     g.assign(m + 1, 0.0);
-    R = FgmresResult();
   }
   bool done() const { return stage == kDone; }
 
@@ -1213,7 +1223,7 @@ struct FgmresRun {
       else
         HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));
     } else if (stage == kFinish) {
-      const int k = R.iterations;
+      const int k = j;
       std::vector<double> y(k, 0.0);
       for (int i = k - 1; i >= 0; --i) {
         double t = g[i];
@@ -1238,7 +1248,10 @@ struct FgmresRun {
       const double beta2 = hp[0];
       if (!std::isfinite(beta2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite initial residual");
       beta = std::sqrt(beta2);
-      R.history.push_back(1.0);
+      if (cycles++ == 0) {
+        beta0 = beta;
+        R.history.push_back(1.0);
+      }
       if (beta == 0.0) {
         R.converged = true;
         stage = kDone;
@@ -1270,18 +1283,21 @@ struct FgmresRun {
       col[j + 1] = 0.0;
       g[j + 1] = -sn[j] * g[j];
       g[j] = cs[j] * g[j];
-      R.history.push_back(std::fabs(g[j + 1]) / beta);
+      R.history.push_back(std::fabs(g[j + 1]) / beta0);
       ++j;
-      R.iterations = j;
-      if (std::fabs(g[j]) <= rtol * beta || hn2 == 0.0) {
+      ++R.iterations;
+      if (std::fabs(g[j]) <= rtol * beta0 || hn2 == 0.0) {
         R.converged = true;
         stage = kFinish;
-      } else if (j >= m) {
+      } else if (j >= m || R.iterations >= max_total) {
         stage = kFinish;
       }
     } else if (stage == kFinish) {
-      R.rel_residual = std::sqrt(hp[0]) / beta;
-      stage = kDone;
+      R.rel_residual = std::sqrt(hp[0]) / beta0;
+      if (!R.converged && R.iterations < max_total)
+        new_cycle();  // the next cycle starts from the true residual of x
+      else
+        stage = kDone;
     }
   }
 };
@@ -1877,6 +1893,7 @@ void dgs_default_options(dgs_options* o) {
   o->max_iter = 200;
   o->rtol = 1e-10;
   o->use_graphs = 1;
+  o->restart = 0;
 }
 
 const char* dgs_last_error(void) { return g_last_error.c_str(); }
@@ -1900,6 +1917,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     if (opt) o = *opt;
     if (o.overlap < 1 || o.pre_smooth < 0 || o.post_smooth < 0 || o.mg_levels < 0 ||
         o.max_iter < 1 || !(o.rtol > 0.0) || o.subdomain_iters < 0 || o.subdomain_iters > 8 ||
+        o.restart < 0 ||
         (o.precision != DGS_FP64 && o.precision != DGS_MIXED))
       return fail(DGS_ERR_INVALID, "invalid options");
     const long long E0 = (long long)elements[0] * elements[1] * elements[2];

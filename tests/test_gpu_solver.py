@@ -221,3 +221,35 @@ def test_cg_solve_matches_oracle(elements, p, levels, precision):
     u0, st0 = prob.solve_cg(to_gpu(np.zeros(m.ndof)))
     assert st0["converged"] and st0["iterations"] == 0 and not to_np(u0).any()
     prob.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("restart", [2, 3, 50])
+def test_restarted_fgmres_matches_oracle(restart, precision):
+    """Restarted FGMRES(m) (options.restart) against the oracle's: the same
+    iteration count within one, the same solution, the true residual at the
+    tolerance; a restart longer than the run gives the unrestarted bits."""
+    import paper_2111_06767_amd as dg
+    announce(f"restarted fgmres m={restart} {precision}")
+    m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (4, 2, 2), 3)
+    x, y, z = m.node_coordinates()
+    b = oop.apply_mass(m, W.sin_product_source(x, y, z)).reshape(-1)
+    b = b + 1e-2 * W.random_normal(71, m.ndof) * np.abs(b).max()
+    A = lambda v: oop.apply_operator(m, v.reshape(m.E, 4, 4, 4), 1.5).reshape(-1)
+    V = multigrid.VCycle(m, 1.5, levels=2)
+    u_ref, its_ref, _ = krylov.fgmres(A, b, precondition=V, rtol=1e-10, restart=restart)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), (4, 2, 2), 3, mg_levels=2, precision=precision,
+                      restart=restart)
+    u, st = prob.solve(to_gpu(b))
+    u = to_np(u)
+    assert st["converged"] and abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
+    assert st["rel_residual"] <= 2e-10
+    assert np.linalg.norm(b - A(u)) / np.linalg.norm(b) <= 2e-10
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
+    assert len(st["history"]) == st["iterations"] + 1
+    if restart == 50:
+        plain = dg.Problem((0, 0, 0), (1, 1, 1), (4, 2, 2), 3, mg_levels=2, precision=precision)
+        u2, st2 = plain.solve(to_gpu(b))
+        assert st2["iterations"] == st["iterations"] and np.array_equal(to_np(u2), u)
+        plain.close()
+    prob.close()

@@ -96,3 +96,28 @@ def test_cg_solves_spd_dg_poisson_and_stops_at_rtol():
     # a zero right-hand side needs no iteration
     x0, k0, h0 = krylov.cg(lambda v: A @ v, np.zeros(m.ndof))
     assert k0 == 0 and h0 == [1.0] and not np.any(x0)
+
+
+def test_restarted_fgmres_equals_scipy_restarted_gmres_and_converges():
+    # unpreconditioned FGMRES(m) is GMRES(m): after c cycles its iterate is
+    # scipy's GMRES with restart=m and maxiter=c cycles
+    m_ = mesh.BoxMesh([0, 0, 0], [1, 1, 1], (2, 2, 1), 2)
+    A = operator.assemble(m_, 1.5)
+    b = np.random.default_rng(8).standard_normal(m_.ndof)
+    for m, c in ((5, 2), (8, 3)):
+        x, k, hist = krylov.fgmres(lambda v: A @ v, b, rtol=1e-300, max_iter=m * c, restart=m)
+        assert k == m * c and len(hist) == k + 1
+        xs, _ = spla.gmres(A, b, rtol=1e-300, atol=0.0, restart=m, maxiter=c)
+        np.testing.assert_allclose(x, xs, rtol=1e-8, atol=1e-10)
+        # the history is relative to the first residual and drops across cycles
+        assert hist[0] == 1.0 and hist[m] < 1.0 and hist[-1] < hist[m]
+    # with the V-cycle it converges to the dense solution; a restart longer
+    # than the run changes nothing
+    V = multigrid.VCycle(m_, 1.5, levels=2)
+    ref = np.linalg.solve(A, b)
+    x1, k1, h1 = krylov.fgmres(lambda v: A @ v, b, precondition=V, rtol=1e-10)
+    x2, k2, h2 = krylov.fgmres(lambda v: A @ v, b, precondition=V, rtol=1e-10, restart=k1)
+    assert k2 == k1 and np.array_equal(x1, x2) and h1 == h2
+    x3, k3, h3 = krylov.fgmres(lambda v: A @ v, b, precondition=V, rtol=1e-10, restart=3)
+    assert k3 >= k1 and h3[-1] <= 1e-10
+    np.testing.assert_allclose(x3, ref, rtol=1e-8, atol=1e-10)
