@@ -374,6 +374,12 @@ def main():
                      iterations=rst["iterations"], rel_residual=rst["rel_residual"],
                      converged=rst["converged"])
     rprob.close()
+    _log("8^3 p=6 with the W-cycle")
+    wprob, wb, _ = build_c2(dg, "mixed", cycle=2)
+    _, wst, wtimes, _ = time_solves(wprob, wb, 10, 2)
+    wcycle = dict(ms_p50=round(1e3 * _pct(wtimes, 50), 3), iterations=wst["iterations"],
+                  rel_residual=wst["rel_residual"], converged=wst["converged"])
+    wprob.close()
     _log("subdomain GEMM and apply timings")
     gemm = time_subdomain_gemm(mixed["prob"])
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
@@ -467,6 +473,7 @@ def main():
                   "sweep_2M_dofs": sweep},
         "c2_conjugate_gradients": cg,
         "c2_restarted_fgmres_mixed": restarted,
+        "c2_wcycle_mixed": wcycle,
         "c5_16x16x16_p7": c5,
         "serving": serving,
         "roofline": roofline,

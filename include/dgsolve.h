@@ -74,6 +74,9 @@ typedef struct {
   int restart;         /* FGMRES: 0 = no restart; m > 0 = restarted FGMRES(m),
                           cycles of at most m iterations from the true residual
                           (max_iter bounds all cycles together)                 [0] */
+  int cycle;           /* visits of each coarser multigrid level per visit of its
+                          parent: 1 = V-cycle (Sec. III.C.3), 2 = W-cycle, whose
+                          second visit starts from the first one's result       [1] */
 } dgs_options;
 
 /* Statistics of a solve.  `history` may be NULL; otherwise it receives up to

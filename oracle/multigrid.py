@@ -96,12 +96,16 @@ def restrict(fine: BoxMesh, coarse: BoxMesh, split, rf):
 
 
 class VCycle:
-    """One multigrid V-cycle with ``pre``/``post`` Schwarz steps per level."""
+    """One multigrid cycle with ``pre``/``post`` Schwarz steps per level
+    (Sec. III.C.3).  ``gamma`` is the number of visits of each coarser level
+    per visit of its parent: 1 is the paper's V-cycle, 2 the W-cycle, whose
+    second visit starts from the first one's coarse-grid result."""
 
     def __init__(self, mesh: BoxMesh, C, levels=2, overlap=2, pre=3, post=3,
-                 diag=None, subdomain_iters=0):
+                 diag=None, subdomain_iters=0, gamma=1):
         self.levels = hierarchy(mesh, levels)
         self.pre, self.post = pre, post
+        self.gamma = gamma
         self.smoothers = []
         d = None if diag is None else np.asarray(diag, float).reshape(-1)
         for li, (m, split) in enumerate(self.levels):
@@ -113,15 +117,18 @@ class VCycle:
     def __call__(self, b):
         return self._cycle(0, np.asarray(b, float).reshape(-1))
 
-    def _cycle(self, l, b):
+    def _cycle(self, l, b, u0=None):
         mesh, split = self.levels[l]
         sm = self.smoothers[l]
-        u = np.zeros_like(b)
+        u = np.zeros_like(b) if u0 is None else u0
         u = sm.smooth(u, b, self.pre)  # presmoothing
         if split is None:  # coarsest grid: pre- and post-smoothing
             return sm.smooth(u, b, self.post)
         coarse = self.levels[l + 1][0]
         r = b - sm.apply(u)  # eq. mg_res
-        uc = self._cycle(l + 1, restrict(mesh, coarse, split, r))
+        bc = restrict(mesh, coarse, split, r)
+        uc = None
+        for _ in range(self.gamma):
+            uc = self._cycle(l + 1, bc, uc)
         u = u + prolongate(mesh, coarse, split, uc)
         return sm.smooth(u, b, self.post)  # postsmoothing

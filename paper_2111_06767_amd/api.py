@@ -44,7 +44,8 @@ class Options(ctypes.Structure):
                 ("pre_smooth", ctypes.c_int), ("post_smooth", ctypes.c_int),
                 ("precision", ctypes.c_int), ("subdomain_iters", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("use_graphs", ctypes.c_int), ("restart", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int), ("restart", ctypes.c_int),
+                ("cycle", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -958,10 +958,38 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
 }
 
 // rs0_ready: the finest level's rows already hold R_S r.
+// One visit of level l in a multigrid cycle (Sec. III.C.3): presmoothing,
+// the residual restricted to the next coarser level, `cycle` visits of that
+// level (the first from zero, a second one from the first one's result: the
+// W-cycle), prolongation, postsmoothing; the coarsest level smooths only.
+// u_zero: u[l] starts from zero (its first smoothing step writes u);
+// rs_ready: the first step's subdomain rows r_S = R_S b are already gathered.
+void mg_visit(dgs_problem* P, int l, const std::vector<const double*>& b,
+              const std::vector<double*>& u, bool u_zero, bool rs_ready, int coarse_steps,
+              hipStream_t s) {
+  const int nl = (int)P->levels.size();
+  const int N = P->N;
+  Level& L = P->levels[l];
+  const int pre = l < nl - 1 ? P->opt.pre_smooth : coarse_steps;
+  // a level without smoothing steps still needs its zero start
+  if (u_zero && pre == 0) HIP_OK(launch_fill(u[l], 0.0, P->nd(l), s));
+  schwarz_steps(P, l, b[l], u[l], pre, u_zero, s, rs_ready);
+  if (l == nl - 1) return;
+  const bool diag = P->diag_active && L.d_diag != nullptr;
+  HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u[l], L.d_r, b[l], L.d_diag, nullptr,
+                      L.d_nbr, L.op, P->dt, L.acfg_out, s, L.d_order));
+  Level& C = P->levels[l + 1];
+  // the restriction also writes the coarse level's first r_S rows
+  HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
+  for (int visit = 0; visit < P->opt.cycle; ++visit)
+    mg_visit(P, l + 1, b, u, visit == 0, visit == 0, coarse_steps, s);
+  HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->dt, s));
+  schwarz_steps(P, l, b[l], u[l], P->opt.post_smooth, false, s);
+}
+
 void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
                   bool rs0_ready = false) {
   const int nl = (int)P->levels.size();
-  const int N = P->N;
   std::vector<const double*> b(nl);
   std::vector<double*> u(nl);
   b[0] = r;
@@ -978,36 +1006,9 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
   int coarse_steps = P->opt.pre_smooth + P->opt.post_smooth;
   if (Lc.E == 1 && !(P->diag_active && Lc.d_diag != nullptr))
     coarse_steps = std::min(coarse_steps, 1);
-  // every level starts from zero: the first smoothing step writes u, so only
-  // a level without smoothing steps needs clearing
-  for (int l = 0; l < nl; ++l) {
-    const int steps = l < nl - 1 ? P->opt.pre_smooth : coarse_steps;
-    if (steps == 0) HIP_OK(launch_fill(u[l], 0.0, P->nd(l), s));
-  }
-  for (int l = 0; l < nl - 1; ++l) {
-    Level& L = P->levels[l];
-    schwarz_steps(P, l, b[l], u[l], P->opt.pre_smooth, true, s, l == 0 ? rs0_ready : true);
-    const bool diag = P->diag_active && L.d_diag != nullptr;
-    HIP_OK(launch_apply(N, diag ? kResidualDiag : kResidual, u[l], L.d_r, b[l], L.d_diag, nullptr,
-                        L.d_nbr, L.op, P->dt, L.acfg_out, s, L.d_order));
-    Level& C = P->levels[l + 1];
-    // the restriction also writes the coarse level's first r_S rows
-    HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
-  }
-  schwarz_steps(P, nl - 1, b[nl - 1], u[nl - 1], coarse_steps, true, s,
-                nl > 1 ? true : rs0_ready);
-  for (int l = nl - 2; l >= 0; --l) {
-    Level& L = P->levels[l];
-    Level& C = P->levels[l + 1];
-    HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->dt, s));
-    schwarz_steps(P, l, b[l], u[l], P->opt.post_smooth, false, s);
-  }
+  mg_visit(P, 0, b, u, true, rs0_ready, coarse_steps, s);
 }
 
-// One V-cycle.  With graphs enabled the cycle is captured once (per operator
-// kind) on an internal stream, reading level 0's right-hand-side buffer and
-// writing level 0's solution buffer, and replayed on the caller's stream with
-// one copy in and one copy out.
 // One captured V-cycle from the finest level's d_b into its d_u (the graph
 // for the current operator kind is captured on first use).
 void vcycle_graph(dgs_problem* P, hipStream_t s) {
@@ -1894,6 +1895,7 @@ void dgs_default_options(dgs_options* o) {
   o->rtol = 1e-10;
   o->use_graphs = 1;
   o->restart = 0;
+  o->cycle = 1;
 }
 
 const char* dgs_last_error(void) { return g_last_error.c_str(); }
@@ -1917,7 +1919,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     if (opt) o = *opt;
     if (o.overlap < 1 || o.pre_smooth < 0 || o.post_smooth < 0 || o.mg_levels < 0 ||
         o.max_iter < 1 || !(o.rtol > 0.0) || o.subdomain_iters < 0 || o.subdomain_iters > 8 ||
-        o.restart < 0 ||
+        o.restart < 0 || o.cycle < 1 || o.cycle > 2 ||
         (o.precision != DGS_FP64 && o.precision != DGS_MIXED))
       return fail(DGS_ERR_INVALID, "invalid options");
     const long long E0 = (long long)elements[0] * elements[1] * elements[2];

@@ -253,3 +253,30 @@ def test_restarted_fgmres_matches_oracle(restart, precision):
         assert st2["iterations"] == st["iterations"] and np.array_equal(to_np(u2), u)
         plain.close()
     prob.close()
+
+
+@pytest.mark.parametrize("elements,p,levels", [((4, 4, 2), 3, 3), ((8, 4, 4), 1, 3),
+                                               ((4, 4, 4), 2, 0), ((2, 2, 2), 4, 2)])
+def test_wcycle_matches_oracle(elements, p, levels):
+    """The W-cycle (options.cycle = 2) against the oracle's (gamma = 2): one
+    cycle in FP64 at the V-cycle's tolerance, and a mixed-precision FGMRES
+    solve preconditioned by it."""
+    import paper_2111_06767_amd as dg
+    announce(f"wcycle elements={elements} p={p} levels={levels}")
+    N = p + 1
+    m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), elements, p)
+    W2 = multigrid.VCycle(m, 1.5, levels=levels if levels else 64, gamma=2)
+    r = W.random_normal(81, m.ndof)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, cycle=2)
+    got = to_np(prob.precondition(to_gpu(r)))
+    assert rel_max(got, W2(r)) < 1e-10, rel_max(got, W2(r))
+    prob.close()
+    A = lambda v: oop.apply_operator(m, v.reshape(m.E, N, N, N), 1.5).reshape(-1)
+    u_ref, its_ref, _ = krylov.fgmres(A, r, precondition=W2, rtol=1e-10)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, cycle=2,
+                      precision="mixed")
+    u, st = prob.solve(to_gpu(r))
+    u = to_np(u)
+    assert st["converged"] and abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
+    prob.close()

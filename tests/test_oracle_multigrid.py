@@ -91,3 +91,38 @@ def test_mg_schwarz_iterations_flat_under_h_refinement():
         its.append(k)
         assert hist[-1] <= 1e-10
     assert abs(its[1] - its[0]) <= 2  # 8 and 9 iterations
+
+
+def test_wcycle_matches_dense_composition():
+    # Three-level W-cycle (gamma = 2) written with dense matrices: every
+    # coarser level is visited twice per visit of its parent, the second
+    # visit starting from the first one's result; smoothing u <- u + B (b - A u)
+    fine = mesh.BoxMesh([0, 0, 0], [1, 1, 1], (8, 4, 4), 1)
+    V = multigrid.VCycle(fine, 1.5, levels=3, gamma=2)
+    lv = [m for m, _ in V.levels]
+    A = [operator.assemble(m, 1.5) for m in lv]
+    B = [_dense(schwarz.SchwarzSmoother(m, 1.5, 2).correction, m.ndof) for m in lv]
+    P = [_dense(lambda v, l=l: multigrid.prolongate(lv[l], lv[l + 1], V.levels[l][1], v),
+                lv[l + 1].ndof) for l in range(2)]
+
+    def smooth(l, u, b, k):
+        for _ in range(k):
+            u = u + B[l] @ (b - A[l] @ u)
+        return u
+
+    def cycle(l, b, u):
+        u = smooth(l, u, b, 3)
+        if l == 2:
+            return smooth(l, u, b, 3)
+        bc = P[l].T @ (b - A[l] @ u)
+        uc = np.zeros(lv[l + 1].ndof)
+        for _ in range(2):
+            uc = cycle(l + 1, bc, uc)
+        return smooth(l, u + P[l] @ uc, b, 3)
+
+    b = np.random.default_rng(3).standard_normal(fine.ndof)
+    np.testing.assert_allclose(V(b), cycle(0, b, np.zeros(fine.ndof)), rtol=1e-11, atol=1e-11)
+    # gamma = 1 is the V-cycle; the W-cycle is a different, also linear map
+    v1 = multigrid.VCycle(fine, 1.5, levels=3)(b)
+    assert np.linalg.norm(V(b) - v1) > 1e-6 * np.linalg.norm(v1)
+    np.testing.assert_allclose(V(3.0 * b), 3.0 * V(b), rtol=1e-11, atol=1e-11)
