@@ -163,7 +163,7 @@ int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, v
  * the options apply to the recursively updated residual, stats->rel_residual
  * is the true relative residual of the result.  DGS_NOT_CONVERGED also when a
  * direction p has p.Ap <= 0 (A not positive definite).  b and u must not
- * overlap; the call synchronises the stream twice per iteration. */
+ * overlap; the call synchronises the stream once per iteration. */
 int dgs_cg_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream);
 
 /* Add a pointwise term: subsequent dgs_schwarz_smooth, dgs_precondition and

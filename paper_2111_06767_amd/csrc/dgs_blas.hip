@@ -44,6 +44,21 @@ __global__ void k_waxpy(double* __restrict__ y, const double* __restrict__ x, do
   if (g < n) y[g] = x[g] + lam * dx[g];
 }
 
+// One conjugate-gradient update with the step length formed on the device:
+// alpha = rz / (p . q) (0 when p . q <= 0, a breakdown the caller detects from
+// the same value), x += alpha p, r_next = r - alpha q.
+__global__ void k_cg_step(double* __restrict__ x, double* __restrict__ r_next,
+                          const double* __restrict__ r, const double* __restrict__ p,
+                          const double* __restrict__ q, double rz, const double* __restrict__ pq,
+                          long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  const double d = pq[0];
+  const double alpha = d > 0.0 ? rz / d : 0.0;
+  x[g] += alpha * p[g];
+  r_next[g] = r[g] - alpha * q[g];
+}
+
 // Two-stage dot products: the vector is cut into multidot_blocks(n) fixed
 // chunks; block b writes partial[b * m + i] = (its chunk of V_i) . w, eight
 // vectors per pass, and one block per i then sums the partials in a fixed
@@ -241,6 +256,12 @@ hipError_t launch_copy(double* y, const double* x, long long n, hipStream_t s) {
 hipError_t launch_axpy(double* y, double a, const double* x, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_axpy, dim3(nblk(n)), dim3(256), 0, s, y, a, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_cg_step(double* x, double* r_next, const double* r, const double* p,
+                          const double* q, double rz, const double* pq, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cg_step, dim3(nblk(n)), dim3(256), 0, s, x, r_next, r, p, q, rz, pq, n);
   return hipGetLastError();
 }
 hipError_t launch_waxpy(double* y, const double* x, double lam, const double* dx, long long n,

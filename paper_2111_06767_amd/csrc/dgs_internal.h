@@ -298,6 +298,10 @@ hipError_t launch_puncture_diag(int N, const double* alpha, const double* beta, 
 // y = x + lam * dx
 hipError_t launch_waxpy(double* y, const double* x, double lam, const double* dx, long long n,
                         hipStream_t s);
+// Conjugate-gradient update: alpha = rz / *pq (0 if *pq <= 0; pq on the
+// device), x += alpha p, r_next = r - alpha q.
+hipError_t launch_cg_step(double* x, double* r_next, const double* r, const double* p,
+                          const double* q, double rz, const double* pq, long long n, hipStream_t s);
 
 // Set-up kernels: unit-vector fill and column gather for the patch apply, the
 // blocked inversion, and the transposed copies of the results.

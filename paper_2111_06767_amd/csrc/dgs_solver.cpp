@@ -1320,9 +1320,9 @@ FgmresResult fgmres(dgs_problem* P, const double* b, double* x, double rtol, int
 // update beta = (z_{k+1}, r_{k+1} - r_k) / (z_k, r_k), which equals the
 // textbook (z_{k+1}, r_{k+1}) / (z_k, r_k) for a fixed symmetric positive
 // definite preconditioner and stays usable with the V-cycle, which is not.
-// Per iteration: one operator application, one V-cycle, and two host round
-// trips (p.Ap, then the dot products of z_{k+1} with both residuals and
-// |r_{k+1}|^2 in one copy).  Stops when |r_k| <= rtol |r_0| (the recursive
+// Per iteration: one operator application, one V-cycle, and one host round
+// trip (p.Ap, the dot products of z_{k+1} with both residuals and |r_{k+1}|^2
+// in one copy); alpha is formed on the device.  Stops when |r_k| <= rtol |r_0| (the recursive
 // residual); the returned residual is the true one.
 FgmresResult cg(dgs_problem* P, const double* b, double* x, double rtol, int max_iter,
                 hipStream_t s) {
@@ -1360,19 +1360,20 @@ FgmresResult cg(dgs_problem* P, const double* b, double* x, double rtol, int max
     double* r = R + (size_t)cur * n;
     double* r_next = R + (size_t)(1 - cur) * n;
     apply_fine(P, p, q, s);
-    HIP_OK(launch_multidot(p, n, 1, q, n, P->d_partial, h, s));
-    fetch(1);
-    if (!(hp[0] > 0.0)) break;  // A is not positive definite on p: stop, not converged
-    const double alpha = rz / hp[0];
-    HIP_OK(launch_axpy(x, alpha, p, n, s));
-    HIP_OK(launch_waxpy(r_next, r, -alpha, q, n, s));
+    // p.Ap stays on the device: the update kernel forms alpha from it
+    HIP_OK(launch_multidot(p, n, 1, q, n, P->d_partial, h + 3, s));
+    HIP_OK(launch_cg_step(x, r_next, r, p, q, rz, h + 3, n, s));
     res.iterations = k;
     // z_{k+1} is computed before |r_{k+1}| is known: one V-cycle more than
-    // needed at the end, one host round trip less in every iteration
+    // needed at the end, one host round trip per iteration
     vcycle(P, r_next, z, s);
     HIP_OK(launch_multidot(R, n, 2, z, n, P->d_partial, h, s));  // (r_0 row, z), (r_1 row, z)
     HIP_OK(launch_multidot(r_next, n, 1, r_next, n, P->d_partial, h + 2, s));
-    fetch(3);
+    fetch(4);
+    if (!(hp[3] > 0.0)) {  // A is not positive definite on p: stopped, not converged
+      res.iterations = k - 1;
+      break;
+    }
     const double nr = std::sqrt(hp[2]);
     res.history.push_back(nr / nr0);
     if (nr <= rtol * nr0) {
