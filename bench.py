@@ -380,6 +380,12 @@ def main():
     wcycle = dict(ms_p50=round(1e3 * _pct(wtimes, 50), 3), iterations=wst["iterations"],
                   rel_residual=wst["rel_residual"], converged=wst["converged"])
     wprob.close()
+    _log("8^3 p=6 with additive multigrid")
+    aprob, ab, _ = build_c2(dg, "mixed", additive=1)
+    _, ast_, atimes, _ = time_solves(aprob, ab, 10, 2)
+    additive = dict(ms_p50=round(1e3 * _pct(atimes, 50), 3), iterations=ast_["iterations"],
+                    rel_residual=ast_["rel_residual"], converged=ast_["converged"])
+    aprob.close()
     _log("subdomain GEMM and apply timings")
     gemm = time_subdomain_gemm(mixed["prob"])
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
@@ -474,6 +480,7 @@ def main():
         "c2_conjugate_gradients": cg,
         "c2_restarted_fgmres_mixed": restarted,
         "c2_wcycle_mixed": wcycle,
+        "c2_additive_mg_mixed": additive,
         "c5_16x16x16_p7": c5,
         "serving": serving,
         "roofline": roofline,

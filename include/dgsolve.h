@@ -77,6 +77,10 @@ typedef struct {
   int cycle;           /* visits of each coarser multigrid level per visit of its
                           parent: 1 = V-cycle (Sec. III.C.3), 2 = W-cycle, whose
                           second visit starts from the first one's result       [1] */
+  int additive;        /* 1 = additive multigrid instead (the variant of Sec. V):
+                          the residual restricted to every level, each level
+                          smoothed from zero with pre + post steps, the
+                          prolongated corrections summed; `cycle` is unused  [0] */
 } dgs_options;
 
 /* Statistics of a solve.  `history` may be NULL; otherwise it receives up to

@@ -132,3 +132,39 @@ class VCycle:
             uc = self._cycle(l + 1, bc, uc)
         u = u + prolongate(mesh, coarse, split, uc)
         return sm.smooth(u, b, self.post)  # postsmoothing
+
+
+class AdditiveMG:
+    """Additive multigrid, the variant Sec. V names: the residual is restricted
+    to every level, each level smooths its restriction independently from
+    zero, and the prolongated corrections of all levels are summed.
+
+    Reading: every level runs pre + post Schwarz steps (the smoothing count the
+    V-cycle gives its coarsest level); with a linearised operator the coarse
+    levels carry the restricted diagonal as in VCycle."""
+
+    def __init__(self, mesh: BoxMesh, C, levels=2, overlap=2, pre=3, post=3,
+                 diag=None, subdomain_iters=0):
+        self.levels = hierarchy(mesh, levels)
+        self.steps = pre + post
+        self.smoothers = []
+        d = None if diag is None else np.asarray(diag, float).reshape(-1)
+        for li, (m, split) in enumerate(self.levels):
+            self.smoothers.append(SchwarzSmoother(m, C, overlap, diag=d,
+                                                  subdomain_iters=subdomain_iters))
+            if split is not None and d is not None:
+                d = restrict(m, self.levels[li + 1][0], split, d)
+
+    def __call__(self, r):
+        b = [np.asarray(r, float).reshape(-1)]
+        for li in range(len(self.levels) - 1):
+            m, split = self.levels[li]
+            b.append(restrict(m, self.levels[li + 1][0], split, b[-1]))
+        z = None
+        for li in reversed(range(len(self.levels))):
+            u = self.smoothers[li].smooth(np.zeros_like(b[li]), b[li], self.steps)
+            if z is not None:
+                m, split = self.levels[li]
+                u = u + prolongate(m, self.levels[li + 1][0], split, z)
+            z = u
+        return z

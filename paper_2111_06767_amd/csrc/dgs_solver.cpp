@@ -1006,7 +1006,29 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
   int coarse_steps = P->opt.pre_smooth + P->opt.post_smooth;
   if (Lc.E == 1 && !(P->diag_active && Lc.d_diag != nullptr))
     coarse_steps = std::min(coarse_steps, 1);
-  mg_visit(P, 0, b, u, true, rs0_ready, coarse_steps, s);
+  if (!P->opt.additive) {
+    mg_visit(P, 0, b, u, true, rs0_ready, coarse_steps, s);
+    return;
+  }
+  // additive multigrid: the residual restricted to every level (each
+  // restriction also writes that level's first r_S rows), every level
+  // smoothed from zero, the corrections prolongated and summed coarsest first
+  const int N = P->N;
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level& L = P->levels[l];
+    Level& C = P->levels[l + 1];
+    HIP_OK(launch_restrict(N, b[l], C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
+  }
+  for (int l = 0; l < nl; ++l) {
+    const int steps = l < nl - 1 ? P->opt.pre_smooth + P->opt.post_smooth : coarse_steps;
+    if (steps == 0) HIP_OK(launch_fill(u[l], 0.0, P->nd(l), s));
+    schwarz_steps(P, l, b[l], u[l], steps, true, s, l == 0 ? rs0_ready : true);
+  }
+  for (int l = nl - 2; l >= 0; --l) {
+    Level& L = P->levels[l];
+    Level& C = P->levels[l + 1];
+    HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->dt, s));
+  }
 }
 
 // One captured V-cycle from the finest level's d_b into its d_u (the graph
@@ -1897,6 +1919,7 @@ void dgs_default_options(dgs_options* o) {
   o->use_graphs = 1;
   o->restart = 0;
   o->cycle = 1;
+  o->additive = 0;
 }
 
 const char* dgs_last_error(void) { return g_last_error.c_str(); }
@@ -1920,7 +1943,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     if (opt) o = *opt;
     if (o.overlap < 1 || o.pre_smooth < 0 || o.post_smooth < 0 || o.mg_levels < 0 ||
         o.max_iter < 1 || !(o.rtol > 0.0) || o.subdomain_iters < 0 || o.subdomain_iters > 8 ||
-        o.restart < 0 || o.cycle < 1 || o.cycle > 2 ||
+        o.restart < 0 || o.cycle < 1 || o.cycle > 2 || o.additive < 0 || o.additive > 1 ||
         (o.precision != DGS_FP64 && o.precision != DGS_MIXED))
       return fail(DGS_ERR_INVALID, "invalid options");
     const long long E0 = (long long)elements[0] * elements[1] * elements[2];

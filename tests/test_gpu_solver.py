@@ -280,3 +280,30 @@ def test_wcycle_matches_oracle(elements, p, levels):
     assert st["converged"] and abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
     assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
     prob.close()
+
+
+@pytest.mark.parametrize("elements,p,levels", [((4, 4, 2), 3, 3), ((8, 4, 4), 1, 3),
+                                               ((2, 2, 2), 4, 2)])
+def test_additive_mg_matches_oracle(elements, p, levels):
+    """Additive multigrid (options.additive = 1) against the oracle's: one
+    application in FP64 at the V-cycle's tolerance, and a mixed-precision
+    FGMRES solve preconditioned by it."""
+    import paper_2111_06767_amd as dg
+    announce(f"additive mg elements={elements} p={p} levels={levels}")
+    N = p + 1
+    m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), elements, p)
+    Add = multigrid.AdditiveMG(m, 1.5, levels=levels)
+    r = W.random_normal(91, m.ndof)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, additive=1)
+    got = to_np(prob.precondition(to_gpu(r)))
+    assert rel_max(got, Add(r)) < 1e-10, rel_max(got, Add(r))
+    prob.close()
+    A = lambda v: oop.apply_operator(m, v.reshape(m.E, N, N, N), 1.5).reshape(-1)
+    u_ref, its_ref, _ = krylov.fgmres(A, r, precondition=Add, rtol=1e-10)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, additive=1,
+                      precision="mixed")
+    u, st = prob.solve(to_gpu(r))
+    u = to_np(u)
+    assert st["converged"] and abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
+    prob.close()

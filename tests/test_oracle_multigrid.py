@@ -126,3 +126,29 @@ def test_wcycle_matches_dense_composition():
     v1 = multigrid.VCycle(fine, 1.5, levels=3)(b)
     assert np.linalg.norm(V(b) - v1) > 1e-6 * np.linalg.norm(v1)
     np.testing.assert_allclose(V(3.0 * b), 3.0 * V(b), rtol=1e-11, atol=1e-11)
+
+
+def test_additive_mg_matches_dense_sum_over_levels():
+    # z = sum_l P_{0<-l} S_l R_{l<-0} r, with S_l the six-step smoothing
+    # operator from zero of level l and P_{0<-l} = P_0 ... P_{l-1}, R = P^T
+    fine = mesh.BoxMesh([0, 0, 0], [1, 1, 1], (8, 4, 4), 1)
+    Add = multigrid.AdditiveMG(fine, 1.5, levels=3)
+    V = multigrid.VCycle(fine, 1.5, levels=3)
+    lv = [m for m, _ in V.levels]
+    A = [operator.assemble(m, 1.5) for m in lv]
+    B = [_dense(schwarz.SchwarzSmoother(m, 1.5, 2).correction, m.ndof) for m in lv]
+    P = [_dense(lambda v, l=l: multigrid.prolongate(lv[l], lv[l + 1], V.levels[l][1], v),
+                lv[l + 1].ndof) for l in range(2)]
+    S = []
+    for l in range(3):  # six steps u <- u + B (b - A u) from zero, as a matrix of b
+        E = np.eye(lv[l].ndof) - B[l] @ A[l]
+        S.append(sum(np.linalg.matrix_power(E, i) for i in range(6)) @ B[l])
+    to0 = [np.eye(fine.ndof), P[0], P[0] @ P[1]]
+    r = np.random.default_rng(5).standard_normal(fine.ndof)
+    want = sum(to0[l] @ S[l] @ to0[l].T @ r for l in range(3))
+    np.testing.assert_allclose(Add(r), want, rtol=1e-10, atol=1e-11)
+    # it preconditions FGMRES, with more iterations than the multiplicative cycle
+    Af = lambda v: A[0] @ v
+    _, k_add, _ = krylov.fgmres(Af, r, precondition=Add, rtol=1e-10)
+    _, k_mul, _ = krylov.fgmres(Af, r, precondition=V, rtol=1e-10)
+    assert k_add > k_mul
