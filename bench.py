@@ -380,6 +380,12 @@ def main():
     wcycle = dict(ms_p50=round(1e3 * _pct(wtimes, 50), 3), iterations=wst["iterations"],
                   rel_residual=wst["rel_residual"], converged=wst["converged"])
     wprob.close()
+    _log("8^3 p=6 with the F-cycle")
+    fprob, fb, _ = build_c2(dg, "mixed", cycle=3)
+    _, fst, ftimes, _ = time_solves(fprob, fb, 10, 2)
+    fcycle = dict(ms_p50=round(1e3 * _pct(ftimes, 50), 3), iterations=fst["iterations"],
+                  rel_residual=fst["rel_residual"], converged=fst["converged"])
+    fprob.close()
     _log("8^3 p=6 with additive multigrid")
     aprob, ab, _ = build_c2(dg, "mixed", additive=1)
     _, ast_, atimes, _ = time_solves(aprob, ab, 10, 2)
@@ -480,6 +486,7 @@ def main():
         "c2_conjugate_gradients": cg,
         "c2_restarted_fgmres_mixed": restarted,
         "c2_wcycle_mixed": wcycle,
+        "c2_fcycle_mixed": fcycle,
         "c2_additive_mg_mixed": additive,
         "c5_16x16x16_p7": c5,
         "serving": serving,

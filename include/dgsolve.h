@@ -74,9 +74,11 @@ typedef struct {
   int restart;         /* FGMRES: 0 = no restart; m > 0 = restarted FGMRES(m),
                           cycles of at most m iterations from the true residual
                           (max_iter bounds all cycles together)                 [0] */
-  int cycle;           /* visits of each coarser multigrid level per visit of its
-                          parent: 1 = V-cycle (Sec. III.C.3), 2 = W-cycle, whose
-                          second visit starts from the first one's result       [1] */
+  int cycle;           /* multigrid cycle: 1 = V-cycle (Sec. III.C.3); 2 = W-cycle,
+                          two visits of each coarser level per visit of its parent;
+                          3 = F-cycle, an F-visit of the coarser level and then a
+                          V-visit; a second visit starts from the first one's
+                          result                                                 [1] */
   int additive;        /* 1 = additive multigrid instead (the variant of Sec. V):
                           the residual restricted to every level, each level
                           smoothed from zero with pre + post steps, the

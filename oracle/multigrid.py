@@ -99,7 +99,9 @@ class VCycle:
     """One multigrid cycle with ``pre``/``post`` Schwarz steps per level
     (Sec. III.C.3).  ``gamma`` is the number of visits of each coarser level
     per visit of its parent: 1 is the paper's V-cycle, 2 the W-cycle, whose
-    second visit starts from the first one's coarse-grid result."""
+    second visit starts from the first one's coarse-grid result.  gamma="F"
+    is the F-cycle (Sec. V names it): an F-visit of the coarser level followed
+    by a V-visit from its result."""
 
     def __init__(self, mesh: BoxMesh, C, levels=2, overlap=2, pre=3, post=3,
                  diag=None, subdomain_iters=0, gamma=1):
@@ -115,9 +117,9 @@ class VCycle:
                 d = restrict(m, self.levels[li + 1][0], split, d)
 
     def __call__(self, b):
-        return self._cycle(0, np.asarray(b, float).reshape(-1))
+        return self._cycle(0, np.asarray(b, float).reshape(-1), None, self.gamma)
 
-    def _cycle(self, l, b, u0=None):
+    def _cycle(self, l, b, u0, kind):
         mesh, split = self.levels[l]
         sm = self.smoothers[l]
         u = np.zeros_like(b) if u0 is None else u0
@@ -127,9 +129,10 @@ class VCycle:
         coarse = self.levels[l + 1][0]
         r = b - sm.apply(u)  # eq. mg_res
         bc = restrict(mesh, coarse, split, r)
+        visits = {1: [1], 2: [2, 2], "F": ["F", 1]}[kind]
         uc = None
-        for _ in range(self.gamma):
-            uc = self._cycle(l + 1, bc, uc)
+        for k in visits:
+            uc = self._cycle(l + 1, bc, uc, k)
         u = u + prolongate(mesh, coarse, split, uc)
         return sm.smooth(u, b, self.post)  # postsmoothing
 

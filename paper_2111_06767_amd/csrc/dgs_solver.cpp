@@ -959,14 +959,15 @@ void schwarz_steps(dgs_problem* P, int l, const double* b, double* u, int steps,
 
 // rs0_ready: the finest level's rows already hold R_S r.
 // One visit of level l in a multigrid cycle (Sec. III.C.3): presmoothing,
-// the residual restricted to the next coarser level, `cycle` visits of that
-// level (the first from zero, a second one from the first one's result: the
-// W-cycle), prolongation, postsmoothing; the coarsest level smooths only.
+// the residual restricted to the next coarser level, the visits of that level
+// (kind 1, V: one; kind 2, W: two W-visits; kind 3, F: an F-visit and then a
+// V-visit; every second visit starts from the first one's result),
+// prolongation, postsmoothing; the coarsest level smooths only.
 // u_zero: u[l] starts from zero (its first smoothing step writes u);
 // rs_ready: the first step's subdomain rows r_S = R_S b are already gathered.
 void mg_visit(dgs_problem* P, int l, const std::vector<const double*>& b,
               const std::vector<double*>& u, bool u_zero, bool rs_ready, int coarse_steps,
-              hipStream_t s) {
+              int kind, hipStream_t s) {
   const int nl = (int)P->levels.size();
   const int N = P->N;
   Level& L = P->levels[l];
@@ -981,8 +982,11 @@ void mg_visit(dgs_problem* P, int l, const std::vector<const double*>& b,
   Level& C = P->levels[l + 1];
   // the restriction also writes the coarse level's first r_S rows
   HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
-  for (int visit = 0; visit < P->opt.cycle; ++visit)
-    mg_visit(P, l + 1, b, u, visit == 0, visit == 0, coarse_steps, s);
+  // V: one V-visit; W: two W-visits; F: an F-visit, then a V-visit
+  const int visits[2] = {kind, kind == 3 ? 1 : kind};
+  const int nvisits = kind == 1 ? 1 : 2;
+  for (int visit = 0; visit < nvisits; ++visit)
+    mg_visit(P, l + 1, b, u, visit == 0, visit == 0, coarse_steps, visits[visit], s);
   HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->dt, s));
   schwarz_steps(P, l, b[l], u[l], P->opt.post_smooth, false, s);
 }
@@ -1007,7 +1011,7 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
   if (Lc.E == 1 && !(P->diag_active && Lc.d_diag != nullptr))
     coarse_steps = std::min(coarse_steps, 1);
   if (!P->opt.additive) {
-    mg_visit(P, 0, b, u, true, rs0_ready, coarse_steps, s);
+    mg_visit(P, 0, b, u, true, rs0_ready, coarse_steps, P->opt.cycle, s);
     return;
   }
   // additive multigrid: the residual restricted to every level (each
@@ -1943,7 +1947,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     if (opt) o = *opt;
     if (o.overlap < 1 || o.pre_smooth < 0 || o.post_smooth < 0 || o.mg_levels < 0 ||
         o.max_iter < 1 || !(o.rtol > 0.0) || o.subdomain_iters < 0 || o.subdomain_iters > 8 ||
-        o.restart < 0 || o.cycle < 1 || o.cycle > 2 || o.additive < 0 || o.additive > 1 ||
+        o.restart < 0 || o.cycle < 1 || o.cycle > 3 || o.additive < 0 || o.additive > 1 ||
         (o.precision != DGS_FP64 && o.precision != DGS_MIXED))
       return fail(DGS_ERR_INVALID, "invalid options");
     const long long E0 = (long long)elements[0] * elements[1] * elements[2];

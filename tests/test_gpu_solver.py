@@ -255,25 +255,27 @@ def test_restarted_fgmres_matches_oracle(restart, precision):
     prob.close()
 
 
+@pytest.mark.parametrize("cycle", [2, 3])
 @pytest.mark.parametrize("elements,p,levels", [((4, 4, 2), 3, 3), ((8, 4, 4), 1, 3),
                                                ((4, 4, 4), 2, 0), ((2, 2, 2), 4, 2)])
-def test_wcycle_matches_oracle(elements, p, levels):
-    """The W-cycle (options.cycle = 2) against the oracle's (gamma = 2): one
-    cycle in FP64 at the V-cycle's tolerance, and a mixed-precision FGMRES
-    solve preconditioned by it."""
+def test_wcycle_matches_oracle(elements, p, levels, cycle):
+    """The W-cycle (options.cycle = 2) and the F-cycle (3) against the
+    oracle's (gamma = 2, "F"): one cycle in FP64 at the V-cycle's tolerance,
+    and a mixed-precision FGMRES solve preconditioned by it."""
     import paper_2111_06767_amd as dg
-    announce(f"wcycle elements={elements} p={p} levels={levels}")
+    announce(f"cycle {cycle} elements={elements} p={p} levels={levels}")
     N = p + 1
     m = omesh.BoxMesh((0, 0, 0), (1, 1, 1), elements, p)
-    W2 = multigrid.VCycle(m, 1.5, levels=levels if levels else 64, gamma=2)
+    W2 = multigrid.VCycle(m, 1.5, levels=levels if levels else 64,
+                          gamma=2 if cycle == 2 else "F")
     r = W.random_normal(81, m.ndof)
-    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, cycle=2)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, cycle=cycle)
     got = to_np(prob.precondition(to_gpu(r)))
     assert rel_max(got, W2(r)) < 1e-10, rel_max(got, W2(r))
     prob.close()
     A = lambda v: oop.apply_operator(m, v.reshape(m.E, N, N, N), 1.5).reshape(-1)
     u_ref, its_ref, _ = krylov.fgmres(A, r, precondition=W2, rtol=1e-10)
-    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, cycle=2,
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), elements, p, mg_levels=levels, cycle=cycle,
                       precision="mixed")
     u, st = prob.solve(to_gpu(r))
     u = to_np(u)

@@ -152,3 +152,35 @@ def test_additive_mg_matches_dense_sum_over_levels():
     _, k_add, _ = krylov.fgmres(Af, r, precondition=Add, rtol=1e-10)
     _, k_mul, _ = krylov.fgmres(Af, r, precondition=V, rtol=1e-10)
     assert k_add > k_mul
+
+
+def test_fcycle_matches_dense_composition():
+    # F-cycle: an F-visit of the coarser level, then a V-visit from its result
+    fine = mesh.BoxMesh([0, 0, 0], [1, 1, 1], (8, 8, 4), 1)
+    F = multigrid.VCycle(fine, 1.5, levels=4, gamma="F")
+    lv = [m for m, _ in F.levels]
+    A = [operator.assemble(m, 1.5) for m in lv]
+    B = [_dense(schwarz.SchwarzSmoother(m, 1.5, 2).correction, m.ndof) for m in lv]
+    P = [_dense(lambda v, l=l: multigrid.prolongate(lv[l], lv[l + 1], F.levels[l][1], v),
+                lv[l + 1].ndof) for l in range(3)]
+
+    def smooth(l, u, b, k):
+        for _ in range(k):
+            u = u + B[l] @ (b - A[l] @ u)
+        return u
+
+    def cycle(l, b, u, kind):
+        u = smooth(l, u, b, 3)
+        if l == 3:
+            return smooth(l, u, b, 3)
+        bc = P[l].T @ (b - A[l] @ u)
+        uc = np.zeros(lv[l + 1].ndof)
+        for k in (("F", "V") if kind == "F" else ("V",)):
+            uc = cycle(l + 1, bc, uc, k)
+        return smooth(l, u + P[l] @ uc, b, 3)
+
+    b = np.random.default_rng(7).standard_normal(fine.ndof)
+    np.testing.assert_allclose(F(b), cycle(0, b, np.zeros(fine.ndof), "F"), rtol=1e-11, atol=1e-11)
+    for other in (1, 2):
+        o = multigrid.VCycle(fine, 1.5, levels=4, gamma=other)(b)
+        assert np.linalg.norm(F(b) - o) > 1e-6 * np.linalg.norm(o)
