@@ -20,7 +20,14 @@ GRID_ELEM_AXIS = (-4, -5, -6)
 
 
 class BoxMesh:
-    def __init__(self, lower, upper, elements, p):
+    """Uniform box grid.  ``neumann`` lists the box faces f = 2 d + side (side
+    0 = low, 1 = high) that carry homogeneous Neumann conditions; the others
+    are homogeneous Dirichlet (eq. bc)."""
+
+    def __init__(self, lower, upper, elements, p, neumann=()):
+        self.neumann = frozenset(int(f) for f in neumann)
+        if not self.neumann <= set(range(6)):
+            raise ValueError("bad face")
         self.lower = np.asarray(lower, dtype=float)
         self.upper = np.asarray(upper, dtype=float)
         self.n = tuple(int(v) for v in elements)  # (nx, ny, nz)

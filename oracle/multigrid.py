@@ -39,7 +39,7 @@ def coarsen(mesh: BoxMesh):
     if not any(split):
         return None
     n = [mesh.n[d] // 2 if split[d] else mesh.n[d] for d in range(3)]
-    return BoxMesh(mesh.lower, mesh.upper, n, mesh.p), split
+    return BoxMesh(mesh.lower, mesh.upper, n, mesh.p, neumann=mesh.neumann), split
 
 
 def hierarchy(mesh: BoxMesh, levels):

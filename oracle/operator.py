@@ -20,7 +20,10 @@ Follows Sec. II literally:
       (n F)_ext = (n F)_int - 2 (n F)_b
   Dirichlet: the auxiliary boundary flux is n u_b and the primal boundary flux
   equals the interior one, i.e. u_ext = 2 u_b - u_int and the exterior normal
-  derivative equals the interior one.
+  derivative equals the interior one.  Homogeneous Neumann (the faces listed
+  in mesh.neumann): the primal boundary flux is 0 and the auxiliary one equals
+  the interior one, i.e. u_ext = u_int and the exterior normal derivative is
+  the negated interior one.
 
 Readings (where the paper leaves a choice):
 * The integrals in eqs. massmat/stiffmat/liftop are evaluated with LGL
@@ -134,9 +137,16 @@ def apply_operator(mesh: BoxMesh, u, C, source=None, dirichlet_u_b=0.0):
             u_ext = _from_neighbor(ug[sl_oth], d, s, mesh.n[d])
             du_ext = _from_neighbor(g[d][sl_oth], d, s, mesh.n[d])
             bmask = _boundary_mask(mesh, d, s, nd)
-            # eq. bc, Dirichlet: u_ext = 2 u_b - u_int, exterior derivative = interior
-            u_ext = np.where(bmask, 2.0 * dirichlet_u_b - u_int, u_ext)
-            du_ext = np.where(bmask, du_int, du_ext)
+            if 2 * d + (s > 0) in mesh.neumann:
+                # eq. bc, homogeneous Neumann: the primal boundary flux is 0
+                # and the auxiliary one equals the interior flux, i.e.
+                # u_ext = u_int and an exterior normal derivative of -du_int
+                u_ext = np.where(bmask, u_int, u_ext)
+                du_ext = np.where(bmask, -du_int, du_ext)
+            else:
+                # eq. bc, Dirichlet: u_ext = 2 u_b - u_int, exterior derivative = interior
+                u_ext = np.where(bmask, 2.0 * dirichlet_u_b - u_int, u_ext)
+                du_ext = np.where(bmask, du_int, du_ext)
             faces[(d, s)] = (sl_own, u_int, u_ext, du_int, du_ext)
 
     # auxiliary variables, eq. dg_op_auxvars with eq. numfluxaux

@@ -162,7 +162,9 @@ def patch_for_class(mesh: BoxMesh, flags):
         upper.append(l0 + nd * mesh.h[d])
         n.append(nd)
         c.append(cd)
-    patch = BoxMesh(lower, upper, n, mesh.p)
+    # the box's boundary conditions by face; the patch's cut faces only touch
+    # rows outside the subdomain, whatever condition they carry
+    patch = BoxMesh(lower, upper, n, mesh.p, neumann=mesh.neumann)
     return patch, patch.elem_index(*c)
 
 

@@ -146,3 +146,35 @@ def test_spectral_convergence_manufactured_solution():
     rates = np.log(errs[:-1] / errs[1:])
     assert rates.mean() > 1.5  # better than a factor e^1.5 per degree
     assert errs[-1] < 1e-5
+
+
+def test_neumann_faces_pure_neumann_kernel_and_mixed_spd():
+    # eq. bc with homogeneous Neumann data on every face: constants are in the
+    # kernel of A (no flux crosses the boundary and a constant has no jump);
+    # with Dirichlet on at least one face A is symmetric positive definite
+    all_n = mesh.BoxMesh([0, 0, 0], [1, 1.2, 0.8], (2, 2, 1), 3, neumann=range(6))
+    one = np.ones((all_n.E, 4, 4, 4))
+    assert np.abs(operator.apply_operator(all_n, one, 1.5)).max() < 1e-12
+    m = mesh.BoxMesh([0, 0, 0], [1, 1.2, 0.8], (2, 2, 1), 3, neumann=(1, 2, 3, 4, 5))
+    A = operator.assemble(m, 1.5)
+    assert np.allclose(A, A.T, atol=1e-12)
+    assert np.linalg.eigvalsh(A).min() > 0
+    # the Dirichlet operator does not annihilate constants
+    d = mesh.BoxMesh([0, 0, 0], [1, 1.2, 0.8], (2, 2, 1), 3)
+    assert np.abs(operator.apply_operator(d, one, 1.5)).max() > 1e-3
+
+
+def test_mixed_dirichlet_neumann_manufactured_solution_converges():
+    # u = sin(pi x / 2) cos(pi y) cos(pi z) on [0,1]^3: zero at x = 0
+    # (Dirichlet) and zero normal derivative on the five other faces; the
+    # discrete solution converges exponentially in p
+    errs = []
+    for p in (2, 3, 4, 5):
+        m = mesh.BoxMesh([0, 0, 0], [1, 1, 1], (2, 2, 2), p, neumann=(1, 2, 3, 4, 5))
+        x, y, z = m.node_coordinates()
+        u = np.sin(np.pi * x / 2) * np.cos(np.pi * y) * np.cos(np.pi * z)
+        f = (np.pi ** 2 / 4 + 2 * np.pi ** 2) * u
+        A = operator.assemble(m, 1.5)
+        uh = np.linalg.solve(A, operator.apply_mass(m, f).reshape(-1))
+        errs.append(np.abs(uh - u.reshape(-1)).max())
+    assert errs[-1] < 1e-3 and all(b < a / 3 for a, b in zip(errs, errs[1:])), errs
