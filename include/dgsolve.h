@@ -83,6 +83,11 @@ typedef struct {
                           the residual restricted to every level, each level
                           smoothed from zero with pre + post steps, the
                           prolongated corrections summed; `cycle` is unused  [0] */
+  int neumann_faces;   /* bit f = 2 d + side (side 0 = low, 1 = high face of the box
+                          along dimension d) set: that face carries a homogeneous
+                          Neumann condition through the ghost fluxes of eq. bc;
+                          the others homogeneous Dirichlet.  At least one face
+                          must stay Dirichlet (63 is DGS_ERR_INVALID)            [0] */
 } dgs_options;
 
 /* Statistics of a solve.  `history` may be NULL; otherwise it receives up to

@@ -45,7 +45,8 @@ class Options(ctypes.Structure):
                 ("precision", ctypes.c_int), ("subdomain_iters", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("use_graphs", ctypes.c_int), ("restart", ctypes.c_int),
-                ("cycle", ctypes.c_int), ("additive", ctypes.c_int)]
+                ("cycle", ctypes.c_int), ("additive", ctypes.c_int),
+                ("neumann_faces", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -21,7 +21,9 @@
 //   A u = sum_d D_d^T (M v_d) - sum_faces ML_f (n F_u)*,
 //   v_d = D_d u + L_d (1/2) n_d (u_ext - u_int)  on the faces normal to d,
 //   (n F_u)* = 1/2 n.(grad u_int + grad u_ext) - sigma (u_int - u_ext).
-// Dirichlet faces use the ghost state u_ext = -u_int, grad u_ext = grad u_int.
+// Dirichlet faces use the ghost state u_ext = -u_int, grad u_ext = grad u_int;
+// homogeneous Neumann faces (P.neumann) u_ext = u_int and the normal
+// derivative negated, so that no flux crosses them.
 #include "dgs_internal.h"
 
 namespace dgs {
@@ -331,11 +333,12 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         const int ie = side ? N - 1 : 0;
         const double sg = side ? 1.0 : -1.0;
         // branch-free: a missing neighbour reads the element itself and the
-        // result is replaced by the Dirichlet ghost state
+        // result is replaced by the boundary's ghost state
         const bool has = nb[side] >= 0;
+        const bool neu = (P.neumann >> side) & 1;
         const double ui = line[ie], gi = g[ie];
-        const double ue = has ? xf[2 * side] : -ui;
-        const double ge = has ? xf[2 * side + 1] : gi;
+        const double ue = has ? xf[2 * side] : (neu ? ui : -ui);
+        const double ge = has ? xf[2 * side + 1] : (neu ? -gi : gi);
         fx[side] = jwab * P.rh[0] * (0.5 * sg * (gi + ge) - P.sig[0] * (ui - ue));
         g[ie] += P.lf[0] * sg * (ue - ui);
       }
@@ -363,9 +366,10 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         const int je = side ? N - 1 : 0;
         const double sg = side ? 1.0 : -1.0;
         const bool has = nb[2 + side] >= 0;
+        const bool neu = (P.neumann >> (2 + side)) & 1;
         const double ui = line[je], gi = g[je];
-        const double ue = has ? yf[2 * side] : -ui;
-        const double ge = has ? yf[2 * side + 1] : gi;
+        const double ue = has ? yf[2 * side] : (neu ? ui : -ui);
+        const double ge = has ? yf[2 * side + 1] : (neu ? -gi : gi);
         fy[side] = jwab * P.rh[1] * (0.5 * sg * (gi + ge) - P.sig[1] * (ui - ue));
         g[je] += P.lf[1] * sg * (ue - ui);
       }
@@ -384,8 +388,9 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         const double sg = side ? 1.0 : -1.0;
         const double ui = uz[ke], gi = g[ke];
         const bool has = nb[4 + side] >= 0;
-        const double ue = has ? zf[2 * side] : -ui;
-        const double ge = has ? zf[2 * side + 1] : gi;
+        const bool neu = (P.neumann >> (4 + side)) & 1;
+        const double ue = has ? zf[2 * side] : (neu ? ui : -ui);
+        const double ge = has ? zf[2 * side + 1] : (neu ? -gi : gi);
         fz[side] = jwab * P.rh[2] * (0.5 * sg * (gi + ge) - P.sig[2] * (ui - ue));
         g[ke] += P.lf[2] * sg * (ue - ui);
       }

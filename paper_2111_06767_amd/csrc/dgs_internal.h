@@ -58,6 +58,10 @@ struct OpParams {
   // derived on the host (set_derived): 2/h_d, sigma_d, lift factor 1/(h_d w_end),
   // J = h_x h_y h_z / 8
   double rh[3], sig[3], lf[3], J;
+  // bit f = 2 d + side set: a missing neighbour across face f is a homogeneous
+  // Neumann boundary (ghost u_ext = u_int, normal derivative negated), else
+  // homogeneous Dirichlet (u_ext = -u_int, normal derivative kept); eq. bc
+  int neumann;
 };
 void set_derived(OpParams& P, int N, double w_end);
 

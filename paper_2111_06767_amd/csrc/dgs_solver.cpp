@@ -79,14 +79,15 @@ void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
 
 const int kFace[6][2] = {{0, -1}, {0, 1}, {1, -1}, {1, 1}, {2, -1}, {2, 1}};
 
-// Boundary class: bit 2f set when face f of the element is external.
-int class_flags(const int c[3], const int n[3]) {
+// Boundary class: bit f (f = 2 d + side) set when face f of the element is
+// external, bit 6 + f when that external face is a Neumann boundary.
+int class_flags(const int c[3], const int n[3], int neumann) {
   int fl = 0;
   for (int d = 0; d < 3; ++d) {
     if (c[d] == 0) fl |= 1 << (2 * d);
     if (c[d] == n[d] - 1) fl |= 1 << (2 * d + 1);
   }
-  return fl;
+  return fl | ((fl & neumann) << 6);
 }
 
 struct ClassLayout {
@@ -309,6 +310,7 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
   L.op.n[0] = L.n[0];
   L.op.n[1] = L.n[1];
   L.op.n[2] = L.n[2];
+  L.op.neumann = P->opt.neumann_faces;
   set_derived(L.op, P->N, P->ht.w[0]);
   const std::vector<int> nbr = host_neighbors(L);
   L.d_nbr = P->alloc<int>(nbr.size());
@@ -367,12 +369,13 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   for (long long e = 0; e < L.E; ++e) {
     const int c[3] = {(int)(e % L.n[0]), (int)((e / L.n[0]) % L.n[1]),
                       (int)(e / ((long long)L.n[0] * L.n[1]))};
-    int fl = class_flags(c, L.n), mask = 0;
+    int fl = class_flags(c, L.n, P->opt.neumann_faces), mask = 0;
     for (int d = 0; d < 3; ++d) {
       const int lo = (fl >> (2 * d)) & 1, hi = (fl >> (2 * d + 1)) & 1;
-      if (!lo && hi) {
+      if (!lo && hi) {  // the face and its boundary type move to the low side
         mask |= 1 << d;
-        fl = (fl & ~(3 << (2 * d))) | (1 << (2 * d));
+        const int nh = (fl >> (6 + 2 * d + 1)) & 1;
+        fl = (fl & ~(3 << (2 * d)) & ~(3 << (6 + 2 * d))) | (1 << (2 * d)) | (nh << (6 + 2 * d));
       }
     }
     int best = fl, best_t = 0;
@@ -380,7 +383,11 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
       const int a = t == 3 ? 1 : 0, b = t == 1 ? 1 : 2;
       if (L.h[a] != L.h[b]) continue;
       int ft = 0;
-      for (int d = 0; d < 3; ++d) ft |= ((fl >> (2 * frame_axis(d, t))) & 3) << (2 * d);
+      for (int d = 0; d < 3; ++d) {
+        const int from = frame_axis(d, t);
+        ft |= ((fl >> (2 * from)) & 3) << (2 * d);
+        ft |= ((fl >> (6 + 2 * from)) & 3) << (6 + 2 * d);
+      }
       if (ft > best) {
         best = ft;
         best_t = t;
@@ -598,6 +605,7 @@ void build_keys(dgs_problem* P, const std::vector<CacheEntry*>& todo,
     HIP_OK(launch_fill(d_X, 0.0, tot, s));
     HIP_OK(launch_unit_columns(d_X, stride, d_idx, n, s));
     OpParams op = ref[k]->op;
+    op.neumann = (lay.flags >> 6) & 63;  // the class's Neumann faces, in its frame
     op.E = (int)(Ep * (long long)n);
     op.n[0] = op.n[1] = op.n[2] = 0;  // patch elements: neighbours from the table
     HIP_OK(launch_apply(N, kApply, d_X, d_AX, nullptr, nullptr, nullptr, d_nb, op, P->dt,
@@ -1924,6 +1932,7 @@ void dgs_default_options(dgs_options* o) {
   o->restart = 0;
   o->cycle = 1;
   o->additive = 0;
+  o->neumann_faces = 0;
 }
 
 const char* dgs_last_error(void) { return g_last_error.c_str(); }
@@ -1948,6 +1957,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     if (o.overlap < 1 || o.pre_smooth < 0 || o.post_smooth < 0 || o.mg_levels < 0 ||
         o.max_iter < 1 || !(o.rtol > 0.0) || o.subdomain_iters < 0 || o.subdomain_iters > 8 ||
         o.restart < 0 || o.cycle < 1 || o.cycle > 3 || o.additive < 0 || o.additive > 1 ||
+        o.neumann_faces < 0 || o.neumann_faces >= 63 ||
         (o.precision != DGS_FP64 && o.precision != DGS_MIXED))
       return fail(DGS_ERR_INVALID, "invalid options");
     const long long E0 = (long long)elements[0] * elements[1] * elements[2];

@@ -129,3 +129,30 @@ def test_brick_shape_solve_is_bit_identical(precision):
         prob.close()
     assert sols[0][1] == sols[1][1]
     assert np.array_equal(sols[0][0], sols[1][0])
+
+
+# (elements, p, size, Neumann face mask): one face, opposite faces, all but one,
+# the brick shape at p = 7 (shape -1) and 1-element dimensions
+NEUMANN_CASES = [((2, 2, 2), 3, (1, 1, 1), 0b000010), ((3, 2, 4), 2, (1, 2, 0.5), 0b001100),
+                 ((3, 3, 3), 5, (1, 1, 1), 0b111110), ((4, 4, 2), 7, (1, 1, 1), 0b010101),
+                 ((5, 1, 2), 4, (2, 1, 1), 0b101010)]
+
+
+@pytest.mark.parametrize("elements,p,size,neumann", NEUMANN_CASES)
+def test_apply_with_neumann_faces_matches_oracle(elements, p, size, neumann):
+    """Homogeneous Neumann box faces (eq. bc ghost fluxes) in every launch
+    shape against the oracle's operator."""
+    import paper_2111_06767_amd as dg
+    announce(f"neumann apply elements={elements} p={p} mask={neumann:06b}")
+    lower = (0.25, -0.5, 0.0)
+    upper = tuple(l + s for l, s in zip(lower, size))
+    faces = [f for f in range(6) if neumann >> f & 1]
+    m = omesh.BoxMesh(lower, upper, elements, p, neumann=faces)
+    u = W.random_normal(W.SEED_APPLY + p, m.ndof)
+    ref = oop.apply_operator(m, u.reshape(m.E, m.N, m.N, m.N), 1.5).reshape(-1)
+    prob = dg.Problem(lower, upper, elements, p, penalty=1.5, mg_levels=1, neumann_faces=neumann)
+    for shape in (1, 2, 0) + ((-1,) if p == 7 else ()):
+        prob.set_apply_shape(shape, level=0)
+        got = to_np(prob.apply(to_gpu(u)))
+        assert rel_max(got, ref) < 1e-13, (shape, rel_max(got, ref))
+    prob.close()

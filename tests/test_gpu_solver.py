@@ -309,3 +309,41 @@ def test_additive_mg_matches_oracle(elements, p, levels):
     assert st["converged"] and abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
     assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
     prob.close()
+
+
+@pytest.mark.parametrize("elements,p,upper,neumann", [
+    ((3, 3, 3), 3, (1, 1, 1), 0b000011), ((4, 4, 2), 2, (1, 1, 0.5), 0b000101),
+    ((3, 2, 4), 2, BOX, 0b110000), ((2, 2, 2), 4, (1, 1, 1), 0b111110)])
+def test_neumann_schwarz_vcycle_and_solve_match_oracle(elements, p, upper, neumann):
+    """Mixed Dirichlet / Neumann boxes: Schwarz steps (classes keyed by their
+    faces' boundary types, also across exchanged axes), one V-cycle and a
+    mixed-precision solve against the oracle."""
+    import paper_2111_06767_amd as dg
+    announce(f"neumann schwarz/vcycle/solve elements={elements} p={p} mask={neumann:06b}")
+    N = p + 1
+    faces = [f for f in range(6) if neumann >> f & 1]
+    m = omesh.BoxMesh((0, 0, 0), upper, elements, p, neumann=faces)
+    b = W.random_normal(101, m.ndof)
+    u0 = W.random_uniform(102, m.ndof)
+    S = schwarz.SchwarzSmoother(m, 1.5, 2)
+    prob = dg.Problem((0, 0, 0), upper, elements, p, penalty=1.5, neumann_faces=neumann)
+    for steps in (1, 2):
+        ref = S.smooth(u0, b, steps)
+        u = to_gpu(u0)
+        prob.smooth(to_gpu(b), u, steps)
+        assert rel_max(to_np(u), ref) < 1e-11, (steps, rel_max(to_np(u), ref))
+    V = multigrid.VCycle(m, 1.5, levels=64)
+    assert rel_max(to_np(prob.precondition(to_gpu(b))), V(b)) < 1e-10
+    prob.close()
+    A = lambda v: oop.apply_operator(m, v.reshape(m.E, N, N, N), 1.5).reshape(-1)
+    u_ref, its_ref, _ = krylov.fgmres(A, b, precondition=V, rtol=1e-10)
+    prob = dg.Problem((0, 0, 0), upper, elements, p, penalty=1.5, neumann_faces=neumann,
+                      precision="mixed")
+    u, st = prob.solve(to_gpu(b))
+    u = to_np(u)
+    assert st["converged"] and abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
+    assert np.linalg.norm(b - A(u)) / np.linalg.norm(b) <= 2e-10
+    assert np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref) <= 1e-9
+    prob.close()
+    with pytest.raises(dg.api.DgsError):
+        dg.Problem((0, 0, 0), upper, elements, p, neumann_faces=63)
