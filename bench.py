@@ -42,12 +42,12 @@ MFMA_FP64_PEAK_TFLOPS = 78.6
 MEASURED_TRAFFIC = {
     "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
-                       "sha256": "d3c431e4058a9339a126de345b69edbfc4056b481fc95cbd88c3749230eb0c90",
-                       "bytes": 68707543},
+                       "sha256": "e938373551449a8ea1a3516b307afcd9e0cd77c4ed5ffdbada422dc884a1f3e7",
+                       "bytes": 68707843},
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
-              "sha256": "300ad51ae61ce4537143d1feb169647c720617982ab53d8c17d8e9a68c688c42",
-              "bytes": 633395536},
+              "sha256": "cb7d0cf42f33170e20ac90f612691b41f7ab274968708ac41cdb48800bedb32f",
+              "bytes": 633367037},
 }
 
 

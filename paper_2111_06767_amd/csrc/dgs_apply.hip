@@ -335,10 +335,14 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         // branch-free: a missing neighbour reads the element itself and the
         // result is replaced by the boundary's ghost state
         const bool has = nb[side] >= 0;
-        const bool neu = (P.neumann >> side) & 1;
+
         const double ui = line[ie], gi = g[ie];
-        const double ue = has ? xf[2 * side] : (neu ? ui : -ui);
-        const double ge = has ? xf[2 * side + 1] : (neu ? -gi : gi);
+        double ue = has ? xf[2 * side] : -ui;
+        double ge = has ? xf[2 * side + 1] : gi;
+        if (P.neumann && !has && ((P.neumann >> (side)) & 1)) {  // Neumann ghost
+          ue = ui;
+          ge = -gi;
+        }
         fx[side] = jwab * P.rh[0] * (0.5 * sg * (gi + ge) - P.sig[0] * (ui - ue));
         g[ie] += P.lf[0] * sg * (ue - ui);
       }
@@ -366,10 +370,14 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         const int je = side ? N - 1 : 0;
         const double sg = side ? 1.0 : -1.0;
         const bool has = nb[2 + side] >= 0;
-        const bool neu = (P.neumann >> (2 + side)) & 1;
+
         const double ui = line[je], gi = g[je];
-        const double ue = has ? yf[2 * side] : (neu ? ui : -ui);
-        const double ge = has ? yf[2 * side + 1] : (neu ? -gi : gi);
+        double ue = has ? yf[2 * side] : -ui;
+        double ge = has ? yf[2 * side + 1] : gi;
+        if (P.neumann && !has && ((P.neumann >> (2 + side)) & 1)) {  // Neumann ghost
+          ue = ui;
+          ge = -gi;
+        }
         fy[side] = jwab * P.rh[1] * (0.5 * sg * (gi + ge) - P.sig[1] * (ui - ue));
         g[je] += P.lf[1] * sg * (ue - ui);
       }
@@ -388,9 +396,13 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
         const double sg = side ? 1.0 : -1.0;
         const double ui = uz[ke], gi = g[ke];
         const bool has = nb[4 + side] >= 0;
-        const bool neu = (P.neumann >> (4 + side)) & 1;
-        const double ue = has ? zf[2 * side] : (neu ? ui : -ui);
-        const double ge = has ? zf[2 * side + 1] : (neu ? -gi : gi);
+
+        double ue = has ? zf[2 * side] : -ui;
+        double ge = has ? zf[2 * side + 1] : gi;
+        if (P.neumann && !has && ((P.neumann >> (4 + side)) & 1)) {  // Neumann ghost
+          ue = ui;
+          ge = -gi;
+        }
         fz[side] = jwab * P.rh[2] * (0.5 * sg * (gi + ge) - P.sig[2] * (ui - ue));
         g[ke] += P.lf[2] * sg * (ue - ui);
       }

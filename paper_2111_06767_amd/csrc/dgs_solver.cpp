@@ -606,6 +606,7 @@ void build_keys(dgs_problem* P, const std::vector<CacheEntry*>& todo,
     HIP_OK(launch_unit_columns(d_X, stride, d_idx, n, s));
     OpParams op = ref[k]->op;
     op.neumann = (lay.flags >> 6) & 63;  // the class's Neumann faces, in its frame
+    set_derived(op, N, P->ht.w[0]);
     op.E = (int)(Ep * (long long)n);
     op.n[0] = op.n[1] = op.n[2] = 0;  // patch elements: neighbours from the table
     HIP_OK(launch_apply(N, kApply, d_X, d_AX, nullptr, nullptr, nullptr, d_nb, op, P->dt,
