@@ -5,7 +5,8 @@
  * Galerkin discretisation of the Poisson equation -Laplace(u) = f on an
  * axis-aligned box split into n_x * n_y * n_z equal elements, each with
  * N = p+1 Legendre-Gauss-Lobatto points per dimension, homogeneous Dirichlet
- * boundaries, and the internal-penalty numerical flux with penalty parameter C
+ * boundaries (or homogeneous Neumann on the faces dgs_options.neumann_faces
+ * names), and the internal-penalty numerical flux with penalty parameter C
  * (eqs. dg_op_auxvars, dg_op_primal, numflux, penalty, bc).  The linear
  * system A u = b is never assembled: only A u is defined.  Nonlinear problems
  * A(u) = b are solved by repeated linearisation (Sec. III.A).
@@ -14,13 +15,14 @@
  * array owned by the caller, in the canonical nodal layout
  *     idx = ((e * N + k) * N + j) * N + i,   e = (e_z * n_y + e_y) * n_x + e_x,
  * i.e. the x point index i fastest, then y, then z, then the element.  The
- * library owns its internal workspaces (device memory it allocates itself).
+ * library owns its internal workspaces: device memory it allocates itself, or
+ * through the allocator passed to dgs_create_problem.
  *
  * Streams.  All device work is enqueued on the hipStream_t passed as
  * `stream` (NULL = the null stream).  dgs_apply_operator, dgs_apply_mass,
  * dgs_node_coordinates and dgs_precondition never synchronise the host.
- * dgs_solve and dgs_newton_solve synchronise once per iteration to read the
- * convergence scalars.
+ * dgs_solve, dgs_cg_solve and dgs_newton_solve synchronise once per
+ * iteration to read the convergence scalars.
  *
  * Return codes.  DGS_OK (0) on success; DGS_NOT_CONVERGED (1) when an
  * iteration limit was hit (outputs and stats are still valid); negative
