@@ -11,7 +11,10 @@ preconditioned vectors.
 
 Readings: no restart unless asked for; the residual is the Euclidean 2-norm
 of the massive DG residual b - A x over all points; the stopping test uses
-the Givens estimate.
+the Givens estimate (FGMRES) or the recursively updated residual (CG), and
+the true residual b - A x then confirms it: when it is still above the
+tolerance, the iteration goes on from the true residual (a new cycle), within
+the same iteration limit.
 """
 from __future__ import annotations
 
@@ -32,6 +35,7 @@ def fgmres(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200, res
     hist = [1.0]
     beta0 = None
     total = 0
+    done = False
     while True:
         r0 = b - apply_A(x)
         beta = np.linalg.norm(r0)
@@ -39,11 +43,13 @@ def fgmres(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200, res
             beta0 = beta
         if beta == 0.0:
             return x, total, hist
+        if done and beta <= rtol * beta0:  # the true residual confirms the estimate
+            return x, total, hist
+        if total >= max_iter:
+            return x, total, hist
         x, k, done = _fgmres_cycle(apply_A, M, x, r0, beta, beta0, rtol,
                                    min(m, max_iter - total), hist)
         total += k
-        if done or total >= max_iter:
-            return x, total, hist
 
 
 def _fgmres_cycle(apply_A, M, x0, r0, beta, beta0, rtol, m, hist):
@@ -107,32 +113,41 @@ def cg(apply_A, b, x0=None, precondition=None, rtol=1e-10, max_iter=200):
     the preconditioner is not a fixed symmetric matrix, as the multigrid
     V-cycle with weighted additive Schwarz smoothing is not.  The iteration
     stops when the recursively updated residual satisfies ||r_k|| <= rtol
-    ||r_0||.  One operator application, one preconditioner application and
-    one round of dot products per iteration."""
+    ||r_0||; the true residual then confirms it, or CG starts again from the
+    true residual.  One operator application, one preconditioner application
+    and one round of dot products per iteration."""
     b = np.asarray(b, float).reshape(-1)
     x = np.zeros_like(b) if x0 is None else np.asarray(x0, float).reshape(-1).copy()
     M = precondition if precondition is not None else (lambda v: v.copy())
-    r = b - apply_A(x)
-    nr0 = np.linalg.norm(r)
     hist = [1.0]
-    if nr0 == 0.0:
-        return x, 0, hist
-    z = M(r)
-    p = z.copy()
-    rz = np.dot(r, z)
+    nr0 = None
     k = 0
-    for k in range(1, max_iter + 1):
-        q = apply_A(p)
-        alpha = rz / np.dot(p, q)
-        x = x + alpha * p
-        r_next = r - alpha * q
-        nr = np.linalg.norm(r_next)
-        hist.append(nr / nr0)
-        if nr <= rtol * nr0:
-            break
-        z = M(r_next)
-        rz_next = np.dot(r_next, z)
-        beta = (rz_next - np.dot(r, z)) / rz
-        p = z + beta * p
-        r, rz = r_next, rz_next
-    return x, k, hist
+    while True:  # runs, each from the true residual of x
+        r = b - apply_A(x)
+        nr_start = np.linalg.norm(r)
+        if nr0 is None:
+            nr0 = nr_start
+        if nr0 == 0.0 or (k > 0 and nr_start <= rtol * nr0) or k >= max_iter:
+            return x, k, hist
+        z = M(r)
+        p = z.copy()
+        rz = np.dot(r, z)
+        hit = False
+        while k < max_iter:
+            k += 1
+            q = apply_A(p)
+            alpha = rz / np.dot(p, q)
+            x = x + alpha * p
+            r_next = r - alpha * q
+            nr = np.linalg.norm(r_next)
+            hist.append(nr / nr0)
+            if nr <= rtol * nr0:
+                hit = True
+                break
+            z = M(r_next)
+            rz_next = np.dot(r_next, z)
+            beta = (rz_next - np.dot(r, z)) / rz
+            p = z + beta * p
+            r, rz = r_next, rz_next
+        if not hit:
+            return x, k, hist

@@ -1,5 +1,6 @@
 """Pins of the oracle's flexible GMRES (Sec. III.B, Saad Alg. 9.6)."""
 import numpy as np
+import pytest
 import scipy.sparse.linalg as spla
 
 from oracle import krylov, mesh, operator, multigrid
@@ -121,3 +122,42 @@ def test_restarted_fgmres_equals_scipy_restarted_gmres_and_converges():
     x3, k3, h3 = krylov.fgmres(lambda v: A @ v, b, precondition=V, rtol=1e-10, restart=3)
     assert k3 >= k1 and h3[-1] <= 1e-10
     np.testing.assert_allclose(x3, ref, rtol=1e-8, atol=1e-10)
+
+
+def _ill_conditioned(seed, n, decades, nonsymmetric):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(np.logspace(0, decades, n)) @ Q.T
+    if nonsymmetric:
+        A = A + 1e2 * rng.standard_normal((n, n))
+    return A, rng.standard_normal(n)
+
+
+@pytest.mark.parametrize("seed", [1, 4, 5, 7])
+def test_fgmres_confirms_the_estimate_with_the_true_residual(seed):
+    # ill-conditioned systems (n = 120, Jacobi preconditioner) on which the
+    # Givens estimate reaches the tolerance one or two iterations before the
+    # true residual b - A x does: the run goes on from the true residual and
+    # returns a solution that meets the tolerance
+    A, b = _ill_conditioned(seed, 120, 6, True)
+    d = np.diag(A).copy()
+    x, k, hist = krylov.fgmres(lambda v: A @ v, b, precondition=lambda v: v / d, rtol=1e-12)
+    assert hist[-1] <= 1e-12 and k < 200
+    assert np.linalg.norm(b - A @ x) <= 1e-12 * np.linalg.norm(b)
+    # a tolerance below the rounding floor is never reported as met
+    x, k, hist = krylov.fgmres(lambda v: A @ v, b, precondition=lambda v: v / d, rtol=1e-15,
+                               max_iter=150)
+    assert k == 150 or np.linalg.norm(b - A @ x) <= 1e-15 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_cg_reports_convergence_only_at_the_true_residual(seed):
+    # at a tolerance near the rounding floor the recursive residual runs
+    # ahead of the true one: a run that stops before the iteration limit
+    # must have its true residual at the tolerance
+    A, b = _ill_conditioned(seed, 150, 4, False)
+    d = np.diag(A).copy()
+    for rtol in (1e-12, 1e-13):
+        x, k, hist = krylov.cg(lambda v: A @ v, b, precondition=lambda v: v / d, rtol=rtol,
+                               max_iter=1500)
+        assert k == 1500 or np.linalg.norm(b - A @ x) <= rtol * np.linalg.norm(b)
