@@ -1,19 +1,29 @@
 """Benchmark of the DG multigrid-Schwarz solver on one MI355X.
 
-Workload (one step = one full solve to a 1e-10 relative residual):
-  3D Poisson on [0,1]^3, 8x8x8 elements, p = 6 (175,616 DOFs), source from 16
-  seeded random Fourier modes (seed 2), homogeneous Dirichlet, penalty C = 1.5,
-  3-level multigrid V-cycle with 3+3 additive Schwarz steps (overlap 2)
-  preconditioning flexible GMRES.  The headline runs the mixed-precision
-  solver (FP32 MFMA subdomain solves, FP64 everywhere else); the plain FP64
-  solver is timed beside it on the same inputs.
+Headline workload (one step = one full solve to a 1e-10 relative residual):
+  3D Poisson on [0,1]^3, 16x16x16 elements, p = 7 (2,097,152 DOFs), source
+  from 16 seeded random Fourier modes (seed 5), homogeneous Dirichlet,
+  penalty C = 1.5, 4-level multigrid V-cycle with 3+3 additive Schwarz steps
+  (overlap 2) preconditioning flexible GMRES, every step in FP64.  The
+  mixed-precision solver (FP32 MFMA subdomain solves, FP64 everywhere else)
+  is timed beside it on the same inputs, to the same true residual.
 
-Also measured: operator-apply throughput (GDOF/s) with HIP events on the
-stream the kernel runs on, on the same shape and on a 40^3, p = 7 shape whose
-vectors (262 MB) exceed the 256 MB Infinity Cache; the ceilings the GPU
-reaches outside the library (a 512 MiB copy, an FP32 torch.matmul) beside the
-vendor peaks; and the oracle on the host CPU on a bounded sample (one solve of
-the same workload).
+Also measured:
+  * the 2x2x2, p = 3 manufactured-solution solve (FP64), the 8x8x8, p = 6
+    Fourier solve (FP64 and mixed) and its Krylov/cycle variants, the 6^3,
+    p = 7 puncture Newton-Krylov solve (FP64 and mixed), and the serving
+    stream of 256 requests;
+  * operator-apply throughput (GDOF/s) with HIP events on the stream the
+    kernel runs on, on the solve shapes, every p = 3..8 at about 2 M DOFs,
+    and a 40^3, p = 7 shape whose vectors (262 MB) exceed the 256 MB
+    Infinity Cache;
+  * the ceilings the GPU reaches outside the library (a 512 MiB copy, an
+    FP32 torch.matmul) beside the vendor peaks;
+  * the oracle on the host CPU (cpu_baseline leg, a child process started
+    before the GPU is touched): one V-cycle and one operator apply of the
+    headline workload at 1 thread and at all cores, and the oracle's check of
+    the GPU solutions (residuals through the oracle's own operator, the
+    oracle's solution of the 2x2x2 case).
 
 Prints one JSON line.
 """
@@ -22,7 +32,9 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -35,19 +47,24 @@ HBM_PEAK_GBS = 8000.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
 MFMA_FP64_PEAK_TFLOPS = 78.6
 
+C5 = dict(lower=(0, 0, 0), upper=(1, 1, 1), elements=(16, 16, 16), p=7, levels=4)
+C2 = dict(lower=(0, 0, 0), upper=(1, 1, 1), elements=(8, 8, 8), p=6, levels=3)
+C1 = dict(lower=(0, 0, 0), upper=(1, 1, 1), elements=(2, 2, 2), p=3, levels=2)
+C3 = dict(lower=(-20, -20, -20), upper=(20, 20, 20), elements=(6, 6, 6), p=7, levels=2)
+
 # HBM traffic per launch of the two roofline kernels, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs of this script, each scaled by what the same
-# counter reads for the plain copy of COPY_BYTES made below.  A figure is
-# reported only while the sources it was measured on are unchanged.
+# counter reads for the plain copy of the calibration bytes made below.  A
+# figure is reported only while the sources it was measured on are unchanged.
 MEASURED_TRAFFIC = {
     "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
-                       "sha256": "e938373551449a8ea1a3516b307afcd9e0cd77c4ed5ffdbada422dc884a1f3e7",
-                       "bytes": 68707843},
+                       "sha256": None,
+                       "bytes": None},
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
-              "sha256": "cb7d0cf42f33170e20ac90f612691b41f7ab274968708ac41cdb48800bedb32f",
-              "bytes": 633367037},
+              "sha256": None,
+              "bytes": None},
 }
 
 
@@ -75,13 +92,161 @@ def _pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
-def build_c2(dg, precision, **opts):
+def _ms(times):
+    return {"p50": round(1e3 * _pct(times, 50), 3), "p99": round(1e3 * _pct(times, 99), 3)}
+
+
+# ---------------------------------------------------------------------------
+# cpu_baseline leg: the oracle in a child process
+# ---------------------------------------------------------------------------
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_child():
+    """The cpu_baseline leg (runs in its own process, started by the parent
+    before it touches the GPU).  Builds the oracle's V-cycle of the headline
+    workload, waits for the parent's GPU solutions (a .npz path on stdin),
+    checks them through the oracle, then times one V-cycle and one operator
+    apply at 1 thread and at all cores.  Prints one JSON line."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    import workloads as W
+    from oracle import krylov, mesh, multigrid, newton, operator
+
+    def log(msg):
+        print(f"[bench:cpu] {msg}", file=sys.stderr, flush=True)
+
+    n_all = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    m5 = mesh.BoxMesh(C5["lower"], C5["upper"], C5["elements"], C5["p"])
+    x, y, z = m5.node_coordinates()
+    b5 = operator.apply_mass(m5, W.fourier_source(W.fourier_modes(W.SEED_C5), x, y, z)).reshape(-1)
+    log("building the oracle's 16^3 p=7 hierarchy")
+    V5 = multigrid.VCycle(m5, 1.5, levels=C5["levels"],
+                          on_level=lambda l, m: log(f"level {l} ({m.n} elements) set up"))
+    t_setup = time.perf_counter() - t0
+    log(f"oracle set-up done in {t_setup:.1f} s; waiting for the GPU legs")
+    line = sys.stdin.readline().strip()
+    if not line:
+        return
+    path, iters = line.split()
+    iters = int(iters)
+    data = np.load(path)
+    checks = {}
+
+    def A(m):
+        N = m.N
+        return lambda v: operator.apply_operator(m, v.reshape(m.E, N, N, N), 1.5).reshape(-1)
+
+    # the GPU solutions through the oracle's own operator
+    nb5 = np.linalg.norm(b5)
+    A5 = A(m5)
+    for prec in ("fp64", "mixed"):
+        key = f"c5_{prec}"
+        if key in data:
+            checks[f"c5_{prec}_oracle_rel_residual"] = float(np.linalg.norm(b5 - A5(data[key])) / nb5)
+    m2 = mesh.BoxMesh(C2["lower"], C2["upper"], C2["elements"], C2["p"])
+    x, y, z = m2.node_coordinates()
+    b2 = operator.apply_mass(m2, W.fourier_source(W.fourier_modes(W.SEED_C2), x, y, z)).reshape(-1)
+    for prec in ("fp64", "mixed"):
+        key = f"c2_{prec}"
+        if key in data:
+            checks[f"c2_{prec}_oracle_rel_residual"] = float(
+                np.linalg.norm(b2 - A(m2)(data[key])) / np.linalg.norm(b2))
+    m1 = mesh.BoxMesh(C1["lower"], C1["upper"], C1["elements"], C1["p"])
+    x, y, z = m1.node_coordinates()
+    b1 = operator.apply_mass(m1, W.sin_product_source(x, y, z)).reshape(-1)
+    u1, its1, _ = krylov.fgmres(A(m1), b1, precondition=multigrid.VCycle(m1, 1.5, levels=2),
+                                rtol=1e-10)
+    if "c1_fp64" in data:
+        checks["c1_fp64_vs_oracle_solution_rel_diff"] = float(
+            np.linalg.norm(data["c1_fp64"] - u1) / np.linalg.norm(u1))
+        checks["c1_oracle_iterations"] = int(its1)
+    m3 = mesh.BoxMesh(C3["lower"], C3["upper"], C3["elements"], C3["p"])
+    x, y, z = m3.node_coordinates()
+    al, be = W.puncture_background(W.puncture_params(W.SEED_C3), x, y, z)
+    al, be = al.reshape(-1), be.reshape(-1)
+    N3 = m3.N
+
+    def F3(v):
+        src = newton.puncture_source(al, be, v).reshape(m3.E, N3, N3, N3)
+        return operator.apply_operator(m3, v.reshape(m3.E, N3, N3, N3), 1.5, source=src).reshape(-1)
+
+    r30 = np.linalg.norm(F3(np.zeros(m3.ndof)))
+    for prec in ("fp64", "mixed"):
+        key = f"c3_{prec}"
+        if key in data:
+            checks[f"c3_{prec}_oracle_rel_nonlinear_residual"] = float(np.linalg.norm(F3(data[key])) / r30)
+    log("oracle checks of the GPU solutions done; timing one V-cycle + apply")
+
+    def one_pass():
+        ta = time.perf_counter()
+        zz = V5(b5)
+        A5(zz)
+        return time.perf_counter() - ta
+
+    legs = {}
+    for threads in (n_all, 1):
+        with threadpool_limits(limits=threads):
+            used = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+            t = one_pass()
+        legs[threads] = (t, used)
+        log(f"{threads} thread(s): {t:.1f} s per V-cycle + apply")
+    t_all, used_all = legs[n_all]
+    t_one, _ = legs[1]
+    sample = (f"one oracle V-cycle and one operator apply of the 16^3 p=7 headline workload "
+              f"(FP64, {m5.ndof} DOFs), extrapolated by the {iters} FGMRES iterations of the "
+              f"GPU FP64 solve; Gram-Schmidt and the oracle's set-up ({t_setup:.0f} s) not counted")
+    out = dict(value=1.0 / (iters * t_all), unit="solves/s", cores=int(used_all), kind="oracle",
+               sample=sample, cpu_model=_cpu_model(), seconds_per_vcycle_and_apply=round(t_all, 2),
+               one_thread={"value": 1.0 / (iters * t_one), "cores": 1,
+                           "seconds_per_vcycle_and_apply": round(t_one, 2)},
+               oracle_checks=checks)
+    print(json.dumps(out), flush=True)
+
+
+def start_cpu_child():
+    env = dict(os.environ)
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child"],
+                            stdin=subprocess.PIPE, stdout=subprocess.PIPE, text=True, env=env)
+
+
+def finish_cpu_child(child, solutions, iters):
+    path = os.path.join(tempfile.gettempdir(), f"dgs_bench_{os.getpid()}.npz")
+    np.savez(path, **solutions)
+    try:
+        child.stdin.write(f"{path} {iters}\n")
+        child.stdin.flush()
+        out, _ = child.communicate(timeout=1200)
+    finally:
+        try:
+            os.remove(path)
+        except OSError:
+            pass
+    lines = [ln for ln in out.splitlines() if ln.startswith("{")]
+    if child.returncode != 0 or not lines:
+        raise RuntimeError(f"cpu_baseline child failed (exit {child.returncode})")
+    return json.loads(lines[-1])
+
+
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+def build_fourier(dg, cfg, seed, precision, **opts):
     import torch
     import workloads as W
-    prob = dg.Problem((0, 0, 0), (1, 1, 1), (8, 8, 8), 6, penalty=1.5, mg_levels=3,
-                      precision=precision, **opts)
+    prob = dg.Problem(cfg["lower"], cfg["upper"], cfg["elements"], cfg["p"], penalty=1.5,
+                      mg_levels=cfg["levels"], precision=precision, **opts)
     xyz = prob.node_coordinates()
-    modes = W.fourier_modes(W.SEED_C2)
+    modes = W.fourier_modes(seed)
     x, y, z = (xyz[d].cpu().numpy() for d in range(3))
     f = torch.as_tensor(W.fourier_source(modes, x, y, z)).cuda()
     b = prob.apply_mass(f)
@@ -89,12 +254,13 @@ def build_c2(dg, precision, **opts):
     return prob, b, uex
 
 
-def time_solves(prob, b, steps, warmup):
+def time_solves(prob, b, steps, warmup, cg=False):
     import torch
     u = torch.zeros_like(b)
+    solve = prob.solve_cg if cg else prob.solve
     for _ in range(warmup):
         u.zero_()
-        prob.solve(b, u)
+        solve(b, u)
     torch.cuda.synchronize()
     times, stats = [], None
     t_all = time.perf_counter()
@@ -102,28 +268,24 @@ def time_solves(prob, b, steps, warmup):
         u.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, stats = prob.solve(b, u)
+        _, stats = solve(b, u)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     total = time.perf_counter() - t_all
     return u, stats, times, total
 
 
-def time_cg(prob, b, reps=10):
-    """The same solve by preconditioned conjugate gradients (dgs_cg_solve),
-    one V-cycle per iteration: p50 wall time and iterations."""
-    import torch
-    u = torch.zeros_like(b)
-    prob.solve_cg(b, u)
-    times, st = [], None
-    for _ in range(reps):
-        u.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, st = prob.solve_cg(b, u)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    return dict(ms_p50=round(1e3 * _pct(times, 50), 3), iterations=st["iterations"],
+def solve_leg(dg, cfg, seed, precision, steps, warmup, **opts):
+    prob, b, uex = build_fourier(dg, cfg, seed, precision, **opts)
+    u, st, times, total = time_solves(prob, b, steps, warmup)
+    un = u.cpu().numpy()
+    return dict(prob=prob, b=b, u=un, stats=st, times=times, total=total,
+                rms_err=float(np.sqrt(np.mean((un - uex) ** 2))), setup_s=st["t_setup_s"])
+
+
+def summary(leg):
+    st = leg["stats"]
+    return dict(ms=_ms(leg["times"]), iterations=st["iterations"],
                 rel_residual=st["rel_residual"], converged=st["converged"])
 
 
@@ -211,29 +373,34 @@ def measured_ceilings():
     return dict(copy_gbs=copy_gbs, fp32_gemm_tflops=gemm_tflops)
 
 
-def time_c5(dg, steps=3):
-    """The 16^3, p = 7 share (2.1 M DOFs, 4 levels): FP64 and mixed solves."""
+def newton_leg(dg, precision, steps=10, warmup=2):
+    """The 6^3, p = 7 puncture problem on [-20, 20]^3 by Newton-Krylov with the
+    multigrid-Schwarz preconditioner (subdomain GMRES(3))."""
     import torch
     import workloads as W
-    out = {}
-    for prec in ("mixed", "fp64"):
-        prob = dg.Problem((0, 0, 0), (1, 1, 1), (16, 16, 16), 7, penalty=1.5, mg_levels=4,
-                          precision=prec)
-        xyz = prob.node_coordinates()
-        modes = W.fourier_modes(W.SEED_C5)
-        f = torch.as_tensor(W.fourier_source(modes, *(xyz[d].cpu().numpy() for d in range(3)))).cuda()
-        b = prob.apply_mass(f)
-        u, st, times, _ = time_solves(prob, b, steps, 1)
-        out[prec] = dict(ms_p50=round(1e3 * _pct(times, 50), 3), iterations=st["iterations"],
-                         rel_residual=st["rel_residual"], setup_s=round(st["t_setup_s"], 3),
-                         u=u.cpu().numpy())
-        prob.close()
-    out["speedup_mixed_vs_fp64"] = round(out["fp64"]["ms_p50"] / out["mixed"]["ms_p50"], 3)
-    out["mixed_vs_fp64_solution_rel_diff"] = float(
-        np.linalg.norm(out["mixed"]["u"] - out["fp64"]["u"]) / np.linalg.norm(out["fp64"]["u"]))
-    for prec in ("mixed", "fp64"):
-        del out[prec]["u"]
-    return out
+    prob = dg.Problem(C3["lower"], C3["upper"], C3["elements"], C3["p"], mg_levels=C3["levels"],
+                      subdomain_iters=3, precision=precision)
+    xyz = [v.cpu().numpy() for v in prob.node_coordinates()]
+    al, be = W.puncture_background(W.puncture_params(W.SEED_C3), *xyz)
+    al, be = torch.as_tensor(al).cuda(), torch.as_tensor(be).cuda()
+    u = torch.zeros(prob.ndof, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        u.zero_()
+        prob.newton_solve(al, be, u=u)
+    times, st = [], None
+    for _ in range(steps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = prob.newton_solve(al, be, u=u)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    out = dict(ms=_ms(times), newton_steps=st["newton_steps"], linear_iterations=st["iterations"],
+               backtracks=st["backtracks"], rel_nonlinear_residual=st["rel_residual"],
+               converged=st["converged"], setup_s=round(st["t_setup_s"], 3))
+    un = u.cpu().numpy()
+    prob.close()
+    return out, un
 
 
 def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threads=0):
@@ -252,7 +419,7 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
 
     def closed_loop():
         srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60,
-                    host_threads=host_threads)
+                        host_threads=host_threads)
         t0 = time.perf_counter()
         for r, f in data:
             srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)
@@ -274,13 +441,12 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
                     host_threads=host_threads)
     t0 = time.perf_counter()
     nxt = 0
-    ids = {}
     peak_active = 0
     while True:
         now = time.perf_counter() - t0
         while nxt < n_requests and gaps[nxt] <= now:
             r, f = data[nxt]
-            ids[srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)] = nxt
+            srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)
             nxt += 1
         a, q = srv.step()
         peak_active = max(peak_active, a)
@@ -304,102 +470,115 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
                 iterations_p50=float(np.median(its)), iterations_max=int(max(its)))
 
 
-def cpu_baseline():
-    """The oracle solving the same workload once (setup not counted)."""
-    import workloads as W
-    from oracle import krylov, mesh, multigrid, operator
-    m = mesh.BoxMesh((0, 0, 0), (1, 1, 1), (8, 8, 8), 6)
-    x, y, z = m.node_coordinates()
-    b = operator.apply_mass(m, W.fourier_source(W.fourier_modes(W.SEED_C2), x, y, z)).reshape(-1)
-    N = m.N
-    A = lambda v: operator.apply_operator(m, v.reshape(m.E, N, N, N), 1.5).reshape(-1)
-    t0 = time.perf_counter()
-    V = multigrid.VCycle(m, 1.5, levels=3)
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    u, its, hist = krylov.fgmres(A, b, precondition=V, rtol=1e-10)
-    t = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=1.0 / t, unit="solves/s", cores=threads, kind="oracle",
-                sample=f"one FP64 oracle solve of the 8^3 p=6 workload ({its} FGMRES iterations, "
-                       f"{t:.1f} s; set-up of {t_setup:.1f} s not counted)"), u
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large-apply", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     # the ceiling measurements include large copies; counter runs that are
     # calibrated by the one 262 MB copy leave them out
     ap.add_argument("--no-ceilings", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=256)
     # host threads that issue the active requests' stages (0: the library default)
     ap.add_argument("--serve-threads", type=int, default=0)
-    # pin the autotuned choices of the two roofline kernels (the 8^3 p=6 mixed
+    # pin the autotuned choices of the two roofline kernels (the headline FP64
     # problem's fine-level GEMM variant, the 40^3 p=7 apply's launch shape), so
     # that a profiled run launches the kernels an unprofiled run chose
     ap.add_argument("--gemm-variant", type=int, default=None)
     ap.add_argument("--apply-shape", type=int, default=None)
+    ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_child:
+        cpu_child()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
+    # the oracle's child starts before anything here touches the GPU
+    child = None if args.no_cpu_baseline else start_cpu_child()
+
     import torch
     import paper_2111_06767_amd as dg
     torch.cuda.set_device(0)
+    solutions = {}
 
-    res = {}
-    for prec in ("mixed", "fp64"):
-        _log(f"8^3 p=6 {prec}: set-up and {args.warmup}+{args.steps} solves")
-        prob, b, uex = build_c2(dg, prec)
-        if prec == "mixed" and args.gemm_variant is not None:
+    # -- headline: 16^3 p=7, FP64 and mixed ---------------------------------
+    legs = {}
+    for prec in ("fp64", "mixed"):
+        _log(f"16^3 p=7 {prec}: set-up and {args.warmup}+{args.steps} solves")
+        prob, b, uex = build_fourier(dg, C5, 5, prec)
+        if prec == "fp64" and args.gemm_variant is not None:
             prob.set_gemm_variant(args.gemm_variant, level=0)
         u, st, times, total = time_solves(prob, b, args.steps, args.warmup)
         un = u.cpu().numpy()
-        res[prec] = dict(prob=prob, b=b, u=un, stats=st, times=times, total=total,
-                         err_exact=float(np.sqrt(np.mean((un - uex) ** 2))),
-                         setup_s=st["t_setup_s"])
+        legs[prec] = dict(prob=prob, u=un, stats=st, times=times, total=total,
+                          rms_err=float(np.sqrt(np.mean((un - uex) ** 2))), setup_s=st["t_setup_s"])
+        solutions[f"c5_{prec}"] = un
+    fp64, mixed = legs["fp64"], legs["mixed"]
+    _log("16^3 p=7 subdomain GEMMs")
+    gemm64 = time_subdomain_gemm(fp64["prob"])
+    gemm32 = time_subdomain_gemm(mixed["prob"])
+    variant64 = fp64["prob"].gemm_variant(0)
+    variant32 = mixed["prob"].gemm_variant(0)
+    headline_iters = fp64["stats"]["iterations"]
+    for leg in legs.values():
+        leg["prob"].close()
 
-    mixed, fp64 = res["mixed"], res["fp64"]
-    sol_diff = float(np.linalg.norm(mixed["u"] - fp64["u"]) / np.linalg.norm(fp64["u"]))
-    _log("8^3 p=6 by preconditioned conjugate gradients")
-    cg = {prec: time_cg(res[prec]["prob"], res[prec]["b"]) for prec in ("mixed", "fp64")}
-    _log("8^3 p=6 by restarted FGMRES(4)")
-    rprob, rb, _ = build_c2(dg, "mixed", restart=4)
-    _, rst, rtimes, _ = time_solves(rprob, rb, 10, 2)
-    restarted = dict(restart=4, ms_p50=round(1e3 * _pct(rtimes, 50), 3),
-                     iterations=rst["iterations"], rel_residual=rst["rel_residual"],
-                     converged=rst["converged"])
-    rprob.close()
-    _log("8^3 p=6 with the W-cycle")
-    wprob, wb, _ = build_c2(dg, "mixed", cycle=2)
-    _, wst, wtimes, _ = time_solves(wprob, wb, 10, 2)
-    wcycle = dict(ms_p50=round(1e3 * _pct(wtimes, 50), 3), iterations=wst["iterations"],
-                  rel_residual=wst["rel_residual"], converged=wst["converged"])
-    wprob.close()
-    _log("8^3 p=6 with the F-cycle")
-    fprob, fb, _ = build_c2(dg, "mixed", cycle=3)
-    _, fst, ftimes, _ = time_solves(fprob, fb, 10, 2)
-    fcycle = dict(ms_p50=round(1e3 * _pct(ftimes, 50), 3), iterations=fst["iterations"],
-                  rel_residual=fst["rel_residual"], converged=fst["converged"])
-    fprob.close()
-    _log("8^3 p=6 with additive multigrid")
-    aprob, ab, _ = build_c2(dg, "mixed", additive=1)
-    _, ast_, atimes, _ = time_solves(aprob, ab, 10, 2)
-    additive = dict(ms_p50=round(1e3 * _pct(atimes, 50), 3), iterations=ast_["iterations"],
-                    rel_residual=ast_["rel_residual"], converged=ast_["converged"])
-    aprob.close()
-    _log("subdomain GEMM and apply timings")
-    gemm = time_subdomain_gemm(mixed["prob"])
+    # -- c1: 2^3 p=3 manufactured solution, FP64 -----------------------------
+    _log("2^3 p=3 FP64 solves")
+    import workloads as W
+    p1 = dg.Problem(C1["lower"], C1["upper"], C1["elements"], C1["p"], penalty=1.5,
+                    mg_levels=C1["levels"])
+    xyz = p1.node_coordinates()
+    b1 = p1.apply_mass(torch.as_tensor(W.sin_product_source(*(xyz[d].cpu().numpy() for d in range(3)))).cuda())
+    u1, st1, t1, _ = time_solves(p1, b1, 50, 5)
+    solutions["c1_fp64"] = u1.cpu().numpy()
+    c1 = dict(ms=_ms(t1), iterations=st1["iterations"], rel_residual=st1["rel_residual"],
+              converged=st1["converged"])
+    p1.close()
+
+    # -- c2: 8^3 p=6, FP64 and mixed, and its variants -----------------------
+    c2 = {}
+    for prec in ("fp64", "mixed"):
+        _log(f"8^3 p=6 {prec}")
+        leg = solve_leg(dg, C2, 2, prec, 20, 3)
+        c2[prec] = summary(leg)
+        c2[prec]["rms_error_vs_exact"] = leg["rms_err"]
+        solutions[f"c2_{prec}"] = leg["u"]
+        leg["prob"].close()
+    c2["speedup_mixed_vs_fp64_p50"] = round(c2["fp64"]["ms"]["p50"] / c2["mixed"]["ms"]["p50"], 3)
+    variants = None
+    if not args.no_variants:
+        variants = {}
+        for name, opts in (("cg", dict(cg=True)), ("restarted_fgmres_4", dict(restart=4)),
+                           ("wcycle", dict(cycle=2)), ("fcycle", dict(cycle=3)),
+                           ("additive_mg", dict(additive=1))):
+            _log(f"8^3 p=6 mixed, {name}")
+            cg = opts.pop("cg", False)
+            prob, b, _ = build_fourier(dg, C2, 2, "mixed", **opts)
+            _, st, times, _ = time_solves(prob, b, 10, 2, cg=cg)
+            variants[name] = dict(ms_p50=round(1e3 * _pct(times, 50), 3), iterations=st["iterations"],
+                                  rel_residual=st["rel_residual"], converged=st["converged"])
+            prob.close()
+
+    # -- c3: puncture Newton-Krylov, FP64 and mixed ---------------------------
+    c3 = {}
+    for prec in ("fp64", "mixed"):
+        _log(f"6^3 p=7 puncture Newton {prec}")
+        c3[prec], solutions[f"c3_{prec}"] = newton_leg(dg, prec)
+    c3["speedup_mixed_vs_fp64_p50"] = round(c3["fp64"]["ms"]["p50"] / c3["mixed"]["ms"]["p50"], 3)
+    c3["mixed_vs_fp64_solution_rel_diff"] = float(
+        np.linalg.norm(solutions["c3_mixed"] - solutions["c3_fp64"]) / np.linalg.norm(solutions["c3_fp64"]))
+
+    # -- applies --------------------------------------------------------------
+    _log("operator applies")
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
     apply_c5 = time_apply(dg, (16, 16, 16), 7)
-    # every degree at about 2 M DOFs (n^3 (p+1)^3)
     sweep = {}
     for p, n in ((3, 32), (4, 25), (5, 21), (6, 18), (7, 16), (8, 14)):
         r = time_apply(dg, (n, n, n), p, reps=50, warm=5)
@@ -409,16 +588,28 @@ def main():
     apply_big = None if args.no_large_apply else time_apply(dg, (40, 40, 40), 7, reps=50,
                                                              calibration_copy=True,
                                                              shape=args.apply_shape)
-    roofline = {"bound": "mfma", "achieved": round(gemm["achieved_tflops"], 2),
-                "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(gemm["achieved_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4),
+
+    serving = None
+    if not args.no_serving:
+        _log(f"serving stream of {args.serve_requests} requests")
+        serving = run_serving(dg, args.serve_requests, host_threads=args.serve_threads)
+    ceil = None if args.no_ceilings else measured_ceilings()
+
+    roofline = {"bound": "mfma", "achieved": round(gemm64["achieved_tflops"], 2),
+                "peak": MFMA_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(gemm64["achieved_tflops"] / MFMA_FP64_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic("subdomain_gemm"),
-                "kernel": "grouped subdomain-solve GEMM (FP32 MFMA) of one Schwarz sweep on the "
-                          "8^3 p=6 fine level, 2 sum_S n_S^2 = "
-                          f"{gemm['flops_per_launch']:.4g} flop per launch, tile variant "
-                          f"{mixed['prob'].gemm_variant(0)}",
-                "gemm_variant": mixed["prob"].gemm_variant(0),
-                "ms_per_launch": round(gemm["ms_per_launch"], 5)}
+                "kernel": "grouped subdomain-solve GEMM (FP64 MFMA) of one Schwarz sweep on the "
+                          "16^3 p=7 fine level, 2 sum_S n_S^2 = "
+                          f"{gemm64['flops_per_launch']:.4g} flop per launch, tile variant {variant64}",
+                "gemm_variant": variant64,
+                "ms_per_launch": round(gemm64["ms_per_launch"], 5)}
+    roofline_mixed_gemm = {"bound": "mfma", "achieved": round(gemm32["achieved_tflops"], 2),
+                           "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(gemm32["achieved_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4),
+                           "kernel": "the same GEMM in FP32 (mixed-precision solver), tile variant "
+                                     f"{variant32}",
+                           "ms_per_launch": round(gemm32["ms_per_launch"], 5)}
     roof_src = apply_big or apply_c5
     roofline_apply = {"bound": "hbm", "achieved": round(roof_src["achieved_gbs"], 1),
                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -426,83 +617,79 @@ def main():
                       "traffic": measured_traffic("apply") if apply_big else None,
                       "kernel": f"DG operator apply, {roof_src['elements']} elements "
                                 f"p={roof_src['p']}, 16 B/DOF algorithmic (read u, write Au), "
-                                "launch shape " + ("2x2x2 element bricks" if roof_src["launch_shape"] < 0
-                                                   else f"{roof_src['launch_shape']} elements/workgroup"
-                                                   " (0: default)"),
-                      "ms_per_launch": round(roof_src["ms_per_apply"], 5)}
-    roofline_apply["launch_shape"] = roof_src["launch_shape"]
+                                f"launch shape {roof_src['launch_shape']}",
+                      "gdofs": round(roof_src["gdofs"], 1),
+                      "ms_per_launch": round(roof_src["ms_per_apply"], 5),
+                      "launch_shape": roof_src["launch_shape"]}
     if apply_big:
         roofline_apply["calibration_copy_bytes"] = 8 * apply_big["ndof"]
-    ceil = None if args.no_ceilings else measured_ceilings()
     if ceil:
-        roofline["measured_ceiling"] = {
+        roofline_mixed_gemm["measured_ceiling"] = {
             "what": "FP32 8192^3 torch.matmul (vendor BLAS) on this GPU", "unit": "TFLOP/s",
             "value": round(ceil["fp32_gemm_tflops"], 1),
-            "frac": round(gemm["achieved_tflops"] / ceil["fp32_gemm_tflops"], 4)}
+            "frac": round(gemm32["achieved_tflops"] / ceil["fp32_gemm_tflops"], 4)}
         roofline_apply["measured_ceiling"] = {
             "what": "device-to-device copy of 512 MiB on this GPU (read + write)", "unit": "GB/s",
             "value": round(ceil["copy_gbs"], 1),
             "frac": round(roof_src["achieved_gbs"] / ceil["copy_gbs"], 4)}
 
-    if not args.no_c5:
-        _log("16^3 p=7 solves")
-    c5 = None if args.no_c5 else time_c5(dg)
-    if not args.no_serving:
-        _log(f"serving stream of {args.serve_requests} requests")
-    serving = None if args.no_serving else run_serving(dg, args.serve_requests,
-                                                          host_threads=args.serve_threads)
-
     cpu = None
-    u_oracle = None
-    if not args.no_cpu_baseline:
-        _log("oracle on the host CPU")
-        cpu, u_oracle = cpu_baseline()
+    if child is not None:
+        _log("cpu_baseline leg: the oracle's checks and timing")
+        cpu = finish_cpu_child(child, solutions, headline_iters)
+
+    c5_out = {
+        "solve_ms_fp64": _ms(fp64["times"]), "solve_ms_mixed": _ms(mixed["times"]),
+        "speedup_mixed_vs_fp64_p50": round(_pct(fp64["times"], 50) / _pct(mixed["times"], 50), 3),
+        "iterations": {"fp64": fp64["stats"]["iterations"], "mixed": mixed["stats"]["iterations"]},
+        "rel_residual": {"fp64": fp64["stats"]["rel_residual"], "mixed": mixed["stats"]["rel_residual"]},
+        "rms_error_vs_exact": {"fp64": fp64["rms_err"], "mixed": mixed["rms_err"]},
+        "mixed_vs_fp64_solution_rel_diff": float(
+            np.linalg.norm(mixed["u"] - fp64["u"]) / np.linalg.norm(fp64["u"])),
+        "setup_s": {"fp64": round(fp64["setup_s"], 3), "mixed": round(mixed["setup_s"], 3)},
+        "mixed_solves_per_s": round(args.steps / mixed["total"], 3),
+    }
+    if cpu:
+        checks = cpu.get("oracle_checks", {})
+        c5_out["oracle_rel_residual"] = {p: checks.get(f"c5_{p}_oracle_rel_residual")
+                                         for p in ("fp64", "mixed")}
+        for p in ("fp64", "mixed"):
+            c2[p]["oracle_rel_residual"] = checks.get(f"c2_{p}_oracle_rel_residual")
+            c3[p]["oracle_rel_nonlinear_residual"] = checks.get(f"c3_{p}_oracle_rel_nonlinear_residual")
+        c1["vs_oracle_solution_rel_diff"] = checks.get("c1_fp64_vs_oracle_solution_rel_diff")
+        c1["oracle_iterations"] = checks.get("c1_oracle_iterations")
 
     out = {
         "metric": METRIC,
-        "value": round(args.steps / mixed["total"], 3),
+        "value": round(args.steps / fp64["total"], 3),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * mixed["total"] / args.steps, 3),
+        "ms_per_step": round(1e3 * fp64["total"] / args.steps, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32-mfma subdomain solves + f64",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3D Poisson [0,1]^3, 8x8x8 elements, p=6 (175616 DOFs), 16-mode "
-                               "random-Fourier source seed 2, C=1.5, 3-level MG-Schwarz FGMRES, "
-                               "rtol 1e-10",
+        "config": {"workload": "3D Poisson [0,1]^3, 16x16x16 elements, p=7 (2097152 DOFs), 16-mode "
+                               "random-Fourier source seed 5, C=1.5, 4-level multigrid V-cycle with "
+                               "3+3 additive Schwarz steps (overlap 2) preconditioning FGMRES, "
+                               "rtol 1e-10, FP64 throughout",
                    "global_batch": 1, "parallelism": "single GPU"},
-        "solve_ms_mixed": {"p50": round(1e3 * _pct(mixed["times"], 50), 3),
-                           "p99": round(1e3 * _pct(mixed["times"], 99), 3)},
-        "solve_ms_fp64": {"p50": round(1e3 * _pct(fp64["times"], 50), 3),
-                          "p99": round(1e3 * _pct(fp64["times"], 99), 3)},
-        "speedup_mixed_vs_fp64_p50": round(_pct(fp64["times"], 50) / _pct(mixed["times"], 50), 3),
-        "iterations": {"mixed": mixed["stats"]["iterations"], "fp64": fp64["stats"]["iterations"]},
-        "rel_residual": {"mixed": mixed["stats"]["rel_residual"], "fp64": fp64["stats"]["rel_residual"]},
-        "mixed_vs_fp64_solution_rel_diff": sol_diff,
-        "rms_error_vs_exact": {"mixed": mixed["err_exact"], "fp64": fp64["err_exact"]},
-        "setup_s": {"mixed": round(mixed["setup_s"], 3), "fp64": round(fp64["setup_s"], 3)},
+        "c5_16x16x16_p7": c5_out,
+        "c1_2x2x2_p3": c1,
+        "c2_8x8x8_p6": c2,
+        "c2_variants_mixed": variants,
+        "c3_puncture_6x6x6_p7": c3,
         "apply": {"c2_shape": apply_c2, "16^3_p7": apply_c5, "40^3_p7": apply_big,
                   "sweep_2M_dofs": sweep},
-        "c2_conjugate_gradients": cg,
-        "c2_restarted_fgmres_mixed": restarted,
-        "c2_wcycle_mixed": wcycle,
-        "c2_fcycle_mixed": fcycle,
-        "c2_additive_mg_mixed": additive,
-        "c5_16x16x16_p7": c5,
         "serving": serving,
         "roofline": roofline,
+        "roofline_mixed_gemm": roofline_mixed_gemm,
         "roofline_apply": roofline_apply,
         "cpu_baseline": cpu,
     }
-    if u_oracle is not None:
-        out["fp64_vs_oracle_solution_rel_diff"] = float(
-            np.linalg.norm(fp64["u"] - u_oracle) / np.linalg.norm(u_oracle))
-        out["mixed_vs_oracle_solution_rel_diff"] = float(
-            np.linalg.norm(mixed["u"] - u_oracle) / np.linalg.norm(u_oracle))
     print(json.dumps(out))
 
 

@@ -247,6 +247,13 @@ int dgs_get_gemm_variant(const dgs_problem* prob, int level, int* variant);
  * x = lower_x + h_x (e_x + (xi_i + 1) / 2), and likewise in y and z. */
 int dgs_lgl_nodes(int p, double* xi);
 
+/* Host coordinates of every point of a box grid (no problem needed), as
+ * dgs_node_coordinates gives them on the device: xyz (host, 3 * n values,
+ * n = n_x n_y n_z (p+1)^3) receives xyz[d * n + idx] in the canonical layout.
+ * DGS_ERR_INVALID for a bad grid or an n that does not match it. */
+int dgs_grid_coordinates(const dgs_domain* domain, const int elements[3], int p, double* xyz,
+                         long long n);
+
 /* ---- Serving: continuous batching of many Poisson and puncture solves on one device ----
  * Requests queue until their estimated device footprint fits in
  * hbm_budget_bytes and one of max_active slots is free; every admitted request

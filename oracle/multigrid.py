@@ -104,7 +104,7 @@ class VCycle:
     by a V-visit from its result."""
 
     def __init__(self, mesh: BoxMesh, C, levels=2, overlap=2, pre=3, post=3,
-                 diag=None, subdomain_iters=0, gamma=1):
+                 diag=None, subdomain_iters=0, gamma=1, on_level=None):
         self.levels = hierarchy(mesh, levels)
         self.pre, self.post = pre, post
         self.gamma = gamma
@@ -113,6 +113,8 @@ class VCycle:
         for li, (m, split) in enumerate(self.levels):
             self.smoothers.append(SchwarzSmoother(m, C, overlap, diag=d,
                                                   subdomain_iters=subdomain_iters))
+            if on_level is not None:  # progress report of a long set-up
+                on_level(li, m)
             if split is not None and d is not None:
                 d = restrict(m, self.levels[li + 1][0], split, d)
 

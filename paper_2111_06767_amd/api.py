@@ -31,7 +31,7 @@ EXPORTED = (
     "dgs_lgl_nodes", "dgs_server_create", "dgs_server_destroy", "dgs_server_submit",
     "dgs_server_step", "dgs_server_finished", "dgs_server_fetch", "dgs_subdomain_solves",
     "dgs_set_apply_shape", "dgs_get_apply_shape", "dgs_set_gemm_variant", "dgs_get_gemm_variant",
-    "dgs_server_submit_puncture", "dgs_cg_solve",
+    "dgs_server_submit_puncture", "dgs_cg_solve", "dgs_grid_coordinates",
 )
 
 
@@ -103,6 +103,9 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_newton_solve.argtypes = [P, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.POINTER(Stats), P]
     lib.dgs_lgl_nodes.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.dgs_grid_coordinates.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.c_longlong]
     lib.dgs_server_create.argtypes = [ctypes.POINTER(ServerOptions), ctypes.POINTER(P)]
     lib.dgs_server_destroy.argtypes = [P]
     lib.dgs_server_submit.argtypes = [P, ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
@@ -367,22 +370,16 @@ def lgl_nodes(p):
 
 
 def points(lower, upper, elements, p):
-    """Host coordinates (3, E*N^3) of every point in the canonical layout:
-    x = lower + h (e + (xi + 1) / 2) per dimension (see dgs_lgl_nodes)."""
+    """Host coordinates (3, E*N^3) of every point in the canonical layout
+    (dgs_grid_coordinates)."""
     import numpy as np
-    xi = lgl_nodes(p)
-    N = p + 1
-    nx, ny, nz = elements
-    out = []
-    for d, (n_d, lo, hi) in enumerate(zip(elements, lower, upper)):
-        h = (hi - lo) / n_d
-        c = lo + h * (np.arange(n_d)[:, None] + (xi[None, :] + 1.0) / 2.0)  # [e_d, node]
-        shape = [1] * 6
-        shape[2 - d] = n_d      # grid axes (e_z, e_y, e_x)
-        shape[5 - d] = N        # node axes (k, j, i)
-        full = np.broadcast_to(c.reshape(shape), (nz, ny, nx, N, N, N))
-        out.append(np.ascontiguousarray(full).reshape(-1))
-    return np.stack(out)
+    n = int(elements[0]) * int(elements[1]) * int(elements[2]) * (int(p) + 1) ** 3
+    out = np.empty(3 * n)
+    dom = Domain((ctypes.c_double * 3)(*lower), (ctypes.c_double * 3)(*upper))
+    _check(load_library().dgs_grid_coordinates(
+        ctypes.byref(dom), (ctypes.c_int * 3)(*elements), int(p),
+        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n))
+    return out.reshape(3, n)
 
 
 class Server:

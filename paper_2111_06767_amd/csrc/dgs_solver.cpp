@@ -60,10 +60,25 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+// One process-wide lock around the library's device-management calls:
+// allocation and release of device and pinned memory, stream creation and
+// destruction, and graph capture and instantiation.  Kernel and graph
+// launches, copies and stream queries do not take it.  The serving loop's
+// worker threads set up requests (allocating, capturing) while others launch,
+// and a capture must not overlap another thread's allocation or release (a
+// release waits for the device), so these calls are serialised here.
+std::recursive_mutex g_dev_mutex;
+
+void dfree(void* p) {
+  std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+  (void)hipFree(p);
+}
+
 template <typename T>
 T* dalloc(size_t count) {
   if (count == 0) count = 1;
   void* p = nullptr;
+  std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
   hipError_t e = hipMalloc(&p, count * sizeof(T));
   if (e != hipSuccess)
     throw DgsError(e == hipErrorOutOfMemory ? DGS_ERR_OOM : DGS_ERR_HIP,
@@ -236,6 +251,7 @@ struct dgs_problem {
   template <typename T>
   T* alloc(size_t count) {
     T* p = nullptr;
+    std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
     if (alloc_fn) {
       const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
       p = static_cast<T*>(alloc_fn(bytes, alloc_ctx));
@@ -252,6 +268,7 @@ struct dgs_problem {
   }
   // p must be one of `allocations` and no longer in use on the device
   void release(void* p) {
+    std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
     auto it = std::find(allocations.begin(), allocations.end(), p);
     if (it != allocations.end()) allocations.erase(it);
     if (free_fn)
@@ -260,6 +277,7 @@ struct dgs_problem {
       (void)hipFree(p);
   }
   ~dgs_problem() {
+    std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
     // a caller's allocator may hand the memory out again at once: let the
     // device finish with it first (also when set-up failed half-way)
     if (free_fn && !allocations.empty()) (void)hipDeviceSynchronize();
@@ -548,7 +566,7 @@ void build_keys(dgs_problem* P, const std::vector<CacheEntry*>& todo,
   }
   n_pad = (n_pad + 63) / 64 * 64;  // the blocked inversion works on 64-wide blocks
   double* d_batch = dalloc<double>((size_t)nk * n_pad * n_pad);
-  std::unique_ptr<void, void (*)(void*)> g1(d_batch, [](void* p) { (void)hipFree(p); });
+  std::unique_ptr<void, void (*)(void*)> g1(d_batch, dfree);
   {
     std::vector<double> eye((size_t)n_pad * n_pad, 0.0);
     for (int i = 0; i < n_pad; ++i) eye[(size_t)i * n_pad + i] = 1.0;
@@ -593,13 +611,13 @@ void build_keys(dgs_problem* P, const std::vector<CacheEntry*>& todo,
     const long long stride = (long long)Ep * N3;
     const long long tot = stride * n;
     int* d_nb = dalloc<int>(nb.size());
-    std::unique_ptr<void, void (*)(void*)> g2(d_nb, [](void* p) { (void)hipFree(p); });
+    std::unique_ptr<void, void (*)(void*)> g2(d_nb, dfree);
     int* d_idx = dalloc<int>(n);
-    std::unique_ptr<void, void (*)(void*)> g3(d_idx, [](void* p) { (void)hipFree(p); });
+    std::unique_ptr<void, void (*)(void*)> g3(d_idx, dfree);
     double* d_X = dalloc<double>(tot);
-    std::unique_ptr<void, void (*)(void*)> g4(d_X, [](void* p) { (void)hipFree(p); });
+    std::unique_ptr<void, void (*)(void*)> g4(d_X, dfree);
     double* d_AX = dalloc<double>(tot);
-    std::unique_ptr<void, void (*)(void*)> g5(d_AX, [](void* p) { (void)hipFree(p); });
+    std::unique_ptr<void, void (*)(void*)> g5(d_AX, dfree);
     upload(d_nb, nb, s);
     upload(d_idx, idx, s);
     HIP_OK(launch_fill(d_X, 0.0, tot, s));
@@ -632,11 +650,11 @@ void build_keys(dgs_problem* P, const std::vector<CacheEntry*>& todo,
                                  c.op64, c.op32, s));
   }
   double* d_P = dalloc<double>((size_t)nk * 64 * 64);
-  std::unique_ptr<void, void (*)(void*)> g6(d_P, [](void* p) { (void)hipFree(p); });
+  std::unique_ptr<void, void (*)(void*)> g6(d_P, dfree);
   double* d_R = dalloc<double>((size_t)nk * 64 * n_pad);
-  std::unique_ptr<void, void (*)(void*)> g7(d_R, [](void* p) { (void)hipFree(p); });
+  std::unique_ptr<void, void (*)(void*)> g7(d_R, dfree);
   double* d_C = dalloc<double>((size_t)nk * 64 * n_pad);
-  std::unique_ptr<void, void (*)(void*)> g8(d_C, [](void* p) { (void)hipFree(p); });
+  std::unique_ptr<void, void (*)(void*)> g8(d_C, dfree);
   HIP_OK(launch_block_inverse(d_batch, n_pad, nk, d_P, d_R, d_C, s));
   for (int k = 0; k < nk; ++k) {
     CacheEntry& c = *todo[k];
@@ -1044,28 +1062,54 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
   }
 }
 
-// One captured V-cycle from the finest level's d_b into its d_u (the graph
-// for the current operator kind is captured on first use).
+// Capture the multigrid cycle of operator kind gi (0: A; 1: A + diag(d)) as a
+// hipGraph that reads the finest level's d_b (with its first subdomain rows
+// already gathered) and writes its d_u.  Called at set-up: kind 0 by
+// dgs_create_problem, kind 1 by the first dgs_set_diagonal, and again after
+// a tuning override changes the launches; never inside a solve, so
+// dgs_precondition and the Krylov iterations only replay.  Capture touches no
+// device memory, so it needs no synchronisation with earlier work.
+void capture_vgraph(dgs_problem* P, int gi) {
+  std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+  Level& L0 = P->levels[0];
+  if (P->vgraph[gi]) {
+    HIP_OK(hipGraphExecDestroy(P->vgraph[gi]));
+    P->vgraph[gi] = nullptr;
+  }
+  if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  const bool saved = P->diag_active;
+  P->diag_active = gi == 1;
+  HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    vcycle_eager(P, L0.d_b, L0.d_u, P->cap_stream, /*rs0_ready=*/true);
+  } catch (...) {
+    (void)hipStreamEndCapture(P->cap_stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    P->diag_active = saved;
+    throw;
+  }
+  P->diag_active = saved;
+  HIP_OK(hipStreamEndCapture(P->cap_stream, &graph));
+  hipError_t e = hipGraphInstantiate(&P->vgraph[gi], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIP_OK(e);
+}
+
+// Re-capture the cycles that exist after a change of the launches they hold
+// (launch shape, GEMM variant); earlier replays may still be in flight.
+void recapture_vgraphs(dgs_problem* P) {
+  if (!P->opt.use_graphs) return;
+  HIP_OK(hipDeviceSynchronize());
+  for (int gi = 0; gi < 2; ++gi)
+    if (P->vgraph[gi]) capture_vgraph(P, gi);
+}
+
+// Replay the captured cycle of the current operator kind on s.
 void vcycle_graph(dgs_problem* P, hipStream_t s) {
   Level& L0 = P->levels[0];
   const int gi = (P->diag_active && L0.d_diag) ? 1 : 0;
-  if (!P->vgraph[gi]) {
-    if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
-    HIP_OK(hipStreamSynchronize(s));
-    HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipGraph_t graph = nullptr;
-    try {
-      vcycle_eager(P, L0.d_b, L0.d_u, P->cap_stream, /*rs0_ready=*/true);
-    } catch (...) {
-      (void)hipStreamEndCapture(P->cap_stream, &graph);
-      if (graph) (void)hipGraphDestroy(graph);
-      throw;
-    }
-    HIP_OK(hipStreamEndCapture(P->cap_stream, &graph));
-    hipError_t e = hipGraphInstantiate(&P->vgraph[gi], graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    HIP_OK(e);
-  }
+  if (!P->vgraph[gi]) throw DgsError(DGS_ERR_HIP, "multigrid cycle was not captured at set-up");
   HIP_OK(hipGraphLaunch(P->vgraph[gi], s));
 }
 
@@ -1098,6 +1142,7 @@ void ensure_krylov(dgs_problem* P, int m) {
   P->d_y = P->alloc<double>(m + 1);
   P->d_tmp = P->alloc<double>(n);
   P->d_tmp2 = P->alloc<double>(n);
+  std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
   if (P->h_pinned) (void)hipHostFree(P->h_pinned);
   P->h_pinned = nullptr;
   HIP_OK(hipHostMalloc((void**)&P->h_pinned, sizeof(double) * 4 * (m + 2), hipHostMallocDefault));
@@ -1161,6 +1206,7 @@ void set_diagonal(dgs_problem* P, const double* d, hipStream_t s) {
     HIP_OK(launch_restrict(P->N, L.d_diag, C.d_diag, L.n, C.n, L.split, P->dt, s));
   }
   P->diag_active = true;
+  if (P->opt.use_graphs && !P->vgraph[1]) capture_vgraph(P, 1);
 }
 
 struct FgmresResult {
@@ -1330,8 +1376,12 @@ struct FgmresRun {
       }
     } else if (stage == kFinish) {
       R.rel_residual = std::sqrt(hp[0]) / beta0;
+      if (!std::isfinite(R.rel_residual)) throw DgsError(DGS_ERR_NONFINITE, "non-finite residual");
+      // the Givens estimate stopped the cycle; the true residual decides:
+      // short of rtol, the next cycle starts from the true residual of x
+      R.converged = R.rel_residual <= rtol;
       if (!R.converged && R.iterations < max_total)
-        new_cycle();  // the next cycle starts from the true residual of x
+        new_cycle();
       else
         stage = kDone;
     }
@@ -1357,18 +1407,25 @@ FgmresResult fgmres(dgs_problem* P, const double* b, double* x, double rtol, int
 // definite preconditioner and stays usable with the V-cycle, which is not.
 // Per iteration: one operator application, one V-cycle, and one host round
 // trip (p.Ap, the dot products of z_{k+1} with both residuals and |r_{k+1}|^2
-// in one copy); alpha is formed on the device.  Stops when |r_k| <= rtol |r_0| (the recursive
-// residual); the returned residual is the true one.
+// in one copy); alpha is formed on the device.  A run stops when the
+// recursively updated residual drops to rtol |r_0|; the true residual then
+// decides: short of rtol (and with iterations left) CG starts again from the
+// true residual of x.  The returned residual is the true one.
+// ws: the work vectors (4 vectors of the fine level, reduction partials, the
+// device scalars and pinned host staging).
+struct CgWork {
+  double *R, *z, *p0, *p1, *q, *t, *partial, *h, *hp;
+};
+
 FgmresResult cg(dgs_problem* P, const double* b, double* x, double rtol, int max_iter,
-                hipStream_t s) {
+                hipStream_t s, const CgWork& ws) {
   const long long n = P->nd(0);
-  ensure_krylov(P, 4);
-  double* R = P->d_V;  // rows 0 and 1: r_k and r_{k+1}, alternating
-  double* z = P->d_Z;
-  double* pdir[2] = {P->d_Z + n, P->d_Z + 2 * n};  // p_k and p_{k+1}, alternating
-  double* q = P->d_tmp;
-  double* h = P->d_h;
-  double* hp = P->h_pinned;
+  double* R = ws.R;  // rows 0 and 1: r_k and r_{k+1}, alternating
+  double* z = ws.z;
+  double* pdir[2] = {ws.p0, ws.p1};  // p_k and p_{k+1}, alternating
+  double* q = ws.q;
+  double* h = ws.h;
+  double* hp = ws.hp;
   FgmresResult res;
   res.history.push_back(1.0);
   auto fetch = [&](int count) {
@@ -1377,56 +1434,77 @@ FgmresResult cg(dgs_problem* P, const double* b, double* x, double rtol, int max
     for (int i = 0; i < count; ++i)
       if (!std::isfinite(hp[i])) throw DgsError(DGS_ERR_NONFINITE, "non-finite value in CG");
   };
-  int cur = 0, pc = 0;
-  residual_fine(P, x, b, R, s);
-  vcycle(P, R, z, s);
-  HIP_OK(launch_copy(pdir[0], z, n, s));
-  HIP_OK(launch_multidot(R, n, 1, R, n, P->d_partial, h, s));
-  HIP_OK(launch_multidot(R, n, 1, z, n, P->d_partial, h + 1, s));
-  fetch(2);
-  const double nr0 = std::sqrt(hp[0]);
-  double rz = hp[1];
-  if (nr0 == 0.0) {
-    res.converged = true;
-    return res;
-  }
-  for (int k = 1; k <= max_iter; ++k) {
-    double* p = pdir[pc];
-    double* r = R + (size_t)cur * n;
-    double* r_next = R + (size_t)(1 - cur) * n;
-    apply_fine(P, p, q, s);
-    // p.Ap stays on the device: the update kernel forms alpha from it
-    HIP_OK(launch_multidot(p, n, 1, q, n, P->d_partial, h + 3, s));
-    HIP_OK(launch_cg_step(x, r_next, r, p, q, rz, h + 3, n, s));
-    res.iterations = k;
-    // z_{k+1} is computed before |r_{k+1}| is known: one V-cycle more than
-    // needed at the end, one host round trip per iteration
-    vcycle(P, r_next, z, s);
-    HIP_OK(launch_multidot(R, n, 2, z, n, P->d_partial, h, s));  // (r_0 row, z), (r_1 row, z)
-    HIP_OK(launch_multidot(r_next, n, 1, r_next, n, P->d_partial, h + 2, s));
-    fetch(4);
-    if (!(hp[3] > 0.0)) {  // A is not positive definite on p: stopped, not converged
-      res.iterations = k - 1;
-      break;
-    }
-    const double nr = std::sqrt(hp[2]);
-    res.history.push_back(nr / nr0);
-    if (nr <= rtol * nr0) {
+  double nr0 = -1.0;  // |r_0| of the first run: the reference of rtol
+  int k = 0;
+  for (;;) {  // runs, each from the true residual of x
+    int cur = 0, pc = 0;
+    residual_fine(P, x, b, R, s);
+    vcycle(P, R, z, s);
+    HIP_OK(launch_copy(pdir[0], z, n, s));
+    HIP_OK(launch_multidot(R, n, 1, R, n, ws.partial, h, s));
+    HIP_OK(launch_multidot(R, n, 1, z, n, ws.partial, h + 1, s));
+    fetch(2);
+    const double nr_start = std::sqrt(hp[0]);
+    if (nr0 < 0.0) nr0 = nr_start;
+    if (nr0 == 0.0) {
       res.converged = true;
-      break;
+      return res;
     }
-    const double rz_next = hp[1 - cur], zr_old = hp[cur];
-    const double beta = (rz_next - zr_old) / rz;
-    HIP_OK(launch_waxpy(pdir[1 - pc], z, beta, p, n, s));
-    rz = rz_next;
-    cur = 1 - cur;
-    pc = 1 - pc;
+    if (nr_start <= rtol * nr0) {  // the true residual of x already meets rtol
+      res.rel_residual = nr_start / nr0;
+      res.converged = true;
+      return res;
+    }
+    double rz = hp[1];
+    bool stopped = false, hit = false;
+    while (k < max_iter) {
+      ++k;
+      double* pv = pdir[pc];
+      double* r = R + (size_t)cur * n;
+      double* r_next = R + (size_t)(1 - cur) * n;
+      apply_fine(P, pv, q, s);
+      // p.Ap stays on the device: the update kernel forms alpha from it
+      HIP_OK(launch_multidot(pv, n, 1, q, n, ws.partial, h + 3, s));
+      HIP_OK(launch_cg_step(x, r_next, r, pv, q, rz, h + 3, n, s));
+      res.iterations = k;
+      // z_{k+1} is computed before |r_{k+1}| is known: one V-cycle more than
+      // needed at the end, one host round trip per iteration
+      vcycle(P, r_next, z, s);
+      HIP_OK(launch_multidot(R, n, 2, z, n, ws.partial, h, s));  // (r_0 row, z), (r_1 row, z)
+      HIP_OK(launch_multidot(r_next, n, 1, r_next, n, ws.partial, h + 2, s));
+      fetch(4);
+      if (!(hp[3] > 0.0)) {  // A is not positive definite on p: stopped, not converged
+        res.iterations = --k;
+        stopped = true;
+        break;
+      }
+      const double nr = std::sqrt(hp[2]);
+      res.history.push_back(nr / nr0);
+      if (nr <= rtol * nr0) {
+        hit = true;
+        break;
+      }
+      const double rz_next = hp[1 - cur], zr_old = hp[cur];
+      const double beta = (rz_next - zr_old) / rz;
+      HIP_OK(launch_waxpy(pdir[1 - pc], z, beta, pv, n, s));
+      rz = rz_next;
+      cur = 1 - cur;
+      pc = 1 - pc;
+    }
+    residual_fine(P, x, b, ws.t, s);
+    HIP_OK(launch_multidot(ws.t, n, 1, ws.t, n, ws.partial, h, s));
+    fetch(1);
+    res.rel_residual = std::sqrt(hp[0]) / nr0;
+    res.converged = res.rel_residual <= rtol;
+    if (res.converged || stopped || !hit || k >= max_iter) return res;
   }
-  residual_fine(P, x, b, P->d_tmp2, s);
-  HIP_OK(launch_multidot(P->d_tmp2, n, 1, P->d_tmp2, n, P->d_partial, h, s));
-  fetch(1);
-  res.rel_residual = std::sqrt(hp[0]) / nr0;
-  return res;
+}
+
+CgWork problem_cg_work(dgs_problem* P) {
+  ensure_krylov(P, 4);
+  const long long n = P->nd(0);
+  return CgWork{P->d_V, P->d_Z, P->d_Z + n, P->d_Z + 2 * n, P->d_tmp, P->d_tmp2,
+                P->d_partial, P->d_h, P->h_pinned};
 }
 
 // Newton-Raphson with a backtracking line search (Sec. III.A) as a resumable
@@ -1729,7 +1807,7 @@ struct dgs_server {
     for (RetiredMemory& m : retired) {
       if (m.prob) delete m.prob;
       for (double* d : {m.d_b, m.d_u, m.d_alpha, m.d_beta})
-        if (d) (void)hipFree(d);
+        if (d) dfree(d);
       used -= m.footprint;
     }
     retired.clear();
@@ -1740,7 +1818,7 @@ struct dgs_server {
       if (r->stream) (void)hipStreamSynchronize(r->stream);  // a stage may be in flight
       if (r->prob) delete r->prob;
       for (double* d : {r->d_b, r->d_u, r->d_alpha, r->d_beta})
-        if (d) (void)hipFree(d);
+        if (d) dfree(d);
       if (r->stream) (void)hipStreamDestroy(r->stream);
     }
     evict_idle(0);
@@ -1853,6 +1931,7 @@ std::vector<std::unique_ptr<ServerRequest>> server_select(dgs_server* S) {
       rq->stream = S->free_streams.back();
       S->free_streams.pop_back();
     } else {
+      std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
       HIP_OK(hipStreamCreateWithFlags(&rq->stream, hipStreamNonBlocking));
     }
     if (match >= 0) {
@@ -2009,6 +2088,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     build_inverses(P.get(), s);
     autotune_apply(P.get(), s);
     autotune_gemm(P.get(), s);
+    if (o.use_graphs) capture_vgraph(P.get(), 0);
     HIP_OK(hipStreamSynchronize(s));
     P->t_setup = now_s() - t0;
     *out = P.release();
@@ -2097,6 +2177,7 @@ int dgs_set_apply_shape(dgs_problem* prob, int level, int shape) {
     if (shape < -1 || shape > 2) return fail(DGS_ERR_INVALID, "unknown apply shape");
     if (shape == -1 && !L.d_bricks) return fail(DGS_ERR_INVALID, "bricks need p = 7");
     L.acfg = L.acfg_out = shape_config(L, shape);
+    recapture_vgraphs(prob);
     return DGS_OK;
   });
 }
@@ -2110,6 +2191,7 @@ int dgs_set_gemm_variant(dgs_problem* prob, int level, int variant) {
     Level& L = prob->levels[level];
     L.gemm_variant = variant;
     L.kparts = L.kparts_of[variant];
+    recapture_vgraphs(prob);
     return DGS_OK;
   });
 }
@@ -2159,7 +2241,8 @@ int dgs_cg_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats
     if (!prob || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
     if (b == u) return fail(DGS_ERR_INVALID, "b and u must not overlap");
     const double t0 = now_s();
-    FgmresResult R = cg(prob, b, u, prob->opt.rtol, prob->opt.max_iter, as_stream(stream));
+    FgmresResult R = cg(prob, b, u, prob->opt.rtol, prob->opt.max_iter, as_stream(stream),
+                        problem_cg_work(prob));
     fill_stats(stats, R, t0, prob->t_setup);
     if (stats) {
       stats->newton_steps = 0;
@@ -2216,6 +2299,37 @@ int dgs_lgl_nodes(int p, double* xi) {
     if (!xi || p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "need p in [1, 8] and xi");
     HostTables t = make_tables(p + 1);
     for (int i = 0; i <= p; ++i) xi[i] = t.xi[i];
+    return DGS_OK;
+  });
+}
+
+int dgs_grid_coordinates(const dgs_domain* domain, const int elements[3], int p, double* xyz,
+                         long long n) {
+  return guarded([&]() -> int {
+    if (!domain || !elements || !xyz) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p out of range");
+    for (int d = 0; d < 3; ++d)
+      if (elements[d] < 1 || !(domain->upper[d] > domain->lower[d]))
+        return fail(DGS_ERR_INVALID, "bad mesh");
+    const int N = p + 1;
+    const long long E = (long long)elements[0] * elements[1] * elements[2];
+    const long long nd = E * N * N * N;
+    if (n != nd) return fail(DGS_ERR_INVALID, "n must be the number of points E (p+1)^3");
+    const HostTables t = make_tables(N);
+    double h[3];
+    for (int d = 0; d < 3; ++d) h[d] = (domain->upper[d] - domain->lower[d]) / elements[d];
+    for (long long e = 0; e < E; ++e) {
+      const long long c[3] = {e % elements[0], (e / elements[0]) % elements[1],
+                              e / ((long long)elements[0] * elements[1])};
+      for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+          for (int i = 0; i < N; ++i) {
+            const long long idx = ((e * N + k) * N + j) * N + i;
+            const int node[3] = {i, j, k};
+            for (int d = 0; d < 3; ++d)
+              xyz[d * nd + idx] = domain->lower[d] + h[d] * ((double)c[d] + 0.5 * (t.xi[node[d]] + 1.0));
+          }
+    }
     return DGS_OK;
   });
 }

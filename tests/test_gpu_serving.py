@@ -141,7 +141,7 @@ def test_puncture_requests_in_a_mix_equal_newton_alone(precision):
                                          source=onewton.puncture_source(alpha, beta, v)
                                          .reshape(m.E, N, N, N))
         r0 = np.linalg.norm(F(np.zeros(m.ndof)))
-        assert np.linalg.norm(F(u)) / r0 <= 1.5e-10
+        assert np.linalg.norm(F(u)) / r0 <= 1e-10
     srv.close()
 
 
