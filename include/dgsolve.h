@@ -40,7 +40,7 @@ extern "C" {
 
 #define DGS_OK 0
 #define DGS_NOT_CONVERGED 1
-#define DGS_ERR_INVALID (-1)   /* bad argument: p outside [1,8], element count < 1,
+#define DGS_ERR_INVALID (-1)   /* bad argument: p outside [1,12], element count < 1,
                                   penalty <= 0, empty box, NULL pointer ...      */
 #define DGS_ERR_OOM (-2)       /* device allocation failed                       */
 #define DGS_ERR_HIP (-3)       /* a HIP runtime call or kernel launch failed     */
@@ -124,7 +124,7 @@ typedef void (*dgs_free_fn)(void* ptr, void* ctx);
  * (Sec. III.D.2, III.E.2), built on the device.
  *   domain    box; upper > lower in every dimension
  *   elements  n_x, n_y, n_z >= 1
- *   p         polynomial degree, 1..8 (N = p+1 points per dimension)
+ *   p         polynomial degree, 1..12 (N = p+1 points per dimension)
  *   penalty   C > 0 in sigma = C (p+1)^2 / h (eq. penalty)
  *   opt       NULL = defaults
  *   alloc_fn, free_fn, alloc_ctx
@@ -149,8 +149,9 @@ int dgs_node_coordinates(const dgs_problem* prob, double* xyz, void* stream);
 int dgs_apply_mass(const dgs_problem* prob, const double* f, double* b, void* stream);
 
 /* Au = A u: the left-hand side of eq. dg_op_primal for the Poisson fluxes
- * (eq. poisson_fluxform) with homogeneous Dirichlet boundaries.  u and Au must
- * not overlap. */
+ * (eq. poisson_fluxform) with homogeneous Dirichlet boundaries, homogeneous
+ * Neumann on the faces the options' neumann_faces names (eq. bc).  u and Au
+ * must not overlap. */
 int dgs_apply_operator(dgs_problem* prob, const double* u, double* Au, void* stream);
 
 /* u <- u + sum of `steps` additive Schwarz iterations on A u = b on the
@@ -280,6 +281,13 @@ typedef struct {
   int host_threads;        /* worker threads that issue and complete the active
                               requests' stages in parallel (launching is
                               host-bound for small requests); 0 = 4              */
+  dgs_alloc_fn alloc_fn;   /* device allocator of every request's memory (its
+                              problem and vectors), as in dgs_create_problem;  */
+  dgs_free_fn free_fn;     /* both NULL = hipMalloc / hipFree.  Called from the
+                              server's worker threads too, one at a time; a
+                              block is freed only after the device is done
+                              with it.                                          */
+  void* alloc_ctx;
 } dgs_server_options;
 
 int dgs_server_create(const dgs_server_options* opt, dgs_server** out);

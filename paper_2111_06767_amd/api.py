@@ -59,7 +59,9 @@ class Stats(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_double), ("max_active", ctypes.c_int),
-                ("penalty", ctypes.c_double), ("solver", Options), ("host_threads", ctypes.c_int)]
+                ("penalty", ctypes.c_double), ("solver", Options), ("host_threads", ctypes.c_int),
+                ("alloc_fn", ctypes.c_void_p), ("free_fn", ctypes.c_void_p),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class DgsError(RuntimeError):
@@ -180,16 +182,24 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 class TorchAllocator:
     """A problem's device workspace from PyTorch's caching allocator (the
-    dgs_alloc_fn / dgs_free_fn pair of dgs_create_problem).  `live` holds the
-    blocks handed out and not yet returned."""
+    dgs_alloc_fn / dgs_free_fn pair of dgs_create_problem).  Every block is
+    allocated on one stream, torch's current stream when the allocator is
+    made unless `stream` names another: the caching allocator only hands a
+    freed block out again once that stream's earlier work is done, so the
+    problem must run its work on that stream (pass the same stream to every
+    call, as Problem does by default).  `live` holds the blocks handed out and
+    not yet returned."""
 
-    def __init__(self):
+    def __init__(self, stream=None):
+        import torch
+        self.stream = torch.cuda.current_stream() if stream is None else stream
         self.live = {}
         self.allocated = 0
 
     def alloc(self, nbytes):
         import torch
-        ptr = torch.cuda.caching_allocator_alloc(int(nbytes))
+        ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.stream.device.index,
+                                                 self.stream)
         self.live[ptr] = int(nbytes)
         self.allocated += 1
         return ptr
@@ -386,7 +396,7 @@ class Server:
     """Continuous-batching solve server (see dgs_server_* in include/dgsolve.h)."""
 
     def __init__(self, hbm_budget_bytes=64e9, max_active=16, penalty=1.5, host_threads=0,
-                 **solver_opts):
+                 allocator=None, **solver_opts):
         lib = load_library()
         self._lib = lib
         o = ServerOptions()
@@ -395,6 +405,13 @@ class Server:
         o.penalty = float(penalty)
         o.host_threads = int(host_threads)
         o.solver = default_options(**solver_opts)
+        self.allocator = allocator
+        if allocator is not None:
+            # kept on the server: the library calls them until it is destroyed
+            self._alloc_cb = ALLOC_FN(lambda nbytes, ctx: allocator.alloc(nbytes))
+            self._free_cb = FREE_FN(lambda ptr, ctx: allocator.free(ptr))
+            o.alloc_fn = ctypes.cast(self._alloc_cb, ctypes.c_void_p)
+            o.free_fn = ctypes.cast(self._free_cb, ctypes.c_void_p)
         h = ctypes.c_void_p()
         _check(lib.dgs_server_create(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

@@ -68,11 +68,11 @@ __device__ __forceinline__ void face_from_line(const double (&x)[N], int side, d
   double acc = 0.0;
   if (side) {  // neighbour on the high side: its low face (layer 0)
 #pragma unroll
-    for (int m = 0; m < N; ++m) acc += T.D[m] * x[m];
+    for (int m = 0; m < N; ++m) acc += T.D0[m] * x[m];
     ue = x[0];
   } else {  // neighbour on the low side: its high face (layer N-1)
 #pragma unroll
-    for (int m = 0; m < N; ++m) acc += T.D[(N - 1) * N + m] * x[m];
+    for (int m = 0; m < N; ++m) acc += T.DN[m] * x[m];
     ue = x[N - 1];
   }
   ge = acc * rh;
@@ -520,7 +520,7 @@ hipError_t launch_apply_n(const ApplyConfig& cfg, int mode, const double* u, dou
                           const double* b, const double* aux0, const double* aux1, const int* nbr,
                           const OpParams& P, const DevTables& T, hipStream_t s, const int* order,
                           const GatherOut& go, double* ucopy) {
-  constexpr int def = (N == 2) ? 64 : (256 / (N * N));  // >= 3 for every N <= 9
+  constexpr int def = (N == 2) ? 64 : (256 / (N * N));  // >= 3 for N <= 9, 1 or 2 beyond
   if (cfg.bricks) {
     // bricks pay off only where one element fills a wavefront (N^2 = 64):
     // then every brick decision is wave-uniform
@@ -582,6 +582,10 @@ hipError_t launch_apply(int N, int mode, const double* u, double* out, const dou
     case 7: return launch_apply_n<7>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
     case 8: return launch_apply_n<8>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
     case 9: return launch_apply_n<9>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 10: return launch_apply_n<10>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 11: return launch_apply_n<11>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 12: return launch_apply_n<12>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
+    case 13: return launch_apply_n<13>(cfg, mode, u, out, b, aux0, aux1, nbr, P, T, s, order, go, ucopy);
     default: return hipErrorInvalidValue;
   }
 }

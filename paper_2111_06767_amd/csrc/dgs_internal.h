@@ -10,7 +10,7 @@
 
 namespace dgs {
 
-constexpr int kMaxN = 9;  // p <= 8
+constexpr int kMaxN = 13;  // p <= 12
 
 // ---------------------------------------------------------------------------
 // Host tables (LGL nodes/weights, derivative and child interpolation)
@@ -35,17 +35,26 @@ struct EvenOdd {
   double rc[kMaxN / 2];
 };
 
-// Kernel-argument copy of the tables (fixed size so one struct serves every N).
+// Kernel-argument copy of the tables the operator kernels read (fixed size
+// so one struct serves every N): nodes, weights, the first and last rows of
+// the derivative matrix (normal derivatives on the faces) and the even-odd
+// splits of D and D^T.
 struct DevTables {
   double xi[kMaxN];
   double w[kMaxN];
-  double D[kMaxN * kMaxN];
-  double Plo[kMaxN * kMaxN];
-  double Phi[kMaxN * kMaxN];
+  double D0[kMaxN];  // D[0][m]
+  double DN[kMaxN];  // D[N-1][m]
   EvenOdd fwd;  // D
   EvenOdd bwd;  // D^T
 };
 DevTables to_dev(const HostTables& t);
+// Kernel-argument copy of the child interpolation matrices (multigrid
+// transfer kernels only).
+struct MgTables {
+  double Plo[kMaxN * kMaxN];
+  double Phi[kMaxN * kMaxN];
+};
+MgTables to_dev_mg(const HostTables& t);
 
 // Geometry of one uniform box level.
 struct OpParams {
@@ -245,10 +254,12 @@ hipError_t launch_reduce_parts(bool f32, void* out, const void* parts_base, int 
 hipError_t launch_sub_start(bool f32, const void* rs, void* V0, double* beta,
                             const int* elem_class, const long long* elem_row, const ClassInfo* cls,
                             int E, hipStream_t s);
+// (max_n: the largest subdomain of the level, at most 4352 points)
 hipError_t launch_sub_arnoldi(int N, bool f32, int j, int kmax, const void* W, void* V, const void* Zj,
                               long long stride, const double* diag, double* H,
                               const int* elem_class, const long long* elem_row, const int* nbr,
-                              const ClassInfo* cls, const int* seg_loc, int E, hipStream_t s);
+                              const ClassInfo* cls, const int* seg_loc, int E, int max_n,
+                              hipStream_t s);
 hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride, const double* H,
                              const double* beta, void* du, const int* elem_class,
                              const long long* elem_row, const ClassInfo* cls, int E, hipStream_t s);
@@ -263,10 +274,10 @@ hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
 
 // Multigrid transfer (per-dimension split flags).
 hipError_t launch_restrict(int N, const double* fine, double* coarse, const int nf[3],
-                           const int nc[3], const int split[3], const DevTables& T, hipStream_t s,
+                           const int nc[3], const int split[3], const MgTables& T, hipStream_t s,
                            const GatherOut& go = GatherOut{});  // go: also the coarse r_S rows
 hipError_t launch_prolongate_add(int N, const double* coarse, double* fine, const int nf[3],
-                                 const int nc[3], const int split[3], const DevTables& T,
+                                 const int nc[3], const int split[3], const MgTables& T,
                                  hipStream_t s);
 
 // Vector kernels.

@@ -276,7 +276,9 @@ __device__ __forceinline__ double block_reduce_sum(double v, double* red) {
 }
 
 constexpr int kSubThreads = 256;
-constexpr int kSubPer = 8;  // points per thread: n_S <= 2048
+// points per thread of the Arnoldi step: n_S <= 2048 (p <= 8) or <= 4352
+// (p <= 12, n_S <= 4225)
+constexpr int kSubPerSmall = 8, kSubPerLarge = 17;
 
 template <typename T>
 __global__ void __launch_bounds__(kSubThreads)
@@ -299,7 +301,7 @@ k_sub_start(const T* __restrict__ rs, T* __restrict__ V0, double* __restrict__ b
     V0[row + i] = b > 0.0 ? (T)((double)rs[row + i] / b) : (T)0;
 }
 
-template <typename T>
+template <typename T, int kSubPer>
 __global__ void __launch_bounds__(kSubThreads)
 k_sub_arnoldi(int j, int kmax, const T* __restrict__ W, T* __restrict__ V, const T* __restrict__ Zj,
               long long stride, const double* __restrict__ diag, double* __restrict__ H,
@@ -459,16 +461,27 @@ hipError_t launch_sub_start(bool f32, const void* rs, void* V0, double* beta,
 hipError_t launch_sub_arnoldi(int N, bool f32, int j, int kmax, const void* W, void* V, const void* Zj,
                               long long stride, const double* diag, double* H,
                               const int* elem_class, const long long* elem_row, const int* nbr,
-                              const ClassInfo* cls, const int* seg_loc, int E, hipStream_t s) {
+                              const ClassInfo* cls, const int* seg_loc, int E, int max_n,
+                              hipStream_t s) {
   if (E <= 0) return hipSuccess;
-  if (f32)
-    hipLaunchKernelGGL(k_sub_arnoldi<float>, dim3(E), dim3(kSubThreads), 0, s, j, kmax,
-                       (const float*)W, (float*)V, (const float*)Zj, stride, diag, H, elem_class,
-                       elem_row, nbr, cls, seg_loc, E, N);
-  else
-    hipLaunchKernelGGL(k_sub_arnoldi<double>, dim3(E), dim3(kSubThreads), 0, s, j, kmax,
-                       (const double*)W, (double*)V, (const double*)Zj, stride, diag, H, elem_class,
-                       elem_row, nbr, cls, seg_loc, E, N);
+  if (max_n > kSubThreads * kSubPerLarge) return hipErrorInvalidValue;
+  const bool large = max_n > kSubThreads * kSubPerSmall;
+#define DGS_ARNOLDI(T, PER)                                                                     \
+  hipLaunchKernelGGL((k_sub_arnoldi<T, PER>), dim3(E), dim3(kSubThreads), 0, s, j, kmax,         \
+                     (const T*)W, (T*)V, (const T*)Zj, stride, diag, H, elem_class, elem_row, nbr, \
+                     cls, seg_loc, E, N)
+  if (f32) {
+    if (large)
+      DGS_ARNOLDI(float, kSubPerLarge);
+    else
+      DGS_ARNOLDI(float, kSubPerSmall);
+  } else {
+    if (large)
+      DGS_ARNOLDI(double, kSubPerLarge);
+    else
+      DGS_ARNOLDI(double, kSubPerSmall);
+  }
+#undef DGS_ARNOLDI
   return hipGetLastError();
 }
 

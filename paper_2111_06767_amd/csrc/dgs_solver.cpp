@@ -226,6 +226,7 @@ struct dgs_problem {
   dgs_domain dom{};
   HostTables ht;
   DevTables dt{};
+  MgTables mt{};
   std::vector<Level> levels;
   std::vector<void*> allocations;
   // the caller's device allocator (null: hipMalloc / hipFree)
@@ -758,7 +759,7 @@ std::map<std::tuple<int, long long, int, int, int, int>, int> g_tuned_epb;
 ApplyConfig shape_config(const Level& L, int shape) {
   ApplyConfig c;
   c.epb = shape;
-  c.bricks = shape < 0 ? L.d_bricks : nullptr;
+  c.bricks = shape == -1 ? L.d_bricks : nullptr;
   return c;
 }
 
@@ -827,8 +828,8 @@ void autotune_apply(dgs_problem* P, hipStream_t s) {
       const float tune_ms = L.E >= 512 ? 0.5f : 0.1f;
       const int tune_trials = L.E >= 512 ? 5 : 3;
       // elements per workgroup; -1: 2 x 2 x 2 bricks
-      const int cands[4] = {1, 2, 0, -1};
-      const int ncand = L.d_bricks ? 4 : 3;
+      int cands[4] = {1, 2, 0}, ncand = 3;
+      if (L.d_bricks) cands[ncand++] = -1;
       int best = cands[0];
       float best_ms = 1e30f;
       for (int ci = 0; ci < ncand; ++ci) {
@@ -937,7 +938,7 @@ void subdomain_gmres(dgs_problem* P, Level& L, hipStream_t s) {
     HIP_OK(launch_reduce_parts(L.f32, L.d_gW, L.d_du, L.kparts, st, st, s));
     HIP_OK(launch_sub_arnoldi(N, L.f32, j, k, L.d_gW, L.d_gV, Zj, st, L.d_diag, L.d_gH,
                               L.d_elem_class, L.d_elem_row, L.d_nbr, L.d_cls, L.d_seg_loc, (int)L.E,
-                              s));
+                              L.max_n, s));
   }
   HIP_OK(launch_sub_finish(L.f32, k, L.d_gZ, st, L.d_gH, L.d_gbeta, L.d_du, L.d_elem_class,
                            L.d_elem_row, L.d_cls, (int)L.E, s));
@@ -1008,13 +1009,13 @@ void mg_visit(dgs_problem* P, int l, const std::vector<const double*>& b,
                       L.d_nbr, L.op, P->dt, L.acfg_out, s, L.d_order));
   Level& C = P->levels[l + 1];
   // the restriction also writes the coarse level's first r_S rows
-  HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
+  HIP_OK(launch_restrict(N, L.d_r, C.d_b, L.n, C.n, L.split, P->mt, s, level_gather(P, C)));
   // V: one V-visit; W: two W-visits; F: an F-visit, then a V-visit
   const int visits[2] = {kind, kind == 3 ? 1 : kind};
   const int nvisits = kind == 1 ? 1 : 2;
   for (int visit = 0; visit < nvisits; ++visit)
     mg_visit(P, l + 1, b, u, visit == 0, visit == 0, coarse_steps, visits[visit], s);
-  HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->dt, s));
+  HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->mt, s));
   schwarz_steps(P, l, b[l], u[l], P->opt.post_smooth, false, s);
 }
 
@@ -1048,7 +1049,7 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
   for (int l = 0; l + 1 < nl; ++l) {
     Level& L = P->levels[l];
     Level& C = P->levels[l + 1];
-    HIP_OK(launch_restrict(N, b[l], C.d_b, L.n, C.n, L.split, P->dt, s, level_gather(P, C)));
+    HIP_OK(launch_restrict(N, b[l], C.d_b, L.n, C.n, L.split, P->mt, s, level_gather(P, C)));
   }
   for (int l = 0; l < nl; ++l) {
     const int steps = l < nl - 1 ? P->opt.pre_smooth + P->opt.post_smooth : coarse_steps;
@@ -1058,7 +1059,7 @@ void vcycle_eager(dgs_problem* P, const double* r, double* z, hipStream_t s,
   for (int l = nl - 2; l >= 0; --l) {
     Level& L = P->levels[l];
     Level& C = P->levels[l + 1];
-    HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->dt, s));
+    HIP_OK(launch_prolongate_add(N, u[l + 1], u[l], L.n, C.n, L.split, P->mt, s));
   }
 }
 
@@ -1185,8 +1186,8 @@ void set_diagonal(dgs_problem* P, const double* d, hipStream_t s) {
   for (Level& L : P->levels) {
     if (!L.d_diag) L.d_diag = P->alloc<double>(L.E * (long long)P->N * P->N * P->N);
     if (k > 0 && L.gk < k) {
-      if (L.max_n > 2048)
-        throw DgsError(DGS_ERR_INVALID, "subdomain GMRES supports subdomains of at most 2048 points");
+      if (L.max_n > 4352)
+        throw DgsError(DGS_ERR_INVALID, "subdomain GMRES supports subdomains of at most 4352 points");
       const size_t es = L.f32 ? sizeof(float) : sizeof(double);
       L.d_gV = P->alloc<char>(es * (size_t)L.rs_total * (k + 1));
       L.d_gZ = P->alloc<char>(es * (size_t)L.rs_total * k);
@@ -1203,7 +1204,7 @@ void set_diagonal(dgs_problem* P, const double* d, hipStream_t s) {
   for (size_t l = 0; l + 1 < P->levels.size(); ++l) {
     Level& L = P->levels[l];
     Level& C = P->levels[l + 1];
-    HIP_OK(launch_restrict(P->N, L.d_diag, C.d_diag, L.n, C.n, L.split, P->dt, s));
+    HIP_OK(launch_restrict(P->N, L.d_diag, C.d_diag, L.n, C.n, L.split, P->mt, s));
   }
   P->diag_active = true;
   if (P->opt.use_graphs && !P->vgraph[1]) capture_vgraph(P, 1);
@@ -1775,6 +1776,25 @@ struct RetiredMemory {
 
 struct dgs_server {
   dgs_server_options opt{};
+  // the requests' own vectors (b, u, puncture fields) from the caller's
+  // allocator when one is given, else hipMalloc
+  double* vec(size_t n) {
+    if (!opt.alloc_fn) return dalloc<double>(n);
+    std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+    void* p = opt.alloc_fn(std::max<size_t>(n, 1) * sizeof(double), opt.alloc_ctx);
+    if (!p) throw DgsError(DGS_ERR_OOM, "the caller's allocator returned NULL");
+    return static_cast<double*>(p);
+  }
+  // released only after the device has finished with it
+  void vec_free(double* p) {
+    if (!p) return;
+    if (!opt.alloc_fn) {
+      dfree(p);
+      return;
+    }
+    std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+    opt.free_fn(p, opt.alloc_ctx);
+  }
   int device = 0;
   std::unique_ptr<WorkerPool> pool;  // launching is host-bound: stages run in parallel
   long long next_id = 1;
@@ -1804,10 +1824,11 @@ struct dgs_server {
     }
   }
   void free_retired() {
+    // a caller's allocator may hand the memory out at once (hipFree waits by itself)
+    if (opt.alloc_fn && !retired.empty()) (void)hipDeviceSynchronize();
     for (RetiredMemory& m : retired) {
       if (m.prob) delete m.prob;
-      for (double* d : {m.d_b, m.d_u, m.d_alpha, m.d_beta})
-        if (d) dfree(d);
+      for (double* d : {m.d_b, m.d_u, m.d_alpha, m.d_beta}) vec_free(d);
       used -= m.footprint;
     }
     retired.clear();
@@ -1817,8 +1838,7 @@ struct dgs_server {
     for (auto& r : active) {
       if (r->stream) (void)hipStreamSynchronize(r->stream);  // a stage may be in flight
       if (r->prob) delete r->prob;
-      for (double* d : {r->d_b, r->d_u, r->d_alpha, r->d_beta})
-        if (d) dfree(d);
+      for (double* d : {r->d_b, r->d_u, r->d_alpha, r->d_beta}) vec_free(d);
       if (r->stream) (void)hipStreamDestroy(r->stream);
     }
     evict_idle(0);
@@ -1850,11 +1870,12 @@ void server_setup(dgs_server* S, ServerRequest& r) {
   if (!r.reused) {
     dgs_problem* created = nullptr;
     const int code = dgs_create_problem(&r.dom, r.elements, r.p, S->opt.penalty, &S->opt.solver,
-                                        nullptr, nullptr, nullptr, r.stream, &created);
+                                        S->opt.alloc_fn, S->opt.free_fn, S->opt.alloc_ctx,
+                                        r.stream, &created);
     if (code != DGS_OK) throw DgsError(code, g_last_error);
     r.prob = created;
-    r.d_b = dalloc<double>(created->nd(0));
-    r.d_u = dalloc<double>(created->nd(0));
+    r.d_b = S->vec(created->nd(0));
+    r.d_u = S->vec(created->nd(0));
   }
   dgs_problem* prob = r.prob;
   const long long n = prob->nd(0);
@@ -1868,8 +1889,8 @@ void server_setup(dgs_server* S, ServerRequest& r) {
   } else {
     // the puncture equation: alpha, beta and b (zero when not given) to the
     // device, u0 = 0, and the first nonlinear residual
-    r.d_alpha = dalloc<double>(n);
-    r.d_beta = dalloc<double>(n);
+    r.d_alpha = S->vec(n);
+    r.d_beta = S->vec(n);
     HIP_OK(hipMemcpyAsync(r.d_alpha, r.alpha.data(), sizeof(double) * n, hipMemcpyHostToDevice,
                           r.stream));
     HIP_OK(hipMemcpyAsync(r.d_beta, r.beta.data(), sizeof(double) * n, hipMemcpyHostToDevice,
@@ -2024,7 +2045,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     if (!domain || !elements || !out) return fail(DGS_ERR_INVALID, "NULL argument");
     *out = nullptr;
     if (!alloc_fn != !free_fn) return fail(DGS_ERR_INVALID, "alloc_fn and free_fn go together");
-    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 8]");
+    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 12]");
     if (!(penalty > 0.0) || !std::isfinite(penalty)) return fail(DGS_ERR_INVALID, "penalty must be > 0");
     for (int d = 0; d < 3; ++d) {
       if (elements[d] < 1) return fail(DGS_ERR_INVALID, "element counts must be >= 1");
@@ -2057,6 +2078,7 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
     P->dom = *domain;
     P->ht = make_tables(P->N);
     P->dt = to_dev(P->ht);
+    P->mt = to_dev_mg(P->ht);
     // hierarchy (Sec. III.C.1): halve every even element count > 1
     int n[3] = {elements[0], elements[1], elements[2]};
     const int max_levels = o.mg_levels > 0 ? o.mg_levels : 64;
@@ -2296,7 +2318,7 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
 
 int dgs_lgl_nodes(int p, double* xi) {
   return guarded([&]() -> int {
-    if (!xi || p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "need p in [1, 8] and xi");
+    if (!xi || p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "need p in [1, 12] and xi");
     HostTables t = make_tables(p + 1);
     for (int i = 0; i <= p; ++i) xi[i] = t.xi[i];
     return DGS_OK;
@@ -2340,6 +2362,8 @@ int dgs_server_create(const dgs_server_options* opt, dgs_server** out) {
     if (opt->max_active < 1 || !(opt->hbm_budget_bytes > 0) || !(opt->penalty > 0))
       return fail(DGS_ERR_INVALID, "invalid server options");
     if (opt->host_threads < 0) return fail(DGS_ERR_INVALID, "host_threads must be >= 0");
+    if (!opt->alloc_fn != !opt->free_fn)
+      return fail(DGS_ERR_INVALID, "alloc_fn and free_fn go together");
     std::unique_ptr<dgs_server> S(new dgs_server());
     S->opt = *opt;
     S->t0 = now_s();
@@ -2365,7 +2389,7 @@ int dgs_server_submit(dgs_server* S, const dgs_domain* domain, const int element
                       const double* f, long long n, long long* id) {
   return guarded([&]() -> int {
     if (!S || !domain || !elements || !f || !id) return fail(DGS_ERR_INVALID, "NULL argument");
-    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 8]");
+    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 12]");
     for (int d = 0; d < 3; ++d)
       if (elements[d] < 1 || !(domain->upper[d] > domain->lower[d]))
         return fail(DGS_ERR_INVALID, "bad mesh");
@@ -2392,7 +2416,7 @@ int dgs_server_submit_puncture(dgs_server* S, const dgs_domain* domain, const in
   return guarded([&]() -> int {
     if (!S || !domain || !elements || !alpha || !beta || !id)
       return fail(DGS_ERR_INVALID, "NULL argument");
-    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 8]");
+    if (p < 1 || p > kMaxN - 1) return fail(DGS_ERR_INVALID, "p must be in [1, 12]");
     for (int d = 0; d < 3; ++d)
       if (elements[d] < 1 || !(domain->upper[d] > domain->lower[d]))
         return fail(DGS_ERR_INVALID, "bad mesh");

@@ -143,8 +143,17 @@ DevTables to_dev(const HostTables& t) {
     d.xi[i] = t.xi[i];
     d.w[i] = t.w[i];
   }
-  for (int i = 0; i < N * N; ++i) {
-    d.D[i] = t.D[i];
+  for (int m = 0; m < N; ++m) {
+    d.D0[m] = t.D[m];
+    d.DN[m] = t.D[(N - 1) * N + m];
+  }
+  return d;
+}
+
+MgTables to_dev_mg(const HostTables& t) {
+  MgTables d;
+  std::memset(&d, 0, sizeof(d));
+  for (int i = 0; i < t.N * t.N; ++i) {
     d.Plo[i] = t.Plo[i];
     d.Phi[i] = t.Phi[i];
   }

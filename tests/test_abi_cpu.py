@@ -40,7 +40,7 @@ def test_default_options_and_invalid_arguments_without_gpu():
     # argument validation happens before any device call
     dom = m.api.Domain((ctypes.c_double * 3)(0, 0, 0), (ctypes.c_double * 3)(1, 1, 1))
     h = ctypes.c_void_p()
-    for el, p, C in [((0, 1, 1), 3, 1.5), ((1, 1, 1), 0, 1.5), ((1, 1, 1), 9, 1.5), ((1, 1, 1), 3, 0.0)]:
+    for el, p, C in [((0, 1, 1), 3, 1.5), ((1, 1, 1), 0, 1.5), ((1, 1, 1), 13, 1.5), ((1, 1, 1), 3, 0.0)]:
         code = lib.dgs_create_problem(ctypes.byref(dom), (ctypes.c_int * 3)(*el), p, C,
                                       ctypes.byref(o), m.api.ALLOC_FN(), m.api.FREE_FN(), None,
                                       None, ctypes.byref(h))

@@ -168,3 +168,28 @@ def test_reused_problems_give_the_bits_of_fresh_ones(precision):
         assert st["converged"] and st["iterations"] == st1["iterations"]
         assert np.array_equal(u, u1), (el, p)
     srv.close()
+
+
+def test_server_memory_from_the_callers_allocator():
+    """With an allocator the server takes every request's device memory
+    (problem workspaces and vectors) from it, gives the bits of the server
+    without one, and returns every block."""
+    import torch
+    import paper_2111_06767_amd as dg
+    announce("serving with the torch allocator")
+    results = []
+    alloc = dg.TorchAllocator()
+    for allocator in (None, alloc):
+        srv = dg.Server(hbm_budget_bytes=32e9, max_active=3, precision="mixed", max_iter=60,
+                        host_threads=2, allocator=allocator)
+        ids = []
+        for i, (el, p, side) in enumerate(REQS[:4]):
+            ids.append(srv.submit((0, 0, 0), (side,) * 3, el, p, _f(el, p, side, 1000 + i)))
+        while srv.step() != (0, 0):
+            pass
+        results.append([srv.fetch(rid)[0] for rid in ids])
+        srv.close()
+    torch.cuda.synchronize()
+    assert alloc.allocated > 0 and not alloc.live
+    for a, b in zip(*results):
+        assert np.array_equal(a, b)

@@ -29,7 +29,7 @@ def test_closed_form_nodes_and_weights(golden_dir):
         np.testing.assert_allclose(lgl.weights(N), w, atol=1e-15)
 
 
-@pytest.mark.parametrize("N", range(2, 12))
+@pytest.mark.parametrize("N", range(2, 14))
 def test_weights_sum_and_endpoint(N):
     w = lgl.weights(N)
     p = N - 1
@@ -38,7 +38,7 @@ def test_weights_sum_and_endpoint(N):
     assert abs(w[-1] - 2.0 / (p * (p + 1))) < 1e-15
 
 
-@pytest.mark.parametrize("N", range(2, 12))
+@pytest.mark.parametrize("N", range(2, 14))
 def test_quadrature_exact_to_degree_2N_minus_3(N):
     # an N-point rule that contains both endpoints and integrates all
     # polynomials of degree <= 2N-3 exactly is the LGL rule (unique)
@@ -48,10 +48,10 @@ def test_quadrature_exact_to_degree_2N_minus_3(N):
         assert abs(np.dot(w, x ** k) - exact) < 1e-13
     # and not degree 2N-2
     k = 2 * N - 2
-    assert abs(np.dot(w, x ** k) - 2.0 / (k + 1)) > 1e-6
+    assert abs(np.dot(w, x ** k) - 2.0 / (k + 1)) > 1e-10
 
 
-@pytest.mark.parametrize("N", range(2, 12))
+@pytest.mark.parametrize("N", range(2, 14))
 def test_diff_matrix_exact_on_polynomials(N):
     x = lgl.nodes(N)
     D = lgl.diff_matrix(N)
@@ -60,7 +60,7 @@ def test_diff_matrix_exact_on_polynomials(N):
         np.testing.assert_allclose(D @ x ** k, d, atol=1e-12 * max(1, k))
 
 
-@pytest.mark.parametrize("N", range(2, 12))
+@pytest.mark.parametrize("N", range(2, 14))
 def test_summation_by_parts(N):
     # W D + D^T W = diag(-1, 0, ..., 0, 1) because LGL quadrature is exact
     # for the degree-(2N-3) products l_i l_j'
@@ -70,7 +70,7 @@ def test_summation_by_parts(N):
     np.testing.assert_allclose(W @ D + D.T @ W, B, atol=1e-12)
 
 
-@pytest.mark.parametrize("N", range(2, 10))
+@pytest.mark.parametrize("N", range(2, 14))
 def test_child_interpolation_reproduces_polynomials(N):
     x = lgl.nodes(N)
     P_lo, P_hi = lgl.child_interpolation(N)

@@ -100,7 +100,8 @@ def test_symmetric_positive_definite(n, p, size, C):
     np.linalg.cholesky(A)  # raises if not SPD
 
 
-@pytest.mark.parametrize("n,p", [((2, 2, 2), 2), ((3, 2, 1), 3), ((2, 3, 2), 4), ((1, 1, 2), 6)])
+@pytest.mark.parametrize("n,p", [((2, 2, 2), 2), ((3, 2, 1), 3), ((2, 3, 2), 4), ((1, 1, 2), 6),
+                                 ((2, 1, 1), 9), ((1, 2, 1), 10), ((1, 1, 2), 11), ((2, 1, 1), 12)])
 def test_polynomial_reproduction(n, p):
     # u = prod x_d (L_d - x_d) is continuous, in Q_p for p >= 2 and zero on the
     # boundary: every jump vanishes, so A u_I = M (-Laplace u)_I exactly
@@ -178,3 +179,11 @@ def test_mixed_dirichlet_neumann_manufactured_solution_converges():
         uh = np.linalg.solve(A, operator.apply_mass(m, f).reshape(-1))
         errs.append(np.abs(uh - u.reshape(-1)).max())
     assert errs[-1] < 1e-3 and all(b < a / 3 for a, b in zip(errs, errs[1:])), errs
+
+
+def test_high_order_operator_is_symmetric_positive_definite():
+    # p = 10 (11^3 points per element) on two elements of unequal widths
+    m = mesh.BoxMesh([0, 0, 0], [1.0, 0.6, 0.8], (2, 1, 1), 10)
+    A = operator.assemble(m, 1.5)
+    assert np.abs(A - A.T).max() <= 1e-12 * np.abs(A).max()
+    np.linalg.cholesky(A)
