@@ -180,6 +180,23 @@ int dgs_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, v
  * overlap; the call synchronises the stream once per iteration. */
 int dgs_cg_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream);
 
+/* dgs_cg_solve without device allocation, for callers that cannot allocate
+ * device memory at the call (tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments, arithmetic and results as dgs_cg_solve, but the
+ * CG work vectors, reduction partials and device scalars live in a static
+ * device workspace of the library instead of the problem's lazily allocated
+ * Krylov buffers, and the few convergence scalars are staged through static
+ * host memory.  The problem itself (created beforehand) supplies the
+ * multigrid hierarchy and the captured V-cycle.  Limit: the fine level may
+ * have at most 1,048,576 points (E (p+1)^3); larger problems get
+ * DGS_ERR_INVALID.  The workspace (about 56 MiB) exists once per GPU for the
+ * life of the process and is shared by every call on that GPU: calls that
+ * overlap on one GPU (from two host threads, or on two streams) race and must
+ * not be made.  Nothing in the workspace needs to start at zero: every entry
+ * is written before it is read. */
+int dgs_cg_solve_noalloc(dgs_problem* prob, const double* b, double* u, dgs_stats* stats,
+                         void* stream);
+
 /* Add a pointwise term: subsequent dgs_schwarz_smooth, dgs_precondition and
  * dgs_solve act on A + diag(d) (d a device field in the nodal layout, e.g. the
  * mass-weighted derivative M S'(u) of a nonlinear source, eq. linearized);

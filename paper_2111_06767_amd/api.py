@@ -32,6 +32,7 @@ EXPORTED = (
     "dgs_server_step", "dgs_server_finished", "dgs_server_fetch", "dgs_subdomain_solves",
     "dgs_set_apply_shape", "dgs_get_apply_shape", "dgs_set_gemm_variant", "dgs_get_gemm_variant",
     "dgs_server_submit_puncture", "dgs_cg_solve", "dgs_grid_coordinates",
+    "dgs_cg_solve_noalloc",
 )
 
 
@@ -102,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_set_diagonal.argtypes = [P, dp, P]
     lib.dgs_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
     lib.dgs_cg_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
+    lib.dgs_cg_solve_noalloc.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
     lib.dgs_newton_solve.argtypes = [P, dp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.POINTER(Stats), P]
     lib.dgs_lgl_nodes.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
@@ -340,6 +342,15 @@ class Problem:
         code = _check(self._lib.dgs_cg_solve(self._h, _ptr(b, self.ndof, "b"),
                                              _ptr(u, self.ndof, "u"), ctypes.byref(st),
                                              _stream(stream)), allow_not_converged=True)
+        return u, _stats_dict(st, hist, code)
+
+    def solve_cg_noalloc(self, b, u, history=256, stream=None):
+        """dgs_cg_solve_noalloc: the CG solve with the library's static device
+        workspace (no device allocation in the call).  Returns (u, stats dict)."""
+        st, hist = _make_stats(history)
+        code = _check(self._lib.dgs_cg_solve_noalloc(self._h, _ptr(b, self.ndof, "b"),
+                                                     _ptr(u, self.ndof, "u"), ctypes.byref(st),
+                                                     _stream(stream)), allow_not_converged=True)
         return u, _stats_dict(st, hist, code)
 
     def newton_solve(self, alpha, beta, b=None, u=None, newton_rtol=1e-10, linear_rtol=1e-4,

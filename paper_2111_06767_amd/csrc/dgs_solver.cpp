@@ -1501,6 +1501,33 @@ FgmresResult cg(dgs_problem* P, const double* b, double* x, double rtol, int max
   }
 }
 
+// Static device workspace of dgs_cg_solve_noalloc: the CG work vectors of
+// a fine level of at most kNoAllocMaxDofs points (6 vectors, each starting on
+// a 256-byte boundary), the reduction partials and the device scalars.
+// Every GPU the library runs on holds its own copy until the process ends.
+constexpr long long kNoAllocMaxDofs = 1LL << 20;
+constexpr long long kNoAllocPartials = 2048;  // multidot_blocks(n) <= 1024, two dots
+constexpr long long kNoAllocDoubles = 7 * kNoAllocMaxDofs + kNoAllocPartials + 64;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};     // device address of `scratch`, per device
+double g_scratch_host[kMaxDevices][8] = {};  // host staging of the reduction results
+
+// The current device's address of `scratch` (looked up once per device).
+double* scratch_for_current_device(int* device) {
+  HIP_OK(hipGetDevice(device));
+  if (*device < 0 || *device >= kMaxDevices) throw DgsError(DGS_ERR_INVALID, "device id out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mutex);
+  if (!g_scratch_ptr[*device]) {
+    void* ptr = nullptr;
+    HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[*device] = static_cast<double*>(ptr);
+  }
+  return g_scratch_ptr[*device];
+}
+
 CgWork problem_cg_work(dgs_problem* P) {
   ensure_krylov(P, 4);
   const long long n = P->nd(0);
@@ -2265,6 +2292,41 @@ int dgs_cg_solve(dgs_problem* prob, const double* b, double* u, dgs_stats* stats
     const double t0 = now_s();
     FgmresResult R = cg(prob, b, u, prob->opt.rtol, prob->opt.max_iter, as_stream(stream),
                         problem_cg_work(prob));
+    fill_stats(stats, R, t0, prob->t_setup);
+    if (stats) {
+      stats->newton_steps = 0;
+      stats->backtracks = 0;
+    }
+    if (!std::isfinite(R.rel_residual)) return fail(DGS_ERR_NONFINITE, "non-finite residual");
+    return R.converged ? DGS_OK : DGS_NOT_CONVERGED;
+  });
+}
+
+int dgs_cg_solve_noalloc(dgs_problem* prob, const double* b, double* u, dgs_stats* stats,
+                         void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (b == u) return fail(DGS_ERR_INVALID, "b and u must not overlap");
+    const long long n = prob->nd(0);
+    if (n > kNoAllocMaxDofs)
+      return fail(DGS_ERR_INVALID, "dgs_cg_solve_noalloc: the problem has " + std::to_string(n) +
+                                       " points, more than its static workspace holds (" +
+                                       std::to_string(kNoAllocMaxDofs) + ")");
+    int device = 0;
+    double* base = scratch_for_current_device(&device);
+    const long long ld = (n + 31) / 32 * 32;  // each vector on a 256-byte boundary
+    CgWork w;
+    w.R = base;  // two rows
+    w.z = base + 2 * ld;
+    w.p0 = base + 3 * ld;
+    w.p1 = base + 4 * ld;
+    w.q = base + 5 * ld;
+    w.t = base + 6 * ld;
+    w.partial = base + 7 * kNoAllocMaxDofs;
+    w.h = w.partial + kNoAllocPartials;
+    w.hp = g_scratch_host[device];
+    const double t0 = now_s();
+    FgmresResult R = cg(prob, b, u, prob->opt.rtol, prob->opt.max_iter, as_stream(stream), w);
     fill_stats(stats, R, t0, prob->t_setup);
     if (stats) {
       stats->newton_steps = 0;
