@@ -185,6 +185,18 @@ def cpu_child():
         key = f"c3_{prec}"
         if key in data:
             checks[f"c3_{prec}_oracle_rel_nonlinear_residual"] = float(np.linalg.norm(F3(data[key])) / r30)
+    served = []
+    reqs = W.request_stream(256, rate=1.0)
+    for key in sorted(k for k in data.files if k.startswith("serve_")):
+        r = reqs[int(key.split("_")[1])]
+        ms = mesh.BoxMesh((0, 0, 0), (r.side,) * 3, r.elements, r.p)
+        xs, ys, zs = ms.node_coordinates()
+        fs = W.fourier_source(W.fourier_modes(r.seed, (0, 0, 0), (r.side,) * 3), xs, ys, zs)
+        bs = operator.apply_mass(ms, fs).reshape(-1)
+        served.append(float(np.linalg.norm(bs - A(ms)(data[key])) / np.linalg.norm(bs)))
+    if served:
+        checks["served_sample_oracle_rel_residual_max"] = max(served)
+        checks["served_sample_size"] = len(served)
     log("oracle checks of the GPU solutions done; timing one V-cycle + apply")
 
     def one_pass():
@@ -403,11 +415,15 @@ def newton_leg(dg, precision, steps=10, warmup=2):
     return out, un
 
 
-def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threads=0):
+def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threads=0,
+                batched=True, paced=True, keep=8):
     """Poisson-process stream of solves (grids {2..6}^3, p in 3..8, cube sides
     1..4, random-Fourier sources): a closed-loop pass measures the saturation
     throughput, then requests arrive at 0.8 of it and p50/p99 latency and
-    throughput are recorded."""
+    throughput are recorded.  batched: the cross-request batch engine (one
+    launch per phase over all active requests), else one stream per request.
+    Returns the summary and the solutions of the first `keep` requests of
+    the paced pass (for the oracle's check)."""
     import workloads as W
     reqs = W.request_stream(n_requests, rate=1.0)
     data = []
@@ -419,7 +435,7 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
 
     def closed_loop():
         srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60,
-                        host_threads=host_threads)
+                        host_threads=host_threads, batched=batched)
         t0 = time.perf_counter()
         for r, f in data:
             srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)
@@ -430,23 +446,35 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
         for rid in srv.finished():
             _, st, _ = srv.fetch(rid)
             its.append(st["iterations"])
+        counters = srv.counters()
         srv.close()
-        return n_requests / dt, its
+        return n_requests / dt, its, counters
 
-    cold_tput, _ = closed_loop()  # fills the inverse cache
-    warm_tput, its = closed_loop()
+    cold_tput, _, _ = closed_loop()  # fills the inverse cache
+    warm_tput, its, counters = closed_loop()
+    summary = dict(requests=n_requests, precision=precision, max_active=max_active,
+                   batched=batched, saturation_solves_per_s_cold_cache=round(cold_tput, 2),
+                   saturation_solves_per_s=round(warm_tput, 2),
+                   iterations_p50=float(np.median(its)), iterations_max=int(max(its)))
+    if batched:
+        steps, bsteps, launches, peak = counters
+        summary["batch_engine"] = dict(steps=bsteps, launches_per_step=round(launches / max(bsteps, 1), 1),
+                                       most_requests_per_step=peak)
+    if not paced:
+        return summary, {}
     rate = 0.8 * warm_tput
     gaps = np.array([r.arrival for r, _ in data]) / rate  # unit-rate arrivals rescaled
     srv = dg.Server(hbm_budget_bytes=64e9, max_active=max_active, precision=precision, max_iter=60,
-                    host_threads=host_threads)
+                    host_threads=host_threads, batched=batched)
     t0 = time.perf_counter()
     nxt = 0
+    index = {}
     peak_active = 0
     while True:
         now = time.perf_counter() - t0
         while nxt < n_requests and gaps[nxt] <= now:
             r, f = data[nxt]
-            srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)
+            index[srv.submit((0, 0, 0), (r.side,) * 3, r.elements, r.p, f)] = nxt
             nxt += 1
         a, q = srv.step()
         peak_active = max(peak_active, a)
@@ -455,19 +483,19 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
         if a == 0 and q == 0 and nxt < n_requests:
             time.sleep(max(0.0, min(0.001, gaps[nxt] - (time.perf_counter() - t0))))
     makespan = time.perf_counter() - t0
-    lat, conv = [], 0
+    lat, conv, kept = [], 0, {}
     for rid in srv.finished():
-        _, st, times = srv.fetch(rid)
+        u, st, times = srv.fetch(rid)
         lat.append(times[2] - times[0])
         conv += int(st["converged"] and st["rel_residual"] <= 1e-10)
+        if index[rid] < keep:
+            kept[f"serve_{index[rid]}"] = u
     srv.close()
-    return dict(requests=n_requests, precision=precision, max_active=max_active,
-                saturation_solves_per_s_cold_cache=round(cold_tput, 2),
-                saturation_solves_per_s=round(warm_tput, 2), arrival_rate_per_s=round(rate, 2),
-                solves_per_s=round(n_requests / makespan, 2),
-                latency_ms_p50=round(1e3 * _pct(lat, 50), 2), latency_ms_p99=round(1e3 * _pct(lat, 99), 2),
-                converged_to_1e10=conv, peak_active=peak_active,
-                iterations_p50=float(np.median(its)), iterations_max=int(max(its)))
+    summary.update(arrival_rate_per_s=round(rate, 2), solves_per_s=round(n_requests / makespan, 2),
+                   latency_ms_p50=round(1e3 * _pct(lat, 50), 2),
+                   latency_ms_p99=round(1e3 * _pct(lat, 99), 2),
+                   converged_to_1e10=conv, peak_active=peak_active)
+    return summary, kept
 
 
 def main():
@@ -591,8 +619,13 @@ def main():
 
     serving = None
     if not args.no_serving:
-        _log(f"serving stream of {args.serve_requests} requests")
-        serving = run_serving(dg, args.serve_requests, host_threads=args.serve_threads)
+        _log(f"serving stream of {args.serve_requests} requests (batched)")
+        serving, kept = run_serving(dg, args.serve_requests, host_threads=args.serve_threads)
+        solutions.update(kept)
+        _log(f"serving stream of {args.serve_requests} requests (one stream per request)")
+        serving["per_request_streams"], _ = run_serving(dg, args.serve_requests,
+                                                        host_threads=args.serve_threads,
+                                                        batched=False, paced=False)
     ceil = None if args.no_ceilings else measured_ceilings()
 
     roofline = {"bound": "mfma", "achieved": round(gemm64["achieved_tflops"], 2),
@@ -657,6 +690,10 @@ def main():
             c2[p]["oracle_rel_residual"] = checks.get(f"c2_{p}_oracle_rel_residual")
             c3[p]["oracle_rel_nonlinear_residual"] = checks.get(f"c3_{p}_oracle_rel_nonlinear_residual")
         c1["vs_oracle_solution_rel_diff"] = checks.get("c1_fp64_vs_oracle_solution_rel_diff")
+        if serving is not None and "served_sample_oracle_rel_residual_max" in checks:
+            serving["oracle_check"] = {
+                "sample": f"the first {checks['served_sample_size']} requests of the paced pass",
+                "max_oracle_rel_residual": checks["served_sample_oracle_rel_residual_max"]}
         c1["oracle_iterations"] = checks.get("c1_oracle_iterations")
 
     out = {

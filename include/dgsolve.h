@@ -305,6 +305,16 @@ typedef struct {
                               block is freed only after the device is done
                               with it.                                          */
   void* alloc_ctx;
+  int batched;             /* 1 = advance the Poisson requests of degree p <= 8
+                              together: every server step moves each of them by
+                              one FGMRES iteration through launches that cover
+                              all of them (one operator launch, one grouped
+                              subdomain GEMM per precision and one scatter per
+                              Schwarz step of the multigrid cycle, one launch
+                              per transfer and per Krylov vector operation),
+                              with one synchronisation per step.  Puncture
+                              requests and p > 8 take the per-request path.
+                              0 = every request on its own stream.              */
 } dgs_server_options;
 
 int dgs_server_create(const dgs_server_options* opt, dgs_server** out);
@@ -331,6 +341,10 @@ int dgs_server_submit_puncture(dgs_server* server, const dgs_domain* domain,
  * of a worker's requests has finished, the worker waits for one, so every
  * call makes progress); reports the active and queued counts. */
 int dgs_server_step(dgs_server* server, int* n_active, int* n_queued);
+/* Counters since dgs_server_create: counters[0] server steps, [1] steps of
+ * the batch engine, [2] kernel launches of those steps, [3] the most requests
+ * the engine advanced together. */
+int dgs_server_counters(const dgs_server* server, long long counters[4]);
 /* Ids of finished requests (up to capacity) and their number. */
 int dgs_server_finished(dgs_server* server, long long* ids, int capacity, int* count);
 /* Copy a finished request's solution (host, n values) and stats, and release

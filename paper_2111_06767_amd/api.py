@@ -32,7 +32,7 @@ EXPORTED = (
     "dgs_server_step", "dgs_server_finished", "dgs_server_fetch", "dgs_subdomain_solves",
     "dgs_set_apply_shape", "dgs_get_apply_shape", "dgs_set_gemm_variant", "dgs_get_gemm_variant",
     "dgs_server_submit_puncture", "dgs_cg_solve", "dgs_grid_coordinates",
-    "dgs_cg_solve_noalloc",
+    "dgs_cg_solve_noalloc", "dgs_server_counters",
 )
 
 
@@ -62,7 +62,7 @@ class ServerOptions(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_double), ("max_active", ctypes.c_int),
                 ("penalty", ctypes.c_double), ("solver", Options), ("host_threads", ctypes.c_int),
                 ("alloc_fn", ctypes.c_void_p), ("free_fn", ctypes.c_void_p),
-                ("alloc_ctx", ctypes.c_void_p)]
+                ("alloc_ctx", ctypes.c_void_p), ("batched", ctypes.c_int)]
 
 
 class DgsError(RuntimeError):
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
         ctypes.POINTER(ctypes.c_double), ctypes.c_longlong, ctypes.c_double, ctypes.c_double,
         ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
     lib.dgs_server_step.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+    lib.dgs_server_counters.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
     lib.dgs_server_finished.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]
     lib.dgs_server_fetch.argtypes = [P, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double),
@@ -407,7 +408,7 @@ class Server:
     """Continuous-batching solve server (see dgs_server_* in include/dgsolve.h)."""
 
     def __init__(self, hbm_budget_bytes=64e9, max_active=16, penalty=1.5, host_threads=0,
-                 allocator=None, **solver_opts):
+                 allocator=None, batched=True, **solver_opts):
         lib = load_library()
         self._lib = lib
         o = ServerOptions()
@@ -416,6 +417,7 @@ class Server:
         o.penalty = float(penalty)
         o.host_threads = int(host_threads)
         o.solver = default_options(**solver_opts)
+        o.batched = 1 if batched else 0
         self.allocator = allocator
         if allocator is not None:
             # kept on the server: the library calls them until it is destroyed
@@ -467,6 +469,13 @@ class Server:
             float(newton_rtol), float(linear_rtol), int(max_newton), ctypes.byref(rid)))
         self._sizes[rid.value] = a.size
         return rid.value
+
+    def counters(self):
+        """(server steps, batch-engine steps, their kernel launches, most
+        requests the engine advanced together)."""
+        c = (ctypes.c_longlong * 4)()
+        _check(self._lib.dgs_server_counters(self._h, c))
+        return tuple(c[i] for i in range(4))
 
     def step(self):
         a, q = ctypes.c_int(), ctypes.c_int()

@@ -239,7 +239,22 @@ struct GemmPlan {
   bool small = false;
   int kparts = 1;
 };
-GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant);
+// parts_cap > 0: at most that many split-K parts (the partial-product
+// buffers of the classes hold no more)
+GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant, int parts_cap = 0);
+// The grouped GEMM over classes of several problems (the serving loop's
+// batched sweeps): class c reads its rows at ptrs[c].rs and writes part p of
+// its corrections at ptrs[c].du + p * ptrs[c].pstride (offsets rs_off within);
+// tiles from plan_subdomain_gemm over the joined class list, variant 2 (or
+// the small-tile form).
+struct GemmPtr {
+  const void* rs;
+  void* du;
+  long long pstride;
+};
+hipError_t launch_subdomain_gemm_batched(bool f32, const ClassInfo* cls, const GemmPtr* ptrs,
+                                         const GemmTile* tiles, int ntiles, bool small,
+                                         hipStream_t s);
 hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long part_stride,
                                  const ClassInfo* cls, const GemmTile* tiles, int ntiles,
                                  bool small, int use_op, hipStream_t s, int variant);
@@ -317,6 +332,80 @@ hipError_t launch_waxpy(double* y, const double* x, double lam, const double* dx
 // device), x += alpha p, r_next = r - alpha q.
 hipError_t launch_cg_step(double* x, double* r_next, const double* r, const double* p,
                           const double* q, double rz, const double* pq, long long n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Cross-request batched launches (the serving loop): each problem's share of
+// a launch is a job; the jobs of a launch are listed by their first
+// workgroup blk0 (ascending), and the last job ends at the launch's block
+// count.  Degrees N <= 9 may mix in one launch.
+// ---------------------------------------------------------------------------
+struct BApplyJob {       // one element per workgroup: blk0 + e for element e
+  const double* u;
+  double* out;           // vector output (when the launch does not write rows)
+  const double* b;       // right-hand side (residual)
+  double* ucopy;         // optional copy of u
+  GatherOut go;          // rows output (rs, f32, pull, nov)
+  OpParams P;            // box grid (P.n set)
+  int N;
+  int blk0;
+};
+struct BScatterJob {     // 256 points per workgroup
+  double* u;
+  const void* du;        // partial products, FP32 (f32) or FP64
+  const double* weights;
+  const PullEntry* pull;
+  long long pstride;     // distance between split-K parts
+  long long total;       // E N^3
+  int N, nov, parts, f32, assign;
+  int blk0;
+};
+struct BTransferJob {    // one coarse (restriction) / fine (prolongation) element per workgroup
+  const double* src;
+  double* dst;
+  GatherOut go;          // restriction: the coarse level's first rows
+  int nf[3], nc[3], split[3];
+  int N;
+  int blk0;
+};
+struct BDotJob {         // multidot_blocks(n) workgroups from blk0, outputs from fblk0
+  const double* V;
+  long long ldv;
+  int m;                 // vectors V_0..V_{m-1}
+  int mode;              // 0 dots with w; 1 w -= V coef, then dots; 2 w -= V coef, then |w|^2
+  const double* coef;
+  double* w;
+  long long n, chunk;
+  double* partial;
+  int nblocks;
+  double* h;             // m results (1 for mode 2)
+  int blk0, fblk0;
+};
+struct BVecJob {         // 256 points per workgroup
+  double* y;             // Z null: y = x / sqrt(*nrm2) (and y2, rows); else y += sum coef_i Z_i
+  const double* x;
+  const double* nrm2;
+  double* y2;
+  GatherOut go;
+  long long n;
+  int N;
+  const double* coef;
+  const double* Z;
+  long long ldz;
+  int m;
+  int blk0;
+};
+// mode kApply (rows = false, with ucopy) or kResidual (rows: write r_S);
+// threads 64 (every N^2 <= 64) or 128; tabs[N] the device tables of degree N-1
+hipError_t launch_batch_apply(int mode, bool rows, const BApplyJob* jobs, int njobs, int nblocks,
+                              int threads, const DevTables* tabs, hipStream_t s);
+hipError_t launch_batch_scatter(const BScatterJob* jobs, int njobs, int nblocks, hipStream_t s);
+hipError_t launch_batch_restrict(const BTransferJob* jobs, int njobs, int nblocks,
+                                 const MgTables* tabs, hipStream_t s);
+hipError_t launch_batch_prolongate(const BTransferJob* jobs, int njobs, int nblocks,
+                                   const MgTables* tabs, hipStream_t s);
+hipError_t launch_batch_dots(const BDotJob* jobs, int njobs, int nblocks, int nfinal,
+                             hipStream_t s);
+hipError_t launch_batch_vec(const BVecJob* jobs, int njobs, int nblocks, hipStream_t s);
 
 // Set-up kernels: unit-vector fill and column gather for the patch apply, the
 // blocked inversion, and the transposed copies of the results.

@@ -153,11 +153,16 @@ struct Mfma<float> {
 // MFMA tiles of 16 x 16; the block tile is BM = 16 WM TM rows by BN = 16 WN TN
 // columns, the K loop steps by BK with the next tile prefetched into registers
 // while the current one is multiplied out of LDS.
-template <typename T, int WM, int WN, int TM, int TN, int BK>
+//
+// BATCH: the classes come from several problems (the serving loop's batched
+// sweeps): class c's subdomain rows and corrections are at ptrs[c].rs /
+// ptrs[c].du, with its own part stride, instead of the shared rs / du.
+template <typename T, int WM, int WN, int TM, int TN, int BK, bool BATCH = false>
 __global__ void __launch_bounds__(256)
 k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
            long long pstride, const ClassInfo* __restrict__ cls,
-           const GemmTile* __restrict__ tiles, int use_op) {
+           const GemmTile* __restrict__ tiles, int use_op,
+           const GemmPtr* __restrict__ ptrs = nullptr) {
   constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
   // LDS row paddings: the MFMA operand reads touch 16 lanes per row and 2 (FP32)
   // or 1 (FP64) rows per LDS cycle; row strides of 36 / 144 floats (FP32) and
@@ -177,9 +182,17 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
   const GemmTile tl = tiles[blockIdx.x];
   const ClassInfo ci = cls[tl.cls];
   const int ld = ci.ld;
-  const T* A = rs + ci.rs_off;
+  const T* A;
+  T* C;
+  if constexpr (BATCH) {
+    const GemmPtr gp = ptrs[tl.cls];
+    A = (const T*)gp.rs + ci.rs_off;
+    C = (T*)gp.du + tl.part * gp.pstride + ci.rs_off;
+  } else {
+    A = rs + ci.rs_off;
+    C = du + tl.part * pstride + ci.rs_off;
+  }
   const T* B = (const T*)(use_op ? ci.op : ci.inv);
-  T* C = du + tl.part * pstride + ci.rs_off;
   const int m0 = tl.m0, n0 = tl.n0, kbeg = tl.k0, kend = tl.k1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave / WN, wn = wave % WN;
@@ -511,7 +524,7 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
   return hipGetLastError();
 }
 
-GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
+GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant, int parts_cap) {
   GemmPlan plan;
   bool any_big = false;
   for (const ClassInfo& c : cls) any_big = any_big || c.count > kGemmSmallCount;
@@ -529,7 +542,8 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant) {
   // shorten the GEMM and lengthen the scatter that sums them)
   int base = 0;
   for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + bn - 1) / bn);
-  const int max_parts = plan.small ? (variant == 1 ? 4 : (variant == 2 ? 8 : kMaxParts)) : 4;
+  int max_parts = plan.small ? (variant == 1 ? 4 : (variant == 2 ? 8 : kMaxParts)) : 4;
+  if (parts_cap > 0) max_parts = std::min(max_parts, parts_cap);
   plan.kparts = 1;
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
   for (int c = 0; c < (int)cls.size(); ++c) {
@@ -583,6 +597,29 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     else
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_subdomain_gemm_batched(bool f32, const ClassInfo* cls, const GemmPtr* ptrs,
+                                         const GemmTile* tiles, int ntiles, bool small,
+                                         hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  const dim3 grid((unsigned)ntiles), block(256);
+  if (f32) {
+    if (small)
+      hipLaunchKernelGGL((k_sub_gemm<float, 1, 4, 1, 1, 32, true>), grid, block, 0, s, nullptr,
+                         nullptr, 0, cls, tiles, 0, ptrs);
+    else
+      hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 1, 2, 32, true>), grid, block, 0, s, nullptr,
+                         nullptr, 0, cls, tiles, 0, ptrs);
+  } else {
+    if (small)
+      hipLaunchKernelGGL((k_sub_gemm<double, 1, 4, 1, 1, 16, true>), grid, block, 0, s, nullptr,
+                         nullptr, 0, cls, tiles, 0, ptrs);
+    else
+      hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 1, 2, 16, true>), grid, block, 0, s, nullptr,
+                         nullptr, 0, cls, tiles, 0, ptrs);
   }
   return hipGetLastError();
 }

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <exception>
 #include <functional>
+#include <limits>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -1718,9 +1719,703 @@ struct ServerRequest {
   FgmresResult result;
   double t_setup = 0;
   int status = 0;
+  bool batched = false;  // advanced by the cross-request batch engine
 };
 
 }  // namespace
+
+// ===========================================================================
+// Cross-request batched engine of the serving loop
+// ===========================================================================
+// The active Poisson requests of degree p <= 8 advance together, one FGMRES
+// iteration per step, through launches that each cover every request: one
+// operator launch, one or two grouped GEMM launches (FP32 and FP64 classes)
+// and one scatter launch per Schwarz step of the multigrid cycle, one launch
+// per transfer, and one per Krylov vector operation.  The launches' job
+// tables (the V-cycle's schedule over the requests' levels, the tiles of the
+// GEMMs grouped across requests) are rebuilt when a request joins or leaves;
+// the few per-step tables (Krylov vectors at the current iteration index)
+// are staged in one host-to-device copy, and the scalars of every request
+// come back in one device-to-host copy, one synchronisation per step.
+namespace {
+
+// A device buffer grown on demand (library memory).
+struct DevBuf {
+  char* p = nullptr;
+  size_t cap = 0;
+  void ensure(size_t n) {
+    if (n <= cap) return;
+    if (p) dfree(p);
+    cap = std::max(n, 2 * cap);
+    p = dalloc<char>(cap);
+  }
+  ~DevBuf() {
+    if (p) dfree(p);
+  }
+};
+
+// Job tables appended to one host byte image (16-byte aligned entries).
+struct JobImage {
+  std::vector<char> bytes;
+  template <typename J>
+  size_t put(const std::vector<J>& v) {
+    const size_t off = (bytes.size() + 15) / 16 * 16;
+    bytes.resize(off + v.size() * sizeof(J));
+    if (!v.empty()) std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(J));
+    return off;
+  }
+};
+
+enum BatchOpKind { kOpApplyRows, kOpApplyVec, kOpGemm, kOpScatter, kOpRestrict, kOpProlong };
+
+struct BatchOp {
+  int kind = 0;
+  size_t off = 0;             // the job table (GEMM: the class list)
+  size_t off_ptrs = 0, off_tiles = 0;  // GEMM: per-class pointers, tiles
+  int njobs = 0, nblocks = 0, threads = 64;
+  bool f32 = false, small = false;
+};
+
+// The engine's per-request state: the host side of FGMRES (Saad Alg. 9.6) as
+// the solo solver keeps it, and the request's slot in the scalar pack.
+struct BatchReq {
+  ServerRequest* r = nullptr;
+  int slot = 0;
+  enum Stage { kStart, kIter, kFinish, kDone } stage = kStart;
+  int m = 0, j = 0, cycles = 0, iterations = 0, max_total = 0;
+  double rtol = 0, beta = 0, beta0 = 0;
+  std::vector<double> H, cs, sn, g, y;
+  bool converged = false;
+};
+
+class BatchEngine {
+ public:
+  BatchEngine(int max_active, int max_iter, int restart)
+      : max_active_(max_active), kmax_(max_iter), restart_(restart) {
+    std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+    HIP_OK(hipStreamCreateWithFlags(&s_, hipStreamNonBlocking));
+    stride_ = 4 * (kmax_ + 2);
+    pack_.ensure(sizeof(double) * (size_t)stride_ * max_active_);
+    HIP_OK(hipHostMalloc((void**)&h_pack_, sizeof(double) * (size_t)stride_ * max_active_,
+                         hipHostMallocDefault));
+    // the operator and transfer tables of every degree p <= 8
+    std::vector<DevTables> dt(kMaxN + 1);
+    std::vector<MgTables> mt(kMaxN + 1);
+    std::memset(dt.data(), 0, dt.size() * sizeof(DevTables));
+    std::memset(mt.data(), 0, mt.size() * sizeof(MgTables));
+    for (int N = 2; N <= 9; ++N) {
+      const HostTables ht = make_tables(N);
+      dt[N] = to_dev(ht);
+      mt[N] = to_dev_mg(ht);
+    }
+    tabs_.ensure(dt.size() * sizeof(DevTables) + mt.size() * sizeof(MgTables) + 16);
+    HIP_OK(hipMemcpy(tabs_.p, dt.data(), dt.size() * sizeof(DevTables), hipMemcpyHostToDevice));
+    mt_off_ = (dt.size() * sizeof(DevTables) + 15) / 16 * 16;
+    HIP_OK(hipMemcpy(tabs_.p + mt_off_, mt.data(), mt.size() * sizeof(MgTables),
+                     hipMemcpyHostToDevice));
+    free_slots_.clear();
+    for (int i = max_active_ - 1; i >= 0; --i) free_slots_.push_back(i);
+  }
+  ~BatchEngine() {
+    if (s_) (void)hipStreamSynchronize(s_);
+    std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+    if (h_pack_) (void)hipHostFree(h_pack_);
+    if (h_stage_) (void)hipHostFree(h_stage_);
+    if (s_) (void)hipStreamDestroy(s_);
+  }
+  hipStream_t stream() const { return s_; }
+  bool empty() const { return reqs_.empty(); }
+  int size() const { return (int)reqs_.size(); }
+  int launches_last_step() const { return launches_; }
+
+  // A request whose problem, b and u = 0 are set up (on its own stream, which
+  // the caller has synchronised) joins at the next step.
+  void add(ServerRequest* r) {
+    if (free_slots_.empty()) throw DgsError(DGS_ERR_INVALID, "batch engine: no free slot");
+    BatchReq q;
+    q.r = r;
+    q.slot = free_slots_.back();
+    free_slots_.pop_back();
+    q.max_total = r->run.max_total;
+    q.rtol = r->run.rtol;
+    // restarted FGMRES(m): cycles of at most m iterations (the basis size)
+    q.m = std::min(restart_ > 0 ? restart_ : kmax_, q.max_total);
+    ensure_krylov(r->prob, q.m);
+    new_cycle(q);
+    r->run.R = FgmresResult();
+    reqs_.push_back(std::move(q));
+    dirty_ = true;
+  }
+
+  // One lockstep step; returns the requests that finished (their results in
+  // r->run.R, r->run.stage = done).
+  std::vector<ServerRequest*> step() {
+    std::vector<ServerRequest*> finished;
+    if (reqs_.empty()) return finished;
+    if (dirty_) rebuild();
+    launches_ = 0;
+    JobImage img;
+    // ---- per-step job lists ----
+    std::vector<BApplyJob> a_start, a_iter, a_fin;
+    std::vector<BDotJob> d_start, d1, d2, d3, d_fin;
+    std::vector<BVecJob> v_start, v_iter, v_comb;
+    int thr_start = 64, thr_iter = 64, thr_fin = 64;
+    for (BatchReq& q : reqs_) {
+      dgs_problem* P = q.r->prob;
+      Level& L0 = P->levels[0];
+      const long long n = P->nd(0);
+      double* pk = (double*)pack_.p + (size_t)q.slot * stride_;
+      const int m2 = q.m + 2;
+      double* h1 = pk;
+      double* h2 = pk + m2;
+      double* hn = pk + 2 * m2;
+      double* beta2 = pk + 2 * m2 + 1;
+      double* res2 = pk + 2 * m2 + 2;
+      double* yv = pk + 3 * m2;
+      double* V = P->d_V;
+      double* Z = P->d_Z;
+      if (q.stage == BatchReq::kStart || q.stage == BatchReq::kIter) {
+        if (q.stage == BatchReq::kStart) {
+          // r0 = b - A x (x = 0 at first: r0 = b exactly), |r0|^2, v_0 = r0 / |r0|
+          a_start.push_back(apply_job(P, 0, q.r->d_u, V, q.r->d_b, nullptr, false));
+          thr_start = std::max(thr_start, P->N * P->N > 64 ? 128 : 64);
+          d_start.push_back(dot_job(V, n, 1, 0, nullptr, V, n, P->d_partial, beta2));
+          v_start.push_back(norm_job(P, V, beta2));
+        }
+        const int j = q.j;
+        // w = A z_j (z_j = the cycle's output, copied to Z_j), CGS2, v_{j+1}
+        a_iter.push_back(apply_job(P, 0, L0.d_u, V + (size_t)(j + 1) * n, nullptr,
+                                   Z + (size_t)j * n, false));
+        thr_iter = std::max(thr_iter, P->N * P->N > 64 ? 128 : 64);
+        double* w = V + (size_t)(j + 1) * n;
+        d1.push_back(dot_job(V, n, j + 1, 0, nullptr, w, n, P->d_partial, h1));
+        d2.push_back(dot_job(V, n, j + 1, 1, h1, w, n, P->d_partial, h2));
+        d3.push_back(dot_job(V, n, j + 1, 2, h2, w, n, P->d_partial, hn));
+        v_iter.push_back(norm_job(P, w, hn));
+      } else if (q.stage == BatchReq::kFinish) {
+        const int k = q.j;
+        double* hp = h_pack_ + (size_t)q.slot * stride_;
+        for (int i = 0; i < k; ++i) hp[3 * m2 + i] = q.y[i];
+        if (k > 0) {
+          BVecJob c{};
+          c.y = q.r->d_u;
+          c.n = n;
+          c.coef = yv;
+          c.Z = Z;
+          c.ldz = n;
+          c.m = k;
+          v_comb.push_back(c);
+        }
+        a_fin.push_back(apply_job(P, 0, q.r->d_u, P->d_tmp, q.r->d_b, nullptr, false));
+        thr_fin = std::max(thr_fin, P->N * P->N > 64 ? 128 : 64);
+        d_fin.push_back(dot_job(P->d_tmp, n, 1, 0, nullptr, P->d_tmp, n, P->d_partial, res2));
+      }
+    }
+    // block offsets
+    auto apply_blocks = [](std::vector<BApplyJob>& v) {
+      int nb = 0;
+      for (auto& jb : v) {
+        jb.blk0 = nb;
+        nb += jb.P.E;
+      }
+      return nb;
+    };
+    auto dot_blocks = [](std::vector<BDotJob>& v, int& nfinal) {
+      int nb = 0;
+      nfinal = 0;
+      for (auto& jb : v) {
+        jb.blk0 = nb;
+        nb += jb.nblocks;
+        jb.fblk0 = nfinal;
+        nfinal += jb.mode == 2 ? 1 : jb.m;
+      }
+      return nb;
+    };
+    auto vec_blocks = [](std::vector<BVecJob>& v) {
+      int nb = 0;
+      for (auto& jb : v) {
+        jb.blk0 = nb;
+        nb += (int)((jb.n + 255) / 256);
+      }
+      return nb;
+    };
+    int fs = 0, f1 = 0, f2 = 0, f3 = 0, ff = 0;
+    const int nb_as = apply_blocks(a_start), nb_ai = apply_blocks(a_iter), nb_af = apply_blocks(a_fin);
+    // the residual of a starting request writes r0 into V_0
+    const int nb_ds = dot_blocks(d_start, fs), nb_d1 = dot_blocks(d1, f1), nb_d2 = dot_blocks(d2, f2),
+              nb_d3 = dot_blocks(d3, f3), nb_df = dot_blocks(d_fin, ff);
+    const int nb_vs = vec_blocks(v_start), nb_vi = vec_blocks(v_iter), nb_vc = vec_blocks(v_comb);
+    const size_t o_as = img.put(a_start), o_ai = img.put(a_iter), o_af = img.put(a_fin);
+    const size_t o_ds = img.put(d_start), o_d1 = img.put(d1), o_d2 = img.put(d2), o_d3 = img.put(d3),
+                 o_df = img.put(d_fin);
+    const size_t o_vs = img.put(v_start), o_vi = img.put(v_iter), o_vc = img.put(v_comb);
+    // ---- upload the per-step tables and the pack (the combine reads y) ----
+    stage_buf_.ensure(img.bytes.size() + 16);
+    if (h_stage_cap_ < img.bytes.size()) {
+      std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+      if (h_stage_) (void)hipHostFree(h_stage_);
+      h_stage_cap_ = std::max(img.bytes.size(), 2 * h_stage_cap_);
+      HIP_OK(hipHostMalloc((void**)&h_stage_, h_stage_cap_, hipHostMallocDefault));
+    }
+    if (!img.bytes.empty()) {
+      std::memcpy(h_stage_, img.bytes.data(), img.bytes.size());
+      HIP_OK(hipMemcpyAsync(stage_buf_.p, h_stage_, img.bytes.size(), hipMemcpyHostToDevice, s_));
+    }
+    if (!v_comb.empty())
+      HIP_OK(hipMemcpyAsync(pack_.p, h_pack_, sizeof(double) * (size_t)stride_ * max_active_,
+                            hipMemcpyHostToDevice, s_));
+    const DevTables* dtabs = (const DevTables*)tabs_.p;
+    auto sp = [&](size_t off) { return stage_buf_.p + off; };
+    // ---- starts ----
+    if (nb_as) {
+      HIP_OK(launch_batch_apply(kResidual, false, (const BApplyJob*)sp(o_as), (int)a_start.size(),
+                                nb_as, thr_start, dtabs, s_));
+      HIP_OK(launch_batch_dots((const BDotJob*)sp(o_ds), (int)d_start.size(), nb_ds, fs, s_));
+      HIP_OK(launch_batch_vec((const BVecJob*)sp(o_vs), (int)v_start.size(), nb_vs, s_));
+      launches_ += 4;
+    }
+    // ---- the multigrid cycle of every request, then the Krylov step ----
+    if (nb_ai) {
+      run_vcycle();
+      HIP_OK(launch_batch_apply(kApply, false, (const BApplyJob*)sp(o_ai), (int)a_iter.size(), nb_ai,
+                                thr_iter, dtabs, s_));
+      HIP_OK(launch_batch_dots((const BDotJob*)sp(o_d1), (int)d1.size(), nb_d1, f1, s_));
+      HIP_OK(launch_batch_dots((const BDotJob*)sp(o_d2), (int)d2.size(), nb_d2, f2, s_));
+      HIP_OK(launch_batch_dots((const BDotJob*)sp(o_d3), (int)d3.size(), nb_d3, f3, s_));
+      HIP_OK(launch_batch_vec((const BVecJob*)sp(o_vi), (int)v_iter.size(), nb_vi, s_));
+      launches_ += 8;
+    }
+    // ---- finishes: x += Z y, the true residual ----
+    if (nb_af) {
+      if (nb_vc) {
+        HIP_OK(launch_batch_vec((const BVecJob*)sp(o_vc), (int)v_comb.size(), nb_vc, s_));
+        ++launches_;
+      }
+      HIP_OK(launch_batch_apply(kResidual, false, (const BApplyJob*)sp(o_af), (int)a_fin.size(),
+                                nb_af, thr_fin, dtabs, s_));
+      HIP_OK(launch_batch_dots((const BDotJob*)sp(o_df), (int)d_fin.size(), nb_df, ff, s_));
+      launches_ += 3;
+    }
+    HIP_OK(hipMemcpyAsync(h_pack_, pack_.p, sizeof(double) * (size_t)stride_ * max_active_,
+                          hipMemcpyDeviceToHost, s_));
+    HIP_OK(hipStreamSynchronize(s_));
+    // ---- host part ----
+    std::vector<BatchReq> keep;
+    for (BatchReq& q : reqs_) {
+      complete(q);
+      if (q.stage == BatchReq::kDone) {
+        q.r->run.stage = FgmresRun::kDone;
+        free_slots_.push_back(q.slot);
+        finished.push_back(q.r);
+        dirty_ = true;
+      } else {
+        keep.push_back(std::move(q));
+      }
+    }
+    reqs_ = std::move(keep);
+    return finished;
+  }
+
+ private:
+  BApplyJob apply_job(dgs_problem* P, int l, const double* u, double* out, const double* b,
+                      double* ucopy, bool rows) {
+    Level& L = P->levels[l];
+    BApplyJob jb{};
+    jb.u = u;
+    jb.out = out;
+    jb.b = b;
+    jb.ucopy = ucopy;
+    if (rows) jb.go = level_gather(P, L);
+    jb.P = L.op;
+    jb.N = P->N;
+    return jb;
+  }
+  static BDotJob dot_job(const double* V, long long ldv, int m, int mode, const double* coef,
+                         double* w, long long n, double* partial, double* h) {
+    BDotJob jb{};
+    jb.V = V;
+    jb.ldv = ldv;
+    jb.m = m;
+    jb.mode = mode;
+    jb.coef = coef;
+    jb.w = w;
+    jb.n = n;
+    jb.nblocks = multidot_blocks(n);
+    jb.chunk = (n + jb.nblocks - 1) / jb.nblocks;
+    jb.partial = partial;
+    jb.h = h;
+    return jb;
+  }
+  // v = w / sqrt(*nrm2), also into the finest level's b and subdomain rows
+  // (the cycle's input)
+  static BVecJob norm_job(dgs_problem* P, double* w, const double* nrm2) {
+    Level& L0 = P->levels[0];
+    BVecJob jb{};
+    jb.y = w;
+    jb.x = w;
+    jb.nrm2 = nrm2;
+    jb.y2 = L0.d_b;
+    jb.go = level_gather(P, L0);
+    jb.n = P->nd(0);
+    jb.N = P->N;
+    return jb;
+  }
+
+  void new_cycle(BatchReq& q) {
+    q.stage = BatchReq::kStart;
+    q.j = 0;
+    q.H.assign((size_t)(q.m + 1) * q.m, 0.0);
+    q.cs.assign(q.m, 0.0);
+    q.sn.assign(q.m, 0.0);
+    q.g.assign(q.m + 1, 0.0);
+  }
+
+  // The host part of a request's step: the scalars of the pack.
+  void complete(BatchReq& q) {
+    FgmresResult& R = q.r->run.R;
+    const double* hp = h_pack_ + (size_t)q.slot * stride_;
+    const int m2 = q.m + 2;
+    auto fail_nonfinite = [&]() {
+      R.converged = false;
+      R.rel_residual = std::numeric_limits<double>::quiet_NaN();
+      q.r->status = DGS_ERR_NONFINITE;
+      q.stage = BatchReq::kDone;
+    };
+    if (q.stage == BatchReq::kFinish) {
+      R.rel_residual = std::sqrt(hp[2 * m2 + 2]) / q.beta0;
+      if (!std::isfinite(R.rel_residual)) return fail_nonfinite();
+      // the Givens estimate ended the cycle; the true residual decides
+      R.converged = R.rel_residual <= q.rtol;
+      if (!R.converged && q.iterations < q.max_total)
+        new_cycle(q);  // the next cycle starts from the true residual of x
+      else
+        q.stage = BatchReq::kDone;
+      return;
+    }
+    if (q.stage == BatchReq::kStart) {
+      const double beta2 = hp[2 * m2 + 1];
+      if (!std::isfinite(beta2)) return fail_nonfinite();
+      q.beta = std::sqrt(beta2);
+      if (q.cycles++ == 0) {
+        q.beta0 = q.beta;
+        R.history.push_back(1.0);
+      }
+      if (q.beta == 0.0) {  // b = A x already: nothing to iterate
+        R.converged = true;
+        R.rel_residual = 0.0;
+        q.stage = BatchReq::kDone;
+        return;
+      }
+      q.g[0] = q.beta;
+      q.stage = BatchReq::kIter;
+    }
+    // the iteration this step ran: Hessenberg column j, Givens rotations
+    const int j = q.j;
+    double* col = &q.H[(size_t)j * (q.m + 1)];
+    for (int i = 0; i <= j; ++i) col[i] = hp[i] + hp[m2 + i];
+    const double hn2 = hp[2 * m2];
+    col[j + 1] = std::sqrt(hn2);
+    for (int i = 0; i <= j + 1; ++i)
+      if (!std::isfinite(col[i])) return fail_nonfinite();
+    for (int i = 0; i < j; ++i) {
+      const double t = q.cs[i] * col[i] + q.sn[i] * col[i + 1];
+      col[i + 1] = -q.sn[i] * col[i] + q.cs[i] * col[i + 1];
+      col[i] = t;
+    }
+    const double den = std::hypot(col[j], col[j + 1]);
+    q.cs[j] = col[j] / den;
+    q.sn[j] = col[j + 1] / den;
+    col[j] = den;
+    col[j + 1] = 0.0;
+    q.g[j + 1] = -q.sn[j] * q.g[j];
+    q.g[j] = q.cs[j] * q.g[j];
+    R.history.push_back(std::fabs(q.g[j + 1]) / q.beta0);
+    ++q.j;
+    ++q.iterations;
+    R.iterations = q.iterations;
+    if (std::fabs(q.g[q.j]) <= q.rtol * q.beta0 || hn2 == 0.0 || q.j >= q.m ||
+        q.iterations >= q.max_total) {
+      // y from the triangular system; the next step forms x += Z y and the
+      // true residual
+      const int k = q.j;
+      q.y.assign(k, 0.0);
+      for (int i = k - 1; i >= 0; --i) {
+        double t = q.g[i];
+        for (int c = i + 1; c < k; ++c) t -= q.H[(size_t)c * (q.m + 1) + i] * q.y[c];
+        q.y[i] = t / q.H[(size_t)i * (q.m + 1) + i];
+      }
+      q.stage = BatchReq::kFinish;
+    }
+  }
+
+  // ---- the multigrid cycle over every request (Sec. III.C.3) ----
+  // The schedule by level index: on level l every request that has it runs
+  // its smoothing steps (presmoothing, or on its coarsest level the coarse
+  // steps), the requests with a coarser level restrict their residual; on the
+  // way back the requests prolongate and postsmooth.  Step s of a level
+  // covers the requests that take more than s steps there.
+  void rebuild() {
+    ops_.clear();
+    JobImage img;
+    int Lmax = 0;
+    for (BatchReq& q : reqs_) Lmax = std::max(Lmax, (int)q.r->prob->levels.size());
+    auto depth = [](const BatchReq& q) { return (int)q.r->prob->levels.size(); };
+    auto coarse_steps = [](const dgs_problem* P) {
+      const Level& Lc = P->levels.back();
+      int c = P->opt.pre_smooth + P->opt.post_smooth;
+      if (Lc.E == 1) c = std::min(c, 1);  // one subdomain: the first step is exact
+      return c;
+    };
+    auto smoothing_ops = [&](int l, const std::vector<BatchReq*>& S, bool first) {
+      // residual + gather (not in a first step from zero: r = b is gathered)
+      if (!first) {
+        std::vector<BApplyJob> aj;
+        int threads = 64;
+        for (BatchReq* q : S) {
+          dgs_problem* P = q->r->prob;
+          Level& L = P->levels[l];
+          aj.push_back(apply_job(P, l, L.d_u, nullptr, L.d_b, nullptr, true));
+          threads = std::max(threads, P->N * P->N > 64 ? 128 : 64);
+        }
+        BatchOp op;
+        op.kind = kOpApplyRows;
+        int nb = 0;
+        for (auto& jb : aj) {
+          jb.blk0 = nb;
+          nb += jb.P.E;
+        }
+        op.nblocks = nb;
+        op.njobs = (int)aj.size();
+        op.threads = threads;
+        op.off = img.put(aj);
+        ops_.push_back(op);
+      }
+      // the subdomain solves: one grouped GEMM per precision over all classes
+      std::vector<BScatterJob> sj;
+      for (int prec = 0; prec < 2; ++prec) {
+        std::vector<ClassInfo> cls;
+        std::vector<GemmPtr> ptrs;
+        std::vector<BatchReq*> who;
+        int cap = kMaxParts;
+        for (BatchReq* q : S) {
+          Level& L = q->r->prob->levels[l];
+          if ((int)L.f32 != prec) continue;
+          int lp = 1;
+          for (int v = 0; v < kGemmVariants; ++v) lp = std::max(lp, L.kparts_of[v]);
+          cap = std::min(cap, lp);
+          for (const ClassInfo& c : L.cls) {
+            cls.push_back(c);
+            ptrs.push_back(GemmPtr{L.d_rs, L.d_du, L.rs_total});
+          }
+          who.push_back(q);
+        }
+        if (cls.empty()) continue;
+        const GemmPlan plan = plan_subdomain_gemm(cls, 2, cap);
+        BatchOp op;
+        op.kind = kOpGemm;
+        op.f32 = prec == 1;
+        op.small = plan.small;
+        op.njobs = (int)plan.tiles.size();
+        op.off = img.put(cls);
+        op.off_ptrs = img.put(ptrs);
+        op.off_tiles = img.put(plan.tiles);
+        ops_.push_back(op);
+        for (BatchReq* q : who) {
+          dgs_problem* P = q->r->prob;
+          Level& L = P->levels[l];
+          BScatterJob s{};
+          s.u = L.d_u;
+          s.du = L.d_du;
+          s.weights = L.d_weights;
+          s.pull = L.d_pull;
+          s.pstride = L.rs_total;
+          s.total = L.E * (long long)P->N * P->N * P->N;
+          s.N = P->N;
+          s.nov = nov_of(P);
+          s.parts = plan.kparts;
+          s.f32 = L.f32 ? 1 : 0;
+          s.assign = first ? 1 : 0;
+          sj.push_back(s);
+        }
+      }
+      BatchOp op;
+      op.kind = kOpScatter;
+      int nb = 0;
+      for (auto& jb : sj) {
+        jb.blk0 = nb;
+        nb += (int)((jb.total + 255) / 256);
+      }
+      op.nblocks = nb;
+      op.njobs = (int)sj.size();
+      op.off = img.put(sj);
+      ops_.push_back(op);
+    };
+    // descent
+    for (int l = 0; l < Lmax; ++l) {
+      std::vector<BatchReq*> part;
+      for (BatchReq& q : reqs_)
+        if (depth(q) > l) part.push_back(&q);
+      auto steps_of = [&](BatchReq* q) {
+        const dgs_problem* P = q->r->prob;
+        return l < depth(*q) - 1 ? P->opt.pre_smooth : coarse_steps(P);
+      };
+      int smax = 0;
+      for (BatchReq* q : part) smax = std::max(smax, steps_of(q));
+      for (int st = 0; st < smax; ++st) {
+        std::vector<BatchReq*> S;
+        for (BatchReq* q : part)
+          if (steps_of(q) > st) S.push_back(q);
+        smoothing_ops(l, S, st == 0);
+      }
+      // residual and restriction of the requests with a coarser level
+      std::vector<BApplyJob> aj;
+      std::vector<BTransferJob> tj;
+      int threads = 64;
+      for (BatchReq* q : part) {
+        if (l >= depth(*q) - 1) continue;
+        dgs_problem* P = q->r->prob;
+        Level& L = P->levels[l];
+        Level& C = P->levels[l + 1];
+        aj.push_back(apply_job(P, l, L.d_u, L.d_r, L.d_b, nullptr, false));
+        threads = std::max(threads, P->N * P->N > 64 ? 128 : 64);
+        BTransferJob t{};
+        t.src = L.d_r;
+        t.dst = C.d_b;
+        t.go = level_gather(P, C);
+        for (int d = 0; d < 3; ++d) {
+          t.nf[d] = L.n[d];
+          t.nc[d] = C.n[d];
+          t.split[d] = L.split[d];
+        }
+        t.N = P->N;
+        tj.push_back(t);
+      }
+      if (!aj.empty()) {
+        BatchOp a;
+        a.kind = kOpApplyVec;
+        int nb = 0;
+        for (auto& jb : aj) {
+          jb.blk0 = nb;
+          nb += jb.P.E;
+        }
+        a.nblocks = nb;
+        a.njobs = (int)aj.size();
+        a.threads = threads;
+        a.off = img.put(aj);
+        ops_.push_back(a);
+        BatchOp r;
+        r.kind = kOpRestrict;
+        nb = 0;
+        for (auto& jb : tj) {
+          jb.blk0 = nb;
+          nb += jb.nc[0] * jb.nc[1] * jb.nc[2];
+        }
+        r.nblocks = nb;
+        r.njobs = (int)tj.size();
+        r.off = img.put(tj);
+        ops_.push_back(r);
+      }
+    }
+    // ascent
+    for (int l = Lmax - 2; l >= 0; --l) {
+      std::vector<BatchReq*> Q;
+      for (BatchReq& q : reqs_)
+        if (l < depth(q) - 1) Q.push_back(&q);
+      if (Q.empty()) continue;
+      std::vector<BTransferJob> tj;
+      for (BatchReq* q : Q) {
+        dgs_problem* P = q->r->prob;
+        Level& L = P->levels[l];
+        Level& C = P->levels[l + 1];
+        BTransferJob t{};
+        t.src = C.d_u;
+        t.dst = L.d_u;
+        for (int d = 0; d < 3; ++d) {
+          t.nf[d] = L.n[d];
+          t.nc[d] = C.n[d];
+          t.split[d] = L.split[d];
+        }
+        t.N = P->N;
+        tj.push_back(t);
+      }
+      BatchOp pr;
+      pr.kind = kOpProlong;
+      int nb = 0;
+      for (auto& jb : tj) {
+        jb.blk0 = nb;
+        nb += jb.nf[0] * jb.nf[1] * jb.nf[2];
+      }
+      pr.nblocks = nb;
+      pr.njobs = (int)tj.size();
+      pr.off = img.put(tj);
+      ops_.push_back(pr);
+      int post = 0;
+      for (BatchReq* q : Q) post = std::max(post, q->r->prob->opt.post_smooth);
+      for (int st = 0; st < post; ++st) {
+        std::vector<BatchReq*> S;
+        for (BatchReq* q : Q)
+          if (q->r->prob->opt.post_smooth > st) S.push_back(q);
+        smoothing_ops(l, S, false);
+      }
+    }
+    vbuf_.ensure(img.bytes.size() + 16);
+    HIP_OK(hipMemcpyAsync(vbuf_.p, img.bytes.data(), img.bytes.size(), hipMemcpyHostToDevice, s_));
+    HIP_OK(hipStreamSynchronize(s_));  // img goes out of scope
+    dirty_ = false;
+  }
+
+  void run_vcycle() {
+    const DevTables* dtabs = (const DevTables*)tabs_.p;
+    const MgTables* mtabs = (const MgTables*)(tabs_.p + mt_off_);
+    for (const BatchOp& op : ops_) {
+      char* base = vbuf_.p;
+      switch (op.kind) {
+        case kOpApplyRows:
+          HIP_OK(launch_batch_apply(kResidual, true, (const BApplyJob*)(base + op.off), op.njobs,
+                                    op.nblocks, op.threads, dtabs, s_));
+          break;
+        case kOpApplyVec:
+          HIP_OK(launch_batch_apply(kResidual, false, (const BApplyJob*)(base + op.off), op.njobs,
+                                    op.nblocks, op.threads, dtabs, s_));
+          break;
+        case kOpGemm:
+          HIP_OK(launch_subdomain_gemm_batched(op.f32, (const ClassInfo*)(base + op.off),
+                                               (const GemmPtr*)(base + op.off_ptrs),
+                                               (const GemmTile*)(base + op.off_tiles), op.njobs,
+                                               op.small, s_));
+          break;
+        case kOpScatter:
+          HIP_OK(launch_batch_scatter((const BScatterJob*)(base + op.off), op.njobs, op.nblocks, s_));
+          break;
+        case kOpRestrict:
+          HIP_OK(launch_batch_restrict((const BTransferJob*)(base + op.off), op.njobs, op.nblocks,
+                                       mtabs, s_));
+          break;
+        case kOpProlong:
+          HIP_OK(launch_batch_prolongate((const BTransferJob*)(base + op.off), op.njobs, op.nblocks,
+                                         mtabs, s_));
+          break;
+      }
+      ++launches_;
+    }
+  }
+
+  int max_active_ = 0, kmax_ = 0, restart_ = 0, stride_ = 0;
+  hipStream_t s_ = nullptr;
+  DevBuf pack_, tabs_, vbuf_, stage_buf_;
+  size_t mt_off_ = 0;
+  double* h_pack_ = nullptr;
+  char* h_stage_ = nullptr;
+  size_t h_stage_cap_ = 0;
+  std::vector<int> free_slots_;
+  std::vector<BatchReq> reqs_;
+  std::vector<BatchOp> ops_;
+  bool dirty_ = true;
+  int launches_ = 0;
+};
+
+}  // namespace
+
 
 namespace {
 
@@ -1793,6 +2488,12 @@ class WorkerPool {
 
 }  // namespace
 
+namespace {
+int create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
+                   const dgs_options* opt, dgs_alloc_fn alloc_fn, dgs_free_fn free_fn,
+                   void* alloc_ctx, void* stream, dgs_problem** out, bool light);
+}  // namespace
+
 // Device memory of a retired request, freed later in a batch: freeing waits
 // for the whole device, which would drain the other requests' stages.
 struct RetiredMemory {
@@ -1840,7 +2541,11 @@ struct dgs_server {
     dgs_problem* prob;
     double *d_b, *d_u;
     size_t footprint;
+    bool batched;  // a light problem of the batch engine
   };
+  // the cross-request batch engine (created with the first batched request)
+  std::unique_ptr<BatchEngine> engine;
+  long long steps = 0, batch_steps = 0, batch_launches = 0, batch_peak = 0;
   std::vector<Idle> idle;
   double t0 = 0;
   void evict_idle(size_t keep) {  // oldest first, into the batch of frees
@@ -1862,6 +2567,7 @@ struct dgs_server {
   }
   ~dgs_server() {
     pool.reset();
+    engine.reset();
     for (auto& r : active) {
       if (r->stream) (void)hipStreamSynchronize(r->stream);  // a stage may be in flight
       if (r->prob) delete r->prob;
@@ -1896,9 +2602,9 @@ void server_setup(dgs_server* S, ServerRequest& r) {
   const double ta = now_s();
   if (!r.reused) {
     dgs_problem* created = nullptr;
-    const int code = dgs_create_problem(&r.dom, r.elements, r.p, S->opt.penalty, &S->opt.solver,
-                                        S->opt.alloc_fn, S->opt.free_fn, S->opt.alloc_ctx,
-                                        r.stream, &created);
+    const int code = create_problem(&r.dom, r.elements, r.p, S->opt.penalty, &S->opt.solver,
+                                    S->opt.alloc_fn, S->opt.free_fn, S->opt.alloc_ctx, r.stream,
+                                    &created, r.batched);
     if (code != DGS_OK) throw DgsError(code, g_last_error);
     r.prob = created;
     r.d_b = S->vec(created->nd(0));
@@ -1912,7 +2618,17 @@ void server_setup(dgs_server* S, ServerRequest& r) {
     const Level& L0 = prob->levels[0];
     HIP_OK(launch_mass(prob->N, r.d_u, r.d_b, L0.E, L0.h, prob->dt, r.stream));
     HIP_OK(launch_fill(r.d_u, 0.0, n, r.stream));
-    r.run.init(prob, r.d_b, r.d_u, S->opt.solver.rtol, S->opt.solver.max_iter, r.stream);
+    if (r.batched) {  // the batch engine takes it from here, on its own stream
+      r.run.P = prob;
+      r.run.b = r.d_b;
+      r.run.x = r.d_u;
+      r.run.rtol = S->opt.solver.rtol;
+      r.run.max_total = S->opt.solver.max_iter;
+      r.run.stage = FgmresRun::kStart;
+      HIP_OK(hipStreamSynchronize(r.stream));
+    } else {
+      r.run.init(prob, r.d_b, r.d_u, S->opt.solver.rtol, S->opt.solver.max_iter, r.stream);
+    }
   } else {
     // the puncture equation: alpha, beta and b (zero when not given) to the
     // device, u0 = 0, and the first nonlinear residual
@@ -1948,7 +2664,8 @@ std::vector<std::unique_ptr<ServerRequest>> server_select(dgs_server* S) {
     const std::array<int, 4> grid = {r.elements[0], r.elements[1], r.elements[2], r.p};
     int match = -1;  // most recently used idle problem of this shape
     for (int i = (int)S->idle.size() - 1; i >= 0 && match < 0; --i)
-      if (S->idle[i].box == box && S->idle[i].grid == grid) match = i;
+      if (S->idle[i].box == box && S->idle[i].grid == grid && S->idle[i].batched == r.batched)
+        match = i;
     // a reused problem's footprint is already counted; only what this request
     // needs beyond it (a puncture request on a Poisson request's problem) is new
     auto extra = [&](int i) -> size_t {
@@ -2014,7 +2731,7 @@ void server_retire(dgs_server* S, std::unique_ptr<ServerRequest> rq) {
     rq->newton_steps = rq->nrun.steps;
     rq->backtracks = rq->nrun.backtracks;
   }
-  rq->status = rq->result.converged ? DGS_OK : DGS_NOT_CONVERGED;
+  if (rq->status >= 0) rq->status = rq->result.converged ? DGS_OK : DGS_NOT_CONVERGED;
   rq->t_done = now_s() - S->t0;
   // the problem stays resident for the next request of its shape; the
   // puncture fields go with the next batch of frees
@@ -2022,7 +2739,7 @@ void server_retire(dgs_server* S, std::unique_ptr<ServerRequest> rq) {
       {rq->dom.lower[0], rq->dom.lower[1], rq->dom.lower[2], rq->dom.upper[0], rq->dom.upper[1],
        rq->dom.upper[2]},
       {rq->elements[0], rq->elements[1], rq->elements[2], rq->p},
-      rq->prob, rq->d_b, rq->d_u, rq->footprint});
+      rq->prob, rq->d_b, rq->d_u, rq->footprint, rq->batched});
   if (rq->d_alpha || rq->d_beta)
     S->retired.push_back(RetiredMemory{nullptr, nullptr, nullptr, rq->d_alpha, rq->d_beta, 0});
   S->evict_idle(kIdleMax);
@@ -2065,9 +2782,14 @@ void dgs_default_options(dgs_options* o) {
 
 const char* dgs_last_error(void) { return g_last_error.c_str(); }
 
-int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
-                       const dgs_options* opt, dgs_alloc_fn alloc_fn, dgs_free_fn free_fn,
-                       void* alloc_ctx, void* stream, dgs_problem** out) {
+}  // extern "C"
+
+namespace {
+// light: no launch-shape / GEMM-variant autotuning and no captured cycles
+// (problems of the serving loop's batch engine use neither)
+int create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
+                   const dgs_options* opt, dgs_alloc_fn alloc_fn, dgs_free_fn free_fn,
+                   void* alloc_ctx, void* stream, dgs_problem** out, bool light) {
   return guarded([&]() -> int {
     if (!domain || !elements || !out) return fail(DGS_ERR_INVALID, "NULL argument");
     *out = nullptr;
@@ -2135,14 +2857,26 @@ int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, d
       build_level_schwarz(P.get(), L, s);
     }
     build_inverses(P.get(), s);
-    autotune_apply(P.get(), s);
-    autotune_gemm(P.get(), s);
-    if (o.use_graphs) capture_vgraph(P.get(), 0);
+    if (!light) {
+      autotune_apply(P.get(), s);
+      autotune_gemm(P.get(), s);
+      if (o.use_graphs) capture_vgraph(P.get(), 0);
+    }
     HIP_OK(hipStreamSynchronize(s));
     P->t_setup = now_s() - t0;
     *out = P.release();
     return DGS_OK;
   });
+}
+}  // namespace
+
+extern "C" {
+
+int dgs_create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
+                       const dgs_options* opt, dgs_alloc_fn alloc_fn, dgs_free_fn free_fn,
+                       void* alloc_ctx, void* stream, dgs_problem** out) {
+  return create_problem(domain, elements, p, penalty, opt, alloc_fn, free_fn, alloc_ctx, stream,
+                        out, false);
 }
 
 int dgs_destroy_problem(dgs_problem* prob) {
@@ -2464,6 +3198,10 @@ int dgs_server_submit(dgs_server* S, const dgs_domain* domain, const int element
     r->p = p;
     r->f.assign(f, f + n);
     r->footprint = request_footprint(S, elements, p);
+    // the batch engine: Poisson requests of degree <= 8 with the V-cycle
+    const dgs_options& so = S->opt.solver;
+    r->batched = S->opt.batched && p <= 8 && so.cycle == 1 && !so.additive &&
+                 so.pre_smooth >= 1 && so.post_smooth >= 1;
     r->t_submit = now_s() - S->t0;
     *id = r->id;
     S->queue.push_back(std::move(r));
@@ -2535,6 +3273,7 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
       ServerRequest* waiting = nullptr;
       for (size_t i = first; i < S->active.size(); i += stride) {
         ServerRequest& r = *S->active[i];
+        if (r.batched) continue;  // advanced by the batch engine below
         if (r.kind == 1) {  // a Newton step runs to its end on the worker
           if (!r.nrun.done()) r.nrun.step();
           progressed = true;
@@ -2563,7 +3302,7 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
       }
       for (size_t i = first; i < admitted.size(); i += stride) {  // their first stages
         ServerRequest& r = *admitted[i];
-        if (r.kind == 0 && !r.run.done()) {
+        if (r.kind == 0 && !r.batched && !r.run.done()) {
           r.run.issue();
           r.in_flight = true;
         }
@@ -2574,6 +3313,22 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
       S->pool->run([&work, W](int w) { work((size_t)w, W); });
     } else {
       work(0, 1);
+    }
+    ++S->steps;
+    // the batch engine: newly set-up requests join, then every batched
+    // request advances by one FGMRES iteration in shared launches
+    for (auto& rq : admitted) {
+      if (!rq->batched) continue;
+      if (!S->engine)
+        S->engine.reset(new BatchEngine(S->opt.max_active, S->opt.solver.max_iter,
+                                        S->opt.solver.restart));
+      S->engine->add(rq.get());
+    }
+    if (S->engine && !S->engine->empty()) {
+      S->batch_peak = std::max<long long>(S->batch_peak, S->engine->size());
+      S->engine->step();
+      ++S->batch_steps;
+      S->batch_launches += S->engine->launches_last_step();
     }
     for (auto& rq : admitted) S->active.push_back(std::move(rq));
     std::vector<std::unique_ptr<ServerRequest>> still;
@@ -2589,6 +3344,15 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
     if (n_queued) *n_queued = (int)S->queue.size();
     return DGS_OK;
   });
+}
+
+int dgs_server_counters(const dgs_server* S, long long counters[4]) {
+  if (!S || !counters) return fail(DGS_ERR_INVALID, "NULL argument");
+  counters[0] = S->steps;
+  counters[1] = S->batch_steps;
+  counters[2] = S->batch_launches;
+  counters[3] = S->batch_peak;
+  return DGS_OK;
 }
 
 int dgs_server_finished(dgs_server* S, long long* ids, int capacity, int* count) {
@@ -2614,7 +3378,8 @@ int dgs_server_fetch(dgs_server* S, long long id, double* u, long long n, dgs_st
     if (r.status < 0) {
       const int st = r.status;
       S->finished.erase(it);
-      return fail(st, "request rejected: its footprint exceeds the device budget");
+      return fail(st, st == DGS_ERR_OOM ? "request rejected: its footprint exceeds the device budget"
+                                        : "request failed: non-finite values in its solve");
     }
     if (u) {
       if (n != (long long)r.u.size()) return fail(DGS_ERR_INVALID, "u has the wrong length");

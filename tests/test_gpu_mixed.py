@@ -8,11 +8,12 @@ accumulates in FP32.  Each entry of du_S = A_S^-1 r_S is a sum of n_S
 products, so its error is bounded by about (n_S + 2) u32 sum_j |a_ij r_j|;
 the tests take that bound with the largest n_S of the level, relative to the
 largest |du| (the sums of absolute products stay within a small factor of it
-for these SPD inverses, which the measured errors, a few 1e-7, confirm).
+for these SPD inverses: the measured step errors are 0.7 to 3e-7, about
+50 times below the bound).
 The residual, the weighted scatter and everything outside the subdomain
 solves stay FP64, so the step's error is that of du alone; a V-cycle repeats
 the step 3 + 3 times per level and the errors add, so its bound is six times
-larger per level."""
+larger per level (measured: below 1e-8 relative to the largest |z|)."""
 import numpy as np
 import pytest
 

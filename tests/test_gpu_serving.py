@@ -1,6 +1,8 @@
-"""GPU tests of the continuous-batching server: every request's result is
-bit-identical alone and in a mix, admission respects the device budget, and
-results satisfy the oracle's DG equations."""
+"""GPU tests of the continuous-batching server: on the per-request path
+every request's result is bit-identical alone and in a mix; on the
+cross-request batched path (one launch per phase over all active requests)
+every result matches its solo solve to the solution tolerance; admission
+respects the device budget, and results satisfy the oracle's DG equations."""
 import numpy as np
 import pytest
 
@@ -38,7 +40,7 @@ def test_mix_equals_alone(precision, host_threads):
     import paper_2111_06767_amd as dg
     announce(f"serving mix vs alone {precision} host_threads={host_threads}")
     srv = dg.Server(hbm_budget_bytes=32e9, max_active=4, precision=precision, max_iter=60,
-                    host_threads=host_threads)
+                    host_threads=host_threads, batched=False)
     ids = {}
     for i, (el, p, side) in enumerate(REQS):
         f = _f(el, p, side, 1000 + i)
@@ -155,7 +157,7 @@ def test_reused_problems_give_the_bits_of_fresh_ones(precision):
     shapes = [((2, 3, 2), 3, 1.0), ((3, 2, 2), 4, 2.0), ((2, 2, 2), 5, 1.0)]
     reqs = [shapes[i % 3] + (90 + i,) for i in range(9)]
     srv = dg.Server(hbm_budget_bytes=32e9, max_active=2, precision=precision, max_iter=60,
-                    host_threads=2)
+                    host_threads=2, batched=False)
     ids = []
     for el, p, side, seed in reqs:
         f = _f(el, p, side, seed)
@@ -193,3 +195,72 @@ def test_server_memory_from_the_callers_allocator():
     assert alloc.allocated > 0 and not alloc.live
     for a, b in zip(*results):
         assert np.array_equal(a, b)
+
+
+# grids with single-element coarsest levels (1x1x1, 2x1x1), odd counts, and
+# p = 8 (81 lanes per element: two wavefronts per workgroup)
+BATCH_REQS = REQS + [((1, 1, 1), 5, 1.0), ((2, 1, 1), 8, 2.0), ((3, 5, 2), 3, 3.0),
+                     ((4, 4, 4), 7, 1.0), ((2, 2, 4), 8, 4.0)]
+
+
+def _oracle_residual(el, p, side, f, u):
+    m = omesh.BoxMesh((0, 0, 0), (side,) * 3, el, p)
+    b = oop.apply_mass(m, f.reshape(m.E, m.N, m.N, m.N)).reshape(-1)
+    r = b - oop.apply_operator(m, u.reshape(m.E, m.N, m.N, m.N), 1.5).reshape(-1)
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("restart", [0, 4])
+def test_batched_mix_matches_alone(precision, restart):
+    """The batched path advances all requests together through shared
+    launches (every request's elements in one operator launch per phase,
+    every request's classes in one GEMM per precision).  Its GEMM tiles and
+    split-K parts differ from the solo solver's autotuned ones, so the
+    subdomain corrections round differently: each result is compared with its
+    solo solve to a relative 1e-9 (the solution tolerance of the solver
+    tests), with the
+    same iteration count within one, a true residual at 1e-10, and the
+    oracle's residual of the result at 1e-10."""
+    import paper_2111_06767_amd as dg
+    announce(f"batched serving vs alone {precision} restart={restart}")
+    srv = dg.Server(hbm_budget_bytes=32e9, max_active=8, precision=precision, max_iter=60,
+                    restart=restart, batched=True)
+    ids = {}
+    for i, (el, p, side) in enumerate(BATCH_REQS):
+        f = _f(el, p, side, 4000 + i)
+        ids[srv.submit((0, 0, 0), (side,) * 3, el, p, f)] = (el, p, side, f)
+    while srv.step() != (0, 0):
+        pass
+    steps, bsteps, launches, peak = srv.counters()
+    assert peak >= 4 and bsteps > 0
+    for rid in srv.finished():
+        u, st, times = srv.fetch(rid)
+        el, p, side, f = ids[rid]
+        ua, sta = _alone(el, p, side, f, precision=precision, max_iter=60, restart=restart)
+        assert st["converged"] and st["rel_residual"] <= 1e-10, (el, p, st)
+        assert abs(st["iterations"] - sta["iterations"]) <= 1, (el, p, st["iterations"],
+                                                               sta["iterations"])
+        assert np.linalg.norm(u - ua) / np.linalg.norm(ua) <= 1e-9, (el, p)
+        assert _oracle_residual(el, p, side, f, u) <= 1e-10, (el, p)
+    srv.close()
+
+
+def test_batched_launches_do_not_grow_with_the_number_of_requests():
+    """Kernel launches per engine step stay flat as the batch grows: one
+    launch per phase covers every request."""
+    import paper_2111_06767_amd as dg
+    announce("batched launches per step")
+    per_step = {}
+    for count in (1, 8):
+        srv = dg.Server(hbm_budget_bytes=32e9, max_active=count, precision="mixed", max_iter=60)
+        for i in range(count):
+            el, p, side = (3, 3, 2), 4, 1.0  # one shape: the same cycle schedule
+            srv.submit((0, 0, 0), (side,) * 3, el, p, _f(el, p, side, 5000 + i))
+        while srv.step() != (0, 0):
+            pass
+        steps, bsteps, launches, peak = srv.counters()
+        assert peak == count
+        per_step[count] = launches / bsteps
+        srv.close()
+    assert per_step[8] <= 1.05 * per_step[1], per_step
