@@ -112,10 +112,11 @@ def _cpu_model():
 
 def cpu_child():
     """The cpu_baseline leg (runs in its own process, started by the parent
-    before it touches the GPU).  Builds the oracle's V-cycle of the headline
-    workload, waits for the parent's GPU solutions (a .npz path on stdin),
-    checks them through the oracle, then times one V-cycle and one operator
-    apply at 1 thread and at all cores.  Prints one JSON line."""
+    before it touches the GPU).  Waits for the parent's GPU solutions (a .npz
+    path on stdin, sent once every GPU leg is over), builds the oracle's
+    V-cycle of the headline workload, checks the solutions through the
+    oracle, then times one V-cycle and one operator apply at 1 thread and at
+    all cores.  Prints one JSON line."""
     from threadpoolctl import threadpool_info, threadpool_limits
 
     import workloads as W
@@ -125,6 +126,14 @@ def cpu_child():
         print(f"[bench:cpu] {msg}", file=sys.stderr, flush=True)
 
     n_all = int(os.environ.get("OMP_NUM_THREADS") or len(os.sched_getaffinity(0)))
+    # nothing runs here until the parent's GPU legs are over: the oracle's
+    # multi-threaded set-up would otherwise compete with the host thread that
+    # launches the GPU work, and stretch the timed GPU legs
+    line = sys.stdin.readline().strip()
+    if not line:
+        return
+    path, iters = line.split()
+    iters = int(iters)
     t0 = time.perf_counter()
     m5 = mesh.BoxMesh(C5["lower"], C5["upper"], C5["elements"], C5["p"])
     x, y, z = m5.node_coordinates()
@@ -133,12 +142,7 @@ def cpu_child():
     V5 = multigrid.VCycle(m5, 1.5, levels=C5["levels"],
                           on_level=lambda l, m: log(f"level {l} ({m.n} elements) set up"))
     t_setup = time.perf_counter() - t0
-    log(f"oracle set-up done in {t_setup:.1f} s; waiting for the GPU legs")
-    line = sys.stdin.readline().strip()
-    if not line:
-        return
-    path, iters = line.split()
-    iters = int(iters)
+    log(f"oracle set-up done in {t_setup:.1f} s")
     data = np.load(path)
     checks = {}
 
@@ -498,6 +502,28 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
     return summary, kept
 
 
+def roofline_kernels(args):
+    """Counter-collection mode for rocprofv3 --pmc runs: the 16^3 p=7 FP64
+    problem's set-up and 5 + 50 launches of its fine-level GEMM, then the
+    40^3 p=7 apply timing followed by its calibration copy, and nothing else,
+    so that each counter pass sees few dispatches.  Prints the two launch
+    times (not a benchmark line)."""
+    import torch
+    import paper_2111_06767_amd as dg
+    torch.cuda.set_device(0)
+    prob, _, _ = build_fourier(dg, C5, 5, "fp64")
+    if args.gemm_variant is not None:
+        prob.set_gemm_variant(args.gemm_variant, level=0)
+    gemm = time_subdomain_gemm(prob)
+    variant = prob.gemm_variant(0)
+    prob.close()
+    ap = time_apply(dg, (40, 40, 40), 7, reps=50, calibration_copy=True, shape=args.apply_shape)
+    print(json.dumps({"mode": "roofline kernels only", "gemm_variant": variant,
+                      "gemm_ms_per_launch": gemm["ms_per_launch"],
+                      "gemm_tflops": gemm["achieved_tflops"], "apply_shape": ap["launch_shape"],
+                      "apply_ms": ap["ms_per_apply"], "calibration_copy_bytes": 8 * ap["ndof"]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -518,14 +544,20 @@ def main():
     # that a profiled run launches the kernels an unprofiled run chose
     ap.add_argument("--gemm-variant", type=int, default=None)
     ap.add_argument("--apply-shape", type=int, default=None)
+    # counter collection: only the launches the two roofline objects come from
+    ap.add_argument("--roofline-kernels-only", action="store_true")
     ap.add_argument("--cpu-baseline-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_baseline_child:
         cpu_child()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+
+    if args.roofline_kernels_only:
+        roofline_kernels(args)
+        return
 
     # the oracle's child starts before anything here touches the GPU
     child = None if args.no_cpu_baseline else start_cpu_child()

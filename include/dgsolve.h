@@ -252,11 +252,12 @@ int dgs_get_apply_shape(const dgs_problem* prob, int level, int* shape);
  * `level` (Sec. III.D.2 subdomain solves; the variant changes the tiling and
  * the split of the K range, so results agree to rounding):
  *   levels whose classes all have at most 32 subdomains: 16 x 64 tiles with
- *   up to 16 (0), 4 (1) or 8 (2) K parts; other levels: 32 x 128 (0),
- *   64 x 128 (1) or 32 x 64 (2) tiles with up to 4 K parts.
+ *   up to 16 (0), 4 (1), 8 (2), 2 (3) or 1 (4) K parts; other levels:
+ *   32 x 128 (0), 64 x 128 (1), 32 x 64 (2), 64 x 64 (3) or 64 x 64 with a
+ *   deeper K step in FP64 (4) tiles, with up to 4 K parts.
  * The autotuner sets one per level when the problem is created;
  * dgs_set_gemm_variant overrides it (DGS_ERR_INVALID for a level outside
- * [0, levels) or a variant outside [0, 2]), dgs_get_gemm_variant reads it. */
+ * [0, levels) or a variant outside [0, 4]), dgs_get_gemm_variant reads it. */
 int dgs_set_gemm_variant(dgs_problem* prob, int level, int variant);
 int dgs_get_gemm_variant(const dgs_problem* prob, int level, int* variant);
 

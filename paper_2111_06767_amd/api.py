@@ -309,7 +309,7 @@ class Problem:
         _check(self._lib.dgs_set_apply_shape(self._h, int(level), int(shape)))
 
     def gemm_variant(self, level=0):
-        """Tile variant (0, 1, 2) of the subdomain-solve GEMM on `level`."""
+        """Tile variant (0 to 4) of the subdomain-solve GEMM on `level`."""
         v = ctypes.c_int()
         _check(self._lib.dgs_get_gemm_variant(self._h, int(level), ctypes.byref(v)))
         return v.value

@@ -14,6 +14,17 @@ __global__ void k_fill(double* x, double v, long long n) {
   if (g < n) x[g] = v;
 }
 
+// Values in [-0.5, 0.5) from a multiplicative hash of the index: operand
+// data for timing runs, whose MFMA power draw (and clock) depends on the bits.
+template <typename T>
+__global__ void k_fill_pattern(T* x, long long n) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) {
+    const unsigned h = (unsigned)(g * 2654435761ull) ^ (unsigned)(g >> 13);
+    x[g] = (T)((double)h * (1.0 / 4294967296.0) - 0.5);
+  }
+}
+
 __global__ void k_copy(double* __restrict__ y, const double* __restrict__ x, long long n) {
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (g < n) y[g] = x[g];
@@ -185,6 +196,14 @@ inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) /
 hipError_t launch_fill(double* x, double v, long long n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3(nblk(n)), dim3(256), 0, s, x, v, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_pattern(void* x, bool f32, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_fill_pattern<float>, dim3(nblk(n)), dim3(256), 0, s, (float*)x, n);
+  else
+    hipLaunchKernelGGL(k_fill_pattern<double>, dim3(nblk(n)), dim3(256), 0, s, (double*)x, n);
   return hipGetLastError();
 }
 hipError_t launch_copy(double* y, const double* x, long long n, hipStream_t s) {

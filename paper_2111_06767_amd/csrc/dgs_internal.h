@@ -227,13 +227,14 @@ hipError_t launch_gather(int N, bool f32, const double* r, void* rs, const int* 
 // for every class c (B_c the stored transposed inverse, or with use_op the
 // stored A_S and factor scale_op).  Output tiles of BM rows (subdomains) by
 // BN columns: BM = 16, BN = 64 when no class has more than kGemmSmallCount
-// subdomains, with the K range split into up to 16 (variant 0), 4 (variant 1)
-// or 8 (variant 2) partial products; else BM x BN = 32 x kGemmN (variant 0),
-// 64 x kGemmN (variant 1) or 32 x 64 (variant 2) and up to 4 parts.  The
-// set-up autotuner picks one per level.
+// subdomains, with the K range split into up to 16 (variant 0), 4 (variant 1),
+// 8 (variant 2), 2 (variant 3) or 1 (variant 4) partial products; else
+// BM x BN = 32 x kGemmN (variant 0), 64 x kGemmN (variant 1), 32 x 64
+// (variant 2), 64 x 64 (variant 3) or 64 x 64 with twice the K step in FP64
+// (variant 4), and up to 4 parts.  The set-up autotuner picks one per level.
 constexpr int kGemmN = 128, kGemmSmallCount = 32;
 constexpr int kMaxParts = 16;  // split-K partial products (1, 2, 4, 8 or 16)
-constexpr int kGemmVariants = 3;
+constexpr int kGemmVariants = 5;
 struct GemmPlan {
   std::vector<GemmTile> tiles;
   bool small = false;
@@ -297,6 +298,8 @@ hipError_t launch_prolongate_add(int N, const double* coarse, double* fine, cons
 
 // Vector kernels.
 hipError_t launch_fill(double* x, double v, long long n, hipStream_t s);
+// FP32 or FP64 pseudo-random values in [-0.5, 0.5) (timing operands)
+hipError_t launch_fill_pattern(void* x, bool f32, long long n, hipStream_t s);
 hipError_t launch_copy(double* y, const double* x, long long n, hipStream_t s);
 hipError_t launch_axpy(double* y, double a, const double* x, long long n, hipStream_t s);
 // Multi-dot: h[i] = <V_i, w> for i < m (V_i = V + i * ldv); partial sums in

@@ -267,6 +267,117 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
       }
 }
 
+// Double-buffered form of the grouped GEMM: two LDS stages and two register
+// stages.  The loads of K step k + 2 are issued before step k is multiplied,
+// so they have two steps of MFMA work to land, and one barrier per step
+// orders the LDS stages.  Same tiles, K ranges and summation order as
+// k_sub_gemm.
+template <typename T, int WM, int WN, int TM, int TN, int BK>
+__global__ void __launch_bounds__(256)
+k_sub_gemm_db(const T* __restrict__ rs, T* __restrict__ du, long long pstride,
+              const ClassInfo* __restrict__ cls, const GemmTile* __restrict__ tiles, int use_op) {
+  constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
+  constexpr int PA = sizeof(T) == 4 ? 4 : 2, PB = sizeof(T) == 4 ? 16 : 8;
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(VW)));
+  constexpr int AV = BM * BK / VW, BV = BK * BN / VW;
+  constexpr int NAV = AV / 256, NBV = BV / 256;
+  static_assert(AV % 256 == 0 && BV % 256 == 0 && BK % VW == 0, "tile");
+  typedef typename Mfma<T>::v4 v4;
+  __shared__ __attribute__((aligned(16))) T As[2][BM][BK + PA];
+  __shared__ __attribute__((aligned(16))) T Bs[2][BK][BN + PB];
+  const GemmTile tl = tiles[blockIdx.x];
+  const ClassInfo ci = cls[tl.cls];
+  const int ld = ci.ld;
+  const T* A = rs + ci.rs_off;
+  T* C = du + tl.part * pstride + ci.rs_off;
+  const T* B = (const T*)(use_op ? ci.op : ci.inv);
+  const int m0 = tl.m0, n0 = tl.n0, kbeg = tl.k0;
+  const int nk = (tl.k1 - tl.k0) / BK;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = wave / WN, wn = wave % WN;
+  v4 acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = v4{0, 0, 0, 0};
+
+  vec ra0[NAV], rb0[NBV], ra1[NAV], rb1[NBV];
+  auto load = [&](vec* ra, vec* rb, int step) {
+    const int k0 = kbeg + step * BK;
+#pragma unroll
+    for (int q = 0; q < NAV; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / (BK / VW), c = idx % (BK / VW);
+      ra[q] = *(const vec*)(A + (long long)(m0 + r) * ld + k0 + c * VW);
+    }
+#pragma unroll
+    for (int q = 0; q < NBV; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / (BN / VW), c = idx % (BN / VW);
+      rb[q] = *(const vec*)(B + (long long)(k0 + r) * ld + n0 + c * VW);
+    }
+  };
+  auto store = [&](int buf, const vec* ra, const vec* rb) {
+#pragma unroll
+    for (int q = 0; q < NAV; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / (BK / VW), c = idx % (BK / VW);
+      *(vec*)&As[buf][r][c * VW] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NBV; ++q) {
+      const int idx = tid + 256 * q;
+      const int r = idx / (BN / VW), c = idx % (BN / VW);
+      *(vec*)&Bs[buf][r][c * VW] = rb[q];
+    }
+  };
+  auto compute = [&](int buf) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      T av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[buf][(wm * TM + a) * 16 + (lane & 15)][kr];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[buf][kr][(wn * TN + b) * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
+    }
+  };
+  // at the top of step k, LDS stage k % 2 holds tile k and register stage
+  // (k + 1) % 2 holds (or is still loading) tile k + 1
+  if (nk > 0) load(ra0, rb0, 0);
+  if (nk > 1) load(ra1, rb1, 1);
+  if (nk > 0) store(0, ra0, rb0);
+  __syncthreads();
+  for (int k = 0; k < nk; k += 2) {
+    if (k + 2 < nk) load(ra0, rb0, k + 2);
+    compute(0);
+    if (k + 1 < nk) store(1, ra1, rb1);
+    __syncthreads();
+    if (k + 1 < nk) {
+      if (k + 3 < nk) load(ra1, rb1, k + 3);
+      compute(1);
+      if (k + 2 < nk) store(0, ra0, rb0);
+      __syncthreads();
+    }
+  }
+  const T sc = (T)(use_op ? ci.scale_op : ci.scale);
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + (wm * TM + a) * 16 + Mfma<T>::row(lane, r);
+        const int col = n0 + (wn * TN + b) * 16 + (lane & 15);
+        C[(long long)row * ld + col] = sc * acc[a][b][r];
+      }
+}
+
 template <typename T>
 __global__ void k_reduce_parts(T* __restrict__ out, const T* __restrict__ parts, int np,
                                long long stride, long long total) {
@@ -530,19 +641,21 @@ GemmPlan plan_subdomain_gemm(const std::vector<ClassInfo>& cls, int variant, int
   for (const ClassInfo& c : cls) any_big = any_big || c.count > kGemmSmallCount;
   // the few partly filled tiles of small classes run beside the large ones
   plan.small = !any_big;
-  const int bm = plan.small ? 16 : (variant == 1 ? 64 : 32);
+  const int bm = plan.small ? 16 : ((variant == 1 || variant == 3) ? 64 : 32);
   // few-subdomain levels: 16 x 64 tiles, twice as many and half as long as
   // 16 x 128 ones (these launches are latency-bound); variant 2 of the large
   // levels: 32 x 64 tiles, for levels whose 32 x 128 tiles leave the compute
-  // units short of work
-  const int bn = (plan.small || variant == 2) ? 64 : kGemmN;
+  // units short of work; variants 3 (64 x 64) and 4 (32 x 64): the
+  // double-buffered kernel, which keeps two K steps of loads in flight
+  const int bn = (plan.small || variant == 2 || variant >= 3) ? 64 : kGemmN;
   // split K until there are enough tiles to fill the 256 compute units; the
   // short K loops of few-subdomain levels are latency-bound, so they may
   // split further (up to 16 parts in variant 0, 4 in variant 1: more parts
   // shorten the GEMM and lengthen the scatter that sums them)
   int base = 0;
   for (const ClassInfo& c : cls) base += ((c.count + bm - 1) / bm) * ((c.n + bn - 1) / bn);
-  int max_parts = plan.small ? (variant == 1 ? 4 : (variant == 2 ? 8 : kMaxParts)) : 4;
+  static const int small_parts[kGemmVariants] = {kMaxParts, 4, 8, 2, 1};
+  int max_parts = plan.small ? small_parts[variant] : 4;
   if (parts_cap > 0) max_parts = std::min(max_parts, parts_cap);
   plan.kparts = 1;
   while (plan.kparts < max_parts && base * plan.kparts < 1024) plan.kparts *= 2;
@@ -579,6 +692,12 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
     else if (variant == 2)
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 1, 2, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
+    else if (variant == 3)
+      hipLaunchKernelGGL((k_sub_gemm_db<float, 2, 2, 2, 2, 32>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
+    else if (variant == 4)
+      hipLaunchKernelGGL((k_sub_gemm_db<float, 2, 2, 1, 2, 32>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
     else
       hipLaunchKernelGGL((k_sub_gemm<float, 2, 2, 2, 4, 32>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
@@ -593,6 +712,12 @@ hipError_t launch_subdomain_gemm(bool f32, const void* rs, void* du, long long p
                          tiles, use_op);
     else if (variant == 2)
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 1, 2, 16>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
+    else if (variant == 3)
+      hipLaunchKernelGGL((k_sub_gemm_db<double, 2, 2, 2, 2, 16>), grid, block, 0, s, a, c, ps, cls,
+                         tiles, use_op);
+    else if (variant == 4)
+      hipLaunchKernelGGL((k_sub_gemm_db<double, 2, 2, 1, 2, 16>), grid, block, 0, s, a, c, ps, cls,
                          tiles, use_op);
     else
       hipLaunchKernelGGL((k_sub_gemm<double, 2, 2, 2, 4, 16>), grid, block, 0, s, a, c, ps, cls,

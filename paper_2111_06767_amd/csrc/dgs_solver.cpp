@@ -884,7 +884,9 @@ void autotune_gemm(dgs_problem* P, hipStream_t s) {
     }
     if (!cached) {
       const size_t es = L.f32 ? sizeof(float) : sizeof(double);
-      HIP_OK(hipMemsetAsync(L.d_rs, 0, es * (size_t)L.rs_total, s));
+      // pseudo-random operands: the MFMA clock under load depends on the data,
+      // and zeros would favour tiles that run hotter on real residuals
+      HIP_OK(launch_fill_pattern(L.d_rs, L.f32, L.rs_total, s));
       HIP_OK(launch_fill(L.d_u, 0.0, L.E * (long long)N * N * N, s));
       float best_ms = 1e30f;
       for (int v = 0; v < kGemmVariants; ++v) {
@@ -903,6 +905,13 @@ void autotune_gemm(dgs_problem* P, hipStream_t s) {
           best = v;
         }
       }
+      // the class blocks' padding must read as zeros again, and nothing
+      // later expects what the timing runs left in u or the products
+      HIP_OK(hipMemsetAsync(L.d_rs, 0, es * (size_t)L.rs_total, s));
+      int mp = 1;
+      for (int v = 0; v < kGemmVariants; ++v) mp = std::max(mp, L.kparts_of[v]);
+      HIP_OK(hipMemsetAsync(L.d_du, 0, es * (size_t)L.rs_total * mp, s));
+      HIP_OK(launch_fill(L.d_u, 0.0, L.E * (long long)N * N * N, s));
       std::lock_guard<std::mutex> lk(g_tune_mutex);
       g_tuned_gemm[key] = best;
     }
