@@ -135,6 +135,38 @@ def puncture_background(pp: Punctures, x, y, z, r_min: float = 1e-14):
 
 
 # ---------------------------------------------------------------------------
+# A coupled linear system of several variables (the structure of linearised
+# XCTS-like equations, Sec. IV.B, on a flat box)
+# ---------------------------------------------------------------------------
+SEED_SYSTEM = 21
+# Neumann faces (f = 2 d + side) of each variable of the standard system:
+# variable 0 plays the conformal factor with Neumann conditions on three
+# faces, the others Dirichlet conditions or one Neumann face
+SYSTEM_NEUMANN = ((0, 2, 4), (), (1,), (), ())
+
+
+def system_coupling(seed: int, nvars: int, x, y, z, strength: float = 10.0) -> np.ndarray:
+    """Pointwise coupling field c_AB(x) of shape (nvars, nvars, npoints):
+    symmetric in A, B, with diagonal strength * (1 + 0.5 cos(.)) and
+    off-diagonal entries of size at most strength * 0.25 / nvars (positive
+    definite at every point by diagonal dominance), smooth random phases."""
+    rng = np.random.default_rng(seed)
+    x, y, z = (np.asarray(v, float).reshape(-1) for v in (x, y, z))
+    c = np.empty((nvars, nvars, x.size))
+    for a in range(nvars):
+        for b in range(a, nvars):
+            k = rng.uniform(1.0, 3.0, 3)
+            ph = rng.uniform(0.0, 2.0 * np.pi, 3)
+            wave = np.cos(k[0] * np.pi * x + ph[0]) * np.cos(k[1] * np.pi * y + ph[1]) \
+                * np.cos(k[2] * np.pi * z + ph[2])
+            if a == b:
+                c[a, a] = strength * (1.0 + 0.5 * wave)
+            else:
+                c[a, b] = c[b, a] = strength * 0.25 / nvars * wave
+    return c
+
+
+# ---------------------------------------------------------------------------
 # Generic seeded fields and the request stream of the serving workload
 # ---------------------------------------------------------------------------
 def random_normal(seed: int, n: int) -> np.ndarray:
