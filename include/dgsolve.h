@@ -355,6 +355,59 @@ int dgs_server_finished(dgs_server* server, long long* ids, int capacity, int* c
 int dgs_server_fetch(dgs_server* server, long long id, double* u, long long n, dgs_stats* stats,
                      double times[4]);
 
+/* ------------------------------------------------------------------------
+ * Systems of several variables (Sec. III.E.1, eq. lapl_approx)
+ *
+ * nvars (1..5) variables u_a on one box grid.  Variable a has homogeneous
+ * Neumann conditions on the faces of neumann_faces[a] (bit f = 2 d + side,
+ * at least one face Dirichlet) and Dirichlet conditions elsewhere; the
+ * operator is
+ *     (A_sys u)_a = A^(a) u_a + sum_b D_ab u_b
+ * with A^(a) the DG Poisson operator under a's conditions (Sec. II) and
+ * pointwise couplings D_ab as they enter the discrete operator (for a PDE
+ * term c_ab u_b, D_ab = M c_ab with the lumped mass), the form of the
+ * linearised equations of a coupled system (eq. linearized).
+ *
+ * Preconditioner: the multigrid V-cycle (Sec. III.C) with additive Schwarz
+ * smoothing (Sec. III.D) on the whole system; each subdomain problem
+ * (blockdiag_a A_S^(a) + D_S) du_S = r_S is solved by opt->subdomain_iters
+ * (k, 0..8) iterations of right-preconditioned GMRES whose preconditioner is
+ * the Laplacian approximation: one Poisson inverse per variable, with that
+ * variable's boundary types on the subdomain's external faces
+ * (laplacian_bc = 0, matched) or the Dirichlet one for every variable
+ * (laplacian_bc = 1, the approximation the paper compares with in Sec. IV.B);
+ * k = 0 applies the approximation alone.  Coarse couplings are restricted,
+ * D_{l+1} = R D_l.  Subdomains are limited to 2048 points (p <= 8 with
+ * overlap 2; DGS_ERR_INVALID beyond).
+ *
+ * Vectors are device arrays of nvars * ndof doubles, variable a's field at
+ * a * ndof in the canonical layout; D is nvars * nvars fields (D_ab at
+ * (a * nvars + b) * ndof).  opt as for dgs_create_problem (its neumann_faces
+ * is ignored); device memory comes from hipMalloc.  All calls are ordered on
+ * `stream` (NULL: the default stream).
+ * ------------------------------------------------------------------------ */
+typedef struct dgs_system dgs_system; /* opaque, owned by the library */
+
+int dgs_create_system(const dgs_domain* domain, const int elements[3], int p, double penalty,
+                      int nvars, const int* neumann_faces, int laplacian_bc,
+                      const dgs_options* opt, void* stream, dgs_system** out);
+int dgs_destroy_system(dgs_system* sys);
+/* Points per variable (ndof). */
+int dgs_system_num_dofs(const dgs_system* sys, long long* n);
+/* Copy the couplings D (device, nvars * nvars * ndof; NULL: no coupling)
+ * and restrict them to the coarse levels. */
+int dgs_system_set_coupling(dgs_system* sys, const double* D, void* stream);
+/* y = A_sys u (device vectors, no overlap). */
+int dgs_system_apply(dgs_system* sys, const double* u, double* y, void* stream);
+/* `steps` Schwarz steps on the finest level, in place on u. */
+int dgs_system_smooth(dgs_system* sys, const double* b, double* u, int steps, void* stream);
+/* z = one V-cycle applied to r (z starts from zero). */
+int dgs_system_precondition(dgs_system* sys, const double* r, double* z, void* stream);
+/* FGMRES (Saad Alg. 9.6, restarts of opt->restart) preconditioned by the
+ * V-cycle, from the initial guess in u, to the relative residual opt->rtol
+ * confirmed by the true residual; DGS_OK or DGS_NOT_CONVERGED. */
+int dgs_system_solve(dgs_system* sys, const double* b, double* u, dgs_stats* stats, void* stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* dgs_last_error(void);
 

@@ -5,4 +5,5 @@ the C ABI of ``include/dgsolve.h``); this package only marshals arguments.
 """
 from .api import (DGS_ERR_HIP, DGS_ERR_INVALID, DGS_ERR_NONFINITE, DGS_ERR_OOM, DGS_FP64,  # noqa: F401
                   DGS_MIXED, DGS_NOT_CONVERGED, DGS_OK, EXPORTED, DgsError, Options, Problem,
-                  Server, TorchAllocator, default_options, lgl_nodes, load_library, points)
+                  Server, System, TorchAllocator, default_options, lgl_nodes, load_library,
+                  points)

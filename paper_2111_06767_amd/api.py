@@ -33,6 +33,8 @@ EXPORTED = (
     "dgs_set_apply_shape", "dgs_get_apply_shape", "dgs_set_gemm_variant", "dgs_get_gemm_variant",
     "dgs_server_submit_puncture", "dgs_cg_solve", "dgs_grid_coordinates",
     "dgs_cg_solve_noalloc", "dgs_server_counters",
+    "dgs_create_system", "dgs_destroy_system", "dgs_system_num_dofs", "dgs_system_set_coupling",
+    "dgs_system_apply", "dgs_system_smooth", "dgs_system_precondition", "dgs_system_solve",
 )
 
 
@@ -133,6 +135,17 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_get_apply_shape.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.dgs_set_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.c_int]
     lib.dgs_get_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.dgs_create_system.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                      ctypes.POINTER(Options), P, ctypes.POINTER(P)]
+    lib.dgs_destroy_system.argtypes = [P]
+    lib.dgs_system_num_dofs.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
+    lib.dgs_system_set_coupling.argtypes = [P, dp, P]
+    lib.dgs_system_apply.argtypes = [P, dp, dp, P]
+    lib.dgs_system_smooth.argtypes = [P, dp, dp, ctypes.c_int, P]
+    lib.dgs_system_precondition.argtypes = [P, dp, dp, P]
+    lib.dgs_system_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
     lib.dgs_last_error.argtypes = []
     lib.dgs_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -402,6 +415,87 @@ def points(lower, upper, elements, p):
         ctypes.byref(dom), (ctypes.c_int * 3)(*elements), int(p),
         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n))
     return out.reshape(3, n)
+
+
+class System:
+    """A system of nvars variables with per-variable Neumann faces and
+    pointwise couplings (see dgs_create_system).  Vectors are float64 device
+    tensors of nvars * ndof entries, variable a's field at a * ndof;
+    laplacian_bc "matched" or "dirichlet" selects the subdomain
+    preconditioner's boundary types."""
+
+    def __init__(self, lower, upper, elements, p, neumann_faces, laplacian_bc="matched",
+                 penalty=1.5, options: Options | None = None, stream=None, **opts):
+        lib = load_library()
+        self._lib = lib
+        self._h = None
+        self.options = options if options is not None else default_options(**opts)
+        masks = []
+        for faces in neumann_faces:
+            m = 0
+            for f in faces:
+                m |= 1 << int(f)
+            masks.append(m)
+        self.nvars = len(masks)
+        dom = Domain((ctypes.c_double * 3)(*lower), (ctypes.c_double * 3)(*upper))
+        h = ctypes.c_void_p()
+        _check(lib.dgs_create_system(ctypes.byref(dom), (ctypes.c_int * 3)(*elements), int(p),
+                                     float(penalty), self.nvars,
+                                     (ctypes.c_int * max(1, self.nvars))(*masks),
+                                     {"matched": 0, "dirichlet": 1}[laplacian_bc],
+                                     ctypes.byref(self.options), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_longlong()
+        _check(lib.dgs_system_num_dofs(h, ctypes.byref(n)))
+        self.ndof = n.value
+        self.size = self.nvars * self.ndof
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dgs_destroy_system(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self):
+        import torch
+        return torch.empty(self.size, dtype=torch.float64, device="cuda")
+
+    def set_coupling(self, D=None, stream=None):
+        """Couplings D (nvars * nvars * ndof, D_ab at (a * nvars + b) * ndof); None: none."""
+        ptr = ctypes.c_void_p(None) if D is None else _ptr(D, self.nvars * self.size, "D")
+        _check(self._lib.dgs_system_set_coupling(self._h, ptr, _stream(stream)))
+
+    def apply(self, u, out=None, stream=None):
+        out = self._new() if out is None else out
+        _check(self._lib.dgs_system_apply(self._h, _ptr(u, self.size, "u"), _ptr(out, self.size, "out"),
+                                          _stream(stream)))
+        return out
+
+    def smooth(self, b, u, steps=1, stream=None):
+        _check(self._lib.dgs_system_smooth(self._h, _ptr(b, self.size, "b"), _ptr(u, self.size, "u"),
+                                           int(steps), _stream(stream)))
+        return u
+
+    def precondition(self, r, out=None, stream=None):
+        out = self._new() if out is None else out
+        _check(self._lib.dgs_system_precondition(self._h, _ptr(r, self.size, "r"),
+                                                 _ptr(out, self.size, "z"), _stream(stream)))
+        return out
+
+    def solve(self, b, u=None, history=256, stream=None):
+        import torch
+        if u is None:
+            u = torch.zeros(self.size, dtype=torch.float64, device="cuda")
+        st, hist = _make_stats(history)
+        code = _check(self._lib.dgs_system_solve(self._h, _ptr(b, self.size, "b"),
+                                                 _ptr(u, self.size, "u"), ctypes.byref(st),
+                                                 _stream(stream)), allow_not_converged=True)
+        return u, _stats_dict(st, hist, code)
 
 
 class Server:

@@ -284,6 +284,27 @@ hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride
 
 // u += sum_S R_S^T (w_S du_S), summing `parts` split-K partials (1, 2, 4, 8, 16) of du.
 // assign: u = (the sum) instead of u += (the sum), for a u that starts at zero.
+// Subdomain GMRES of a system of nv <= kSysMaxVars variables whose rows sit
+// at a * stride (see k_sys_arnoldi); D holds the pointwise couplings D_ab as
+// nv * nv fields of nd points.  Subdomains of at most 2048 points.
+constexpr int kSysMaxVars = 5;
+constexpr int kSysMaxRows = 2048;  // subdomain points of the system Arnoldi step (256 x 8)
+hipError_t launch_sys_start(bool f32, int nv, const void* rs, void* V0, double* beta,
+                            long long stride, const int* elem_class, const long long* elem_row,
+                            const ClassInfo* cls, int E, hipStream_t s);
+hipError_t launch_sys_arnoldi(int N, bool f32, int j, int kmax, int nv, const void* W, void* V,
+                              const void* Zj, long long stride, const double* D, long long nd,
+                              double* H, const int* elem_class, const long long* elem_row,
+                              const int* nbr, const ClassInfo* cls, const int* seg_loc, int E,
+                              int max_n, hipStream_t s);
+hipError_t launch_sys_finish(bool f32, int kmax, int nv, const void* Z, long long stride,
+                             const double* H, const double* beta, void* du, const int* elem_class,
+                             const long long* elem_row, const ClassInfo* cls, int E,
+                             hipStream_t s);
+// y_a += sign * sum_b D_ab u_b at every point (nv fields of nd points each)
+hipError_t launch_sys_couple(double* y, const double* u, const double* D, int nv, long long nd,
+                             double sign, hipStream_t s);
+
 hipError_t launch_scatter(int N, bool f32, double* u, const void* du, int parts,
                           long long part_stride, const double* weights, const PullEntry* pull,
                           int nov, long long E, hipStream_t s, bool assign = false);

@@ -494,6 +494,44 @@ k_sub_arnoldi(int j, int kmax, const T* __restrict__ W, T* __restrict__ V, const
   }
 }
 
+// Least squares min |beta e1 - H y| of one subdomain's (kmax+1) x kmax
+// Hessenberg matrix Hs (column-major) by Givens rotations, stopping at a
+// breakdown column (zero subdiagonal); returns the number of columns used
+// (0 for beta = 0) and writes y.  One thread.
+__device__ int small_lsq(const double* Hs, int kmax, double beta, double* y) {
+  double h[9][8], g[9];
+  int m = kmax;
+  for (int jj = 0; jj < kmax; ++jj)
+    if (Hs[jj * (kmax + 1) + jj + 1] == 0.0) {
+      m = jj + 1;
+      break;
+    }
+  for (int jj = 0; jj < m; ++jj)
+    for (int ii = 0; ii <= m; ++ii) h[ii][jj] = (ii <= jj + 1) ? Hs[jj * (kmax + 1) + ii] : 0.0;
+  for (int ii = 0; ii <= m; ++ii) g[ii] = 0.0;
+  g[0] = beta;
+  if (g[0] == 0.0) return 0;
+  for (int jj = 0; jj < m; ++jj) {
+    const double a = h[jj][jj], b = h[jj + 1][jj];
+    const double r = sqrt(a * a + b * b);
+    const double c = a / r, sn = b / r;
+    for (int q = jj; q < m; ++q) {
+      const double t0 = h[jj][q], t1 = h[jj + 1][q];
+      h[jj][q] = c * t0 + sn * t1;
+      h[jj + 1][q] = -sn * t0 + c * t1;
+    }
+    const double g0 = g[jj], g1 = g[jj + 1];
+    g[jj] = c * g0 + sn * g1;
+    g[jj + 1] = -sn * g0 + c * g1;
+  }
+  for (int ii = m - 1; ii >= 0; --ii) {
+    double t = g[ii];
+    for (int q = ii + 1; q < m; ++q) t -= h[ii][q] * y[q];
+    y[ii] = t / h[ii][ii];
+  }
+  return m;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kSubThreads)
 k_sub_finish(int kmax, const T* __restrict__ Z, long long stride, const double* __restrict__ H,
@@ -506,51 +544,175 @@ k_sub_finish(int kmax, const T* __restrict__ Z, long long stride, const double* 
   if (e >= E) return;
   const int n = cls[elem_class[e] & kGroupMask].n;
   const long long row = elem_row[e];
-  if (threadIdx.x == 0) {
-    // least squares min |beta e1 - H y| by Givens rotations, stopping at a
-    // breakdown column (zero subdiagonal)
-    double h[9][8], g[9];
-    const double* Hs = H + (long long)e * (kmax + 1) * kmax;
-    int m = kmax;
-    for (int jj = 0; jj < kmax; ++jj)
-      if (Hs[jj * (kmax + 1) + jj + 1] == 0.0) {
-        m = jj + 1;
-        break;
-      }
-    for (int jj = 0; jj < m; ++jj)
-      for (int ii = 0; ii <= m; ++ii) h[ii][jj] = (ii <= jj + 1) ? Hs[jj * (kmax + 1) + ii] : 0.0;
-    for (int ii = 0; ii <= m; ++ii) g[ii] = 0.0;
-    g[0] = beta[e];
-    if (g[0] == 0.0) {
-      m = 0;
-    } else {
-      for (int jj = 0; jj < m; ++jj) {
-        const double a = h[jj][jj], b = h[jj + 1][jj];
-        const double r = sqrt(a * a + b * b);
-        const double c = a / r, sn = b / r;
-        for (int q = jj; q < m; ++q) {
-          const double t0 = h[jj][q], t1 = h[jj + 1][q];
-          h[jj][q] = c * t0 + sn * t1;
-          h[jj + 1][q] = -sn * t0 + c * t1;
-        }
-        const double g0 = g[jj], g1 = g[jj + 1];
-        g[jj] = c * g0 + sn * g1;
-        g[jj + 1] = -sn * g0 + c * g1;
-      }
-      for (int ii = m - 1; ii >= 0; --ii) {
-        double t = g[ii];
-        for (int q = ii + 1; q < m; ++q) t -= h[ii][q] * y[q];
-        y[ii] = t / h[ii][ii];
-      }
-    }
-    mm = m;
-  }
+  if (threadIdx.x == 0) mm = small_lsq(H + (long long)e * (kmax + 1) * kmax, kmax, beta[e], y);
   __syncthreads();
   const int m = mm;
   for (int i = threadIdx.x; i < n; i += kSubThreads) {
     double v = 0.0;
     for (int jj = 0; jj < m; ++jj) v += y[jj] * (double)Z[jj * stride + row + i];
     du[row + i] = (T)v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Subdomain GMRES(k) of a system of nv variables (Sec. III.E.1): the
+// subdomain vector stacks the variables' rows, variable a's at a * stride in
+// every buffer (the variables share one class structure, so a subdomain's
+// rows sit at the same offset for all of them).  The operator is
+// blockdiag_a(A_S^(a)) + D_S with pointwise couplings D_ab; the GEMMs with
+// each variable's Poisson inverse and subdomain operator run between the
+// Arnoldi steps, like the scalar form above.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kSubThreads)
+k_sys_start(int nv, const T* __restrict__ rs, T* __restrict__ V0, double* __restrict__ beta,
+            long long stride, const int* __restrict__ elem_class,
+            const long long* __restrict__ elem_row, const ClassInfo* __restrict__ cls, int E) {
+  __shared__ double red[kSubThreads / 64];
+  const int e = blockIdx.x;
+  if (e >= E) return;
+  const int n = cls[elem_class[e] & kGroupMask].n;
+  const long long row = elem_row[e];
+  double s = 0.0;
+  for (int a = 0; a < nv; ++a)
+    for (int i = threadIdx.x; i < n; i += kSubThreads) {
+      const double x = (double)rs[a * stride + row + i];
+      s += x * x;
+    }
+  const double b = sqrt(block_reduce_sum(s, red));
+  if (threadIdx.x == 0) beta[e] = b;
+  for (int a = 0; a < nv; ++a)
+    for (int i = threadIdx.x; i < n; i += kSubThreads)
+      V0[a * stride + row + i] = b > 0.0 ? (T)((double)rs[a * stride + row + i] / b) : (T)0;
+}
+
+// One Arnoldi step j: w_a = W_a + sum_b D_ab z_b at every subdomain point
+// (W_a = A_S^(a) z_a from the GEMM), classical Gram-Schmidt against the
+// stacked basis vectors 0..j, the Hessenberg column, and v_{j+1}.  Basis slot
+// i of V is at i * nv * stride.  Subdomains of at most kSubThreads *
+// kSubPerSmall points and at most kSysMaxVars variables.
+template <typename T>
+__global__ void __launch_bounds__(kSubThreads)
+k_sys_arnoldi(int j, int kmax, int nv, const T* __restrict__ W, T* __restrict__ V,
+              const T* __restrict__ Zj, long long stride, const double* __restrict__ D,
+              long long nd, double* __restrict__ H, const int* __restrict__ elem_class,
+              const long long* __restrict__ elem_row, const int* __restrict__ nbr,
+              const ClassInfo* __restrict__ cls, const int* __restrict__ seg_loc, int E, int N) {
+  __shared__ double red[kSubThreads / 64];
+  __shared__ long long src[7];
+  const int N3 = N * N * N;
+  const int e = blockIdx.x;
+  if (e >= E) return;
+  const int cv = elem_class[e];
+  const int code = cv >> 24;
+  const ClassInfo ci = cls[cv & kGroupMask];
+  const int n = ci.n;
+  const long long row = elem_row[e];
+  if (threadIdx.x < 7) {
+    const int el = threadIdx.x == 0 ? e : nbr[(long long)e * 6 + threadIdx.x - 1];
+    src[threadIdx.x] = (long long)el * N3;
+  }
+  __syncthreads();
+  const int* lay = seg_loc + ci.layout_off;
+  double w[kSysMaxVars][kSubPerSmall];
+#pragma unroll
+  for (int q = 0; q < kSubPerSmall; ++q) {
+    const int i = threadIdx.x + q * kSubThreads;
+    long long g = 0;
+    if (i < n) {
+      const int sl = lay[i];
+      int seg = sl / N3;
+      int loc = sl - seg * N3;
+      frame_point(seg, loc, code, N);
+      g = src[seg] + loc;
+    }
+#pragma unroll
+    for (int a = 0; a < kSysMaxVars; ++a) {
+      double v = 0.0;
+      if (a < nv && i < n) {
+        v = (double)W[a * stride + row + i];
+        for (int b = 0; b < nv; ++b)
+          v += D[(long long)(a * nv + b) * nd + g] * (double)Zj[b * stride + row + i];
+      }
+      w[a][q] = v;
+    }
+  }
+  const long long slot = (long long)nv * stride;
+  double* Hs = H + (long long)e * (kmax + 1) * kmax;  // column-major (kmax+1) x kmax
+  for (int ii = 0; ii <= j; ++ii) {
+    const T* vi = V + ii * slot + row;
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < kSysMaxVars; ++a)
+#pragma unroll
+      for (int q = 0; q < kSubPerSmall; ++q) {
+        const int p = threadIdx.x + q * kSubThreads;
+        if (a < nv && p < n) s += w[a][q] * (double)vi[a * stride + p];
+      }
+    const double h = block_reduce_sum(s, red);
+#pragma unroll
+    for (int a = 0; a < kSysMaxVars; ++a)
+#pragma unroll
+      for (int q = 0; q < kSubPerSmall; ++q) {
+        const int p = threadIdx.x + q * kSubThreads;
+        if (a < nv && p < n) w[a][q] -= h * (double)vi[a * stride + p];
+      }
+    if (threadIdx.x == 0) Hs[j * (kmax + 1) + ii] = h;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < kSysMaxVars; ++a)
+#pragma unroll
+    for (int q = 0; q < kSubPerSmall; ++q) s += w[a][q] * w[a][q];
+  const double hn = sqrt(block_reduce_sum(s, red));
+  if (threadIdx.x == 0) Hs[j * (kmax + 1) + j + 1] = hn;
+  if (j + 1 <= kmax) {
+    T* vn = V + (j + 1) * slot + row;
+#pragma unroll
+    for (int a = 0; a < kSysMaxVars; ++a)
+#pragma unroll
+      for (int q = 0; q < kSubPerSmall; ++q) {
+        const int p = threadIdx.x + q * kSubThreads;
+        if (a < nv && p < n) vn[a * stride + p] = hn > 0.0 ? (T)(w[a][q] / hn) : (T)0;
+      }
+  }
+}
+
+// du_a = sum_j y_j Z_j,a with y the least-squares coefficients (Z slot j at
+// j * nv * stride); du is written as part 0 of each variable's block.
+template <typename T>
+__global__ void __launch_bounds__(kSubThreads)
+k_sys_finish(int kmax, int nv, const T* __restrict__ Z, long long stride,
+             const double* __restrict__ H, const double* __restrict__ beta, T* __restrict__ du,
+             const int* __restrict__ elem_class, const long long* __restrict__ elem_row,
+             const ClassInfo* __restrict__ cls, int E) {
+  __shared__ double y[16];
+  __shared__ int mm;
+  const int e = blockIdx.x;
+  if (e >= E) return;
+  const int n = cls[elem_class[e] & kGroupMask].n;
+  const long long row = elem_row[e];
+  if (threadIdx.x == 0) mm = small_lsq(H + (long long)e * (kmax + 1) * kmax, kmax, beta[e], y);
+  __syncthreads();
+  const int m = mm;
+  const long long slot = (long long)nv * stride;
+  for (int a = 0; a < nv; ++a)
+    for (int i = threadIdx.x; i < n; i += kSubThreads) {
+      double v = 0.0;
+      for (int jj = 0; jj < m; ++jj) v += y[jj] * (double)Z[jj * slot + a * stride + row + i];
+      du[a * stride + row + i] = (T)v;
+    }
+}
+
+// y_a += sign * sum_b D_ab u_b pointwise (the coupling of a system)
+__global__ void k_sys_couple(double* __restrict__ y, const double* __restrict__ u,
+                             const double* __restrict__ D, int nv, long long nd, double sign) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nd) return;
+  for (int a = 0; a < nv; ++a) {
+    double acc = 0.0;
+    for (int b = 0; b < nv; ++b) acc += D[(long long)(a * nv + b) * nd + g] * u[b * nd + g];
+    y[a * nd + g] += sign * acc;
   }
 }
 
@@ -619,6 +781,60 @@ hipError_t launch_sub_finish(bool f32, int kmax, const void* Z, long long stride
   else
     hipLaunchKernelGGL(k_sub_finish<double>, dim3(E), dim3(kSubThreads), 0, s, kmax,
                        (const double*)Z, stride, H, beta, (double*)du, elem_class, elem_row, cls, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_sys_start(bool f32, int nv, const void* rs, void* V0, double* beta,
+                            long long stride, const int* elem_class, const long long* elem_row,
+                            const ClassInfo* cls, int E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_sys_start<float>, dim3(E), dim3(kSubThreads), 0, s, nv, (const float*)rs,
+                       (float*)V0, beta, stride, elem_class, elem_row, cls, E);
+  else
+    hipLaunchKernelGGL(k_sys_start<double>, dim3(E), dim3(kSubThreads), 0, s, nv,
+                       (const double*)rs, (double*)V0, beta, stride, elem_class, elem_row, cls, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_sys_arnoldi(int N, bool f32, int j, int kmax, int nv, const void* W, void* V,
+                              const void* Zj, long long stride, const double* D, long long nd,
+                              double* H, const int* elem_class, const long long* elem_row,
+                              const int* nbr, const ClassInfo* cls, const int* seg_loc, int E,
+                              int max_n, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  if (max_n > kSubThreads * kSubPerSmall || nv < 1 || nv > kSysMaxVars) return hipErrorInvalidValue;
+  if (f32)
+    hipLaunchKernelGGL(k_sys_arnoldi<float>, dim3(E), dim3(kSubThreads), 0, s, j, kmax, nv,
+                       (const float*)W, (float*)V, (const float*)Zj, stride, D, nd, H, elem_class,
+                       elem_row, nbr, cls, seg_loc, E, N);
+  else
+    hipLaunchKernelGGL(k_sys_arnoldi<double>, dim3(E), dim3(kSubThreads), 0, s, j, kmax, nv,
+                       (const double*)W, (double*)V, (const double*)Zj, stride, D, nd, H,
+                       elem_class, elem_row, nbr, cls, seg_loc, E, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_sys_finish(bool f32, int kmax, int nv, const void* Z, long long stride,
+                             const double* H, const double* beta, void* du, const int* elem_class,
+                             const long long* elem_row, const ClassInfo* cls, int E,
+                             hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_sys_finish<float>, dim3(E), dim3(kSubThreads), 0, s, kmax, nv,
+                       (const float*)Z, stride, H, beta, (float*)du, elem_class, elem_row, cls, E);
+  else
+    hipLaunchKernelGGL(k_sys_finish<double>, dim3(E), dim3(kSubThreads), 0, s, kmax, nv,
+                       (const double*)Z, stride, H, beta, (double*)du, elem_class, elem_row, cls,
+                       E);
+  return hipGetLastError();
+}
+
+hipError_t launch_sys_couple(double* y, const double* u, const double* D, int nv, long long nd,
+                             double sign, hipStream_t s) {
+  if (nd <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sys_couple, dim3((unsigned)((nd + 255) / 256)), dim3(256), 0, s, y, u, D,
+                     nv, nd, sign);
   return hipGetLastError();
 }
 

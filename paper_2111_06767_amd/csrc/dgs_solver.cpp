@@ -244,6 +244,9 @@ struct dgs_problem {
   bool diag_active = false;
   double t_setup = 0;
   double* d_newton = nullptr;  // Newton work vectors
+  // a variable of a system: the Neumann faces of all its variables, which
+  // decide the classes and frames (empty for a scalar problem)
+  std::vector<int> class_masks;
   // captured V-cycles (index: linearised operator or not) and the capture stream
   hipGraphExec_t vgraph[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
@@ -383,50 +386,81 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   // geometry and the weights are all symmetric under the mirror); then, of the
   // exchanges of two axes with equal element widths (under which they are
   // symmetric too), the one that gives the largest flags is taken, so that
-  // faces, edges and corners of every orientation share a class
-  std::map<int, int> cls_of_flags;
+  // faces, edges and corners of every orientation share a class.  A variable
+  // of a system (class_masks: the Neumann faces of all its variables) takes
+  // the frame and the classes from the flags of all variables together, so
+  // that every variable has the same classes, frames and row layout, and
+  // only its own boundary types in the inverses.
+  const std::vector<int> key_masks =
+      P->class_masks.empty() ? std::vector<int>{P->opt.neumann_faces} : P->class_masks;
+  const int nk = (int)key_masks.size();
+  auto mirror = [](int fl, int d) {  // the face and its boundary type move to the low side
+    const int nh = (fl >> (6 + 2 * d + 1)) & 1;
+    return (fl & ~(3 << (2 * d)) & ~(3 << (6 + 2 * d))) | (1 << (2 * d)) | (nh << (6 + 2 * d));
+  };
+  auto exchange = [](int fl, int t) {
+    int ft = 0;
+    for (int d = 0; d < 3; ++d) {
+      const int from = frame_axis(d, t);
+      ft |= ((fl >> (2 * from)) & 3) << (2 * d);
+      ft |= ((fl >> (6 + 2 * from)) & 3) << (6 + 2 * d);
+    }
+    return ft;
+  };
+  auto combine = [&](const int* f) {
+    uint64_t k = 0;
+    for (int v = 0; v < nk; ++v) k |= (uint64_t)f[v] << (12 * v);
+    return k;
+  };
+  std::map<uint64_t, int> cls_of_key;
+  std::vector<uint64_t> elem_key(L.E);
   std::vector<int> elem_flags(L.E), elem_code(L.E);
   for (long long e = 0; e < L.E; ++e) {
     const int c[3] = {(int)(e % L.n[0]), (int)((e / L.n[0]) % L.n[1]),
                       (int)(e / ((long long)L.n[0] * L.n[1]))};
-    int fl = class_flags(c, L.n, P->opt.neumann_faces), mask = 0;
+    int own = class_flags(c, L.n, P->opt.neumann_faces), mask = 0;
+    int kf[kSysMaxVars], tf[kSysMaxVars];
+    for (int v = 0; v < nk; ++v) kf[v] = class_flags(c, L.n, key_masks[v]);
     for (int d = 0; d < 3; ++d) {
-      const int lo = (fl >> (2 * d)) & 1, hi = (fl >> (2 * d + 1)) & 1;
-      if (!lo && hi) {  // the face and its boundary type move to the low side
+      const int lo = (own >> (2 * d)) & 1, hi = (own >> (2 * d + 1)) & 1;
+      if (!lo && hi) {
         mask |= 1 << d;
-        const int nh = (fl >> (6 + 2 * d + 1)) & 1;
-        fl = (fl & ~(3 << (2 * d)) & ~(3 << (6 + 2 * d))) | (1 << (2 * d)) | (nh << (6 + 2 * d));
+        own = mirror(own, d);
+        for (int v = 0; v < nk; ++v) kf[v] = mirror(kf[v], d);
       }
     }
-    int best = fl, best_t = 0;
+    uint64_t best = combine(kf);
+    int best_t = 0, best_own = own;
     for (int t = 1; t <= 3; ++t) {
       const int a = t == 3 ? 1 : 0, b = t == 1 ? 1 : 2;
       if (L.h[a] != L.h[b]) continue;
-      int ft = 0;
-      for (int d = 0; d < 3; ++d) {
-        const int from = frame_axis(d, t);
-        ft |= ((fl >> (2 * from)) & 3) << (2 * d);
-        ft |= ((fl >> (6 + 2 * from)) & 3) << (6 + 2 * d);
-      }
-      if (ft > best) {
-        best = ft;
+      for (int v = 0; v < nk; ++v) tf[v] = exchange(kf[v], t);
+      const uint64_t kt = combine(tf);
+      if (kt > best) {
+        best = kt;
         best_t = t;
+        best_own = exchange(own, t);
       }
     }
-    elem_flags[e] = best;
+    elem_flags[e] = best_own;
+    elem_key[e] = best;
     elem_code[e] = mask | best_t << 3;
-    cls_of_flags.emplace(best, 0);
+    cls_of_key.emplace(best, 0);
   }
   int ci = 0;
-  for (auto& kv : cls_of_flags) kv.second = ci++;
-  L.layouts.clear();
-  L.cls.assign(ci, ClassInfo{});
-  for (auto& kv : cls_of_flags) L.layouts.push_back(make_layout(kv.first, N, nov, P->ht.xi));
+  for (auto& kv : cls_of_key) kv.second = ci++;
+  // a class's own flags (the same for all its elements: the own boundary
+  // types are part of the key)
+  std::vector<int> own_of_class(ci, 0);
   std::vector<int> elem_class(L.E), count(ci, 0), pos(L.E);
   for (long long e = 0; e < L.E; ++e) {
-    elem_class[e] = cls_of_flags[elem_flags[e]];
+    elem_class[e] = cls_of_key[elem_key[e]];
+    own_of_class[elem_class[e]] = elem_flags[e];
     pos[e] = count[elem_class[e]]++;
   }
+  L.layouts.clear();
+  L.cls.assign(ci, ClassInfo{});
+  for (int c = 0; c < ci; ++c) L.layouts.push_back(make_layout(own_of_class[c], N, nov, P->ht.xi));
   std::vector<int> seg_loc;
   std::vector<double> weights;
   long long rs_off = 0;
@@ -2500,7 +2534,8 @@ class WorkerPool {
 namespace {
 int create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
                    const dgs_options* opt, dgs_alloc_fn alloc_fn, dgs_free_fn free_fn,
-                   void* alloc_ctx, void* stream, dgs_problem** out, bool light);
+                   void* alloc_ctx, void* stream, dgs_problem** out, bool light,
+                   const std::vector<int>* class_masks = nullptr);
 }  // namespace
 
 // Device memory of a retired request, freed later in a batch: freeing waits
@@ -2798,7 +2833,8 @@ namespace {
 // (problems of the serving loop's batch engine use neither)
 int create_problem(const dgs_domain* domain, const int elements[3], int p, double penalty,
                    const dgs_options* opt, dgs_alloc_fn alloc_fn, dgs_free_fn free_fn,
-                   void* alloc_ctx, void* stream, dgs_problem** out, bool light) {
+                   void* alloc_ctx, void* stream, dgs_problem** out, bool light,
+                   const std::vector<int>* class_masks) {
   return guarded([&]() -> int {
     if (!domain || !elements || !out) return fail(DGS_ERR_INVALID, "NULL argument");
     *out = nullptr;
@@ -2834,6 +2870,7 @@ int create_problem(const dgs_domain* domain, const int elements[3], int p, doubl
     P->N = p + 1;
     P->penalty = penalty;
     P->dom = *domain;
+    if (class_masks) P->class_masks = *class_masks;
     P->ht = make_tables(P->N);
     P->dt = to_dev(P->ht);
     P->mt = to_dev_mg(P->ht);
@@ -3417,6 +3454,486 @@ int dgs_server_fetch(dgs_server* S, long long id, double* u, long long n, dgs_st
     const int status = r.status;
     S->finished.erase(it);
     return status;
+  });
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Systems of several variables (Sec. III.E.1): each variable has its own
+// boundary types; the Schwarz subdomain problem of the whole system is
+// solved by k iterations of right-preconditioned GMRES whose preconditioner
+// is the Laplacian approximation (eq. lapl_approx), one Poisson inverse per
+// variable with that variable's boundary types (or, for comparison, the
+// Dirichlet one for every variable).
+//
+// A system is one scalar problem per variable, all built with the Neumann
+// faces of every variable in their class key, so that they share classes,
+// element frames, row layouts, tiles and tables; each holds the inverses and
+// subdomain operators of its own boundary types (the process-wide inverse
+// cache stores a class's inverse once however many variables use it, so a
+// subdomain with only internal faces has one inverse for all variables).
+// ===========================================================================
+namespace {
+
+struct SysLevel {
+  long long nd = 0;       // points per variable
+  long long st = 0;       // subdomain rows per variable (shared by all variables)
+  double* D = nullptr;    // couplings D_ab, nv * nv fields of nd points
+  double* b = nullptr;    // coarse levels: restricted residual, nv * nd
+  double* u = nullptr;    // coarse levels: correction, nv * nd
+  double* r = nullptr;    // residual, nv * nd
+  void* rs = nullptr;     // gathered rows, nv * st (level precision)
+  void* du = nullptr;     // subdomain corrections, nv * st
+  void* parts = nullptr;  // split-K partial products of one GEMM
+  void *gV = nullptr, *gZ = nullptr, *gW = nullptr;  // subdomain GMRES bases
+  double *H = nullptr, *beta = nullptr;
+};
+
+}  // namespace
+
+struct dgs_system {
+  int nv = 0;
+  int matched = 1;
+  bool coupled = false;
+  std::vector<dgs_problem*> var;  // one scalar problem per variable
+  dgs_problem* dir = nullptr;     // all-Dirichlet problem of the naive approximation
+  std::vector<SysLevel> lv;
+  int kry_m = 0;
+  double *V = nullptr, *Z = nullptr, *partial = nullptr, *h = nullptr, *y = nullptr, *tmp = nullptr;
+  double* h_pinned = nullptr;
+  double t_setup = 0;
+
+  dgs_problem* base() const { return var[0]; }
+  // the system's buffers are allocations of the first variable's problem
+  template <typename T>
+  T* alloc(size_t n) { return var[0]->alloc<T>(n); }
+  ~dgs_system() {
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+    if (h_pinned) (void)hipHostFree(h_pinned);
+    for (dgs_problem* p : var) delete p;
+    delete dir;
+  }
+};
+
+namespace {
+
+const ClassInfo* sys_inverse_classes(dgs_system* S, int l, int a) {
+  return (S->matched ? S->var[a] : S->dir)->levels[l].d_cls;
+}
+
+// One class GEMM of variable a on level l: its inverse (use_op = 0; the
+// Laplacian approximation) or its subdomain operator (use_op = 1) times
+// rows `in`, split-K partials into the level's parts buffer.
+void sys_gemm(dgs_system* S, int l, int a, const void* in, int use_op, hipStream_t s) {
+  SysLevel& SL = S->lv[l];
+  const Level& L0 = S->base()->levels[l];
+  const ClassInfo* cls = use_op ? S->var[a]->levels[l].d_cls : sys_inverse_classes(S, l, a);
+  const int v = L0.gemm_variant;
+  HIP_OK(launch_subdomain_gemm(L0.f32, in, SL.parts, SL.st, cls, L0.d_tiles[v], L0.ntiles[v],
+                               L0.gemm_small, use_op, s, v));
+}
+
+// r = b - A_sys u on level l (vectors of nv * nd)
+void sys_residual(dgs_system* S, int l, const double* u, const double* b, double* r, hipStream_t s) {
+  const dgs_problem* P = S->base();
+  const long long nd = S->lv[l].nd;
+  for (int a = 0; a < S->nv; ++a) {
+    const dgs_problem* Pa = S->var[a];
+    const Level& L = Pa->levels[l];
+    HIP_OK(launch_apply(P->N, kResidual, u + a * nd, r + a * nd, b + a * nd, nullptr, nullptr,
+                        L.d_nbr, L.op, Pa->dt, L.acfg_out, s, L.d_order));
+  }
+  if (S->coupled) HIP_OK(launch_sys_couple(r, u, S->lv[l].D, S->nv, nd, -1.0, s));
+}
+
+void sys_apply(dgs_system* S, const double* u, double* y, hipStream_t s) {
+  const dgs_problem* P = S->base();
+  const long long nd = S->lv[0].nd;
+  for (int a = 0; a < S->nv; ++a) {
+    const dgs_problem* Pa = S->var[a];
+    const Level& L = Pa->levels[0];
+    HIP_OK(launch_apply(P->N, kApply, u + a * nd, y + a * nd, nullptr, nullptr, nullptr, L.d_nbr,
+                        L.op, Pa->dt, L.acfg_out, s, L.d_order));
+  }
+  if (S->coupled) HIP_OK(launch_sys_couple(y, u, S->lv[0].D, S->nv, nd, 1.0, s));
+}
+
+// Subdomain GMRES(k) of the system on level l: rows in SL.rs, corrections
+// into SL.du (one block per variable).
+void sys_subdomain_gmres(dgs_system* S, int l, hipStream_t s) {
+  const dgs_problem* P = S->base();
+  SysLevel& SL = S->lv[l];
+  const Level& L0 = P->levels[l];
+  const int k = P->opt.subdomain_iters, nv = S->nv;
+  const size_t es = L0.f32 ? sizeof(float) : sizeof(double);
+  auto at = [&](void* base, long long blocks) { return (void*)((char*)base + es * (size_t)(SL.st * blocks)); };
+  HIP_OK(launch_sys_start(L0.f32, nv, SL.rs, SL.gV, SL.beta, SL.st, L0.d_elem_class, L0.d_elem_row,
+                          L0.d_cls, (int)L0.E, s));
+  for (int j = 0; j < k; ++j) {
+    void* Vj = at(SL.gV, (long long)j * nv);
+    void* Zj = at(SL.gZ, (long long)j * nv);
+    for (int a = 0; a < nv; ++a) {
+      // z_a = M_a v_a (Laplacian approximation), w_a = A_S^(a) z_a
+      sys_gemm(S, l, a, at(Vj, a), 0, s);
+      HIP_OK(launch_reduce_parts(L0.f32, at(Zj, a), SL.parts, L0.kparts, SL.st, SL.st, s));
+      sys_gemm(S, l, a, at(Zj, a), 1, s);
+      HIP_OK(launch_reduce_parts(L0.f32, at(SL.gW, a), SL.parts, L0.kparts, SL.st, SL.st, s));
+    }
+    HIP_OK(launch_sys_arnoldi(P->N, L0.f32, j, k, nv, SL.gW, SL.gV, Zj, SL.st, SL.D, SL.nd, SL.H,
+                              L0.d_elem_class, L0.d_elem_row, L0.d_nbr, L0.d_cls, L0.d_seg_loc,
+                              (int)L0.E, L0.max_n, s));
+  }
+  HIP_OK(launch_sys_finish(L0.f32, k, nv, SL.gZ, SL.st, SL.H, SL.beta, SL.du, L0.d_elem_class,
+                           L0.d_elem_row, L0.d_cls, (int)L0.E, s));
+}
+
+// `steps` additive Schwarz steps on A_sys u = b, level l (u_zero: u starts
+// at zero and the first step writes it)
+void sys_schwarz_steps(dgs_system* S, int l, const double* b, double* u, int steps, bool u_zero,
+                       hipStream_t s) {
+  const dgs_problem* P = S->base();
+  SysLevel& SL = S->lv[l];
+  const Level& L0 = P->levels[l];
+  const int N = P->N, nv = S->nv;
+  const size_t es = L0.f32 ? sizeof(float) : sizeof(double);
+  auto at = [&](void* base, long long blocks) { return (void*)((char*)base + es * (size_t)(SL.st * blocks)); };
+  for (int it = 0; it < steps; ++it) {
+    const bool first = it == 0 && u_zero;
+    const double* src = b;
+    if (!first) {
+      sys_residual(S, l, u, b, SL.r, s);
+      src = SL.r;
+    }
+    for (int a = 0; a < nv; ++a)
+      HIP_OK(launch_gather(N, L0.f32, src + a * SL.nd, at(SL.rs, a), L0.d_elem_class,
+                           L0.d_elem_row, L0.d_nbr, L0.d_cls, L0.d_seg_loc, (int)L0.E, s));
+    if (P->opt.subdomain_iters > 0) {
+      sys_subdomain_gmres(S, l, s);
+      for (int a = 0; a < nv; ++a)
+        HIP_OK(launch_scatter(N, L0.f32, u + a * SL.nd, at(SL.du, a), 1, SL.st, L0.d_weights,
+                              L0.d_pull, nov_of(P), L0.E, s, first));
+    } else {
+      // the Laplacian approximation alone: du_a = M_a r_a
+      for (int a = 0; a < nv; ++a) {
+        sys_gemm(S, l, a, at(SL.rs, a), 0, s);
+        HIP_OK(launch_scatter(N, L0.f32, u + a * SL.nd, SL.parts, L0.kparts, SL.st, L0.d_weights,
+                              L0.d_pull, nov_of(P), L0.E, s, first));
+      }
+    }
+  }
+}
+
+// One V-cycle visit of level l (Sec. III.C.3) on the system
+void sys_visit(dgs_system* S, int l, const double* b, double* u, bool u_zero, hipStream_t s) {
+  const dgs_problem* P = S->base();
+  const int nl = (int)S->lv.size(), nv = S->nv;
+  const int pre = l < nl - 1 ? P->opt.pre_smooth : P->opt.pre_smooth + P->opt.post_smooth;
+  SysLevel& SL = S->lv[l];
+  if (u_zero && pre == 0) HIP_OK(launch_fill(u, 0.0, nv * SL.nd, s));
+  sys_schwarz_steps(S, l, b, u, pre, u_zero, s);
+  if (l == nl - 1) return;
+  sys_residual(S, l, u, b, SL.r, s);
+  SysLevel& C = S->lv[l + 1];
+  const Level& L = P->levels[l];
+  const Level& Lc = P->levels[l + 1];
+  for (int a = 0; a < nv; ++a)
+    HIP_OK(launch_restrict(P->N, SL.r + a * SL.nd, C.b + a * C.nd, L.n, Lc.n, L.split, P->mt, s));
+  sys_visit(S, l + 1, C.b, C.u, true, s);
+  for (int a = 0; a < nv; ++a)
+    HIP_OK(launch_prolongate_add(P->N, C.u + a * C.nd, u + a * SL.nd, L.n, Lc.n, L.split, P->mt, s));
+  sys_schwarz_steps(S, l, b, u, P->opt.post_smooth, false, s);
+}
+
+void sys_ensure_krylov(dgs_system* S, int m) {
+  if (S->kry_m >= m) return;
+  if (S->kry_m > 0) HIP_OK(hipDeviceSynchronize());
+  dgs_problem* P = S->base();
+  for (double* p : {S->V, S->Z, S->partial, S->h, S->y, S->tmp})
+    if (p) P->release(p);
+  const long long n = S->nv * S->lv[0].nd;
+  S->V = S->alloc<double>((size_t)(m + 1) * n);
+  S->Z = S->alloc<double>((size_t)m * n);
+  S->partial = S->alloc<double>((size_t)multidot_blocks(n) * (m + 2));
+  S->h = S->alloc<double>(3 * (m + 2));
+  S->y = S->alloc<double>(m + 1);
+  S->tmp = S->alloc<double>(n);
+  std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+  if (S->h_pinned) (void)hipHostFree(S->h_pinned);
+  S->h_pinned = nullptr;
+  HIP_OK(hipHostMalloc((void**)&S->h_pinned, sizeof(double) * 4 * (m + 2), hipHostMallocDefault));
+  S->kry_m = m;
+}
+
+double sys_norm2(dgs_system* S, const double* x, long long n, hipStream_t s) {
+  HIP_OK(launch_multidot(x, n, 1, x, n, S->partial, S->h, s));
+  HIP_OK(hipMemcpyAsync(S->h_pinned, S->h, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return S->h_pinned[0];
+}
+
+// Flexible GMRES (Saad Alg. 9.6) on the system with one V-cycle per
+// iteration: classical Gram-Schmidt twice, Givens rotations on the host,
+// restarts of the options' length, and convergence decided by the true
+// residual of the solution (a cycle whose estimate meets rtol while the true
+// residual does not is followed by another cycle).
+FgmresResult sys_fgmres(dgs_system* S, const double* b, double* x, hipStream_t s) {
+  const dgs_problem* P = S->base();
+  const double rtol = P->opt.rtol;
+  const int max_total = P->opt.max_iter;
+  const int m = P->opt.restart > 0 ? std::min(P->opt.restart, max_total) : max_total;
+  sys_ensure_krylov(S, m);
+  const long long n = S->nv * S->lv[0].nd;
+  double* hp = S->h_pinned;
+  FgmresResult R;
+  double beta0 = 0.0;
+  for (int cycle = 0;; ++cycle) {
+    sys_residual(S, 0, x, b, S->V, s);
+    const double beta2 = sys_norm2(S, S->V, n, s);
+    if (!std::isfinite(beta2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite initial residual");
+    const double beta = std::sqrt(beta2);
+    if (cycle == 0) {
+      beta0 = beta;
+      R.history.push_back(1.0);
+    }
+    if (beta == 0.0) {
+      R.converged = true;
+      R.rel_residual = 0.0;
+      return R;
+    }
+    HIP_OK(launch_scale_by_inv_norm(S->V, S->V, S->h, n, s));
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
+    g[0] = beta;
+    int j = 0;
+    while (true) {
+      double* vj = S->V + (size_t)j * n;
+      double* zj = S->Z + (size_t)j * n;
+      double* w = S->V + (size_t)(j + 1) * n;
+      sys_visit(S, 0, vj, zj, true, s);
+      sys_apply(S, zj, w, s);
+      double* h1 = S->h;
+      double* h2 = S->h + (m + 2);
+      double* hn = S->h + 2 * (m + 2);
+      HIP_OK(launch_multidot(S->V, n, j + 1, w, n, S->partial, h1, s));
+      HIP_OK(launch_axpy_multidot(S->V, n, j + 1, h1, w, n, false, S->partial, h2, s));
+      HIP_OK(launch_axpy_multidot(S->V, n, j + 1, h2, w, n, true, S->partial, hn, s));
+      HIP_OK(hipMemcpyAsync(hp, S->h, sizeof(double) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, s));
+      HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));
+      HIP_OK(hipStreamSynchronize(s));
+      double* col = &H[(size_t)j * (m + 1)];
+      for (int i = 0; i <= j; ++i) col[i] = hp[i] + hp[(m + 2) + i];
+      const double hn2 = hp[2 * (m + 2)];
+      col[j + 1] = std::sqrt(hn2);
+      for (int i = 0; i <= j + 1; ++i)
+        if (!std::isfinite(col[i])) throw DgsError(DGS_ERR_NONFINITE, "non-finite Hessenberg entry");
+      for (int i = 0; i < j; ++i) {
+        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+        col[i] = t;
+      }
+      const double den = std::hypot(col[j], col[j + 1]);
+      cs[j] = col[j] / den;
+      sn[j] = col[j + 1] / den;
+      col[j] = den;
+      col[j + 1] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      R.history.push_back(std::fabs(g[j + 1]) / beta0);
+      ++j;
+      ++R.iterations;
+      if (std::fabs(g[j]) <= rtol * beta0 || hn2 == 0.0 || j >= m || R.iterations >= max_total) break;
+    }
+    std::vector<double> y(j, 0.0);
+    for (int i = j - 1; i >= 0; --i) {
+      double t = g[i];
+      for (int q = i + 1; q < j; ++q) t -= H[(size_t)q * (m + 1) + i] * y[q];
+      y[i] = t / H[(size_t)i * (m + 1) + i];
+    }
+    double* ypin = hp + 3 * (m + 2);
+    for (int i = 0; i < j; ++i) ypin[i] = y[i];
+    HIP_OK(hipMemcpyAsync(S->y, ypin, sizeof(double) * j, hipMemcpyHostToDevice, s));
+    HIP_OK(launch_combine(x, S->Z, n, j, S->y, n, s));
+    sys_residual(S, 0, x, b, S->tmp, s);
+    R.rel_residual = std::sqrt(sys_norm2(S, S->tmp, n, s)) / beta0;
+    if (!std::isfinite(R.rel_residual)) throw DgsError(DGS_ERR_NONFINITE, "non-finite residual");
+    R.converged = R.rel_residual <= rtol;
+    if (R.converged || R.iterations >= max_total) return R;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int dgs_create_system(const dgs_domain* domain, const int elements[3], int p, double penalty,
+                      int nvars, const int* neumann_faces, int laplacian_bc,
+                      const dgs_options* opt, void* stream, dgs_system** out) {
+  return guarded([&]() -> int {
+    if (!domain || !elements || !neumann_faces || !out) return fail(DGS_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    if (nvars < 1 || nvars > kSysMaxVars) return fail(DGS_ERR_INVALID, "nvars must be in [1, 5]");
+    if (laplacian_bc != 0 && laplacian_bc != 1)
+      return fail(DGS_ERR_INVALID, "laplacian_bc must be 0 (matched) or 1 (Dirichlet)");
+    std::vector<int> masks(neumann_faces, neumann_faces + nvars);
+    for (int m : masks)
+      if (m < 0 || m >= 63) return fail(DGS_ERR_INVALID, "Neumann faces must leave one face Dirichlet");
+    dgs_options o;
+    dgs_default_options(&o);
+    if (opt) o = *opt;
+    const double t0 = now_s();
+    hipStream_t s = as_stream(stream);
+    std::unique_ptr<dgs_system> S(new dgs_system());
+    S->nv = nvars;
+    S->matched = laplacian_bc == 0;
+    for (int a = 0; a <= nvars; ++a) {
+      if (a == nvars && S->matched) break;
+      o.neumann_faces = a < nvars ? masks[a] : 0;
+      dgs_problem* Pa = nullptr;
+      const int rc = create_problem(domain, elements, p, penalty, &o, nullptr, nullptr, nullptr,
+                                    stream, &Pa, /*light=*/true, &masks);
+      if (rc != DGS_OK) return rc;
+      if (a < nvars)
+        S->var.push_back(Pa);
+      else
+        S->dir = Pa;
+    }
+    dgs_problem* P = S->base();
+    for (const Level& L : P->levels)
+      if (L.max_n > kSysMaxRows)
+        return fail(DGS_ERR_INVALID, "system subdomains are limited to 2048 points (p <= 8 with overlap 2)");
+    // tune the first variable; the others share its level shapes
+    autotune_apply(P, s);
+    autotune_gemm(P, s);
+    std::vector<dgs_problem*> others(S->var.begin() + 1, S->var.end());
+    if (S->dir) others.push_back(S->dir);
+    for (dgs_problem* Q : others)
+      for (size_t l = 0; l < P->levels.size(); ++l) {
+        Q->levels[l].acfg = P->levels[l].acfg;
+        Q->levels[l].acfg_out = P->levels[l].acfg_out;
+        Q->levels[l].gemm_variant = P->levels[l].gemm_variant;
+        Q->levels[l].kparts = P->levels[l].kparts;
+      }
+    const int nv = nvars, k = o.subdomain_iters;
+    for (size_t l = 0; l < P->levels.size(); ++l) {
+      const Level& L = P->levels[l];
+      SysLevel SL;
+      SL.nd = P->nd((int)l);
+      SL.st = L.rs_total;
+      const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+      int mp = 1;
+      for (int v = 0; v < kGemmVariants; ++v) mp = std::max(mp, L.kparts_of[v]);
+      SL.D = S->alloc<double>((size_t)nv * nv * SL.nd);
+      HIP_OK(launch_fill(SL.D, 0.0, (long long)nv * nv * SL.nd, s));
+      SL.r = S->alloc<double>((size_t)nv * SL.nd);
+      if (l > 0) {
+        SL.b = S->alloc<double>((size_t)nv * SL.nd);
+        SL.u = S->alloc<double>((size_t)nv * SL.nd);
+      }
+      // rows and products: the class blocks' padding must read as zero
+      SL.rs = S->alloc<char>(es * nv * SL.st);
+      SL.du = S->alloc<char>(es * nv * SL.st);
+      SL.parts = S->alloc<char>(es * mp * SL.st);
+      HIP_OK(hipMemsetAsync(SL.rs, 0, es * nv * SL.st, s));
+      HIP_OK(hipMemsetAsync(SL.du, 0, es * nv * SL.st, s));
+      HIP_OK(hipMemsetAsync(SL.parts, 0, es * mp * SL.st, s));
+      if (k > 0) {
+        SL.gV = S->alloc<char>(es * (size_t)(k + 1) * nv * SL.st);
+        SL.gZ = S->alloc<char>(es * (size_t)k * nv * SL.st);
+        SL.gW = S->alloc<char>(es * nv * SL.st);
+        HIP_OK(hipMemsetAsync(SL.gV, 0, es * (size_t)(k + 1) * nv * SL.st, s));
+        HIP_OK(hipMemsetAsync(SL.gZ, 0, es * (size_t)k * nv * SL.st, s));
+        HIP_OK(hipMemsetAsync(SL.gW, 0, es * nv * SL.st, s));
+        SL.H = S->alloc<double>((size_t)L.E * (k + 1) * k);
+        SL.beta = S->alloc<double>(L.E);
+      }
+      S->lv.push_back(SL);
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    S->t_setup = now_s() - t0;
+    *out = S.release();
+    return DGS_OK;
+  });
+}
+
+int dgs_destroy_system(dgs_system* sys) {
+  return guarded([&]() -> int {
+    delete sys;
+    return DGS_OK;
+  });
+}
+
+int dgs_system_num_dofs(const dgs_system* sys, long long* n) {
+  if (!sys || !n) return fail(DGS_ERR_INVALID, "NULL argument");
+  *n = sys->lv[0].nd;
+  return DGS_OK;
+}
+
+int dgs_system_set_coupling(dgs_system* sys, const double* D, void* stream) {
+  return guarded([&]() -> int {
+    if (!sys) return fail(DGS_ERR_INVALID, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    const dgs_problem* P = sys->base();
+    const int nv = sys->nv;
+    if (!D) {
+      for (SysLevel& SL : sys->lv) HIP_OK(launch_fill(SL.D, 0.0, (long long)nv * nv * SL.nd, s));
+      sys->coupled = false;
+      return DGS_OK;
+    }
+    SysLevel& F = sys->lv[0];
+    HIP_OK(hipMemcpyAsync(F.D, D, sizeof(double) * nv * nv * F.nd, hipMemcpyDeviceToDevice, s));
+    // coarse couplings D_{l+1} = R D_l, field by field
+    for (size_t l = 0; l + 1 < sys->lv.size(); ++l) {
+      const Level& L = P->levels[l];
+      const Level& Lc = P->levels[l + 1];
+      for (int ab = 0; ab < nv * nv; ++ab)
+        HIP_OK(launch_restrict(P->N, sys->lv[l].D + ab * sys->lv[l].nd,
+                               sys->lv[l + 1].D + ab * sys->lv[l + 1].nd, L.n, Lc.n, L.split, P->mt, s));
+    }
+    sys->coupled = true;
+    return DGS_OK;
+  });
+}
+
+int dgs_system_apply(dgs_system* sys, const double* u, double* y, void* stream) {
+  return guarded([&]() -> int {
+    if (!sys || !u || !y) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (u == y) return fail(DGS_ERR_INVALID, "u and y must not overlap");
+    sys_apply(sys, u, y, as_stream(stream));
+    return DGS_OK;
+  });
+}
+
+int dgs_system_smooth(dgs_system* sys, const double* b, double* u, int steps, void* stream) {
+  return guarded([&]() -> int {
+    if (!sys || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (steps < 0) return fail(DGS_ERR_INVALID, "steps must be >= 0");
+    sys_schwarz_steps(sys, 0, b, u, steps, false, as_stream(stream));
+    return DGS_OK;
+  });
+}
+
+int dgs_system_precondition(dgs_system* sys, const double* r, double* z, void* stream) {
+  return guarded([&]() -> int {
+    if (!sys || !r || !z) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (r == z) return fail(DGS_ERR_INVALID, "r and z must not overlap");
+    sys_visit(sys, 0, r, z, true, as_stream(stream));
+    return DGS_OK;
+  });
+}
+
+int dgs_system_solve(dgs_system* sys, const double* b, double* u, dgs_stats* stats, void* stream) {
+  return guarded([&]() -> int {
+    if (!sys || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (b == u) return fail(DGS_ERR_INVALID, "b and u must not overlap");
+    const double t0 = now_s();
+    FgmresResult R = sys_fgmres(sys, b, u, as_stream(stream));
+    fill_stats(stats, R, t0, sys->t_setup);
+    if (stats) {
+      stats->newton_steps = 0;
+      stats->backtracks = 0;
+    }
+    return R.converged ? DGS_OK : DGS_NOT_CONVERGED;
   });
 }
 
