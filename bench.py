@@ -57,14 +57,21 @@ C3 = dict(lower=(-20, -20, -20), upper=(20, 20, 20), elements=(6, 6, 6), p=7, le
 # counter reads for the plain copy of the calibration bytes made below.  A
 # figure is reported only while the sources it was measured on are unchanged.
 MEASURED_TRAFFIC = {
+    # k_sub_gemm_db<double, 2, 2, 2, 2, 16> (tile variant 3), 1264 workgroups:
+    # 254184.0 KiB fetched x 1.99982 + 40448.0 KiB written
     "subdomain_gemm": {"sources": ["paper_2111_06767_amd/csrc/dgs_schwarz.hip",
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
-                       "sha256": None,
-                       "bytes": None},
+                       "sha256": "c9f5c420d9cd2700e3e99daed6836118659112ec812e3a870b10422c4ec99950",
+                       "choice": 3,
+                       "bytes": 561940818},
+    # k_apply<8, 2, 0, 0, false> (two elements per workgroup), 40^3 p=7:
+    # 181532.9 KiB fetched x 1.99982 + 256000.0 KiB written
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
+                          "paper_2111_06767_amd/csrc/dgs_elem.h",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
-              "sha256": None,
-              "bytes": None},
+              "sha256": "381f693b89a7687e53ba2622666855f0e15f3f909c2f143e29af0535b7892f16",
+              "choice": 2,
+              "bytes": 633889980},
 }
 
 
@@ -77,9 +84,11 @@ def _sources_sha256(paths):
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, choice):
+    """Counted bytes per launch, if measured on these sources for this tile
+    variant / launch shape (the autotuner's choice of the run)."""
     t = MEASURED_TRAFFIC[kernel]
-    if t["bytes"] is None or _sources_sha256(t["sources"]) != t["sha256"]:
+    if t["bytes"] is None or t["choice"] != choice or _sources_sha256(t["sources"]) != t["sha256"]:
         return None
     return t["bytes"]
 
@@ -389,6 +398,49 @@ def measured_ceilings():
     return dict(copy_gbs=copy_gbs, fp32_gemm_tflops=gemm_tflops)
 
 
+def system_leg(dg, precision, laplacian_bc, k, steps=5, warmup=1):
+    """A coupled system of five variables on 8^3 elements, p = 6 (the shape
+    of the linearised XCTS equations of Sec. IV.B on a flat box: variable 0
+    with Neumann faces x-, y-, z-, variable 2 with Neumann face x+, the others
+    Dirichlet; pointwise couplings D_ab = M c_ab), solved by FGMRES with the
+    system V-cycle whose subdomain problems take k GMRES iterations with the
+    matched or the Dirichlet Laplacian approximation."""
+    import torch
+    import workloads as W
+    nv = len(W.SYSTEM_NEUMANN)
+    el, p = C2["elements"], C2["p"]
+    aux = dg.Problem(C2["lower"], C2["upper"], el, p, mg_levels=1)
+    xyz = aux.node_coordinates()
+    x, y, z = (xyz[d].cpu().numpy() for d in range(3))
+    c = W.system_coupling(W.SEED_SYSTEM, nv, x, y, z)
+    D = torch.empty(nv * nv * aux.ndof, dtype=torch.float64, device="cuda")
+    for ab in range(nv * nv):
+        aux.apply_mass(torch.as_tensor(c[ab // nv, ab % nv]).cuda(), out=D[ab * aux.ndof:(ab + 1) * aux.ndof])
+    b = torch.empty(nv * aux.ndof, dtype=torch.float64, device="cuda")
+    for a in range(nv):
+        f = torch.as_tensor(W.fourier_source(W.fourier_modes(W.SEED_SYSTEM + 1 + a), x, y, z)).cuda()
+        aux.apply_mass(f, out=b[a * aux.ndof:(a + 1) * aux.ndof])
+    aux.close()
+    S = dg.System(C2["lower"], C2["upper"], el, p, W.SYSTEM_NEUMANN, laplacian_bc=laplacian_bc,
+                  mg_levels=C2["levels"], subdomain_iters=k, precision=precision, max_iter=100)
+    S.set_coupling(D)
+    u = torch.zeros_like(b)
+    for _ in range(warmup):
+        u.zero_()
+        S.solve(b, u)
+    times, st = [], None
+    for _ in range(steps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = S.solve(b, u)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    S.close()
+    return dict(ms=_ms(times), iterations=st["iterations"], rel_residual=st["rel_residual"],
+                converged=st["converged"])
+
+
 def newton_leg(dg, precision, steps=10, warmup=2):
     """The 6^3, p = 7 puncture problem on [-20, 20]^3 by Newton-Krylov with the
     multigrid-Schwarz preconditioner (subdomain GMRES(3))."""
@@ -635,6 +687,16 @@ def main():
     c3["mixed_vs_fp64_solution_rel_diff"] = float(
         np.linalg.norm(solutions["c3_mixed"] - solutions["c3_fp64"]) / np.linalg.norm(solutions["c3_fp64"]))
 
+    # -- a coupled five-variable system: matched vs Dirichlet Laplacian approximation
+    systems = None
+    if not args.no_variants:
+        systems = {}
+        for k in (3, 1):
+            for bc in ("matched", "dirichlet"):
+                for prec in (("fp64", "mixed") if k == 3 else ("fp64",)):
+                    _log(f"8^3 p=6 five-variable system, {bc} k={k} {prec}")
+                    systems[f"k{k}_{bc}_{prec}"] = system_leg(dg, prec, bc, k)
+
     # -- applies --------------------------------------------------------------
     _log("operator applies")
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
@@ -663,7 +725,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(gemm64["achieved_tflops"], 2),
                 "peak": MFMA_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(gemm64["achieved_tflops"] / MFMA_FP64_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic("subdomain_gemm"),
+                "traffic": measured_traffic("subdomain_gemm", variant64),
                 "kernel": "grouped subdomain-solve GEMM (FP64 MFMA) of one Schwarz sweep on the "
                           "16^3 p=7 fine level, 2 sum_S n_S^2 = "
                           f"{gemm64['flops_per_launch']:.4g} flop per launch, tile variant {variant64}",
@@ -679,7 +741,8 @@ def main():
     roofline_apply = {"bound": "hbm", "achieved": round(roof_src["achieved_gbs"], 1),
                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": round(roof_src["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                      "traffic": measured_traffic("apply") if apply_big else None,
+                      "traffic": (measured_traffic("apply", roof_src["launch_shape"])
+                                  if apply_big else None),
                       "kernel": f"DG operator apply, {roof_src['elements']} elements "
                                 f"p={roof_src['p']}, 16 B/DOF algorithmic (read u, write Au), "
                                 f"launch shape {roof_src['launch_shape']}",
@@ -751,6 +814,7 @@ def main():
         "c2_8x8x8_p6": c2,
         "c2_variants_mixed": variants,
         "c3_puncture_6x6x6_p7": c3,
+        "system_5var_8x8x8_p6": systems,
         "apply": {"c2_shape": apply_c2, "16^3_p7": apply_c5, "40^3_p7": apply_big,
                   "sweep_2M_dofs": sweep},
         "serving": serving,
