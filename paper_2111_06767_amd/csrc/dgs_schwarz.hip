@@ -20,6 +20,13 @@ namespace {
 // class frame.  elem_class[e] = group | (frame code << 24).
 constexpr int kGroupMask = 0xFFFFFF;
 
+// Pointers into device (global) memory.  Matrices whose addresses are read
+// from a table (the class inverses, the per-class rows of the batched GEMM)
+// would otherwise be generic pointers, whose loads are flat loads: these count
+// against the LDS counter too, so every wait for an LDS read would also wait
+// for the prefetch of the next K step.
+#define DGS_GLOBAL __attribute__((address_space(1)))
+
 // class-frame point (seg, loc) -> the element's own frame: seg 0 is the
 // element itself, seg 1 + f the face neighbour across class-frame face f
 __device__ __forceinline__ void frame_point(int& seg, int& loc, int code, int N) {
@@ -182,17 +189,17 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
   const GemmTile tl = tiles[blockIdx.x];
   const ClassInfo ci = cls[tl.cls];
   const int ld = ci.ld;
-  const T* A;
-  T* C;
+  const T DGS_GLOBAL* A;
+  T DGS_GLOBAL* C;
   if constexpr (BATCH) {
     const GemmPtr gp = ptrs[tl.cls];
-    A = (const T*)gp.rs + ci.rs_off;
-    C = (T*)gp.du + tl.part * gp.pstride + ci.rs_off;
+    A = (const T DGS_GLOBAL*)gp.rs + ci.rs_off;
+    C = (T DGS_GLOBAL*)gp.du + tl.part * gp.pstride + ci.rs_off;
   } else {
-    A = rs + ci.rs_off;
-    C = du + tl.part * pstride + ci.rs_off;
+    A = (const T DGS_GLOBAL*)rs + ci.rs_off;
+    C = (T DGS_GLOBAL*)du + tl.part * pstride + ci.rs_off;
   }
-  const T* B = (const T*)(use_op ? ci.op : ci.inv);
+  const T DGS_GLOBAL* B = (const T DGS_GLOBAL*)(use_op ? ci.op : ci.inv);
   const int m0 = tl.m0, n0 = tl.n0, kbeg = tl.k0, kend = tl.k1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave / WN, wn = wave % WN;
@@ -209,14 +216,14 @@ k_sub_gemm(const T* __restrict__ rs, T* __restrict__ du,
       const int idx = tid + 256 * q;
       if (AV % 256 == 0 || idx < AV) {
         const int r = idx / (BK / VW), c = idx % (BK / VW);
-        ra[q] = *(const vec*)(A + (long long)(m0 + r) * ld + k0 + c * VW);
+        ra[q] = *(const vec DGS_GLOBAL*)(A + (long long)(m0 + r) * ld + k0 + c * VW);
       }
     }
 #pragma unroll
     for (int q = 0; q < NBV; ++q) {
       const int idx = tid + 256 * q;
       const int r = idx / (BN / VW), c = idx % (BN / VW);
-      rb[q] = *(const vec*)(B + (long long)(k0 + r) * ld + n0 + c * VW);
+      rb[q] = *(const vec DGS_GLOBAL*)(B + (long long)(k0 + r) * ld + n0 + c * VW);
     }
   };
   if (kbeg < kend) load(kbeg);
@@ -289,9 +296,9 @@ k_sub_gemm_db(const T* __restrict__ rs, T* __restrict__ du, long long pstride,
   const GemmTile tl = tiles[blockIdx.x];
   const ClassInfo ci = cls[tl.cls];
   const int ld = ci.ld;
-  const T* A = rs + ci.rs_off;
-  T* C = du + tl.part * pstride + ci.rs_off;
-  const T* B = (const T*)(use_op ? ci.op : ci.inv);
+  const T DGS_GLOBAL* A = (const T DGS_GLOBAL*)rs + ci.rs_off;
+  T DGS_GLOBAL* C = (T DGS_GLOBAL*)du + tl.part * pstride + ci.rs_off;
+  const T DGS_GLOBAL* B = (const T DGS_GLOBAL*)(use_op ? ci.op : ci.inv);
   const int m0 = tl.m0, n0 = tl.n0, kbeg = tl.k0;
   const int nk = (tl.k1 - tl.k0) / BK;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -309,13 +316,13 @@ k_sub_gemm_db(const T* __restrict__ rs, T* __restrict__ du, long long pstride,
     for (int q = 0; q < NAV; ++q) {
       const int idx = tid + 256 * q;
       const int r = idx / (BK / VW), c = idx % (BK / VW);
-      ra[q] = *(const vec*)(A + (long long)(m0 + r) * ld + k0 + c * VW);
+      ra[q] = *(const vec DGS_GLOBAL*)(A + (long long)(m0 + r) * ld + k0 + c * VW);
     }
 #pragma unroll
     for (int q = 0; q < NBV; ++q) {
       const int idx = tid + 256 * q;
       const int r = idx / (BN / VW), c = idx % (BN / VW);
-      rb[q] = *(const vec*)(B + (long long)(k0 + r) * ld + n0 + c * VW);
+      rb[q] = *(const vec DGS_GLOBAL*)(B + (long long)(k0 + r) * ld + n0 + c * VW);
     }
   };
   auto store = [&](int buf, const vec* ra, const vec* rb) {
