@@ -3488,6 +3488,18 @@ struct SysLevel {
   void* parts = nullptr;  // split-K partial products of one GEMM
   void *gV = nullptr, *gZ = nullptr, *gW = nullptr;  // subdomain GMRES bases
   double *H = nullptr, *beta = nullptr;
+  // one grouped GEMM over the classes of all variables: class a * ncls + c
+  // is variable a's class c (its Laplacian-approximation inverse in cls_inv,
+  // its A_S in cls_op); the rows of slot j (ptr_inv[j]: V_j, ptr_op[j]: Z_j)
+  // and the split-K partials, [part][variable][row]
+  int ncls = 0;
+  ClassInfo* cls_inv = nullptr;
+  ClassInfo* cls_op = nullptr;
+  std::vector<GemmPtr*> ptr_inv, ptr_op;
+  GemmPtr* ptr_rs = nullptr;  // the gathered rows (k = 0)
+  GemmTile* tiles = nullptr;
+  int ntiles = 0, kparts = 1;
+  bool small = false;
 };
 
 }  // namespace
@@ -3519,20 +3531,13 @@ struct dgs_system {
 
 namespace {
 
-const ClassInfo* sys_inverse_classes(dgs_system* S, int l, int a) {
-  return (S->matched ? S->var[a] : S->dir)->levels[l].d_cls;
-}
-
-// One class GEMM of variable a on level l: its inverse (use_op = 0; the
-// Laplacian approximation) or its subdomain operator (use_op = 1) times
-// rows `in`, split-K partials into the level's parts buffer.
-void sys_gemm(dgs_system* S, int l, int a, const void* in, int use_op, hipStream_t s) {
+// One grouped GEMM over all variables on level l: every variable's inverse
+// (the Laplacian approximation, cls_inv) or A_S (cls_op) times its rows as
+// listed in ptrs, split-K partials into the level's parts buffer.
+void sys_gemm(dgs_system* S, int l, const ClassInfo* cls, const GemmPtr* ptrs, hipStream_t s) {
   SysLevel& SL = S->lv[l];
   const Level& L0 = S->base()->levels[l];
-  const ClassInfo* cls = use_op ? S->var[a]->levels[l].d_cls : sys_inverse_classes(S, l, a);
-  const int v = L0.gemm_variant;
-  HIP_OK(launch_subdomain_gemm(L0.f32, in, SL.parts, SL.st, cls, L0.d_tiles[v], L0.ntiles[v],
-                               L0.gemm_small, use_op, s, v));
+  HIP_OK(launch_subdomain_gemm_batched(L0.f32, cls, ptrs, SL.tiles, SL.ntiles, SL.small, s));
 }
 
 // r = b - A_sys u on level l (vectors of nv * nd)
@@ -3571,16 +3576,16 @@ void sys_subdomain_gmres(dgs_system* S, int l, hipStream_t s) {
   auto at = [&](void* base, long long blocks) { return (void*)((char*)base + es * (size_t)(SL.st * blocks)); };
   HIP_OK(launch_sys_start(L0.f32, nv, SL.rs, SL.gV, SL.beta, SL.st, L0.d_elem_class, L0.d_elem_row,
                           L0.d_cls, (int)L0.E, s));
+  const long long all = (long long)nv * SL.st;
   for (int j = 0; j < k; ++j) {
     void* Vj = at(SL.gV, (long long)j * nv);
     void* Zj = at(SL.gZ, (long long)j * nv);
-    for (int a = 0; a < nv; ++a) {
-      // z_a = M_a v_a (Laplacian approximation), w_a = A_S^(a) z_a
-      sys_gemm(S, l, a, at(Vj, a), 0, s);
-      HIP_OK(launch_reduce_parts(L0.f32, at(Zj, a), SL.parts, L0.kparts, SL.st, SL.st, s));
-      sys_gemm(S, l, a, at(Zj, a), 1, s);
-      HIP_OK(launch_reduce_parts(L0.f32, at(SL.gW, a), SL.parts, L0.kparts, SL.st, SL.st, s));
-    }
+    // z_a = M_a v_a (Laplacian approximation), then w_a = A_S^(a) z_a, each
+    // one launch over all variables and one reduction of its partials
+    sys_gemm(S, l, SL.cls_inv, SL.ptr_inv[j], s);
+    HIP_OK(launch_reduce_parts(L0.f32, Zj, SL.parts, SL.kparts, all, all, s));
+    sys_gemm(S, l, SL.cls_op, SL.ptr_op[j], s);
+    HIP_OK(launch_reduce_parts(L0.f32, SL.gW, SL.parts, SL.kparts, all, all, s));
     HIP_OK(launch_sys_arnoldi(P->N, L0.f32, j, k, nv, SL.gW, SL.gV, Zj, SL.st, SL.D, SL.nd, SL.H,
                               L0.d_elem_class, L0.d_elem_row, L0.d_nbr, L0.d_cls, L0.d_seg_loc,
                               (int)L0.E, L0.max_n, s));
@@ -3615,12 +3620,13 @@ void sys_schwarz_steps(dgs_system* S, int l, const double* b, double* u, int ste
         HIP_OK(launch_scatter(N, L0.f32, u + a * SL.nd, at(SL.du, a), 1, SL.st, L0.d_weights,
                               L0.d_pull, nov_of(P), L0.E, s, first));
     } else {
-      // the Laplacian approximation alone: du_a = M_a r_a
-      for (int a = 0; a < nv; ++a) {
-        sys_gemm(S, l, a, at(SL.rs, a), 0, s);
-        HIP_OK(launch_scatter(N, L0.f32, u + a * SL.nd, SL.parts, L0.kparts, SL.st, L0.d_weights,
-                              L0.d_pull, nov_of(P), L0.E, s, first));
-      }
+      // the Laplacian approximation alone: du_a = M_a r_a, one launch for all
+      // variables; the scatter of each variable sums its partials
+      sys_gemm(S, l, SL.cls_inv, SL.ptr_rs, s);
+      for (int a = 0; a < nv; ++a)
+        HIP_OK(launch_scatter(N, L0.f32, u + a * SL.nd, at(SL.parts, a), SL.kparts,
+                              (long long)nv * SL.st, L0.d_weights, L0.d_pull, nov_of(P), L0.E, s,
+                              first));
     }
   }
 }
@@ -3821,8 +3827,33 @@ int dgs_create_system(const dgs_domain* domain, const int elements[3], int p, do
       SL.nd = P->nd((int)l);
       SL.st = L.rs_total;
       const size_t es = L.f32 ? sizeof(float) : sizeof(double);
-      int mp = 1;
-      for (int v = 0; v < kGemmVariants; ++v) mp = std::max(mp, L.kparts_of[v]);
+      // the joined class list of all variables and its tile plan (32 x 64 or
+      // 16 x 64 tiles, the instances of the grouped GEMM with class pointers)
+      SL.ncls = (int)L.cls.size();
+      std::vector<ClassInfo> ci_inv, ci_op;
+      for (int a = 0; a < nv; ++a) {
+        const Level& La = S->var[a]->levels[l];
+        const Level& Lm = (S->matched ? S->var[a] : S->dir)->levels[l];
+        for (int c = 0; c < SL.ncls; ++c) {
+          ClassInfo I = Lm.cls[c];
+          ci_inv.push_back(I);
+          ClassInfo O = La.cls[c];
+          O.inv = O.op;
+          O.scale = O.scale_op;
+          ci_op.push_back(O);
+        }
+      }
+      const GemmPlan plan = plan_subdomain_gemm(ci_inv, 2);
+      SL.kparts = plan.kparts;
+      SL.small = plan.small;
+      SL.ntiles = (int)plan.tiles.size();
+      SL.tiles = S->alloc<GemmTile>(plan.tiles.size());
+      upload(SL.tiles, plan.tiles, s);
+      SL.cls_inv = S->alloc<ClassInfo>(ci_inv.size());
+      upload(SL.cls_inv, ci_inv, s);
+      SL.cls_op = S->alloc<ClassInfo>(ci_op.size());
+      upload(SL.cls_op, ci_op, s);
+      const int mp = SL.kparts;
       SL.D = S->alloc<double>((size_t)nv * nv * SL.nd);
       HIP_OK(launch_fill(SL.D, 0.0, (long long)nv * nv * SL.nd, s));
       SL.r = S->alloc<double>((size_t)nv * SL.nd);
@@ -3833,10 +3864,24 @@ int dgs_create_system(const dgs_domain* domain, const int elements[3], int p, do
       // rows and products: the class blocks' padding must read as zero
       SL.rs = S->alloc<char>(es * nv * SL.st);
       SL.du = S->alloc<char>(es * nv * SL.st);
-      SL.parts = S->alloc<char>(es * mp * SL.st);
+      SL.parts = S->alloc<char>(es * (size_t)mp * nv * SL.st);
       HIP_OK(hipMemsetAsync(SL.rs, 0, es * nv * SL.st, s));
       HIP_OK(hipMemsetAsync(SL.du, 0, es * nv * SL.st, s));
-      HIP_OK(hipMemsetAsync(SL.parts, 0, es * mp * SL.st, s));
+      HIP_OK(hipMemsetAsync(SL.parts, 0, es * (size_t)mp * nv * SL.st, s));
+      // class (a, c) reads variable a's rows and writes variable a's block of
+      // every part ([part][variable][row])
+      auto ptr_table = [&](const void* rows_base) {
+        std::vector<GemmPtr> t;
+        for (int a = 0; a < nv; ++a)
+          for (int c = 0; c < SL.ncls; ++c)
+            t.push_back(GemmPtr{(const char*)rows_base + es * (size_t)(a * SL.st),
+                                (char*)SL.parts + es * (size_t)(a * SL.st), (long long)nv * SL.st});
+        GemmPtr* d = S->alloc<GemmPtr>(t.size());
+        upload(d, t, s);
+        HIP_OK(hipStreamSynchronize(s));  // t goes out of scope
+        return d;
+      };
+      SL.ptr_rs = ptr_table(SL.rs);
       if (k > 0) {
         SL.gV = S->alloc<char>(es * (size_t)(k + 1) * nv * SL.st);
         SL.gZ = S->alloc<char>(es * (size_t)k * nv * SL.st);
@@ -3846,7 +3891,12 @@ int dgs_create_system(const dgs_domain* domain, const int elements[3], int p, do
         HIP_OK(hipMemsetAsync(SL.gW, 0, es * nv * SL.st, s));
         SL.H = S->alloc<double>((size_t)L.E * (k + 1) * k);
         SL.beta = S->alloc<double>(L.E);
+        for (int j = 0; j < k; ++j) {
+          SL.ptr_inv.push_back(ptr_table((const char*)SL.gV + es * (size_t)j * nv * SL.st));
+          SL.ptr_op.push_back(ptr_table((const char*)SL.gZ + es * (size_t)j * nv * SL.st));
+        }
       }
+      HIP_OK(hipStreamSynchronize(s));  // the class lists and the plan go out of scope
       S->lv.push_back(SL);
     }
     HIP_OK(hipStreamSynchronize(s));
