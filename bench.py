@@ -502,7 +502,7 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
         for rid in srv.finished():
             _, st, _ = srv.fetch(rid)
             its.append(st["iterations"])
-        counters = srv.counters()
+        counters = srv.counters() + srv.timings()
         srv.close()
         return n_requests / dt, its, counters
 
@@ -512,8 +512,13 @@ def run_serving(dg, n_requests=256, max_active=16, precision="mixed", host_threa
                    batched=batched, saturation_solves_per_s_cold_cache=round(cold_tput, 2),
                    saturation_solves_per_s=round(warm_tput, 2),
                    iterations_p50=float(np.median(its)), iterations_max=int(max(its)))
+    steps, bsteps, launches, peak, t_work, t_issue, t_wait, t_host, t_ret = counters
+    summary["host_seconds_warm_loop"] = dict(admission_setup_and_workers=round(t_work, 3),
+                                             engine_issue=round(t_issue, 3),
+                                             engine_wait=round(t_wait, 3),
+                                             engine_host_part=round(t_host, 3),
+                                             retire=round(t_ret, 3))
     if batched:
-        steps, bsteps, launches, peak = counters
         summary["batch_engine"] = dict(steps=bsteps, launches_per_step=round(launches / max(bsteps, 1), 1),
                                        most_requests_per_step=peak)
     if not paced:

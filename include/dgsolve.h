@@ -346,6 +346,14 @@ int dgs_server_step(dgs_server* server, int* n_active, int* n_queued);
  * the batch engine, [2] kernel launches of those steps, [3] the most requests
  * the engine advanced together. */
 int dgs_server_counters(const dgs_server* server, long long counters[4]);
+/* Host seconds since dgs_server_create spent in dgs_server_step:
+ * seconds[0] admission, the set-up of admitted requests and the per-request
+ * work of the worker threads (overlapping the batch engine's step on the
+ * device), [1] issuing the engine's steps (job tables and launches), [2]
+ * waiting for them, [3] the engine's host part (the Givens updates), [4]
+ * retiring finished requests (their solutions copied to the host, memory
+ * released). */
+int dgs_server_timings(const dgs_server* server, double seconds[5]);
 /* Ids of finished requests (up to capacity) and their number. */
 int dgs_server_finished(dgs_server* server, long long* ids, int capacity, int* count);
 /* Copy a finished request's solution (host, n values) and stats, and release

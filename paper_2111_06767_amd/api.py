@@ -32,7 +32,7 @@ EXPORTED = (
     "dgs_server_step", "dgs_server_finished", "dgs_server_fetch", "dgs_subdomain_solves",
     "dgs_set_apply_shape", "dgs_get_apply_shape", "dgs_set_gemm_variant", "dgs_get_gemm_variant",
     "dgs_server_submit_puncture", "dgs_cg_solve", "dgs_grid_coordinates",
-    "dgs_cg_solve_noalloc", "dgs_server_counters",
+    "dgs_cg_solve_noalloc", "dgs_server_counters", "dgs_server_timings",
     "dgs_create_system", "dgs_destroy_system", "dgs_system_num_dofs", "dgs_system_set_coupling",
     "dgs_system_apply", "dgs_system_smooth", "dgs_system_precondition", "dgs_system_solve",
 )
@@ -124,6 +124,7 @@ def load_library(path: str = LIB_PATH):
         ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]
     lib.dgs_server_step.argtypes = [P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
     lib.dgs_server_counters.argtypes = [P, ctypes.POINTER(ctypes.c_longlong)]
+    lib.dgs_server_timings.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     lib.dgs_server_finished.argtypes = [P, ctypes.POINTER(ctypes.c_longlong), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]
     lib.dgs_server_fetch.argtypes = [P, ctypes.c_longlong, ctypes.POINTER(ctypes.c_double),
@@ -570,6 +571,14 @@ class Server:
         c = (ctypes.c_longlong * 4)()
         _check(self._lib.dgs_server_counters(self._h, c))
         return tuple(c[i] for i in range(4))
+
+    def timings(self):
+        """Host seconds in dgs_server_step: (admission, set-up and
+        per-request work; issuing the engine's steps; waiting for them; the
+        engine's host part; retiring finished requests)."""
+        t = (ctypes.c_double * 5)()
+        _check(self._lib.dgs_server_timings(self._h, t))
+        return tuple(t[i] for i in range(5))
 
     def step(self):
         a, q = ctypes.c_int(), ctypes.c_int()

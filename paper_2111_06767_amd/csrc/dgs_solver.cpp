@@ -21,6 +21,7 @@
 #include <functional>
 #include <limits>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -281,11 +282,24 @@ struct dgs_problem {
     else
       (void)hipFree(p);
   }
+  // false when the allocator is the server's block pool and the problem is
+  // deleted only after its work has finished
+  bool sync_before_free = true;
+  // host arrays of set-up uploads that may still be in flight, kept until
+  // the set-up's final synchronisation (one wait instead of one per table)
+  std::vector<std::shared_ptr<void>> setup_keep;
+  template <typename T>
+  void upload_kept(T* dst, std::vector<T>&& src, hipStream_t s) {
+    auto h = std::make_shared<std::vector<T>>(std::move(src));
+    upload(dst, *h, s);
+    setup_keep.push_back(h);
+  }
   ~dgs_problem() {
     std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+    if (!setup_keep.empty()) (void)hipDeviceSynchronize();  // a failed set-up
     // a caller's allocator may hand the memory out again at once: let the
     // device finish with it first (also when set-up failed half-way)
-    if (free_fn && !allocations.empty()) (void)hipDeviceSynchronize();
+    if (free_fn && sync_before_free && !allocations.empty()) (void)hipDeviceSynchronize();
     for (void* p : allocations) {
       if (free_fn)
         free_fn(p, alloc_ctx);
@@ -335,9 +349,9 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
   L.op.n[2] = L.n[2];
   L.op.neumann = P->opt.neumann_faces;
   set_derived(L.op, P->N, P->ht.w[0]);
-  const std::vector<int> nbr = host_neighbors(L);
+  std::vector<int> nbr = host_neighbors(L);
   L.d_nbr = P->alloc<int>(nbr.size());
-  upload(L.d_nbr, nbr, s);
+  P->upload_kept(L.d_nbr, std::move(nbr), s);
   // processing order: columns of 8 x 8 elements in x-y, each swept through z
   // (x fastest inside a layer), so that every face neighbour of an element is
   // processed within about one column layer of it and is still in L2
@@ -354,7 +368,7 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
   for (size_t i = 0; i < order.size() && identity; ++i) identity = order[i] == (int)i;
   if (!identity) {  // the identity order needs no table (and no load)
     L.d_order = P->alloc<int>(order.size());
-    upload(L.d_order, order, s);
+    P->upload_kept(L.d_order, std::move(order), s);
   }
   if (P->N == 8) {  // bricks (p = 7): the same column order at brick granularity
     const int bn[3] = {(L.n[0] + 1) / 2, (L.n[1] + 1) / 2, (L.n[2] + 1) / 2};
@@ -368,10 +382,8 @@ void build_level_mesh(dgs_problem* P, Level& L, hipStream_t s) {
             for (int x = tx; x < std::min(tx + TB, bn[0]); ++x)
               border.push_back((z * bn[1] + y) * bn[0] + x);
     L.d_bricks = P->alloc<int>(border.size());
-    upload(L.d_bricks, border, s);
-    HIP_OK(hipStreamSynchronize(s));
+    P->upload_kept(L.d_bricks, std::move(border), s);
   }
-  HIP_OK(hipStreamSynchronize(s));  // nbr and order go out of scope
   const long long nd = L.E * (long long)P->N * P->N * P->N;
   L.d_u = P->alloc<double>(nd);
   L.d_b = P->alloc<double>(nd);
@@ -488,14 +500,13 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   for (int c = 0; c < ci; ++c) L.max_n = std::max(L.max_n, L.cls[c].n);
   int max_parts = 1;
   for (int v = 0; v < kGemmVariants; ++v) {
-    const GemmPlan plan = plan_subdomain_gemm(L.cls, v);
+    GemmPlan plan = plan_subdomain_gemm(L.cls, v);
     L.gemm_small = plan.small;
     L.kparts_of[v] = plan.kparts;
     L.ntiles[v] = (int)plan.tiles.size();
     L.d_tiles[v] = P->alloc<GemmTile>(plan.tiles.size());
-    upload(L.d_tiles[v], plan.tiles, s);
-    HIP_OK(hipStreamSynchronize(s));  // plan.tiles goes out of scope
     max_parts = std::max(max_parts, plan.kparts);
+    P->upload_kept(L.d_tiles[v], std::move(plan.tiles), s);
   }
   L.gemm_variant = 0;
   L.kparts = L.kparts_of[0];
@@ -505,15 +516,13 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
   L.d_cls = P->alloc<ClassInfo>(ci);
   upload(L.d_cls, L.cls, s);
   L.d_seg_loc = P->alloc<int>(seg_loc.size());
-  upload(L.d_seg_loc, seg_loc, s);
+  P->upload_kept(L.d_seg_loc, std::move(seg_loc), s);
   L.d_weights = P->alloc<double>(weights.size());
-  upload(L.d_weights, weights, s);
+  P->upload_kept(L.d_weights, std::move(weights), s);
   std::vector<int> elem_cv(L.E);
   for (long long e = 0; e < L.E; ++e) elem_cv[e] = elem_class[e] | (elem_code[e] << 24);
   L.d_elem_class = P->alloc<int>(L.E);
-  upload(L.d_elem_class, elem_cv, s);
-  L.d_elem_row = P->alloc<long long>(L.E);
-  upload(L.d_elem_row, elem_row, s);
+  P->upload_kept(L.d_elem_class, std::move(elem_cv), s);
   // scatter pull table: the element's own row, and for every face neighbour b
   // the start of b's strip toward the element (in b's class frame)
   const std::vector<int> nbr = host_neighbors(L);
@@ -542,15 +551,15 @@ void build_level_schwarz(dgs_problem* P, Level& L, hipStream_t s) {
     }
   }
   L.d_pull = P->alloc<PullEntry>(pull.size());
-  upload(L.d_pull, pull, s);
+  P->upload_kept(L.d_pull, std::move(pull), s);
+  L.d_elem_row = P->alloc<long long>(L.E);
+  P->upload_kept(L.d_elem_row, std::move(elem_row), s);
   // the padding of the subdomain rows is never written and must read as zero
   const size_t es = L.f32 ? sizeof(float) : sizeof(double);
   L.d_rs = P->alloc<char>(es * (size_t)L.rs_total);
   L.d_du = P->alloc<char>(es * (size_t)L.rs_total * max_parts);
   HIP_OK(hipMemsetAsync(L.d_rs, 0, es * (size_t)L.rs_total, s));
   HIP_OK(hipMemsetAsync(L.d_du, 0, es * (size_t)L.rs_total * max_parts, s));
-  // host copies of the elem tables are kept in the layouts only
-  HIP_OK(hipStreamSynchronize(s));  // host vectors above go out of scope
 }
 
 // Explicit inverses of A_S for every (class flags, element aspect) key, built
@@ -1870,6 +1879,7 @@ class BatchEngine {
   bool empty() const { return reqs_.empty(); }
   int size() const { return (int)reqs_.size(); }
   int launches_last_step() const { return launches_; }
+  bool issued() const { return issued_; }
 
   // A request whose problem, b and u = 0 are set up (on its own stream, which
   // the caller has synchronised) joins at the next step.
@@ -1892,9 +1902,13 @@ class BatchEngine {
 
   // One lockstep step; returns the requests that finished (their results in
   // r->run.R, r->run.stage = done).
-  std::vector<ServerRequest*> step() {
-    std::vector<ServerRequest*> finished;
-    if (reqs_.empty()) return finished;
+  // One step of every member: issue() enqueues the tables, the launches and
+  // the copy of the pack back to the host; finish() waits for them and runs
+  // the host part.  Host work between the two (the set-up of newly admitted
+  // requests) overlaps the step on the device.
+  void issue() {
+    issued_ = false;
+    if (reqs_.empty()) return;
     if (dirty_) rebuild();
     launches_ = 0;
     JobImage img;
@@ -2041,7 +2055,25 @@ class BatchEngine {
     }
     HIP_OK(hipMemcpyAsync(h_pack_, pack_.p, sizeof(double) * (size_t)stride_ * max_active_,
                           hipMemcpyDeviceToHost, s_));
+    issued_ = true;
+  }
+
+  // t_wait, t_host (optional): seconds spent waiting and in the host part
+  std::vector<ServerRequest*> finish(double* t_wait = nullptr, double* t_host = nullptr) {
+    std::vector<ServerRequest*> finished;
+    if (!issued_) return finished;
+    issued_ = false;
+    const double t0 = now_s();
     HIP_OK(hipStreamSynchronize(s_));
+    const double t1 = now_s();
+    if (t_wait) *t_wait += t1 - t0;
+    struct HostClock {
+      double t1;
+      double* out;
+      ~HostClock() {
+        if (out) *out += now_s() - t1;
+      }
+    } clock{t1, t_host};
     // ---- host part ----
     std::vector<BatchReq> keep;
     for (BatchReq& q : reqs_) {
@@ -2454,6 +2486,7 @@ class BatchEngine {
   std::vector<BatchReq> reqs_;
   std::vector<BatchOp> ops_;
   bool dirty_ = true;
+  bool issued_ = false;  // a step is on the device and finish() has not run
   int launches_ = 0;
 };
 
@@ -2538,6 +2571,61 @@ int create_problem(const dgs_domain* domain, const int elements[3], int p, doubl
                    const std::vector<int>* class_masks = nullptr);
 }  // namespace
 
+// Device blocks of a server's requests when the caller gives no allocator.
+// A freed block is kept by its size class (the next power of two) and handed
+// out again, so that retiring a request costs no hipFree, which waits for
+// the whole device; blocks are freed only once their request's work has
+// finished.  Held blocks beyond `cap` bytes, and all of them when the server
+// is destroyed, go back with hipFree.
+struct BlockPool {
+  std::mutex m;
+  std::map<size_t, std::vector<void*>> free;  // by size class
+  std::unordered_map<void*, size_t> size_of;   // every block handed out
+  size_t held = 0, cap = 0;
+  static size_t size_class(size_t bytes) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    return c;
+  }
+  void* get(size_t bytes) {
+    const size_t c = size_class(bytes);
+    {
+      std::lock_guard<std::mutex> lk(m);
+      auto it = free.find(c);
+      if (it != free.end() && !it->second.empty()) {
+        void* p = it->second.back();
+        it->second.pop_back();
+        held -= c;
+        size_of[p] = c;
+        return p;
+      }
+    }
+    void* p = dalloc<char>(c);
+    std::lock_guard<std::mutex> lk(m);
+    size_of[p] = c;
+    return p;
+  }
+  void put(void* p) {
+    std::lock_guard<std::mutex> lk(m);
+    auto it = size_of.find(p);
+    if (it == size_of.end()) return;
+    const size_t c = it->second;
+    size_of.erase(it);
+    if (held + c > cap) {
+      dfree(p);
+      return;
+    }
+    free[c].push_back(p);
+    held += c;
+  }
+  ~BlockPool() {
+    for (auto& kv : free)
+      for (void* p : kv.second) (void)hipFree(p);
+  }
+  static void* alloc_cb(size_t bytes, void* ctx) { return static_cast<BlockPool*>(ctx)->get(bytes); }
+  static void free_cb(void* p, void* ctx) { static_cast<BlockPool*>(ctx)->put(p); }
+};
+
 // Device memory of a retired request, freed later in a batch: freeing waits
 // for the whole device, which would drain the other requests' stages.
 struct RetiredMemory {
@@ -2548,24 +2636,24 @@ struct RetiredMemory {
 
 struct dgs_server {
   dgs_server_options opt{};
+  // the library's block pool, used when the caller gives no allocator
+  BlockPool blocks;
+  dgs_alloc_fn alloc_fn() const { return opt.alloc_fn ? opt.alloc_fn : &BlockPool::alloc_cb; }
+  dgs_free_fn free_fn() const { return opt.alloc_fn ? opt.free_fn : &BlockPool::free_cb; }
+  void* alloc_ctx() { return opt.alloc_fn ? opt.alloc_ctx : (void*)&blocks; }
   // the requests' own vectors (b, u, puncture fields) from the caller's
-  // allocator when one is given, else hipMalloc
+  // allocator when one is given, else from the block pool
   double* vec(size_t n) {
-    if (!opt.alloc_fn) return dalloc<double>(n);
     std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
-    void* p = opt.alloc_fn(std::max<size_t>(n, 1) * sizeof(double), opt.alloc_ctx);
+    void* p = alloc_fn()(std::max<size_t>(n, 1) * sizeof(double), alloc_ctx());
     if (!p) throw DgsError(DGS_ERR_OOM, "the caller's allocator returned NULL");
     return static_cast<double*>(p);
   }
   // released only after the device has finished with it
   void vec_free(double* p) {
     if (!p) return;
-    if (!opt.alloc_fn) {
-      dfree(p);
-      return;
-    }
     std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
-    opt.free_fn(p, opt.alloc_ctx);
+    free_fn()(p, alloc_ctx());
   }
   int device = 0;
   std::unique_ptr<WorkerPool> pool;  // launching is host-bound: stages run in parallel
@@ -2590,6 +2678,10 @@ struct dgs_server {
   // the cross-request batch engine (created with the first batched request)
   std::unique_ptr<BatchEngine> engine;
   long long steps = 0, batch_steps = 0, batch_launches = 0, batch_peak = 0;
+  // host seconds spent in: admission and the per-request work of the workers
+  // (set-up included), issuing the engine's steps, waiting for them, and the
+  // engine's host part
+  double t_workers = 0, t_issue = 0, t_wait = 0, t_engine_host = 0, t_retire = 0;
   std::vector<Idle> idle;
   double t0 = 0;
   void evict_idle(size_t keep) {  // oldest first, into the batch of frees
@@ -2647,9 +2739,11 @@ void server_setup(dgs_server* S, ServerRequest& r) {
   if (!r.reused) {
     dgs_problem* created = nullptr;
     const int code = create_problem(&r.dom, r.elements, r.p, S->opt.penalty, &S->opt.solver,
-                                    S->opt.alloc_fn, S->opt.free_fn, S->opt.alloc_ctx, r.stream,
+                                    S->alloc_fn(), S->free_fn(), S->alloc_ctx(), r.stream,
                                     &created, r.batched);
     if (code != DGS_OK) throw DgsError(code, g_last_error);
+    // a server deletes a problem only once its work has finished
+    if (!S->opt.alloc_fn) created->sync_before_free = false;
     r.prob = created;
     r.d_b = S->vec(created->nd(0));
     r.d_u = S->vec(created->nd(0));
@@ -2909,6 +3003,7 @@ int create_problem(const dgs_domain* domain, const int elements[3], int p, doubl
       if (o.use_graphs) capture_vgraph(P.get(), 0);
     }
     HIP_OK(hipStreamSynchronize(s));
+    P->setup_keep.clear();
     P->t_setup = now_s() - t0;
     *out = P.release();
     return DGS_OK;
@@ -3209,6 +3304,8 @@ int dgs_server_create(const dgs_server_options* opt, dgs_server** out) {
     std::unique_ptr<dgs_server> S(new dgs_server());
     S->opt = *opt;
     S->t0 = now_s();
+    // free blocks kept for reuse: at most half the budget on top of it
+    S->blocks.cap = (size_t)(opt->hbm_budget_bytes / 2);
     HIP_OK(hipGetDevice(&S->device));
     const int threads = std::min(opt->host_threads > 0 ? opt->host_threads : 4, opt->max_active);
     if (threads > 1) S->pool.reset(new WorkerPool(threads, S->device));
@@ -3295,7 +3392,19 @@ int dgs_server_submit_puncture(dgs_server* S, const dgs_domain* domain, const in
 int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
   return guarded([&]() -> int {
     if (!S) return fail(DGS_ERR_INVALID, "NULL argument");
+    const double t_begin = now_s();
     std::vector<std::unique_ptr<ServerRequest>> admitted = server_select(S);
+    S->t_workers += now_s() - t_begin;
+    // the batch engine's step goes to the device first, so that the set-up
+    // of the newly admitted requests and the per-request work below overlap
+    // it; the requests set up here join the engine after its step
+    double t = now_s();
+    if (S->engine && !S->engine->empty()) {
+      S->batch_peak = std::max<long long>(S->batch_peak, S->engine->size());
+      S->engine->issue();
+    }
+    S->t_issue += now_s() - t;
+    t = now_s();
     // each worker first sets up every W-th newly admitted request (host work
     // that overlaps the stages already on the device), then takes every W-th
     // active request: a request whose stage has finished is completed on the
@@ -3361,8 +3470,14 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
       work(0, 1);
     }
     ++S->steps;
-    // the batch engine: newly set-up requests join, then every batched
-    // request advances by one FGMRES iteration in shared launches
+    S->t_workers += now_s() - t;
+    // the batch engine: every member advanced by one FGMRES iteration in
+    // shared launches; then the newly set-up requests join for the next step
+    if (S->engine && S->engine->issued()) {
+      S->engine->finish(&S->t_wait, &S->t_engine_host);
+      ++S->batch_steps;
+      S->batch_launches += S->engine->launches_last_step();
+    }
     for (auto& rq : admitted) {
       if (!rq->batched) continue;
       if (!S->engine)
@@ -3370,13 +3485,8 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
                                         S->opt.solver.restart));
       S->engine->add(rq.get());
     }
-    if (S->engine && !S->engine->empty()) {
-      S->batch_peak = std::max<long long>(S->batch_peak, S->engine->size());
-      S->engine->step();
-      ++S->batch_steps;
-      S->batch_launches += S->engine->launches_last_step();
-    }
     for (auto& rq : admitted) S->active.push_back(std::move(rq));
+    const double t_ret = now_s();
     std::vector<std::unique_ptr<ServerRequest>> still;
     for (auto& r : S->active) {
       if (r->done())
@@ -3386,6 +3496,7 @@ int dgs_server_step(dgs_server* S, int* n_active, int* n_queued) {
     }
     S->active = std::move(still);
     if (S->active.empty() && S->queue.empty()) S->free_retired();  // idle: return the memory
+    S->t_retire += now_s() - t_ret;
     if (n_active) *n_active = (int)S->active.size();
     if (n_queued) *n_queued = (int)S->queue.size();
     return DGS_OK;
@@ -3398,6 +3509,16 @@ int dgs_server_counters(const dgs_server* S, long long counters[4]) {
   counters[1] = S->batch_steps;
   counters[2] = S->batch_launches;
   counters[3] = S->batch_peak;
+  return DGS_OK;
+}
+
+int dgs_server_timings(const dgs_server* S, double seconds[5]) {
+  if (!S || !seconds) return fail(DGS_ERR_INVALID, "NULL argument");
+  seconds[0] = S->t_workers;
+  seconds[1] = S->t_issue;
+  seconds[2] = S->t_wait;
+  seconds[3] = S->t_engine_host;
+  seconds[4] = S->t_retire;
   return DGS_OK;
 }
 
