@@ -1,0 +1,90 @@
+"""Pins of the oracle's DG operator on curved (isoparametric) elements
+(Sec. II, eqs. massmat, stiffmat, liftop with the element Jacobian), each
+against something other than the code it checks: the affine box operator
+(pinned by its own tests), exact derivatives of polynomial maps, the exact
+reproduction of linear functions, and convergence to a manufactured
+solution."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import curved, mesh as omesh, operator as oop
+
+C = 1.5
+
+
+@pytest.mark.parametrize("elements,p,neumann", [((3, 2, 2), 3, ()), ((2, 2, 3), 4, (1, 4)),
+                                                ((1, 3, 2), 2, (0,))])
+def test_affine_coordinates_give_the_box_operator(elements, p, neumann):
+    box = omesh.BoxMesh((0, 0, 0), (1.0, 1.2, 0.9), elements, p, neumann=neumann)
+    cm = curved.CurvedMesh(box, np.stack(box.node_coordinates()))
+    u = W.random_normal(41, box.ndof)
+    ref = oop.apply_operator(box, u.reshape(box.E, box.N, box.N, box.N), C).reshape(-1)
+    got = curved.apply_operator(cm, u, C)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    assert np.allclose(curved.mass_diagonal(cm),
+                       np.broadcast_to(oop.mass_diagonal(box), cm.det.shape), rtol=1e-14, atol=0)
+
+
+def test_geometry_of_a_polynomial_map_is_exact():
+    # a quadratic map is its own degree-p interpolant (p >= 2), so the
+    # collocation Jacobian equals the analytic one
+    box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 1, 2), 3)
+    X = np.stack(box.node_coordinates())
+    e = 0.1
+    x = np.stack([X[0] + e * X[0] * X[1], X[1] + e * X[1] ** 2, X[2] + e * X[0] * X[2]])
+    cm = curved.CurvedMesh(box, x)
+    # dx/dX analytic; dX/dxi = h/2 per axis
+    dxdX = np.zeros(X.shape[1:] + (3, 3))
+    dxdX[..., 0, 0] = 1 + e * X[1]
+    dxdX[..., 0, 1] = e * X[0]
+    dxdX[..., 1, 1] = 1 + 2 * e * X[1]
+    dxdX[..., 2, 0] = e * X[2]
+    dxdX[..., 2, 2] = 1 + e * X[0]
+    J = dxdX * (box.h / 2.0)[None, None, None, None, None, :]
+    assert np.allclose(cm.jac, J, rtol=0, atol=1e-13)
+    assert np.allclose(cm.det, np.linalg.det(J), rtol=1e-13, atol=0)
+    assert np.allclose(np.einsum("...ij,...jk->...ik", cm.inv, J), np.eye(3), atol=1e-13)
+
+
+def test_linear_functions_are_reproduced_exactly_inside():
+    # u = a.x + c is a degree-p polynomial in xi on every element and
+    # continuous across faces: its lifted gradient is the constant a, so
+    # -M D_i v_i vanishes and every interior face flux cancels
+    box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (4, 4, 4), 3)
+    cm = curved.CurvedMesh(box, curved.deformed_box(box, 0.1))
+    x = cm.xyz
+    u = 0.3 * x[0] - 0.7 * x[1] + 0.2 * x[2] + 1.0
+    Au = curved.apply_operator(cm, u, C).reshape(box.E, -1)
+    inner = [e for e in range(box.E) if not any(f for pair in box.external_flags(e) for f in pair)]
+    assert len(inner) == 8
+    assert np.abs(Au[inner]).max() <= 1e-13 * np.abs(Au).max()
+
+
+def test_converges_to_a_manufactured_solution_on_a_curved_grid():
+    # -Delta u = 3 pi^2 u with u = prod sin(pi x_d) on the deformed unit cube
+    # (the map keeps the boundary, where u = 0)
+    errs = []
+    for p in (2, 3, 4, 5):
+        box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 2, 2), p)
+        cm = curved.CurvedMesh(box, curved.deformed_box(box, 0.1))
+        X = cm.xyz
+        uex = (np.sin(np.pi * X[0]) * np.sin(np.pi * X[1]) * np.sin(np.pi * X[2])).reshape(-1)
+        b = curved.apply_mass(cm, 3 * np.pi ** 2 * uex).reshape(-1)
+        us = np.linalg.solve(curved.assemble(cm, C), b)
+        errs.append(np.abs(us - uex).max())
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[-1] < 2e-4 and errs[0] / errs[-1] > 200, errs
+
+
+def test_operator_on_curved_elements():
+    # the strong form with a varying metric is not symmetric (D_i applies the
+    # metric after the derivative), but its asymmetry vanishes with the
+    # deformation and its symmetric part stays positive definite
+    box = omesh.BoxMesh((0, 0, 0), (1, 1.2, 0.9), (3, 2, 2), 2)
+    asym = []
+    for amp in (0.0, 0.05, 0.1):
+        A = curved.assemble(curved.CurvedMesh(box, curved.deformed_box(box, amp)), C)
+        asym.append(np.abs(A - A.T).max() / np.abs(A).max())
+        assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+    assert asym[0] < 1e-14 and 0 < asym[1] < asym[2] < 0.05, asym
