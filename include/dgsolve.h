@@ -248,6 +248,24 @@ int dgs_subdomain_solves(dgs_problem* prob, int level, int reps, double* flops, 
 int dgs_set_apply_shape(dgs_problem* prob, int level, int shape);
 int dgs_get_apply_shape(const dgs_problem* prob, int level, int* shape);
 
+/* Curved (isoparametric) elements, Sec. II: eqs. massmat, stiffmat and
+ * liftop with the element Jacobian, flat background metric.  xyz (device,
+ * 3 * ndof doubles: all x, then all y, then all z, canonical layout) gives
+ * the physical coordinates of every node of the finest grid; the element
+ * maps are their degree-p interpolants and must agree on shared faces (the
+ * box topology and its boundary faces stay those of the problem).  The
+ * library computes the Jacobian, its determinant and inverse at every node;
+ * then dgs_apply_operator, dgs_apply_mass, dgs_solve and dgs_cg_solve use
+ * the curved operator (unit normals n_c = s invJ^d_c/|invJ^d|, surface
+ * Jacobian det(J) |invJ^d|, element size 2/|invJ^d| in the penalty), while
+ * dgs_precondition and dgs_schwarz_smooth keep the multigrid-Schwarz cycle
+ * of the box grid: a preconditioner that approximates the curved operator.
+ * NULL returns to the box operator.  p <= 7; DGS_ERR_INVALID for a
+ * Jacobian determinant <= 0 anywhere.  dgs_newton_solve refuses a problem
+ * with curved elements.  Synchronises the stream once (the determinant
+ * check). */
+int dgs_set_geometry(dgs_problem* prob, const double* xyz, void* stream);
+
 /* Tile variant of the grouped subdomain-solve GEMM on multigrid level
  * `level` (Sec. III.D.2 subdomain solves; the variant changes the tiling and
  * the split of the K range, so results agree to rounding):

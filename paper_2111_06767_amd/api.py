@@ -33,7 +33,7 @@ EXPORTED = (
     "dgs_set_apply_shape", "dgs_get_apply_shape", "dgs_set_gemm_variant", "dgs_get_gemm_variant",
     "dgs_server_submit_puncture", "dgs_cg_solve", "dgs_grid_coordinates",
     "dgs_cg_solve_noalloc", "dgs_server_counters", "dgs_server_timings",
-    "dgs_create_system", "dgs_destroy_system", "dgs_system_num_dofs", "dgs_system_set_coupling",
+    "dgs_set_geometry", "dgs_create_system", "dgs_destroy_system", "dgs_system_num_dofs", "dgs_system_set_coupling",
     "dgs_system_apply", "dgs_system_smooth", "dgs_system_precondition", "dgs_system_solve",
 )
 
@@ -136,6 +136,7 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_get_apply_shape.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.dgs_set_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.c_int]
     lib.dgs_get_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.dgs_set_geometry.argtypes = [P, dp, P]
     lib.dgs_create_system.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
                                       ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.c_int,
@@ -331,6 +332,12 @@ class Problem:
     def set_gemm_variant(self, variant, level=0):
         """Override the autotuned GEMM tile variant of `level`."""
         _check(self._lib.dgs_set_gemm_variant(self._h, int(level), int(variant)))
+
+    def set_geometry(self, xyz=None, stream=None):
+        """Curved elements: physical coordinates of every node (a device tensor
+        of 3 * ndof: x, then y, then z); None returns to the box grid."""
+        ptr = ctypes.c_void_p(None) if xyz is None else _ptr(xyz, 3 * self.ndof, "xyz")
+        _check(self._lib.dgs_set_geometry(self._h, ptr, _stream(stream)))
 
     def set_diagonal(self, d=None, stream=None):
         """Operator A + diag(d) for smoothing, preconditioning and solves (None: A)."""

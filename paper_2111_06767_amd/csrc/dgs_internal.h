@@ -317,6 +317,27 @@ hipError_t launch_prolongate_add(int N, const double* coarse, double* fine, cons
                                  const int nc[3], const int split[3], const MgTables& T,
                                  hipStream_t s);
 
+// Curved (isoparametric) elements: per-node metric of the finest level, set
+// from caller-given node coordinates.  inv holds invJ^d_c = dxi^d/dx^c as 9
+// fields (field 3 d + c), det the Jacobian determinant, grad 3 work fields
+// (the physical gradient of the operand), D the N x N LGL derivative and w
+// the N LGL weights (device copies).  Elements of 2..8 points per dimension.
+struct CurvedGeometry {
+  double* inv = nullptr;
+  double* det = nullptr;
+  double* grad = nullptr;
+  double* D = nullptr;
+  double* w = nullptr;
+};
+hipError_t launch_curved_geometry(int N, const double* xyz, long long E, const double* D,
+                                  double* inv, double* det, hipStream_t s);
+// out = A u (+ diag u) or, with residual, out = b - (A u + diag u) (diag may be NULL)
+hipError_t launch_curved_apply(int N, bool residual, const double* u, double* out, const double* b,
+                               const double* diag, const CurvedGeometry& G, const int* nbr, double C,
+                               int neumann, long long E, hipStream_t s);
+hipError_t launch_curved_mass(int N, const double* f, double* out, const CurvedGeometry& G,
+                              long long E, hipStream_t s);
+
 // Vector kernels.
 hipError_t launch_fill(double* x, double v, long long n, hipStream_t s);
 // FP32 or FP64 pseudo-random values in [-0.5, 0.5) (timing operands)

@@ -248,6 +248,11 @@ struct dgs_problem {
   // a variable of a system: the Neumann faces of all its variables, which
   // decide the classes and frames (empty for a scalar problem)
   std::vector<int> class_masks;
+  // curved elements on the finest level (dgs_set_geometry): the operator,
+  // the mass and the Krylov solves use this metric; the multigrid
+  // preconditioner keeps the box hierarchy
+  bool curved_on = false;
+  CurvedGeometry curved;
   // captured V-cycles (index: linearised operator or not) and the capture stream
   hipGraphExec_t vgraph[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
@@ -1217,6 +1222,12 @@ void apply_fine(dgs_problem* P, const double* x, double* y, hipStream_t s,
                 double* xcopy = nullptr) {
   Level& L = P->levels[0];
   const bool diag = P->diag_active && L.d_diag != nullptr;
+  if (P->curved_on) {
+    if (xcopy) HIP_OK(launch_copy(xcopy, x, P->nd(0), s));
+    HIP_OK(launch_curved_apply(P->N, false, x, y, nullptr, diag ? L.d_diag : nullptr, P->curved,
+                               L.d_nbr, P->penalty, L.op.neumann, L.E, s));
+    return;
+  }
   HIP_OK(launch_apply(P->N, diag ? kApplyDiag : kApply, x, y, nullptr, L.d_diag, nullptr, L.d_nbr,
                       L.op, P->dt, L.acfg_out, s, L.d_order, GatherOut{}, xcopy));
 }
@@ -1224,6 +1235,11 @@ void apply_fine(dgs_problem* P, const double* x, double* y, hipStream_t s,
 void residual_fine(dgs_problem* P, const double* x, const double* b, double* r, hipStream_t s) {
   Level& L = P->levels[0];
   const bool diag = P->diag_active && L.d_diag != nullptr;
+  if (P->curved_on) {
+    HIP_OK(launch_curved_apply(P->N, true, x, r, b, diag ? L.d_diag : nullptr, P->curved, L.d_nbr,
+                               P->penalty, L.op.neumann, L.E, s));
+    return;
+  }
   HIP_OK(launch_apply(P->N, diag ? kResidualDiag : kResidual, x, r, b, L.d_diag, nullptr, L.d_nbr,
                       L.op, P->dt, L.acfg_out, s, L.d_order));
 }
@@ -3048,7 +3064,10 @@ int dgs_apply_mass(const dgs_problem* prob, const double* f, double* b, void* st
   return guarded([&]() -> int {
     if (!prob || !f || !b) return fail(DGS_ERR_INVALID, "NULL argument");
     const Level& L = prob->levels[0];
-    HIP_OK(launch_mass(prob->N, f, b, L.E, L.h, prob->dt, as_stream(stream)));
+    if (prob->curved_on)
+      HIP_OK(launch_curved_mass(prob->N, f, b, prob->curved, L.E, as_stream(stream)));
+    else
+      HIP_OK(launch_mass(prob->N, f, b, L.E, L.h, prob->dt, as_stream(stream)));
     return DGS_OK;
   });
 }
@@ -3058,8 +3077,49 @@ int dgs_apply_operator(dgs_problem* prob, const double* u, double* Au, void* str
     if (!prob || !u || !Au) return fail(DGS_ERR_INVALID, "NULL argument");
     if (u == Au) return fail(DGS_ERR_INVALID, "u and Au must not overlap");
     Level& L = prob->levels[0];
-    HIP_OK(launch_apply(prob->N, kApply, u, Au, nullptr, nullptr, nullptr, L.d_nbr, L.op, prob->dt,
-                        L.acfg_out, as_stream(stream), L.d_order));
+    if (prob->curved_on)
+      HIP_OK(launch_curved_apply(prob->N, false, u, Au, nullptr, nullptr, prob->curved, L.d_nbr,
+                                 prob->penalty, L.op.neumann, L.E, as_stream(stream)));
+    else
+      HIP_OK(launch_apply(prob->N, kApply, u, Au, nullptr, nullptr, nullptr, L.d_nbr, L.op, prob->dt,
+                          L.acfg_out, as_stream(stream), L.d_order));
+    return DGS_OK;
+  });
+}
+
+int dgs_set_geometry(dgs_problem* prob, const double* xyz, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob) return fail(DGS_ERR_INVALID, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    if (!xyz) {
+      prob->curved_on = false;
+      return DGS_OK;
+    }
+    const int N = prob->N;
+    if (N > 8) return fail(DGS_ERR_INVALID, "curved elements are limited to p <= 7");
+    Level& L = prob->levels[0];
+    const long long nd = prob->nd(0);
+    CurvedGeometry& G = prob->curved;
+    if (!G.inv) {
+      G.inv = prob->alloc<double>((size_t)9 * nd);
+      G.det = prob->alloc<double>(nd);
+      G.grad = prob->alloc<double>((size_t)3 * nd);
+      G.D = prob->alloc<double>((size_t)N * N);
+      G.w = prob->alloc<double>(N);
+      upload(G.D, prob->ht.D, s);
+      upload(G.w, prob->ht.w, s);
+    }
+    HIP_OK(launch_curved_geometry(N, xyz, L.E, G.D, G.inv, G.det, s));
+    // every element map must preserve orientation
+    std::vector<double> det(nd);
+    HIP_OK(hipMemcpyAsync(det.data(), G.det, sizeof(double) * nd, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (double v : det)
+      if (!(v > 0.0) || !std::isfinite(v)) {
+        prob->curved_on = false;
+        return fail(DGS_ERR_INVALID, "the node coordinates give a Jacobian determinant <= 0");
+      }
+    prob->curved_on = true;
     return DGS_OK;
   });
 }
@@ -3227,6 +3287,7 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
     if (!prob || !alpha || !beta || !b || !u) return fail(DGS_ERR_INVALID, "NULL argument");
     if (!(newton_rtol > 0.0) || !(linear_rtol > 0.0) || max_newton < 1)
       return fail(DGS_ERR_INVALID, "invalid Newton tolerances");
+    if (prob->curved_on) return fail(DGS_ERR_INVALID, "the puncture problem is set on the box grid");
     hipStream_t s = as_stream(stream);
     const double t0 = now_s();
     NewtonRun nr;

@@ -1,0 +1,116 @@
+"""GPU parity of curved (isoparametric) elements against the oracle, through
+the C ABI: the operator and the mass on deformed grids (Sec. II with the
+element Jacobian), and FGMRES solves whose multigrid-Schwarz preconditioner
+keeps the box grid."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import curved, krylov, mesh as omesh, multigrid
+from tests.gpu_util import announce, rel_max, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+C = 1.5
+
+
+def _problem(box, **opts):
+    import paper_2111_06767_amd as dg
+    return dg.Problem(tuple(box.lower), tuple(box.upper), box.n, box.p, penalty=C,
+                      neumann_faces=sum(1 << f for f in box.neumann), **opts)
+
+
+@pytest.mark.parametrize("elements,p,neumann,amp", [((3, 2, 2), 3, (), 0.1), ((2, 3, 2), 5, (1, 4), 0.08),
+                                                    ((2, 2, 2), 7, (0,), 0.05), ((4, 1, 2), 2, (), 0.12),
+                                                    ((1, 1, 1), 4, (), 0.1)])
+def test_curved_apply_matches_oracle(elements, p, neumann, amp):
+    announce(f"curved apply elements={elements} p={p} neumann={neumann}")
+    box = omesh.BoxMesh((0, 0, 0), (1.0, 1.1, 0.9), elements, p, neumann=neumann)
+    xyz = curved.deformed_box(box, amp)
+    cm = curved.CurvedMesh(box, xyz)
+    prob = _problem(box, mg_levels=1)
+    prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    u = W.random_normal(51 + p, box.ndof)
+    ref = curved.apply_operator(cm, u, C)
+    got = to_np(prob.apply(to_gpu(u)))
+    assert rel_max(got, ref) < 1e-12, rel_max(got, ref)
+    f = W.random_uniform(52, box.ndof)
+    assert rel_max(to_np(prob.apply_mass(to_gpu(f))), curved.apply_mass(cm, f).reshape(-1)) < 1e-14
+    prob.close()
+
+
+def test_box_coordinates_give_the_box_operator():
+    announce("curved kernel on box coordinates")
+    box = omesh.BoxMesh((0, 0, 0), (1.2, 1.0, 0.8), (3, 2, 2), 4, neumann=(3,))
+    prob = _problem(box, mg_levels=1)
+    u = to_gpu(W.random_normal(53, box.ndof))
+    ref = to_np(prob.apply(u))
+    prob.set_geometry(to_gpu(np.stack(box.node_coordinates()).reshape(-1)))
+    got = to_np(prob.apply(u))
+    assert rel_max(got, ref) < 1e-13
+    prob.set_geometry(None)
+    assert np.array_equal(to_np(prob.apply(u)), ref)
+    prob.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_curved_solve_matches_oracle(precision):
+    # the operator is the curved one, the V-cycle that of the box grid: the
+    # oracle runs the same FGMRES with its box V-cycle
+    announce(f"curved solve {precision}")
+    box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (4, 4, 2), 3)
+    xyz = curved.deformed_box(box, 0.1)
+    cm = curved.CurvedMesh(box, xyz)
+    X = cm.xyz
+    f = 3 * np.pi ** 2 * np.sin(np.pi * X[0]) * np.sin(np.pi * X[1]) * np.sin(np.pi * X[2])
+    b = curved.apply_mass(cm, f).reshape(-1)
+    A = lambda v: curved.apply_operator(cm, v, C)
+    x_ref, its_ref, _ = krylov.fgmres(A, b, precondition=multigrid.VCycle(box, C, levels=2),
+                                      rtol=1e-10)
+    prob = _problem(box, mg_levels=2, precision=precision)
+    prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    u, st = prob.solve(to_gpu(b))
+    u = to_np(u)
+    assert st["converged"] and st["rel_residual"] <= 1e-10
+    assert abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
+    assert np.linalg.norm(b - A(u)) / np.linalg.norm(b) <= 1e-10
+    assert np.linalg.norm(u - x_ref) / np.linalg.norm(x_ref) <= 1e-9
+    prob.close()
+
+
+def test_curved_solve_equals_the_dense_solution():
+    announce("curved solve vs dense")
+    box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 2, 2), 3)
+    xyz = curved.deformed_box(box, 0.15)
+    cm = curved.CurvedMesh(box, xyz)
+    b = W.random_normal(54, box.ndof)
+    exact = np.linalg.solve(curved.assemble(cm, C), b)
+    prob = _problem(box, mg_levels=2)
+    prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    u, st = prob.solve(to_gpu(b))
+    assert st["converged"]
+    assert np.linalg.norm(to_np(u) - exact) / np.linalg.norm(exact) <= 1e-9
+    prob.close()
+
+
+def test_geometry_checks():
+    import paper_2111_06767_amd as dg
+    announce("curved geometry checks")
+    box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 1, 1), 2)
+    prob = _problem(box, mg_levels=1)
+    xyz = np.stack(box.node_coordinates())
+    flipped = xyz.copy()
+    flipped[0, 0] = flipped[0, 0][:, :, ::-1]  # mirror element 0 in x: det < 0
+    with pytest.raises(dg.DgsError):
+        prob.set_geometry(to_gpu(flipped.reshape(-1)))
+    prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    n = prob.ndof
+    al, be = to_gpu(np.ones(n)), to_gpu(np.ones(n))
+    with pytest.raises(dg.DgsError):  # the puncture problem is set on the box grid
+        prob.newton_solve(al, be)
+    prob.close()
+    big = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (1, 1, 1), 8)
+    prob = _problem(big, mg_levels=1)
+    with pytest.raises(dg.DgsError):
+        prob.set_geometry(to_gpu(np.stack(big.node_coordinates()).reshape(-1)))
+    prob.close()
