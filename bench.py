@@ -441,6 +441,68 @@ def system_leg(dg, precision, laplacian_bc, k, steps=5, warmup=1):
                 converged=st["converged"])
 
 
+def deformed_coordinates(dg, cfg, amplitude, elements=None, p=None):
+    """Node coordinates of the box map x = X + a c prod_d sin(pi (X_d - lo_d)/L_d),
+    c = (1, 0.7, 0.4) (the box boundary stays in place): a device tensor of
+    3 * ndof (x, then y, then z)."""
+    import torch
+    el = elements or cfg["elements"]
+    pp = p or cfg["p"]
+    X = dg.points(cfg["lower"], cfg["upper"], el, pp)
+    lo = np.asarray(cfg["lower"], float)
+    L = np.asarray(cfg["upper"], float) - lo
+    bump = np.prod([np.sin(np.pi * (X[d] - lo[d]) / L[d]) for d in range(3)], axis=0)
+    xyz = X + amplitude * np.array([1.0, 0.7, 0.4])[:, None] * bump[None, :]
+    return torch.as_tensor(xyz.reshape(-1)).cuda()
+
+
+def curved_leg(dg, precision, amplitude=0.1, steps=10, warmup=2):
+    """The 16^3 p=7 headline solve on a deformed grid: curved operator,
+    V-cycle of the box grid as the preconditioner."""
+    import torch
+    import workloads as W
+    prob = dg.Problem(C5["lower"], C5["upper"], C5["elements"], C5["p"], penalty=1.5,
+                      mg_levels=C5["levels"], precision=precision)
+    prob.set_geometry(deformed_coordinates(dg, C5, amplitude))
+    xyz = deformed_coordinates(dg, C5, amplitude).view(3, -1)
+    x, y, z = (xyz[d].cpu().numpy() for d in range(3))
+    f = torch.as_tensor(W.fourier_source(W.fourier_modes(W.SEED_C5), x, y, z)).cuda()
+    b = prob.apply_mass(f)
+    u, st, times, total = time_solves(prob, b, steps, warmup)
+    prob.close()
+    return dict(ms=_ms(times), iterations=st["iterations"], rel_residual=st["rel_residual"],
+                converged=st["converged"])
+
+
+def time_curved_apply(dg, elements, p, amplitude=0.1, reps=50, warm=5):
+    """Curved-element apply (the gradient and operator kernels), HIP events."""
+    import torch
+    import workloads as W
+    cfg = dict(lower=(0, 0, 0), upper=(1, 1, 1), elements=elements, p=p)
+    prob = dg.Problem(cfg["lower"], cfg["upper"], elements, p, mg_levels=1)
+    prob.set_geometry(deformed_coordinates(dg, cfg, amplitude))
+    u = torch.as_tensor(W.random_normal(W.SEED_APPLY, prob.ndof)).cuda()
+    out = torch.empty_like(u)
+    for _ in range(warm):
+        prob.apply(u, out)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        prob.apply(u, out)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = prob.ndof
+    prob.close()
+    del u, out
+    torch.cuda.empty_cache()
+    # algorithmic: read u and the metric (9 inverse-Jacobian entries and the
+    # determinant), write A u: 96 B per DOF
+    return dict(elements=list(elements), p=p, ndof=n, ms_per_apply=ms, gdofs=n / (ms * 1e-3) / 1e9,
+                algorithmic_bytes_per_dof=96, achieved_gbs=96 * n / (ms * 1e-3) / 1e9)
+
+
 def newton_leg(dg, precision, steps=10, warmup=2):
     """The 6^3, p = 7 puncture problem on [-20, 20]^3 by Newton-Krylov with the
     multigrid-Schwarz preconditioner (subdomain GMRES(3))."""
@@ -702,6 +764,16 @@ def main():
                     _log(f"8^3 p=6 five-variable system, {bc} k={k} {prec}")
                     systems[f"k{k}_{bc}_{prec}"] = system_leg(dg, prec, bc, k)
 
+    # -- curved elements: the headline solve on a deformed grid ----------------
+    curved = None
+    if not args.no_variants:
+        curved = {}
+        for prec in ("fp64", "mixed"):
+            _log(f"16^3 p=7 deformed grid {prec}")
+            curved[prec] = curved_leg(dg, prec)
+        _log("curved apply 40^3 p=7")
+        curved["apply_40^3_p7"] = time_curved_apply(dg, (40, 40, 40), 7)
+
     # -- applies --------------------------------------------------------------
     _log("operator applies")
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
@@ -820,6 +892,7 @@ def main():
         "c2_variants_mixed": variants,
         "c3_puncture_6x6x6_p7": c3,
         "system_5var_8x8x8_p6": systems,
+        "curved_16x16x16_p7": curved,
         "apply": {"c2_shape": apply_c2, "16^3_p7": apply_c5, "40^3_p7": apply_big,
                   "sweep_2M_dofs": sweep},
         "serving": serving,
