@@ -434,6 +434,65 @@ int dgs_system_precondition(dgs_system* sys, const double* r, double* z, void* s
  * confirmed by the true residual; DGS_OK or DGS_NOT_CONVERGED. */
 int dgs_system_solve(dgs_system* sys, const double* b, double* u, dgs_stats* stats, void* stream);
 
+/* ---- hp-nonuniform meshes (Sec. II: blocks split into elements by h
+ * refinement with two-to-one balance, elements of their own degree; Sec.
+ * III.C.1: coarsening keeps the smaller degree) ------------------------------
+ *
+ * The box `domain` is a grid of blocks[0] x blocks[1] x blocks[2] equal
+ * blocks, numbered x fastest.  Block b is split 2^L times along dimension d,
+ * L = block_levels[3 b + d] in [0, 10]; the levels of face neighbours may
+ * differ by at most one along every dimension of their shared face
+ * (DGS_ERR_INVALID otherwise).  Elements are numbered block by block and x
+ * fastest inside a block; element e has degree degrees[3 e + d] in [1, 7]
+ * along dimension d (N_d = degree + 1 points).  num_elements must equal the
+ * sum over blocks of 2^(L_x + L_y + L_z).
+ *
+ * Data layout: element by element, element e's N_x N_y N_z nodes in
+ * [k][j][i] order (x fastest), FP64, device pointers owned by the caller.
+ *
+ * Faces shared by elements of different degree or size carry mortars: both
+ * sides' traces and normal derivatives are interpolated to the mortar (the
+ * larger degree per face dimension over the common part of the faces), the
+ * internal-penalty fluxes (eqs. numflux, penalty, with the degree and width
+ * normal to the face) are evaluated there and projected back to each
+ * element's face points by the exact L2 projection.  The operator is not
+ * symmetric on nonconforming faces (lumped element mass against the exact
+ * projection), so the solver is FGMRES; CG is not offered.
+ *
+ * Schwarz subdomains reach N_overlap points into every face neighbour, all
+ * neighbours of a finer face included; each point's weights come from its
+ * own element and sum to one.  Subdomains of equal structure share one
+ * explicit inverse, built on the device.  Options: overlap, mg_levels,
+ * pre_smooth, post_smooth, max_iter, rtol, restart and neumann_faces apply;
+ * precision must be DGS_FP64 and cycle 1 with additive 0 (DGS_ERR_INVALID
+ * otherwise); the other fields are unused.  Workspaces are allocated with
+ * hipMalloc.  The set-up synchronises the stream. */
+typedef struct dgs_hp_problem dgs_hp_problem;
+int dgs_create_hp_problem(const dgs_domain* domain, const int blocks[3], const int* block_levels,
+                          const int* degrees, int num_elements, double penalty,
+                          const dgs_options* opt, void* stream, dgs_hp_problem** out);
+int dgs_destroy_hp_problem(dgs_hp_problem* prob);
+/* Points of the finest mesh (-1 for NULL). */
+long long dgs_hp_num_dofs(const dgs_hp_problem* prob);
+/* Multigrid levels, and the number of distinct subdomain inverses of one
+ * level (-1 for a bad argument). */
+int dgs_hp_num_levels(const dgs_hp_problem* prob);
+int dgs_hp_num_classes(const dgs_hp_problem* prob, int level);
+/* xyz (device, 3 * ndof): xyz[d * ndof + idx], the node coordinates.
+ * Synchronises the stream. */
+int dgs_hp_node_coordinates(dgs_hp_problem* prob, double* xyz, void* stream);
+/* Au = A u and Mf = M f (eq. massmat) on the finest mesh; no synchronisation. */
+int dgs_hp_apply_operator(dgs_hp_problem* prob, const double* u, double* Au, void* stream);
+int dgs_hp_apply_mass(dgs_hp_problem* prob, const double* f, double* Mf, void* stream);
+/* `steps` additive Schwarz steps on the finest mesh, in place on u. */
+int dgs_hp_smooth(dgs_hp_problem* prob, const double* b, double* u, int steps, void* stream);
+/* z = one V-cycle applied to r (z starts from zero). */
+int dgs_hp_precondition(dgs_hp_problem* prob, const double* r, double* z, void* stream);
+/* FGMRES preconditioned by the V-cycle from the initial guess in u, to the
+ * relative residual opt->rtol confirmed by the true residual; DGS_OK or
+ * DGS_NOT_CONVERGED.  Synchronises once per iteration. */
+int dgs_hp_solve(dgs_hp_problem* prob, const double* b, double* u, dgs_stats* stats, void* stream);
+
 /* Message of the last error on the calling thread ("" if none). */
 const char* dgs_last_error(void);
 

@@ -35,6 +35,9 @@ EXPORTED = (
     "dgs_cg_solve_noalloc", "dgs_server_counters", "dgs_server_timings",
     "dgs_set_geometry", "dgs_create_system", "dgs_destroy_system", "dgs_system_num_dofs", "dgs_system_set_coupling",
     "dgs_system_apply", "dgs_system_smooth", "dgs_system_precondition", "dgs_system_solve",
+    "dgs_create_hp_problem", "dgs_destroy_hp_problem", "dgs_hp_num_dofs", "dgs_hp_num_levels",
+    "dgs_hp_num_classes", "dgs_hp_node_coordinates", "dgs_hp_apply_operator", "dgs_hp_apply_mass",
+    "dgs_hp_smooth", "dgs_hp_precondition", "dgs_hp_solve",
 )
 
 
@@ -148,11 +151,26 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_system_smooth.argtypes = [P, dp, dp, ctypes.c_int, P]
     lib.dgs_system_precondition.argtypes = [P, dp, dp, P]
     lib.dgs_system_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
+    lib.dgs_create_hp_problem.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
+                                          ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                          ctypes.c_int, ctypes.c_double, ctypes.POINTER(Options), P,
+                                          ctypes.POINTER(P)]
+    lib.dgs_destroy_hp_problem.argtypes = [P]
+    lib.dgs_hp_num_dofs.argtypes = [P]
+    lib.dgs_hp_num_levels.argtypes = [P]
+    lib.dgs_hp_num_classes.argtypes = [P, ctypes.c_int]
+    lib.dgs_hp_node_coordinates.argtypes = [P, dp, P]
+    lib.dgs_hp_apply_operator.argtypes = [P, dp, dp, P]
+    lib.dgs_hp_apply_mass.argtypes = [P, dp, dp, P]
+    lib.dgs_hp_smooth.argtypes = [P, dp, dp, ctypes.c_int, P]
+    lib.dgs_hp_precondition.argtypes = [P, dp, dp, P]
+    lib.dgs_hp_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
     lib.dgs_last_error.argtypes = []
     lib.dgs_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
         if name not in ("dgs_default_options", "dgs_last_error"):
             getattr(lib, name).restype = ctypes.c_int
+    lib.dgs_hp_num_dofs.restype = ctypes.c_longlong
     _lib = lib
     return lib
 
@@ -609,3 +627,85 @@ class Server:
         code = _check(self._lib.dgs_server_fetch(self._h, rid, u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                                  n, ctypes.byref(st), times), allow_not_converged=True)
         return u, _stats_dict(st, hist, code), list(times)
+
+
+class HpProblem:
+    """An hp-nonuniform mesh (see dgs_create_hp_problem): the box split into
+    blocks[0] x blocks[1] x blocks[2] equal blocks, block b refined
+    block_levels[b][d] times along d, element e of degree degrees[e][d].
+    Vectors are float64 device tensors of ndof entries, element by element."""
+
+    def __init__(self, lower, upper, blocks, block_levels, degrees, penalty=1.5,
+                 options: Options | None = None, stream=None, **opts):
+        lib = load_library()
+        self._lib = lib
+        self._h = None
+        self.options = options if options is not None else default_options(**opts)
+        lv = [int(v) for row in block_levels for v in row]
+        dg = [int(v) for row in degrees for v in row]
+        ne = len(dg) // 3
+        dom = Domain((ctypes.c_double * 3)(*lower), (ctypes.c_double * 3)(*upper))
+        h = ctypes.c_void_p()
+        _check(lib.dgs_create_hp_problem(ctypes.byref(dom), (ctypes.c_int * 3)(*blocks),
+                                         (ctypes.c_int * max(1, len(lv)))(*lv),
+                                         (ctypes.c_int * max(1, len(dg)))(*dg), ne, float(penalty),
+                                         ctypes.byref(self.options), _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self.ndof = lib.dgs_hp_num_dofs(h)
+        self.levels = lib.dgs_hp_num_levels(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.dgs_destroy_hp_problem(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, n=None):
+        import torch
+        return torch.empty(self.ndof if n is None else n, dtype=torch.float64, device="cuda")
+
+    def num_classes(self, level=0):
+        return self._lib.dgs_hp_num_classes(self._h, int(level))
+
+    def node_coordinates(self, stream=None):
+        xyz = self._new(3 * self.ndof)
+        _check(self._lib.dgs_hp_node_coordinates(self._h, _ptr(xyz, 3 * self.ndof, "xyz"),
+                                                 _stream(stream)))
+        return xyz.view(3, self.ndof)
+
+    def apply(self, u, out=None, stream=None):
+        out = self._new() if out is None else out
+        _check(self._lib.dgs_hp_apply_operator(self._h, _ptr(u, self.ndof, "u"), _ptr(out, self.ndof, "out"),
+                                               _stream(stream)))
+        return out
+
+    def apply_mass(self, f, out=None, stream=None):
+        out = self._new() if out is None else out
+        _check(self._lib.dgs_hp_apply_mass(self._h, _ptr(f, self.ndof, "f"), _ptr(out, self.ndof, "out"),
+                                           _stream(stream)))
+        return out
+
+    def smooth(self, b, u, steps=1, stream=None):
+        _check(self._lib.dgs_hp_smooth(self._h, _ptr(b, self.ndof, "b"), _ptr(u, self.ndof, "u"),
+                                       int(steps), _stream(stream)))
+        return u
+
+    def precondition(self, r, out=None, stream=None):
+        out = self._new() if out is None else out
+        _check(self._lib.dgs_hp_precondition(self._h, _ptr(r, self.ndof, "r"), _ptr(out, self.ndof, "z"),
+                                             _stream(stream)))
+        return out
+
+    def solve(self, b, u=None, history=256, stream=None):
+        import torch
+        if u is None:
+            u = torch.zeros(self.ndof, dtype=torch.float64, device="cuda")
+        st, hist = _make_stats(history)
+        code = _check(self._lib.dgs_hp_solve(self._h, _ptr(b, self.ndof, "b"), _ptr(u, self.ndof, "u"),
+                                             ctypes.byref(st), _stream(stream)), allow_not_converged=True)
+        return u, _stats_dict(st, hist, code)

@@ -1,0 +1,388 @@
+// Kernels of the hp-nonuniform path (Sec. II with mortars on nonconforming
+// faces, Sec. III.C.1-2 transfers, Sec. III.D Schwarz gather and scatter).
+//
+// Operator: one workgroup per element, one thread per node (loops for more
+// nodes than threads).  The element's values and its three unlifted
+// derivatives sit in LDS.  Every face is a list of terms: a box-boundary term
+// (the ghost state of eq. bc on the element's own face points) or a mortar
+// shared with one neighbour, on which both sides' traces and normal
+// derivatives are interpolated, the fluxes of eq. numflux evaluated, and the
+// auxiliary and primal corrections projected back to the element's face
+// points (exact L2 projection).  The lift (eq. liftop) and the strong-form
+// primal equation (eq. dg_op_primal) follow as on the uniform grid.
+#include "dgs_hp.h"
+
+namespace dgs {
+namespace {
+
+constexpr int kHpThreads = 256;
+constexpr int kF = kHpMaxN * kHpMaxN;  // points of a face or mortar
+
+__device__ __forceinline__ double mat(const double* pool, int off, int r, int c, int ncols) {
+  return off < 0 ? (r == c ? 1.0 : 0.0) : pool[off + r * ncols + c];
+}
+
+// out[r1][r0] = sum_{c1, c0} A1[r1][c1] A0[r0][c0] in[c1][c0] for two fields
+// (A0: r0 x c0, A1: r1 x c1, pool offsets, -1 = identity).  Called by every
+// thread of the workgroup; ends with a barrier.
+__device__ void tensor2(const double* pool, int A0, int r0, int c0, int A1, int r1, int c1,
+                        const double* inA, const double* inB, double* tA, double* tB,
+                        double* outA, double* outB) {
+  for (int q = threadIdx.x; q < c1 * r0; q += blockDim.x) {
+    const int j = q / r0, i = q - j * r0;
+    double a = 0.0, b = 0.0;
+    for (int m = 0; m < c0; ++m) {
+      const double w = mat(pool, A0, i, m, c0);
+      a += w * inA[j * c0 + m];
+      b += w * inB[j * c0 + m];
+    }
+    tA[q] = a;
+    tB[q] = b;
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < r1 * r0; q += blockDim.x) {
+    const int j = q / r0, i = q - j * r0;
+    double a = 0.0, b = 0.0;
+    for (int m = 0; m < c1; ++m) {
+      const double w = mat(pool, A1, j, m, c1);
+      a += w * tA[m * r0 + i];
+      b += w * tB[m * r0 + i];
+    }
+    outA[q] = a;
+    outB[q] = b;
+  }
+  __syncthreads();
+}
+
+// Node of an element with N points per dimension at position od along d and
+// (b0, b1) along the transverse dimensions t0 < t1.
+__device__ __forceinline__ int face_node(int d, int od, int b0, int b1, const int N[3]) {
+  int idx[3];
+  idx[d] = od;
+  idx[d == 0 ? 1 : 0] = b0;
+  idx[d == 2 ? 1 : 2] = b1;
+  return (idx[2] * N[1] + idx[1]) * N[0] + idx[0];
+}
+
+template <bool RES>
+__global__ void __launch_bounds__(kHpThreads)
+    k_hp_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ b,
+               const HpElem* __restrict__ el, const HpTerm* __restrict__ terms,
+               const double* __restrict__ pool, HpRule R, long long copy_stride) {
+  __shared__ double su[kHpMaxNodes];
+  __shared__ double sg[3][kHpMaxNodes];
+  __shared__ double scu[6][kF], scp[6][kF];
+  __shared__ double fa[kF], fb[kF], oa[kF], ob[kF], ma[kF], mb[kF], na[kF], nbv[kF], ta[kF], tb[kF];
+  const HpElem E = el[blockIdx.x];
+  const long long base = (long long)blockIdx.y * copy_stride + E.off;
+  const int N0 = E.N[0], N1 = E.N[1], N2 = E.N[2];
+  const int n = N0 * N1 * N2;
+  const int str[3] = {1, N0, N0 * N1};
+  const int tid = threadIdx.x;
+  for (int p = tid; p < n; p += blockDim.x) su[p] = u[base + p];
+  for (int q = tid; q < 6 * kF; q += blockDim.x) {
+    (&scu[0][0])[q] = 0.0;
+    (&scp[0][0])[q] = 0.0;
+  }
+  __syncthreads();
+  // unlifted derivatives D_d u = (2/h_d) D_xi u
+  for (int p = tid; p < n; p += blockDim.x) {
+    const int idx[3] = {p % N0, (p / N0) % N1, p / (N0 * N1)};
+    for (int d = 0; d < 3; ++d) {
+      const int Nd = E.N[d];
+      const double* D = R.D + (Nd - 2) * 64 + idx[d] * Nd;
+      const int l0 = p - idx[d] * str[d];
+      double acc = 0.0;
+      for (int m = 0; m < Nd; ++m) acc += D[m] * su[l0 + m * str[d]];
+      sg[d][p] = E.rh[d] * acc;
+    }
+  }
+  __syncthreads();
+  int t = E.term0;
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1;
+    const double sgn = (f & 1) ? 1.0 : -1.0;
+    const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+    const int n0 = E.N[t0], n1 = E.N[t1];
+    const int od = (f & 1) ? E.N[d] - 1 : 0;
+    for (int k = 0; k < E.nterm[f]; ++k, ++t) {
+      const HpTerm T = terms[t];
+      if (T.nb == kHpDirichlet || T.nb == kHpNeumann) {
+        // ghost state on the element's own face points (eq. bc)
+        const bool dir = T.nb == kHpDirichlet;
+        for (int q = tid; q < n0 * n1; q += blockDim.x) {
+          const int p = face_node(d, od, q % n0, q / n0, E.N);
+          const double ui = su[p], dui = sg[d][p];
+          const double ue = dir ? -ui : ui, due = dir ? dui : -dui;
+          scu[f][q] += 0.5 * (ue - ui);
+          scp[f][q] += 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
+        }
+        continue;
+      }
+      for (int q = tid; q < n0 * n1; q += blockDim.x) {
+        const int p = face_node(d, od, q % n0, q / n0, E.N);
+        fa[q] = su[p];
+        fb[q] = sg[d][p];
+      }
+      int m0 = 0, m1 = 0;
+      if (T.nb >= 0) {
+        // the neighbour's trace and normal derivative on its own face points
+        const HpElem F = el[T.nb];
+        m0 = F.N[t0];
+        m1 = F.N[t1];
+        const int Nd = F.N[d];
+        const int fod = (f & 1) ? 0 : Nd - 1;
+        const double* D = R.D + (Nd - 2) * 64 + fod * Nd;
+        const int strd = d == 0 ? 1 : (d == 1 ? F.N[0] : F.N[0] * F.N[1]);
+        const double* fu = u + (long long)blockIdx.y * copy_stride + F.off;
+        for (int q = tid; q < m0 * m1; q += blockDim.x) {
+          const double* line = fu + face_node(d, 0, q % m0, q / m0, F.N);
+          double acc = 0.0;
+          for (int m = 0; m < Nd; ++m) acc += D[m] * line[m * strd];
+          oa[q] = line[fod * strd];
+          ob[q] = F.rh[d] * acc;
+        }
+      }
+      __syncthreads();
+      tensor2(pool, T.Ie0, T.M0, n0, T.Ie1, T.M1, n1, fa, fb, ta, tb, ma, mb);
+      if (T.nb >= 0) tensor2(pool, T.If0, T.M0, m0, T.If1, T.M1, m1, oa, ob, ta, tb, na, nbv);
+      // fluxes of eq. numflux on the mortar (a zero neighbour contributes 0)
+      for (int q = tid; q < T.M0 * T.M1; q += blockDim.x) {
+        const double ui = ma[q], dui = mb[q];
+        const double ue = T.nb >= 0 ? na[q] : 0.0, due = T.nb >= 0 ? nbv[q] : 0.0;
+        fa[q] = 0.5 * (ue - ui);
+        fb[q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
+      }
+      __syncthreads();
+      tensor2(pool, T.Pe0, n0, T.M0, T.Pe1, n1, T.M1, fa, fb, ta, tb, oa, ob);
+      for (int q = tid; q < n0 * n1; q += blockDim.x) {
+        scu[f][q] += oa[q];
+        scp[f][q] += ob[q];
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // auxiliary variable (eq. dg_op_auxvars): v_d = D_d u + M^-1 ML n_d cu on
+  // the faces normal to d, M^-1 ML = (2/h_d) / w_end
+  for (int p = tid; p < n; p += blockDim.x) {
+    const int idx[3] = {p % N0, (p / N0) % N1, p / (N0 * N1)};
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1;
+      if (idx[d] != ((f & 1) ? E.N[d] - 1 : 0)) continue;
+      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      const int q = idx[t1] * E.N[t0] + idx[t0];
+      const double lift = E.rh[d] / R.w[(E.N[d] - 2) * 8];
+      sg[d][p] += lift * ((f & 1) ? 1.0 : -1.0) * scu[f][q];
+    }
+  }
+  __syncthreads();
+  // primal equation (eq. dg_op_primal): -M D_d v_d - ML ((n F_u)* - n_d v_d)
+  for (int p = tid; p < n; p += blockDim.x) {
+    const int idx[3] = {p % N0, (p / N0) % N1, p / (N0 * N1)};
+    double acc = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const int Nd = E.N[d];
+      const double* D = R.D + (Nd - 2) * 64 + idx[d] * Nd;
+      const int l0 = p - idx[d] * str[d];
+      double a = 0.0;
+      for (int m = 0; m < Nd; ++m) a += D[m] * sg[d][l0 + m * str[d]];
+      acc += E.rh[d] * a;
+    }
+    const double wx = R.w[(N0 - 2) * 8 + idx[0]], wy = R.w[(N1 - 2) * 8 + idx[1]],
+                 wz = R.w[(N2 - 2) * 8 + idx[2]];
+    const double wd[3] = {wx, wy, wz};
+    double Au = -E.jac * wx * wy * wz * acc;
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1;
+      if (idx[d] != ((f & 1) ? E.N[d] - 1 : 0)) continue;
+      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      const int q = idx[t1] * E.N[t0] + idx[t0];
+      const double ML = E.jac * E.rh[d] * wd[t0] * wd[t1];
+      Au -= ML * (scp[f][q] - ((f & 1) ? 1.0 : -1.0) * sg[d][p]);
+    }
+    out[base + p] = RES ? b[base + p] - Au : Au;
+  }
+}
+
+__global__ void k_hp_mass(const double* __restrict__ f, double* __restrict__ out,
+                          const HpElem* __restrict__ el, HpRule R) {
+  const HpElem E = el[blockIdx.x];
+  const int N0 = E.N[0], N1 = E.N[1], N2 = E.N[2];
+  for (int p = threadIdx.x; p < N0 * N1 * N2; p += blockDim.x) {
+    const int i = p % N0, j = (p / N0) % N1, k = p / (N0 * N1);
+    const double M = E.jac * R.w[(N0 - 2) * 8 + i] * R.w[(N1 - 2) * 8 + j] * R.w[(N2 - 2) * 8 + k];
+    out[E.off + p] = M * f[E.off + p];
+  }
+}
+
+__global__ void k_hp_coords(double* __restrict__ xyz, long long ndof, const HpElem* __restrict__ el,
+                            const double* __restrict__ plo_h, HpRule R) {
+  const HpElem E = el[blockIdx.x];
+  const double* g = plo_h + 6 * (long long)blockIdx.x;
+  const int N0 = E.N[0], N1 = E.N[1], N2 = E.N[2];
+  for (int p = threadIdx.x; p < N0 * N1 * N2; p += blockDim.x) {
+    const int idx[3] = {p % N0, (p / N0) % N1, p / (N0 * N1)};
+    for (int d = 0; d < 3; ++d)
+      xyz[d * ndof + E.off + p] = g[d] + g[3 + d] * 0.5 * (R.xi[(E.N[d] - 2) * 8 + idx[d]] + 1.0);
+  }
+}
+
+__global__ void k_hp_gather(const double* __restrict__ r, double* __restrict__ rs,
+                            const HpSub* __restrict__ subs, const long long* __restrict__ gidx) {
+  const HpSub S = subs[blockIdx.x];
+  for (int q = threadIdx.x; q < S.n; q += blockDim.x) rs[S.rs + q] = r[gidx[S.start + q]];
+}
+
+__global__ void k_hp_scatter(double* __restrict__ u, const double* __restrict__ du, int parts,
+                             long long stride, const long long* __restrict__ ptr,
+                             const HpPull* __restrict__ pull, long long ndof) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= ndof) return;
+  double acc = 0.0;
+  for (long long q = ptr[p]; q < ptr[p + 1]; ++q) {
+    const HpPull e = pull[q];
+    double v = 0.0;
+    for (int k = 0; k < parts; ++k) v += du[k * stride + e.pos];
+    acc += e.w * v;
+  }
+  u[p] += acc;
+}
+
+// One 1D pass of a tensor-product transfer in LDS: out = (A along dimension
+// d) in, with A row-major R x C and `in` of extents n[3] (n[d] = C before,
+// R after).  trans: use A^T (C x R view) instead.
+__device__ void pass1d(const double* A, int Rr, int Cc, bool trans, int d, const int nin[3],
+                       const double* in, double* outv) {
+  int nout[3] = {nin[0], nin[1], nin[2]};
+  nout[d] = trans ? Cc : Rr;
+  const int total = nout[0] * nout[1] * nout[2];
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    int idx[3] = {q % nout[0], (q / nout[0]) % nout[1], q / (nout[0] * nout[1])};
+    const int o = idx[d];
+    double acc = 0.0;
+    const int K = nin[d];
+    for (int m = 0; m < K; ++m) {
+      idx[d] = m;
+      const double a = trans ? A[m * Cc + o] : A[o * Cc + m];
+      acc += a * in[(idx[2] * nin[1] + idx[1]) * nin[0] + idx[0]];
+    }
+    outv[q] = acc;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kHpThreads)
+    k_hp_prolongate_add(const double* __restrict__ coarse, double* __restrict__ fine,
+                        const HpElem* __restrict__ fel, const HpElem* __restrict__ cel,
+                        const HpChild* __restrict__ ch, const double* __restrict__ pool) {
+  __shared__ double s0[kHpMaxNodes], s1[kHpMaxNodes];
+  const HpChild C = ch[blockIdx.x];
+  const HpElem F = fel[blockIdx.x], P = cel[C.parent];
+  const int nc = P.N[0] * P.N[1] * P.N[2];
+  for (int p = threadIdx.x; p < nc; p += blockDim.x) s0[p] = coarse[P.off + p];
+  __syncthreads();
+  int n[3] = {P.N[0], P.N[1], P.N[2]};
+  pass1d(pool + C.P[0], F.N[0], P.N[0], false, 0, n, s0, s1);
+  n[0] = F.N[0];
+  pass1d(pool + C.P[1], F.N[1], P.N[1], false, 1, n, s1, s0);
+  n[1] = F.N[1];
+  pass1d(pool + C.P[2], F.N[2], P.N[2], false, 2, n, s0, s1);
+  for (int p = threadIdx.x; p < F.N[0] * F.N[1] * F.N[2]; p += blockDim.x) fine[F.off + p] += s1[p];
+}
+
+__global__ void __launch_bounds__(kHpThreads)
+    k_hp_restrict(const double* __restrict__ fine, double* __restrict__ coarse,
+                  const HpElem* __restrict__ fel, const HpElem* __restrict__ cel,
+                  const HpChild* __restrict__ ch, const int* __restrict__ kid_ptr,
+                  const int* __restrict__ kids, const double* __restrict__ pool) {
+  __shared__ double s0[kHpMaxNodes], s1[kHpMaxNodes], acc[kHpMaxNodes];
+  const HpElem P = cel[blockIdx.x];
+  const int nc = P.N[0] * P.N[1] * P.N[2];
+  for (int p = threadIdx.x; p < nc; p += blockDim.x) acc[p] = 0.0;
+  for (int k = kid_ptr[blockIdx.x]; k < kid_ptr[blockIdx.x + 1]; ++k) {
+    const int e = kids[k];
+    const HpElem F = fel[e];
+    const HpChild C = ch[e];
+    __syncthreads();
+    for (int p = threadIdx.x; p < F.N[0] * F.N[1] * F.N[2]; p += blockDim.x) s0[p] = fine[F.off + p];
+    __syncthreads();
+    int n[3] = {F.N[0], F.N[1], F.N[2]};
+    pass1d(pool + C.P[0], F.N[0], P.N[0], true, 0, n, s0, s1);
+    n[0] = P.N[0];
+    pass1d(pool + C.P[1], F.N[1], P.N[1], true, 1, n, s1, s0);
+    n[1] = P.N[1];
+    pass1d(pool + C.P[2], F.N[2], P.N[2], true, 2, n, s0, s1);
+    for (int p = threadIdx.x; p < nc; p += blockDim.x) acc[p] += s1[p];
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < nc; p += blockDim.x) coarse[P.off + p] = acc[p];
+}
+
+unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t launch_hp_apply(bool residual, const double* u, double* out, const double* b,
+                           const HpElem* el, int E, const HpTerm* terms, const double* pool,
+                           const HpRule& R, int copies, long long copy_stride, hipStream_t s) {
+  if (E <= 0 || copies <= 0) return hipSuccess;
+  const dim3 grid((unsigned)E, (unsigned)copies);
+  if (residual)
+    hipLaunchKernelGGL(k_hp_apply<true>, grid, dim3(kHpThreads), 0, s, u, out, b, el, terms, pool, R,
+                       copy_stride);
+  else
+    hipLaunchKernelGGL(k_hp_apply<false>, grid, dim3(kHpThreads), 0, s, u, out, b, el, terms, pool, R,
+                       copy_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_hp_mass(const double* f, double* out, const HpElem* el, int E, const HpRule& R,
+                          hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hp_mass, dim3((unsigned)E), dim3(kHpThreads), 0, s, f, out, el, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_hp_coords(double* xyz, long long ndof, const HpElem* el, const double* plo_h,
+                            int E, const HpRule& R, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hp_coords, dim3((unsigned)E), dim3(kHpThreads), 0, s, xyz, ndof, el, plo_h, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_hp_gather(const double* r, double* rs, const HpSub* subs, int nsub,
+                            const long long* gidx, hipStream_t s) {
+  if (nsub <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hp_gather, dim3((unsigned)nsub), dim3(256), 0, s, r, rs, subs, gidx);
+  return hipGetLastError();
+}
+
+hipError_t launch_hp_scatter(double* u, const double* du, int parts, long long part_stride,
+                             const long long* ptr, const HpPull* pull, long long ndof,
+                             hipStream_t s) {
+  if (ndof <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hp_scatter, dim3(nblk(ndof)), dim3(256), 0, s, u, du, parts, part_stride, ptr,
+                     pull, ndof);
+  return hipGetLastError();
+}
+
+hipError_t launch_hp_prolongate_add(const double* coarse, double* fine, const HpElem* fel,
+                                    const HpElem* cel, const HpChild* ch, int Ef,
+                                    const double* pool, hipStream_t s) {
+  if (Ef <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hp_prolongate_add, dim3((unsigned)Ef), dim3(kHpThreads), 0, s, coarse, fine,
+                     fel, cel, ch, pool);
+  return hipGetLastError();
+}
+
+hipError_t launch_hp_restrict(const double* fine, double* coarse, const HpElem* fel,
+                              const HpElem* cel, const HpChild* ch, const int* kid_ptr,
+                              const int* kids, int Ec, const double* pool, hipStream_t s) {
+  if (Ec <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_hp_restrict, dim3((unsigned)Ec), dim3(kHpThreads), 0, s, fine, coarse, fel,
+                     cel, ch, kid_ptr, kids, pool);
+  return hipGetLastError();
+}
+
+}  // namespace dgs

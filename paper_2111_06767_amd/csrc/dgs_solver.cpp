@@ -31,68 +31,12 @@
 
 #include "../../include/dgsolve.h"
 #include "dgs_internal.h"
+#include "dgs_host.h"
 
 using namespace dgs;
 
 namespace {
 
-thread_local std::string g_last_error;
-
-struct Status {
-  int code = DGS_OK;
-  std::string msg;
-};
-
-class DgsError {
- public:
-  DgsError(int c, std::string m) : code(c), msg(std::move(m)) {}
-  int code;
-  std::string msg;
-};
-
-#define HIP_OK(expr)                                                                        \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      throw DgsError(e_ == hipErrorOutOfMemory ? DGS_ERR_OOM : DGS_ERR_HIP,                \
-                     std::string(#expr) + ": " + hipGetErrorString(e_));                    \
-  } while (0)
-
-double now_s() {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
-// One process-wide lock around the library's device-management calls:
-// allocation and release of device and pinned memory, stream creation and
-// destruction, and graph capture and instantiation.  Kernel and graph
-// launches, copies and stream queries do not take it.  The serving loop's
-// worker threads set up requests (allocating, capturing) while others launch,
-// and a capture must not overlap another thread's allocation or release (a
-// release waits for the device), so these calls are serialised here.
-std::recursive_mutex g_dev_mutex;
-
-void dfree(void* p) {
-  std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
-  (void)hipFree(p);
-}
-
-template <typename T>
-T* dalloc(size_t count) {
-  if (count == 0) count = 1;
-  void* p = nullptr;
-  std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
-  hipError_t e = hipMalloc(&p, count * sizeof(T));
-  if (e != hipSuccess)
-    throw DgsError(e == hipErrorOutOfMemory ? DGS_ERR_OOM : DGS_ERR_HIP,
-                   std::string("hipMalloc: ") + hipGetErrorString(e));
-  return static_cast<T*>(p);
-}
-
-template <typename T>
-void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
-  if (src.empty()) return;
-  HIP_OK(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
-}
 
 const int kFace[6][2] = {{0, -1}, {0, 1}, {1, -1}, {1, 1}, {2, -1}, {2, 1}};
 
@@ -785,7 +729,6 @@ void build_inverses(dgs_problem* P, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));
 }
 
-hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Per-degree launch-shape autotuner of the operator kernel: time every
 // candidate elements-per-workgroup value on the finest mesh and keep the
@@ -1279,12 +1222,6 @@ void set_diagonal(dgs_problem* P, const double* d, hipStream_t s) {
   if (P->opt.use_graphs && !P->vgraph[1]) capture_vgraph(P, 1);
 }
 
-struct FgmresResult {
-  int iterations = 0;
-  double rel_residual = 0;
-  bool converged = false;
-  std::vector<double> history;
-};
 
 // Flexible GMRES (Saad Alg. 9.6) on the fine level as a resumable state
 // machine: issue() enqueues the device work of the current stage on the
@@ -1712,24 +1649,6 @@ struct NewtonRun {
   }
 };
 
-int fail(int code, const std::string& msg) {
-  g_last_error = msg;
-  return code;
-}
-
-template <typename F>
-int guarded(F&& f) {
-  try {
-    g_last_error.clear();
-    return f();
-  } catch (const DgsError& e) {
-    return fail(e.code, e.msg);
-  } catch (const std::bad_alloc&) {
-    return fail(DGS_ERR_OOM, "host allocation failed");
-  } catch (const std::exception& e) {
-    return fail(DGS_ERR_HIP, e.what());
-  }
-}
 
 void fill_stats(dgs_stats* st, const FgmresResult& R, double t0, double t_setup) {
   if (!st) return;
@@ -3854,100 +3773,27 @@ void sys_ensure_krylov(dgs_system* S, int m) {
   S->kry_m = m;
 }
 
-double sys_norm2(dgs_system* S, const double* x, long long n, hipStream_t s) {
-  HIP_OK(launch_multidot(x, n, 1, x, n, S->partial, S->h, s));
-  HIP_OK(hipMemcpyAsync(S->h_pinned, S->h, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  return S->h_pinned[0];
-}
-
-// Flexible GMRES (Saad Alg. 9.6) on the system with one V-cycle per
-// iteration: classical Gram-Schmidt twice, Givens rotations on the host,
-// restarts of the options' length, and convergence decided by the true
-// residual of the solution (a cycle whose estimate meets rtol while the true
-// residual does not is followed by another cycle).
+// FGMRES on the system with one V-cycle per iteration (restarts of the
+// options' length).
 FgmresResult sys_fgmres(dgs_system* S, const double* b, double* x, hipStream_t s) {
   const dgs_problem* P = S->base();
-  const double rtol = P->opt.rtol;
   const int max_total = P->opt.max_iter;
   const int m = P->opt.restart > 0 ? std::min(P->opt.restart, max_total) : max_total;
   sys_ensure_krylov(S, m);
-  const long long n = S->nv * S->lv[0].nd;
-  double* hp = S->h_pinned;
-  FgmresResult R;
-  double beta0 = 0.0;
-  for (int cycle = 0;; ++cycle) {
-    sys_residual(S, 0, x, b, S->V, s);
-    const double beta2 = sys_norm2(S, S->V, n, s);
-    if (!std::isfinite(beta2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite initial residual");
-    const double beta = std::sqrt(beta2);
-    if (cycle == 0) {
-      beta0 = beta;
-      R.history.push_back(1.0);
-    }
-    if (beta == 0.0) {
-      R.converged = true;
-      R.rel_residual = 0.0;
-      return R;
-    }
-    HIP_OK(launch_scale_by_inv_norm(S->V, S->V, S->h, n, s));
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), g(m + 1, 0.0);
-    g[0] = beta;
-    int j = 0;
-    while (true) {
-      double* vj = S->V + (size_t)j * n;
-      double* zj = S->Z + (size_t)j * n;
-      double* w = S->V + (size_t)(j + 1) * n;
-      sys_visit(S, 0, vj, zj, true, s);
-      sys_apply(S, zj, w, s);
-      double* h1 = S->h;
-      double* h2 = S->h + (m + 2);
-      double* hn = S->h + 2 * (m + 2);
-      HIP_OK(launch_multidot(S->V, n, j + 1, w, n, S->partial, h1, s));
-      HIP_OK(launch_axpy_multidot(S->V, n, j + 1, h1, w, n, false, S->partial, h2, s));
-      HIP_OK(launch_axpy_multidot(S->V, n, j + 1, h2, w, n, true, S->partial, hn, s));
-      HIP_OK(hipMemcpyAsync(hp, S->h, sizeof(double) * (2 * (m + 2) + 1), hipMemcpyDeviceToHost, s));
-      HIP_OK(launch_scale_by_inv_norm(w, w, hn, n, s));
-      HIP_OK(hipStreamSynchronize(s));
-      double* col = &H[(size_t)j * (m + 1)];
-      for (int i = 0; i <= j; ++i) col[i] = hp[i] + hp[(m + 2) + i];
-      const double hn2 = hp[2 * (m + 2)];
-      col[j + 1] = std::sqrt(hn2);
-      for (int i = 0; i <= j + 1; ++i)
-        if (!std::isfinite(col[i])) throw DgsError(DGS_ERR_NONFINITE, "non-finite Hessenberg entry");
-      for (int i = 0; i < j; ++i) {
-        const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-        col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-        col[i] = t;
-      }
-      const double den = std::hypot(col[j], col[j + 1]);
-      cs[j] = col[j] / den;
-      sn[j] = col[j + 1] / den;
-      col[j] = den;
-      col[j + 1] = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      R.history.push_back(std::fabs(g[j + 1]) / beta0);
-      ++j;
-      ++R.iterations;
-      if (std::fabs(g[j]) <= rtol * beta0 || hn2 == 0.0 || j >= m || R.iterations >= max_total) break;
-    }
-    std::vector<double> y(j, 0.0);
-    for (int i = j - 1; i >= 0; --i) {
-      double t = g[i];
-      for (int q = i + 1; q < j; ++q) t -= H[(size_t)q * (m + 1) + i] * y[q];
-      y[i] = t / H[(size_t)i * (m + 1) + i];
-    }
-    double* ypin = hp + 3 * (m + 2);
-    for (int i = 0; i < j; ++i) ypin[i] = y[i];
-    HIP_OK(hipMemcpyAsync(S->y, ypin, sizeof(double) * j, hipMemcpyHostToDevice, s));
-    HIP_OK(launch_combine(x, S->Z, n, j, S->y, n, s));
-    sys_residual(S, 0, x, b, S->tmp, s);
-    R.rel_residual = std::sqrt(sys_norm2(S, S->tmp, n, s)) / beta0;
-    if (!std::isfinite(R.rel_residual)) throw DgsError(DGS_ERR_NONFINITE, "non-finite residual");
-    R.converged = R.rel_residual <= rtol;
-    if (R.converged || R.iterations >= max_total) return R;
-  }
+  KrylovSpace K;
+  K.m = m;
+  K.n = S->nv * S->lv[0].nd;
+  K.V = S->V;
+  K.Z = S->Z;
+  K.partial = S->partial;
+  K.h = S->h;
+  K.y = S->y;
+  K.tmp = S->tmp;
+  K.pinned = S->h_pinned;
+  return fgmres_run(
+      K, P->opt.rtol, max_total, [&](const double* xx, const double* bb, double* out) { sys_residual(S, 0, xx, bb, out, s); },
+      [&](const double* z, double* w) { sys_apply(S, z, w, s); },
+      [&](const double* v, double* z) { sys_visit(S, 0, v, z, true, s); }, b, x, s);
 }
 
 }  // namespace
