@@ -503,6 +503,64 @@ def time_curved_apply(dg, elements, p, amplitude=0.1, reps=50, warm=5):
                 algorithmic_bytes_per_dof=96, achieved_gbs=96 * n / (ms * 1e-3) / 1e9)
 
 
+def hp_workload():
+    """hp-nonuniform mesh of the unit cube: 2 x 2 x 2 blocks in a checkerboard
+    of refinement levels 3 (8^3 elements of degree 5) and 2 (4^3 elements of
+    degree 7), so that every block face is nonconforming in both h and p:
+    2304 elements, 573440 DOFs."""
+    levels, degrees = [], []
+    for b in range(8):
+        fine = (b % 2 + (b // 2) % 2 + b // 4) % 2 == 0
+        L = 3 if fine else 2
+        levels.append((L, L, L))
+        degrees += [(5, 5, 5) if fine else (7, 7, 7)] * (8 ** L)
+    return levels, degrees
+
+
+def hp_leg(dg, steps=5, warmup=1, reps=50):
+    """FGMRES with the hp V-cycle on the hp workload (FP64), and the hp
+    operator apply timed with HIP events on the launch stream."""
+    import torch
+    import workloads as W
+    levels, degrees = hp_workload()
+    t0 = time.perf_counter()
+    prob = dg.HpProblem((0, 0, 0), (1, 1, 1), (2, 2, 2), levels, degrees, penalty=1.5, mg_levels=4)
+    setup_s = time.perf_counter() - t0
+    xyz = prob.node_coordinates()
+    x, y, z = (xyz[d].cpu().numpy() for d in range(3))
+    b = prob.apply_mass(torch.as_tensor(W.fourier_source(W.fourier_modes(W.SEED_C5), x, y, z)).cuda())
+    u = torch.zeros_like(b)
+    for _ in range(warmup):
+        u.zero_()
+        prob.solve(b, u)
+    times, st = [], None
+    for _ in range(steps):
+        u.zero_()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, st = prob.solve(b, u)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+    out = torch.empty_like(b)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        prob.apply(b, out)
+    e1.record(s)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n = prob.ndof
+    res = dict(elements=len(degrees), ndof=n, levels=prob.levels,
+               subdomain_inverses_per_level=[prob.num_classes(l) for l in range(prob.levels)],
+               setup_s=round(setup_s, 3), ms=_ms(times), iterations=st["iterations"],
+               rel_residual=st["rel_residual"], converged=st["converged"],
+               apply=dict(ms_per_apply=round(ms, 5), gdofs=round(n / (ms * 1e-3) / 1e9, 2),
+                          achieved_gbs=round(16 * n / (ms * 1e-3) / 1e9, 1)))
+    prob.close()
+    return res
+
+
 def newton_leg(dg, precision, steps=10, warmup=2):
     """The 6^3, p = 7 puncture problem on [-20, 20]^3 by Newton-Krylov with the
     multigrid-Schwarz preconditioner (subdomain GMRES(3))."""
@@ -774,6 +832,12 @@ def main():
         _log("curved apply 40^3 p=7")
         curved["apply_40^3_p7"] = time_curved_apply(dg, (40, 40, 40), 7)
 
+    # -- hp-nonuniform mesh ---------------------------------------------------
+    hp_out = None
+    if not args.no_variants:
+        _log("hp-nonuniform mesh, 573440 DOFs")
+        hp_out = hp_leg(dg)
+
     # -- applies --------------------------------------------------------------
     _log("operator applies")
     apply_c2 = time_apply(dg, (8, 8, 8), 6)
@@ -893,6 +957,7 @@ def main():
         "c3_puncture_6x6x6_p7": c3,
         "system_5var_8x8x8_p6": systems,
         "curved_16x16x16_p7": curved,
+        "hp_checkerboard_2304_elements": hp_out,
         "apply": {"c2_shape": apply_c2, "16^3_p7": apply_c5, "40^3_p7": apply_big,
                   "sweep_2M_dofs": sweep},
         "serving": serving,

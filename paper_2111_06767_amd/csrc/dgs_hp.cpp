@@ -282,6 +282,7 @@ void build_terms(const HMesh& m, double C, MatPool& pool, std::vector<HpElem>& h
         T.M1 = E.N[t1];
         T.Ie0 = T.Ie1 = T.If0 = T.If1 = T.Pe0 = T.Pe1 = -1;
         T.sigma = C * E.N[d] * E.N[d] / E.h[d];
+        T.direct = 1;
         terms.push_back(T);
         H.nterm[f] = 1;
         continue;
@@ -330,6 +331,7 @@ void build_terms(const HMesh& m, double C, MatPool& pool, std::vector<HpElem>& h
           side(E, Ie[k], Pe[k]);
           side(F, If[k], nullptr);
         }
+        T.direct = (T.Ie0 < 0 && T.Ie1 < 0 && T.If0 < 0 && T.If1 < 0 && T.Pe0 < 0 && T.Pe1 < 0) ? 1 : 0;
         terms.push_back(T);
       }
     }
@@ -503,7 +505,7 @@ std::string signature(const Patch& P, const SubLayout& S) {
       for (int k = 0; k < H.nterm[f]; ++k, ++t) {
         if (far) continue;
         const HpTerm& T = P.terms[t];
-        for (int x : {T.nb, T.M0, T.M1, T.Ie0, T.Ie1, T.If0, T.If1, T.Pe0, T.Pe1}) v.push_back(x);
+        for (int x : {T.nb, T.direct, T.M0, T.M1, T.Ie0, T.Ie1, T.If0, T.If1, T.Pe0, T.Pe1}) v.push_back(x);
         v.push_back(T.sigma);
       }
     }

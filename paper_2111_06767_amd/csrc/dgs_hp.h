@@ -22,6 +22,8 @@ constexpr int kHpZero = -3;       // a neighbour whose values are zero (set-up p
 // Matrices live in a pool of doubles (row-major); offset -1 is the identity.
 struct HpTerm {
   int nb;        // neighbour element (>= 0) or one of the codes above
+  int direct;    // 1: a box face, or a conforming face of equal points (every
+                 //    matrix the identity): the flux is formed point by point
   int M0, M1;    // mortar points along t0, t1
   int Ie0, Ie1;  // own face points -> mortar points (M x N_own)
   int If0, If1;  // neighbour face points -> mortar points (M x N_nb)

@@ -18,23 +18,26 @@ namespace {
 constexpr int kHpThreads = 256;
 constexpr int kF = kHpMaxN * kHpMaxN;  // points of a face or mortar
 
-__device__ __forceinline__ double mat(const double* pool, int off, int r, int c, int ncols) {
-  return off < 0 ? (r == c ? 1.0 : 0.0) : pool[off + r * ncols + c];
-}
-
 // out[r1][r0] = sum_{c1, c0} A1[r1][c1] A0[r0][c0] in[c1][c0] for two fields
-// (A0: r0 x c0, A1: r1 x c1, pool offsets, -1 = identity).  Called by every
-// thread of the workgroup; ends with a barrier.
-__device__ void tensor2(const double* pool, int A0, int r0, int c0, int A1, int r1, int c1,
+// (A0: r0 x c0, A1: r1 x c1, row-major in LDS; nullptr = identity).  Called
+// by every thread of the workgroup; ends with a barrier.
+__device__ void tensor2(const double* A0, int r0, int c0, const double* A1, int r1, int c1,
                         const double* inA, const double* inB, double* tA, double* tB,
                         double* outA, double* outB) {
   for (int q = threadIdx.x; q < c1 * r0; q += blockDim.x) {
     const int j = q / r0, i = q - j * r0;
-    double a = 0.0, b = 0.0;
-    for (int m = 0; m < c0; ++m) {
-      const double w = mat(pool, A0, i, m, c0);
-      a += w * inA[j * c0 + m];
-      b += w * inB[j * c0 + m];
+    double a, b;
+    if (A0) {
+      a = 0.0;
+      b = 0.0;
+      for (int m = 0; m < c0; ++m) {
+        const double w = A0[i * c0 + m];
+        a += w * inA[j * c0 + m];
+        b += w * inB[j * c0 + m];
+      }
+    } else {
+      a = inA[j * c0 + i];
+      b = inB[j * c0 + i];
     }
     tA[q] = a;
     tB[q] = b;
@@ -42,11 +45,18 @@ __device__ void tensor2(const double* pool, int A0, int r0, int c0, int A1, int 
   __syncthreads();
   for (int q = threadIdx.x; q < r1 * r0; q += blockDim.x) {
     const int j = q / r0, i = q - j * r0;
-    double a = 0.0, b = 0.0;
-    for (int m = 0; m < c1; ++m) {
-      const double w = mat(pool, A1, j, m, c1);
-      a += w * tA[m * r0 + i];
-      b += w * tB[m * r0 + i];
+    double a, b;
+    if (A1) {
+      a = 0.0;
+      b = 0.0;
+      for (int m = 0; m < c1; ++m) {
+        const double w = A1[j * c1 + m];
+        a += w * tA[m * r0 + i];
+        b += w * tB[m * r0 + i];
+      }
+    } else {
+      a = tA[j * r0 + i];
+      b = tB[j * r0 + i];
     }
     outA[q] = a;
     outB[q] = b;
@@ -73,6 +83,7 @@ __global__ void __launch_bounds__(kHpThreads)
   __shared__ double sg[3][kHpMaxNodes];
   __shared__ double scu[6][kF], scp[6][kF];
   __shared__ double fa[kF], fb[kF], oa[kF], ob[kF], ma[kF], mb[kF], na[kF], nbv[kF], ta[kF], tb[kF];
+  __shared__ double smat[6][kF];
   const HpElem E = el[blockIdx.x];
   const long long base = (long long)blockIdx.y * copy_stride + E.off;
   const int N0 = E.N[0], N1 = E.N[1], N2 = E.N[2];
@@ -80,10 +91,6 @@ __global__ void __launch_bounds__(kHpThreads)
   const int str[3] = {1, N0, N0 * N1};
   const int tid = threadIdx.x;
   for (int p = tid; p < n; p += blockDim.x) su[p] = u[base + p];
-  for (int q = tid; q < 6 * kF; q += blockDim.x) {
-    (&scu[0][0])[q] = 0.0;
-    (&scp[0][0])[q] = 0.0;
-  }
   __syncthreads();
   // unlifted derivatives D_d u = (2/h_d) D_xi u
   for (int p = tid; p < n; p += blockDim.x) {
@@ -98,38 +105,91 @@ __global__ void __launch_bounds__(kHpThreads)
     }
   }
   __syncthreads();
-  int t = E.term0;
+  int tf[6];
+  {
+    int t = E.term0;
+    for (int f = 0; f < 6; ++f) {
+      tf[f] = t;
+      t += E.nterm[f];
+    }
+  }
+  // pass 1, without barriers: box faces and conforming faces of equal points
+  // (a single term each), point by point from the ghost state (eq. bc) or the
+  // neighbour's trace and normal derivative at the matching point
   for (int f = 0; f < 6; ++f) {
+    const HpTerm T = terms[tf[f]];
+    if (!T.direct) continue;
+    const int d = f >> 1;
+    const double sgn = (f & 1) ? 1.0 : -1.0;
+    const int n0 = E.N[d == 0 ? 1 : 0], n1 = E.N[d == 2 ? 1 : 2];
+    const int od = (f & 1) ? E.N[d] - 1 : 0;
+    if (T.nb < 0) {
+      // ghost state of a box face; a zero neighbour (set-up patches) has
+      // neither value nor derivative
+      const bool dir = T.nb == kHpDirichlet, zero = T.nb == kHpZero;
+      for (int q = tid; q < n0 * n1; q += blockDim.x) {
+        const int p = face_node(d, od, q % n0, q / n0, E.N);
+        const double ui = su[p], dui = sg[d][p];
+        const double ue = zero ? 0.0 : (dir ? -ui : ui), due = zero ? 0.0 : (dir ? dui : -dui);
+        scu[f][q] = 0.5 * (ue - ui);
+        scp[f][q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
+      }
+    } else {
+      const HpElem F = el[T.nb];
+      const int Nd = F.N[d];
+      const int fod = (f & 1) ? 0 : Nd - 1;
+      const double* D = R.D + (Nd - 2) * 64 + fod * Nd;
+      const int strd = d == 0 ? 1 : (d == 1 ? F.N[0] : F.N[0] * F.N[1]);
+      const double* fu = u + (long long)blockIdx.y * copy_stride + F.off;
+      for (int q = tid; q < n0 * n1; q += blockDim.x) {
+        const int b0 = q % n0, b1 = q / n0;
+        const double* line = fu + face_node(d, 0, b0, b1, F.N);
+        double acc = 0.0;
+        for (int m = 0; m < Nd; ++m) acc += D[m] * line[m * strd];
+        const double ue = line[fod * strd], due = F.rh[d] * acc;
+        const int p = face_node(d, od, b0, b1, E.N);
+        const double ui = su[p], dui = sg[d][p];
+        scu[f][q] = 0.5 * (ue - ui);
+        scp[f][q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
+      }
+    }
+  }
+  // pass 2: mortars of nonconforming faces; every face data interpolated to
+  // the mortar, the fluxes of eq. numflux there, the corrections projected
+  // back (matrices staged in LDS per term)
+  for (int f = 0; f < 6; ++f) {
+    if (terms[tf[f]].direct) continue;
     const int d = f >> 1;
     const double sgn = (f & 1) ? 1.0 : -1.0;
     const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
     const int n0 = E.N[t0], n1 = E.N[t1];
     const int od = (f & 1) ? E.N[d] - 1 : 0;
-    for (int k = 0; k < E.nterm[f]; ++k, ++t) {
-      const HpTerm T = terms[t];
-      if (T.nb == kHpDirichlet || T.nb == kHpNeumann) {
-        // ghost state on the element's own face points (eq. bc)
-        const bool dir = T.nb == kHpDirichlet;
-        for (int q = tid; q < n0 * n1; q += blockDim.x) {
-          const int p = face_node(d, od, q % n0, q / n0, E.N);
-          const double ui = su[p], dui = sg[d][p];
-          const double ue = dir ? -ui : ui, due = dir ? dui : -dui;
-          scu[f][q] += 0.5 * (ue - ui);
-          scp[f][q] += 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
-        }
-        continue;
+    for (int k = 0; k < E.nterm[f]; ++k) {
+      const HpTerm T = terms[tf[f] + k];
+      int m0 = 0, m1 = 0;
+      HpElem F{};
+      if (T.nb >= 0) {
+        F = el[T.nb];
+        m0 = F.N[t0];
+        m1 = F.N[t1];
+      }
+      const int offs[6] = {T.Ie0, T.Ie1, T.If0, T.If1, T.Pe0, T.Pe1};
+      const int sizes[6] = {T.M0 * n0, T.M1 * n1, T.M0 * m0, T.M1 * m1, n0 * T.M0, n1 * T.M1};
+      for (int q = tid; q < 6 * kF; q += blockDim.x) {
+        const int mi = q / kF, e = q - mi * kF;
+        if (offs[mi] >= 0 && e < sizes[mi]) smat[mi][e] = pool[offs[mi] + e];
       }
       for (int q = tid; q < n0 * n1; q += blockDim.x) {
         const int p = face_node(d, od, q % n0, q / n0, E.N);
+        if (k == 0) {
+          scu[f][q] = 0.0;
+          scp[f][q] = 0.0;
+        }
         fa[q] = su[p];
         fb[q] = sg[d][p];
       }
-      int m0 = 0, m1 = 0;
       if (T.nb >= 0) {
         // the neighbour's trace and normal derivative on its own face points
-        const HpElem F = el[T.nb];
-        m0 = F.N[t0];
-        m1 = F.N[t1];
         const int Nd = F.N[d];
         const int fod = (f & 1) ? 0 : Nd - 1;
         const double* D = R.D + (Nd - 2) * 64 + fod * Nd;
@@ -144,9 +204,11 @@ __global__ void __launch_bounds__(kHpThreads)
         }
       }
       __syncthreads();
-      tensor2(pool, T.Ie0, T.M0, n0, T.Ie1, T.M1, n1, fa, fb, ta, tb, ma, mb);
-      if (T.nb >= 0) tensor2(pool, T.If0, T.M0, m0, T.If1, T.M1, m1, oa, ob, ta, tb, na, nbv);
-      // fluxes of eq. numflux on the mortar (a zero neighbour contributes 0)
+      const double* A[6];
+      for (int mi = 0; mi < 6; ++mi) A[mi] = offs[mi] >= 0 ? smat[mi] : nullptr;
+      tensor2(A[0], T.M0, n0, A[1], T.M1, n1, fa, fb, ta, tb, ma, mb);
+      if (T.nb >= 0) tensor2(A[2], T.M0, m0, A[3], T.M1, m1, oa, ob, ta, tb, na, nbv);
+      // a zero neighbour (set-up patches) contributes 0
       for (int q = tid; q < T.M0 * T.M1; q += blockDim.x) {
         const double ui = ma[q], dui = mb[q];
         const double ue = T.nb >= 0 ? na[q] : 0.0, due = T.nb >= 0 ? nbv[q] : 0.0;
@@ -154,7 +216,7 @@ __global__ void __launch_bounds__(kHpThreads)
         fb[q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
       }
       __syncthreads();
-      tensor2(pool, T.Pe0, n0, T.M0, T.Pe1, n1, T.M1, fa, fb, ta, tb, oa, ob);
+      tensor2(A[4], n0, T.M0, A[5], n1, T.M1, fa, fb, ta, tb, oa, ob);
       for (int q = tid; q < n0 * n1; q += blockDim.x) {
         scu[f][q] += oa[q];
         scp[f][q] += ob[q];
