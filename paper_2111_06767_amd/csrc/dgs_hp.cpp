@@ -278,9 +278,7 @@ void build_terms(const HMesh& m, double C, MatPool& pool, std::vector<HpElem>& h
       if (nb.empty()) {
         HpTerm T{};
         T.nb = ((m.neumann >> f) & 1) ? kHpNeumann : kHpDirichlet;
-        T.M0 = E.N[t0];
-        T.M1 = E.N[t1];
-        T.Ie0 = T.Ie1 = T.If0 = T.If1 = T.Pe0 = T.Pe1 = -1;
+        T.A0 = T.A1 = T.B0 = T.B1 = -1;
         T.sigma = C * E.N[d] * E.N[d] / E.h[d];
         T.direct = 1;
         terms.push_back(T);
@@ -293,45 +291,58 @@ void build_terms(const HMesh& m, double C, MatPool& pool, std::vector<HpElem>& h
         HpTerm T{};
         T.nb = g;
         T.sigma = C * std::pow((double)std::max(E.N[d], F.N[d]), 2) / std::min(E.h[d], F.h[d]);
-        int* Ms[2] = {&T.M0, &T.M1};
-        int* Ie[2] = {&T.Ie0, &T.Ie1};
-        int* If[2] = {&T.If0, &T.If1};
-        int* Pe[2] = {&T.Pe0, &T.Pe1};
+        int* As[2] = {&T.A0, &T.A1};
+        int* Bs[2] = {&T.B0, &T.B1};
         const int ts[2] = {t0, t1};
+        bool identity = true;
         for (int k = 0; k < 2; ++k) {
           const int t = ts[k];
           const long long a = std::max(E.lo[t], F.lo[t]), b = std::min(E.hi[t], F.hi[t]);
           const int M = std::max(E.N[t], F.N[t]);
-          *Ms[k] = M;
           const std::vector<double>& eta = lgl(M);
-          auto side = [&](const HElem& G, int* I, int* P) {
+          // interpolation of side G's face points to the mortar points (M x N_G),
+          // empty for the identity
+          auto interp = [&](const HElem& G, double& al, double& be) {
             const double w = (double)(G.hi[t] - G.lo[t]);
-            const double al = -1.0 + 2.0 * (a - G.lo[t]) / w, be = -1.0 + 2.0 * (b - G.lo[t]) / w;
-            if (M == G.N[t] && al == -1.0 && be == 1.0) {
-              *I = -1;
-              if (P) *P = -1;
-              return;
-            }
+            al = -1.0 + 2.0 * (a - G.lo[t]) / w;
+            be = -1.0 + 2.0 * (b - G.lo[t]) / w;
+            if (M == G.N[t] && al == -1.0 && be == 1.0) return std::vector<double>();
             std::vector<double> x(M);
             for (int q = 0; q < M; ++q) x[q] = al + (be - al) * (eta[q] + 1.0) / 2.0;
-            const std::vector<double> Imat = lagrange(lgl(G.N[t]), x);  // M x N_G
-            *I = pool.add(Imat);
-            if (P) {
-              // P = Mex(N_G)^-1 I^T Mex(M) (be - al) / 2, N_G x M
-              const int NG = G.N[t];
-              const std::vector<double> Mm = exact_mass(M);
-              std::vector<double> rhs(NG * M, 0.0);
-              for (int i = 0; i < NG; ++i)
-                for (int j = 0; j < M; ++j)
-                  for (int q = 0; q < M; ++q) rhs[i * M + j] += Imat[q * NG + i] * Mm[q * M + j];
-              for (double& v : rhs) v *= (be - al) / 2.0;
-              *P = pool.add(solve_dense(exact_mass(NG), rhs, NG, M));
-            }
+            return lagrange(lgl(G.N[t]), x);
           };
-          side(E, Ie[k], Pe[k]);
-          side(F, If[k], nullptr);
+          double ale, bee, alf, bef;
+          const std::vector<double> Ie = interp(E, ale, bee), If = interp(F, alf, bef);
+          const int NE = E.N[t], NF = F.N[t];
+          if (Ie.empty() && If.empty()) {
+            *As[k] = *Bs[k] = -1;
+            continue;
+          }
+          identity = false;
+          // P = Mex(N_E)^-1 Ie^T Mex(M) (be - al) / 2, N_E x M (Ie empty: M = N_E, Ie = I)
+          const std::vector<double> Mm = exact_mass(M);
+          std::vector<double> rhs(NE * M, 0.0);
+          for (int i = 0; i < NE; ++i)
+            for (int j = 0; j < M; ++j) {
+              double v = 0.0;
+              for (int q = 0; q < M; ++q) v += (Ie.empty() ? (q == i ? 1.0 : 0.0) : Ie[q * NE + i]) * Mm[q * M + j];
+              rhs[i * M + j] = v * (bee - ale) / 2.0;
+            }
+          const std::vector<double> P = solve_dense(exact_mass(NE), rhs, NE, M);
+          auto times = [&](const std::vector<double>& I, int NG) {
+            std::vector<double> out(NE * NG, 0.0);
+            for (int i = 0; i < NE; ++i)
+              for (int j = 0; j < NG; ++j) {
+                double v = 0.0;
+                for (int q = 0; q < M; ++q) v += P[i * M + q] * (I.empty() ? (q == j ? 1.0 : 0.0) : I[q * NG + j]);
+                out[i * NG + j] = v;
+              }
+            return out;
+          };
+          *As[k] = pool.add(times(Ie, NE));
+          *Bs[k] = pool.add(times(If, NF));
         }
-        T.direct = (T.Ie0 < 0 && T.Ie1 < 0 && T.If0 < 0 && T.If1 < 0 && T.Pe0 < 0 && T.Pe1 < 0) ? 1 : 0;
+        T.direct = identity ? 1 : 0;
         terms.push_back(T);
       }
     }
@@ -505,7 +516,7 @@ std::string signature(const Patch& P, const SubLayout& S) {
       for (int k = 0; k < H.nterm[f]; ++k, ++t) {
         if (far) continue;
         const HpTerm& T = P.terms[t];
-        for (int x : {T.nb, T.direct, T.M0, T.M1, T.Ie0, T.Ie1, T.If0, T.If1, T.Pe0, T.Pe1}) v.push_back(x);
+        for (int x : {T.nb, T.direct, T.A0, T.A1, T.B0, T.B1}) v.push_back(x);
         v.push_back(T.sigma);
       }
     }

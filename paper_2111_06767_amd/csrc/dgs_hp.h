@@ -18,16 +18,21 @@ constexpr int kHpNeumann = -2;    // box face, homogeneous Neumann ghost (eq. bc
 constexpr int kHpZero = -3;       // a neighbour whose values are zero (set-up patches)
 
 // One mortar of an element face: the part shared with one neighbour.  The
-// face's transverse dimensions are t0 < t1; face arrays are [t1][t0].
-// Matrices live in a pool of doubles (row-major); offset -1 is the identity.
+// face's transverse dimensions are t0 < t1; face arrays are [t1][t0].  The
+// mortar's interpolations I (face points -> mortar points) and its exact L2
+// projection P back to the element's face points are stored premultiplied
+// per dimension: A_t = P_t I_own,t (N_own x N_own) and B_t = P_t I_nb,t
+// (N_own x N_nb), so that the projected corrections are
+//   cu = 1/2 (B u_nb - A u_own),
+//   cp = 1/2 s (A du_own + B du_nb) - sigma (A u_own - B u_nb)
+// with A = A_t1 (x) A_t0 and B = B_t1 (x) B_t0.  Matrices live in a pool of
+// doubles (row-major); offset -1 is the identity.
 struct HpTerm {
   int nb;        // neighbour element (>= 0) or one of the codes above
   int direct;    // 1: a box face, or a conforming face of equal points (every
                  //    matrix the identity): the flux is formed point by point
-  int M0, M1;    // mortar points along t0, t1
-  int Ie0, Ie1;  // own face points -> mortar points (M x N_own)
-  int If0, If1;  // neighbour face points -> mortar points (M x N_nb)
-  int Pe0, Pe1;  // mortar -> own face points, exact L2 projection (N_own x M)
+  int A0, A1;    // P I_own per transverse dimension
+  int B0, B1;    // P I_nb per transverse dimension
   double sigma;  // penalty (eq. penalty)
 };
 

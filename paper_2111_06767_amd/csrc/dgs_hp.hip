@@ -4,12 +4,12 @@
 // Operator: one workgroup per element, one thread per node (loops for more
 // nodes than threads).  The element's values and its three unlifted
 // derivatives sit in LDS.  Every face is a list of terms: a box-boundary term
-// (the ghost state of eq. bc on the element's own face points) or a mortar
-// shared with one neighbour, on which both sides' traces and normal
-// derivatives are interpolated, the fluxes of eq. numflux evaluated, and the
-// auxiliary and primal corrections projected back to the element's face
-// points (exact L2 projection).  The lift (eq. liftop) and the strong-form
-// primal equation (eq. dg_op_primal) follow as on the uniform grid.
+// (the ghost state of eq. bc on the element's own face points), a conforming
+// neighbour of equal points (the flux point by point), or a mortar shared
+// with one neighbour, whose corrections reach the element's face points
+// through the premultiplied interpolation-and-projection matrices.  The lift
+// (eq. liftop) and the strong-form primal equation (eq. dg_op_primal) follow
+// as on the uniform grid.
 #include "dgs_hp.h"
 
 namespace dgs {
@@ -17,52 +17,6 @@ namespace {
 
 constexpr int kHpThreads = 256;
 constexpr int kF = kHpMaxN * kHpMaxN;  // points of a face or mortar
-
-// out[r1][r0] = sum_{c1, c0} A1[r1][c1] A0[r0][c0] in[c1][c0] for two fields
-// (A0: r0 x c0, A1: r1 x c1, row-major in LDS; nullptr = identity).  Called
-// by every thread of the workgroup; ends with a barrier.
-__device__ void tensor2(const double* A0, int r0, int c0, const double* A1, int r1, int c1,
-                        const double* inA, const double* inB, double* tA, double* tB,
-                        double* outA, double* outB) {
-  for (int q = threadIdx.x; q < c1 * r0; q += blockDim.x) {
-    const int j = q / r0, i = q - j * r0;
-    double a, b;
-    if (A0) {
-      a = 0.0;
-      b = 0.0;
-      for (int m = 0; m < c0; ++m) {
-        const double w = A0[i * c0 + m];
-        a += w * inA[j * c0 + m];
-        b += w * inB[j * c0 + m];
-      }
-    } else {
-      a = inA[j * c0 + i];
-      b = inB[j * c0 + i];
-    }
-    tA[q] = a;
-    tB[q] = b;
-  }
-  __syncthreads();
-  for (int q = threadIdx.x; q < r1 * r0; q += blockDim.x) {
-    const int j = q / r0, i = q - j * r0;
-    double a, b;
-    if (A1) {
-      a = 0.0;
-      b = 0.0;
-      for (int m = 0; m < c1; ++m) {
-        const double w = A1[j * c1 + m];
-        a += w * tA[m * r0 + i];
-        b += w * tB[m * r0 + i];
-      }
-    } else {
-      a = tA[j * r0 + i];
-      b = tB[j * r0 + i];
-    }
-    outA[q] = a;
-    outB[q] = b;
-  }
-  __syncthreads();
-}
 
 // Node of an element with N points per dimension at position od along d and
 // (b0, b1) along the transverse dimensions t0 < t1.
@@ -82,8 +36,8 @@ __global__ void __launch_bounds__(kHpThreads)
   __shared__ double su[kHpMaxNodes];
   __shared__ double sg[3][kHpMaxNodes];
   __shared__ double scu[6][kF], scp[6][kF];
-  __shared__ double fa[kF], fb[kF], oa[kF], ob[kF], ma[kF], mb[kF], na[kF], nbv[kF], ta[kF], tb[kF];
-  __shared__ double smat[6][kF];
+  __shared__ double fa[kF], fb[kF], oa[kF], ob[kF], ma[kF], mb[kF], na[kF], nbv[kF];
+  __shared__ double smat[4][kF];
   const HpElem E = el[blockIdx.x];
   const long long base = (long long)blockIdx.y * copy_stride + E.off;
   const int N0 = E.N[0], N1 = E.N[1], N2 = E.N[2];
@@ -115,48 +69,54 @@ __global__ void __launch_bounds__(kHpThreads)
   }
   // pass 1, without barriers: box faces and conforming faces of equal points
   // (a single term each), point by point from the ghost state (eq. bc) or the
-  // neighbour's trace and normal derivative at the matching point
+  // neighbour's trace and normal derivative at the matching point; the points
+  // of all such faces are spread over the workgroup together, so the
+  // neighbours' loads are in flight at once
+  int fstart[7];
+  fstart[0] = 0;
   for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1;
+    const int nf = E.N[d == 0 ? 1 : 0] * E.N[d == 2 ? 1 : 2];
+    fstart[f + 1] = fstart[f] + (terms[tf[f]].direct ? nf : 0);
+  }
+  for (int g = tid; g < fstart[6]; g += blockDim.x) {
+    int f = 0;
+    while (g >= fstart[f + 1]) ++f;
+    const int q = g - fstart[f];
     const HpTerm T = terms[tf[f]];
-    if (!T.direct) continue;
     const int d = f >> 1;
     const double sgn = (f & 1) ? 1.0 : -1.0;
-    const int n0 = E.N[d == 0 ? 1 : 0], n1 = E.N[d == 2 ? 1 : 2];
-    const int od = (f & 1) ? E.N[d] - 1 : 0;
-    if (T.nb < 0) {
-      // ghost state of a box face; a zero neighbour (set-up patches) has
-      // neither value nor derivative
-      const bool dir = T.nb == kHpDirichlet, zero = T.nb == kHpZero;
-      for (int q = tid; q < n0 * n1; q += blockDim.x) {
-        const int p = face_node(d, od, q % n0, q / n0, E.N);
-        const double ui = su[p], dui = sg[d][p];
-        const double ue = zero ? 0.0 : (dir ? -ui : ui), due = zero ? 0.0 : (dir ? dui : -dui);
-        scu[f][q] = 0.5 * (ue - ui);
-        scp[f][q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
-      }
-    } else {
+    const int n0 = E.N[d == 0 ? 1 : 0];
+    const int b0 = q % n0, b1 = q / n0;
+    const int p = face_node(d, (f & 1) ? E.N[d] - 1 : 0, b0, b1, E.N);
+    const double ui = su[p], dui = sg[d][p];
+    double ue, due;
+    if (T.nb >= 0) {
       const HpElem F = el[T.nb];
       const int Nd = F.N[d];
       const int fod = (f & 1) ? 0 : Nd - 1;
       const double* D = R.D + (Nd - 2) * 64 + fod * Nd;
       const int strd = d == 0 ? 1 : (d == 1 ? F.N[0] : F.N[0] * F.N[1]);
-      const double* fu = u + (long long)blockIdx.y * copy_stride + F.off;
-      for (int q = tid; q < n0 * n1; q += blockDim.x) {
-        const int b0 = q % n0, b1 = q / n0;
-        const double* line = fu + face_node(d, 0, b0, b1, F.N);
-        double acc = 0.0;
-        for (int m = 0; m < Nd; ++m) acc += D[m] * line[m * strd];
-        const double ue = line[fod * strd], due = F.rh[d] * acc;
-        const int p = face_node(d, od, b0, b1, E.N);
-        const double ui = su[p], dui = sg[d][p];
-        scu[f][q] = 0.5 * (ue - ui);
-        scp[f][q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
-      }
+      const double* line = u + (long long)blockIdx.y * copy_stride + F.off + face_node(d, 0, b0, b1, F.N);
+      double acc = 0.0;
+      for (int m = 0; m < Nd; ++m) acc += D[m] * line[m * strd];
+      ue = line[fod * strd];
+      due = F.rh[d] * acc;
+    } else if (T.nb == kHpZero) {  // a zero neighbour (set-up patches)
+      ue = 0.0;
+      due = 0.0;
+    } else {
+      const bool dir = T.nb == kHpDirichlet;
+      ue = dir ? -ui : ui;
+      due = dir ? dui : -dui;
     }
+    scu[f][q] = 0.5 * (ue - ui);
+    scp[f][q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
   }
-  // pass 2: mortars of nonconforming faces; every face data interpolated to
-  // the mortar, the fluxes of eq. numflux there, the corrections projected
-  // back (matrices staged in LDS per term)
+  // pass 2: mortars of nonconforming faces.  Per term, the premultiplied
+  // matrices A = P I_own and B = P I_nb (staged in LDS) carry the element's
+  // and the neighbour's face data through the mortar and back to the
+  // element's face points; the fluxes of eq. numflux combine them there
   for (int f = 0; f < 6; ++f) {
     if (terms[tf[f]].direct) continue;
     const int d = f >> 1;
@@ -164,6 +124,13 @@ __global__ void __launch_bounds__(kHpThreads)
     const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
     const int n0 = E.N[t0], n1 = E.N[t1];
     const int od = (f & 1) ? E.N[d] - 1 : 0;
+    for (int q = tid; q < n0 * n1; q += blockDim.x) {
+      const int p = face_node(d, od, q % n0, q / n0, E.N);
+      scu[f][q] = 0.0;
+      scp[f][q] = 0.0;
+      fa[q] = su[p];
+      fb[q] = sg[d][p];
+    }
     for (int k = 0; k < E.nterm[f]; ++k) {
       const HpTerm T = terms[tf[f] + k];
       int m0 = 0, m1 = 0;
@@ -173,20 +140,11 @@ __global__ void __launch_bounds__(kHpThreads)
         m0 = F.N[t0];
         m1 = F.N[t1];
       }
-      const int offs[6] = {T.Ie0, T.Ie1, T.If0, T.If1, T.Pe0, T.Pe1};
-      const int sizes[6] = {T.M0 * n0, T.M1 * n1, T.M0 * m0, T.M1 * m1, n0 * T.M0, n1 * T.M1};
-      for (int q = tid; q < 6 * kF; q += blockDim.x) {
+      const int offs[4] = {T.A0, T.A1, T.B0, T.B1};
+      const int sizes[4] = {n0 * n0, n1 * n1, n0 * m0, n1 * m1};
+      for (int q = tid; q < 4 * kF; q += blockDim.x) {
         const int mi = q / kF, e = q - mi * kF;
         if (offs[mi] >= 0 && e < sizes[mi]) smat[mi][e] = pool[offs[mi] + e];
-      }
-      for (int q = tid; q < n0 * n1; q += blockDim.x) {
-        const int p = face_node(d, od, q % n0, q / n0, E.N);
-        if (k == 0) {
-          scu[f][q] = 0.0;
-          scp[f][q] = 0.0;
-        }
-        fa[q] = su[p];
-        fb[q] = sg[d][p];
       }
       if (T.nb >= 0) {
         // the neighbour's trace and normal derivative on its own face points
@@ -204,22 +162,73 @@ __global__ void __launch_bounds__(kHpThreads)
         }
       }
       __syncthreads();
-      const double* A[6];
-      for (int mi = 0; mi < 6; ++mi) A[mi] = offs[mi] >= 0 ? smat[mi] : nullptr;
-      tensor2(A[0], T.M0, n0, A[1], T.M1, n1, fa, fb, ta, tb, ma, mb);
-      if (T.nb >= 0) tensor2(A[2], T.M0, m0, A[3], T.M1, m1, oa, ob, ta, tb, na, nbv);
-      // a zero neighbour (set-up patches) contributes 0
-      for (int q = tid; q < T.M0 * T.M1; q += blockDim.x) {
-        const double ui = ma[q], dui = mb[q];
-        const double ue = T.nb >= 0 ? na[q] : 0.0, due = T.nb >= 0 ? nbv[q] : 0.0;
-        fa[q] = 0.5 * (ue - ui);
-        fb[q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
+      const double* A0 = T.A0 >= 0 ? smat[0] : nullptr;
+      const double* A1 = T.A1 >= 0 ? smat[1] : nullptr;
+      const double* B0 = T.B0 >= 0 ? smat[2] : nullptr;
+      const double* B1 = T.B1 >= 0 ? smat[3] : nullptr;
+      // along t0: own data [n1][n0] -> [n1][n0], neighbour data [m1][m0] -> [m1][n0]
+      for (int q = tid; q < n1 * n0; q += blockDim.x) {
+        const int j = q / n0, i = q - j * n0;
+        double a = 0.0, b = 0.0;
+        if (A0) {
+          for (int m = 0; m < n0; ++m) {
+            const double w = A0[i * n0 + m];
+            a += w * fa[j * n0 + m];
+            b += w * fb[j * n0 + m];
+          }
+        } else {
+          a = fa[q];
+          b = fb[q];
+        }
+        ma[q] = a;
+        mb[q] = b;
       }
+      if (T.nb >= 0)
+        for (int q = tid; q < m1 * n0; q += blockDim.x) {
+          const int j = q / n0, i = q - j * n0;
+          double a = 0.0, b = 0.0;
+          if (B0) {
+            for (int m = 0; m < m0; ++m) {
+              const double w = B0[i * m0 + m];
+              a += w * oa[j * m0 + m];
+              b += w * ob[j * m0 + m];
+            }
+          } else {
+            a = oa[j * m0 + i];
+            b = ob[j * m0 + i];
+          }
+          na[q] = a;
+          nbv[q] = b;
+        }
       __syncthreads();
-      tensor2(A[4], n0, T.M0, A[5], n1, T.M1, fa, fb, ta, tb, oa, ob);
-      for (int q = tid; q < n0 * n1; q += blockDim.x) {
-        scu[f][q] += oa[q];
-        scp[f][q] += ob[q];
+      // along t1, then the fluxes (a zero neighbour contributes nothing)
+      for (int q = tid; q < n1 * n0; q += blockDim.x) {
+        const int j = q / n0, i = q - j * n0;
+        double hu = 0.0, hd = 0.0, gu = 0.0, gd = 0.0;
+        if (A1) {
+          for (int m = 0; m < n1; ++m) {
+            const double w = A1[j * n1 + m];
+            hu += w * ma[m * n0 + i];
+            hd += w * mb[m * n0 + i];
+          }
+        } else {
+          hu = ma[q];
+          hd = mb[q];
+        }
+        if (T.nb >= 0) {
+          if (B1) {
+            for (int m = 0; m < m1; ++m) {
+              const double w = B1[j * m1 + m];
+              gu += w * na[m * n0 + i];
+              gd += w * nbv[m * n0 + i];
+            }
+          } else {
+            gu = na[q];
+            gd = nbv[q];
+          }
+        }
+        scu[f][q] += 0.5 * (gu - hu);
+        scp[f][q] += 0.5 * sgn * (hd + gd) - T.sigma * (hu - gu);
       }
       __syncthreads();
     }
