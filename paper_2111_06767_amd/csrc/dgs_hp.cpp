@@ -461,7 +461,6 @@ SubLayout sub_layout(const HMesh& m, int e, int overlap, std::vector<std::array<
 // terms pointing at patch-local elements (others become zero neighbours).
 struct Patch {
   std::vector<int> elems;
-  std::vector<int> via;  // the face of the centre a neighbour lies across (-1: the centre)
   std::vector<HpElem> hel;
   std::vector<HpTerm> terms;
   long long ndof = 0;
@@ -469,12 +468,8 @@ struct Patch {
 Patch make_patch(const HMesh& m, const std::vector<HpElem>& hel, const std::vector<HpTerm>& terms, int e) {
   Patch P;
   P.elems.push_back(e);
-  P.via.push_back(-1);
   for (int f = 0; f < 6; ++f)
-    for (int g : m.nbr[e][f]) {
-      P.elems.push_back(g);
-      P.via.push_back(f);
-    }
+    for (int g : m.nbr[e][f]) P.elems.push_back(g);
   std::map<int, int> local;
   for (int i = 0; i < (int)P.elems.size(); ++i) local[P.elems[i]] = i;
   for (int g : P.elems) {
@@ -498,35 +493,219 @@ Patch make_patch(const HMesh& m, const std::vector<HpElem>& hel, const std::vect
   return P;
 }
 
-// The structure of a subdomain that decides A_S: the patch's elements
-// (degrees, widths, face terms in patch-local form) and the rows.  The face
-// of a neighbour that points away from the centre is left out: the
-// subdomain's values vanish on it and beyond it (N_ov stops short of it), so
-// its auxiliary correction is zero and its primal correction reaches only
-// its own points, which are outside the subdomain.
-std::string signature(const Patch& P, const SubLayout& S) {
+
+
+// Frames of the symmetry group of axis-aligned boxes: new axis a is old axis
+// perm[a], reversed when mir[a].  The DG operator, the LGL points, the
+// weights and the mortar rules are invariant under these maps, so subdomains
+// that coincide after one of them share A_S up to the order of their rows.
+struct Frame {
+  int perm[3];
+  int mir[3];
+};
+std::vector<Frame> all_frames() {
+  static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  std::vector<Frame> out;
+  for (auto& p : perms)
+    for (int mm = 0; mm < 8; ++mm) {
+      Frame T;
+      for (int a = 0; a < 3; ++a) {
+        T.perm[a] = p[a];
+        T.mir[a] = (mm >> a) & 1;
+      }
+      out.push_back(T);
+    }
+  return out;
+}
+// the old face that new face fn of a frame is
+int old_face(const Frame& T, int fn) {
+  const int a = fn >> 1;
+  const int s = (fn & 1) ? 1 : -1;
+  const int so = T.mir[a] ? -s : s;
+  return 2 * T.perm[a] + (so > 0 ? 1 : 0);
+}
+// old node of the node with new indices inew of an element with old extents N
+int old_node(const Frame& T, const int N[3], const int inew[3]) {
+  int io[3];
+  for (int a = 0; a < 3; ++a) {
+    const int d = T.perm[a];
+    io[d] = T.mir[a] ? N[d] - 1 - inew[a] : inew[a];
+  }
+  return (io[2] * N[1] + io[1]) * N[0] + io[0];
+}
+
+struct FrameView {
+  const HMesh& m;
+  int e;
+  Frame T;
+  double unit[3];  // physical length of one integer unit per old axis (halved)
+  // box of g relative to the centre of e, in the new frame (physical units)
+  void box(int g, double lo[3], double hi[3]) const {
+    const HElem &E = m.el[e], &G = m.el[g];
+    for (int a = 0; a < 3; ++a) {
+      const int d = T.perm[a];
+      const long long c2 = E.lo[d] + E.hi[d];
+      long long l = 2 * G.lo[d] - c2, h = 2 * G.hi[d] - c2;
+      if (T.mir[a]) {
+        const long long t = -l;
+        l = -h;
+        h = t;
+      }
+      lo[a] = l * unit[d];
+      hi[a] = h * unit[d];
+    }
+  }
+  int Nn(int g, int a) const { return m.el[g].N[T.perm[a]]; }
+  // neighbours of g across new face fn, ordered by their boxes in the new frame
+  std::vector<int> nbrs(int g, int fn) const {
+    std::vector<int> v = m.nbr[g][old_face(T, fn)];
+    std::vector<std::array<double, 3>> key(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+      double lo[3], hi[3];
+      box(v[i], lo, hi);
+      key[i] = {lo[2], lo[1], lo[0]};
+    }
+    std::vector<size_t> idx(v.size());
+    for (size_t i = 0; i < v.size(); ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return key[a] < key[b]; });
+    std::vector<int> out;
+    for (size_t i : idx) out.push_back(v[i]);
+    return out;
+  }
+};
+
+// The structure of subdomain e seen in frame T (everything that decides A_S
+// in that frame's row order): the patch (the centre and its face
+// neighbours) with boxes, points and the face data of each patch element,
+// except the faces of the neighbours that point away from the centre (the
+// subdomain's values vanish on them and beyond, so they reach no row).
+std::vector<double> frame_signature(const FrameView& V, std::vector<int>& patch) {
+  const HMesh& m = V.m;
+  patch.assign(1, V.e);
+  std::vector<int> via(1, -1);
+  for (int fn = 0; fn < 6; ++fn)
+    for (int g : V.nbrs(V.e, fn)) {
+      patch.push_back(g);
+      via.push_back(fn);
+    }
   std::vector<double> v;
-  for (size_t i = 0; i < P.hel.size(); ++i) {
-    const HpElem& H = P.hel[i];
-    for (int d = 0; d < 3; ++d) v.push_back(H.N[d]), v.push_back(H.rh[d]);
-    int t = H.term0;
-    for (int f = 0; f < 6; ++f) {
-      const bool far = P.via[i] == f;
-      v.push_back(far ? -1 : H.nterm[f]);
-      for (int k = 0; k < H.nterm[f]; ++k, ++t) {
-        if (far) continue;
-        const HpTerm& T = P.terms[t];
-        for (int x : {T.nb, T.direct, T.A0, T.A1, T.B0, T.B1}) v.push_back(x);
-        v.push_back(T.sigma);
+  auto put_elem = [&](int g) {
+    double lo[3], hi[3];
+    V.box(g, lo, hi);
+    for (int a = 0; a < 3; ++a) v.push_back(lo[a]), v.push_back(hi[a]), v.push_back(V.Nn(g, a));
+  };
+  for (size_t i = 0; i < patch.size(); ++i) {
+    const int g = patch[i];
+    put_elem(g);
+    for (int fn = 0; fn < 6; ++fn) {
+      if (via[i] == fn) {
+        v.push_back(-7.0);
+        continue;
+      }
+      const std::vector<int> nb = V.nbrs(g, fn);
+      if (nb.empty()) {
+        v.push_back(((m.neumann >> old_face(V.T, fn)) & 1) ? -2.0 : -1.0);
+        continue;
+      }
+      v.push_back((double)nb.size());
+      for (int k : nb) {
+        const auto it = std::find(patch.begin(), patch.end(), k);
+        if (it != patch.end() && (size_t)(it - patch.begin()) < patch.size()) {
+          v.push_back(-1000.0 - (double)(it - patch.begin()));
+        } else {
+          v.push_back(-3.0);
+          put_elem(k);
+        }
       }
     }
   }
-  std::map<int, int> local;
-  for (int i = 0; i < (int)P.elems.size(); ++i) local[P.elems[i]] = i;
-  for (size_t r = 0; r < S.elem.size(); ++r) v.push_back(local[S.elem[r]]), v.push_back(S.node[r]);
-  return std::string(reinterpret_cast<const char*>(v.data()), v.size() * sizeof(double));
+  return v;
 }
 
+// Rows of subdomain e in frame T: the centre's points in the new [k][j][i]
+// order, then per new face the neighbours in frame order, N_ov layers each,
+// layer 0 nearest the face, the lower new transverse dimension fastest.
+void frame_rows(const FrameView& V, int overlap, std::vector<int>& elem, std::vector<int>& node) {
+  const HMesh& m = V.m;
+  const int e = V.e;
+  elem.clear();
+  node.clear();
+  int n[3] = {V.Nn(e, 0), V.Nn(e, 1), V.Nn(e, 2)};
+  for (int k = 0; k < n[2]; ++k)
+    for (int j = 0; j < n[1]; ++j)
+      for (int i = 0; i < n[0]; ++i) {
+        const int inew[3] = {i, j, k};
+        elem.push_back(e);
+        node.push_back(old_node(V.T, m.el[e].N, inew));
+      }
+  for (int fn = 0; fn < 6; ++fn) {
+    const int a = fn >> 1, s = (fn & 1) ? 1 : -1;
+    const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+    for (int g : V.nbrs(e, fn)) {
+      const int Na = V.Nn(g, a);
+      const int nov = overlap_layers(Na, overlap);
+      for (int layer = 0; layer < nov; ++layer)
+        for (int b1 = 0; b1 < V.Nn(g, t1); ++b1)
+          for (int b0 = 0; b0 < V.Nn(g, t0); ++b0) {
+            int inew[3];
+            inew[a] = s > 0 ? layer : Na - 1 - layer;
+            inew[t0] = b0;
+            inew[t1] = b1;
+            elem.push_back(g);
+            node.push_back(old_node(V.T, m.el[g].N, inew));
+          }
+    }
+  }
+}
+
+// Canonical form of subdomain e: the smallest signature over the frames (a
+// cheap key of the centre alone selects the candidate frames first), its
+// rows in that frame with their weights, and the patch elements.
+std::string canonical_subdomain(const HMesh& m, int e, int overlap, const SubLayout& own,
+                                SubLayout& rows, std::vector<int>& patch) {
+  static const std::vector<Frame> frames = all_frames();
+  double unit[3];
+  for (int d = 0; d < 3; ++d) unit[d] = 0.5 * (m.upper[d] - m.lower[d]) / m.blocks[d] / (double)m.R[d];
+  std::vector<std::vector<double>> small(frames.size());
+  for (size_t f = 0; f < frames.size(); ++f) {
+    FrameView V{m, e, frames[f], {unit[0], unit[1], unit[2]}};
+    std::vector<double>& k = small[f];
+    for (int a = 0; a < 3; ++a) k.push_back(V.Nn(e, a)), k.push_back(m.el[e].h[frames[f].perm[a]]);
+    for (int fn = 0; fn < 6; ++fn) {
+      const auto& nb = m.nbr[e][old_face(frames[f], fn)];
+      k.push_back(nb.empty() ? (((m.neumann >> old_face(frames[f], fn)) & 1) ? -2.0 : -1.0) : (double)nb.size());
+      for (int g : nb) k.push_back(m.el[g].N[frames[f].perm[fn >> 1]]);
+    }
+  }
+  const std::vector<double> kmin = *std::min_element(small.begin(), small.end());
+  std::vector<double> best;
+  int bestf = -1;
+  std::vector<int> bestpatch;
+  for (size_t f = 0; f < frames.size(); ++f) {
+    if (small[f] != kmin) continue;
+    FrameView V{m, e, frames[f], {unit[0], unit[1], unit[2]}};
+    std::vector<int> pt;
+    std::vector<double> sig = frame_signature(V, pt);
+    if (bestf < 0 || sig < best) {
+      best = std::move(sig);
+      bestf = (int)f;
+      bestpatch = std::move(pt);
+    }
+  }
+  FrameView V{m, e, frames[bestf], {unit[0], unit[1], unit[2]}};
+  frame_rows(V, overlap, rows.elem, rows.node);
+  // weights of the points, from the subdomain's own layout
+  std::map<std::pair<int, int>, double> w;
+  for (size_t r = 0; r < own.elem.size(); ++r) w[{own.elem[r], own.node[r]}] = own.w[r];
+  rows.w.resize(rows.elem.size());
+  for (size_t r = 0; r < rows.elem.size(); ++r) {
+    const auto it = w.find({rows.elem[r], rows.node[r]});
+    if (it == w.end()) throw DgsError(DGS_ERR_HIP, "hp subdomain rows do not match their layout");
+    rows.w[r] = it->second;
+  }
+  patch = std::move(bestpatch);
+  return std::string(reinterpret_cast<const char*>(best.data()), best.size() * sizeof(double));
+}
 }  // namespace
 
 struct dgs_hp_problem {
@@ -578,14 +757,14 @@ void build_schwarz(dgs_hp_problem* P, HpLevel& L, hipStream_t s) {
   std::vector<std::vector<int>> members;
   std::vector<Patch> rep;
   for (int e = 0; e < m.E(); ++e) {
-    lay[e] = sub_layout(m, e, overlap, fac);
-    Patch p = make_patch(m, L.hel, L.terms, e);
-    const std::string key = signature(p, lay[e]);
+    const SubLayout own = sub_layout(m, e, overlap, fac);
+    std::vector<int> pe;
+    const std::string key = canonical_subdomain(m, e, overlap, own, lay[e], pe);
     auto it = class_of.find(key);
     if (it == class_of.end()) {
       it = class_of.emplace(key, (int)members.size()).first;
       members.emplace_back();
-      rep.push_back(std::move(p));
+      rep.push_back(make_patch(m, L.hel, L.terms, e));
     }
     members[it->second].push_back(e);
   }

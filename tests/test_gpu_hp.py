@@ -107,12 +107,12 @@ def test_hp_solve_matches_oracle():
 
 
 def test_equal_subdomains_share_an_inverse():
-    # one block of 4 x 4 x 4 elements of one degree: the 27 boundary
-    # configurations (interior, faces, edges, corners) give 27 classes
+    # one cube of 4 x 4 x 4 elements of one degree: up to mirrors and axis
+    # exchanges the subdomains are interior, face, edge or corner ones
     announce("hp classes")
     m = hp.HpMesh((0, 0, 0), (1, 1, 1), (1, 1, 1), [(2, 2, 2)], np.full((64, 3), 3))
     prob = _gpu(m, np.full((64, 3), 3), mg_levels=1)
-    assert prob.num_classes(0) == 27
+    assert prob.num_classes(0) == 4
     b = W.random_normal(65, m.ndof)
     ref = hp.HpSchwarzSmoother(m, C).smooth(np.zeros(m.ndof), b, 1)
     u = to_gpu(np.zeros(m.ndof))
