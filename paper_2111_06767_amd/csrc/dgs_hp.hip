@@ -18,14 +18,20 @@ namespace {
 constexpr int kHpThreads = 256;
 constexpr int kF = kHpMaxN * kHpMaxN;  // points of a face or mortar
 
-// Node of an element with N points per dimension at position od along d and
+// Select one of three values by a dimension index without a runtime-indexed
+// private array (those go to scratch memory).
+__device__ __forceinline__ int pick(int d, int a, int b, int c) { return d == 0 ? a : (d == 1 ? b : c); }
+__device__ __forceinline__ double pick(int d, double a, double b, double c) {
+  return d == 0 ? a : (d == 1 ? b : c);
+}
+
+// Node of an element with N0 x N1 (x N2) points at position od along d and
 // (b0, b1) along the transverse dimensions t0 < t1.
-__device__ __forceinline__ int face_node(int d, int od, int b0, int b1, const int N[3]) {
-  int idx[3];
-  idx[d] = od;
-  idx[d == 0 ? 1 : 0] = b0;
-  idx[d == 2 ? 1 : 2] = b1;
-  return (idx[2] * N[1] + idx[1]) * N[0] + idx[0];
+__device__ __forceinline__ int face_node(int d, int od, int b0, int b1, int N0, int N1) {
+  const int i = d == 0 ? od : b0;
+  const int j = d == 0 ? b0 : (d == 1 ? od : b1);
+  const int k = d == 2 ? od : b1;
+  return (k * N1 + j) * N0 + i;
 }
 
 template <bool RES>
@@ -39,69 +45,75 @@ __global__ void __launch_bounds__(kHpThreads)
   __shared__ double fa[kF], fb[kF], oa[kF], ob[kF], ma[kF], mb[kF], na[kF], nbv[kF];
   __shared__ double smat[4][kF];
   const HpElem E = el[blockIdx.x];
-  const long long base = (long long)blockIdx.y * copy_stride + E.off;
+  const long long cbase = (long long)blockIdx.y * copy_stride;
+  const long long base = cbase + E.off;
   const int N0 = E.N[0], N1 = E.N[1], N2 = E.N[2];
   const int n = N0 * N1 * N2;
-  const int str[3] = {1, N0, N0 * N1};
   const int tid = threadIdx.x;
   for (int p = tid; p < n; p += blockDim.x) su[p] = u[base + p];
   __syncthreads();
   // unlifted derivatives D_d u = (2/h_d) D_xi u
   for (int p = tid; p < n; p += blockDim.x) {
-    const int idx[3] = {p % N0, (p / N0) % N1, p / (N0 * N1)};
+    const int i = p % N0, j = (p / N0) % N1, k = p / (N0 * N1);
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int Nd = E.N[d];
-      const double* D = R.D + (Nd - 2) * 64 + idx[d] * Nd;
-      const int l0 = p - idx[d] * str[d];
+      const int Nd = pick(d, N0, N1, N2), id = pick(d, i, j, k), st = pick(d, 1, N0, N0 * N1);
+      const double* D = R.D + (Nd - 2) * 64 + id * Nd;
+      const int l0 = p - id * st;
       double acc = 0.0;
-      for (int m = 0; m < Nd; ++m) acc += D[m] * su[l0 + m * str[d]];
+      for (int m = 0; m < Nd; ++m) acc += D[m] * su[l0 + m * st];
       sg[d][p] = E.rh[d] * acc;
     }
   }
   __syncthreads();
-  int tf[6];
-  {
-    int t = E.term0;
-    for (int f = 0; f < 6; ++f) {
-      tf[f] = t;
-      t += E.nterm[f];
-    }
-  }
   // pass 1, without barriers: box faces and conforming faces of equal points
   // (a single term each), point by point from the ghost state (eq. bc) or the
   // neighbour's trace and normal derivative at the matching point; the points
   // of all such faces are spread over the workgroup together, so the
   // neighbours' loads are in flight at once
-  int fstart[7];
-  fstart[0] = 0;
-  for (int f = 0; f < 6; ++f) {
-    const int d = f >> 1;
-    const int nf = E.N[d == 0 ? 1 : 0] * E.N[d == 2 ? 1 : 2];
-    fstart[f + 1] = fstart[f] + (terms[tf[f]].direct ? nf : 0);
+  int nd[6];  // points of each face handled here (0: a mortar face)
+  bool any_mortar = false;
+  {
+    int t = E.term0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int d = f >> 1;
+      const bool direct = terms[t].direct;
+      nd[f] = direct ? pick(d, N1, N0, N0) * pick(d, N2, N2, N1) : 0;
+      any_mortar = any_mortar || !direct;
+      t += E.nterm[f];
+    }
   }
-  for (int g = tid; g < fstart[6]; g += blockDim.x) {
-    int f = 0;
-    while (g >= fstart[f + 1]) ++f;
-    const int q = g - fstart[f];
-    const HpTerm T = terms[tf[f]];
+  const int ndirect = nd[0] + nd[1] + nd[2] + nd[3] + nd[4] + nd[5];
+  for (int g = tid; g < ndirect; g += blockDim.x) {
+    int f = 0, q = g, t = E.term0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (f == k && q >= nd[k]) {
+        q -= nd[k];
+        t += E.nterm[k];
+        f = k + 1;
+      }
+    const HpTerm T = terms[t];
     const int d = f >> 1;
     const double sgn = (f & 1) ? 1.0 : -1.0;
-    const int n0 = E.N[d == 0 ? 1 : 0];
+    const int n0 = d == 0 ? N1 : N0;
     const int b0 = q % n0, b1 = q / n0;
-    const int p = face_node(d, (f & 1) ? E.N[d] - 1 : 0, b0, b1, E.N);
+    const int Nd = pick(d, N0, N1, N2);
+    const int p = face_node(d, (f & 1) ? Nd - 1 : 0, b0, b1, N0, N1);
     const double ui = su[p], dui = sg[d][p];
     double ue, due;
     if (T.nb >= 0) {
       const HpElem F = el[T.nb];
-      const int Nd = F.N[d];
-      const int fod = (f & 1) ? 0 : Nd - 1;
-      const double* D = R.D + (Nd - 2) * 64 + fod * Nd;
-      const int strd = d == 0 ? 1 : (d == 1 ? F.N[0] : F.N[0] * F.N[1]);
-      const double* line = u + (long long)blockIdx.y * copy_stride + F.off + face_node(d, 0, b0, b1, F.N);
+      const int FN = pick(d, F.N[0], F.N[1], F.N[2]);
+      const int fod = (f & 1) ? 0 : FN - 1;
+      const double* D = R.D + (FN - 2) * 64 + fod * FN;
+      const int strd = pick(d, 1, F.N[0], F.N[0] * F.N[1]);
+      const double* line = u + cbase + F.off + face_node(d, 0, b0, b1, F.N[0], F.N[1]);
       double acc = 0.0;
-      for (int m = 0; m < Nd; ++m) acc += D[m] * line[m * strd];
+      for (int m = 0; m < FN; ++m) acc += D[m] * line[m * strd];
       ue = line[fod * strd];
-      due = F.rh[d] * acc;
+      due = pick(d, F.rh[0], F.rh[1], F.rh[2]) * acc;
     } else if (T.nb == kHpZero) {  // a zero neighbour (set-up patches)
       ue = 0.0;
       due = 0.0;
@@ -117,159 +129,172 @@ __global__ void __launch_bounds__(kHpThreads)
   // matrices A = P I_own and B = P I_nb (staged in LDS) carry the element's
   // and the neighbour's face data through the mortar and back to the
   // element's face points; the fluxes of eq. numflux combine them there
-  for (int f = 0; f < 6; ++f) {
-    if (terms[tf[f]].direct) continue;
-    const int d = f >> 1;
-    const double sgn = (f & 1) ? 1.0 : -1.0;
-    const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-    const int n0 = E.N[t0], n1 = E.N[t1];
-    const int od = (f & 1) ? E.N[d] - 1 : 0;
-    for (int q = tid; q < n0 * n1; q += blockDim.x) {
-      const int p = face_node(d, od, q % n0, q / n0, E.N);
-      scu[f][q] = 0.0;
-      scp[f][q] = 0.0;
-      fa[q] = su[p];
-      fb[q] = sg[d][p];
-    }
-    for (int k = 0; k < E.nterm[f]; ++k) {
-      const HpTerm T = terms[tf[f] + k];
-      int m0 = 0, m1 = 0;
-      HpElem F{};
-      if (T.nb >= 0) {
-        F = el[T.nb];
-        m0 = F.N[t0];
-        m1 = F.N[t1];
+  if (any_mortar) {
+    int t = E.term0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      const int tf = t;
+      t += E.nterm[f];
+      if (nd[f] > 0) continue;
+      const int d = f >> 1;
+      const double sgn = (f & 1) ? 1.0 : -1.0;
+      const int n0 = d == 0 ? N1 : N0, n1 = d == 2 ? N1 : N2;
+      const int Nd = pick(d, N0, N1, N2);
+      const int od = (f & 1) ? Nd - 1 : 0;
+      for (int q = tid; q < n0 * n1; q += blockDim.x) {
+        const int p = face_node(d, od, q % n0, q / n0, N0, N1);
+        scu[f][q] = 0.0;
+        scp[f][q] = 0.0;
+        fa[q] = su[p];
+        fb[q] = sg[d][p];
       }
-      const int offs[4] = {T.A0, T.A1, T.B0, T.B1};
-      const int sizes[4] = {n0 * n0, n1 * n1, n0 * m0, n1 * m1};
-      for (int q = tid; q < 4 * kF; q += blockDim.x) {
-        const int mi = q / kF, e = q - mi * kF;
-        if (offs[mi] >= 0 && e < sizes[mi]) smat[mi][e] = pool[offs[mi] + e];
-      }
-      if (T.nb >= 0) {
-        // the neighbour's trace and normal derivative on its own face points
-        const int Nd = F.N[d];
-        const int fod = (f & 1) ? 0 : Nd - 1;
-        const double* D = R.D + (Nd - 2) * 64 + fod * Nd;
-        const int strd = d == 0 ? 1 : (d == 1 ? F.N[0] : F.N[0] * F.N[1]);
-        const double* fu = u + (long long)blockIdx.y * copy_stride + F.off;
-        for (int q = tid; q < m0 * m1; q += blockDim.x) {
-          const double* line = fu + face_node(d, 0, q % m0, q / m0, F.N);
-          double acc = 0.0;
-          for (int m = 0; m < Nd; ++m) acc += D[m] * line[m * strd];
-          oa[q] = line[fod * strd];
-          ob[q] = F.rh[d] * acc;
+      for (int k = 0; k < E.nterm[f]; ++k) {
+        const HpTerm T = terms[tf + k];
+        int m0 = 0, m1 = 0, FN = 2, FN0 = 1, FN1 = 1;
+        long long foff = 0;
+        double frh = 0.0;
+        if (T.nb >= 0) {
+          const HpElem F = el[T.nb];
+          m0 = d == 0 ? F.N[1] : F.N[0];
+          m1 = d == 2 ? F.N[1] : F.N[2];
+          FN = pick(d, F.N[0], F.N[1], F.N[2]);
+          FN0 = F.N[0];
+          FN1 = F.N[1];
+          foff = F.off;
+          frh = pick(d, F.rh[0], F.rh[1], F.rh[2]);
         }
-      }
-      __syncthreads();
-      const double* A0 = T.A0 >= 0 ? smat[0] : nullptr;
-      const double* A1 = T.A1 >= 0 ? smat[1] : nullptr;
-      const double* B0 = T.B0 >= 0 ? smat[2] : nullptr;
-      const double* B1 = T.B1 >= 0 ? smat[3] : nullptr;
-      // along t0: own data [n1][n0] -> [n1][n0], neighbour data [m1][m0] -> [m1][n0]
-      for (int q = tid; q < n1 * n0; q += blockDim.x) {
-        const int j = q / n0, i = q - j * n0;
-        double a = 0.0, b = 0.0;
-        if (A0) {
-          for (int m = 0; m < n0; ++m) {
-            const double w = A0[i * n0 + m];
-            a += w * fa[j * n0 + m];
-            b += w * fb[j * n0 + m];
-          }
-        } else {
-          a = fa[q];
-          b = fb[q];
-        }
-        ma[q] = a;
-        mb[q] = b;
-      }
-      if (T.nb >= 0)
-        for (int q = tid; q < m1 * n0; q += blockDim.x) {
-          const int j = q / n0, i = q - j * n0;
-          double a = 0.0, b = 0.0;
-          if (B0) {
-            for (int m = 0; m < m0; ++m) {
-              const double w = B0[i * m0 + m];
-              a += w * oa[j * m0 + m];
-              b += w * ob[j * m0 + m];
-            }
-          } else {
-            a = oa[j * m0 + i];
-            b = ob[j * m0 + i];
-          }
-          na[q] = a;
-          nbv[q] = b;
-        }
-      __syncthreads();
-      // along t1, then the fluxes (a zero neighbour contributes nothing)
-      for (int q = tid; q < n1 * n0; q += blockDim.x) {
-        const int j = q / n0, i = q - j * n0;
-        double hu = 0.0, hd = 0.0, gu = 0.0, gd = 0.0;
-        if (A1) {
-          for (int m = 0; m < n1; ++m) {
-            const double w = A1[j * n1 + m];
-            hu += w * ma[m * n0 + i];
-            hd += w * mb[m * n0 + i];
-          }
-        } else {
-          hu = ma[q];
-          hd = mb[q];
+        for (int q = tid; q < 4 * kF; q += blockDim.x) {
+          const int mi = q / kF, e = q - mi * kF;
+          const int off = mi == 0 ? T.A0 : (mi == 1 ? T.A1 : (mi == 2 ? T.B0 : T.B1));
+          const int size = mi == 0 ? n0 * n0 : (mi == 1 ? n1 * n1 : (mi == 2 ? n0 * m0 : n1 * m1));
+          if (off >= 0 && e < size) smat[mi][e] = pool[off + e];
         }
         if (T.nb >= 0) {
-          if (B1) {
-            for (int m = 0; m < m1; ++m) {
-              const double w = B1[j * m1 + m];
-              gu += w * na[m * n0 + i];
-              gd += w * nbv[m * n0 + i];
-            }
-          } else {
-            gu = na[q];
-            gd = nbv[q];
+          // the neighbour's trace and normal derivative on its own face points
+          const int fod = (f & 1) ? 0 : FN - 1;
+          const double* D = R.D + (FN - 2) * 64 + fod * FN;
+          const int strd = pick(d, 1, FN0, FN0 * FN1);
+          const double* fu = u + cbase + foff;
+          for (int q = tid; q < m0 * m1; q += blockDim.x) {
+            const double* line = fu + face_node(d, 0, q % m0, q / m0, FN0, FN1);
+            double acc = 0.0;
+            for (int m = 0; m < FN; ++m) acc += D[m] * line[m * strd];
+            oa[q] = line[fod * strd];
+            ob[q] = frh * acc;
           }
         }
-        scu[f][q] += 0.5 * (gu - hu);
-        scp[f][q] += 0.5 * sgn * (hd + gd) - T.sigma * (hu - gu);
+        __syncthreads();
+        const double* A0 = T.A0 >= 0 ? smat[0] : nullptr;
+        const double* A1 = T.A1 >= 0 ? smat[1] : nullptr;
+        const double* B0 = T.B0 >= 0 ? smat[2] : nullptr;
+        const double* B1 = T.B1 >= 0 ? smat[3] : nullptr;
+        // along t0: own data [n1][n0] -> [n1][n0], neighbour data [m1][m0] -> [m1][n0]
+        for (int q = tid; q < n1 * n0; q += blockDim.x) {
+          const int j = q / n0, i = q - j * n0;
+          double a = 0.0, c = 0.0;
+          if (A0) {
+            for (int m = 0; m < n0; ++m) {
+              const double w = A0[i * n0 + m];
+              a += w * fa[j * n0 + m];
+              c += w * fb[j * n0 + m];
+            }
+          } else {
+            a = fa[q];
+            c = fb[q];
+          }
+          ma[q] = a;
+          mb[q] = c;
+        }
+        if (T.nb >= 0)
+          for (int q = tid; q < m1 * n0; q += blockDim.x) {
+            const int j = q / n0, i = q - j * n0;
+            double a = 0.0, c = 0.0;
+            if (B0) {
+              for (int m = 0; m < m0; ++m) {
+                const double w = B0[i * m0 + m];
+                a += w * oa[j * m0 + m];
+                c += w * ob[j * m0 + m];
+              }
+            } else {
+              a = oa[j * m0 + i];
+              c = ob[j * m0 + i];
+            }
+            na[q] = a;
+            nbv[q] = c;
+          }
+        __syncthreads();
+        // along t1, then the fluxes (a zero neighbour contributes nothing)
+        for (int q = tid; q < n1 * n0; q += blockDim.x) {
+          const int j = q / n0, i = q - j * n0;
+          double hu = 0.0, hd = 0.0, gu = 0.0, gd = 0.0;
+          if (A1) {
+            for (int m = 0; m < n1; ++m) {
+              const double w = A1[j * n1 + m];
+              hu += w * ma[m * n0 + i];
+              hd += w * mb[m * n0 + i];
+            }
+          } else {
+            hu = ma[q];
+            hd = mb[q];
+          }
+          if (T.nb >= 0) {
+            if (B1) {
+              for (int m = 0; m < m1; ++m) {
+                const double w = B1[j * m1 + m];
+                gu += w * na[m * n0 + i];
+                gd += w * nbv[m * n0 + i];
+              }
+            } else {
+              gu = na[q];
+              gd = nbv[q];
+            }
+          }
+          scu[f][q] += 0.5 * (gu - hu);
+          scp[f][q] += 0.5 * sgn * (hd + gd) - T.sigma * (hu - gu);
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   __syncthreads();
   // auxiliary variable (eq. dg_op_auxvars): v_d = D_d u + M^-1 ML n_d cu on
   // the faces normal to d, M^-1 ML = (2/h_d) / w_end
   for (int p = tid; p < n; p += blockDim.x) {
-    const int idx[3] = {p % N0, (p / N0) % N1, p / (N0 * N1)};
+    const int i = p % N0, j = (p / N0) % N1, k = p / (N0 * N1);
+#pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1;
-      if (idx[d] != ((f & 1) ? E.N[d] - 1 : 0)) continue;
-      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-      const int q = idx[t1] * E.N[t0] + idx[t0];
-      const double lift = E.rh[d] / R.w[(E.N[d] - 2) * 8];
+      const int Nd = pick(d, N0, N1, N2), id = pick(d, i, j, k);
+      if (id != ((f & 1) ? Nd - 1 : 0)) continue;
+      const int q = d == 0 ? k * N1 + j : (d == 1 ? k * N0 + i : j * N0 + i);
+      const double lift = E.rh[d] / R.w[(Nd - 2) * 8];
       sg[d][p] += lift * ((f & 1) ? 1.0 : -1.0) * scu[f][q];
     }
   }
   __syncthreads();
   // primal equation (eq. dg_op_primal): -M D_d v_d - ML ((n F_u)* - n_d v_d)
   for (int p = tid; p < n; p += blockDim.x) {
-    const int idx[3] = {p % N0, (p / N0) % N1, p / (N0 * N1)};
+    const int i = p % N0, j = (p / N0) % N1, k = p / (N0 * N1);
     double acc = 0.0;
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const int Nd = E.N[d];
-      const double* D = R.D + (Nd - 2) * 64 + idx[d] * Nd;
-      const int l0 = p - idx[d] * str[d];
+      const int Nd = pick(d, N0, N1, N2), id = pick(d, i, j, k), st = pick(d, 1, N0, N0 * N1);
+      const double* D = R.D + (Nd - 2) * 64 + id * Nd;
+      const int l0 = p - id * st;
       double a = 0.0;
-      for (int m = 0; m < Nd; ++m) a += D[m] * sg[d][l0 + m * str[d]];
+      for (int m = 0; m < Nd; ++m) a += D[m] * sg[d][l0 + m * st];
       acc += E.rh[d] * a;
     }
-    const double wx = R.w[(N0 - 2) * 8 + idx[0]], wy = R.w[(N1 - 2) * 8 + idx[1]],
-                 wz = R.w[(N2 - 2) * 8 + idx[2]];
-    const double wd[3] = {wx, wy, wz};
+    const double wx = R.w[(N0 - 2) * 8 + i], wy = R.w[(N1 - 2) * 8 + j], wz = R.w[(N2 - 2) * 8 + k];
     double Au = -E.jac * wx * wy * wz * acc;
+#pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1;
-      if (idx[d] != ((f & 1) ? E.N[d] - 1 : 0)) continue;
-      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-      const int q = idx[t1] * E.N[t0] + idx[t0];
-      const double ML = E.jac * E.rh[d] * wd[t0] * wd[t1];
+      const int Nd = pick(d, N0, N1, N2), id = pick(d, i, j, k);
+      if (id != ((f & 1) ? Nd - 1 : 0)) continue;
+      const int q = d == 0 ? k * N1 + j : (d == 1 ? k * N0 + i : j * N0 + i);
+      const double wt = d == 0 ? wy * wz : (d == 1 ? wx * wz : wx * wy);
+      const double ML = E.jac * E.rh[d] * wt;
       Au -= ML * (scp[f][q] - ((f & 1) ? 1.0 : -1.0) * sg[d][p]);
     }
     out[base + p] = RES ? b[base + p] - Au : Au;
