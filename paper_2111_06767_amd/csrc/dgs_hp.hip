@@ -16,6 +16,7 @@ namespace dgs {
 namespace {
 
 constexpr int kHpThreads = 256;
+constexpr int kNodesPerThread = kHpMaxNodes / kHpThreads;
 constexpr int kF = kHpMaxN * kHpMaxN;  // points of a face or mortar
 
 // Select one of three values by a dimension index without a runtime-indexed
@@ -50,11 +51,23 @@ __global__ void __launch_bounds__(kHpThreads)
   const int N0 = E.N[0], N1 = E.N[1], N2 = E.N[2];
   const int n = N0 * N1 * N2;
   const int tid = threadIdx.x;
-  for (int p = tid; p < n; p += blockDim.x) su[p] = u[base + p];
+  // this thread's nodes (at most kNodesPerThread) and their indices
+  int ni[kNodesPerThread], nj[kNodesPerThread], nk[kNodesPerThread];
+#pragma unroll
+  for (int r = 0; r < kNodesPerThread; ++r) {
+    const int p = tid + r * kHpThreads;
+    ni[r] = p % N0;
+    nj[r] = (p / N0) % N1;
+    nk[r] = p / (N0 * N1);
+    if (p < n) su[p] = u[base + p];
+  }
   __syncthreads();
   // unlifted derivatives D_d u = (2/h_d) D_xi u
-  for (int p = tid; p < n; p += blockDim.x) {
-    const int i = p % N0, j = (p / N0) % N1, k = p / (N0 * N1);
+#pragma unroll
+  for (int r = 0; r < kNodesPerThread; ++r) {
+    const int p = tid + r * kHpThreads;
+    if (p >= n) continue;
+    const int i = ni[r], j = nj[r], k = nk[r];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const int Nd = pick(d, N0, N1, N2), id = pick(d, i, j, k), st = pick(d, 1, N0, N0 * N1);
@@ -259,8 +272,11 @@ __global__ void __launch_bounds__(kHpThreads)
   __syncthreads();
   // auxiliary variable (eq. dg_op_auxvars): v_d = D_d u + M^-1 ML n_d cu on
   // the faces normal to d, M^-1 ML = (2/h_d) / w_end
-  for (int p = tid; p < n; p += blockDim.x) {
-    const int i = p % N0, j = (p / N0) % N1, k = p / (N0 * N1);
+#pragma unroll
+  for (int r = 0; r < kNodesPerThread; ++r) {
+    const int p = tid + r * kHpThreads;
+    if (p >= n) continue;
+    const int i = ni[r], j = nj[r], k = nk[r];
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1;
@@ -273,8 +289,11 @@ __global__ void __launch_bounds__(kHpThreads)
   }
   __syncthreads();
   // primal equation (eq. dg_op_primal): -M D_d v_d - ML ((n F_u)* - n_d v_d)
-  for (int p = tid; p < n; p += blockDim.x) {
-    const int i = p % N0, j = (p / N0) % N1, k = p / (N0 * N1);
+#pragma unroll
+  for (int r = 0; r < kNodesPerThread; ++r) {
+    const int p = tid + r * kHpThreads;
+    if (p >= n) continue;
+    const int i = ni[r], j = nj[r], k = nk[r];
     double acc = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
