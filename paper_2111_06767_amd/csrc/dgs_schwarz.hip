@@ -505,8 +505,10 @@ k_sub_arnoldi(int j, int kmax, const T* __restrict__ W, T* __restrict__ V, const
 // Hessenberg matrix Hs (column-major) by Givens rotations, stopping at a
 // breakdown column (zero subdiagonal); returns the number of columns used
 // (0 for beta = 0) and writes y.  One thread.
-__device__ int small_lsq(const double* Hs, int kmax, double beta, double* y) {
-  double h[9][8], g[9];
+// h and g: LDS scratch of the calling workgroup (runtime-indexed arrays in
+// private memory would live in scratch memory)
+__device__ int small_lsq(const double* Hs, int kmax, double beta, double* y, double (*h)[8],
+                         double* g) {
   int m = kmax;
   for (int jj = 0; jj < kmax; ++jj)
     if (Hs[jj * (kmax + 1) + jj + 1] == 0.0) {
@@ -546,12 +548,14 @@ k_sub_finish(int kmax, const T* __restrict__ Z, long long stride, const double* 
              const int* __restrict__ elem_class, const long long* __restrict__ elem_row,
              const ClassInfo* __restrict__ cls, int E) {
   __shared__ double y[16];
+  __shared__ double lsq_h[9][8], lsq_g[9];
   __shared__ int mm;
   const int e = blockIdx.x;
   if (e >= E) return;
   const int n = cls[elem_class[e] & kGroupMask].n;
   const long long row = elem_row[e];
-  if (threadIdx.x == 0) mm = small_lsq(H + (long long)e * (kmax + 1) * kmax, kmax, beta[e], y);
+  if (threadIdx.x == 0)
+    mm = small_lsq(H + (long long)e * (kmax + 1) * kmax, kmax, beta[e], y, lsq_h, lsq_g);
   __syncthreads();
   const int m = mm;
   for (int i = threadIdx.x; i < n; i += kSubThreads) {
@@ -694,12 +698,14 @@ k_sys_finish(int kmax, int nv, const T* __restrict__ Z, long long stride,
              const int* __restrict__ elem_class, const long long* __restrict__ elem_row,
              const ClassInfo* __restrict__ cls, int E) {
   __shared__ double y[16];
+  __shared__ double lsq_h[9][8], lsq_g[9];
   __shared__ int mm;
   const int e = blockIdx.x;
   if (e >= E) return;
   const int n = cls[elem_class[e] & kGroupMask].n;
   const long long row = elem_row[e];
-  if (threadIdx.x == 0) mm = small_lsq(H + (long long)e * (kmax + 1) * kmax, kmax, beta[e], y);
+  if (threadIdx.x == 0)
+    mm = small_lsq(H + (long long)e * (kmax + 1) * kmax, kmax, beta[e], y, lsq_h, lsq_g);
   __syncthreads();
   const int m = mm;
   const long long slot = (long long)nv * stride;
