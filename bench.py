@@ -517,14 +517,15 @@ def hp_workload():
     return levels, degrees
 
 
-def hp_leg(dg, steps=5, warmup=1, reps=50):
-    """FGMRES with the hp V-cycle on the hp workload (FP64), and the hp
-    operator apply timed with HIP events on the launch stream."""
+def hp_leg(dg, precision="fp64", steps=5, warmup=1, reps=50):
+    """FGMRES with the hp V-cycle on the hp workload, and the hp operator
+    apply timed with HIP events on the launch stream."""
     import torch
     import workloads as W
     levels, degrees = hp_workload()
     t0 = time.perf_counter()
-    prob = dg.HpProblem((0, 0, 0), (1, 1, 1), (2, 2, 2), levels, degrees, penalty=1.5, mg_levels=4)
+    prob = dg.HpProblem((0, 0, 0), (1, 1, 1), (2, 2, 2), levels, degrees, penalty=1.5, mg_levels=4,
+                        precision=precision)
     setup_s = time.perf_counter() - t0
     xyz = prob.node_coordinates()
     x, y, z = (xyz[d].cpu().numpy() for d in range(3))
@@ -835,8 +836,10 @@ def main():
     # -- hp-nonuniform mesh ---------------------------------------------------
     hp_out = None
     if not args.no_variants:
-        _log("hp-nonuniform mesh, 573440 DOFs")
-        hp_out = hp_leg(dg)
+        hp_out = {}
+        for prec in ("fp64", "mixed"):
+            _log(f"hp-nonuniform mesh, 573440 DOFs, {prec}")
+            hp_out[prec] = hp_leg(dg, prec)
 
     # -- applies --------------------------------------------------------------
     _log("operator applies")

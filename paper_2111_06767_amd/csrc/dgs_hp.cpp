@@ -367,7 +367,8 @@ struct HpLevel {
   long long* d_gidx = nullptr;
   long long* d_pull_ptr = nullptr;
   HpPull* d_pull = nullptr;
-  double *rs = nullptr, *du = nullptr;
+  bool f32 = false;  // FP32 subdomain rows, inverses and GEMM (mixed precision)
+  void *rs = nullptr, *du = nullptr;
   long long rs_total = 0;
   GemmTile* d_tiles = nullptr;
   int ntiles = 0, kparts = 1, variant = 2;
@@ -822,7 +823,7 @@ void build_schwarz(dgs_hp_problem* P, HpLevel& L, hipStream_t s) {
   // explicit inverses: A_S assembled column by column by the operator kernel
   // on copies of the class patch, then blocked Gauss-Jordan elimination
   // (no pivoting; the symmetric part of A_S dominates)
-  std::vector<double*> inv(nc, nullptr);
+  std::vector<void*> inv(nc, nullptr);
   std::vector<int> order(nc);
   for (int c = 0; c < nc; ++c) order[c] = c;
   std::sort(order.begin(), order.end(), [&](int a, int b) { return L.cls[a].n < L.cls[b].n; });
@@ -887,10 +888,12 @@ void build_schwarz(dgs_hp_problem* P, HpLevel& L, hipStream_t s) {
     for (int k = 0; k < nk; ++k) {
       const int c = group[k];
       const size_t nn = (size_t)L.cls[c].ld * L.cls[c].ld;
-      inv[c] = P->alloc<double>(nn);
-      HIP_OK(hipMemsetAsync(inv[c], 0, nn * sizeof(double), s));
+      const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+      inv[c] = P->alloc<char>(nn * es);
+      HIP_OK(hipMemsetAsync(inv[c], 0, nn * es, s));
       HIP_OK(launch_finish_inverse(batch + (size_t)k * n_pad * n_pad, n_pad, L.cls[c].n, L.cls[c].ld, 1.0,
-                                   inv[c], nullptr, s));
+                                   L.f32 ? nullptr : (double*)inv[c], L.f32 ? (float*)inv[c] : nullptr,
+                                   s));
     }
     HIP_OK(hipStreamSynchronize(s));
   }
@@ -903,10 +906,11 @@ void build_schwarz(dgs_hp_problem* P, HpLevel& L, hipStream_t s) {
   L.ntiles = (int)plan.tiles.size();
   L.d_tiles = P->alloc<GemmTile>(plan.tiles.size());
   upload(L.d_tiles, plan.tiles, s);
-  L.rs = P->alloc<double>(L.rs_total);
-  L.du = P->alloc<double>(L.rs_total * L.kparts);
-  HIP_OK(hipMemsetAsync(L.rs, 0, L.rs_total * sizeof(double), s));
-  HIP_OK(hipMemsetAsync(L.du, 0, L.rs_total * L.kparts * sizeof(double), s));
+  const size_t es = L.f32 ? sizeof(float) : sizeof(double);
+  L.rs = P->alloc<char>(L.rs_total * es);
+  L.du = P->alloc<char>(L.rs_total * L.kparts * es);
+  HIP_OK(hipMemsetAsync(L.rs, 0, L.rs_total * es, s));
+  HIP_OK(hipMemsetAsync(L.du, 0, L.rs_total * L.kparts * es, s));
   HIP_OK(hipStreamSynchronize(s));
 }
 
@@ -1008,10 +1012,10 @@ void hp_schwarz(dgs_hp_problem* P, int l, const double* b, double* u, int steps,
       hp_residual(P, l, u, b, L.r, s);
       r = L.r;
     }
-    HIP_OK(launch_hp_gather(r, L.rs, L.d_subs, (int)L.subs.size(), L.d_gidx, s));
-    HIP_OK(launch_subdomain_gemm(false, L.rs, L.du, L.rs_total, L.d_cls, L.d_tiles, L.ntiles, L.small, 0, s,
+    HIP_OK(launch_hp_gather(L.f32, r, L.rs, L.d_subs, (int)L.subs.size(), L.d_gidx, s));
+    HIP_OK(launch_subdomain_gemm(L.f32, L.rs, L.du, L.rs_total, L.d_cls, L.d_tiles, L.ntiles, L.small, 0, s,
                                  L.variant));
-    HIP_OK(launch_hp_scatter(u, L.du, L.kparts, L.rs_total, L.d_pull_ptr, L.d_pull, n, s));
+    HIP_OK(launch_hp_scatter(L.f32, u, L.du, L.kparts, L.rs_total, L.d_pull_ptr, L.d_pull, n, s));
   }
 }
 
@@ -1070,7 +1074,7 @@ int dgs_create_hp_problem(const dgs_domain* domain, const int blocks[3], const i
     dgs_options o;
     dgs_default_options(&o);
     if (opt) o = *opt;
-    if (o.precision != DGS_FP64) return fail(DGS_ERR_INVALID, "hp meshes solve in FP64 only");
+    if (o.precision != DGS_FP64 && o.precision != DGS_MIXED) return fail(DGS_ERR_INVALID, "unknown precision");
     if (o.cycle != 1 || o.additive != 0) return fail(DGS_ERR_INVALID, "hp meshes use the V-cycle");
     if (o.neumann_faces < 0 || o.neumann_faces >= 63)
       return fail(DGS_ERR_INVALID, "Neumann faces must leave one face Dirichlet");
@@ -1141,6 +1145,8 @@ int dgs_create_hp_problem(const dgs_domain* domain, const int blocks[3], const i
     upload(P->d_pool, P->pool.data, s);
     for (auto& L : P->lv) upload_level_mesh(P.get(), *L, s);
     HIP_OK(hipStreamSynchronize(s));
+    // mixed precision: FP32 subdomain solves on every level but the coarsest
+    for (size_t l = 0; l + 1 < P->lv.size(); ++l) P->lv[l]->f32 = o.precision == DGS_MIXED;
     for (auto& L : P->lv) build_schwarz(P.get(), *L, s);
     P->t_setup = now_s() - t0;
     *out = P.release();

@@ -83,11 +83,13 @@ hipError_t launch_hp_mass(const double* f, double* out, const HpElem* el, int E,
 // node coordinates: plo (3 per element, the lower corner) and h (3 per element)
 hipError_t launch_hp_coords(double* xyz, long long ndof, const HpElem* el, const double* plo_h,
                             int E, const HpRule& R, hipStream_t s);
-// RS[sub.rs + q] = r[gidx[sub.start + q]] for every subdomain
-hipError_t launch_hp_gather(const double* r, double* rs, const HpSub* subs, int nsub,
+// RS[sub.rs + q] = r[gidx[sub.start + q]] for every subdomain (RS in FP32
+// with f32, else FP64)
+hipError_t launch_hp_gather(bool f32, const double* r, void* rs, const HpSub* subs, int nsub,
                             const long long* gidx, hipStream_t s);
 // u[p] += sum over the pull entries of p of w * sum_parts DU[part * stride + pos]
-hipError_t launch_hp_scatter(double* u, const double* du, int parts, long long part_stride,
+// (DU in FP32 with f32), summed in FP64
+hipError_t launch_hp_scatter(bool f32, double* u, const void* du, int parts, long long part_stride,
                              const long long* ptr, const HpPull* pull, long long ndof,
                              hipStream_t s);
 // fine[e] += P_e coarse[parent]

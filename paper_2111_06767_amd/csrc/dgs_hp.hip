@@ -343,13 +343,15 @@ __global__ void k_hp_coords(double* __restrict__ xyz, long long ndof, const HpEl
   }
 }
 
-__global__ void k_hp_gather(const double* __restrict__ r, double* __restrict__ rs,
+template <typename TS>
+__global__ void k_hp_gather(const double* __restrict__ r, TS* __restrict__ rs,
                             const HpSub* __restrict__ subs, const long long* __restrict__ gidx) {
   const HpSub S = subs[blockIdx.x];
-  for (int q = threadIdx.x; q < S.n; q += blockDim.x) rs[S.rs + q] = r[gidx[S.start + q]];
+  for (int q = threadIdx.x; q < S.n; q += blockDim.x) rs[S.rs + q] = (TS)r[gidx[S.start + q]];
 }
 
-__global__ void k_hp_scatter(double* __restrict__ u, const double* __restrict__ du, int parts,
+template <typename TS>
+__global__ void k_hp_scatter(double* __restrict__ u, const TS* __restrict__ du, int parts,
                              long long stride, const long long* __restrict__ ptr,
                              const HpPull* __restrict__ pull, long long ndof) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -358,7 +360,7 @@ __global__ void k_hp_scatter(double* __restrict__ u, const double* __restrict__ 
   for (long long q = ptr[p]; q < ptr[p + 1]; ++q) {
     const HpPull e = pull[q];
     double v = 0.0;
-    for (int k = 0; k < parts; ++k) v += du[k * stride + e.pos];
+    for (int k = 0; k < parts; ++k) v += (double)du[k * stride + e.pos];
     acc += e.w * v;
   }
   u[p] += acc;
@@ -466,19 +468,27 @@ hipError_t launch_hp_coords(double* xyz, long long ndof, const HpElem* el, const
   return hipGetLastError();
 }
 
-hipError_t launch_hp_gather(const double* r, double* rs, const HpSub* subs, int nsub,
+hipError_t launch_hp_gather(bool f32, const double* r, void* rs, const HpSub* subs, int nsub,
                             const long long* gidx, hipStream_t s) {
   if (nsub <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hp_gather, dim3((unsigned)nsub), dim3(256), 0, s, r, rs, subs, gidx);
+  if (f32)
+    hipLaunchKernelGGL(k_hp_gather<float>, dim3((unsigned)nsub), dim3(256), 0, s, r, (float*)rs, subs, gidx);
+  else
+    hipLaunchKernelGGL(k_hp_gather<double>, dim3((unsigned)nsub), dim3(256), 0, s, r, (double*)rs, subs,
+                       gidx);
   return hipGetLastError();
 }
 
-hipError_t launch_hp_scatter(double* u, const double* du, int parts, long long part_stride,
+hipError_t launch_hp_scatter(bool f32, double* u, const void* du, int parts, long long part_stride,
                              const long long* ptr, const HpPull* pull, long long ndof,
                              hipStream_t s) {
   if (ndof <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_hp_scatter, dim3(nblk(ndof)), dim3(256), 0, s, u, du, parts, part_stride, ptr,
-                     pull, ndof);
+  if (f32)
+    hipLaunchKernelGGL(k_hp_scatter<float>, dim3(nblk(ndof)), dim3(256), 0, s, u, (const float*)du, parts,
+                       part_stride, ptr, pull, ndof);
+  else
+    hipLaunchKernelGGL(k_hp_scatter<double>, dim3(nblk(ndof)), dim3(256), 0, s, u, (const double*)du,
+                       parts, part_stride, ptr, pull, ndof);
   return hipGetLastError();
 }
 
