@@ -463,10 +463,11 @@ int dgs_system_solve(dgs_system* sys, const double* b, double* u, dgs_stats* sta
  * neighbours of a finer face included; each point's weights come from its
  * own element and sum to one.  Subdomains of equal structure share one
  * explicit inverse, built on the device.  Options: overlap, mg_levels,
- * pre_smooth, post_smooth, max_iter, rtol, restart, neumann_faces and
- * precision apply (DGS_MIXED: FP32 subdomain solves on every level but the
- * coarsest, as for box grids); cycle must be 1 and additive 0
- * (DGS_ERR_INVALID otherwise); the other fields are unused.  Workspaces are allocated with
+ * pre_smooth, post_smooth, max_iter, rtol, restart, neumann_faces,
+ * precision (DGS_MIXED: FP32 subdomain solves on every level but the
+ * coarsest, as for box grids) and use_graphs (the V-cycle captured at set-up
+ * and replayed) apply; cycle must be 1 and additive 0 (DGS_ERR_INVALID
+ * otherwise); the other fields are unused.  Workspaces are allocated with
  * hipMalloc.  The set-up synchronises the stream. */
 typedef struct dgs_hp_problem dgs_hp_problem;
 int dgs_create_hp_problem(const dgs_domain* domain, const int blocks[3], const int* block_levels,

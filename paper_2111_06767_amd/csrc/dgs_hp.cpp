@@ -719,6 +719,10 @@ struct dgs_hp_problem {
   std::vector<void*> allocations;
   KrylovSpace K;
   double t_setup = 0;
+  // the V-cycle captured at set-up (input in the finest level's b, output in
+  // its u) and the capture stream
+  hipGraphExec_t vgraph = nullptr;
+  hipStream_t cap_stream = nullptr;
 
   template <typename T>
   T* alloc(size_t count) {
@@ -728,6 +732,8 @@ struct dgs_hp_problem {
   }
   ~dgs_hp_problem() {
     std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+    if (vgraph) (void)hipGraphExecDestroy(vgraph);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocations) (void)hipFree(p);
     if (K.pinned) (void)hipHostFree(K.pinned);
   }
@@ -1038,6 +1044,41 @@ void hp_visit(dgs_hp_problem* P, int l, const double* b, double* u, hipStream_t 
   hp_schwarz(P, l, b, u, post, false, s);
 }
 
+// Capture one V-cycle from the finest level's b into its u as a hipGraph
+// (the launches of a cycle depend only on the problem, so the graph is
+// replayed by every preconditioner application).
+void hp_capture(dgs_hp_problem* P) {
+  std::lock_guard<std::recursive_mutex> lk(g_dev_mutex);
+  HpLevel& L0 = *P->lv[0];
+  if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    hp_visit(P, 0, L0.b, L0.u, P->cap_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(P->cap_stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  HIP_OK(hipStreamEndCapture(P->cap_stream, &graph));
+  const hipError_t e = hipGraphInstantiate(&P->vgraph, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIP_OK(e);
+}
+
+// z = one V-cycle applied to r: the captured cycle between two copies, or
+// the launches themselves without graphs
+void hp_precondition(dgs_hp_problem* P, const double* r, double* z, hipStream_t s) {
+  if (!P->vgraph) {
+    hp_visit(P, 0, r, z, s);
+    return;
+  }
+  HpLevel& L0 = *P->lv[0];
+  HIP_OK(launch_copy(L0.b, r, L0.mesh.ndof, s));
+  HIP_OK(hipGraphLaunch(P->vgraph, s));
+  HIP_OK(launch_copy(z, L0.u, L0.mesh.ndof, s));
+}
+
 void hp_ensure_krylov(dgs_hp_problem* P, int m) {
   if (P->K.m >= m) return;
   const long long n = P->lv[0]->mesh.ndof;
@@ -1148,6 +1189,7 @@ int dgs_create_hp_problem(const dgs_domain* domain, const int blocks[3], const i
     // mixed precision: FP32 subdomain solves on every level but the coarsest
     for (size_t l = 0; l + 1 < P->lv.size(); ++l) P->lv[l]->f32 = o.precision == DGS_MIXED;
     for (auto& L : P->lv) build_schwarz(P.get(), *L, s);
+    if (o.use_graphs) hp_capture(P.get());
     P->t_setup = now_s() - t0;
     *out = P.release();
     return DGS_OK;
@@ -1215,7 +1257,7 @@ int dgs_hp_smooth(dgs_hp_problem* prob, const double* b, double* u, int steps, v
 int dgs_hp_precondition(dgs_hp_problem* prob, const double* r, double* z, void* stream) {
   return guarded([&]() -> int {
     if (!prob || !r || !z) return fail(DGS_ERR_INVALID, "NULL argument");
-    hp_visit(prob, 0, r, z, as_stream(stream));
+    hp_precondition(prob, r, z, as_stream(stream));
     return DGS_OK;
   });
 }
@@ -1234,7 +1276,7 @@ int dgs_hp_solve(dgs_hp_problem* prob, const double* b, double* u, dgs_stats* st
         K, prob->opt.rtol, max_total,
         [&](const double* x, const double* bb, double* out) { hp_residual(prob, 0, x, bb, out, s); },
         [&](const double* z, double* w) { hp_apply(prob, 0, z, w, s); },
-        [&](const double* v, double* z) { hp_visit(prob, 0, v, z, s); }, b, u, s);
+        [&](const double* v, double* z) { hp_precondition(prob, v, z, s); }, b, u, s);
     if (stats) {
       stats->iterations = R.iterations;
       stats->newton_steps = 0;

@@ -109,6 +109,25 @@ def test_hp_solve_matches_oracle(precision):
     prob.close()
 
 
+def test_graph_replays_match_the_eager_cycle():
+    # the V-cycle captured at set-up, replayed several times with other work
+    # and synchronisations in between, equals the launches made one by one
+    import torch
+    announce("hp graph replays")
+    m, deg = _mesh("two_blocks", 12, 2, 4)
+    g = _gpu(m, deg, mg_levels=2)
+    e = _gpu(m, deg, mg_levels=2, use_graphs=0)
+    for seed in (66, 67, 68):
+        r = to_gpu(W.random_normal(seed, m.ndof))
+        zg = g.precondition(r)
+        g.apply(r)
+        torch.cuda.synchronize()
+        ze = e.precondition(r)
+        assert torch.equal(zg, ze)
+    g.close()
+    e.close()
+
+
 def test_equal_subdomains_share_an_inverse():
     # one cube of 4 x 4 x 4 elements of one degree: up to mirrors and axis
     # exchanges the subdomains are interior, face, edge or corner ones
