@@ -906,7 +906,8 @@ void build_schwarz(dgs_hp_problem* P, HpLevel& L, hipStream_t s) {
   for (int c = 0; c < nc; ++c) L.cls[c].inv = inv[c];
   L.d_cls = P->alloc<ClassInfo>(nc);
   upload(L.d_cls, L.cls, s);
-  GemmPlan plan = plan_subdomain_gemm(L.cls, L.variant);
+  // at most 4 split-K parts: the scatter sums every part of every entry
+  GemmPlan plan = plan_subdomain_gemm(L.cls, L.variant, 4);
   L.small = plan.small;
   L.kparts = plan.kparts;
   L.ntiles = (int)plan.tiles.size();

@@ -356,12 +356,20 @@ __global__ void k_hp_scatter(double* __restrict__ u, const TS* __restrict__ du, 
                              const HpPull* __restrict__ pull, long long ndof) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= ndof) return;
+  // entries four at a time, their loads issued together (the chain of
+  // dependent loads, not the bytes, bounds this kernel)
   double acc = 0.0;
-  for (long long q = ptr[p]; q < ptr[p + 1]; ++q) {
-    const HpPull e = pull[q];
-    double v = 0.0;
-    for (int k = 0; k < parts; ++k) v += (double)du[k * stride + e.pos];
-    acc += e.w * v;
+  const long long q1 = ptr[p + 1];
+  for (long long q0 = ptr[p]; q0 < q1; q0 += 4) {
+    HpPull e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = q0 + k < q1 ? pull[q0 + k] : HpPull{0, 0.0};
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int part = 0; part < parts; ++part)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] += (double)du[part * stride + e[k].pos];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc += e[k].w * v[k];
   }
   u[p] += acc;
 }
