@@ -476,6 +476,26 @@ def curved_leg(dg, precision, amplitude=0.1, steps=10, warmup=2):
                 converged=st["converged"])
 
 
+def wedge_leg(dg, precision, steps=5, warmup=1):
+    """One wedge of the spherical shell of Sec. IV.B (r from 2 to 10,
+    logarithmic radius, equiangular angles) as 16^3 elements of p = 7 on the
+    logical cube [-1, 1]^3: the curved operator, FGMRES preconditioned by the
+    cube's V-cycle, right-hand side M 1."""
+    import torch
+    import workloads as W
+    lower, upper = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    X = dg.points(lower, upper, C5["elements"], C5["p"])
+    xyz = torch.as_tensor(W.wedge_coordinates(X, 2.0, 10.0).reshape(-1)).cuda()
+    prob = dg.Problem(lower, upper, C5["elements"], C5["p"], penalty=1.5, mg_levels=C5["levels"],
+                      precision=precision)
+    prob.set_geometry(xyz)
+    b = prob.apply_mass(torch.ones(prob.ndof, dtype=torch.float64, device="cuda"))
+    u, st, times, total = time_solves(prob, b, steps, warmup)
+    prob.close()
+    return dict(ms=_ms(times), iterations=st["iterations"], rel_residual=st["rel_residual"],
+                converged=st["converged"])
+
+
 def time_curved_apply(dg, elements, p, amplitude=0.1, reps=50, warm=5):
     """Curved-element apply (the gradient and operator kernels), HIP events."""
     import torch
@@ -834,6 +854,9 @@ def main():
             curved[prec] = curved_leg(dg, prec)
         _log("curved apply 40^3 p=7")
         curved["apply_40^3_p7"] = time_curved_apply(dg, (40, 40, 40), 7)
+        for prec in ("fp64", "mixed"):
+            _log(f"wedge of a spherical shell, 16^3 p=7 {prec}")
+            curved[f"wedge_16^3_p7_{prec}"] = wedge_leg(dg, prec)
 
     # -- hp-nonuniform mesh ---------------------------------------------------
     hp_out = None

@@ -94,15 +94,18 @@ def _face_index(N, d, idx):
     return tuple(sl)
 
 
-def apply_operator(cm: CurvedMesh, u, C, diag=None):
+def apply_operator(cm: CurvedMesh, u, C, diag=None, dirichlet_values=None):
     """A u for nodal values u (E * N^3), with the optional pointwise term
-    diag * u (a massive diagonal, as the linearised operators use)."""
+    diag * u (a massive diagonal, as the linearised operators use).
+    ``dirichlet_values`` (nodal, read at Dirichlet boundary nodes) gives
+    inhomogeneous boundary data u_b (eq. bc); the default is u_b = 0."""
     box = cm.box
     N, E = box.N, box.E
     D = lgl.diff_matrix(N)
     w = lgl.weights(N)
     W3 = w[:, None, None] * w[None, :, None] * w[None, None, :]
     u = np.asarray(u, float).reshape(E, N, N, N)
+    ub = None if dirichlet_values is None else np.asarray(dirichlet_values, float).reshape(E, N, N, N)
     inv = cm.inv
     du = [_apply_1d(u, D, NODE_AXIS[j]) for j in range(3)]
     # unlifted physical gradient g_i = invJ^j_i D^xi_j u
@@ -131,7 +134,8 @@ def apply_operator(cm: CurvedMesh, u, C, diag=None):
                 elif 2 * d + (s > 0) in box.neumann:
                     u_ext, ndu_ext, nrm_ext = u_int, -ndu_int, nrm
                 else:
-                    u_ext, ndu_ext, nrm_ext = -u_int, ndu_int, nrm
+                    u_b = 0.0 if ub is None else ub[fi]
+                    u_ext, ndu_ext, nrm_ext = 2.0 * u_b - u_int, ndu_int, nrm
                 # auxiliary lift, eq. dg_op_auxvars: L (1/2 n (u_ext - u_int))
                 lift = (nrm / w[own]) * 0.5 * (u_ext - u_int)
                 for i in range(3):

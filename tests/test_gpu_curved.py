@@ -1,7 +1,7 @@
 """GPU parity of curved (isoparametric) elements against the oracle, through
-the C ABI: the operator and the mass on deformed grids (Sec. II with the
-element Jacobian), and FGMRES solves whose multigrid-Schwarz preconditioner
-keeps the box grid."""
+the C ABI: the operator and the mass on deformed grids and on a wedge of a
+spherical shell (Sec. II with the element Jacobian), and FGMRES solves whose
+multigrid-Schwarz preconditioner keeps the box grid."""
 import numpy as np
 import pytest
 
@@ -113,4 +113,29 @@ def test_geometry_checks():
     prob = _problem(big, mg_levels=1)
     with pytest.raises(dg.DgsError):
         prob.set_geometry(to_gpu(np.stack(big.node_coordinates()).reshape(-1)))
+    prob.close()
+
+
+def test_wedge_of_a_spherical_shell_matches_oracle():
+    # one wedge of the shell of Sec. IV.B, r from 2 to 10 (logarithmic): the
+    # operator on its node coordinates, and FGMRES preconditioned by the
+    # V-cycle of the logical cube
+    announce("curved wedge")
+    box = omesh.BoxMesh((-1, -1, -1), (1, 1, 1), (4, 4, 4), 3)
+    xyz = W.wedge_coordinates(np.stack(box.node_coordinates()), 2.0, 10.0)
+    cm = curved.CurvedMesh(box, xyz)
+    prob = _problem(box, mg_levels=2)
+    prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    u = W.random_normal(56, box.ndof)
+    ref = curved.apply_operator(cm, u, C)
+    assert rel_max(to_np(prob.apply(to_gpu(u))), ref) < 1e-12
+    A = lambda v: curved.apply_operator(cm, v, C)
+    b = curved.apply_mass(cm, np.ones(box.ndof)).reshape(-1)
+    x_ref, its_ref, _ = krylov.fgmres(A, b, precondition=multigrid.VCycle(box, C, levels=2), rtol=1e-10,
+                                      max_iter=100)
+    x, st = prob.solve(to_gpu(b))
+    x = to_np(x)
+    assert st["converged"] and abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
+    assert np.linalg.norm(b - A(x)) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
     prob.close()

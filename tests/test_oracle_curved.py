@@ -88,3 +88,26 @@ def test_operator_on_curved_elements():
         asym.append(np.abs(A - A.T).max() / np.abs(A).max())
         assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
     assert asym[0] < 1e-14 and 0 < asym[1] < asym[2] < 0.05, asym
+
+
+def test_wedge_of_a_spherical_shell():
+    # one wedge of the shell of Sec. IV.B (equiangular, logarithmic radius):
+    # the map is orientation preserving, its inner and outer faces lie on the
+    # spheres, and the discrete solution with the harmonic 1/r as Dirichlet
+    # data converges to 1/r exponentially in p
+    errs = []
+    for p in (2, 4, 6):
+        box = omesh.BoxMesh((-1, -1, -1), (1, 1, 1), (2, 2, 2), p)
+        xyz = W.wedge_coordinates(np.stack(box.node_coordinates()), 2.0, 10.0)
+        cm = curved.CurvedMesh(box, xyz)
+        r = np.sqrt(np.sum(cm.xyz ** 2, axis=0))
+        zeta = np.stack(box.node_coordinates())[2]
+        assert np.allclose(r[np.isclose(zeta, -1.0)], 2.0, rtol=1e-14)
+        assert np.allclose(r[np.isclose(zeta, 1.0)], 10.0, rtol=1e-14)
+        uex = (1.0 / r).reshape(-1)
+        A = curved.assemble(cm, C)
+        rhs = -curved.apply_operator(cm, np.zeros(box.ndof), C, dirichlet_values=uex)
+        us = np.linalg.solve(A, rhs)
+        errs.append(np.abs(us - uex).max() / np.abs(uex).max())
+    assert errs[0] > 10 * errs[1] > 100 * errs[2], errs
+    assert errs[-1] < 1e-5, errs

@@ -169,6 +169,21 @@ def system_coupling(seed: int, nvars: int, x, y, z, strength: float = 10.0) -> n
 # ---------------------------------------------------------------------------
 # Generic seeded fields and the request stream of the serving workload
 # ---------------------------------------------------------------------------
+def wedge_coordinates(X, r_in: float, r_out: float):
+    """Node coordinates of one wedge of a spherical shell (the blocks of the
+    shell domain of Sec. IV.B), from logical coordinates X = (xi, eta, zeta)
+    in [-1, 1]^3 (shape (3, ...)): equiangular in the two angles
+    (a = tan(pi xi / 4), b = tan(pi eta / 4)), logarithmic in the radius
+    r = r_in (r_out / r_in)^((zeta + 1) / 2), and x = r (a, b, 1) / |(a, b, 1)|,
+    the wedge around the +z axis."""
+    X = np.asarray(X, dtype=float)
+    a = np.tan(np.pi / 4.0 * X[0])
+    b = np.tan(np.pi / 4.0 * X[1])
+    r = r_in * (r_out / r_in) ** ((X[2] + 1.0) / 2.0)
+    s = r / np.sqrt(1.0 + a * a + b * b)
+    return np.stack([s * a, s * b, s])
+
+
 def random_normal(seed: int, n: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(n)
 
