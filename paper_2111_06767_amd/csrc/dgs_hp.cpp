@@ -1137,11 +1137,32 @@ int dgs_create_hp_problem(const dgs_domain* domain, const int blocks[3], const i
     std::vector<std::array<int, 3>> deg(E);
     for (long long e = 0; e < E; ++e)
       for (int d = 0; d < 3; ++d) deg[e][d] = degrees[3 * e + d];
+    if (E > (1LL << 22)) return fail(DGS_ERR_INVALID, "more than 2^22 hp elements");
     const double t0 = now_s();
     hipStream_t s = as_stream(stream);
     std::unique_ptr<dgs_hp_problem> P(new dgs_hp_problem());
     P->opt = o;
     P->penalty = penalty;
+    // host set-up first (meshes, hierarchy, mortars), so that an invalid mesh
+    // is refused before any device work
+    std::vector<std::vector<int>> parents;
+    std::vector<std::vector<std::array<int, 3>>> poss;
+    {
+      auto L0 = std::make_unique<HpLevel>();
+      L0->mesh = make_mesh(domain->lower, domain->upper, blocks, blev, deg, o.neumann_faces);
+      P->lv.push_back(std::move(L0));
+      const int cap = o.mg_levels > 0 ? o.mg_levels : 64;
+      while ((int)P->lv.size() < cap) {
+        auto C = std::make_unique<HpLevel>();
+        std::vector<int> parent;
+        std::vector<std::array<int, 3>> pos;
+        if (!coarsen(P->lv.back()->mesh, C->mesh, parent, pos)) break;
+        parents.push_back(parent);
+        poss.push_back(pos);
+        P->lv.push_back(std::move(C));
+      }
+    }
+    for (auto& L : P->lv) build_terms(L->mesh, penalty, P->pool, L->hel, L->terms);
     // the LGL rules for 2..8 points
     {
       std::vector<double> D(7 * 64, 0.0), w(7 * 8, 0.0), xi(7 * 8, 0.0);
@@ -1162,25 +1183,6 @@ int dgs_create_hp_problem(const dgs_domain* domain, const int blocks[3], const i
       P->rule = HpRule{dD, dw, dx};
       HIP_OK(hipStreamSynchronize(s));
     }
-    // levels: meshes and face terms first (they fill the matrix pool)
-    std::vector<std::vector<int>> parents;
-    std::vector<std::vector<std::array<int, 3>>> poss;
-    {
-      auto L0 = std::make_unique<HpLevel>();
-      L0->mesh = make_mesh(domain->lower, domain->upper, blocks, blev, deg, o.neumann_faces);
-      P->lv.push_back(std::move(L0));
-      const int cap = o.mg_levels > 0 ? o.mg_levels : 64;
-      while ((int)P->lv.size() < cap) {
-        auto C = std::make_unique<HpLevel>();
-        std::vector<int> parent;
-        std::vector<std::array<int, 3>> pos;
-        if (!coarsen(P->lv.back()->mesh, C->mesh, parent, pos)) break;
-        parents.push_back(parent);
-        poss.push_back(pos);
-        P->lv.push_back(std::move(C));
-      }
-    }
-    for (auto& L : P->lv) build_terms(L->mesh, penalty, P->pool, L->hel, L->terms);
     for (size_t l = 0; l + 1 < P->lv.size(); ++l)
       build_transfer(P.get(), *P->lv[l], *P->lv[l + 1], parents[l], poss[l], s);
     P->d_pool = P->alloc<double>(std::max<size_t>(1, P->pool.data.size()));

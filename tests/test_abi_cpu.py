@@ -64,3 +64,35 @@ def test_subdomain_solves_rejects_null_problem_without_gpu():
         pytest.skip("library not built")
     lib = m.load_library()
     assert lib.dgs_subdomain_solves(None, 0, 1, None, None) == m.DGS_ERR_INVALID
+
+
+def test_hp_mesh_validation_without_gpu():
+    # the hp set-up checks the mesh on the host before any device call
+    import ctypes
+    import paper_2111_06767_amd as m
+    if not os.path.exists(m.api.LIB_PATH):
+        pytest.skip("library not built")
+    lib = m.load_library()
+    dom = m.api.Domain((ctypes.c_double * 3)(0, 0, 0), (ctypes.c_double * 3)(2, 1, 1))
+    h = ctypes.c_void_p()
+
+    def create(blocks, levels, degrees, **opts):
+        o = m.default_options(**opts)
+        lv = [v for row in levels for v in row]
+        dg = [v for row in degrees for v in row]
+        return lib.dgs_create_hp_problem(ctypes.byref(dom), (ctypes.c_int * 3)(*blocks),
+                                         (ctypes.c_int * len(lv))(*lv), (ctypes.c_int * len(dg))(*dg),
+                                         len(dg) // 3, 1.5, ctypes.byref(o), None, ctypes.byref(h))
+
+    cases = [
+        ((2, 1, 1), [(2, 2, 2), (0, 0, 0)], [(2, 2, 2)] * 65, {}),  # levels 2 against 0 across a face
+        ((2, 1, 1), [(1, 1, 1), (0, 0, 0)], [(2, 2, 2)] * 8, {}),  # element count
+        ((2, 1, 1), [(0, 0, 0), (0, 0, 0)], [(8, 2, 2), (2, 2, 2)], {}),  # degree 8
+        ((2, 1, 1), [(0, 0, 0), (0, 0, 0)], [(0, 2, 2), (2, 2, 2)], {}),  # degree 0
+        ((2, 1, 1), [(0, 0, 0), (0, 0, 0)], [(2, 2, 2)] * 2, {"cycle": 2}),
+        ((2, 1, 1), [(0, 0, 0), (0, 0, 0)], [(2, 2, 2)] * 2, {"neumann_faces": 63}),
+    ]
+    for blocks, levels, degrees, opts in cases:
+        assert create(blocks, levels, degrees, **opts) == m.DGS_ERR_INVALID, (levels, degrees, opts)
+        assert lib.dgs_last_error().decode() != ""
+    assert "balanced" in (create(*cases[0][:3]) and lib.dgs_last_error().decode())
