@@ -160,6 +160,98 @@ def apply_operator(cm: CurvedMesh, u, C, diag=None, dirichlet_values=None):
     return Au.reshape(-1)
 
 
+def metric_source(cm: CurvedMesh, sqrtg):
+    """The contraction of the Christoffel symbols Gamma^i_ik = d_k ln sqrt(g)
+    of the background metric at every node, (3, E, N, N, N): the collocation
+    derivative of the interpolant of sqrt(g), divided by sqrt(g).
+
+    Reading: the paper does not say how derivatives of background fields are
+    formed; they are taken here like those of the solution."""
+    N = cm.box.N
+    D = lgl.diff_matrix(N)
+    sg = np.asarray(sqrtg, float).reshape(cm.det.shape)
+    ds = [_apply_1d(sg, D, NODE_AXIS[j]) for j in range(3)]
+    return np.stack([sum(cm.inv[..., j, i] * ds[j] for j in range(3)) / sg for i in range(3)])
+
+
+def apply_operator_metric(cm: CurvedMesh, u, C, ginv, sqrtg, dirichlet_values=None):
+    """A u on a curved background metric g_ij (Sec. II: sqrt(g) in eqs.
+    massmat, stiffmat and liftop), for the Poisson equation
+    -nabla_i (g^ij d_j u) = f in the flux form of the paper: F_v = u delta,
+    F_u^i = g^ij v_j, S_u = -Gamma^i_ik F_u^k.  ginv is g^ij at the nodes,
+    shape (3, 3, E, N, N, N); sqrtg the metric determinant's root.
+
+    Under LGL quadrature sqrt(g) J cancels between M and MD, so D_i is the
+    collocation derivative as for the flat metric; M = sqrt(g) J w_i w_j w_k.
+    On a face normal to xi^d the unit normal one-form is
+    n_i = s invJ^d_i / |invJ^d|_g with |a|_g = sqrt(g^ij a_i a_j), the
+    surface element sqrt(g) J |invJ^d|_g (so L = |invJ^d|_g / w_end), and h
+    in eq. penalty is 2 / |invJ^d|_g on each side.  The fluxes of eq. numflux
+    take n_i F_u^i of each side's own unlifted gradient."""
+    box = cm.box
+    N, E = box.N, box.E
+    D = lgl.diff_matrix(N)
+    w = lgl.weights(N)
+    W3 = w[:, None, None] * w[None, :, None] * w[None, None, :]
+    u = np.asarray(u, float).reshape(E, N, N, N)
+    ub = None if dirichlet_values is None else np.asarray(dirichlet_values, float).reshape(E, N, N, N)
+    G = np.asarray(ginv, float).reshape((3, 3) + cm.det.shape)
+    sg = np.asarray(sqrtg, float).reshape(cm.det.shape)
+    gam = metric_source(cm, sg)
+    inv = cm.inv
+    du = [_apply_1d(u, D, NODE_AXIS[j]) for j in range(3)]
+    g = [sum(inv[..., j, i] * du[j] for j in range(3)) for i in range(3)]  # d_i u
+    F = [sum(G[i, j] * g[j] for j in range(3)) for i in range(3)]  # g^ij d_j u
+
+    def gnorm(a, at):
+        # |a|_g at the face nodes `at`, a of shape (..., 3)
+        return np.sqrt(sum(G[i, j][at] * a[..., i] * a[..., j] for i in range(3) for j in range(3)))
+
+    faces = []
+    v = [gi.copy() for gi in g]
+    for e in range(E):
+        for d in range(3):
+            for s in (-1, +1):
+                own = 0 if s < 0 else N - 1
+                fi = (e,) + _face_index(N, d, own)
+                invd = inv[fi][..., d, :]
+                nrm = gnorm(invd, fi)
+                n = s * invd / nrm[..., None]
+                u_int = u[fi]
+                ndu_int = sum(n[..., i] * F[i][fi] for i in range(3))
+                nb = box.neighbor(e, d, s)
+                if nb is not None:
+                    fo = (nb,) + _face_index(N, d, N - 1 if s < 0 else 0)
+                    u_ext = u[fo]
+                    ndu_ext = sum(n[..., i] * F[i][fo] for i in range(3))
+                    nrm_ext = gnorm(inv[fo][..., d, :], fo)
+                elif 2 * d + (s > 0) in box.neumann:
+                    u_ext, ndu_ext, nrm_ext = u_int, -ndu_int, nrm
+                else:
+                    u_b = 0.0 if ub is None else ub[fi]
+                    u_ext, ndu_ext, nrm_ext = 2.0 * u_b - u_int, ndu_int, nrm
+                lift = (nrm / w[own]) * 0.5 * (u_ext - u_int)
+                for i in range(3):
+                    v[i][fi] += lift * n[..., i]
+                sigma = C * N ** 2 / np.minimum(2.0 / nrm, 2.0 / nrm_ext)
+                ML = sg[fi] * cm.det[fi] * nrm * W3[_face_index(N, d, own)] / w[own]
+                faces.append((fi, n, u_int, u_ext, ndu_int, ndu_ext, sigma, ML))
+
+    Fv = [sum(G[i, j] * v[j] for j in range(3)) for i in range(3)]  # F_u^i of the lifted v
+    div = np.zeros_like(u)
+    for i in range(3):
+        for j in range(3):
+            div += inv[..., j, i] * _apply_1d(Fv[i], D, NODE_AXIS[j])
+    M = sg * mass_diagonal(cm)
+    src = -sum(gam[i] * Fv[i] for i in range(3))  # S_u = -Gamma^i_ik F_u^k
+    Au = -M * div + M * src
+    for fi, n, u_int, u_ext, ndu_int, ndu_ext, sigma, ML in faces:
+        flux_star = 0.5 * (ndu_int + ndu_ext) - sigma * (u_int - u_ext)
+        flux_int = sum(n[..., i] * Fv[i][fi] for i in range(3))
+        Au[fi] -= ML * (flux_star - flux_int)
+    return Au.reshape(-1)
+
+
 def assemble(cm: CurvedMesh, C):
     n = cm.ndof
     A = np.empty((n, n))

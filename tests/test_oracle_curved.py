@@ -111,3 +111,54 @@ def test_wedge_of_a_spherical_shell():
         errs.append(np.abs(us - uex).max() / np.abs(uex).max())
     assert errs[0] > 10 * errs[1] > 100 * errs[2], errs
     assert errs[-1] < 1e-5, errs
+
+
+def _unit_metric(shape):
+    G = np.zeros((3, 3) + shape)
+    for i in range(3):
+        G[i, i] = 1.0
+    return G, np.ones(shape)
+
+
+def test_background_metric_flat_and_constant():
+    # with g = delta the metric operator is the flat one; a constant metric
+    # g = A^T A on the box is the flat operator on the box mapped by x = A X
+    box = omesh.BoxMesh((0, 0, 0), (1, 1.2, 0.9), (3, 2, 2), 3, neumann=(1,))
+    cm = curved.CurvedMesh(box, curved.deformed_box(box, 0.1))
+    u = W.random_normal(42, box.ndof)
+    G, sg = _unit_metric(cm.det.shape)
+    ref = curved.apply_operator(cm, u, C)
+    assert np.abs(curved.apply_operator_metric(cm, u, C, G, sg) - ref).max() <= 1e-14 * np.abs(ref).max()
+    A = np.array([[1.0, 0.3, 0.1], [0.0, 0.9, 0.2], [0.1, 0.0, 1.1]])
+    X = np.stack(box.node_coordinates())
+    ref = curved.apply_operator(curved.CurvedMesh(box, np.einsum("ij,j...->i...", A, X)), u, C)
+    gi = np.linalg.inv(A.T @ A)
+    G = np.broadcast_to(gi[:, :, None, None, None, None], (3, 3) + cm.det.shape)
+    got = curved.apply_operator_metric(curved.CurvedMesh(box, X), u, C, G,
+                                       np.full(cm.det.shape, np.linalg.det(A)))
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_background_metric_converges_to_a_harmonic_function():
+    # the pullback of the flat metric under a curved map: u = 1/|phi(X) - x0|
+    # solves the Laplace-Beltrami equation; with it as Dirichlet data the
+    # discrete solution converges exponentially in p, and dropping the
+    # Christoffel source (a constant sqrt(g)) leaves an O(1e-2) error
+    x0 = np.array([-0.5, -0.5, -0.5])
+
+    def solve(p, drop_source=False):
+        box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 2, 2), p)
+        X = np.stack(box.node_coordinates())
+        phi, ginv, sqrtg = W.pullback_metric(X, box.lower, box.upper, 0.15)
+        if drop_source:
+            sqrtg = np.ones_like(sqrtg)
+        cm = curved.CurvedMesh(box, X)
+        uex = (1.0 / np.sqrt(np.sum((phi - x0[:, None, None, None, None]) ** 2, axis=0))).reshape(-1)
+        n = box.ndof
+        A = np.stack([curved.apply_operator_metric(cm, e, C, ginv, sqrtg) for e in np.eye(n)], axis=1)
+        rhs = -curved.apply_operator_metric(cm, np.zeros(n), C, ginv, sqrtg, dirichlet_values=uex)
+        return np.abs(np.linalg.solve(A, rhs) - uex).max() / np.abs(uex).max()
+
+    errs = [solve(p) for p in (2, 3, 4)]
+    assert errs[0] > 5 * errs[1] > 25 * errs[2] and errs[2] < 5e-5, errs
+    assert solve(4, drop_source=True) > 100 * errs[2]

@@ -184,6 +184,34 @@ def wedge_coordinates(X, r_in: float, r_out: float):
     return np.stack([s * a, s * b, s])
 
 
+def pullback_metric(X, lower, upper, amplitude: float, direction=(1.0, 0.7, 0.4)):
+    """A curved background metric with known harmonic functions: the pullback
+    g = J^T J of the flat metric under the box map
+    phi(X) = X + a c prod_d sin(pi (X_d - lo_d) / L_d) (which keeps the box
+    boundary in place), with its analytic Jacobian J.  X: node coordinates,
+    shape (3, ...).  Returns phi(X) (3, ...), g^ij (3, 3, ...) and sqrt(det g)
+    (...); for h harmonic in flat space, u = h(phi(X)) solves the
+    Laplace-Beltrami equation of g."""
+    X = np.asarray(X, dtype=float)
+    lo = np.asarray(lower, float)
+    L = np.asarray(upper, float) - lo
+    c = np.asarray(direction, float)
+    ext = (slice(None),) + (None,) * (X.ndim - 1)
+    S = [np.sin(np.pi * (X[d] - lo[d]) / L[d]) for d in range(3)]
+    Co = [np.cos(np.pi * (X[d] - lo[d]) / L[d]) for d in range(3)]
+    bump = S[0] * S[1] * S[2]
+    dbump = [np.pi / L[0] * Co[0] * S[1] * S[2], np.pi / L[1] * S[0] * Co[1] * S[2],
+             np.pi / L[2] * S[0] * S[1] * Co[2]]
+    J = np.empty((3, 3) + X.shape[1:])
+    for i in range(3):
+        for j in range(3):
+            J[i, j] = (1.0 if i == j else 0.0) + amplitude * c[i] * dbump[j]
+    phi = X + amplitude * c[ext] * bump
+    g = np.einsum("ki...,kj...->...ij", J, J)
+    ginv = np.moveaxis(np.linalg.inv(g), (-2, -1), (0, 1))
+    return phi, ginv, np.sqrt(np.linalg.det(g))
+
+
 def random_normal(seed: int, n: int) -> np.ndarray:
     return np.random.default_rng(seed).standard_normal(n)
 
