@@ -476,6 +476,40 @@ def curved_leg(dg, precision, amplitude=0.1, steps=10, warmup=2):
                 converged=st["converged"])
 
 
+def metric_fields(xyz, cfg, amplitude):
+    """g^ij (6 fields xx, xy, xz, yy, yz, zz) and sqrt(g) of the pullback
+    metric of the box map with the given amplitude, at the node coordinates
+    xyz (a device tensor of 3 * ndof): device tensors of 6 * ndof and ndof."""
+    import torch
+    import workloads as W
+    X = xyz.view(3, -1).cpu().numpy()
+    _, G, sg = W.pullback_metric(X, cfg["lower"], cfg["upper"], amplitude)
+    six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
+    return torch.as_tensor(six).cuda(), torch.as_tensor(sg).cuda()
+
+
+def metric_leg(dg, precision, amplitude=0.1, metric_amplitude=0.15, steps=10, warmup=2):
+    """The 16^3 p=7 headline solve on a deformed grid and a curved background
+    metric (the pullback of the box map, amplitude 0.15, at the physical
+    nodes): the Laplace-Beltrami operator with sqrt(g) in M, MD and ML,
+    preconditioned by the box grid's flat V-cycle."""
+    import torch
+    import workloads as W
+    prob = dg.Problem(C5["lower"], C5["upper"], C5["elements"], C5["p"], penalty=1.5,
+                      mg_levels=C5["levels"], precision=precision)
+    xyz = deformed_coordinates(dg, C5, amplitude)
+    prob.set_geometry(xyz)
+    six, sg = metric_fields(xyz, C5, metric_amplitude)
+    prob.set_metric(six, sg)
+    x, y, z = (xyz.view(3, -1)[d].cpu().numpy() for d in range(3))
+    f = torch.as_tensor(W.fourier_source(W.fourier_modes(W.SEED_C5), x, y, z)).cuda()
+    b = prob.apply_mass(f)
+    u, st, times, total = time_solves(prob, b, steps, warmup)
+    prob.close()
+    return dict(ms=_ms(times), iterations=st["iterations"], rel_residual=st["rel_residual"],
+                converged=st["converged"])
+
+
 def wedge_leg(dg, precision, steps=5, warmup=1):
     """One wedge of the spherical shell of Sec. IV.B (r from 2 to 10,
     logarithmic radius, equiangular angles) as 16^3 elements of p = 7 on the
@@ -496,13 +530,18 @@ def wedge_leg(dg, precision, steps=5, warmup=1):
                 converged=st["converged"])
 
 
-def time_curved_apply(dg, elements, p, amplitude=0.1, reps=50, warm=5):
-    """Curved-element apply (the gradient and operator kernels), HIP events."""
+def time_curved_apply(dg, elements, p, amplitude=0.1, metric_amplitude=None, reps=50, warm=5):
+    """Curved-element apply (the gradient and operator kernels), HIP events;
+    with metric_amplitude on the pullback background metric."""
     import torch
     import workloads as W
     cfg = dict(lower=(0, 0, 0), upper=(1, 1, 1), elements=elements, p=p)
     prob = dg.Problem(cfg["lower"], cfg["upper"], elements, p, mg_levels=1)
-    prob.set_geometry(deformed_coordinates(dg, cfg, amplitude))
+    xyz = deformed_coordinates(dg, cfg, amplitude)
+    prob.set_geometry(xyz)
+    if metric_amplitude is not None:
+        prob.set_metric(*metric_fields(xyz, cfg, metric_amplitude))
+    del xyz
     u = torch.as_tensor(W.random_normal(W.SEED_APPLY, prob.ndof)).cuda()
     out = torch.empty_like(u)
     for _ in range(warm):
@@ -519,10 +558,12 @@ def time_curved_apply(dg, elements, p, amplitude=0.1, reps=50, warm=5):
     prob.close()
     del u, out
     torch.cuda.empty_cache()
-    # algorithmic: read u and the metric (9 inverse-Jacobian entries and the
-    # determinant), write A u: 96 B per DOF
+    # algorithmic: read u and the element metric (9 inverse-Jacobian entries
+    # and the determinant), write A u: 96 B per DOF; the background metric
+    # adds g^ij (6), sqrt(g) and d ln sqrt(g) (3): 176 B per DOF
+    bpd = 96 if metric_amplitude is None else 176
     return dict(elements=list(elements), p=p, ndof=n, ms_per_apply=ms, gdofs=n / (ms * 1e-3) / 1e9,
-                algorithmic_bytes_per_dof=96, achieved_gbs=96 * n / (ms * 1e-3) / 1e9)
+                algorithmic_bytes_per_dof=bpd, achieved_gbs=bpd * n / (ms * 1e-3) / 1e9)
 
 
 def hp_workload():
@@ -857,6 +898,11 @@ def main():
         for prec in ("fp64", "mixed"):
             _log(f"wedge of a spherical shell, 16^3 p=7 {prec}")
             curved[f"wedge_16^3_p7_{prec}"] = wedge_leg(dg, prec)
+        for prec in ("fp64", "mixed"):
+            _log(f"16^3 p=7 deformed grid on a background metric {prec}")
+            curved[f"metric_16^3_p7_{prec}"] = metric_leg(dg, prec)
+        _log("curved apply on a background metric 24^3 p=7")
+        curved["metric_apply_24^3_p7"] = time_curved_apply(dg, (24, 24, 24), 7, metric_amplitude=0.15)
 
     # -- hp-nonuniform mesh ---------------------------------------------------
     hp_out = None

@@ -266,6 +266,26 @@ int dgs_get_apply_shape(const dgs_problem* prob, int level, int* shape);
  * check). */
 int dgs_set_geometry(dgs_problem* prob, const double* xyz, void* stream);
 
+/* A curved background metric g_ij on the finest grid, Sec. II: the Poisson
+ * equation -nabla_i (g^ij d_j u) = f in the flux form F_u^i = g^ij v_j with
+ * the source S_u = -Gamma^i_ik F_u^k (Gamma^i_ik = d_k ln sqrt(g)), and
+ * sqrt(g) in eqs. massmat, stiffmat and liftop.  ginv (device, 6 * ndof
+ * doubles: the fields g^xx, g^xy, g^xz, g^yy, g^yz, g^zz, one after the
+ * other, canonical layout) and sqrtg (device, ndof doubles) are copied; the
+ * library forms d_k ln sqrt(g) as the collocation derivative of sqrt(g) on
+ * each element, divided by sqrt(g).  Unit normals and face measures are
+ * taken in the metric norm |a|_g = sqrt(g^ij a_i a_j), and the penalty's
+ * element size is 2 / |invJ^d|_g.  Without curved node coordinates
+ * (dgs_set_geometry) the box grid's own coordinates are set first.  Then
+ * dgs_apply_operator, dgs_apply_mass, dgs_solve and dgs_cg_solve use the
+ * metric operator; dgs_precondition and dgs_schwarz_smooth keep the box
+ * grid's flat cycle.  Both NULL returns to the flat metric (the curved
+ * elements stay); dgs_set_geometry with NULL also drops the metric.
+ * DGS_ERR_INVALID if only one of ginv and sqrtg is given, for p > 7, or if
+ * g^ij is not positive definite or sqrt(g) not positive and finite at some
+ * node (checked on the host, which synchronises the stream). */
+int dgs_set_metric(dgs_problem* prob, const double* ginv, const double* sqrtg, void* stream);
+
 /* Tile variant of the grouped subdomain-solve GEMM on multigrid level
  * `level` (Sec. III.D.2 subdomain solves; the variant changes the tiling and
  * the split of the K range, so results agree to rounding):

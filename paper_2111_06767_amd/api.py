@@ -37,7 +37,7 @@ EXPORTED = (
     "dgs_system_apply", "dgs_system_smooth", "dgs_system_precondition", "dgs_system_solve",
     "dgs_create_hp_problem", "dgs_destroy_hp_problem", "dgs_hp_num_dofs", "dgs_hp_num_levels",
     "dgs_hp_num_classes", "dgs_hp_node_coordinates", "dgs_hp_apply_operator", "dgs_hp_apply_mass",
-    "dgs_hp_smooth", "dgs_hp_precondition", "dgs_hp_solve",
+    "dgs_hp_smooth", "dgs_hp_precondition", "dgs_hp_solve", "dgs_set_metric",
 )
 
 
@@ -140,6 +140,7 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_set_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.c_int]
     lib.dgs_get_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.dgs_set_geometry.argtypes = [P, dp, P]
+    lib.dgs_set_metric.argtypes = [P, dp, dp, P]
     lib.dgs_create_system.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
                                       ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.c_int,
@@ -356,6 +357,19 @@ class Problem:
         of 3 * ndof: x, then y, then z); None returns to the box grid."""
         ptr = ctypes.c_void_p(None) if xyz is None else _ptr(xyz, 3 * self.ndof, "xyz")
         _check(self._lib.dgs_set_geometry(self._h, ptr, _stream(stream)))
+
+    def set_metric(self, ginv=None, sqrtg=None, stream=None):
+        """A curved background metric: g^ij as a device tensor of 6 * ndof (the
+        fields xx, xy, xz, yy, yz, zz) and sqrt(g) of ndof; both None return to
+        the flat metric."""
+        if (ginv is None) != (sqrtg is None):
+            raise ValueError("ginv and sqrtg are given together")
+        if ginv is None:
+            _check(self._lib.dgs_set_metric(self._h, ctypes.c_void_p(None), ctypes.c_void_p(None),
+                                            _stream(stream)))
+            return
+        _check(self._lib.dgs_set_metric(self._h, _ptr(ginv, 6 * self.ndof, "ginv"),
+                                        _ptr(sqrtg, self.ndof, "sqrtg"), _stream(stream)))
 
     def set_diagonal(self, d=None, stream=None):
         """Operator A + diag(d) for smoothing, preconditioning and solves (None: A)."""

@@ -1,0 +1,34 @@
+// Curved elements on a curved background metric g_ij (Sec. II: sqrt(g) in
+// eqs. massmat, stiffmat and liftop): the Poisson equation
+// -nabla_i (g^ij d_j u) = f in the paper's flux form, F_u^i = g^ij v_j and
+// the source S_u = -Gamma^i_ik F_u^k with Gamma^i_ik = d_k ln sqrt(g).
+#pragma once
+
+#include "dgs_internal.h"
+
+namespace dgs {
+
+// Per-node background fields of the finest level (device): g^ij as 6 fields
+// (xx, xy, xz, yy, yz, zz at f * nd), sqrt(g), and d_k ln sqrt(g) as 3 fields
+// (formed at set-up as the collocation derivative of sqrt(g), divided by it).
+struct CurvedMetric {
+  double* ginv = nullptr;
+  double* sqrtg = nullptr;
+  double* dlsg = nullptr;
+};
+
+// dlsg from sqrtg (the element metric of G)
+hipError_t launch_curved_metric_source(int N, const CurvedGeometry& G, CurvedMetric& Mt, long long E,
+                                       hipStream_t s);
+// A u (+ diag u; residual: b - (A u + diag u)) with the metric: normals and
+// face measures in the metric norm, F_u = g v in the divergence and the
+// fluxes, M = sqrt(g) J w w w (diag may be NULL)
+hipError_t launch_curved_apply_metric(int N, bool residual, const double* u, double* out,
+                                      const double* b, const double* diag, const CurvedGeometry& G,
+                                      const CurvedMetric& Mt,
+                                      const int* nbr, double C, int neumann, long long E, hipStream_t s);
+// b = M f with M = sqrt(g) det(J) w_i w_j w_k
+hipError_t launch_curved_mass_metric(int N, const double* f, double* out, const CurvedGeometry& G,
+                                     const CurvedMetric& Mt, long long E, hipStream_t s);
+
+}  // namespace dgs

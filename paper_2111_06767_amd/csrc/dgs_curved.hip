@@ -15,7 +15,7 @@
 // the geometry (invJ and det(J) from the coordinates, at set-up), the
 // physical gradient of u, and the operator, which reads the neighbours'
 // values and gradients at the shared face nodes.
-#include "dgs_internal.h"
+#include "dgs_curved.h"
 
 namespace dgs {
 namespace {
@@ -35,6 +35,12 @@ __device__ __forceinline__ double dxi(const double* f, const double* D, int d, i
     for (int m = 0; m < N; ++m) s += D[k * N + m] * f[(m * N + j) * N + i];
   }
   return s;
+}
+
+// |a|_g = sqrt(g^ab a_a a_b) with g^ab as (xx, xy, xz, yy, yz, zz)
+__device__ __forceinline__ double gnorm(const double G[6], double a0, double a1, double a2) {
+  return sqrt(G[0] * a0 * a0 + G[3] * a1 * a1 + G[5] * a2 * a2 +
+              2.0 * (G[1] * a0 * a1 + G[2] * a0 * a2 + G[4] * a1 * a2));
 }
 
 // invJ (9 fields, invJ^d_c at (3 d + c) * nd) and det(J) from the coordinates
@@ -109,14 +115,18 @@ k_curved_grad(const double* __restrict__ u, long long nd, const double* __restri
 // The operator: v = grad u + lifts of the auxiliary flux jumps (eq.
 // dg_op_auxvars), A u = -M D_c v_c - ML ((n F_u)* - n.v) (eq. dg_op_primal),
 // plus diag * u when diag is given.  RES: out = b - A u.
-template <int N, bool RES>
+// MET: on a curved background metric (the fields of CurvedMetric): normals
+// and face measures in the metric norm, F_u = g v, M = sqrt(g) J w w w and
+// the source -M Gamma^i_ik F_u^k.
+template <int N, bool RES, bool MET = false>
 __global__ void __launch_bounds__(N * N * N)
 k_curved_apply(const double* __restrict__ u, const double* __restrict__ grad,
                const double* __restrict__ inv, const double* __restrict__ det, long long nd,
                const double* __restrict__ Dg, const double* __restrict__ wg,
                const int* __restrict__ nbr, double C, int neumann,
                const double* __restrict__ diag, const double* __restrict__ b,
-               double* __restrict__ out) {
+               double* __restrict__ out, const double* __restrict__ ginv = nullptr,
+               const double* __restrict__ sqrtg = nullptr, const double* __restrict__ dlsg = nullptr) {
   constexpr int N3 = N * N * N;
   __shared__ double D[N * N];
   __shared__ double V[3][N3];
@@ -138,6 +148,15 @@ k_curved_apply(const double* __restrict__ u, const double* __restrict__ grad,
     v[c] = gr[c];
   }
   const double W3 = wg[ijk[0]] * wg[ijk[1]] * wg[ijk[2]];
+  // the metric g^ab (symmetric, 6 fields) and F of the unlifted gradient
+  double Gm[6] = {1.0, 0.0, 0.0, 1.0, 0.0, 1.0}, Fg[3] = {gr[0], gr[1], gr[2]};
+  if constexpr (MET) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) Gm[q] = ginv[q * nd + g];
+    Fg[0] = Gm[0] * gr[0] + Gm[1] * gr[1] + Gm[2] * gr[2];
+    Fg[1] = Gm[1] * gr[0] + Gm[3] * gr[1] + Gm[4] * gr[2];
+    Fg[2] = Gm[2] * gr[0] + Gm[4] * gr[1] + Gm[5] * gr[2];
+  }
   // the faces this node lies on (at most one per dimension): their normal,
   // exterior value, normal derivatives of both sides, penalty and ML
   double fn[3][3] = {}, fue[3] = {}, fndi[3] = {}, fnde[3] = {}, fsig[3] = {}, fml[3] = {};
@@ -148,11 +167,12 @@ k_curved_apply(const double* __restrict__ u, const double* __restrict__ grad,
     on[d] = idx == 0 || idx == N - 1;
     if (!on[d]) continue;
     const int s = idx == 0 ? -1 : 1;
-    const double nrm = sqrt(I[d][0] * I[d][0] + I[d][1] * I[d][1] + I[d][2] * I[d][2]);
+    const double nrm = MET ? gnorm(Gm, I[d][0], I[d][1], I[d][2])
+                           : sqrt(I[d][0] * I[d][0] + I[d][1] * I[d][1] + I[d][2] * I[d][2]);
     double n[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) n[c] = s * I[d][c] / nrm;
-    const double ndi = n[0] * gr[0] + n[1] * gr[1] + n[2] * gr[2];
+    const double ndi = n[0] * Fg[0] + n[1] * Fg[1] + n[2] * Fg[2];
     const int f = 2 * d + (s > 0 ? 1 : 0);
     const int nb = nbr[e * 6 + f];
     double uext, ndext, nrmext;
@@ -161,10 +181,21 @@ k_curved_apply(const double* __restrict__ u, const double* __restrict__ grad,
       m[d] = N - 1 - idx;
       const long long gm = (long long)nb * N3 + (m[2] * N + m[1]) * N + m[0];
       uext = u[gm];
-      ndext = n[0] * grad[gm] + n[1] * grad[nd + gm] + n[2] * grad[2 * nd + gm];
       const double a0 = inv[(3 * d) * nd + gm], a1 = inv[(3 * d + 1) * nd + gm],
                    a2 = inv[(3 * d + 2) * nd + gm];
-      nrmext = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+      const double e0 = grad[gm], e1 = grad[nd + gm], e2 = grad[2 * nd + gm];
+      if constexpr (MET) {
+        double Ge[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) Ge[q] = ginv[q * nd + gm];
+        ndext = n[0] * (Ge[0] * e0 + Ge[1] * e1 + Ge[2] * e2) +
+                n[1] * (Ge[1] * e0 + Ge[3] * e1 + Ge[4] * e2) +
+                n[2] * (Ge[2] * e0 + Ge[4] * e1 + Ge[5] * e2);
+        nrmext = gnorm(Ge, a0, a1, a2);
+      } else {
+        ndext = n[0] * e0 + n[1] * e1 + n[2] * e2;
+        nrmext = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+      }
     } else if ((neumann >> f) & 1) {
       uext = ue;  // homogeneous Neumann ghost (eq. bc)
       ndext = -ndi;
@@ -187,8 +218,17 @@ k_curved_apply(const double* __restrict__ u, const double* __restrict__ grad,
     fsig[d] = C * (double)(N * N) / fmin(2.0 / nrm, 2.0 / nrmext);
     fml[d] = dt * nrm * W3 / wg[idx];
   }
+  // F_u of the lifted v (v itself for the flat metric)
+  double F[3] = {v[0], v[1], v[2]};
+  double sg = 1.0;
+  if constexpr (MET) {
+    F[0] = Gm[0] * v[0] + Gm[1] * v[1] + Gm[2] * v[2];
+    F[1] = Gm[1] * v[0] + Gm[3] * v[1] + Gm[4] * v[2];
+    F[2] = Gm[2] * v[0] + Gm[4] * v[1] + Gm[5] * v[2];
+    sg = sqrtg[g];
+  }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) V[c][t] = v[c];
+  for (int c = 0; c < 3; ++c) V[c][t] = F[c];
   __syncthreads();
   // -M D_c v_c with D_c = invJ^d_c D^xi_d
   double div = 0.0;
@@ -196,16 +236,56 @@ k_curved_apply(const double* __restrict__ u, const double* __restrict__ grad,
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int d = 0; d < 3; ++d) div += I[d][c] * dxi<N>(V[c], D, d, ijk[0], ijk[1], ijk[2]);
-  double Au = -dt * W3 * div;
+  double Au = -sg * dt * W3 * div;
+  if constexpr (MET)  // + M S_u, S_u = -Gamma^i_ik F_u^k
+    Au -= sg * dt * W3 * (dlsg[g] * F[0] + dlsg[nd + g] * F[1] + dlsg[2 * nd + g] * F[2]);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (!on[d]) continue;
     const double flux_star = 0.5 * (fndi[d] + fnde[d]) - fsig[d] * (ue - fue[d]);
-    const double flux_int = fn[d][0] * v[0] + fn[d][1] * v[1] + fn[d][2] * v[2];
-    Au -= fml[d] * (flux_star - flux_int);
+    const double flux_int = fn[d][0] * F[0] + fn[d][1] * F[1] + fn[d][2] * F[2];
+    Au -= sg * fml[d] * (flux_star - flux_int);
   }
   if (diag) Au += diag[g] * ue;
   out[g] = RES ? b[g] - Au : Au;
+}
+
+// d_c ln sqrt(g) = (invJ^d_c D^xi_d sqrt(g)) / sqrt(g) (3 fields)
+template <int N>
+__global__ void __launch_bounds__(N * N * N)
+k_curved_metric_source(const double* __restrict__ sqrtg, long long nd, const double* __restrict__ Dg,
+                       const double* __restrict__ inv, double* __restrict__ dlsg) {
+  constexpr int N3 = N * N * N;
+  __shared__ double D[N * N];
+  __shared__ double S[N3];
+  const int t = threadIdx.x;
+  const long long g = (long long)blockIdx.x * N3 + t;
+  if (t < N * N) D[t] = Dg[t];
+  S[t] = sqrtg[g];
+  __syncthreads();
+  const int i = t % N, j = (t / N) % N, k = t / (N * N);
+  double ds[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) ds[d] = dxi<N>(S, D, d, i, j, k);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    double v = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) v += inv[(3 * d + c) * nd + g] * ds[d];
+    dlsg[c * nd + g] = v / S[t];
+  }
+}
+
+// b = M f = sqrt(g) det(J) w_i w_j w_k f
+template <int N>
+__global__ void __launch_bounds__(N * N * N)
+k_curved_mass_metric(const double* __restrict__ f, const double* __restrict__ det,
+                     const double* __restrict__ sqrtg, const double* __restrict__ wg,
+                     double* __restrict__ out) {
+  constexpr int N3 = N * N * N;
+  const int t = threadIdx.x;
+  const long long g = (long long)blockIdx.x * N3 + t;
+  out[g] = sqrtg[g] * det[g] * wg[t % N] * wg[(t / N) % N] * wg[t / (N * N)] * f[g];
 }
 
 // b = M f = det(J) w_i w_j w_k f
@@ -271,6 +351,51 @@ hipError_t launch_curved_mass(int N, const double* f, double* out, const CurvedG
 #define DGS_CALL(NN)                                                                              \
   hipLaunchKernelGGL(k_curved_mass<NN>, dim3((unsigned)E), dim3(NN * NN * NN), 0, s, f, G.det, G.w, \
                      out)
+  DGS_CURVED_SWITCH(N, DGS_CALL)
+#undef DGS_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_curved_metric_source(int N, const CurvedGeometry& G, CurvedMetric& Mt, long long E,
+                                       hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  const long long nd = E * N * N * N;
+#define DGS_CALL(NN)                                                                               \
+  hipLaunchKernelGGL(k_curved_metric_source<NN>, dim3((unsigned)E), dim3(NN * NN * NN), 0, s, Mt.sqrtg, \
+                     nd, G.D, G.inv, Mt.dlsg)
+  DGS_CURVED_SWITCH(N, DGS_CALL)
+#undef DGS_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_curved_apply_metric(int N, bool residual, const double* u, double* out,
+                                      const double* b, const double* diag, const CurvedGeometry& G,
+                                      const CurvedMetric& Mt,
+                                      const int* nbr, double C, int neumann, long long E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  const long long nd = E * N * N * N;
+#define DGS_CALL(NN)                                                                                  \
+  hipLaunchKernelGGL(k_curved_grad<NN>, dim3((unsigned)E), dim3(NN * NN * NN), 0, s, u, nd, G.D,       \
+                     G.inv, G.grad);                                                                  \
+  if (residual)                                                                                       \
+    hipLaunchKernelGGL((k_curved_apply<NN, true, true>), dim3((unsigned)E), dim3(NN * NN * NN), 0, s,  \
+                       u, G.grad, G.inv, G.det, nd, G.D, G.w, nbr, C, neumann, diag, b, out, Mt.ginv, \
+                       Mt.sqrtg, Mt.dlsg);                                                            \
+  else                                                                                                \
+    hipLaunchKernelGGL((k_curved_apply<NN, false, true>), dim3((unsigned)E), dim3(NN * NN * NN), 0, s, \
+                       u, G.grad, G.inv, G.det, nd, G.D, G.w, nbr, C, neumann, diag, b, out, Mt.ginv, \
+                       Mt.sqrtg, Mt.dlsg)
+  DGS_CURVED_SWITCH(N, DGS_CALL)
+#undef DGS_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_curved_mass_metric(int N, const double* f, double* out, const CurvedGeometry& G,
+                                     const CurvedMetric& Mt, long long E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+#define DGS_CALL(NN)                                                                                \
+  hipLaunchKernelGGL(k_curved_mass_metric<NN>, dim3((unsigned)E), dim3(NN * NN * NN), 0, s, f, G.det, \
+                     Mt.sqrtg, G.w, out)
   DGS_CURVED_SWITCH(N, DGS_CALL)
 #undef DGS_CALL
   return hipGetLastError();

@@ -31,6 +31,7 @@
 
 #include "../../include/dgsolve.h"
 #include "dgs_internal.h"
+#include "dgs_curved.h"
 #include "dgs_host.h"
 
 using namespace dgs;
@@ -197,6 +198,9 @@ struct dgs_problem {
   // preconditioner keeps the box hierarchy
   bool curved_on = false;
   CurvedGeometry curved;
+  // a curved background metric on those elements (dgs_set_metric)
+  bool metric_on = false;
+  CurvedMetric metric;
   // captured V-cycles (index: linearised operator or not) and the capture stream
   hipGraphExec_t vgraph[2] = {nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
@@ -1167,8 +1171,13 @@ void apply_fine(dgs_problem* P, const double* x, double* y, hipStream_t s,
   const bool diag = P->diag_active && L.d_diag != nullptr;
   if (P->curved_on) {
     if (xcopy) HIP_OK(launch_copy(xcopy, x, P->nd(0), s));
-    HIP_OK(launch_curved_apply(P->N, false, x, y, nullptr, diag ? L.d_diag : nullptr, P->curved,
-                               L.d_nbr, P->penalty, L.op.neumann, L.E, s));
+    if (P->metric_on)
+      HIP_OK(launch_curved_apply_metric(P->N, false, x, y, nullptr, diag ? L.d_diag : nullptr,
+                                        P->curved, P->metric, L.d_nbr, P->penalty, L.op.neumann,
+                                        L.E, s));
+    else
+      HIP_OK(launch_curved_apply(P->N, false, x, y, nullptr, diag ? L.d_diag : nullptr, P->curved,
+                                 L.d_nbr, P->penalty, L.op.neumann, L.E, s));
     return;
   }
   HIP_OK(launch_apply(P->N, diag ? kApplyDiag : kApply, x, y, nullptr, L.d_diag, nullptr, L.d_nbr,
@@ -1179,8 +1188,12 @@ void residual_fine(dgs_problem* P, const double* x, const double* b, double* r, 
   Level& L = P->levels[0];
   const bool diag = P->diag_active && L.d_diag != nullptr;
   if (P->curved_on) {
-    HIP_OK(launch_curved_apply(P->N, true, x, r, b, diag ? L.d_diag : nullptr, P->curved, L.d_nbr,
-                               P->penalty, L.op.neumann, L.E, s));
+    if (P->metric_on)
+      HIP_OK(launch_curved_apply_metric(P->N, true, x, r, b, diag ? L.d_diag : nullptr, P->curved,
+                                        P->metric, L.d_nbr, P->penalty, L.op.neumann, L.E, s));
+    else
+      HIP_OK(launch_curved_apply(P->N, true, x, r, b, diag ? L.d_diag : nullptr, P->curved,
+                                 L.d_nbr, P->penalty, L.op.neumann, L.E, s));
     return;
   }
   HIP_OK(launch_apply(P->N, diag ? kResidualDiag : kResidual, x, r, b, L.d_diag, nullptr, L.d_nbr,
@@ -2983,7 +2996,10 @@ int dgs_apply_mass(const dgs_problem* prob, const double* f, double* b, void* st
   return guarded([&]() -> int {
     if (!prob || !f || !b) return fail(DGS_ERR_INVALID, "NULL argument");
     const Level& L = prob->levels[0];
-    if (prob->curved_on)
+    if (prob->metric_on)
+      HIP_OK(launch_curved_mass_metric(prob->N, f, b, prob->curved, prob->metric, L.E,
+                                       as_stream(stream)));
+    else if (prob->curved_on)
       HIP_OK(launch_curved_mass(prob->N, f, b, prob->curved, L.E, as_stream(stream)));
     else
       HIP_OK(launch_mass(prob->N, f, b, L.E, L.h, prob->dt, as_stream(stream)));
@@ -2996,7 +3012,11 @@ int dgs_apply_operator(dgs_problem* prob, const double* u, double* Au, void* str
     if (!prob || !u || !Au) return fail(DGS_ERR_INVALID, "NULL argument");
     if (u == Au) return fail(DGS_ERR_INVALID, "u and Au must not overlap");
     Level& L = prob->levels[0];
-    if (prob->curved_on)
+    if (prob->metric_on)
+      HIP_OK(launch_curved_apply_metric(prob->N, false, u, Au, nullptr, nullptr, prob->curved,
+                                        prob->metric, L.d_nbr, prob->penalty, L.op.neumann, L.E,
+                                        as_stream(stream)));
+    else if (prob->curved_on)
       HIP_OK(launch_curved_apply(prob->N, false, u, Au, nullptr, nullptr, prob->curved, L.d_nbr,
                                  prob->penalty, L.op.neumann, L.E, as_stream(stream)));
     else
@@ -3012,6 +3032,7 @@ int dgs_set_geometry(dgs_problem* prob, const double* xyz, void* stream) {
     hipStream_t s = as_stream(stream);
     if (!xyz) {
       prob->curved_on = false;
+      prob->metric_on = false;
       return DGS_OK;
     }
     const int N = prob->N;
@@ -3036,9 +3057,63 @@ int dgs_set_geometry(dgs_problem* prob, const double* xyz, void* stream) {
     for (double v : det)
       if (!(v > 0.0) || !std::isfinite(v)) {
         prob->curved_on = false;
+        prob->metric_on = false;
         return fail(DGS_ERR_INVALID, "the node coordinates give a Jacobian determinant <= 0");
       }
     prob->curved_on = true;
+    if (prob->metric_on)  // the Christoffel contraction depends on the element maps
+      HIP_OK(launch_curved_metric_source(N, G, prob->metric, L.E, s));
+    return DGS_OK;
+  });
+}
+
+int dgs_set_metric(dgs_problem* prob, const double* ginv, const double* sqrtg, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (!ginv != !sqrtg) return fail(DGS_ERR_INVALID, "ginv and sqrtg are given together");
+    hipStream_t s = as_stream(stream);
+    if (!ginv) {
+      prob->metric_on = false;
+      return DGS_OK;
+    }
+    const int N = prob->N;
+    if (N > 8) return fail(DGS_ERR_INVALID, "curved elements are limited to p <= 7");
+    const Level& L = prob->levels[0];
+    const long long nd = prob->nd(0);
+    // the metric must be positive definite with a positive root of its
+    // determinant at every node: check on the host before any use
+    std::vector<double> hg((size_t)6 * nd), hs(nd);
+    HIP_OK(hipMemcpyAsync(hg.data(), ginv, sizeof(double) * 6 * nd, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(hs.data(), sqrtg, sizeof(double) * nd, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    for (long long i = 0; i < nd; ++i) {
+      const double a = hg[i], b = hg[nd + i], c = hg[2 * nd + i], d = hg[3 * nd + i],
+                   e = hg[4 * nd + i], f = hg[5 * nd + i];
+      const double m2 = a * d - b * b;
+      const double m3 = a * (d * f - e * e) - b * (b * f - e * c) + c * (b * e - d * c);
+      if (!(a > 0.0) || !(m2 > 0.0) || !(m3 > 0.0) || !std::isfinite(m3))
+        return fail(DGS_ERR_INVALID, "g^ij is not positive definite at every node");
+      if (!(hs[i] > 0.0) || !std::isfinite(hs[i]))
+        return fail(DGS_ERR_INVALID, "sqrt(g) must be positive and finite at every node");
+    }
+    if (!prob->curved_on) {  // the box grid's own coordinates as the element maps
+      double* xyz = prob->alloc<double>((size_t)3 * nd);
+      HIP_OK(launch_coords(N, xyz, L.n, prob->dom.lower, L.h, prob->dt, s));
+      const int rc = dgs_set_geometry(prob, xyz, stream);
+      HIP_OK(hipStreamSynchronize(s));
+      prob->release(xyz);
+      if (rc != DGS_OK) return rc;
+    }
+    CurvedMetric& Mt = prob->metric;
+    if (!Mt.ginv) {
+      Mt.ginv = prob->alloc<double>((size_t)6 * nd);
+      Mt.sqrtg = prob->alloc<double>(nd);
+      Mt.dlsg = prob->alloc<double>((size_t)3 * nd);
+    }
+    HIP_OK(hipMemcpyAsync(Mt.ginv, ginv, sizeof(double) * 6 * nd, hipMemcpyDeviceToDevice, s));
+    HIP_OK(hipMemcpyAsync(Mt.sqrtg, sqrtg, sizeof(double) * nd, hipMemcpyDeviceToDevice, s));
+    HIP_OK(launch_curved_metric_source(N, prob->curved, Mt, L.E, s));
+    prob->metric_on = true;
     return DGS_OK;
   });
 }

@@ -139,3 +139,97 @@ def test_wedge_of_a_spherical_shell_matches_oracle():
     assert np.linalg.norm(b - A(x)) <= 1e-10 * np.linalg.norm(b)
     assert np.linalg.norm(x - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
     prob.close()
+
+
+def _metric(cm, box, amp):
+    """g^ij (as the 6 fields xx, xy, xz, yy, yz, zz) and sqrt(g) of a pullback
+    metric at the physical node coordinates, for the oracle and the library."""
+    _, G, sg = W.pullback_metric(cm.xyz, box.lower, box.upper, amp)
+    six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
+    return G, sg, six
+
+
+@pytest.mark.parametrize("elements,p,neumann,geom,amp", [((3, 2, 2), 3, (), 0.1, 0.15),
+                                                         ((2, 3, 2), 5, (1, 4), 0.0, 0.2),
+                                                         ((2, 2, 2), 7, (0,), 0.05, 0.1),
+                                                         ((4, 1, 2), 2, (), 0.12, 0.12)])
+def test_metric_apply_matches_oracle(elements, p, neumann, geom, amp):
+    # the Laplace-Beltrami operator of a curved background metric (sqrt(g) in
+    # M, MD and ML of Sec. II) on curved elements or on the box grid
+    announce(f"metric apply elements={elements} p={p} neumann={neumann} geometry={geom} metric={amp}")
+    box = omesh.BoxMesh((0, 0, 0), (1.0, 1.1, 0.9), elements, p, neumann=neumann)
+    xyz = curved.deformed_box(box, geom)
+    cm = curved.CurvedMesh(box, xyz)
+    G, sg, six = _metric(cm, box, amp)
+    prob = _problem(box, mg_levels=1)
+    if geom:
+        prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    prob.set_metric(to_gpu(six), to_gpu(sg.reshape(-1)))  # box coordinates when geom == 0
+    u = W.random_normal(57 + p, box.ndof)
+    ref = curved.apply_operator_metric(cm, u, C, G, sg)
+    got = to_np(prob.apply(to_gpu(u)))
+    assert rel_max(got, ref) < 1e-12, rel_max(got, ref)
+    f = W.random_uniform(58, box.ndof)
+    ref_m = (sg.reshape(-1) * curved.apply_mass(cm, f).reshape(-1))
+    assert rel_max(to_np(prob.apply_mass(to_gpu(f))), ref_m) < 1e-14
+    # dropping the metric gives the flat operator of the same elements back
+    prob.set_metric(None, None)
+    assert rel_max(to_np(prob.apply(to_gpu(u))), curved.apply_operator(cm, u, C)) < 1e-12
+    prob.close()
+
+
+def test_metric_solve_matches_oracle():
+    # FGMRES on the metric operator with the flat box V-cycle, on the GPU and
+    # in the oracle; then the geometry reset drops the metric too
+    announce("metric solve")
+    box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (4, 4, 2), 3)
+    xyz = curved.deformed_box(box, 0.08)
+    cm = curved.CurvedMesh(box, xyz)
+    G, sg, six = _metric(cm, box, 0.15)
+    X = cm.xyz
+    f = np.sin(np.pi * X[0]) * np.sin(np.pi * X[1]) * np.sin(np.pi * X[2])
+    b = (sg * curved.apply_mass(cm, f)).reshape(-1)
+    A = lambda v: curved.apply_operator_metric(cm, v, C, G, sg)
+    x_ref, its_ref, _ = krylov.fgmres(A, b, precondition=multigrid.VCycle(box, C, levels=2),
+                                      rtol=1e-10, max_iter=100)
+    prob = _problem(box, mg_levels=2)
+    prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    prob.set_metric(to_gpu(six), to_gpu(sg.reshape(-1)))
+    u, st = prob.solve(to_gpu(b))
+    u = to_np(u)
+    assert st["converged"] and st["rel_residual"] <= 1e-10
+    assert abs(st["iterations"] - its_ref) <= 1, (st["iterations"], its_ref)
+    assert np.linalg.norm(b - A(u)) <= 1e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(u - x_ref) <= 1e-9 * np.linalg.norm(x_ref)
+    prob.set_geometry(None)
+    v = W.random_normal(59, box.ndof)
+    ref = curved.apply_operator(curved.CurvedMesh(box, np.stack(box.node_coordinates())), v, C)
+    assert rel_max(to_np(prob.apply(to_gpu(v))), ref) < 1e-12
+    prob.close()
+
+
+def test_metric_checks():
+    import paper_2111_06767_amd as dg
+    announce("metric checks")
+    box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 1, 1), 2)
+    prob = _problem(box, mg_levels=1)
+    u = to_gpu(W.random_normal(60, box.ndof))
+    flat = to_np(prob.apply(u))
+    n = box.ndof
+    good = np.concatenate([np.ones(n), np.zeros(n), np.zeros(n), np.ones(n), np.zeros(n), np.ones(n)])
+    indefinite = good.copy()
+    indefinite[n + 3] = 1.5  # g^xy > sqrt(g^xx g^yy) at one node
+    with pytest.raises(dg.DgsError):
+        prob.set_metric(to_gpu(indefinite), to_gpu(np.ones(n)))
+    bad_root = np.ones(n)
+    bad_root[7] = 0.0
+    with pytest.raises(dg.DgsError):
+        prob.set_metric(to_gpu(good), to_gpu(bad_root))
+    with pytest.raises(ValueError):
+        prob.set_metric(to_gpu(good), None)
+    # refused metrics leave the operator as it was
+    assert np.array_equal(to_np(prob.apply(u)), flat)
+    # the unit metric on the box coordinates is the box operator
+    prob.set_metric(to_gpu(good), to_gpu(np.ones(n)))
+    assert rel_max(to_np(prob.apply(u)), flat) < 1e-13
+    prob.close()
