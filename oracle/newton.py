@@ -11,6 +11,13 @@ Laplace(u) + beta (alpha (1+u) + 1)^-7 = 0 in flux form -Laplace(u) + S_u = 0
 has S_u(u) = -beta (alpha (1+u) + 1)^-7 and dS_u/du = 7 alpha beta
 (alpha (1+u) + 1)^-8.
 
+Power-law sources on curved elements (newton_solve_powers): S(u) =
+sum_t c_t(x) u^(k_t), the form one XCTS equation (eq. xcts) takes when the
+other variables are held fixed, with Dirichlet data through the ghost state
+of eq. bc; pinned by the Kerr-Schild lapse equation on a wedge (exponential
+convergence to the analytic lapse), by Newton with dense linear solves, and
+by the one-step solve of an affine source.
+
 Readings:
 * f(u) = 1/2 ||F(u)||^2; the predicted decrease is that of the linear model,
   so the initial slope is -||F(u)||^2; sufficient decrease
@@ -25,6 +32,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from . import curved
 from .mesh import BoxMesh
 from .operator import apply_operator, mass_diagonal
 from .krylov import fgmres
@@ -111,3 +119,88 @@ def newton_solve(mesh: BoxMesh, C, alpha, beta, b=None, u0=None, newton_rtol=1e-
         hist.append(np.linalg.norm(Fu) / norm0)
     return u.reshape(-1), dict(steps=steps, history=hist, linear_iterations=linear_its,
                                backtracks=backtracks)
+
+
+def power_source(coefs, powers, u):
+    """S(u) = sum_t c_t u^(k_t) and dS/du, for integer powers k_t."""
+    S = np.zeros_like(u)
+    dS = np.zeros_like(u)
+    for c, k in zip(coefs, powers):
+        S += c * u ** float(k)
+        if k != 0:
+            dS += c * k * u ** float(k - 1)
+    return S, dS
+
+
+def newton_solve_powers(cm, C, coefs, powers, ginv=None, sqrtg=None, dirichlet=None, b=None,
+                        u0=None, newton_rtol=1e-10, linear_rtol=1e-4, max_newton=20, levels=2,
+                        overlap=2, pre=3, post=3, subdomain_iters=3, sufficient_decrease=1e-4,
+                        max_backtracks=10, max_linear_iter=200, dense=False):
+    """Newton-Raphson on curved elements for F(u) = A(u; u_b) + M S(u) - b with
+    the pointwise source S(u) = sum_t c_t u^(k_t) (Sec. III.A; on a
+    background metric when ginv and sqrtg are given, Sec. II).  A(u; u_b) is
+    the curved operator with the Dirichlet data u_b (nodal, read at boundary
+    nodes; None: homogeneous); M its diagonal mass.  Each linearisation
+    A + diag(M S'(u)) is solved by FGMRES preconditioned by the box grid's
+    V-cycle on A_box + diag(M S'(u)) (or, with dense=True, by a dense solve),
+    then the step length is backtracked as in newton_solve.  u0: initial guess
+    (ones if None).  Returns (u, info)."""
+    box = cm.box
+    n = box.ndof
+    coefs = [np.asarray(c, float).reshape(-1) for c in np.asarray(coefs, float).reshape(len(powers), -1)]
+    if ginv is None:
+        Mdiag = curved.mass_diagonal(cm).reshape(-1)
+
+        def A(v, ub=None):
+            return curved.apply_operator(cm, v, C, dirichlet_values=ub)
+    else:
+        Mdiag = (np.asarray(sqrtg, float).reshape(cm.det.shape) * curved.mass_diagonal(cm)).reshape(-1)
+
+        def A(v, ub=None):
+            return curved.apply_operator_metric(cm, v, C, ginv, sqrtg, dirichlet_values=ub)
+    ub = None if dirichlet is None else np.asarray(dirichlet, float).reshape(-1)
+    b = np.zeros(n) if b is None else np.asarray(b, float).reshape(-1)
+    u = np.ones(n) if u0 is None else np.asarray(u0, float).reshape(-1).copy()
+
+    def F(v):
+        return A(v, ub) + Mdiag * power_source(coefs, powers, v)[0] - b
+
+    Fu = F(u)
+    norm0 = np.linalg.norm(Fu)
+    hist = [1.0]
+    linear_its = []
+    steps = backtracks = 0
+    for _ in range(max_newton):
+        nrm = np.linalg.norm(Fu)
+        if nrm <= newton_rtol * norm0 or nrm == 0.0:
+            break
+        d = Mdiag * power_source(coefs, powers, u)[1]
+
+        def J(x):
+            return A(x) + d * x
+
+        if dense:
+            Jm = np.stack([J(e) for e in np.eye(n)], axis=1)
+            du = np.linalg.solve(Jm, -Fu)
+            linear_its.append(0)
+        else:
+            V = VCycle(box, C, levels=levels, overlap=overlap, pre=pre, post=post, diag=d,
+                       subdomain_iters=subdomain_iters)
+            du, its, _ = fgmres(J, -Fu, precondition=V, rtol=linear_rtol, max_iter=max_linear_iter)
+            linear_its.append(its)
+        f0 = 0.5 * nrm ** 2
+        slope = -nrm ** 2
+        lam, lam_prev, f_prev = 1.0, None, None
+        for bt in range(max_backtracks + 1):
+            Ft = F(u + lam * du)
+            ft = 0.5 * np.linalg.norm(Ft) ** 2
+            if ft <= f0 + sufficient_decrease * lam * slope or bt == max_backtracks:
+                break
+            new = backtrack(f0, slope, lam, ft, lam_prev, f_prev, first=(bt == 0))
+            lam_prev, f_prev, lam = lam, ft, new
+            backtracks += 1
+        u = u + lam * du
+        Fu = Ft
+        steps += 1
+        hist.append(np.linalg.norm(Fu) / norm0)
+    return u, dict(steps=steps, history=hist, linear_iterations=linear_its, backtracks=backtracks)

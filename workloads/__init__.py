@@ -184,6 +184,49 @@ def wedge_coordinates(X, r_in: float, r_out: float):
     return np.stack([s * a, s * b, s])
 
 
+def kerr_schild_lapse(xyz, mass: float = 1.0):
+    """The lapse equation of the XCTS system (eq. xcts_lapse) on the
+    Kerr-Schild background of a Schwarzschild black hole (eq. kerrschild_bg),
+    with the conformal factor psi = 1 and the shift held at its Kerr-Schild
+    value (eq. kerrschild_shift), at the node coordinates xyz (3, ...).
+
+    With H = M/r, l = x/r: g_ij = delta_ij + 2H l_i l_j, so g^ij = delta^ij -
+    alpha^2 2H l^i l^j and sqrt(g) = (1 + 2H)^(1/2); the Kerr-Schild lapse
+    alpha = (1 + 2H)^(-1/2) and extrinsic curvature
+    K_ij = (2 M alpha / r^2)(delta_ij - (2 + H) l_i l_j) (tangential
+    eigenvalue a = 2 M alpha / r^2, radial -a alpha^2 (1 + H) of K^i_j), so
+    K_ij K^ij = 2 a^2 + a^2 alpha^4 (1 + H)^2 and K = 2 M alpha^3 / r^2 (1 + 3H).
+    With psi = 1, u_ij = 0, no matter: (L beta)^ij = 2 alpha A^ij (A the
+    trace-free part of K), R = K_ij K^ij - K^2 (Hamiltonian constraint), and
+    for the unknown Phi = alpha psi the lapse equation reads
+      Laplace_g Phi = c_-1 / Phi + c_1 Phi + c_0,
+      c_-1 = 7/8 alpha^2 A_ij A^ij,  c_1 = 5/12 K^2 + R / 8,
+      c_0 = beta^i d_i K = 2H alpha^2 dK/dr.
+    Its exact solution is Phi = alpha.  Returns g^ij (3, 3, ...), sqrt(g),
+    alpha, the coefficients (3, ...) and their powers (-1, 1, 0)."""
+    x = np.asarray(xyz, dtype=float)
+    M = float(mass)
+    r = np.sqrt((x * x).sum(axis=0))
+    lv = x / r
+    H = M / r
+    alpha = 1.0 / np.sqrt(1.0 + 2.0 * H)
+    ginv = (np.eye(3).reshape((3, 3) + (1,) * r.ndim) -
+            (2.0 * H * alpha ** 2) * lv[:, None] * lv[None, :])
+    sqrtg = np.sqrt(1.0 + 2.0 * H)
+    a = 2.0 * M * alpha / r ** 2
+    kr = -a * alpha ** 2 * (1.0 + H)
+    KK = 2.0 * a * a + kr * kr
+    K = 2.0 * a + kr
+    AA = KK - K * K / 3.0
+    R = KK - K * K
+    dalpha = alpha ** 3 * M / r ** 2
+    dK = 2.0 * M * ((3.0 * alpha ** 2 * dalpha / r ** 2 - 2.0 * alpha ** 3 / r ** 3) * (1.0 + 3.0 * H)
+                    - 3.0 * M * alpha ** 3 / r ** 4)
+    coefs = np.stack([7.0 / 8.0 * alpha ** 2 * AA, 5.0 / 12.0 * K * K + R / 8.0,
+                      2.0 * H * alpha ** 2 * dK])
+    return ginv, sqrtg, alpha, coefs, (-1, 1, 0)
+
+
 def pullback_metric(X, lower, upper, amplitude: float, direction=(1.0, 0.7, 0.4)):
     """A curved background metric with known harmonic functions: the pullback
     g = J^T J of the flat metric under the box map
