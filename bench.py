@@ -510,6 +510,44 @@ def metric_leg(dg, precision, amplitude=0.1, metric_amplitude=0.15, steps=10, wa
                 converged=st["converged"])
 
 
+def lapse_leg(dg, precision, steps=3, warmup=1):
+    """The lapse equation of the XCTS system on the Kerr-Schild background
+    (psi = 1, shift fixed at its Kerr-Schild value) on one wedge of the shell
+    (r from 2M to 10M) as 16^3 elements of p = 7: Newton with the power-law
+    source c_-1/Phi + c_1 Phi + c_0 on the metric operator, Dirichlet data
+    from the analytic lapse, flat initial guess Phi = 1, linear solves to
+    1e-4 by FGMRES with the cube's V-cycle on the linearised operator."""
+    import torch
+    import workloads as W
+    lower, upper = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    X = dg.points(lower, upper, C5["elements"], C5["p"])
+    xyz = W.wedge_coordinates(X, 2.0, 10.0)
+    G, sg, alpha, coefs, powers = W.kerr_schild_lapse(xyz)
+    six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
+    prob = dg.Problem(lower, upper, C5["elements"], C5["p"], penalty=1.5, mg_levels=C5["levels"],
+                      precision=precision, subdomain_iters=3)
+    prob.set_geometry(torch.as_tensor(xyz.reshape(-1)).cuda())
+    prob.set_metric(torch.as_tensor(six).cuda(), torch.as_tensor(sg.reshape(-1)).cuda())
+    cf = torch.as_tensor(coefs.reshape(-1)).cuda()
+    ub = torch.as_tensor(alpha.reshape(-1)).cuda()
+    u = torch.empty(prob.ndof, dtype=torch.float64, device="cuda")
+    times, st = [], None
+    for i in range(warmup + steps):
+        u.fill_(1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = prob.newton_solve_powers(cf, powers, dirichlet=ub, u=u, newton_rtol=1e-10,
+                                         linear_rtol=1e-4)
+        torch.cuda.synchronize()
+        if i >= warmup:
+            times.append(time.perf_counter() - t0)
+    err = float(np.abs(u.cpu().numpy() - alpha.reshape(-1)).max())
+    prob.close()
+    return dict(ms=_ms(times), newton_steps=st["newton_steps"], linear_iterations=st["iterations"],
+                rel_residual=st["rel_residual"], converged=st["converged"],
+                max_error_vs_analytic_lapse=err)
+
+
 def wedge_leg(dg, precision, steps=5, warmup=1):
     """One wedge of the spherical shell of Sec. IV.B (r from 2 to 10,
     logarithmic radius, equiangular angles) as 16^3 elements of p = 7 on the
@@ -901,6 +939,9 @@ def main():
         for prec in ("fp64", "mixed"):
             _log(f"16^3 p=7 deformed grid on a background metric {prec}")
             curved[f"metric_16^3_p7_{prec}"] = metric_leg(dg, prec)
+        for prec in ("fp64", "mixed"):
+            _log(f"Kerr-Schild lapse equation on a wedge, 16^3 p=7 {prec}")
+            curved[f"kerr_schild_lapse_16^3_p7_{prec}"] = lapse_leg(dg, prec)
         _log("curved apply on a background metric 24^3 p=7")
         curved["metric_apply_24^3_p7"] = time_curved_apply(dg, (24, 24, 24), 7, metric_amplitude=0.15)
 

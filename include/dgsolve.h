@@ -220,6 +220,31 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
                      double* u, double newton_rtol, double linear_rtol, int max_newton,
                      dgs_stats* stats, void* stream);
 
+/* Solve a nonlinear equation with a pointwise power-law source on curved
+ * elements (Sec. III.A, eq. linearized): the DG residual
+ *   F(u) = A(u; u_b) + M S(u) - b,  S(u) = sum_t c_t(x) u^(k_t),
+ * with A the curved operator (on the background metric when dgs_set_metric
+ * gave one), M its diagonal mass, and u_b the Dirichlet data (`dirichlet`,
+ * device, ndof values read at the Dirichlet boundary nodes through the
+ * ghost u_ext = 2 u_b - u_int of eq. bc; NULL = homogeneous).  The XCTS
+ * equations (eq. xcts) take this form for one variable when the others are
+ * held fixed, e.g. the lapse equation with S(Phi) = c_-1 / Phi + c_1 Phi +
+ * c_0.  powers: host, nterms integers in [-12, 12]; coef: device, nterms
+ * fields of ndof values (term t at t * ndof); b: device or NULL (zero).
+ * Newton-Raphson with the backtracking line search of dgs_newton_solve;
+ * each linearisation A + diag(M S'(u)) is solved to linear_rtol by FGMRES
+ * preconditioned by the box grid's multigrid-Schwarz cycle on
+ * A_box + diag(M S'(u)).  u holds the initial guess on entry (it must keep
+ * u != 0 where negative powers appear) and the solution on exit; converged
+ * when ||F(u)|| <= newton_rtol ||F(u0)||.  Needs curved elements
+ * (dgs_set_geometry, or dgs_set_metric, which sets the box coordinates);
+ * DGS_ERR_INVALID otherwise, for nterms outside [1, 8] or a power outside
+ * [-12, 12]; DGS_ERR_NONFINITE when a residual is not finite (u = 0 under
+ * a negative power).  Synchronises the stream once per Krylov iteration. */
+int dgs_newton_solve_powers(dgs_problem* prob, int nterms, const int* powers, const double* coef,
+                            const double* dirichlet, const double* b, double* u, double newton_rtol,
+                            double linear_rtol, int max_newton, dgs_stats* stats, void* stream);
+
 /* The subdomain solves of one Schwarz sweep alone (Sec. III.D.2, III.E.2):
  * du_S = s A_S^-1 r_S for every subdomain of multigrid level `level`
  * (0 = finest), one grouped GEMM launch on the matrix cores, repeated `reps`

@@ -37,7 +37,7 @@ EXPORTED = (
     "dgs_system_apply", "dgs_system_smooth", "dgs_system_precondition", "dgs_system_solve",
     "dgs_create_hp_problem", "dgs_destroy_hp_problem", "dgs_hp_num_dofs", "dgs_hp_num_levels",
     "dgs_hp_num_classes", "dgs_hp_node_coordinates", "dgs_hp_apply_operator", "dgs_hp_apply_mass",
-    "dgs_hp_smooth", "dgs_hp_precondition", "dgs_hp_solve", "dgs_set_metric",
+    "dgs_hp_smooth", "dgs_hp_precondition", "dgs_hp_solve", "dgs_set_metric", "dgs_newton_solve_powers",
 )
 
 
@@ -141,6 +141,9 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_get_gemm_variant.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.dgs_set_geometry.argtypes = [P, dp, P]
     lib.dgs_set_metric.argtypes = [P, dp, dp, P]
+    lib.dgs_newton_solve_powers.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            ctypes.POINTER(Stats), P]
     lib.dgs_create_system.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
                                       ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int), ctypes.c_int,
@@ -419,6 +422,27 @@ class Problem:
             self._h, _ptr(alpha, self.ndof, "alpha"), _ptr(beta, self.ndof, "beta"),
             _ptr(b, self.ndof, "b"), _ptr(u, self.ndof, "u"), float(newton_rtol), float(linear_rtol),
             int(max_newton), ctypes.byref(st), _stream(stream)), allow_not_converged=True)
+        return u, _stats_dict(st, hist, code)
+
+    def newton_solve_powers(self, coef, powers, dirichlet=None, b=None, u=None, newton_rtol=1e-10,
+                            linear_rtol=1e-4, max_newton=20, history=256, stream=None):
+        """Newton on curved elements for A(u; u_b) + M S(u) = b with the source
+        S(u) = sum_t coef_t u^powers_t: coef a device tensor of len(powers) * ndof,
+        dirichlet the boundary data (None: homogeneous), u the initial guess
+        (ones if None).  Returns (u, stats dict)."""
+        import torch
+        if u is None:
+            u = torch.ones(self.ndof, dtype=torch.float64, device="cuda")
+        k = len(powers)
+        pw = (ctypes.c_int * max(1, k))(*[int(x) for x in powers])
+        null = ctypes.c_void_p(None)
+        st, hist = _make_stats(history)
+        code = _check(self._lib.dgs_newton_solve_powers(
+            self._h, k, pw, _ptr(coef, k * self.ndof, "coef"),
+            null if dirichlet is None else _ptr(dirichlet, self.ndof, "dirichlet"),
+            null if b is None else _ptr(b, self.ndof, "b"), _ptr(u, self.ndof, "u"),
+            float(newton_rtol), float(linear_rtol), int(max_newton), ctypes.byref(st), _stream(stream)),
+            allow_not_converged=True)
         return u, _stats_dict(st, hist, code)
 
 

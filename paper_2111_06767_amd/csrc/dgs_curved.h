@@ -17,6 +17,18 @@ struct CurvedMetric {
   double* dlsg = nullptr;
 };
 
+// A pointwise source S(u) = sum_t c_t(x) u^(k_t) with integer powers
+// (Sec. III.A: the nonlinear sources of eq. linearized; the XCTS sources of
+// eq. xcts are of this form once the other variables are fixed).  coef:
+// device, nterms fields of n values.
+constexpr int kMaxPowerTerms = 8;
+constexpr int kMaxPower = 12;
+struct PowerSource {
+  int nterms = 0;
+  int power[kMaxPowerTerms] = {};
+  const double* coef = nullptr;
+};
+
 // dlsg from sqrtg (the element metric of G)
 hipError_t launch_curved_metric_source(int N, const CurvedGeometry& G, CurvedMetric& Mt, long long E,
                                        hipStream_t s);
@@ -27,6 +39,16 @@ hipError_t launch_curved_apply_metric(int N, bool residual, const double* u, dou
                                       const double* b, const double* diag, const CurvedGeometry& G,
                                       const CurvedMetric& Mt,
                                       const int* nbr, double C, int neumann, long long E, hipStream_t s);
+// out = A u with Dirichlet data bvals (device, read at the Dirichlet boundary
+// nodes; the ghost u_ext = 2 u_b - u_int of eq. bc), on the background metric
+// when Mt is given
+hipError_t launch_curved_apply_bc(int N, const double* u, double* out, const double* bvals,
+                                  const CurvedGeometry& G, const CurvedMetric* Mt, const int* nbr,
+                                  double C, int neumann, long long E, hipStream_t s);
+// F += m S(u) - b (F may be NULL; b may be NULL) and d = m dS/du (d may be
+// NULL), m the diagonal mass
+hipError_t launch_power_source(const PowerSource& ps, const double* u, const double* mdiag,
+                               const double* b, double* F, double* d, long long n, hipStream_t s);
 // b = M f with M = sqrt(g) det(J) w_i w_j w_k
 hipError_t launch_curved_mass_metric(int N, const double* f, double* out, const CurvedGeometry& G,
                                      const CurvedMetric& Mt, long long E, hipStream_t s);

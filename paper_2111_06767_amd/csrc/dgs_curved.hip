@@ -17,6 +17,8 @@
 // values and gradients at the shared face nodes.
 #include "dgs_curved.h"
 
+#include <algorithm>
+
 namespace dgs {
 namespace {
 
@@ -115,6 +117,8 @@ k_curved_grad(const double* __restrict__ u, long long nd, const double* __restri
 // The operator: v = grad u + lifts of the auxiliary flux jumps (eq.
 // dg_op_auxvars), A u = -M D_c v_c - ML ((n F_u)* - n.v) (eq. dg_op_primal),
 // plus diag * u when diag is given.  RES: out = b - A u.
+// bvals (optional): Dirichlet data at the boundary nodes (otherwise the
+// homogeneous ghost).
 // MET: on a curved background metric (the fields of CurvedMetric): normals
 // and face measures in the metric norm, F_u = g v, M = sqrt(g) J w w w and
 // the source -M Gamma^i_ik F_u^k.
@@ -126,7 +130,8 @@ k_curved_apply(const double* __restrict__ u, const double* __restrict__ grad,
                const int* __restrict__ nbr, double C, int neumann,
                const double* __restrict__ diag, const double* __restrict__ b,
                double* __restrict__ out, const double* __restrict__ ginv = nullptr,
-               const double* __restrict__ sqrtg = nullptr, const double* __restrict__ dlsg = nullptr) {
+               const double* __restrict__ sqrtg = nullptr, const double* __restrict__ dlsg = nullptr,
+               const double* __restrict__ bvals = nullptr) {
   constexpr int N3 = N * N * N;
   __shared__ double D[N * N];
   __shared__ double V[3][N3];
@@ -201,7 +206,8 @@ k_curved_apply(const double* __restrict__ u, const double* __restrict__ grad,
       ndext = -ndi;
       nrmext = nrm;
     } else {
-      uext = -ue;  // homogeneous Dirichlet ghost (eq. bc)
+      // Dirichlet ghost (eq. bc): u_ext = 2 u_b - u_int, homogeneous without data
+      uext = bvals ? 2.0 * bvals[g] - ue : -ue;
       ndext = ndi;
       nrmext = nrm;
     }
@@ -288,6 +294,35 @@ k_curved_mass_metric(const double* __restrict__ f, const double* __restrict__ de
   out[g] = sqrtg[g] * det[g] * wg[t % N] * wg[(t / N) % N] * wg[t / (N * N)] * f[g];
 }
 
+// u^k for an integer power k (|k| <= kMaxPower): repeated products, a
+// reciprocal for negative powers
+__device__ __forceinline__ double ipow(double u, int k) {
+  double r = 1.0;
+  const int m = k < 0 ? -k : k;
+  for (int q = 0; q < m; ++q) r *= u;
+  return k < 0 ? 1.0 / r : r;
+}
+
+// F = F + m S(u) - b and d = m dS/du(u), S(u) = sum_t c_t u^(k_t) (either
+// output may be NULL; b may be NULL)
+__global__ void k_power_source(PowerSource ps, const double* __restrict__ u,
+                               const double* __restrict__ mdiag, const double* __restrict__ b,
+                               double* __restrict__ F, double* __restrict__ d, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double ui = u[i], m = mdiag[i];
+    double S = 0.0, dS = 0.0;
+    for (int t = 0; t < ps.nterms; ++t) {
+      const double c = ps.coef[t * n + i];
+      const int k = ps.power[t];
+      S += c * ipow(ui, k);
+      if (k != 0) dS += c * (double)k * ipow(ui, k - 1);
+    }
+    if (F) F[i] = F[i] + m * S - (b ? b[i] : 0.0);
+    if (d) d[i] = m * dS;
+  }
+}
+
 // b = M f = det(J) w_i w_j w_k f
 template <int N>
 __global__ void __launch_bounds__(N * N * N)
@@ -353,6 +388,35 @@ hipError_t launch_curved_mass(int N, const double* f, double* out, const CurvedG
                      out)
   DGS_CURVED_SWITCH(N, DGS_CALL)
 #undef DGS_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_curved_apply_bc(int N, const double* u, double* out, const double* bvals,
+                                  const CurvedGeometry& G, const CurvedMetric* Mt, const int* nbr,
+                                  double C, int neumann, long long E, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  const long long nd = E * N * N * N;
+#define DGS_CALL(NN)                                                                                  \
+  hipLaunchKernelGGL(k_curved_grad<NN>, dim3((unsigned)E), dim3(NN * NN * NN), 0, s, u, nd, G.D,       \
+                     G.inv, G.grad);                                                                  \
+  if (Mt)                                                                                             \
+    hipLaunchKernelGGL((k_curved_apply<NN, false, true>), dim3((unsigned)E), dim3(NN * NN * NN), 0, s, \
+                       u, G.grad, G.inv, G.det, nd, G.D, G.w, nbr, C, neumann, nullptr, nullptr, out,  \
+                       Mt->ginv, Mt->sqrtg, Mt->dlsg, bvals);                                         \
+  else                                                                                                \
+    hipLaunchKernelGGL((k_curved_apply<NN, false, false>), dim3((unsigned)E), dim3(NN * NN * NN), 0, s, \
+                       u, G.grad, G.inv, G.det, nd, G.D, G.w, nbr, C, neumann, nullptr, nullptr, out,  \
+                       nullptr, nullptr, nullptr, bvals)
+  DGS_CURVED_SWITCH(N, DGS_CALL)
+#undef DGS_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_power_source(const PowerSource& ps, const double* u, const double* mdiag,
+                               const double* b, double* F, double* d, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_power_source, dim3(blocks), dim3(256), 0, s, ps, u, mdiag, b, F, d, n);
   return hipGetLastError();
 }
 

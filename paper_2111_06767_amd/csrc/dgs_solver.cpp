@@ -190,6 +190,9 @@ struct dgs_problem {
   bool diag_active = false;
   double t_setup = 0;
   double* d_newton = nullptr;  // Newton work vectors
+  // the diagonal mass of the curved elements (power-source Newton solves);
+  // invalidated when the geometry or the metric changes
+  double* d_mdiag = nullptr;
   // a variable of a system: the Neumann faces of all its variables, which
   // decide the classes and frames (empty for a scalar problem)
   std::vector<int> class_masks;
@@ -1560,6 +1563,12 @@ CgWork problem_cg_work(dgs_problem* P) {
 // search) and waits for it; done() once converged or after max_newton steps.
 struct NewtonRun {
   dgs_problem* P = nullptr;
+  // kind 0: the puncture source on the box grid (alpha, beta); kind 1: a
+  // power-law source S(u) = sum_t c_t u^k_t on curved elements, with
+  // Dirichlet data bvals (NULL: homogeneous) and the diagonal mass mdiag
+  int kind = 0;
+  PowerSource ps;
+  const double *bvals = nullptr, *mdiag = nullptr;
   const double *alpha = nullptr, *beta = nullptr, *b = nullptr;
   double* u = nullptr;
   double newton_rtol = 0, linear_rtol = 0;
@@ -1574,14 +1583,44 @@ struct NewtonRun {
 
   void residual(const double* x, double* out) {  // A x + M S(x) - b
     const Level& L0 = P->levels[0];
+    if (kind == 1) {
+      HIP_OK(launch_curved_apply_bc(P->N, x, out, bvals, P->curved,
+                                    P->metric_on ? &P->metric : nullptr, L0.d_nbr, P->penalty,
+                                    L0.op.neumann, L0.E, s));
+      HIP_OK(launch_power_source(ps, x, mdiag, b, out, nullptr, n, s));
+      return;
+    }
     HIP_OK(launch_apply(P->N, kPuncture, x, out, b, alpha, beta, L0.d_nbr, L0.op, P->dt,
                         L0.acfg_out, s, L0.d_order));
   }
+  void init_powers(dgs_problem* p, const PowerSource& src, const double* bv, const double* bb,
+                   double* uu, double nrt, double lrt, int mn, hipStream_t st) {
+    kind = 1;
+    ps = src;
+    bvals = bv;
+    const long long nn = p->nd(0);
+    if (!p->d_mdiag) {  // the diagonal mass of the curved elements (and metric)
+      p->d_mdiag = p->alloc<double>(nn);
+      HIP_OK(launch_fill(p->d_mdiag, 1.0, nn, st));
+      if (p->metric_on)
+        HIP_OK(launch_curved_mass_metric(p->N, p->d_mdiag, p->d_mdiag, p->curved, p->metric,
+                                         p->levels[0].E, st));
+      else
+        HIP_OK(launch_curved_mass(p->N, p->d_mdiag, p->d_mdiag, p->curved, p->levels[0].E, st));
+    }
+    mdiag = p->d_mdiag;
+    start(p, bb, uu, nrt, lrt, mn, st);
+  }
   void init(dgs_problem* p, const double* a, const double* be, const double* bb, double* uu,
             double nrt, double lrt, int mn, hipStream_t st) {
-    P = p;
+    kind = 0;
     alpha = a;
     beta = be;
+    start(p, bb, uu, nrt, lrt, mn, st);
+  }
+  void start(dgs_problem* p, const double* bb, double* uu, double nrt, double lrt, int mn,
+             hipStream_t st) {
+    P = p;
     b = bb;
     u = uu;
     newton_rtol = nrt;
@@ -1611,7 +1650,10 @@ struct NewtonRun {
   void step() {
     // linearisation A + diag(M dS/du(u)) and the linear solve for du
     const Level& L0 = P->levels[0];
-    HIP_OK(launch_puncture_diag(P->N, alpha, beta, u, work, L0.E, L0.h, P->dt, s));
+    if (kind == 1)
+      HIP_OK(launch_power_source(ps, u, mdiag, nullptr, nullptr, work, n, s));
+    else
+      HIP_OK(launch_puncture_diag(P->N, alpha, beta, u, work, L0.E, L0.h, P->dt, s));
     set_diagonal(P, work, s);
     HIP_OK(launch_fill(work, 0.0, n, s));
     HIP_OK(launch_axpy(work, -1.0, F, n, s));  // right-hand side -F
@@ -3049,6 +3091,11 @@ int dgs_set_geometry(dgs_problem* prob, const double* xyz, void* stream) {
       upload(G.D, prob->ht.D, s);
       upload(G.w, prob->ht.w, s);
     }
+    if (prob->d_mdiag) {  // formed again from the new geometry when needed
+      HIP_OK(hipStreamSynchronize(s));
+      prob->release(prob->d_mdiag);
+      prob->d_mdiag = nullptr;
+    }
     HIP_OK(launch_curved_geometry(N, xyz, L.E, G.D, G.inv, G.det, s));
     // every element map must preserve orientation
     std::vector<double> det(nd);
@@ -3073,6 +3120,11 @@ int dgs_set_metric(dgs_problem* prob, const double* ginv, const double* sqrtg, v
     if (!ginv != !sqrtg) return fail(DGS_ERR_INVALID, "ginv and sqrtg are given together");
     hipStream_t s = as_stream(stream);
     if (!ginv) {
+      if (prob->metric_on && prob->d_mdiag) {
+        HIP_OK(hipStreamSynchronize(s));
+        prob->release(prob->d_mdiag);
+        prob->d_mdiag = nullptr;
+      }
       prob->metric_on = false;
       return DGS_OK;
     }
@@ -3103,6 +3155,11 @@ int dgs_set_metric(dgs_problem* prob, const double* ginv, const double* sqrtg, v
       HIP_OK(hipStreamSynchronize(s));
       prob->release(xyz);
       if (rc != DGS_OK) return rc;
+    }
+    if (prob->d_mdiag) {
+      HIP_OK(hipStreamSynchronize(s));
+      prob->release(prob->d_mdiag);
+      prob->d_mdiag = nullptr;
     }
     CurvedMetric& Mt = prob->metric;
     if (!Mt.ginv) {
@@ -3305,6 +3362,49 @@ int dgs_newton_solve(dgs_problem* prob, const double* alpha, const double* beta,
       }
     }
     return converged ? DGS_OK : DGS_NOT_CONVERGED;
+  });
+}
+
+int dgs_newton_solve_powers(dgs_problem* prob, int nterms, const int* powers, const double* coef,
+                            const double* dirichlet, const double* b, double* u, double newton_rtol,
+                            double linear_rtol, int max_newton, dgs_stats* stats, void* stream) {
+  return guarded([&]() -> int {
+    if (!prob || !powers || !coef || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    if (nterms < 1 || nterms > kMaxPowerTerms)
+      return fail(DGS_ERR_INVALID, "the source takes 1 to 8 terms");
+    for (int t = 0; t < nterms; ++t)
+      if (powers[t] < -kMaxPower || powers[t] > kMaxPower)
+        return fail(DGS_ERR_INVALID, "powers must lie in [-12, 12]");
+    if (!(newton_rtol > 0.0) || !(linear_rtol > 0.0) || max_newton < 1)
+      return fail(DGS_ERR_INVALID, "invalid Newton tolerances");
+    if (!prob->curved_on)
+      return fail(DGS_ERR_INVALID, "set node coordinates (dgs_set_geometry) or a metric first");
+    hipStream_t s = as_stream(stream);
+    const double t0 = now_s();
+    PowerSource src;
+    src.nterms = nterms;
+    for (int t = 0; t < nterms; ++t) src.power[t] = powers[t];
+    src.coef = coef;
+    NewtonRun nr;
+    nr.init_powers(prob, src, dirichlet, b, u, newton_rtol, linear_rtol, max_newton, s);
+    while (!nr.done()) nr.step();
+    prob->diag_active = false;
+    HIP_OK(hipStreamSynchronize(s));
+    if (stats) {
+      stats->iterations = nr.its;
+      stats->newton_steps = nr.steps;
+      stats->backtracks = nr.backtracks;
+      stats->rel_residual = nr.rel_residual();
+      stats->t_solve_s = now_s() - t0;
+      stats->t_setup_s = prob->t_setup;
+      stats->history_len = 0;
+      if (stats->history && stats->history_capacity > 0) {
+        const int m = std::min<int>(stats->history_capacity, (int)nr.hist.size());
+        for (int i = 0; i < m; ++i) stats->history[i] = nr.hist[i];
+        stats->history_len = m;
+      }
+    }
+    return nr.converged ? DGS_OK : DGS_NOT_CONVERGED;
   });
 }
 

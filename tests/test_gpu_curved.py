@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import curved, krylov, mesh as omesh, multigrid
+from oracle import curved, krylov, mesh as omesh, multigrid, newton as onewton
 from tests.gpu_util import announce, rel_max, to_gpu, to_np
 
 pytestmark = pytest.mark.gpu
@@ -232,4 +232,83 @@ def test_metric_checks():
     # the unit metric on the box coordinates is the box operator
     prob.set_metric(to_gpu(good), to_gpu(np.ones(n)))
     assert rel_max(to_np(prob.apply(u)), flat) < 1e-13
+    prob.close()
+
+
+def _ks_wedge(elements, p):
+    box = omesh.BoxMesh((-1, -1, -1), (1, 1, 1), elements, p)
+    xyz = W.wedge_coordinates(np.stack(box.node_coordinates()), 2.0, 10.0)
+    cm = curved.CurvedMesh(box, xyz)
+    G, sg, alpha, coefs, powers = W.kerr_schild_lapse(cm.xyz)
+    six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
+    return box, cm, G, sg, six, alpha.reshape(-1), coefs, powers
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_kerr_schild_lapse_newton_matches_oracle(precision):
+    # the XCTS lapse equation on the Kerr-Schild background (psi = 1, shift
+    # fixed) on a wedge from r = 2M to 10M, Dirichlet data from the analytic
+    # lapse, flat initial guess: Newton with the power-law source on the GPU
+    # against the oracle's Newton with the same V-cycle
+    announce(f"kerr-schild lapse newton 2x2x2 p=4 {precision}")
+    box, cm, G, sg, six, alpha, coefs, powers = _ks_wedge((2, 2, 2), 4)
+    u_ref, info = onewton.newton_solve_powers(cm, C, coefs, powers, ginv=G, sqrtg=sg, dirichlet=alpha,
+                                              newton_rtol=1e-10, linear_rtol=1e-4, levels=2,
+                                              subdomain_iters=3)
+    prob = _problem(box, mg_levels=2, subdomain_iters=3, precision=precision)
+    prob.set_geometry(to_gpu(cm.xyz.reshape(-1)))
+    prob.set_metric(to_gpu(six), to_gpu(sg.reshape(-1)))
+    u, st = prob.newton_solve_powers(to_gpu(coefs.reshape(-1)), powers, dirichlet=to_gpu(alpha),
+                                     newton_rtol=1e-10, linear_rtol=1e-4)
+    u = to_np(u)
+    assert st["converged"], st
+    # the oracle's own nonlinear residual of the GPU solution
+    Mg = (sg * curved.mass_diagonal(cm)).reshape(-1)
+    cf = [c.reshape(-1) for c in coefs]
+    F = lambda v: (curved.apply_operator_metric(cm, v, C, G, sg, dirichlet_values=alpha)
+                   + Mg * onewton.power_source(cf, powers, v)[0])
+    assert np.linalg.norm(F(u)) <= 1e-10 * np.linalg.norm(F(np.ones(box.ndof)))
+    assert np.linalg.norm(u - u_ref) <= 1e-9 * np.linalg.norm(u_ref)
+    if precision == "fp64":
+        assert st["newton_steps"] == info["steps"]
+    assert np.abs(u - alpha).max() < 1e-4  # the discretisation error at p = 4
+
+
+def test_power_source_newton_on_box_coordinates():
+    # -Laplace(u) + u^3 - 2 u^-2 = f on the box with its own coordinates as
+    # curved elements, Dirichlet data u_b = 1 + x y z, homogeneous Neumann on
+    # one face, the right-hand side b = M f given
+    announce("power-source newton on box coordinates")
+    box = omesh.BoxMesh((0, 0, 0), (1, 1.2, 0.9), (3, 2, 2), 3, neumann=(1,))
+    X = np.stack(box.node_coordinates())
+    cm = curved.CurvedMesh(box, X)
+    ub = (1.0 + X[0] * X[1] * X[2]).reshape(-1)
+    coefs = np.stack([np.ones(box.ndof), -2.0 * np.ones(box.ndof)])
+    f = W.random_uniform(70, box.ndof, 0.5, 1.5)
+    b = curved.apply_mass(cm, f).reshape(-1)
+    u_ref, info = onewton.newton_solve_powers(cm, C, coefs, (3, -2), dirichlet=ub, b=b, levels=2,
+                                              subdomain_iters=3)
+    prob = _problem(box, mg_levels=2, subdomain_iters=3)
+    prob.set_geometry(to_gpu(X.reshape(-1)))
+    u, st = prob.newton_solve_powers(to_gpu(coefs.reshape(-1)), (3, -2), dirichlet=to_gpu(ub), b=to_gpu(b))
+    assert st["converged"] and st["newton_steps"] == info["steps"], (st, info["steps"])
+    assert np.linalg.norm(to_np(u) - u_ref) <= 1e-9 * np.linalg.norm(u_ref)
+
+
+def test_power_source_checks():
+    import paper_2111_06767_amd as dg
+    announce("power-source newton checks")
+    box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 1, 1), 2)
+    prob = _problem(box, mg_levels=1)
+    n = box.ndof
+    coef = to_gpu(np.ones(n))
+    with pytest.raises(dg.DgsError):  # no curved elements yet
+        prob.newton_solve_powers(coef, (1,))
+    prob.set_geometry(to_gpu(np.stack(box.node_coordinates()).reshape(-1)))
+    with pytest.raises(dg.DgsError):
+        prob.newton_solve_powers(coef, (13,))
+    with pytest.raises(dg.DgsError):
+        prob.newton_solve_powers(to_gpu(np.ones(9 * n)), (1,) * 9)
+    with pytest.raises(dg.DgsError):  # u = 0 under a negative power
+        prob.newton_solve_powers(coef, (-1,), u=to_gpu(np.zeros(n)))
     prob.close()
