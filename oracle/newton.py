@@ -204,3 +204,108 @@ def newton_solve_powers(cm, C, coefs, powers, ginv=None, sqrtg=None, dirichlet=N
         steps += 1
         hist.append(np.linalg.norm(Fu) / norm0)
     return u, dict(steps=steps, history=hist, linear_iterations=linear_its, backtracks=backtracks)
+
+
+def monomial_source(terms, u):
+    """S_a(u) = sum over the terms (c, k) of variable a of c prod_b u_b^(k_b),
+    and D_ab = dS_a/du_b, for u of shape (V, n)."""
+    V, n = u.shape
+    S = np.zeros((V, n))
+    D = np.zeros((V, V, n))
+    for a in range(V):
+        for c, k in terms[a]:
+            c = np.asarray(c, float).reshape(-1)
+            S[a] += c * np.prod([u[q] ** float(k[q]) for q in range(V)], axis=0)
+            for b in range(V):
+                if k[b] == 0:
+                    continue
+                f = c * k[b] * u[b] ** float(k[b] - 1)
+                for q in range(V):
+                    if q != b:
+                        f = f * u[q] ** float(k[q])
+                D[a, b] += f
+    return S, D
+
+
+def system_newton_solve_powers(meshes, xyz, C, terms, ginv=None, sqrtg=None, dirichlet=None, b=None,
+                               u0=None, newton_rtol=1e-10, linear_rtol=1e-4, max_newton=20, levels=2,
+                               overlap=2, pre=3, post=3, subdomain_iters=3, laplacian_bc="matched",
+                               sufficient_decrease=1e-4, max_backtracks=10, max_linear_iter=200,
+                               dense=False):
+    """Newton-Raphson (Sec. III.A) for a coupled system of V variables on
+    curved elements: F_a(u) = A_a(u_a; u_b,a) + M S_a(u) - b_a with sources
+    that are sums of monomials in all variables (``terms[a]`` lists (c, k),
+    k the V powers), e.g. the XCTS equations (eq. xcts) with some variables
+    held fixed.  ``meshes[a]`` is variable a's box grid (its own Neumann
+    faces), all with the node coordinates xyz; on a background metric when
+    ginv and sqrtg are given.  Each linearisation blockdiag(A_a) + M dS/du is
+    solved by FGMRES preconditioned by the system V-cycle of the box grids
+    with the couplings D = M dS/du (Sec. III.E.1; or by a dense solve), then
+    the step length is backtracked as in newton_solve.  u0: (V, n), ones if
+    None.  Returns (u of shape (V, n), info)."""
+    from .system import SystemOperator, SystemVCycle
+    V = len(meshes)
+    cms = [curved.CurvedMesh(m, xyz) for m in meshes]
+    n = meshes[0].ndof
+    if ginv is None:
+        Mdiag = curved.mass_diagonal(cms[0]).reshape(-1)
+
+        def A(a, v, ub=None):
+            return curved.apply_operator(cms[a], v, C, dirichlet_values=ub)
+    else:
+        Mdiag = (np.asarray(sqrtg, float).reshape(cms[0].det.shape) *
+                 curved.mass_diagonal(cms[0])).reshape(-1)
+
+        def A(a, v, ub=None):
+            return curved.apply_operator_metric(cms[a], v, C, ginv, sqrtg, dirichlet_values=ub)
+    ub = [None] * V if dirichlet is None else np.asarray(dirichlet, float).reshape(V, n)
+    b = np.zeros((V, n)) if b is None else np.asarray(b, float).reshape(V, n)
+    u = np.ones((V, n)) if u0 is None else np.asarray(u0, float).reshape(V, n).copy()
+    m0 = meshes[0]
+    sysop = SystemOperator(m0.lower, m0.upper, m0.n, m0.p, [m.neumann for m in meshes], C)
+
+    def F(v):
+        return np.stack([A(a, v[a], ub[a]) for a in range(V)]) + Mdiag * monomial_source(terms, v)[0] - b
+
+    Fu = F(u)
+    norm0 = np.linalg.norm(Fu)
+    hist = [1.0]
+    linear_its = []
+    steps = backtracks = 0
+    for _ in range(max_newton):
+        nrm = np.linalg.norm(Fu)
+        if nrm <= newton_rtol * norm0 or nrm == 0.0:
+            break
+        D = Mdiag * monomial_source(terms, u)[1]
+
+        def J(x):
+            x = x.reshape(V, n)
+            return (np.stack([A(a, x[a]) for a in range(V)]) + np.einsum("abn,bn->an", D, x)).reshape(-1)
+
+        if dense:
+            Jm = np.stack([J(e) for e in np.eye(V * n)], axis=1)
+            du = np.linalg.solve(Jm, -Fu.reshape(-1))
+            linear_its.append(0)
+        else:
+            P = SystemVCycle(sysop, D, levels=levels, overlap=overlap, pre=pre, post=post,
+                             subdomain_iters=subdomain_iters, laplacian_bc=laplacian_bc)
+            du, its, _ = fgmres(J, -Fu.reshape(-1), precondition=P, rtol=linear_rtol,
+                                max_iter=max_linear_iter)
+            linear_its.append(its)
+        du = du.reshape(V, n)
+        f0 = 0.5 * nrm ** 2
+        slope = -nrm ** 2
+        lam, lam_prev, f_prev = 1.0, None, None
+        for bt in range(max_backtracks + 1):
+            Ft = F(u + lam * du)
+            ft = 0.5 * np.linalg.norm(Ft) ** 2
+            if ft <= f0 + sufficient_decrease * lam * slope or bt == max_backtracks:
+                break
+            new = backtrack(f0, slope, lam, ft, lam_prev, f_prev, first=(bt == 0))
+            lam_prev, f_prev, lam = lam, ft, new
+            backtracks += 1
+        u = u + lam * du
+        Fu = Ft
+        steps += 1
+        hist.append(np.linalg.norm(Fu) / norm0)
+    return u, dict(steps=steps, history=hist, linear_iterations=linear_its, backtracks=backtracks)

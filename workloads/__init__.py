@@ -184,26 +184,19 @@ def wedge_coordinates(X, r_in: float, r_out: float):
     return np.stack([s * a, s * b, s])
 
 
-def kerr_schild_lapse(xyz, mass: float = 1.0):
-    """The lapse equation of the XCTS system (eq. xcts_lapse) on the
-    Kerr-Schild background of a Schwarzschild black hole (eq. kerrschild_bg),
-    with the conformal factor psi = 1 and the shift held at its Kerr-Schild
-    value (eq. kerrschild_shift), at the node coordinates xyz (3, ...).
+def _kerr_schild_fields(xyz, mass):
+    """Background fields of a Schwarzschild black hole in Kerr-Schild
+    coordinates (eq. kerrschild_bg) at the node coordinates xyz (3, ...).
 
     With H = M/r, l = x/r: g_ij = delta_ij + 2H l_i l_j, so g^ij = delta^ij -
     alpha^2 2H l^i l^j and sqrt(g) = (1 + 2H)^(1/2); the Kerr-Schild lapse
-    alpha = (1 + 2H)^(-1/2) and extrinsic curvature
-    K_ij = (2 M alpha / r^2)(delta_ij - (2 + H) l_i l_j) (tangential
+    alpha = (1 + 2H)^(-1/2), shift beta^i = 2H alpha^2 l^i and extrinsic
+    curvature K_ij = (2 M alpha / r^2)(delta_ij - (2 + H) l_i l_j) (tangential
     eigenvalue a = 2 M alpha / r^2, radial -a alpha^2 (1 + H) of K^i_j), so
     K_ij K^ij = 2 a^2 + a^2 alpha^4 (1 + H)^2 and K = 2 M alpha^3 / r^2 (1 + 3H).
-    With psi = 1, u_ij = 0, no matter: (L beta)^ij = 2 alpha A^ij (A the
-    trace-free part of K), R = K_ij K^ij - K^2 (Hamiltonian constraint), and
-    for the unknown Phi = alpha psi the lapse equation reads
-      Laplace_g Phi = c_-1 / Phi + c_1 Phi + c_0,
-      c_-1 = 7/8 alpha^2 A_ij A^ij,  c_1 = 5/12 K^2 + R / 8,
-      c_0 = beta^i d_i K = 2H alpha^2 dK/dr.
-    Its exact solution is Phi = alpha.  Returns g^ij (3, 3, ...), sqrt(g),
-    alpha, the coefficients (3, ...) and their powers (-1, 1, 0)."""
+    With psi = 1, u_ij = 0 and no matter, (L beta)^ij = 2 alpha A^ij (A the
+    trace-free part of K), so (L beta)_ij (L beta)^ij = 4 alpha^2 A_ij A^ij,
+    and R = K_ij K^ij - K^2 (the vacuum Hamiltonian constraint)."""
     x = np.asarray(xyz, dtype=float)
     M = float(mass)
     r = np.sqrt((x * x).sum(axis=0))
@@ -218,13 +211,48 @@ def kerr_schild_lapse(xyz, mass: float = 1.0):
     KK = 2.0 * a * a + kr * kr
     K = 2.0 * a + kr
     AA = KK - K * K / 3.0
-    R = KK - K * K
     dalpha = alpha ** 3 * M / r ** 2
     dK = 2.0 * M * ((3.0 * alpha ** 2 * dalpha / r ** 2 - 2.0 * alpha ** 3 / r ** 3) * (1.0 + 3.0 * H)
                     - 3.0 * M * alpha ** 3 / r ** 4)
-    coefs = np.stack([7.0 / 8.0 * alpha ** 2 * AA, 5.0 / 12.0 * K * K + R / 8.0,
-                      2.0 * H * alpha ** 2 * dK])
-    return ginv, sqrtg, alpha, coefs, (-1, 1, 0)
+    return dict(ginv=ginv, sqrtg=sqrtg, alpha=alpha, K2=K * K, R=KK - K * K,
+                LL=4.0 * alpha ** 2 * AA, beta_dK=2.0 * H * alpha ** 2 * dK)
+
+
+def kerr_schild_lapse(xyz, mass: float = 1.0):
+    """The lapse equation of the XCTS system (eq. xcts_lapse) on the
+    Kerr-Schild background (eq. kerrschild_bg), with psi = 1 and the shift
+    held at its Kerr-Schild value (eq. kerrschild_shift), at the node
+    coordinates xyz (3, ...).  For Phi = alpha psi it reads
+      Laplace_g Phi = c_-1 / Phi + c_1 Phi + c_0,
+      c_-1 = 7/32 (L beta)_ij (L beta)^ij,  c_1 = 5/12 K^2 + R / 8,
+      c_0 = beta^i d_i K,
+    with exact solution Phi = alpha (eq. kerrschild_lapse).  Returns g^ij
+    (3, 3, ...), sqrt(g), alpha, the coefficients (3, ...) and their powers
+    (-1, 1, 0)."""
+    f = _kerr_schild_fields(xyz, mass)
+    coefs = np.stack([7.0 / 32.0 * f["LL"], 5.0 / 12.0 * f["K2"] + f["R"] / 8.0, f["beta_dK"]])
+    return f["ginv"], f["sqrtg"], f["alpha"], coefs, (-1, 1, 0)
+
+
+def kerr_schild_xcts(xyz, mass: float = 1.0):
+    """The Hamiltonian and lapse equations of the XCTS system (eqs.
+    xcts_hamiltonian, xcts_lapse) for psi and Phi = alpha psi on the
+    Kerr-Schild background, the shift held at its Kerr-Schild value, at the
+    node coordinates xyz (3, ...).  With alpha_bar = Phi psi^-7,
+    A_ij A^ij = (L beta)^2 psi^14 / (4 Phi^2), so the right-hand sides are
+    sums of monomials in (psi, Phi):
+      Laplace_g psi = R/8 psi + K^2/12 psi^5 - (L beta)^2/32 psi^7 Phi^-2,
+      Laplace_g Phi = 7 (L beta)^2/32 psi^6 Phi^-1 + 5 K^2/12 psi^4 Phi
+                      + R/8 Phi + beta^i d_i K psi^5,
+    with exact solution psi = 1, Phi = alpha (eqs. kerrschild_psi,
+    kerrschild_lapse).  Returns g^ij, sqrt(g), alpha and, per variable, the
+    list of (coefficient field, (power of psi, power of Phi))."""
+    f = _kerr_schild_fields(xyz, mass)
+    LL, K2, R = f["LL"], f["K2"], f["R"]
+    terms = [[(R / 8.0, (1, 0)), (K2 / 12.0, (5, 0)), (-LL / 32.0, (7, -2))],
+             [(7.0 * LL / 32.0, (6, -1)), (5.0 * K2 / 12.0, (4, 1)), (R / 8.0, (0, 1)),
+              (f["beta_dK"], (5, 0))]]
+    return f["ginv"], f["sqrtg"], f["alpha"], terms
 
 
 def pullback_metric(X, lower, upper, amplitude: float, direction=(1.0, 0.7, 0.4)):
