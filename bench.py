@@ -548,6 +548,49 @@ def lapse_leg(dg, precision, steps=3, warmup=1):
                 max_error_vs_analytic_lapse=err)
 
 
+def xcts_leg(dg, precision, steps=2, warmup=1):
+    """The Hamiltonian and lapse equations of the XCTS system for psi and
+    alpha psi on the Kerr-Schild background (shift held at its Kerr-Schild
+    value) on one wedge (r from 2M to 10M) as 16^3 elements of p = 7: psi
+    Neumann at the inner sphere (Sec. IV.B), Dirichlet data from the analytic
+    solution elsewhere, flat initial guess; the system Newton with the
+    BC-matched Laplacian approximation in the system V-cycle."""
+    import torch
+    import workloads as W
+    lower, upper = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    X = dg.points(lower, upper, C5["elements"], C5["p"])
+    xyz = W.wedge_coordinates(X, 2.0, 10.0)
+    G, sg, alpha, terms = W.kerr_schild_xcts(xyz)
+    six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
+    S = dg.System(lower, upper, C5["elements"], C5["p"], [(4,), ()], laplacian_bc="matched", penalty=1.5,
+                  mg_levels=C5["levels"], precision=precision, subdomain_iters=3)
+    S.set_geometry(torch.as_tensor(xyz.reshape(-1)).cuda())
+    S.set_metric(torch.as_tensor(six).cuda(), torch.as_tensor(sg.reshape(-1)).cuda())
+    n = S.ndof
+    vars_ = [a for a in range(2) for _ in terms[a]]
+    powers = [k for a in range(2) for _, k in terms[a]]
+    coef = torch.as_tensor(np.concatenate([np.asarray(c, float).reshape(-1)
+                                           for a in range(2) for c, _ in terms[a]])).cuda()
+    ub = torch.as_tensor(np.concatenate([np.ones(n), alpha.reshape(-1)])).cuda()
+    u = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    times, st = [], None
+    for i in range(warmup + steps):
+        u.fill_(1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = S.newton_solve_powers(coef, vars_, powers, dirichlet=ub, u=u, newton_rtol=1e-10,
+                                      linear_rtol=1e-4)
+        torch.cuda.synchronize()
+        if i >= warmup:
+            times.append(time.perf_counter() - t0)
+    uh = u.cpu().numpy().reshape(2, n)
+    S.close()
+    return dict(ms=_ms(times), newton_steps=st["newton_steps"], linear_iterations=st["iterations"],
+                rel_residual=st["rel_residual"], converged=st["converged"],
+                max_error_psi=float(np.abs(uh[0] - 1.0).max()),
+                max_error_lapse=float(np.abs(uh[1] - alpha.reshape(-1)).max()))
+
+
 def wedge_leg(dg, precision, steps=5, warmup=1):
     """One wedge of the spherical shell of Sec. IV.B (r from 2 to 10,
     logarithmic radius, equiangular angles) as 16^3 elements of p = 7 on the
@@ -942,6 +985,9 @@ def main():
         for prec in ("fp64", "mixed"):
             _log(f"Kerr-Schild lapse equation on a wedge, 16^3 p=7 {prec}")
             curved[f"kerr_schild_lapse_16^3_p7_{prec}"] = lapse_leg(dg, prec)
+        for prec in ("fp64", "mixed"):
+            _log(f"XCTS Hamiltonian and lapse equations on a wedge, 16^3 p=7 {prec}")
+            curved[f"xcts_psi_lapse_16^3_p7_{prec}"] = xcts_leg(dg, prec)
         _log("curved apply on a background metric 24^3 p=7")
         curved["metric_apply_24^3_p7"] = time_curved_apply(dg, (24, 24, 24), 7, metric_amplitude=0.15)
 

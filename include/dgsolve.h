@@ -479,6 +479,41 @@ int dgs_system_precondition(dgs_system* sys, const double* r, double* z, void* s
  * confirmed by the true residual; DGS_OK or DGS_NOT_CONVERGED. */
 int dgs_system_solve(dgs_system* sys, const double* b, double* u, dgs_stats* stats, void* stream);
 
+/* Curved elements and a background metric for every variable of the system
+ * (as dgs_set_geometry and dgs_set_metric on each variable's operator):
+ * dgs_system_apply and dgs_system_solve then use the curved operators, the
+ * V-cycle keeps the box grids'.  Same arguments and errors as the scalar
+ * calls. */
+int dgs_system_set_geometry(dgs_system* sys, const double* xyz, void* stream);
+int dgs_system_set_metric(dgs_system* sys, const double* ginv, const double* sqrtg, void* stream);
+
+/* Newton-Raphson (Sec. III.A) for the system on curved elements with sources
+ * that are sums of monomials in all variables,
+ *   F_a(u) = A_a(u_a; u_b,a) + M S_a(u) - b_a,
+ *   S_a(u) = sum over the terms t with vars[t] = a of c_t prod_q u_q^k(t,q),
+ * the form the XCTS equations (eq. xcts) take when the shift is held fixed.
+ * A_a is variable a's curved operator (its own Neumann faces; on the metric
+ * when one is set) with Dirichlet data `dirichlet` (device, nvars * ndof,
+ * variable a at a * ndof, read at its Dirichlet boundary nodes through the
+ * ghost of eq. bc; NULL = homogeneous).  vars: host, nterms variable
+ * indices; powers: host, nterms * nvars integers in [-12, 12] (term t at
+ * t * nvars); coef: device, nterms fields of ndof values; b: device
+ * (nvars * ndof) or NULL (zero); u: device, nvars * ndof, the initial guess
+ * on entry and the solution on exit.  Each step sets the couplings
+ * D_ab = M dS_a/du_b and solves the linearisation to linear_rtol by FGMRES
+ * preconditioned by the system V-cycle (its subdomain problems carry D,
+ * Sec. III.E.1), then backtracks the step length as dgs_newton_solve does;
+ * converged when ||F(u)|| <= newton_rtol ||F(u0)||.  The couplings are
+ * cleared on return.  Needs curved elements on every variable
+ * (dgs_system_set_geometry or dgs_system_set_metric); DGS_ERR_INVALID
+ * otherwise, for nterms outside [1, 16], a variable index outside
+ * [0, nvars) or a power outside [-12, 12]; DGS_ERR_NONFINITE when a residual
+ * is not finite. */
+int dgs_system_newton_solve_powers(dgs_system* sys, int nterms, const int* vars, const int* powers,
+                                   const double* coef, const double* dirichlet, const double* b,
+                                   double* u, double newton_rtol, double linear_rtol, int max_newton,
+                                   dgs_stats* stats, void* stream);
+
 /* ---- hp-nonuniform meshes (Sec. II: blocks split into elements by h
  * refinement with two-to-one balance, elements of their own degree; Sec.
  * III.C.1: coarsening keeps the smaller degree) ------------------------------

@@ -38,6 +38,7 @@ EXPORTED = (
     "dgs_create_hp_problem", "dgs_destroy_hp_problem", "dgs_hp_num_dofs", "dgs_hp_num_levels",
     "dgs_hp_num_classes", "dgs_hp_node_coordinates", "dgs_hp_apply_operator", "dgs_hp_apply_mass",
     "dgs_hp_smooth", "dgs_hp_precondition", "dgs_hp_solve", "dgs_set_metric", "dgs_newton_solve_powers",
+    "dgs_system_set_geometry", "dgs_system_set_metric", "dgs_system_newton_solve_powers",
 )
 
 
@@ -155,6 +156,12 @@ def load_library(path: str = LIB_PATH):
     lib.dgs_system_smooth.argtypes = [P, dp, dp, ctypes.c_int, P]
     lib.dgs_system_precondition.argtypes = [P, dp, dp, P]
     lib.dgs_system_solve.argtypes = [P, dp, dp, ctypes.POINTER(Stats), P]
+    lib.dgs_system_set_geometry.argtypes = [P, dp, P]
+    lib.dgs_system_set_metric.argtypes = [P, dp, dp, P]
+    lib.dgs_system_newton_solve_powers.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                   ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp,
+                                                   ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                                   ctypes.POINTER(Stats), P]
     lib.dgs_create_hp_problem.argtypes = [ctypes.POINTER(Domain), ctypes.POINTER(ctypes.c_int),
                                           ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                           ctypes.c_int, ctypes.c_double, ctypes.POINTER(Options), P,
@@ -559,6 +566,44 @@ class System:
         code = _check(self._lib.dgs_system_solve(self._h, _ptr(b, self.size, "b"),
                                                  _ptr(u, self.size, "u"), ctypes.byref(st),
                                                  _stream(stream)), allow_not_converged=True)
+        return u, _stats_dict(st, hist, code)
+
+    def set_geometry(self, xyz=None, stream=None):
+        """Curved elements for every variable (3 * ndof coordinates; None: the box grid)."""
+        ptr = ctypes.c_void_p(None) if xyz is None else _ptr(xyz, 3 * self.ndof, "xyz")
+        _check(self._lib.dgs_system_set_geometry(self._h, ptr, _stream(stream)))
+
+    def set_metric(self, ginv=None, sqrtg=None, stream=None):
+        """A background metric for every variable (g^ij as 6 * ndof, sqrt(g) as ndof)."""
+        if (ginv is None) != (sqrtg is None):
+            raise ValueError("ginv and sqrtg are given together")
+        null = ctypes.c_void_p(None)
+        _check(self._lib.dgs_system_set_metric(
+            self._h, null if ginv is None else _ptr(ginv, 6 * self.ndof, "ginv"),
+            null if sqrtg is None else _ptr(sqrtg, self.ndof, "sqrtg"), _stream(stream)))
+
+    def newton_solve_powers(self, coef, vars, powers, dirichlet=None, b=None, u=None, newton_rtol=1e-10,
+                            linear_rtol=1e-4, max_newton=20, history=256, stream=None):
+        """Newton on curved elements for the monomial sources: term t adds
+        coef_t prod_q u_q^powers[t][q] to variable vars[t]'s source; coef a
+        device tensor of len(vars) * ndof.  u: nvars * ndof (ones if None).
+        Returns (u, stats dict)."""
+        import torch
+        if u is None:
+            u = torch.ones(self.size, dtype=torch.float64, device="cuda")
+        k = len(vars)
+        if len(powers) != k or any(len(pw) != self.nvars for pw in powers):
+            raise ValueError("one power per variable for every term")
+        va = (ctypes.c_int * max(1, k))(*[int(x) for x in vars])
+        pa = (ctypes.c_int * max(1, k * self.nvars))(*[int(x) for pw in powers for x in pw])
+        null = ctypes.c_void_p(None)
+        st, hist = _make_stats(history)
+        code = _check(self._lib.dgs_system_newton_solve_powers(
+            self._h, k, va, pa, _ptr(coef, k * self.ndof, "coef"),
+            null if dirichlet is None else _ptr(dirichlet, self.size, "dirichlet"),
+            null if b is None else _ptr(b, self.size, "b"), _ptr(u, self.size, "u"),
+            float(newton_rtol), float(linear_rtol), int(max_newton), ctypes.byref(st), _stream(stream)),
+            allow_not_converged=True)
         return u, _stats_dict(st, hist, code)
 
 

@@ -29,6 +29,19 @@ struct PowerSource {
   const double* coef = nullptr;
 };
 
+// Sources of a system of nv <= kSysMaxVars variables: variable var[t] of
+// term t receives c_t prod_b u_b^(power[t][b]) (the XCTS equations, eq. xcts,
+// are of this form when the shift is held fixed).  coef: device, nterm
+// fields of n values.
+constexpr int kMaxMonomials = 16;
+struct MonomialSource {
+  int nv = 0;
+  int nterm = 0;
+  int var[kMaxMonomials] = {};
+  int power[kMaxMonomials][kSysMaxVars] = {};
+  const double* coef = nullptr;
+};
+
 // dlsg from sqrtg (the element metric of G)
 hipError_t launch_curved_metric_source(int N, const CurvedGeometry& G, CurvedMetric& Mt, long long E,
                                        hipStream_t s);
@@ -49,6 +62,10 @@ hipError_t launch_curved_apply_bc(int N, const double* u, double* out, const dou
 // NULL), m the diagonal mass
 hipError_t launch_power_source(const PowerSource& ps, const double* u, const double* mdiag,
                                const double* b, double* F, double* d, long long n, hipStream_t s);
+// For u of nv fields of n values: F_a += m S_a(u) - b_a (F, b may be NULL)
+// and D_ab = m dS_a/du_b at (a nv + b) n (D may be NULL)
+hipError_t launch_monomial_source(const MonomialSource& ms, const double* u, const double* mdiag,
+                                  const double* b, double* F, double* D, long long n, hipStream_t s);
 // b = M f with M = sqrt(g) det(J) w_i w_j w_k
 hipError_t launch_curved_mass_metric(int N, const double* f, double* out, const CurvedGeometry& G,
                                      const CurvedMetric& Mt, long long E, hipStream_t s);

@@ -323,6 +323,65 @@ __global__ void k_power_source(PowerSource ps, const double* __restrict__ u,
   }
 }
 
+// S_a and D_ab = dS_a/du_b of a monomial source at every point; the
+// per-variable values stay in registers (compile-time indices, selected by
+// the term's variable)
+__global__ void k_monomial_source(MonomialSource ms, const double* __restrict__ u,
+                                  const double* __restrict__ mdiag, const double* __restrict__ b,
+                                  double* __restrict__ F, double* __restrict__ D, long long n) {
+  constexpr int V = kSysMaxVars;
+  const int nv = ms.nv;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    double uv[V], S[V], Dv[V][V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      uv[q] = q < nv ? u[q * n + i] : 1.0;
+      S[q] = 0.0;
+#pragma unroll
+      for (int r = 0; r < V; ++r) Dv[q][r] = 0.0;
+    }
+    for (int t = 0; t < ms.nterm; ++t) {
+      const double c = ms.coef[t * n + i];
+      const int a = ms.var[t];
+      double pw[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) pw[q] = ipow(uv[q], ms.power[t][q]);
+      double mono = c;
+#pragma unroll
+      for (int q = 0; q < V; ++q) mono *= pw[q];
+      double dm[V];
+#pragma unroll
+      for (int r = 0; r < V; ++r) {
+        const int k = ms.power[t][r];
+        double f = k != 0 ? c * (double)k * ipow(uv[r], k - 1) : 0.0;
+#pragma unroll
+        for (int q = 0; q < V; ++q)
+          if (q != r) f *= pw[q];
+        dm[r] = f;
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        if (q != a) continue;
+        S[q] += mono;
+#pragma unroll
+        for (int r = 0; r < V; ++r) Dv[q][r] += dm[r];
+      }
+    }
+    const double m = mdiag[i];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      if (q >= nv) break;
+      if (F) F[q * n + i] += m * S[q] - (b ? b[q * n + i] : 0.0);
+      if (D) {
+#pragma unroll
+        for (int r = 0; r < V; ++r)
+          if (r < nv) D[(long long)(q * nv + r) * n + i] = m * Dv[q][r];
+      }
+    }
+  }
+}
+
 // b = M f = det(J) w_i w_j w_k f
 template <int N>
 __global__ void __launch_bounds__(N * N * N)
@@ -417,6 +476,14 @@ hipError_t launch_power_source(const PowerSource& ps, const double* u, const dou
   if (n <= 0) return hipSuccess;
   const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 1 << 20);
   hipLaunchKernelGGL(k_power_source, dim3(blocks), dim3(256), 0, s, ps, u, mdiag, b, F, d, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_monomial_source(const MonomialSource& ms, const double* u, const double* mdiag,
+                                  const double* b, double* F, double* D, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(k_monomial_source, dim3(blocks), dim3(256), 0, s, ms, u, mdiag, b, F, D, n);
   return hipGetLastError();
 }
 

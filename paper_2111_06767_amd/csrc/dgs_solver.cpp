@@ -1557,6 +1557,62 @@ CgWork problem_cg_work(dgs_problem* P) {
                 P->d_partial, P->d_h, P->h_pinned};
 }
 
+// Backtracking line search on f = |F|^2 / 2 with the linear model's slope
+// -|F|^2 (Dennis & Schnabel: quadratic interpolation first, cubic after,
+// each new step in [0.1, 0.5] times the previous, at most 10 backtracks).
+// trial(lam) evaluates the residual at u + lam du and returns its f; the
+// return value is the accepted trial's f.
+template <class Trial>
+double backtracking_line_search(double nrm2, Trial&& trial, int& backtracks) {
+  const double alpha_sd = 1e-4;  // sufficient-decrease parameter
+  const int max_bt = 10;
+  const double f0 = 0.5 * nrm2, slope = -nrm2;
+  double lam = 1.0, lam_prev = 0.0, f_prev = 0.0, ft = 0.0;
+  for (int bt = 0; bt <= max_bt; ++bt) {
+    ft = trial(lam);
+    if (!std::isfinite(ft)) throw DgsError(DGS_ERR_NONFINITE, "non-finite trial residual");
+    if (ft <= f0 + alpha_sd * lam * slope || bt == max_bt) break;
+    double next;
+    if (bt == 0) {
+      next = -slope * lam * lam / (2.0 * (ft - f0 - slope * lam));
+    } else {
+      const double r1 = ft - f0 - lam * slope, r2 = f_prev - f0 - lam_prev * slope;
+      const double ca = (r1 / (lam * lam) - r2 / (lam_prev * lam_prev)) / (lam - lam_prev);
+      const double cb = (-lam_prev * r1 / (lam * lam) + lam * r2 / (lam_prev * lam_prev)) /
+                        (lam - lam_prev);
+      if (ca == 0.0) {
+        next = -slope / (2.0 * cb);
+      } else {
+        const double disc = std::max(cb * cb - 3.0 * ca * slope, 0.0);
+        next = (-cb + std::sqrt(disc)) / (3.0 * ca);
+      }
+    }
+    next = std::min(next, 0.5 * lam);
+    next = std::max(next, 0.1 * lam);
+    lam_prev = lam;
+    f_prev = ft;
+    lam = next;
+    ++backtracks;
+  }
+  return ft;
+}
+
+// The diagonal mass of a problem's curved elements (and metric), formed once
+// per geometry
+const double* ensure_mdiag(dgs_problem* p, hipStream_t st) {
+  if (!p->d_mdiag) {
+    const long long nn = p->nd(0);
+    p->d_mdiag = p->alloc<double>(nn);
+    HIP_OK(launch_fill(p->d_mdiag, 1.0, nn, st));
+    if (p->metric_on)
+      HIP_OK(launch_curved_mass_metric(p->N, p->d_mdiag, p->d_mdiag, p->curved, p->metric,
+                                       p->levels[0].E, st));
+    else
+      HIP_OK(launch_curved_mass(p->N, p->d_mdiag, p->d_mdiag, p->curved, p->levels[0].E, st));
+  }
+  return p->d_mdiag;
+}
+
 // Newton-Raphson with a backtracking line search (Sec. III.A) as a resumable
 // run: init() evaluates the first residual, each step() performs one Newton
 // step (linearise, solve the linear system with FGMRES to linear_rtol, line
@@ -1598,17 +1654,7 @@ struct NewtonRun {
     kind = 1;
     ps = src;
     bvals = bv;
-    const long long nn = p->nd(0);
-    if (!p->d_mdiag) {  // the diagonal mass of the curved elements (and metric)
-      p->d_mdiag = p->alloc<double>(nn);
-      HIP_OK(launch_fill(p->d_mdiag, 1.0, nn, st));
-      if (p->metric_on)
-        HIP_OK(launch_curved_mass_metric(p->N, p->d_mdiag, p->d_mdiag, p->curved, p->metric,
-                                         p->levels[0].E, st));
-      else
-        HIP_OK(launch_curved_mass(p->N, p->d_mdiag, p->d_mdiag, p->curved, p->levels[0].E, st));
-    }
-    mdiag = p->d_mdiag;
+    mdiag = ensure_mdiag(p, st);
     start(p, bb, uu, nrt, lrt, mn, st);
   }
   void init(dgs_problem* p, const double* a, const double* be, const double* bb, double* uu,
@@ -1661,39 +1707,14 @@ struct NewtonRun {
     FgmresResult R = fgmres(P, work, du, linear_rtol, P->opt.max_iter, s);
     its += R.iterations;
     P->diag_active = false;
-    // backtracking line search on f = |F|^2 / 2 with the linear model's slope
-    const double alpha_sd = 1e-4;  // sufficient-decrease parameter
-    const int max_bt = 10;
-    const double f0 = 0.5 * nrm2, slope = -nrm2;
-    double lam = 1.0, lam_prev = 0.0, f_prev = 0.0, ft = 0.0;
-    for (int bt = 0; bt <= max_bt; ++bt) {
-      HIP_OK(launch_waxpy(ut, u, lam, du, n, s));
-      residual(ut, Ft);
-      ft = 0.5 * device_norm2(P, Ft, n, s);
-      if (!std::isfinite(ft)) throw DgsError(DGS_ERR_NONFINITE, "non-finite trial residual");
-      if (ft <= f0 + alpha_sd * lam * slope || bt == max_bt) break;
-      double next;
-      if (bt == 0) {
-        next = -slope * lam * lam / (2.0 * (ft - f0 - slope * lam));
-      } else {
-        const double r1 = ft - f0 - lam * slope, r2 = f_prev - f0 - lam_prev * slope;
-        const double ca = (r1 / (lam * lam) - r2 / (lam_prev * lam_prev)) / (lam - lam_prev);
-        const double cb = (-lam_prev * r1 / (lam * lam) + lam * r2 / (lam_prev * lam_prev)) /
-                          (lam - lam_prev);
-        if (ca == 0.0) {
-          next = -slope / (2.0 * cb);
-        } else {
-          const double disc = std::max(cb * cb - 3.0 * ca * slope, 0.0);
-          next = (-cb + std::sqrt(disc)) / (3.0 * ca);
-        }
-      }
-      next = std::min(next, 0.5 * lam);
-      next = std::max(next, 0.1 * lam);
-      lam_prev = lam;
-      f_prev = ft;
-      lam = next;
-      ++backtracks;
-    }
+    const double ft = backtracking_line_search(
+        nrm2,
+        [&](double lam) {
+          HIP_OK(launch_waxpy(ut, u, lam, du, n, s));
+          residual(ut, Ft);
+          return 0.5 * device_norm2(P, Ft, n, s);
+        },
+        backtracks);
     HIP_OK(launch_copy(u, ut, n, s));
     std::swap(F, Ft);
     nrm2 = 2.0 * ft;
@@ -3790,6 +3811,7 @@ struct dgs_system {
   int kry_m = 0;
   double *V = nullptr, *Z = nullptr, *partial = nullptr, *h = nullptr, *y = nullptr, *tmp = nullptr;
   double* h_pinned = nullptr;
+  double* d_newton = nullptr;  // Newton work vectors (5 system vectors)
   double t_setup = 0;
 
   dgs_problem* base() const { return var[0]; }
@@ -3829,16 +3851,20 @@ void sys_residual(dgs_system* S, int l, const double* u, const double* b, double
   if (S->coupled) HIP_OK(launch_sys_couple(r, u, S->lv[l].D, S->nv, nd, -1.0, s));
 }
 
+// y = A_sys u on the finest level: each variable's own operator (the curved
+// one when its problem has curved elements), then the couplings
 void sys_apply(dgs_system* S, const double* u, double* y, hipStream_t s) {
-  const dgs_problem* P = S->base();
   const long long nd = S->lv[0].nd;
-  for (int a = 0; a < S->nv; ++a) {
-    const dgs_problem* Pa = S->var[a];
-    const Level& L = Pa->levels[0];
-    HIP_OK(launch_apply(P->N, kApply, u + a * nd, y + a * nd, nullptr, nullptr, nullptr, L.d_nbr,
-                        L.op, Pa->dt, L.acfg_out, s, L.d_order));
-  }
+  for (int a = 0; a < S->nv; ++a) apply_fine(S->var[a], u + a * nd, y + a * nd, s);
   if (S->coupled) HIP_OK(launch_sys_couple(y, u, S->lv[0].D, S->nv, nd, 1.0, s));
+}
+
+// r = b - A_sys u on the finest level with the operators of sys_apply (the
+// V-cycle's residuals stay those of the box grids, sys_residual)
+void sys_residual_fine(dgs_system* S, const double* u, const double* b, double* r, hipStream_t s) {
+  const long long nd = S->lv[0].nd;
+  for (int a = 0; a < S->nv; ++a) residual_fine(S->var[a], u + a * nd, b + a * nd, r + a * nd, s);
+  if (S->coupled) HIP_OK(launch_sys_couple(r, u, S->lv[0].D, S->nv, nd, -1.0, s));
 }
 
 // Subdomain GMRES(k) of the system on level l: rows in SL.rs, corrections
@@ -3928,6 +3954,24 @@ void sys_visit(dgs_system* S, int l, const double* b, double* u, bool u_zero, hi
   sys_schwarz_steps(S, l, b, u, P->opt.post_smooth, false, s);
 }
 
+// Couplings D (nv * nv fields of the finest level) copied into the system and
+// restricted to the coarse levels, D_{l+1} = R D_l field by field
+void sys_set_coupling(dgs_system* sys, const double* D, hipStream_t s) {
+  const dgs_problem* P = sys->base();
+  const int nv = sys->nv;
+  SysLevel& F = sys->lv[0];
+  if (D != F.D)
+    HIP_OK(hipMemcpyAsync(F.D, D, sizeof(double) * nv * nv * F.nd, hipMemcpyDeviceToDevice, s));
+  for (size_t l = 0; l + 1 < sys->lv.size(); ++l) {
+    const Level& L = P->levels[l];
+    const Level& Lc = P->levels[l + 1];
+    for (int ab = 0; ab < nv * nv; ++ab)
+      HIP_OK(launch_restrict(P->N, sys->lv[l].D + ab * sys->lv[l].nd,
+                             sys->lv[l + 1].D + ab * sys->lv[l + 1].nd, L.n, Lc.n, L.split, P->mt, s));
+  }
+  sys->coupled = true;
+}
+
 void sys_ensure_krylov(dgs_system* S, int m) {
   if (S->kry_m >= m) return;
   if (S->kry_m > 0) HIP_OK(hipDeviceSynchronize());
@@ -3950,7 +3994,8 @@ void sys_ensure_krylov(dgs_system* S, int m) {
 
 // FGMRES on the system with one V-cycle per iteration (restarts of the
 // options' length).
-FgmresResult sys_fgmres(dgs_system* S, const double* b, double* x, hipStream_t s) {
+FgmresResult sys_fgmres(dgs_system* S, const double* b, double* x, hipStream_t s,
+                        double rtol = -1.0) {
   const dgs_problem* P = S->base();
   const int max_total = P->opt.max_iter;
   const int m = P->opt.restart > 0 ? std::min(P->opt.restart, max_total) : max_total;
@@ -3966,10 +4011,106 @@ FgmresResult sys_fgmres(dgs_system* S, const double* b, double* x, hipStream_t s
   K.tmp = S->tmp;
   K.pinned = S->h_pinned;
   return fgmres_run(
-      K, P->opt.rtol, max_total, [&](const double* xx, const double* bb, double* out) { sys_residual(S, 0, xx, bb, out, s); },
+      K, rtol > 0.0 ? rtol : P->opt.rtol, max_total,
+      [&](const double* xx, const double* bb, double* out) { sys_residual_fine(S, xx, bb, out, s); },
       [&](const double* z, double* w) { sys_apply(S, z, w, s); },
       [&](const double* v, double* z) { sys_visit(S, 0, v, z, true, s); }, b, x, s);
 }
+
+// Newton-Raphson (Sec. III.A) for a system on curved elements with a
+// monomial source: F_a = A_a(u_a; u_b,a) + M S_a(u) - b_a; each step sets the
+// couplings D = M dS/du, solves blockdiag(A_a) + D by FGMRES with the system
+// V-cycle to linear_rtol, and backtracks the step length.
+struct SysNewtonRun {
+  dgs_system* S = nullptr;
+  MonomialSource ms;
+  const double *bvals = nullptr, *b = nullptr, *mdiag = nullptr;
+  double* u = nullptr;
+  double newton_rtol = 0;
+  hipStream_t s = nullptr;
+  long long nd = 0, n = 0;
+  double *F = nullptr, *Ft = nullptr, *du = nullptr, *ut = nullptr, *work = nullptr;
+  KrylovSpace K;
+  double nrm2 = 0, norm0 = 0;
+  std::vector<double> hist;
+  int its = 0, steps = 0, backtracks = 0;
+  bool converged = false;
+
+  void residual(const double* x, double* out) {
+    for (int a = 0; a < S->nv; ++a) {
+      dgs_problem* Pa = S->var[a];
+      const Level& L0 = Pa->levels[0];
+      HIP_OK(launch_curved_apply_bc(Pa->N, x + a * nd, out + a * nd, bvals ? bvals + a * nd : nullptr,
+                                    Pa->curved, Pa->metric_on ? &Pa->metric : nullptr, L0.d_nbr,
+                                    Pa->penalty, L0.op.neumann, L0.E, s));
+    }
+    HIP_OK(launch_monomial_source(ms, x, mdiag, b, out, nullptr, nd, s));
+  }
+  double norm2(const double* x) { return device_norm2(K, x, s); }
+  void init(dgs_system* sys, const MonomialSource& src, const double* bv, const double* bb, double* uu,
+            double nrt, hipStream_t st) {
+    S = sys;
+    newton_rtol = nrt;
+    ms = src;
+    bvals = bv;
+    b = bb;
+    u = uu;
+    s = st;
+    dgs_problem* P = S->base();
+    nd = S->lv[0].nd;
+    n = (long long)S->nv * nd;
+    mdiag = ensure_mdiag(P, s);
+    const int m = P->opt.restart > 0 ? std::min(P->opt.restart, P->opt.max_iter) : P->opt.max_iter;
+    sys_ensure_krylov(S, m);
+    K.m = m;
+    K.n = n;
+    K.V = S->V;
+    K.Z = S->Z;
+    K.partial = S->partial;
+    K.h = S->h;
+    K.y = S->y;
+    K.tmp = S->tmp;
+    K.pinned = S->h_pinned;
+    if (!S->d_newton) S->d_newton = S->alloc<double>((size_t)5 * n);
+    F = S->d_newton;
+    Ft = F + n;
+    du = F + 2 * n;
+    ut = F + 3 * n;
+    work = F + 4 * n;
+    residual(u, F);
+    nrm2 = norm2(F);
+    if (!std::isfinite(nrm2)) throw DgsError(DGS_ERR_NONFINITE, "non-finite nonlinear residual");
+    norm0 = std::sqrt(nrm2);
+    hist.assign(1, 1.0);
+    converged = norm0 == 0.0;
+  }
+  void step(double linear_rtol) {
+    // the couplings of the linearisation, D = M dS/du, written straight into
+    // the finest level's coupling fields
+    HIP_OK(launch_monomial_source(ms, u, mdiag, nullptr, nullptr, S->lv[0].D, nd, s));
+    sys_set_coupling(S, S->lv[0].D, s);
+    HIP_OK(launch_fill(work, 0.0, n, s));
+    HIP_OK(launch_axpy(work, -1.0, F, n, s));
+    HIP_OK(launch_fill(du, 0.0, n, s));
+    FgmresResult R = sys_fgmres(S, work, du, s, linear_rtol);
+    its += R.iterations;
+    const double ft = backtracking_line_search(
+        nrm2,
+        [&](double lam) {
+          HIP_OK(launch_waxpy(ut, u, lam, du, n, s));
+          residual(ut, Ft);
+          return 0.5 * norm2(Ft);
+        },
+        backtracks);
+    HIP_OK(launch_copy(u, ut, n, s));
+    std::swap(F, Ft);
+    nrm2 = 2.0 * ft;
+    ++steps;
+    hist.push_back(std::sqrt(nrm2) / norm0);
+    converged = std::sqrt(nrm2) <= newton_rtol * norm0;
+    HIP_OK(hipStreamSynchronize(s));
+  }
+};
 
 }  // namespace
 
@@ -4133,18 +4274,86 @@ int dgs_system_set_coupling(dgs_system* sys, const double* D, void* stream) {
       sys->coupled = false;
       return DGS_OK;
     }
-    SysLevel& F = sys->lv[0];
-    HIP_OK(hipMemcpyAsync(F.D, D, sizeof(double) * nv * nv * F.nd, hipMemcpyDeviceToDevice, s));
-    // coarse couplings D_{l+1} = R D_l, field by field
-    for (size_t l = 0; l + 1 < sys->lv.size(); ++l) {
-      const Level& L = P->levels[l];
-      const Level& Lc = P->levels[l + 1];
-      for (int ab = 0; ab < nv * nv; ++ab)
-        HIP_OK(launch_restrict(P->N, sys->lv[l].D + ab * sys->lv[l].nd,
-                               sys->lv[l + 1].D + ab * sys->lv[l + 1].nd, L.n, Lc.n, L.split, P->mt, s));
-    }
-    sys->coupled = true;
+    (void)P;
+    (void)nv;
+    sys_set_coupling(sys, D, s);
     return DGS_OK;
+  });
+}
+
+int dgs_system_set_geometry(dgs_system* sys, const double* xyz, void* stream) {
+  return guarded([&]() -> int {
+    if (!sys) return fail(DGS_ERR_INVALID, "NULL argument");
+    for (dgs_problem* p : sys->var) {
+      const int rc = dgs_set_geometry(p, xyz, stream);
+      if (rc != DGS_OK) return rc;
+    }
+    return DGS_OK;
+  });
+}
+
+int dgs_system_set_metric(dgs_system* sys, const double* ginv, const double* sqrtg, void* stream) {
+  return guarded([&]() -> int {
+    if (!sys) return fail(DGS_ERR_INVALID, "NULL argument");
+    for (dgs_problem* p : sys->var) {
+      const int rc = dgs_set_metric(p, ginv, sqrtg, stream);
+      if (rc != DGS_OK) return rc;
+    }
+    return DGS_OK;
+  });
+}
+
+int dgs_system_newton_solve_powers(dgs_system* sys, int nterms, const int* vars, const int* powers,
+                                   const double* coef, const double* dirichlet, const double* b,
+                                   double* u, double newton_rtol, double linear_rtol, int max_newton,
+                                   dgs_stats* stats, void* stream) {
+  return guarded([&]() -> int {
+    if (!sys || !vars || !powers || !coef || !u) return fail(DGS_ERR_INVALID, "NULL argument");
+    const int nv = sys->nv;
+    if (nterms < 1 || nterms > kMaxMonomials)
+      return fail(DGS_ERR_INVALID, "the sources take 1 to 16 terms");
+    MonomialSource ms;
+    ms.nv = nv;
+    ms.nterm = nterms;
+    ms.coef = coef;
+    for (int t = 0; t < nterms; ++t) {
+      if (vars[t] < 0 || vars[t] >= nv) return fail(DGS_ERR_INVALID, "a term's variable is out of range");
+      ms.var[t] = vars[t];
+      for (int q = 0; q < nv; ++q) {
+        const int k = powers[t * nv + q];
+        if (k < -kMaxPower || k > kMaxPower) return fail(DGS_ERR_INVALID, "powers must lie in [-12, 12]");
+        ms.power[t][q] = k;
+      }
+    }
+    if (!(newton_rtol > 0.0) || !(linear_rtol > 0.0) || max_newton < 1)
+      return fail(DGS_ERR_INVALID, "invalid Newton tolerances");
+    for (const dgs_problem* p : sys->var)
+      if (!p->curved_on)
+        return fail(DGS_ERR_INVALID, "set node coordinates (dgs_system_set_geometry) or a metric first");
+    hipStream_t s = as_stream(stream);
+    const double t0 = now_s();
+    SysNewtonRun nr;
+    nr.init(sys, ms, dirichlet, b, u, newton_rtol, s);
+    while (!nr.converged && nr.steps < max_newton) nr.step(linear_rtol);
+    // the linearisation's couplings are dropped again
+    for (SysLevel& SL : sys->lv) HIP_OK(launch_fill(SL.D, 0.0, (long long)nv * nv * SL.nd, s));
+    sys->coupled = false;
+    HIP_OK(hipStreamSynchronize(s));
+    if (stats) {
+      stats->iterations = nr.its;
+      stats->newton_steps = nr.steps;
+      stats->backtracks = nr.backtracks;
+      stats->rel_residual = std::sqrt(nr.nrm2) / (nr.norm0 > 0 ? nr.norm0 : 1.0);
+      stats->t_solve_s = now_s() - t0;
+      stats->t_setup_s = sys->t_setup;
+      stats->history_len = 0;
+      if (stats->history && stats->history_capacity > 0) {
+        const int m = std::min<int>(stats->history_capacity, (int)nr.hist.size());
+        for (int i = 0; i < m; ++i) stats->history[i] = nr.hist[i];
+        stats->history_len = m;
+      }
+    }
+    return nr.converged ? DGS_OK : DGS_NOT_CONVERGED;
   });
 }
 

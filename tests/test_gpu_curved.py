@@ -312,3 +312,92 @@ def test_power_source_checks():
     with pytest.raises(dg.DgsError):  # u = 0 under a negative power
         prob.newton_solve_powers(coef, (-1,), u=to_gpu(np.zeros(n)))
     prob.close()
+
+
+def _xcts_system(elements, p):
+    mp = omesh.BoxMesh((-1, -1, -1), (1, 1, 1), elements, p, neumann=(4,))  # n.grad psi = 0 at r = 2M
+    mf = omesh.BoxMesh((-1, -1, -1), (1, 1, 1), elements, p)
+    xyz = W.wedge_coordinates(np.stack(mp.node_coordinates()), 2.0, 10.0)
+    G, sg, alpha, terms = W.kerr_schild_xcts(xyz)
+    six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
+    ub = np.stack([np.ones(mp.ndof), alpha.reshape(-1)])
+    vars_ = [a for a in range(2) for _ in terms[a]]
+    powers = [k for a in range(2) for _, k in terms[a]]
+    coef = np.concatenate([np.asarray(c, float).reshape(-1) for a in range(2) for c, _ in terms[a]])
+    return mp, mf, xyz, G, sg, six, alpha.reshape(-1), terms, ub, vars_, powers, coef
+
+
+def _gpu_system(mp, precision, **opts):
+    import paper_2111_06767_amd as dg
+    return dg.System(tuple(mp.lower), tuple(mp.upper), mp.n, mp.p, [(4,), ()], laplacian_bc="matched",
+                     penalty=C, precision=precision, **opts)
+
+
+def test_system_curved_apply_matches_oracle():
+    # the system operator on curved elements and the metric: each variable's
+    # metric operator with its own boundary faces, plus pointwise couplings
+    announce("system apply on a metric")
+    mp, mf, xyz, G, sg, six, alpha, terms, ub, vars_, powers, coef = _xcts_system((2, 2, 2), 3)
+    n = mp.ndof
+    S = _gpu_system(mp, "fp64", mg_levels=1)
+    S.set_geometry(to_gpu(xyz.reshape(-1)))
+    S.set_metric(to_gpu(six), to_gpu(sg.reshape(-1)))
+    D = W.random_uniform(71, 4 * n, 0.0, 2.0)
+    S.set_coupling(to_gpu(D))
+    u = W.random_normal(72, 2 * n)
+    cms = [curved.CurvedMesh(mp, xyz), curved.CurvedMesh(mf, xyz)]
+    ref = np.concatenate([curved.apply_operator_metric(cms[a], u[a * n:(a + 1) * n], C, G, sg) for a in range(2)])
+    ref += np.einsum("abn,bn->an", D.reshape(2, 2, n), u.reshape(2, n)).reshape(-1)
+    assert rel_max(to_np(S.apply(to_gpu(u))), ref) < 1e-12
+    S.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_xcts_hamiltonian_and_lapse_match_oracle(precision):
+    # psi and alpha psi of the XCTS system (eqs. xcts_hamiltonian, xcts_lapse)
+    # on the Kerr-Schild background with the shift fixed, on a wedge from 2M
+    # to 10M: Neumann psi at the inner sphere, Dirichlet data elsewhere, flat
+    # initial guess; the system Newton on the GPU against the oracle's
+    announce(f"xcts hamiltonian + lapse 2x2x2 p=3 {precision}")
+    mp, mf, xyz, G, sg, six, alpha, terms, ub, vars_, powers, coef = _xcts_system((2, 2, 2), 3)
+    n = mp.ndof
+    u_ref, info = onewton.system_newton_solve_powers([mp, mf], xyz, C, terms, ginv=G, sqrtg=sg, dirichlet=ub,
+                                                     levels=2, subdomain_iters=3)
+    S = _gpu_system(mp, precision, mg_levels=2, subdomain_iters=3)
+    S.set_geometry(to_gpu(xyz.reshape(-1)))
+    S.set_metric(to_gpu(six), to_gpu(sg.reshape(-1)))
+    u, st = S.newton_solve_powers(to_gpu(coef), vars_, powers, dirichlet=to_gpu(ub.reshape(-1)))
+    u = to_np(u).reshape(2, n)
+    assert st["converged"], st
+    if precision == "fp64":
+        assert st["newton_steps"] == info["steps"], (st["newton_steps"], info["steps"])
+    assert np.linalg.norm(u - u_ref) <= 1e-9 * np.linalg.norm(u_ref)
+    # the oracle's own nonlinear residual of the GPU solution
+    cms = [curved.CurvedMesh(mp, xyz), curved.CurvedMesh(mf, xyz)]
+    Mg = (sg * curved.mass_diagonal(cms[0])).reshape(-1)
+
+    def F(v):
+        Av = np.stack([curved.apply_operator_metric(cms[a], v[a], C, G, sg, dirichlet_values=ub[a])
+                       for a in range(2)])
+        return Av + Mg * onewton.monomial_source(terms, v)[0]
+
+    assert np.linalg.norm(F(u)) <= 1e-10 * np.linalg.norm(F(np.ones((2, n))))
+    assert np.abs(u[0] - 1.0).max() < 1e-5 and np.abs(u[1] - alpha).max() < 1e-3
+    S.close()
+
+
+def test_system_newton_checks():
+    import paper_2111_06767_amd as dg
+    announce("system newton checks")
+    mp = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (2, 1, 1), 2)
+    S = _gpu_system(mp, "fp64", mg_levels=1)
+    n = mp.ndof
+    coef = to_gpu(np.ones(n))
+    with pytest.raises(dg.DgsError):  # no curved elements yet
+        S.newton_solve_powers(coef, [0], [(1, 0)])
+    S.set_geometry(to_gpu(np.stack(mp.node_coordinates()).reshape(-1)))
+    with pytest.raises(dg.DgsError):  # variable out of range
+        S.newton_solve_powers(coef, [2], [(1, 0)])
+    with pytest.raises(dg.DgsError):  # power out of range
+        S.newton_solve_powers(coef, [0], [(13, 0)])
+    S.close()
