@@ -401,3 +401,52 @@ def test_system_newton_checks():
     with pytest.raises(dg.DgsError):  # power out of range
         S.newton_solve_powers(coef, [0], [(13, 0)])
     S.close()
+
+
+def _sampled_patches(n, seed, count=6):
+    rng = np.random.default_rng(seed)
+    samples = [np.array(c) for c in [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n // 2, n - 1), (n // 3, 0, 2)]]
+    return samples + [rng.integers(0, n, 3) for _ in range(count)]
+
+
+@pytest.mark.parametrize("case", ["deformed_pullback", "wedge_kerr_schild"])
+def test_metric_apply_full_size_sampled(case):
+    # the 16^3, p = 7 grids of the benchmark's metric and lapse legs: the GPU
+    # operator on the whole grid, the oracle on the 3 x 3 x 3 patch of elements
+    # around each sampled element (its result depends only on the element and
+    # its face neighbours)
+    n, p = 16, 7
+    N = p + 1
+    announce(f"metric apply 16^3 p=7 sampled, {case}")
+    if case == "deformed_pullback":
+        box = omesh.BoxMesh((0, 0, 0), (1, 1, 1), (n, n, n), p)
+        xyz = curved.deformed_box(box, 0.1)
+        _, G, sg = W.pullback_metric(xyz, box.lower, box.upper, 0.15)
+    else:
+        box = omesh.BoxMesh((-1, -1, -1), (1, 1, 1), (n, n, n), p)
+        xyz = W.wedge_coordinates(np.stack(box.node_coordinates()), 2.0, 10.0).reshape(3, box.E, N, N, N)
+        G, sg, _, _, _ = W.kerr_schild_lapse(xyz)
+    six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
+    prob = _problem(box, mg_levels=1)
+    prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    prob.set_metric(to_gpu(six), to_gpu(sg.reshape(-1)))
+    u = W.random_normal(73, box.ndof)
+    got = to_np(prob.apply(to_gpu(u))).reshape(n, n, n, N, N, N)
+    prob.close()
+    ug = u.reshape(n, n, n, N, N, N)
+    xg = xyz.reshape(3, n, n, n, N, N, N)
+    Gg = G.reshape(3, 3, n, n, n, N, N, N)
+    sgg = sg.reshape(n, n, n, N, N, N)
+    hx = (box.upper - box.lower) / n
+    for c in _sampled_patches(n, 2):
+        lo = np.maximum(c - 1, 0)
+        hi = np.minimum(c + 2, n)
+        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        pm = omesh.BoxMesh(box.lower + lo * hx, box.lower + hi * hx, tuple(hi - lo), p)
+        pxyz = xg[(slice(None),) + sl].reshape(3, -1, N, N, N)
+        pcm = curved.CurvedMesh(pm, pxyz)
+        pG = Gg[(slice(None), slice(None)) + sl].reshape(3, 3, -1, N, N, N)
+        psg = sgg[sl].reshape(-1, N, N, N)
+        ref = curved.apply_operator_metric(pcm, ug[sl].reshape(-1), C, pG, psg).reshape(-1, N, N, N)
+        e = pm.elem_index(*(c - lo))
+        assert rel_max(got[c[2], c[1], c[0]], ref[e]) < 1e-12, (case, c)
