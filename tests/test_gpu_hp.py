@@ -154,3 +154,34 @@ def test_hp_limits():
         dg.HpProblem((0, 0, 0), (2, 1, 1), (2, 1, 1), [(1, 1, 1), (0, 0, 0)], [(2, 2, 2)] * 8)
     with pytest.raises(dg.DgsError):  # the V-cycle only
         dg.HpProblem((0, 0, 0), (1, 1, 1), (1, 1, 1), [(0, 0, 0)], [(2, 2, 2)], cycle=2)
+
+
+def test_hp_checkerboard_full_size():
+    # the benchmark's hp workload (2 x 2 x 2 blocks in a checkerboard of 8^3
+    # elements of degree 5 and 4^3 of degree 7: every block face nonconforming
+    # in h and p; 573,440 points): the operator against the oracle's on the
+    # whole mesh, and FP64 and mixed solves through the oracle's operator
+    import paper_2111_06767_amd as dg
+    announce("hp checkerboard full size")
+    levels, degrees = [], []
+    for b in range(8):
+        fine = (b % 2 + (b // 2) % 2 + b // 4) % 2 == 0
+        L = 3 if fine else 2
+        levels.append((L, L, L))
+        degrees += [(5, 5, 5) if fine else (7, 7, 7)] * (8 ** L)
+    m = hp.HpMesh((0, 0, 0), (1, 1, 1), (2, 2, 2), levels, np.asarray(degrees))
+    u = W.random_normal(74, m.ndof)
+    x, y, z = m.node_coordinates()
+    b = hp.apply_mass(m, W.sin_product_source(x, y, z))
+    for precision in ("fp64", "mixed"):
+        prob = dg.HpProblem((0, 0, 0), (1, 1, 1), (2, 2, 2), levels, degrees, penalty=C, mg_levels=4,
+                            precision=precision)
+        assert prob.ndof == m.ndof == 573440
+        if precision == "fp64":
+            got = to_np(prob.apply(to_gpu(u)))
+            assert rel_max(got, hp.apply_operator(m, u, C)) < 1e-12
+        sol, st = prob.solve(to_gpu(b))
+        prob.close()
+        assert st["converged"] and st["iterations"] <= 15, st
+        r = b - hp.apply_operator(m, to_np(sol), C)
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b), precision
