@@ -145,13 +145,16 @@ int dgs_num_dofs(const dgs_problem* prob, long long* n);
 /* Physical coordinates of every point: xyz[d * ndof + idx], d = x, y, z. */
 int dgs_node_coordinates(const dgs_problem* prob, double* xyz, void* stream);
 
-/* b = M f with the LGL-quadrature mass matrix M = J w_i w_j w_k (eq. massmat). */
+/* b = M f with the LGL-quadrature mass matrix M = J w_i w_j w_k (eq. massmat);
+ * J = det(J) at each point on curved elements (dgs_set_geometry), times
+ * sqrt(g) on a background metric (dgs_set_metric). */
 int dgs_apply_mass(const dgs_problem* prob, const double* f, double* b, void* stream);
 
 /* Au = A u: the left-hand side of eq. dg_op_primal for the Poisson fluxes
  * (eq. poisson_fluxform) with homogeneous Dirichlet boundaries, homogeneous
- * Neumann on the faces the options' neumann_faces names (eq. bc).  u and Au
- * must not overlap. */
+ * Neumann on the faces the options' neumann_faces names (eq. bc); the curved
+ * operator once dgs_set_geometry or dgs_set_metric has been called.  u and
+ * Au must not overlap. */
 int dgs_apply_operator(dgs_problem* prob, const double* u, double* Au, void* stream);
 
 /* u <- u + sum of `steps` additive Schwarz iterations on A u = b on the
