@@ -2,6 +2,9 @@
 conjugate gradients for symmetric positive definite problems (Sec. III.B;
 Saad 2003, Alg. 9.1).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's
+CPU leg, never by the product path.
+
 One operator application and one preconditioner application per iteration;
 the new basis vector is orthogonalised against all previous ones (modified
 Gram-Schmidt), the small least-squares problem is updated with Givens

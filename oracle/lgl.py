@@ -1,5 +1,8 @@
 """Legendre-Gauss-Lobatto collocation (Sec. II, eqs. field_expansion, lagrprod).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's
+CPU leg, never by the product path.
+
 Fields are nodal values at N = p+1 LGL points per dimension; the basis is the
 tensor product of 1D Lagrange polynomials through those points.  The 1D
 Lagrange polynomials are evaluated with the textbook barycentric weights.

@@ -1,5 +1,8 @@
 """Axis-aligned box of uniform elements (Sec. II, blocks split into elements).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's
+CPU leg, never by the product path.
+
 One block, the box [lo, hi], split into n_x * n_y * n_z equal elements.  Each
 element carries N = p+1 LGL points per dimension.  Nodal arrays have shape
 (..., E, N, N, N) indexed [e, k, j, i] with the x index i fastest and the

@@ -1,5 +1,8 @@
 """Geometric multigrid V-cycle with Schwarz smoothing (Sec. III.C).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's
+CPU leg, never by the product path.
+
 * hierarchy (Sec. III.C.1, Fig. mg_hierarchy): level l+1 merges two elements
   into one along every dimension; all elements share one degree p here.
 * prolongation (eq. prol): Lagrange interpolation from the parent to the child

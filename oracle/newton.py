@@ -1,5 +1,8 @@
 """Newton-Raphson with a backtracking line search (Sec. III.A, eq. linearized).
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's
+CPU leg, never by the product path.
+
 The nonlinear DG residual is F(u) = A u + M S(u) - b, with the linear flux
 part A of Sec. II and a pointwise source S.  Each step solves the linearised
 problem (dA/du)(u) du = b - A(u) with preconditioned flexible GMRES to a

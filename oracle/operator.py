@@ -1,5 +1,8 @@
 """Strong DG operator of the Poisson equation in first-order flux form.
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's
+CPU leg, never by the product path.
+
 Follows Sec. II literally:
 
 * Poisson fluxes (eq. poisson_fluxform): F_v^i_j = u delta^i_j, S_v = v

@@ -1,5 +1,8 @@
 """Additive Schwarz smoother on element-centred overlapping subdomains.
 
+Test infrastructure only: imported by the tests, smoke() and the benchmark's
+CPU leg, never by the product path.
+
 Follows Sec. III.D:
 
 * geometry (Sec. III.D.1, Fig. subdomain_structure): subdomain S_k is the
