@@ -548,7 +548,8 @@ def lapse_leg(dg, precision, steps=3, warmup=1):
                 max_error_vs_analytic_lapse=err)
 
 
-def xcts_leg(dg, precision, steps=2, warmup=1, laplacian_bc="matched", k=3):
+def xcts_leg(dg, precision, steps=2, warmup=1, laplacian_bc="matched", k=3, elements=None, p=None,
+             levels=None):
     """The Hamiltonian and lapse equations of the XCTS system for psi and
     alpha psi on the Kerr-Schild background (shift held at its Kerr-Schild
     value) on one wedge (r from 2M to 10M) as 16^3 elements of p = 7: psi
@@ -558,12 +559,15 @@ def xcts_leg(dg, precision, steps=2, warmup=1, laplacian_bc="matched", k=3):
     import torch
     import workloads as W
     lower, upper = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
-    X = dg.points(lower, upper, C5["elements"], C5["p"])
+    elements = elements or C5["elements"]
+    p = p or C5["p"]
+    levels = levels or C5["levels"]
+    X = dg.points(lower, upper, elements, p)
     xyz = W.wedge_coordinates(X, 2.0, 10.0)
     G, sg, alpha, terms = W.kerr_schild_xcts(xyz)
     six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
-    S = dg.System(lower, upper, C5["elements"], C5["p"], [(4,), ()], laplacian_bc=laplacian_bc, penalty=1.5,
-                  mg_levels=C5["levels"], precision=precision, subdomain_iters=k)
+    S = dg.System(lower, upper, elements, p, [(4,), ()], laplacian_bc=laplacian_bc, penalty=1.5,
+                  mg_levels=levels, precision=precision, subdomain_iters=k)
     S.set_geometry(torch.as_tensor(xyz.reshape(-1)).cuda())
     S.set_metric(torch.as_tensor(six).cuda(), torch.as_tensor(sg.reshape(-1)).cuda())
     n = S.ndof
@@ -994,6 +998,15 @@ def main():
             _log(f"XCTS Hamiltonian and lapse, fp64, {bc} Laplacian approximation, k={k}")
             curved[f"xcts_psi_lapse_16^3_p7_fp64_{bc}_k{k}"] = xcts_leg(dg, "fp64", steps=1,
                                                                          laplacian_bc=bc, k=k)
+        # scale independence: FGMRES iterations of the whole Newton solve as
+        # the wedge is refined (p = 5, matched approximation, k = 1)
+        scaling = {}
+        for n, lv in ((4, 2), (8, 3), (16, 4), (32, 5)):
+            _log(f"XCTS Hamiltonian and lapse, {n}^3 p=5 (scale independence)")
+            r = xcts_leg(dg, "fp64", steps=1, k=1, elements=(n, n, n), p=5, levels=lv)
+            scaling[f"{n}^3"] = {key: r[key] for key in ("ms", "newton_steps", "linear_iterations",
+                                                          "max_error_psi", "max_error_lapse")}
+        curved["xcts_psi_lapse_p5_refinement"] = scaling
         _log("curved apply on a background metric 24^3 p=7")
         curved["metric_apply_24^3_p7"] = time_curved_apply(dg, (24, 24, 24), 7, metric_amplitude=0.15)
 
