@@ -358,6 +358,8 @@ struct HpLevel {
   std::vector<HpTerm> terms;
   HpElem* d_el = nullptr;
   HpTerm* d_terms = nullptr;
+  std::vector<int> order;  // launch order of the operator: most mortar terms first
+  int* d_order = nullptr;
   double *r = nullptr, *b = nullptr, *u = nullptr;
   // Schwarz
   std::vector<ClassInfo> cls;
@@ -746,6 +748,23 @@ void upload_level_mesh(dgs_hp_problem* P, HpLevel& L, hipStream_t s) {
   upload(L.d_el, L.hel, s);
   L.d_terms = P->alloc<HpTerm>(L.terms.size());
   upload(L.d_terms, L.terms, s);
+  // an element's work grows with its mortar terms (each a serial chain of
+  // tensor passes) and its points: the costly ones are launched first
+  const int E = (int)L.hel.size();
+  std::vector<int>& order = L.order;  // kept: the upload may still read it
+  order.resize(E);
+  std::vector<long long> cost(E);
+  for (int e = 0; e < E; ++e) {
+    const HpElem& H = L.hel[e];
+    long long c = (long long)H.N[0] * H.N[1] * H.N[2];
+    for (int f = 0, t = H.term0; f < 6; t += H.nterm[f], ++f)
+      if (!L.terms[t].direct) c += 512LL * H.nterm[f];
+    order[e] = e;
+    cost[e] = c;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  L.d_order = P->alloc<int>(E);
+  upload(L.d_order, order, s);
   L.r = P->alloc<double>(L.mesh.ndof);
   L.b = P->alloc<double>(L.mesh.ndof);
   L.u = P->alloc<double>(L.mesh.ndof);
@@ -998,12 +1017,14 @@ void build_transfer(dgs_hp_problem* P, HpLevel& F, const HpLevel& Cl, const std:
 
 void hp_residual(dgs_hp_problem* P, int l, const double* u, const double* b, double* r, hipStream_t s) {
   HpLevel& L = *P->lv[l];
-  HIP_OK(launch_hp_apply(true, u, r, b, L.d_el, L.mesh.E(), L.d_terms, P->d_pool, P->rule, 1, 0, s));
+  HIP_OK(launch_hp_apply(true, u, r, b, L.d_el, L.mesh.E(), L.d_terms, P->d_pool, P->rule, 1, 0, s,
+                         L.d_order));
 }
 
 void hp_apply(dgs_hp_problem* P, int l, const double* u, double* y, hipStream_t s) {
   HpLevel& L = *P->lv[l];
-  HIP_OK(launch_hp_apply(false, u, y, nullptr, L.d_el, L.mesh.E(), L.d_terms, P->d_pool, P->rule, 1, 0, s));
+  HIP_OK(launch_hp_apply(false, u, y, nullptr, L.d_el, L.mesh.E(), L.d_terms, P->d_pool, P->rule, 1, 0, s,
+                         L.d_order));
 }
 
 // Additive Schwarz steps (Sec. III.D.5) on level l: residual, gather into

@@ -75,9 +75,12 @@ struct HpChild {
 
 // out = A u (residual: b - A u) for elements [0, E) of a mesh or of
 // `copies` copies of a set-up patch (copy c reads and writes at c * copy_stride).
+// order (optional): workgroup w takes element order[w] (the most expensive
+// elements first, so that their longer chains of face terms start early).
 hipError_t launch_hp_apply(bool residual, const double* u, double* out, const double* b,
                            const HpElem* el, int E, const HpTerm* terms, const double* pool,
-                           const HpRule& R, int copies, long long copy_stride, hipStream_t s);
+                           const HpRule& R, int copies, long long copy_stride, hipStream_t s,
+                           const int* order = nullptr);
 hipError_t launch_hp_mass(const double* f, double* out, const HpElem* el, int E, const HpRule& R,
                           hipStream_t s);
 // node coordinates: plo (3 per element, the lower corner) and h (3 per element)

@@ -39,13 +39,14 @@ template <bool RES>
 __global__ void __launch_bounds__(kHpThreads)
     k_hp_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ b,
                const HpElem* __restrict__ el, const HpTerm* __restrict__ terms,
-               const double* __restrict__ pool, HpRule R, long long copy_stride) {
+               const double* __restrict__ pool, HpRule R, long long copy_stride,
+               const int* __restrict__ order) {
   __shared__ double su[kHpMaxNodes];
   __shared__ double sg[3][kHpMaxNodes];
   __shared__ double scu[6][kF], scp[6][kF];
   __shared__ double fa[kF], fb[kF], oa[kF], ob[kF], ma[kF], mb[kF], na[kF], nbv[kF];
   __shared__ double smat[4][kF];
-  const HpElem E = el[blockIdx.x];
+  const HpElem E = el[order ? order[blockIdx.x] : (int)blockIdx.x];
   const long long cbase = (long long)blockIdx.y * copy_stride;
   const long long base = cbase + E.off;
   const int N0 = E.N[0], N1 = E.N[1], N2 = E.N[2];
@@ -450,15 +451,16 @@ unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_hp_apply(bool residual, const double* u, double* out, const double* b,
                            const HpElem* el, int E, const HpTerm* terms, const double* pool,
-                           const HpRule& R, int copies, long long copy_stride, hipStream_t s) {
+                           const HpRule& R, int copies, long long copy_stride, hipStream_t s,
+                           const int* order) {
   if (E <= 0 || copies <= 0) return hipSuccess;
   const dim3 grid((unsigned)E, (unsigned)copies);
   if (residual)
     hipLaunchKernelGGL(k_hp_apply<true>, grid, dim3(kHpThreads), 0, s, u, out, b, el, terms, pool, R,
-                       copy_stride);
+                       copy_stride, order);
   else
     hipLaunchKernelGGL(k_hp_apply<false>, grid, dim3(kHpThreads), 0, s, u, out, b, el, terms, pool, R,
-                       copy_stride);
+                       copy_stride, order);
   return hipGetLastError();
 }
 
