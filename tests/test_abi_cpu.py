@@ -96,3 +96,23 @@ def test_hp_mesh_validation_without_gpu():
         assert create(blocks, levels, degrees, **opts) == m.DGS_ERR_INVALID, (levels, degrees, opts)
         assert lib.dgs_last_error().decode() != ""
     assert "balanced" in (create(*cases[0][:3]) and lib.dgs_last_error().decode())
+
+
+def test_curved_and_newton_entries_reject_null_handles_without_gpu():
+    # the metric, geometry and power-source Newton entries validate their
+    # handles and sizes on the host before any device call
+    import ctypes
+    import paper_2111_06767_amd as m
+    if not os.path.exists(m.api.LIB_PATH):
+        pytest.skip("library not built")
+    lib = m.load_library()
+    pw = (ctypes.c_int * 2)(1, 0)
+    va = (ctypes.c_int * 1)(0)
+    assert lib.dgs_set_metric(None, None, None, None) == m.DGS_ERR_INVALID
+    assert lib.dgs_system_set_metric(None, None, None, None) == m.DGS_ERR_INVALID
+    assert lib.dgs_system_set_geometry(None, None, None) == m.DGS_ERR_INVALID
+    assert lib.dgs_newton_solve_powers(None, 1, pw, None, None, None, None, 1e-10, 1e-4, 5, None,
+                                       None) == m.DGS_ERR_INVALID
+    assert lib.dgs_system_newton_solve_powers(None, 1, va, pw, None, None, None, None, 1e-10, 1e-4, 5,
+                                              None, None) == m.DGS_ERR_INVALID
+    assert lib.dgs_last_error().decode() != ""
