@@ -18,6 +18,18 @@ namespace {
 constexpr int kHpThreads = 256;
 constexpr int kNodesPerThread = kHpMaxNodes / kHpThreads;
 constexpr int kF = kHpMaxN * kHpMaxN;  // points of a face or mortar
+static_assert(kF <= 64, "a face's points fit one wavefront");
+// wavefronts that take mortar faces side by side (LDS: 3 KB each)
+constexpr int kMortarWaves = 3;
+static_assert(kMortarWaves <= kHpThreads / 64, "one wavefront per mortar face");
+
+// Orders the LDS accesses of one wavefront: its lanes exchange data through
+// LDS between the passes of a mortar term, with no other wave involved.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Select one of three values by a dimension index without a runtime-indexed
 // private array (those go to scratch memory).
@@ -44,8 +56,7 @@ __global__ void __launch_bounds__(kHpThreads)
   __shared__ double su[kHpMaxNodes];
   __shared__ double sg[3][kHpMaxNodes];
   __shared__ double scu[6][kF], scp[6][kF];
-  __shared__ double fa[kF], fb[kF], oa[kF], ob[kF], ma[kF], mb[kF], na[kF], nbv[kF];
-  __shared__ double smat[4][kF];
+  __shared__ double wb[kMortarWaves][6][kF];  // per-wave mortar buffers
   const HpElem E = el[order ? order[blockIdx.x] : (int)blockIdx.x];
   const long long cbase = (long long)blockIdx.y * copy_stride;
   const long long base = cbase + E.off;
@@ -139,30 +150,41 @@ __global__ void __launch_bounds__(kHpThreads)
     scu[f][q] = 0.5 * (ue - ui);
     scp[f][q] = 0.5 * sgn * (dui + due) - T.sigma * (ui - ue);
   }
-  // pass 2: mortars of nonconforming faces.  Per term, the premultiplied
-  // matrices A = P I_own and B = P I_nb (staged in LDS) carry the element's
-  // and the neighbour's face data through the mortar and back to the
-  // element's face points; the fluxes of eq. numflux combine them there
+  // pass 2: mortars of nonconforming faces.  The terms of one face are taken
+  // in sequence by one wavefront (a face writes only its own corrections), so
+  // up to kMortarWaves faces proceed side by side; within the wave every lane
+  // holds one face point (at most kF).  Per term, the premultiplied matrices
+  // A = P I_own and B = P I_nb (read from the pool) carry the element's and
+  // the neighbour's face data through the mortar and back to the element's
+  // face points; the fluxes of eq. numflux combine them there.
   if (any_mortar) {
-    int t = E.term0;
-#pragma unroll
+    const int wave = tid >> 6, q = tid & 63;
+    int c = 0, t = E.term0;
+#pragma unroll 1
     for (int f = 0; f < 6; ++f) {
+      const int ntf = f < 3 ? pick(f, E.nterm[0], E.nterm[1], E.nterm[2])
+                            : pick(f - 3, E.nterm[3], E.nterm[4], E.nterm[5]);
       const int tf = t;
-      t += E.nterm[f];
-      if (nd[f] > 0) continue;
+      t += ntf;
+      if (terms[tf].direct) continue;
+      const bool mine = (c % kMortarWaves) == wave;
+      ++c;
+      if (!mine) continue;
+      double* oa = wb[wave][0];
+      double* ob = wb[wave][1];
+      double* ma = wb[wave][2];
+      double* mb = wb[wave][3];
+      double* na = wb[wave][4];
+      double* nbv = wb[wave][5];
       const int d = f >> 1;
       const double sgn = (f & 1) ? 1.0 : -1.0;
       const int n0 = d == 0 ? N1 : N0, n1 = d == 2 ? N1 : N2;
       const int Nd = pick(d, N0, N1, N2);
       const int od = (f & 1) ? Nd - 1 : 0;
-      for (int q = tid; q < n0 * n1; q += blockDim.x) {
-        const int p = face_node(d, od, q % n0, q / n0, N0, N1);
-        scu[f][q] = 0.0;
-        scp[f][q] = 0.0;
-        fa[q] = su[p];
-        fb[q] = sg[d][p];
-      }
-      for (int k = 0; k < E.nterm[f]; ++k) {
+      const bool qon = q < n0 * n1;
+      const int qi = q % n0, qj = q / n0;
+      double cu = 0.0, cp = 0.0;
+      for (int k = 0; k < ntf; ++k) {
         const HpTerm T = terms[tf + k];
         int m0 = 0, m1 = 0, FN = 2, FN0 = 1, FN1 = 1;
         long long foff = 0;
@@ -176,76 +198,67 @@ __global__ void __launch_bounds__(kHpThreads)
           FN1 = F.N[1];
           foff = F.off;
           frh = pick(d, F.rh[0], F.rh[1], F.rh[2]);
-        }
-        for (int q = tid; q < 4 * kF; q += blockDim.x) {
-          const int mi = q / kF, e = q - mi * kF;
-          const int off = mi == 0 ? T.A0 : (mi == 1 ? T.A1 : (mi == 2 ? T.B0 : T.B1));
-          const int size = mi == 0 ? n0 * n0 : (mi == 1 ? n1 * n1 : (mi == 2 ? n0 * m0 : n1 * m1));
-          if (off >= 0 && e < size) smat[mi][e] = pool[off + e];
-        }
-        if (T.nb >= 0) {
           // the neighbour's trace and normal derivative on its own face points
-          const int fod = (f & 1) ? 0 : FN - 1;
-          const double* D = R.D + (FN - 2) * 64 + fod * FN;
-          const int strd = pick(d, 1, FN0, FN0 * FN1);
-          const double* fu = u + cbase + foff;
-          for (int q = tid; q < m0 * m1; q += blockDim.x) {
-            const double* line = fu + face_node(d, 0, q % m0, q / m0, FN0, FN1);
+          if (q < m0 * m1) {
+            const int fod = (f & 1) ? 0 : FN - 1;
+            const double* D = R.D + (FN - 2) * 64 + fod * FN;
+            const int strd = pick(d, 1, FN0, FN0 * FN1);
+            const double* line = u + cbase + foff + face_node(d, 0, q % m0, q / m0, FN0, FN1);
             double acc = 0.0;
             for (int m = 0; m < FN; ++m) acc += D[m] * line[m * strd];
             oa[q] = line[fod * strd];
             ob[q] = frh * acc;
           }
         }
-        __syncthreads();
-        const double* A0 = T.A0 >= 0 ? smat[0] : nullptr;
-        const double* A1 = T.A1 >= 0 ? smat[1] : nullptr;
-        const double* B0 = T.B0 >= 0 ? smat[2] : nullptr;
-        const double* B1 = T.B1 >= 0 ? smat[3] : nullptr;
-        // along t0: own data [n1][n0] -> [n1][n0], neighbour data [m1][m0] -> [m1][n0]
-        for (int q = tid; q < n1 * n0; q += blockDim.x) {
-          const int j = q / n0, i = q - j * n0;
-          double a = 0.0, c = 0.0;
+        wave_sync();
+        const double* A0 = T.A0 >= 0 ? pool + T.A0 : nullptr;
+        const double* A1 = T.A1 >= 0 ? pool + T.A1 : nullptr;
+        const double* B0 = T.B0 >= 0 ? pool + T.B0 : nullptr;
+        const double* B1 = T.B1 >= 0 ? pool + T.B1 : nullptr;
+        // along t0: own data [n1][n0] -> [n1][n0] (read from the element's
+        // trace and derivative in place), neighbour data [m1][m0] -> [m1][n0]
+        if (qon) {
+          double a = 0.0, cc = 0.0;
           if (A0) {
             for (int m = 0; m < n0; ++m) {
-              const double w = A0[i * n0 + m];
-              a += w * fa[j * n0 + m];
-              c += w * fb[j * n0 + m];
+              const double w = A0[qi * n0 + m];
+              const int p = face_node(d, od, m, qj, N0, N1);
+              a += w * su[p];
+              cc += w * sg[d][p];
             }
           } else {
-            a = fa[q];
-            c = fb[q];
+            const int p = face_node(d, od, qi, qj, N0, N1);
+            a = su[p];
+            cc = sg[d][p];
           }
           ma[q] = a;
-          mb[q] = c;
+          mb[q] = cc;
         }
-        if (T.nb >= 0)
-          for (int q = tid; q < m1 * n0; q += blockDim.x) {
-            const int j = q / n0, i = q - j * n0;
-            double a = 0.0, c = 0.0;
-            if (B0) {
-              for (int m = 0; m < m0; ++m) {
-                const double w = B0[i * m0 + m];
-                a += w * oa[j * m0 + m];
-                c += w * ob[j * m0 + m];
-              }
-            } else {
-              a = oa[j * m0 + i];
-              c = ob[j * m0 + i];
-            }
-            na[q] = a;
-            nbv[q] = c;
-          }
-        __syncthreads();
-        // along t1, then the fluxes (a zero neighbour contributes nothing)
-        for (int q = tid; q < n1 * n0; q += blockDim.x) {
+        if (T.nb >= 0 && q < m1 * n0) {
           const int j = q / n0, i = q - j * n0;
+          double a = 0.0, cc = 0.0;
+          if (B0) {
+            for (int m = 0; m < m0; ++m) {
+              const double w = B0[i * m0 + m];
+              a += w * oa[j * m0 + m];
+              cc += w * ob[j * m0 + m];
+            }
+          } else {
+            a = oa[j * m0 + i];
+            cc = ob[j * m0 + i];
+          }
+          na[q] = a;
+          nbv[q] = cc;
+        }
+        wave_sync();
+        // along t1, then the fluxes (a zero neighbour contributes nothing)
+        if (qon) {
           double hu = 0.0, hd = 0.0, gu = 0.0, gd = 0.0;
           if (A1) {
             for (int m = 0; m < n1; ++m) {
-              const double w = A1[j * n1 + m];
-              hu += w * ma[m * n0 + i];
-              hd += w * mb[m * n0 + i];
+              const double w = A1[qj * n1 + m];
+              hu += w * ma[m * n0 + qi];
+              hd += w * mb[m * n0 + qi];
             }
           } else {
             hu = ma[q];
@@ -254,19 +267,23 @@ __global__ void __launch_bounds__(kHpThreads)
           if (T.nb >= 0) {
             if (B1) {
               for (int m = 0; m < m1; ++m) {
-                const double w = B1[j * m1 + m];
-                gu += w * na[m * n0 + i];
-                gd += w * nbv[m * n0 + i];
+                const double w = B1[qj * m1 + m];
+                gu += w * na[m * n0 + qi];
+                gd += w * nbv[m * n0 + qi];
               }
             } else {
               gu = na[q];
               gd = nbv[q];
             }
           }
-          scu[f][q] += 0.5 * (gu - hu);
-          scp[f][q] += 0.5 * sgn * (hd + gd) - T.sigma * (hu - gu);
+          cu += 0.5 * (gu - hu);
+          cp += 0.5 * sgn * (hd + gd) - T.sigma * (hu - gu);
         }
-        __syncthreads();
+        wave_sync();  // the next term overwrites this wave's buffers
+      }
+      if (qon) {
+        scu[f][q] = cu;
+        scp[f][q] = cp;
       }
     }
   }
