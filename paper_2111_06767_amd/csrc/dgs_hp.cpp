@@ -291,6 +291,9 @@ void build_terms(const HMesh& m, double C, MatPool& pool, std::vector<HpElem>& h
         HpTerm T{};
         T.nb = g;
         T.sigma = C * std::pow((double)std::max(E.N[d], F.N[d]), 2) / std::min(E.h[d], F.h[d]);
+        T.foff = F.off;
+        for (int q = 0; q < 3; ++q) T.fN[q] = F.N[q];
+        T.frh = 2.0 / F.h[d];
         int* As[2] = {&T.A0, &T.A1};
         int* Bs[2] = {&T.B0, &T.B1};
         const int ts[2] = {t0, t1};
@@ -475,6 +478,15 @@ Patch make_patch(const HMesh& m, const std::vector<HpElem>& hel, const std::vect
     for (int g : m.nbr[e][f]) P.elems.push_back(g);
   std::map<int, int> local;
   for (int i = 0; i < (int)P.elems.size(); ++i) local[P.elems[i]] = i;
+  std::vector<long long> loff(P.elems.size());  // patch-local first nodes
+  {
+    long long o = 0;
+    for (size_t i = 0; i < P.elems.size(); ++i) {
+      const HpElem& H = hel[P.elems[i]];
+      loff[i] = o;
+      o += (long long)H.N[0] * H.N[1] * H.N[2];
+    }
+  }
   for (int g : P.elems) {
     HpElem H = hel[g];
     H.off = P.ndof;
@@ -488,6 +500,7 @@ Patch make_patch(const HMesh& m, const std::vector<HpElem>& hel, const std::vect
       if (T.nb >= 0) {
         auto it = local.find(T.nb);
         T.nb = it == local.end() ? kHpZero : it->second;
+        T.foff = T.nb >= 0 ? loff[T.nb] : 0;
       }
       P.terms.push_back(T);
     }

@@ -34,6 +34,12 @@ struct HpTerm {
   int A0, A1;    // P I_own per transverse dimension
   int B0, B1;    // P I_nb per transverse dimension
   double sigma;  // penalty (eq. penalty)
+  // the neighbour's first node, points per dimension and 2 / h along the
+  // face normal (copies of its HpElem fields, so that its face data can be
+  // read without first loading its element record)
+  long long foff;
+  int fN[3];
+  double frh;
 };
 
 struct HpElem {

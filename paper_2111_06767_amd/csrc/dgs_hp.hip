@@ -129,16 +129,15 @@ __global__ void __launch_bounds__(kHpThreads)
     const double ui = su[p], dui = sg[d][p];
     double ue, due;
     if (T.nb >= 0) {
-      const HpElem F = el[T.nb];
-      const int FN = pick(d, F.N[0], F.N[1], F.N[2]);
+      const int FN = pick(d, T.fN[0], T.fN[1], T.fN[2]);
       const int fod = (f & 1) ? 0 : FN - 1;
       const double* D = R.D + (FN - 2) * 64 + fod * FN;
-      const int strd = pick(d, 1, F.N[0], F.N[0] * F.N[1]);
-      const double* line = u + cbase + F.off + face_node(d, 0, b0, b1, F.N[0], F.N[1]);
+      const int strd = pick(d, 1, T.fN[0], T.fN[0] * T.fN[1]);
+      const double* line = u + cbase + T.foff + face_node(d, 0, b0, b1, T.fN[0], T.fN[1]);
       double acc = 0.0;
       for (int m = 0; m < FN; ++m) acc += D[m] * line[m * strd];
       ue = line[fod * strd];
-      due = pick(d, F.rh[0], F.rh[1], F.rh[2]) * acc;
+      due = T.frh * acc;
     } else if (T.nb == kHpZero) {  // a zero neighbour (set-up patches)
       ue = 0.0;
       due = 0.0;
@@ -190,14 +189,13 @@ __global__ void __launch_bounds__(kHpThreads)
         long long foff = 0;
         double frh = 0.0;
         if (T.nb >= 0) {
-          const HpElem F = el[T.nb];
-          m0 = d == 0 ? F.N[1] : F.N[0];
-          m1 = d == 2 ? F.N[1] : F.N[2];
-          FN = pick(d, F.N[0], F.N[1], F.N[2]);
-          FN0 = F.N[0];
-          FN1 = F.N[1];
-          foff = F.off;
-          frh = pick(d, F.rh[0], F.rh[1], F.rh[2]);
+          m0 = d == 0 ? T.fN[1] : T.fN[0];
+          m1 = d == 2 ? T.fN[1] : T.fN[2];
+          FN = pick(d, T.fN[0], T.fN[1], T.fN[2]);
+          FN0 = T.fN[0];
+          FN1 = T.fN[1];
+          foff = T.foff;
+          frh = T.frh;
           // the neighbour's trace and normal derivative on its own face points
           if (q < m0 * m1) {
             const int fod = (f & 1) ? 0 : FN - 1;
