@@ -370,6 +370,10 @@ struct HpLevel {
   std::vector<HpSub> subs;
   HpSub* d_subs = nullptr;
   long long* d_gidx = nullptr;
+  // per point, the subdomain row positions that hold it (the gather pushed
+  // from the residual kernel)
+  long long* d_push_ptr = nullptr;
+  long long* d_push_pos = nullptr;
   long long* d_pull_ptr = nullptr;
   HpPull* d_pull = nullptr;
   bool f32 = false;  // FP32 subdomain rows, inverses and GEMM (mixed precision)
@@ -856,6 +860,19 @@ void build_schwarz(dgs_hp_problem* P, HpLevel& L, hipStream_t s) {
   upload(L.d_pull_ptr, ptr, s);
   L.d_pull = P->alloc<HpPull>(flat.size());
   upload(L.d_pull, flat, s);
+  // the same row positions grouped by point: pos = sub.rs + q for point gidx
+  std::vector<long long> pptr(m.ndof + 1, 0), ppos(gidx.size());
+  for (long long g : gidx) ++pptr[g + 1];
+  for (long long p = 0; p < m.ndof; ++p) pptr[p + 1] += pptr[p];
+  {
+    std::vector<long long> fill(pptr.begin(), pptr.end() - 1);
+    for (const HpSub& sub : L.subs)
+      for (int q = 0; q < sub.n; ++q) ppos[fill[gidx[sub.start + q]]++] = sub.rs + q;
+  }
+  L.d_push_ptr = P->alloc<long long>(pptr.size());
+  upload(L.d_push_ptr, pptr, s);
+  L.d_push_pos = P->alloc<long long>(ppos.size());
+  upload(L.d_push_pos, ppos, s);
   HIP_OK(hipStreamSynchronize(s));
 
   // explicit inverses: A_S assembled column by column by the operator kernel
@@ -1048,12 +1065,11 @@ void hp_schwarz(dgs_hp_problem* P, int l, const double* b, double* u, int steps,
   const long long n = L.mesh.ndof;
   if (u_zero) HIP_OK(launch_fill(u, 0.0, n, s));
   for (int k = 0; k < steps; ++k) {
-    const double* r = b;
-    if (!(u_zero && k == 0)) {
-      hp_residual(P, l, u, b, L.r, s);
-      r = L.r;
-    }
-    HIP_OK(launch_hp_gather(L.f32, r, L.rs, L.d_subs, (int)L.subs.size(), L.d_gidx, s));
+    if (u_zero && k == 0)  // the residual is b itself
+      HIP_OK(launch_hp_gather(L.f32, b, L.rs, L.d_subs, (int)L.subs.size(), L.d_gidx, s));
+    else  // the residual written straight into the subdomain rows
+      HIP_OK(launch_hp_residual_gather(u, b, L.d_el, L.mesh.E(), L.d_terms, P->d_pool, P->rule,
+                                       L.d_order, L.d_push_ptr, L.d_push_pos, L.f32, L.rs, s));
     HIP_OK(launch_subdomain_gemm(L.f32, L.rs, L.du, L.rs_total, L.d_cls, L.d_tiles, L.ntiles, L.small, 0, s,
                                  L.variant));
     HIP_OK(launch_hp_scatter(L.f32, u, L.du, L.kparts, L.rs_total, L.d_pull_ptr, L.d_pull, n, s));

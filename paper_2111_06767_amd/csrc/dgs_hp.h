@@ -87,6 +87,13 @@ hipError_t launch_hp_apply(bool residual, const double* u, double* out, const do
                            const HpElem* el, int E, const HpTerm* terms, const double* pool,
                            const HpRule& R, int copies, long long copy_stride, hipStream_t s,
                            const int* order = nullptr);
+// RS[pos] = (b - A u)[p] for every row position pos that push_ptr / push_pos
+// list for point p (the Schwarz gather fused into the residual; RS in FP32
+// with f32); the residual vector itself is not written
+hipError_t launch_hp_residual_gather(const double* u, const double* b, const HpElem* el, int E,
+                                     const HpTerm* terms, const double* pool, const HpRule& R,
+                                     const int* order, const long long* push_ptr,
+                                     const long long* push_pos, bool f32, void* rs, hipStream_t s);
 hipError_t launch_hp_mass(const double* f, double* out, const HpElem* el, int E, const HpRule& R,
                           hipStream_t s);
 // node coordinates: plo (3 per element, the lower corner) and h (3 per element)

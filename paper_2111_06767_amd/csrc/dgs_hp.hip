@@ -47,12 +47,18 @@ __device__ __forceinline__ int face_node(int d, int od, int b0, int b1, int N0, 
   return (k * N1 + j) * N0 + i;
 }
 
-template <bool RES>
+// PUSH (residual mode on a mesh): instead of out, every point's residual is
+// written into the Schwarz subdomain rows that hold it (push_ptr / push_pos
+// list the row positions of each point; rows in FP32 with rs_f32), the
+// gather fused into the residual.
+template <bool RES, bool PUSH = false>
 __global__ void __launch_bounds__(kHpThreads)
     k_hp_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ b,
                const HpElem* __restrict__ el, const HpTerm* __restrict__ terms,
                const double* __restrict__ pool, HpRule R, long long copy_stride,
-               const int* __restrict__ order) {
+               const int* __restrict__ order, const long long* __restrict__ push_ptr = nullptr,
+               const long long* __restrict__ push_pos = nullptr, void* __restrict__ rs = nullptr,
+               int rs_f32 = 0) {
   __shared__ double su[kHpMaxNodes];
   __shared__ double sg[3][kHpMaxNodes];
   __shared__ double scu[6][kF], scp[6][kF];
@@ -332,7 +338,19 @@ __global__ void __launch_bounds__(kHpThreads)
       const double ML = E.jac * E.rh[d] * wt;
       Au -= ML * (scp[f][q] - ((f & 1) ? 1.0 : -1.0) * sg[d][p]);
     }
-    out[base + p] = RES ? b[base + p] - Au : Au;
+    const double val = RES ? b[base + p] - Au : Au;
+    if constexpr (PUSH) {
+      const long long g = base + p;
+      const long long q1 = push_ptr[g + 1];
+      for (long long q = push_ptr[g]; q < q1; ++q) {
+        if (rs_f32)
+          static_cast<float*>(rs)[push_pos[q]] = (float)val;
+        else
+          static_cast<double*>(rs)[push_pos[q]] = val;
+      }
+    } else {
+      out[base + p] = val;
+    }
   }
 }
 
@@ -476,6 +494,16 @@ hipError_t launch_hp_apply(bool residual, const double* u, double* out, const do
   else
     hipLaunchKernelGGL(k_hp_apply<false>, grid, dim3(kHpThreads), 0, s, u, out, b, el, terms, pool, R,
                        copy_stride, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_hp_residual_gather(const double* u, const double* b, const HpElem* el, int E,
+                                     const HpTerm* terms, const double* pool, const HpRule& R,
+                                     const int* order, const long long* push_ptr,
+                                     const long long* push_pos, bool f32, void* rs, hipStream_t s) {
+  if (E <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_hp_apply<true, true>), dim3((unsigned)E), dim3(kHpThreads), 0, s, u, nullptr, b,
+                     el, terms, pool, R, 0LL, order, push_ptr, push_pos, rs, f32 ? 1 : 0);
   return hipGetLastError();
 }
 
