@@ -66,14 +66,15 @@ MEASURED_TRAFFIC = {
                                    "paper_2111_06767_amd/csrc/dgs_internal.h"],
                        "sha256": "9f082964d70abd00e4cbcbbe58d8115eb0ad696728b23c76bdaaf50fce0348ba",
                        "bytes": {0: 716658737, 1: 609315841, 2: 700374145, 3: 571243620, 4: 675797563}},
-    # the 40^3 p=7 apply per launch shape (k_apply<8, epb, 0, 0, brick>):
-    # bricks (-1) 181277.4, one element per workgroup 181359.9, two 181511.8,
-    # four 181363.7 KiB fetched x 1.99981, each + 256000.0 KiB written
+    # the 40^3 p=7 apply per launch shape (k_apply<8, epb, 0, 0, brick, true>,
+    # non-temporal stores): bricks (-1) 181232.1 + 256028.8, one element per
+    # workgroup 181320.1, two 181312.5, four 181312.6 KiB fetched x 1.99982,
+    # each + 256000.0 KiB written
     "apply": {"sources": ["paper_2111_06767_amd/csrc/dgs_apply.hip",
                           "paper_2111_06767_amd/csrc/dgs_elem.h",
                           "paper_2111_06767_amd/csrc/dgs_internal.h"],
-              "sha256": "615fc09fbee603fb5600ab476284007e8d9ca3d66a8f3f0644b72044db6e3acf",
-              "bytes": {-1: 633365603, 1: 633534547, 2: 633845610, 4: 633542329}},
+              "sha256": "ef2f59d67748230c12f631ee4c19ec8cd2fd13e162e7b1790380da014a5b4985",
+              "bytes": {-1: 633303488, 1: 633454205, 2: 633438641, 4: 633438846}},
 }
 
 

@@ -40,7 +40,7 @@ namespace {
 // direction inside the brick, whose lines are read from that element's LDS
 // copy, and only the three outside neighbours come from global memory: four
 // element reads per element instead of seven.
-template <int N, int EPB, int MODE, int GO, bool BR>
+template <int N, int EPB, int MODE, int GO, bool BR, bool NT = false>
 __global__ void __launch_bounds__(((EPB * N * N + 63) / 64) * 64)
 k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __restrict__ bvec,
         const double* __restrict__ aux0, const double* __restrict__ aux1,
@@ -364,8 +364,17 @@ k_apply(const double* __restrict__ u, double* __restrict__ out, const double* __
       for (int k = 0; k < N; ++k) ucopy[e * N3 + k * N2 + t] = uz[k];
     }
     if constexpr (GO == 0) {
+      // NT: streamed out with non-temporal stores, which leave the cached
+      // input lines (the neighbours' lines read by later workgroups) in place
+      // (a compile-time choice: a runtime branch lets the compiler merge the
+      // two stores and drop the non-temporal hint)
+      if constexpr (NT) {
 #pragma unroll
-      for (int k = 0; k < N; ++k) out[e * N3 + k * N2 + t] = rz[k];
+        for (int k = 0; k < N; ++k) __builtin_nontemporal_store(rz[k], &out[e * N3 + k * N2 + t]);
+      } else {
+#pragma unroll
+        for (int k = 0; k < N; ++k) out[e * N3 + k * N2 + t] = rz[k];
+      }
     } else if constexpr (GO == 1) {
       store_subdomain_rows<float, N>(rz, (float*)go.rs, sPull[slot], a, b, go.nov);
     } else {
@@ -383,6 +392,19 @@ hipError_t launch_apply_k(const double* u, double* out, const double* b, const d
   if (BR)
     need = (long long)((P.n[0] + 1) / 2) * ((P.n[1] + 1) / 2) * ((P.n[2] + 1) / 2);
   const long long blocks = ((need + 7) / 8) * 8;  // whole rounds over the 8 XCDs
+  // when u and A u together exceed the 256 MB Infinity Cache, the output
+  // would only push out input lines that neighbouring workgroups still read:
+  // it is then written with non-temporal stores (measured at 40^3, p = 7:
+  // 12-18 % faster; on cache-resident sizes the solves that read the output
+  // next lose 0.3-1.4 % with them, so those keep ordinary stores)
+  const long long vec_bytes = (long long)P.E * N * N * N * (long long)sizeof(double);
+  if constexpr (GO == 0) {
+    if (2 * vec_bytes > (256LL << 20)) {
+      hipLaunchKernelGGL((k_apply<N, EPB, MODE, GO, BR, true>), dim3((unsigned)blocks), dim3(threads), 0,
+                         s, u, out, b, aux0, aux1, nbr, P, T, order, go, ucopy);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_apply<N, EPB, MODE, GO, BR>), dim3((unsigned)blocks), dim3(threads), 0, s,
                      u, out, b, aux0, aux1, nbr, P, T, order, go, ucopy);
   return hipGetLastError();
