@@ -472,3 +472,33 @@ def test_xcts_matched_laplacian_approximation_needs_fewer_iterations():
         S.close()
     assert its["matched"] < its["dirichlet"], its
     assert np.linalg.norm(sols["matched"] - sols["dirichlet"]) <= 1e-9 * np.linalg.norm(sols["dirichlet"])
+
+
+def test_kerr_schild_full_size_solutions_match_the_analytic_ones():
+    # at the benchmark's 16^3 grids of the wedge, the Newton solutions of the
+    # lapse equation (p = 7) and of the Hamiltonian + lapse system (p = 5)
+    # equal the analytic Kerr-Schild solution (eqs. kerrschild_psi,
+    # kerrschild_lapse) to the discretisation error, far below 1e-8
+    import paper_2111_06767_amd as dg
+    announce("kerr-schild lapse 16^3 p=7 and xcts system 16^3 p=5 against the analytic solution")
+    box = omesh.BoxMesh((-1, -1, -1), (1, 1, 1), (16, 16, 16), 7)
+    xyz = W.wedge_coordinates(np.stack(box.node_coordinates()), 2.0, 10.0)
+    G, sg, alpha, coefs, powers = W.kerr_schild_lapse(xyz)
+    six = np.stack([G[0, 0], G[0, 1], G[0, 2], G[1, 1], G[1, 2], G[2, 2]]).reshape(-1)
+    prob = _problem(box, mg_levels=4, subdomain_iters=3)
+    prob.set_geometry(to_gpu(xyz.reshape(-1)))
+    prob.set_metric(to_gpu(six), to_gpu(sg.reshape(-1)))
+    u, st = prob.newton_solve_powers(to_gpu(coefs.reshape(-1)), powers, dirichlet=to_gpu(alpha.reshape(-1)))
+    prob.close()
+    assert st["converged"] and st["newton_steps"] <= 4, st
+    assert np.abs(to_np(u) - alpha.reshape(-1)).max() < 1e-8
+    mp, mf, xyz2, G2, sg2, six2, alpha2, terms, ub, vars_, pw, coef = _xcts_system((16, 16, 16), 5)
+    S = dg.System(tuple(mp.lower), tuple(mp.upper), mp.n, mp.p, [(4,), ()], laplacian_bc="matched", penalty=C,
+                  mg_levels=4, subdomain_iters=1)
+    S.set_geometry(to_gpu(xyz2.reshape(-1)))
+    S.set_metric(to_gpu(six2), to_gpu(sg2.reshape(-1)))
+    v, st = S.newton_solve_powers(to_gpu(coef), vars_, pw, dirichlet=to_gpu(ub.reshape(-1)))
+    S.close()
+    v = to_np(v).reshape(2, -1)
+    assert st["converged"] and st["newton_steps"] <= 4, st
+    assert np.abs(v[0] - 1.0).max() < 1e-8 and np.abs(v[1] - alpha2).max() < 1e-8
