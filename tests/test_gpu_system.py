@@ -142,3 +142,30 @@ def test_system_limits():
         dg.System((0, 0, 0), (1, 1, 1), (3, 3, 3), 9, [(), ()], mg_levels=1)
     with pytest.raises(dg.DgsError):  # every face Neumann
         dg.System((0, 0, 0), (1, 1, 1), (2, 2, 2), 2, [tuple(range(6))])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_five_variable_system_full_size_through_oracle_operator(precision):
+    # the benchmark's system: five variables on 8^3 elements, p = 6, with their
+    # own Neumann faces and pointwise couplings; the GPU solution's residual
+    # taken with the oracle's system operator
+    import paper_2111_06767_amd as dg
+    announce(f"five-variable system 8^3 p=6 {precision} through the oracle operator")
+    nv = len(W.SYSTEM_NEUMANN)
+    lower, upper, el, p = (0, 0, 0), (1, 1, 1), (8, 8, 8), 6
+    sysop = system.SystemOperator(lower, upper, el, p, W.SYSTEM_NEUMANN, C)
+    m = sysop.mesh
+    x, y, z = m.node_coordinates()
+    c = W.system_coupling(W.SEED_SYSTEM, nv, x, y, z)
+    mass = np.broadcast_to(oop.mass_diagonal(m), (m.E, m.N, m.N, m.N)).reshape(-1)
+    D = c * mass[None, None, :]
+    b = np.concatenate([oop.apply_mass(m, W.fourier_source(W.fourier_modes(W.SEED_SYSTEM + 1 + a), x, y, z)
+                                       .reshape(m.E, m.N, m.N, m.N)).reshape(-1) for a in range(nv)])
+    S = dg.System(lower, upper, el, p, W.SYSTEM_NEUMANN, mg_levels=3, subdomain_iters=3,
+                  precision=precision, max_iter=100)
+    S.set_coupling(to_gpu(D.reshape(-1)))
+    u, st = S.solve(to_gpu(b))
+    S.close()
+    assert st["converged"] and st["iterations"] <= 12, st
+    r = b - sysop.apply(to_np(u), D).reshape(-1)
+    assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b)
