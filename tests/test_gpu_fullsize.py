@@ -103,3 +103,22 @@ def test_apply_40cubed_p7_sampled():
         pm = omesh.BoxMesh(lo * h, hi * h, tuple(hi - lo), p)
         ref = oop.apply_operator(pm, sub.reshape(-1, N, N, N), C)[pm.elem_index(*(c - lo))]
         assert rel_max(got[c[2], c[1], c[0]], ref) < 1e-13, c
+
+
+@pytest.mark.parametrize("name,opts", [("cg", dict()), ("restarted_fgmres_4", dict(restart=4)),
+                                       ("wcycle", dict(cycle=2)), ("fcycle", dict(cycle=3)),
+                                       ("additive_mg", dict(additive=1))])
+def test_c2_solver_variants_through_oracle_operator(name, opts):
+    # the benchmark's c2 variants (8^3, p = 6, mixed precision): CG, restarted
+    # FGMRES and the W-, F- and additive cycles, each checked by the oracle's
+    # residual of its solution
+    import paper_2111_06767_amd as dg
+    announce(f"c2 variant {name}")
+    m, b, uex = _fourier_problem(8, 6, W.SEED_C2)
+    prob = dg.Problem((0, 0, 0), (1, 1, 1), (8, 8, 8), 6, penalty=C, mg_levels=3, precision="mixed",
+                      **opts)
+    u, st = (prob.solve_cg if name == "cg" else prob.solve)(to_gpu(b))
+    un = to_np(u)
+    prob.close()
+    assert st["converged"], st
+    assert _oracle_residual(m, un, b) <= 1e-10
